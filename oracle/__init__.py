@@ -1,0 +1,215 @@
+"""Python access to the CPU oracle (test infrastructure only).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark
+may import this package.  The product library never does.
+
+Arrays follow numpy C order: a field of shape (nz, ny, nx) has x fastest,
+which the oracle calls dims = (nx, ny, nz).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+OK, ERR_ARG, ERR_EB, ERR_NONFINITE, ERR_CAPACITY, ERR_CORRUPT = 0, -1, -2, -3, -4, -5
+ERR_NOMEM, ERR_UNSUPPORTED = -7, -8
+HDR = 128
+NBINS = 1024
+RADIUS = 512
+LMAX = 12
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code):
+        super().__init__(f"oracle error {code}")
+        self.code = code
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        vp = ctypes.c_void_p
+        L.orc_eb_abs.argtypes = [vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_double,
+                                 ctypes.POINTER(ctypes.c_double)]
+        L.orc_prequant.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, vp, vp]
+        L.orc_prequant.restype = None
+        L.orc_lorenzo1.argtypes = [vp, ctypes.c_int, u64p, vp]
+        L.orc_lorenzo1.restype = None
+        L.orc_lorenzo1_inverse.argtypes = [vp, ctypes.c_int, u64p, vp]
+        L.orc_lorenzo1_inverse.restype = None
+        L.orc_histogram.argtypes = [vp, ctypes.c_uint64, vp]
+        L.orc_histogram.restype = None
+        L.orc_codebook_lmax.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
+        L.orc_codebook.argtypes = [vp, vp]
+        L.orc_canonical.argtypes = [vp, ctypes.c_int, vp]
+        L.orc_canonical.restype = None
+        L.orc_compress_bound.argtypes = [ctypes.c_int, u64p]
+        L.orc_compress_bound.restype = ctypes.c_uint64
+        L.orc_compress.argtypes = [vp, ctypes.c_int, u64p, ctypes.c_int, ctypes.c_double, vp,
+                                   ctypes.c_uint64, u64p]
+        L.orc_decompress.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_uint64]
+        L.orc_stage_codes.argtypes = [vp, ctypes.c_int, u64p, ctypes.c_int, ctypes.c_double, vp, vp,
+                                      vp, ctypes.POINTER(ctypes.c_double)]
+        L.orc_encode_symbols.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_int, vp]
+        L.orc_encode_symbols.restype = ctypes.c_uint64
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def dims_of(shape):
+    """numpy shape (C order) -> (ndim, dims[3]) with dims[0] fastest."""
+    nd = len(shape)
+    if nd < 1 or nd > 3:
+        raise ValueError("1-3 dimensions")
+    d = list(reversed([int(s) for s in shape])) + [1] * (3 - nd)
+    return nd, (ctypes.c_uint64 * 3)(*d)
+
+
+def eb_abs(x, mode, eb):
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    out = ctypes.c_double()
+    rc = lib().orc_eb_abs(_ptr(x), x.size, int(mode), float(eb), ctypes.byref(out))
+    if rc:
+        raise OracleError(rc)
+    return out.value
+
+
+def prequant(x, eb_abs_value):
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    q = np.empty(x.shape, np.int32)
+    p = np.empty(x.shape, np.uint8)
+    lib().orc_prequant(_ptr(x), x.size, float(eb_abs_value), _ptr(q), _ptr(p))
+    return q, p.astype(bool)
+
+
+def lorenzo1(q):
+    q = np.ascontiguousarray(q, dtype=np.int32)
+    nd, d = dims_of(q.shape)
+    out = np.empty_like(q)
+    lib().orc_lorenzo1(_ptr(q), nd, d, _ptr(out))
+    return out
+
+
+def lorenzo1_inverse(delta):
+    delta = np.ascontiguousarray(delta, dtype=np.int32)
+    nd, d = dims_of(delta.shape)
+    out = np.empty_like(delta)
+    lib().orc_lorenzo1_inverse(_ptr(delta), nd, d, _ptr(out))
+    return out
+
+
+def histogram(codes):
+    codes = np.ascontiguousarray(codes, dtype=np.uint16)
+    h = np.empty(NBINS, np.uint32)
+    lib().orc_histogram(_ptr(codes), codes.size, _ptr(h))
+    return h
+
+
+def codebook(hist, lmax=LMAX):
+    hist = np.ascontiguousarray(hist, dtype=np.uint32)
+    ln = np.zeros(hist.size, np.uint8)
+    rc = lib().orc_codebook_lmax(_ptr(hist), hist.size, int(lmax), _ptr(ln))
+    if rc:
+        raise OracleError(rc)
+    return ln
+
+
+def canonical(lengths):
+    lengths = np.ascontiguousarray(lengths, dtype=np.uint8)
+    c = np.zeros(lengths.size, np.uint32)
+    lib().orc_canonical(_ptr(lengths), lengths.size, _ptr(c))
+    return c
+
+
+def compress_bound(shape):
+    nd, d = dims_of(shape)
+    return int(lib().orc_compress_bound(nd, d))
+
+
+def compress(x, eb, mode=1):
+    """Compress a float32 field; returns the container as bytes.  mode 0 = absolute, 1 = relative."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    nd, d = dims_of(x.shape)
+    cap = compress_bound(x.shape)
+    out = np.zeros(max(cap, HDR), np.uint8)
+    n = ctypes.c_uint64(0)
+    rc = lib().orc_compress(_ptr(x), nd, d, int(mode), float(eb), _ptr(out), out.size, ctypes.byref(n))
+    if rc:
+        raise OracleError(rc)
+    return out[: n.value].tobytes()
+
+
+def header(buf):
+    """Parse the container header into a dict (fields used by the tests)."""
+    b = np.frombuffer(bytes(buf[:HDR]), np.uint8)
+
+    def u(o, n):
+        return int.from_bytes(bytes(b[o:o + n]), "little")
+
+    return dict(magic=u(0, 4), version=u(4, 2), flags=u(6, 2), ndim=u(8, 4), pred=u(12, 4),
+                dims=(u(16, 8), u(24, 8), u(32, 8)), eb_mode=u(40, 4), radius=u(44, 4),
+                eb=np.frombuffer(bytes(b[48:56]), np.float64)[0],
+                eb_abs=np.frombuffer(bytes(b[56:64]), np.float64)[0],
+                total=u(64, 8), nblocks=u(72, 4), n_outliers=u(76, 4), n_patches=u(80, 4),
+                stream_words=u(84, 4), stream_bits=u(88, 8))
+
+
+def shape_of(h):
+    nd = h["ndim"]
+    return tuple(reversed(h["dims"][:nd]))
+
+
+def decompress(buf):
+    buf = np.frombuffer(bytes(buf), np.uint8)
+    h = header(buf)
+    shape = shape_of(h)
+    out = np.empty(shape, np.float32)
+    rc = lib().orc_decompress(_ptr(buf), buf.size, _ptr(out), out.size)
+    if rc:
+        raise OracleError(rc)
+    return out
+
+
+def decompress_rc(buf, out_elems=None):
+    """Return code only (for corruption tests); never raises."""
+    buf = np.frombuffer(bytes(buf), np.uint8)
+    n = out_elems if out_elems is not None else (1 << 20)
+    out = np.empty(max(n, 1), np.float32)
+    return int(lib().orc_decompress(_ptr(buf), buf.size, _ptr(out), out.size))
+
+
+def stage_codes(x, eb, mode=1):
+    """Codes (block-major), their positions, the histogram and eb_abs."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    nd, d = dims_of(x.shape)
+    codes = np.empty(x.size, np.uint16)
+    pos = np.empty(x.size, np.uint32)
+    hist = np.empty(NBINS, np.uint32)
+    e = ctypes.c_double()
+    rc = lib().orc_stage_codes(_ptr(x), nd, d, int(mode), float(eb), _ptr(codes), _ptr(pos), _ptr(hist),
+                               ctypes.byref(e))
+    if rc:
+        raise OracleError(rc)
+    return codes, pos, hist, e.value
+
+
+def encode_symbols(syms, lengths):
+    """Bits of a symbol sequence under the canonical code of ``lengths``: (words u32, nbits)."""
+    syms = np.ascontiguousarray(syms, dtype=np.uint16)
+    lengths = np.ascontiguousarray(lengths, dtype=np.uint8)
+    nbits_max = int(sum(int(lengths[s]) for s in syms))
+    words = np.zeros(nbits_max // 32 + 2, np.uint32)
+    nb = lib().orc_encode_symbols(_ptr(syms), syms.size, _ptr(lengths), lengths.size, _ptr(words))
+    return words[: (nb + 31) // 32], int(nb)

@@ -1,0 +1,714 @@
+/*
+ * CPU oracle for the error-bounded Lorenzo + Huffman compression path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or constant
+ * generator with the HIP implementation: every step is written out here
+ * again, slowly and plainly, in the order the method defines it.
+ *
+ * What it computes (FZModules, Sec. 3.1 "cuSZ Design", Sec. 3.2 "Modularity",
+ * Sec. 3.3 pipeline "FZMod-Default"; Sec. 4.2 "Evaluation Metrics"):
+ *   1. error-bound resolution: absolute, or value-range relative
+ *      (Sec. 3.2: the relative mode needs the data minimum and maximum);
+ *   2. prequantisation of every value onto the grid of step 2*eb
+ *      (dual quantisation of cuSZ, Sec. 3.1);
+ *   3. block-local first-order Lorenzo prediction on the integer grid,
+ *      residual = backward difference along every axis (Sec. 3.1, 3.2);
+ *   4. post-quantisation: residuals inside the radius become integer codes,
+ *      the rest are stored as outliers (Sec. 3.1 "saves data as outliers
+ *      if they are unpredictable"; Sec. 3.3.1 outlier handling);
+ *   5. a histogram of the codes (Sec. 3.2: the Huffman encoder needs it);
+ *   6. a length-limited minimum-redundancy (Huffman) code built from the
+ *      histogram, in canonical form (Sec. 3.2 "optimal compression ratio");
+ *   7. chunked Huffman encoding, one chunk per block (Sec. 3.3);
+ *   8. the container; decoding, outlier scatter and inverse Lorenzo
+ *      (prefix sums) with dequantisation (Sec. 1 and Sec. 3.3.1 describe
+ *      decompression as Huffman decoding plus outlier scatter).
+ * The paper leaves every bit-level choice to the cuSZ papers; the readings
+ * taken here (block shapes, code layout, tie rules, container layout, the
+ * lossless patches that make the bound strict) are the ones the HIP path
+ * must reproduce and are listed with the design notes of the project.
+ *
+ * Pins: tests/test_oracle_*.py check this file against brute force on tiny
+ * inputs, closed forms, textbook Huffman costs, invariants (max error <= eb,
+ * histogram sums to N, Kraft equality, round trip) and hand-made examples.
+ *
+ * Build: gcc -O2 -std=c99 -ffp-contract=off -fno-fast-math (no contraction,
+ * no fast math, SSE2 doubles, round-to-nearest-even).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ----------------------------------------------------------------- errors */
+#define ORC_OK 0
+#define ORC_ERR_ARG (-1)
+#define ORC_ERR_EB (-2)
+#define ORC_ERR_NONFINITE (-3)
+#define ORC_ERR_CAPACITY (-4)
+#define ORC_ERR_CORRUPT (-5)
+#define ORC_ERR_NOMEM (-7)
+#define ORC_ERR_UNSUPPORTED (-8)
+
+/* --------------------------------------------------------------- constants */
+#define ORC_RADIUS 512        /* codes 1..1023 hold residuals -511..511      */
+#define ORC_NBINS 1024        /* code 0 marks an outlier                     */
+#define ORC_LMAX 12           /* longest codeword                            */
+#define ORC_HDR 128           /* container header bytes                      */
+#define ORC_BLOCK_ELEMS 512   /* every block holds at most 512 values        */
+#define ORC_MAGIC 0x314D5A46u /* bytes 'F' 'Z' 'M' '1'                       */
+#define ORC_VERSION 1
+
+/* ------------------------------------------------------------ block shapes
+ * 1D blocks are 512 long, 2D blocks 32 (x) by 16 (y), 3D blocks 8x8x8.
+ * dims[0] is the fastest-varying axis.  Edge blocks are truncated.        */
+static void block_shape(int ndim, int bs[3]) {
+    if (ndim == 1) { bs[0] = 512; bs[1] = 1; bs[2] = 1; }
+    else if (ndim == 2) { bs[0] = 32; bs[1] = 16; bs[2] = 1; }
+    else { bs[0] = 8; bs[1] = 8; bs[2] = 8; }
+}
+
+typedef struct {
+    int ndim;
+    uint64_t n[3];   /* field extent per axis (unused axes are 1) */
+    int bs[3];       /* block extent per axis                     */
+    uint64_t nb[3];  /* number of blocks per axis                 */
+    uint64_t nblocks;
+    uint64_t N;
+} geom_t;
+
+static int make_geom(int ndim, const uint64_t dims[3], geom_t *g) {
+    if (ndim < 1 || ndim > 3) return ORC_ERR_ARG;
+    g->ndim = ndim;
+    for (int a = 0; a < 3; a++) g->n[a] = (a < ndim) ? dims[a] : 1;
+    for (int a = 0; a < 3; a++) if (g->n[a] < 1) return ORC_ERR_ARG;
+    block_shape(ndim, g->bs);
+    g->N = g->n[0] * g->n[1] * g->n[2];
+    if (g->n[0] > 0xFFFFFFFFull || g->n[1] > 0xFFFFFFFFull || g->n[2] > 0xFFFFFFFFull) return ORC_ERR_ARG;
+    for (int a = 0; a < 3; a++) g->nb[a] = (g->n[a] + g->bs[a] - 1) / g->bs[a];
+    g->nblocks = g->nb[0] * g->nb[1] * g->nb[2];
+    /* positions are u32: block index * 512 + in-block offset */
+    if (g->nblocks > (1ull << 23)) return ORC_ERR_ARG;
+    return ORC_OK;
+}
+
+/* row-major index of (x, y, z) */
+static uint64_t rm(const geom_t *g, uint64_t x, uint64_t y, uint64_t z) {
+    return x + g->n[0] * (y + g->n[1] * z);
+}
+
+/* --------------------------------------------- step 1: error-bound resolution
+ * Absolute mode: eb_abs = eb.  Relative mode: eb_abs = eb * (max - min),
+ * range taken in double; a constant field (range 0) uses eb itself.
+ * (Sec. 3.2 preprocessors; Sec. 4.2 value-range relative bound.)         */
+int orc_eb_abs(const float *x, uint64_t N, int mode, double eb, double *eb_abs) {
+    if (!(eb > 0.0) || !isfinite(eb)) return ORC_ERR_EB;
+    for (uint64_t i = 0; i < N; i++)
+        if (!isfinite(x[i])) return ORC_ERR_NONFINITE;
+    double e;
+    if (mode == 0) {
+        e = eb;
+    } else if (mode == 1) {
+        float lo = x[0], hi = x[0];
+        for (uint64_t i = 1; i < N; i++) {
+            if (x[i] < lo) lo = x[i];
+            if (x[i] > hi) hi = x[i];
+        }
+        double range = (double)hi - (double)lo;
+        e = (range > 0.0) ? eb * range : eb;
+    } else {
+        return ORC_ERR_ARG;
+    }
+    if (!(e >= 1e-300 && e <= 1e300)) return ORC_ERR_EB;
+    *eb_abs = e;
+    return ORC_OK;
+}
+
+/* -------------------------------------------------- step 2: prequantisation
+ * q = round-half-even(x / (2 eb_abs)) computed as x * (1 / (2 eb_abs)) in
+ * double.  A value is a lossless patch when the grid value is out of the
+ * 2^24 range (q is then 0) or when the reconstruction rounded to float
+ * misses the bound (q is kept).  The bound is inclusive.                  */
+void orc_prequant(const float *x, uint64_t N, double eb_abs, int32_t *q, uint8_t *patch) {
+    double e2 = 2.0 * eb_abs;
+    double inv = 1.0 / e2;
+    for (uint64_t i = 0; i < N; i++) {
+        double t = (double)x[i] * inv;
+        if (fabs(t) >= 16777216.0) {
+            q[i] = 0;
+            patch[i] = 1;
+        } else {
+            int32_t qi = (int32_t)nearbyint(t);
+            float xh = (float)((double)qi * e2);
+            q[i] = qi;
+            patch[i] = fabs((double)x[i] - (double)xh) > eb_abs ? 1 : 0;
+        }
+    }
+}
+
+/* dequantisation of one grid value */
+static float dequant(int32_t qv, double e2) { return (float)((double)qv * e2); }
+
+/* ------------------------------------- step 3: block-local Lorenzo residual
+ * Neighbours outside the element's own block count as zero.
+ * 1D: d = q - q[x-1]
+ * 2D: d = q - q[x-1] - q[y-1] + q[x-1,y-1]
+ * 3D: d = q - q[x-1] - q[y-1] - q[z-1] + q[x-1,y-1] + q[x-1,z-1]
+ *         + q[y-1,z-1] - q[x-1,y-1,z-1]
+ * Output is in row-major order like the input.                           */
+static int32_t qnb(const geom_t *g, const int32_t *q, uint64_t x, uint64_t y, uint64_t z,
+                   int dx, int dy, int dz) {
+    /* q at (x-dx, y-dy, z-dz) if that point lies in the same block, else 0 */
+    uint64_t lx = x % (uint64_t)g->bs[0], ly = y % (uint64_t)g->bs[1], lz = z % (uint64_t)g->bs[2];
+    if ((uint64_t)dx > lx || (uint64_t)dy > ly || (uint64_t)dz > lz) return 0;
+    return q[rm(g, x - dx, y - dy, z - dz)];
+}
+
+void orc_lorenzo1(const int32_t *q, int ndim, const uint64_t dims[3], int32_t *delta) {
+    geom_t g;
+    if (make_geom(ndim, dims, &g) != ORC_OK) return;
+    for (uint64_t z = 0; z < g.n[2]; z++)
+        for (uint64_t y = 0; y < g.n[1]; y++)
+            for (uint64_t x = 0; x < g.n[0]; x++) {
+                int32_t d;
+                if (ndim == 1) {
+                    d = qnb(&g, q, x, y, z, 0, 0, 0) - qnb(&g, q, x, y, z, 1, 0, 0);
+                } else if (ndim == 2) {
+                    d = qnb(&g, q, x, y, z, 0, 0, 0) - qnb(&g, q, x, y, z, 1, 0, 0)
+                      - qnb(&g, q, x, y, z, 0, 1, 0) + qnb(&g, q, x, y, z, 1, 1, 0);
+                } else {
+                    d = qnb(&g, q, x, y, z, 0, 0, 0) - qnb(&g, q, x, y, z, 1, 0, 0)
+                      - qnb(&g, q, x, y, z, 0, 1, 0) - qnb(&g, q, x, y, z, 0, 0, 1)
+                      + qnb(&g, q, x, y, z, 1, 1, 0) + qnb(&g, q, x, y, z, 1, 0, 1)
+                      + qnb(&g, q, x, y, z, 0, 1, 1) - qnb(&g, q, x, y, z, 1, 1, 1);
+                }
+                delta[rm(&g, x, y, z)] = d;
+            }
+}
+
+/* Inverse: inclusive prefix sums inside each block, along x, then y, then z. */
+void orc_lorenzo1_inverse(const int32_t *delta, int ndim, const uint64_t dims[3], int32_t *q) {
+    geom_t g;
+    if (make_geom(ndim, dims, &g) != ORC_OK) return;
+    memcpy(q, delta, sizeof(int32_t) * g.N);
+    for (uint64_t z = 0; z < g.n[2]; z++)
+        for (uint64_t y = 0; y < g.n[1]; y++)
+            for (uint64_t x = 0; x < g.n[0]; x++)
+                if (x % g.bs[0] != 0) q[rm(&g, x, y, z)] += q[rm(&g, x - 1, y, z)];
+    for (uint64_t z = 0; z < g.n[2]; z++)
+        for (uint64_t y = 0; y < g.n[1]; y++)
+            for (uint64_t x = 0; x < g.n[0]; x++)
+                if (y % g.bs[1] != 0) q[rm(&g, x, y, z)] += q[rm(&g, x, y - 1, z)];
+    for (uint64_t z = 0; z < g.n[2]; z++)
+        for (uint64_t y = 0; y < g.n[1]; y++)
+            for (uint64_t x = 0; x < g.n[0]; x++)
+                if (z % g.bs[2] != 0) q[rm(&g, x, y, z)] += q[rm(&g, x, y, z - 1)];
+}
+
+/* --------------------------------------------------- block-major traversal
+ * Blocks in row-major order over the block grid (block x fastest); inside a
+ * block, elements x fastest, then y, then z, over the block's real extent.
+ * An element's position is  block_index * 512 + lx + bs0 * (ly + bs1 * lz)
+ * (full-block strides, so truncated blocks leave gaps in the numbering).   */
+typedef struct {
+    uint64_t idx;  /* row-major index */
+    uint32_t pos;  /* position        */
+} elem_ref;
+
+/* Fill refs[] with every element in block-major order; returns count (= N). */
+static uint64_t block_major_order(const geom_t *g, elem_ref *refs, uint32_t *block_count) {
+    uint64_t k = 0, b = 0;
+    for (uint64_t bz = 0; bz < g->nb[2]; bz++)
+        for (uint64_t by = 0; by < g->nb[1]; by++)
+            for (uint64_t bx = 0; bx < g->nb[0]; bx++, b++) {
+                uint32_t cnt = 0;
+                for (int lz = 0; lz < g->bs[2]; lz++)
+                    for (int ly = 0; ly < g->bs[1]; ly++)
+                        for (int lx = 0; lx < g->bs[0]; lx++) {
+                            uint64_t x = bx * g->bs[0] + lx, y = by * g->bs[1] + ly, z = bz * g->bs[2] + lz;
+                            if (x >= g->n[0] || y >= g->n[1] || z >= g->n[2]) continue;
+                            refs[k].idx = rm(g, x, y, z);
+                            refs[k].pos = (uint32_t)(b * ORC_BLOCK_ELEMS + lx + g->bs[0] * (ly + g->bs[1] * lz));
+                            k++;
+                            cnt++;
+                        }
+                block_count[b] = cnt;
+            }
+    return k;
+}
+
+/* ---------------------------------------------- step 4: post-quantisation
+ * |d| < radius -> code d + radius (1..1023); otherwise code 0 and outlier. */
+static uint16_t postquant(int32_t d) {
+    if (d > -ORC_RADIUS && d < ORC_RADIUS) return (uint16_t)(d + ORC_RADIUS);
+    return 0;
+}
+
+/* ------------------------------------------------------- step 5: histogram */
+void orc_histogram(const uint16_t *codes, uint64_t n, uint32_t *hist) {
+    memset(hist, 0, sizeof(uint32_t) * ORC_NBINS);
+    for (uint64_t i = 0; i < n; i++) hist[codes[i]]++;
+}
+
+/* ---------------------------------- step 6: length-limited Huffman lengths
+ * Minimum-redundancy prefix code with every length <= lmax, by the
+ * package-merge method (Larmore & Hirschberg, 1990), written out plainly:
+ *
+ *   leaves   : used symbols sorted by (count, symbol) ascending;
+ *   list[lmax] = leaves;
+ *   list[l]  = merge of leaves and packages of list[l+1], where package j
+ *              is item 2j + item 2j+1 of list[l+1] (an unpaired last item is
+ *              dropped); equal weights put the leaf first, packages keep
+ *              their order;
+ *   select the first 2n-2 items of list[1]; the selected packages of
+ *   list[l] stand for the first 2*(#packages) items of list[l+1];
+ *   a symbol's length is the number of levels at which it was selected.
+ *
+ * A single used symbol gets a companion of weight 0 (the smallest unused
+ * symbol) so that both get length 1 and the Kraft sum is exactly 1.
+ * Returns 0, or -1 if lmax cannot hold the alphabet.                      */
+typedef struct {
+    uint64_t w;
+    int leaf;   /* leaf rank in the sorted leaf list, or -1 for a package */
+} pm_item;
+
+int orc_codebook_lmax(const uint32_t *hist, int nsym, int lmax, uint8_t *len) {
+    int *sym = (int *)malloc(sizeof(int) * (nsym + 1));
+    uint64_t *w = (uint64_t *)malloc(sizeof(uint64_t) * (nsym + 1));
+    int n = 0;
+    for (int s = 0; s < nsym; s++) len[s] = 0;
+    for (int s = 0; s < nsym; s++)
+        if (hist[s] > 0) { sym[n] = s; w[n] = hist[s]; n++; }
+    if (n == 0) { free(sym); free(w); return 0; }
+    if (n == 1) {
+        int ph = 0;
+        while (ph < nsym && hist[ph] > 0) ph++;
+        if (ph == nsym) { len[sym[0]] = 1; free(sym); free(w); return 0; }
+        len[sym[0]] = 1;
+        len[ph] = 1;
+        free(sym); free(w);
+        return 0;
+    }
+    if ((1ull << lmax) < (uint64_t)n) { free(sym); free(w); return -1; }
+    /* sort leaves by (weight, symbol): insertion sort keeps it plain */
+    for (int i = 1; i < n; i++) {
+        int s = sym[i];
+        uint64_t ws = w[i];
+        int j = i - 1;
+        while (j >= 0 && (w[j] > ws || (w[j] == ws && sym[j] > s))) {
+            sym[j + 1] = sym[j];
+            w[j + 1] = w[j];
+            j--;
+        }
+        sym[j + 1] = s;
+        w[j + 1] = ws;
+    }
+    /* lists[l] for l = 1..lmax */
+    int maxlen = 2 * n;
+    pm_item **lists = (pm_item **)calloc(lmax + 1, sizeof(pm_item *));
+    int *llen = (int *)calloc(lmax + 1, sizeof(int));
+    for (int l = 1; l <= lmax; l++) lists[l] = (pm_item *)malloc(sizeof(pm_item) * maxlen);
+    for (int i = 0; i < n; i++) { lists[lmax][i].w = w[i]; lists[lmax][i].leaf = i; }
+    llen[lmax] = n;
+    for (int l = lmax - 1; l >= 1; l--) {
+        const pm_item *prev = lists[l + 1];
+        int np = llen[l + 1] / 2;
+        int a = 0, p = 0, k = 0;
+        while (a < n || p < np) {
+            uint64_t pw = (p < np) ? prev[2 * p].w + prev[2 * p + 1].w : 0;
+            if (p >= np || (a < n && w[a] <= pw)) {
+                lists[l][k].w = w[a];
+                lists[l][k].leaf = a;
+                a++;
+            } else {
+                lists[l][k].w = pw;
+                lists[l][k].leaf = -1;
+                p++;
+            }
+            k++;
+        }
+        llen[l] = k;
+    }
+    /* selection, top level down */
+    int take = 2 * n - 2;
+    for (int l = 1; l <= lmax && take > 0; l++) {
+        int packages = 0;
+        for (int i = 0; i < take; i++) {
+            if (lists[l][i].leaf >= 0) len[sym[lists[l][i].leaf]]++;
+            else packages++;
+        }
+        take = 2 * packages;
+    }
+    for (int l = 1; l <= lmax; l++) free(lists[l]);
+    free(lists); free(llen); free(sym); free(w);
+    return 0;
+}
+
+int orc_codebook(const uint32_t *hist, uint8_t *len) {
+    return orc_codebook_lmax(hist, ORC_NBINS, ORC_LMAX, len);
+}
+
+/* Canonical codewords: used symbols ordered by (length, symbol); the first
+ * gets 0, each next one (previous + 1) shifted left by the length step.   */
+void orc_canonical(const uint8_t *len, int nsym, uint32_t *code) {
+    uint32_t c = 0;
+    int prev_len = 0, first = 1;
+    for (int L = 1; L <= 32; L++)
+        for (int s = 0; s < nsym; s++) {
+            if (len[s] != L) continue;
+            if (first) { c = 0; first = 0; }
+            else c = (c + 1) << (L - prev_len);
+            code[s] = c;
+            prev_len = L;
+        }
+    for (int s = 0; s < nsym; s++) if (len[s] == 0) code[s] = 0;
+}
+
+/* ------------------------------------------------------------- bit writer
+ * Bits are packed MSB-first into 32-bit words (bit 31 first); words are
+ * stored little-endian.                                                   */
+typedef struct {
+    uint32_t *words;
+    uint64_t nbits;
+} bitw;
+
+static void put_bits(bitw *bw, uint32_t value, int nbits) {
+    for (int i = nbits - 1; i >= 0; i--) {
+        uint32_t bit = (value >> i) & 1u;
+        uint64_t w = bw->nbits / 32;
+        int off = 31 - (int)(bw->nbits % 32);
+        if (off == 31) bw->words[w] = 0;
+        bw->words[w] |= bit << off;
+        bw->nbits++;
+    }
+}
+
+/* --------------------------------------------------- little-endian helpers */
+static void st16(uint8_t *p, uint16_t v) { p[0] = (uint8_t)v; p[1] = (uint8_t)(v >> 8); }
+static void st32(uint8_t *p, uint32_t v) { for (int i = 0; i < 4; i++) p[i] = (uint8_t)(v >> (8 * i)); }
+static void st64(uint8_t *p, uint64_t v) { for (int i = 0; i < 8; i++) p[i] = (uint8_t)(v >> (8 * i)); }
+static uint16_t ld16(const uint8_t *p) { return (uint16_t)(p[0] | (p[1] << 8)); }
+static uint32_t ld32(const uint8_t *p) {
+    uint32_t v = 0;
+    for (int i = 0; i < 4; i++) v |= (uint32_t)p[i] << (8 * i);
+    return v;
+}
+static uint64_t ld64(const uint8_t *p) {
+    uint64_t v = 0;
+    for (int i = 0; i < 8; i++) v |= (uint64_t)p[i] << (8 * i);
+    return v;
+}
+static uint64_t a16(uint64_t v) { return (v + 15) & ~15ull; }
+static uint64_t f64bits(double d) { uint64_t u; memcpy(&u, &d, 8); return u; }
+static double bitsf64(uint64_t u) { double d; memcpy(&d, &u, 8); return d; }
+
+/* ---------------------------------------------------------- container layout
+ * header (128 B) | code lengths, 4 bits each, 512 B | chunk bits u16[nblocks]
+ * | stream u32[words] | outlier pos u32[] | outlier residual i32[] |
+ * patch pos u32[] | patch float bits u32[]; every section starts on a
+ * 16-byte boundary and padding is zero.  Verbatim container: header with
+ * flag bit 0 set, then the raw floats in row-major order.                */
+typedef struct {
+    uint64_t lens, chunks, stream, opos, oval, ppos, pbits, total;
+} layout_t;
+
+static layout_t make_layout(uint64_t nblocks, uint64_t words, uint64_t nout, uint64_t npat) {
+    layout_t L;
+    L.lens = ORC_HDR;
+    L.chunks = L.lens + ORC_NBINS / 2;
+    L.stream = a16(L.chunks + 2 * nblocks);
+    L.opos = a16(L.stream + 4 * words);
+    L.oval = a16(L.opos + 4 * nout);
+    L.ppos = a16(L.oval + 4 * nout);
+    L.pbits = a16(L.ppos + 4 * npat);
+    L.total = a16(L.pbits + 4 * npat);
+    return L;
+}
+
+uint64_t orc_compress_bound(int ndim, const uint64_t dims[3]) {
+    geom_t g;
+    if (make_geom(ndim, dims, &g) != ORC_OK) return 0;
+    return ORC_HDR + 4 * g.N;
+}
+
+static void write_header(uint8_t *h, const geom_t *g, int flags, int mode, double eb, double eb_abs,
+                         uint64_t total, uint64_t nblocks, uint64_t nout, uint64_t npat,
+                         uint64_t words, uint64_t bits) {
+    memset(h, 0, ORC_HDR);
+    st32(h + 0, ORC_MAGIC);
+    st16(h + 4, ORC_VERSION);
+    st16(h + 6, (uint16_t)flags);
+    st32(h + 8, (uint32_t)g->ndim);
+    st32(h + 12, 0); /* predictor: first-order Lorenzo */
+    st64(h + 16, g->n[0]);
+    st64(h + 24, g->n[1]);
+    st64(h + 32, g->n[2]);
+    st32(h + 40, (uint32_t)mode);
+    st32(h + 44, ORC_RADIUS);
+    st64(h + 48, f64bits(eb));
+    st64(h + 56, f64bits(eb_abs));
+    st64(h + 64, total);
+    st32(h + 72, (uint32_t)nblocks);
+    st32(h + 76, (uint32_t)nout);
+    st32(h + 80, (uint32_t)npat);
+    st32(h + 84, (uint32_t)words);
+    st64(h + 88, bits);
+}
+
+/* ---------------------------------------------------------------- compress */
+int orc_compress(const float *x, int ndim, const uint64_t dims[3], int mode, double eb,
+                 uint8_t *out, uint64_t cap, uint64_t *out_bytes) {
+    geom_t g;
+    int rc = make_geom(ndim, dims, &g);
+    if (rc) return rc;
+    if (cap < ORC_HDR + 4 * g.N) return ORC_ERR_CAPACITY;
+    double eb_abs;
+    rc = orc_eb_abs(x, g.N, mode, eb, &eb_abs);
+    if (rc) return rc;
+    double e2 = 2.0 * eb_abs;
+
+    int32_t *q = (int32_t *)malloc(sizeof(int32_t) * g.N);
+    uint8_t *patch = (uint8_t *)malloc(g.N);
+    int32_t *delta = (int32_t *)malloc(sizeof(int32_t) * g.N);
+    elem_ref *refs = (elem_ref *)malloc(sizeof(elem_ref) * g.N);
+    uint32_t *bcount = (uint32_t *)malloc(sizeof(uint32_t) * g.nblocks);
+    uint16_t *codes = (uint16_t *)malloc(sizeof(uint16_t) * g.N);
+    if (!q || !patch || !delta || !refs || !bcount || !codes) {
+        free(q); free(patch); free(delta); free(refs); free(bcount); free(codes);
+        return ORC_ERR_NOMEM;
+    }
+    orc_prequant(x, g.N, eb_abs, q, patch);
+    orc_lorenzo1(q, ndim, dims, delta);
+    block_major_order(&g, refs, bcount);
+
+    /* codes, outliers and patches in block-major order */
+    uint64_t nout = 0, npat = 0;
+    for (uint64_t k = 0; k < g.N; k++) {
+        codes[k] = postquant(delta[refs[k].idx]);
+        if (codes[k] == 0) nout++;
+        if (patch[refs[k].idx]) npat++;
+    }
+    uint32_t hist[ORC_NBINS];
+    orc_histogram(codes, g.N, hist);
+    uint8_t len[ORC_NBINS];
+    uint32_t cw[ORC_NBINS];
+    orc_codebook(hist, len);
+    orc_canonical(len, ORC_NBINS, cw);
+
+    uint64_t bits = 0;
+    for (int s = 0; s < ORC_NBINS; s++) bits += (uint64_t)hist[s] * len[s];
+    uint64_t words = (bits + 31) / 32;
+    layout_t L = make_layout(g.nblocks, words, nout, npat);
+
+    if (L.total >= ORC_HDR + 4 * g.N) {
+        /* verbatim */
+        write_header(out, &g, 1, mode, eb, eb_abs, ORC_HDR + 4 * g.N, 0, 0, 0, 0, 0);
+        for (uint64_t i = 0; i < g.N; i++) memcpy(out + ORC_HDR + 4 * i, &x[i], 4);
+        *out_bytes = ORC_HDR + 4 * g.N;
+    } else {
+        memset(out, 0, L.total);
+        write_header(out, &g, 0, mode, eb, eb_abs, L.total, g.nblocks, nout, npat, words, bits);
+        for (int s = 0; s < ORC_NBINS; s++)
+            out[L.lens + s / 2] |= (uint8_t)((len[s] & 15) << (4 * (s % 2)));
+        uint32_t *stream = (uint32_t *)calloc(words + 1, sizeof(uint32_t));
+        bitw bw = {stream, 0};
+        uint64_t k = 0, io = 0, ip = 0;
+        for (uint64_t b = 0; b < g.nblocks; b++) {
+            uint64_t start = bw.nbits;
+            for (uint32_t e = 0; e < bcount[b]; e++, k++) {
+                put_bits(&bw, cw[codes[k]], len[codes[k]]);
+                if (codes[k] == 0) {
+                    st32(out + L.opos + 4 * io, refs[k].pos);
+                    st32(out + L.oval + 4 * io, (uint32_t)delta[refs[k].idx]);
+                    io++;
+                }
+                if (patch[refs[k].idx]) {
+                    uint32_t fb;
+                    memcpy(&fb, &x[refs[k].idx], 4);
+                    st32(out + L.ppos + 4 * ip, refs[k].pos);
+                    st32(out + L.pbits + 4 * ip, fb);
+                    ip++;
+                }
+            }
+            st16(out + L.chunks + 2 * b, (uint16_t)(bw.nbits - start));
+        }
+        for (uint64_t w = 0; w < words; w++) st32(out + L.stream + 4 * w, stream[w]);
+        free(stream);
+        *out_bytes = L.total;
+    }
+    (void)e2;
+    free(q); free(patch); free(delta); free(refs); free(bcount); free(codes);
+    return ORC_OK;
+}
+
+/* -------------------------------------------------------------- decompress
+ * Canonical decoding, one bit at a time: a codeword of length L is the
+ * L-bit value v with first[L] <= v < first[L] + count[L]; its symbol is
+ * the (v - first[L])-th symbol of length L in symbol order.              */
+int orc_header(const uint8_t *in, uint64_t n, int *ndim, uint64_t dims[3], int *mode,
+               double *eb, double *eb_abs, int *verbatim) {
+    if (n < ORC_HDR) return ORC_ERR_CORRUPT;
+    if (ld32(in) != ORC_MAGIC || ld16(in + 4) != ORC_VERSION) return ORC_ERR_CORRUPT;
+    *verbatim = ld16(in + 6) & 1;
+    *ndim = (int)ld32(in + 8);
+    dims[0] = ld64(in + 16);
+    dims[1] = ld64(in + 24);
+    dims[2] = ld64(in + 32);
+    *mode = (int)ld32(in + 40);
+    *eb = bitsf64(ld64(in + 48));
+    *eb_abs = bitsf64(ld64(in + 56));
+    return ORC_OK;
+}
+
+int orc_decompress(const uint8_t *in, uint64_t n, float *out, uint64_t out_elems) {
+    int ndim, mode, verbatim;
+    uint64_t dims[3];
+    double eb, eb_abs;
+    int rc = orc_header(in, n, &ndim, dims, &mode, &eb, &eb_abs, &verbatim);
+    if (rc) return rc;
+    geom_t g;
+    if (make_geom(ndim, dims, &g) != ORC_OK) return ORC_ERR_CORRUPT;
+    if (ld32(in + 12) != 0 || ld32(in + 44) != ORC_RADIUS) return ORC_ERR_UNSUPPORTED;
+    if (out_elems < g.N) return ORC_ERR_CAPACITY;
+    uint64_t total = ld64(in + 64);
+    if (total > n) return ORC_ERR_CORRUPT;
+    if (verbatim) {
+        if (total != ORC_HDR + 4 * g.N) return ORC_ERR_CORRUPT;
+        memcpy(out, in + ORC_HDR, 4 * g.N);
+        return ORC_OK;
+    }
+    if (!(eb_abs >= 1e-300 && eb_abs <= 1e300)) return ORC_ERR_CORRUPT;
+    uint64_t nblocks = ld32(in + 72), nout = ld32(in + 76), npat = ld32(in + 80);
+    uint64_t words = ld32(in + 84), bits = ld64(in + 88);
+    if (nblocks != g.nblocks || words != (bits + 31) / 32) return ORC_ERR_CORRUPT;
+    layout_t L = make_layout(nblocks, words, nout, npat);
+    if (L.total != total) return ORC_ERR_CORRUPT;
+
+    uint8_t len[ORC_NBINS];
+    for (int s = 0; s < ORC_NBINS; s++) len[s] = (in[L.lens + s / 2] >> (4 * (s % 2))) & 15;
+    /* the code must be complete: Kraft sum exactly 1 */
+    uint64_t kraft = 0;
+    int used = 0;
+    for (int s = 0; s < ORC_NBINS; s++) {
+        if (len[s] > ORC_LMAX) return ORC_ERR_CORRUPT;
+        if (len[s]) { kraft += 1ull << (ORC_LMAX - len[s]); used++; }
+    }
+    if (used < 2 || kraft != (1ull << ORC_LMAX)) return ORC_ERR_CORRUPT;
+    uint32_t first[ORC_LMAX + 2], count[ORC_LMAX + 2];
+    int symidx[ORC_LMAX + 2][ORC_NBINS];
+    uint32_t cw[ORC_NBINS];
+    orc_canonical(len, ORC_NBINS, cw);
+    for (int L2 = 0; L2 <= ORC_LMAX + 1; L2++) { first[L2] = 0xFFFFFFFFu; count[L2] = 0; }
+    for (int L2 = 1; L2 <= ORC_LMAX; L2++)
+        for (int s = 0; s < ORC_NBINS; s++)
+            if (len[s] == L2) {
+                if (count[L2] == 0) first[L2] = cw[s];
+                symidx[L2][count[L2]++] = s;
+            }
+
+    geom_t *gp = &g;
+    elem_ref *refs = (elem_ref *)malloc(sizeof(elem_ref) * g.N);
+    uint32_t *bcount = (uint32_t *)malloc(sizeof(uint32_t) * g.nblocks);
+    int32_t *delta = (int32_t *)malloc(sizeof(int32_t) * g.N);
+    int32_t *q = (int32_t *)malloc(sizeof(int32_t) * g.N);
+    if (!refs || !bcount || !delta || !q) {
+        free(refs); free(bcount); free(delta); free(q);
+        return ORC_ERR_NOMEM;
+    }
+    block_major_order(gp, refs, bcount);
+    const uint8_t *stream = in + L.stream;
+    uint64_t bitpos = 0, k = 0, io = 0;
+    rc = ORC_OK;
+    for (uint64_t b = 0; b < g.nblocks && rc == ORC_OK; b++) {
+        uint64_t start = bitpos;
+        for (uint32_t e = 0; e < bcount[b] && rc == ORC_OK; e++, k++) {
+            uint32_t v = 0;
+            int L2 = 0, sym = -1;
+            while (L2 < ORC_LMAX) {
+                if (bitpos >= bits) { rc = ORC_ERR_CORRUPT; break; }
+                uint32_t word = ld32(stream + 4 * (bitpos / 32));
+                uint32_t bit = (word >> (31 - bitpos % 32)) & 1u;
+                bitpos++;
+                v = (v << 1) | bit;
+                L2++;
+                if (count[L2] && v >= first[L2] && v - first[L2] < count[L2]) {
+                    sym = symidx[L2][v - first[L2]];
+                    break;
+                }
+            }
+            if (rc) break;
+            if (sym < 0) { rc = ORC_ERR_CORRUPT; break; }
+            int32_t d;
+            if (sym == 0) {
+                if (io >= nout || ld32(in + L.opos + 4 * io) != refs[k].pos) { rc = ORC_ERR_CORRUPT; break; }
+                d = (int32_t)ld32(in + L.oval + 4 * io);
+                io++;
+            } else {
+                d = sym - ORC_RADIUS;
+            }
+            delta[refs[k].idx] = d;
+        }
+        if (rc == ORC_OK && bitpos - start != ld16(in + L.chunks + 2 * b)) rc = ORC_ERR_CORRUPT;
+    }
+    if (rc == ORC_OK && (io != nout || bitpos != bits)) rc = ORC_ERR_CORRUPT;
+    if (rc == ORC_OK) {
+        orc_lorenzo1_inverse(delta, ndim, dims, q);
+        double e2 = 2.0 * eb_abs;
+        for (uint64_t i = 0; i < g.N; i++) out[i] = dequant(q[i], e2);
+        /* lossless patches: positions ascending, each names a real element */
+        uint64_t kk = 0;
+        uint32_t last = 0;
+        for (uint64_t ip = 0; ip < npat; ip++) {
+            uint32_t pos = ld32(in + L.ppos + 4 * ip);
+            uint32_t fb = ld32(in + L.pbits + 4 * ip);
+            if (ip > 0 && pos <= last) { rc = ORC_ERR_CORRUPT; break; }
+            last = pos;
+            while (kk < g.N && refs[kk].pos < pos) kk++;
+            if (kk >= g.N || refs[kk].pos != pos) { rc = ORC_ERR_CORRUPT; break; }
+            memcpy(&out[refs[kk].idx], &fb, 4);
+        }
+    }
+    free(refs); free(bcount); free(delta); free(q);
+    return rc;
+}
+
+/* ------------------------------------------------------- stage dumps (tests)
+ * Codes, outlier count and histogram exactly as compression computes them,
+ * in block-major order, for stage-level comparisons.                      */
+int orc_stage_codes(const float *x, int ndim, const uint64_t dims[3], int mode, double eb,
+                    uint16_t *codes_out, uint32_t *pos_out, uint32_t *hist_out, double *eb_abs_out) {
+    geom_t g;
+    int rc = make_geom(ndim, dims, &g);
+    if (rc) return rc;
+    double eb_abs;
+    rc = orc_eb_abs(x, g.N, mode, eb, &eb_abs);
+    if (rc) return rc;
+    int32_t *q = (int32_t *)malloc(sizeof(int32_t) * g.N);
+    uint8_t *patch = (uint8_t *)malloc(g.N);
+    int32_t *delta = (int32_t *)malloc(sizeof(int32_t) * g.N);
+    elem_ref *refs = (elem_ref *)malloc(sizeof(elem_ref) * g.N);
+    uint32_t *bcount = (uint32_t *)malloc(sizeof(uint32_t) * g.nblocks);
+    orc_prequant(x, g.N, eb_abs, q, patch);
+    orc_lorenzo1(q, ndim, dims, delta);
+    block_major_order(&g, refs, bcount);
+    for (uint64_t k = 0; k < g.N; k++) {
+        codes_out[k] = postquant(delta[refs[k].idx]);
+        if (pos_out) pos_out[k] = refs[k].pos;
+    }
+    orc_histogram(codes_out, g.N, hist_out);
+    *eb_abs_out = eb_abs;
+    free(q); free(patch); free(delta); free(refs); free(bcount);
+    return ORC_OK;
+}
+
+/* Encode a plain symbol sequence with the canonical code of len[] (tests). */
+uint64_t orc_encode_symbols(const uint16_t *syms, uint64_t n, const uint8_t *len, int nsym, uint32_t *words) {
+    uint32_t *cw = (uint32_t *)malloc(sizeof(uint32_t) * nsym);
+    orc_canonical(len, nsym, cw);
+    bitw bw = {words, 0};
+    for (uint64_t i = 0; i < n; i++) put_bits(&bw, cw[syms[i]], len[syms[i]]);
+    free(cw);
+    return bw.nbits;
+}
