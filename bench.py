@@ -1,0 +1,206 @@
+"""Benchmark: compress + decompress of a 512^3 float32 field on one MI355X.
+
+Workload (one "step"): the 512^3 Gaussian random field with P(k) ~ k^-3
+(seeded FFT synthesis, scaled to [0, 1]) is compressed and decompressed at
+value-range-relative error bounds 1e-2, 1e-3 and 1e-4 - three full round
+trips of the whole path (value range, prequantisation + Lorenzo + codes +
+histogram, Huffman code, encode, container; decode + inverse Lorenzo +
+patches).  Inputs and output buffers are resident in HBM before timing.
+
+Prints one JSON line.  `value` is round-trip throughput: input bytes
+(3 x 4 N per step) divided by the wall time of the timed steps.
+Per-stage times come from HIP events the library records on the stream
+the kernels run on, inside the timed region.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+EBS = (1e-2, 1e-3, 1e-4)
+SHAPE = (512, 512, 512)
+LINK_GBPS = 35.7  # the paper's measured GPU-to-host bandwidth on its H100 node (Table 1), for Eq. (1)
+
+
+def stage_bytes(stage: str, n: int, nblocks: int, h: dict, total: int) -> float:
+    """Algorithmic bytes one launch of a stage must move (see the design notes)."""
+    side = 8 * (h["n_outliers"] + h["n_patches"])
+    stream = 4 * h["stream_words"]
+    return {
+        "minmax": 4 * n,
+        "quant": 4 * n + 2 * n + side,
+        "encode": 2 * n + stream + 2 * nblocks,
+        "finalize": 2 * side,
+        "lut": 512,
+        "scan": 2 * nblocks + 8 * nblocks,
+        "decode": stream + 2 * nblocks + 8 * h["n_outliers"] + 4 * n,
+        "patch": 8 * h["n_patches"] + 4 * h["n_patches"],
+    }.get(stage, 0.0)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--shape", type=str, default="512,512,512")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see the design notes on sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from inputs import fields
+    from paper_2509_20563_amd import fz, metrics
+
+    shape = tuple(int(s) for s in args.shape.split(","))
+    n = int(np.prod(shape))
+    print(f"[bench] generating {shape} k^-3 field", file=sys.stderr, flush=True)
+    x_host = fields.grf(shape, alpha=3.0, seed=2)
+    dev = torch.device("cuda", 0)
+    x = torch.from_numpy(x_host).to(dev)
+    ctx = fz.Context(0, max_elems=n)
+    cap = ctx.compress_bound(shape)
+    outs = [torch.empty(cap, dtype=torch.uint8, device=dev) for _ in EBS]
+    recs = [torch.empty(shape, dtype=torch.float32, device=dev) for _ in EBS]
+    headers = [None] * len(EBS)
+    sizes = [0] * len(EBS)
+
+    def step(timed_stages=None):
+        for i, eb in enumerate(EBS):
+            c = ctx.compress(x, eb, fz.EB_REL, out=outs[i])
+            if timed_stages is not None:
+                for name, ms in ctx.stage_times():
+                    timed_stages.setdefault(("c", i, name), []).append(ms)
+            sizes[i] = c.numel()
+            if headers[i] is None:
+                headers[i] = c[:128].cpu().numpy().tobytes()
+            ctx.decompress(c, header=headers[i], out=recs[i])
+            if timed_stages is not None:
+                for name, ms in ctx.stage_times():
+                    timed_stages.setdefault(("d", i, name), []).append(ms)
+
+    print("[bench] warmup", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    ctx.set_timing(True)
+    stages: dict = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(stages)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.set_timing(False)
+    print("[bench] timed steps done", file=sys.stderr, flush=True)
+
+    # per-direction throughput (separate passes, after the timed region)
+    per_eb = []
+    parse_header = fz.header_fields
+    for i, eb in enumerate(EBS):
+        h = parse_header(headers[i])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            ctx.compress(x, eb, fz.EB_REL, out=outs[i])
+        torch.cuda.synchronize()
+        tc = (time.perf_counter() - t) / 3
+        c = outs[i][: sizes[i]]
+        t = time.perf_counter()
+        for _ in range(3):
+            ctx.decompress(c, header=headers[i], out=recs[i])
+        torch.cuda.synchronize()
+        td = (time.perf_counter() - t) / 3
+        err = (recs[i].double() - x.double()).abs().max().item()
+        rng = float(x_host.max()) - float(x_host.min())
+        mse = ((recs[i].double() - x.double()) ** 2).mean().item()
+        cr = metrics.compression_ratio(n, sizes[i])
+        comp = metrics.throughput_gbps(n, tc)
+        per_eb.append({
+            "eb_rel": eb, "eb_abs": h["eb_abs"], "bytes": sizes[i], "cr": round(cr, 4),
+            "bit_rate": round(metrics.bit_rate(n, sizes[i]), 4),
+            "psnr_db": round(20 * math.log10(rng / math.sqrt(mse)), 3) if mse > 0 else None,
+            "max_err_over_eb": err / h["eb_abs"],
+            "compress_gbps": round(comp, 2), "decompress_gbps": round(metrics.throughput_gbps(n, td), 2),
+            "n_outliers": h["n_outliers"], "n_patches": h["n_patches"], "verbatim": bool(h["flags"] & 1),
+            "eq1_speedup_at_35.7GBps": round(metrics.overall_speedup(LINK_GBPS, cr, comp), 3),
+        })
+
+    # dominant kernel and its roofline (HIP-event stage times inside the timed region)
+    nblocks = (-(-shape[-1] // 8)) * (-(-shape[-2] // 8)) * (-(-shape[0] // 8)) if len(shape) == 3 else 0
+    by_stage: dict = {}
+    for (d, i, name), ms in stages.items():
+        h = parse_header(headers[i])
+        key = ("compress:" if d == "c" else "decompress:") + name
+        e = by_stage.setdefault(key, {"ms": 0.0, "bytes": 0.0, "launches": 0})
+        e["ms"] += sum(ms)
+        e["launches"] += len(ms)
+        e["bytes"] += len(ms) * stage_bytes(name, n, nblocks, h, sizes[i])
+    dom_name, dom = max(by_stage.items(), key=lambda kv: kv[1]["ms"])
+    avg_ms = dom["ms"] / dom["launches"]
+    bytes_per_launch = dom["bytes"] / dom["launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": int(bytes_per_launch)}
+    stage_summary = {k: {"avg_ms": round(v["ms"] / v["launches"], 4),
+                         "gbps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
+                     for k, v in sorted(by_stage.items())}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(x_host)
+
+    value = 3 * 4.0 * n * args.steps / wall / 1e9
+    line = {
+        "metric": "compress/decompress GB/s and % HBM roofline on 1 MI355X; ratio at fixed eb",
+        "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{'x'.join(map(str, shape))} k^-3 Gaussian random field, rel eb 1e-2/1e-3/1e-4, "
+                               "compress + decompress per eb (first-order Lorenzo, radius 512, Huffman)",
+                   "n_values": n, "ebs": list(EBS)},
+        "per_eb": per_eb,
+        "stages": stage_summary,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(x_host):
+    """The CPU oracle, single-threaded, on the first half (z) of the same field
+    at all three bounds: round-trip GB/s of input."""
+    import numpy as np
+
+    import oracle
+
+    sample = np.ascontiguousarray(x_host[: x_host.shape[0] // 2])
+    print(f"[bench] cpu baseline on {sample.shape}", file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    for eb in EBS:
+        c = oracle.compress(sample, eb, 1)
+        oracle.decompress(c)
+    dt = time.perf_counter() - t
+    return {"value": round(3 * 4.0 * sample.size / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {sample.shape[0]} z-planes ({'x'.join(map(str, sample.shape))}) of the same field, "
+                      f"compress + decompress at rel eb 1e-2/1e-3/1e-4, single-threaded C oracle",
+            "seconds": round(dt, 2)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,127 @@
+/*
+ * fz.h - C ABI of the MI355X (gfx950) error-bounded compressor.
+ *
+ * The library implements the data-parallel path of the FZMod-Default pipeline
+ * of FZModules (Sec. 3.3): value-range or absolute error bound (Sec. 3.2
+ * preprocessing), dual-quantisation Lorenzo prediction with outliers
+ * (Sec. 3.1), a histogram of the quantisation codes and a Huffman code built
+ * from it (Sec. 3.2), chunked Huffman encoding, and the reverse path
+ * (Huffman decoding, outlier scatter and inverse Lorenzo, Sec. 1 and
+ * Sec. 3.3.1).  Every stage runs as a HIP kernel on the device; the
+ * Huffman stages, which FZMod-Default runs on the CPU, run on the GPU here.
+ *
+ * Conventions
+ *  - Pointers named d_* are device pointers; h_* are host pointers.
+ *  - A field is float32, row-major, dims[0] the fastest axis; unused axes of
+ *    dims are 1.  ndim is 1, 2 or 3.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    All work of a call is enqueued on it.
+ *  - The caller owns every buffer and the stream; the library never frees
+ *    them.  The context owns all scratch memory.
+ *  - Functions return FZ_OK (0) or a negative FZ_ERR_* code; no exception or
+ *    abort crosses the boundary.  On error, output contents are unspecified,
+ *    *h_out_bytes is 0, and the context stays usable.
+ *  - A context is used by one host thread at a time.  Calls on one context
+ *    are serialised by that thread; two contexts may run concurrently.
+ *
+ * Container ("FZM1", little-endian): a 128-byte header, the code lengths
+ * (4 bits per symbol, 1024 symbols), one u16 bit count per block, the
+ * bit-contiguous Huffman stream (u32 words, most significant bit first), the
+ * outliers (u32 position[], i32 residual[]) and the lossless patches
+ * (u32 position[], u32 float bits[]), each section 16-byte aligned.  When
+ * that would not be smaller than the raw data the container holds the raw
+ * floats instead ("verbatim", header flag bit 0).
+ */
+#ifndef FZ_H
+#define FZ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fz_ctx fz_ctx;
+
+/* Error-bound modes (Sec. 3.2 preprocessing, Sec. 4.2 metrics).
+ * FZ_EB_ABS: |x - x_hat| <= eb for every value.
+ * FZ_EB_REL: |x - x_hat| <= eb * (max(x) - min(x)); a constant field uses eb. */
+enum { FZ_EB_ABS = 0, FZ_EB_REL = 1 };
+
+/* Predictors.  FZ_PRED_LORENZO1: block-local first-order Lorenzo (Sec. 3.1). */
+enum { FZ_PRED_LORENZO1 = 0 };
+
+enum {
+    FZ_OK = 0,
+    FZ_ERR_ARG = -1,         /* bad ndim/dims/pointer/size argument             */
+    FZ_ERR_EB = -2,          /* eb not finite or <= 0, or resolved eb out of range */
+    FZ_ERR_NONFINITE = -3,   /* the field holds a NaN or an infinity            */
+    FZ_ERR_CAPACITY = -4,    /* output buffer smaller than required             */
+    FZ_ERR_CORRUPT = -5,     /* container fails validation                      */
+    FZ_ERR_HIP = -6,         /* a HIP runtime call failed                       */
+    FZ_ERR_NOMEM = -7,       /* device or host allocation failed                */
+    FZ_ERR_UNSUPPORTED = -8, /* valid but unsupported option (radius, predictor) */
+    FZ_ERR_INTERNAL = -9     /* a device-side consistency check failed          */
+};
+
+typedef struct {
+    uint32_t ndim;     /* 1, 2 or 3                                   */
+    uint64_t dims[3];  /* extents, dims[0] fastest; unused axes = 1  */
+    uint32_t eb_mode;  /* FZ_EB_ABS or FZ_EB_REL                      */
+    double eb;         /* > 0 and finite                              */
+    uint32_t pred;     /* FZ_PRED_LORENZO1                            */
+    uint32_t radius;   /* quantisation radius; 512 (1024 code bins)   */
+} fz_params;
+
+/* Create a context on HIP device `device`.  `max_elems` sizes the scratch
+ * memory up front (0 = allocate on first use); larger fields later grow it.
+ * Returns FZ_OK, FZ_ERR_ARG, FZ_ERR_HIP or FZ_ERR_NOMEM. */
+int fz_ctx_create(fz_ctx **out, int device, uint64_t max_elems);
+
+/* Release the context and its scratch memory (NULL is ignored). */
+void fz_ctx_destroy(fz_ctx *ctx);
+
+/* Bytes the output buffer of fz_compress must hold for these parameters:
+ * the larger of the verbatim container (128 + 4 N) and the packed sections
+ * written before the verbatim decision (about 656 + N / 256 + 1.5 N), rounded
+ * up to 16.  0 if the parameters are invalid. */
+uint64_t fz_compress_bound(const fz_params *p);
+
+/* Compress the field d_in (N floats, device) into d_out (device, out_cap
+ * bytes, out_cap >= fz_compress_bound).  Synchronises `stream` once and
+ * writes the container size to *h_out_bytes.  Sec. 3.1-3.3. */
+int fz_compress(fz_ctx *ctx, const fz_params *p, const float *d_in, void *d_out, uint64_t out_cap,
+                uint64_t *h_out_bytes, void *stream);
+
+/* Parse a container header held in host memory (at least 128 bytes).
+ * Fills *p, *n_elems (values in the field) and *total_bytes (container size).
+ * Returns FZ_OK or FZ_ERR_CORRUPT. */
+int fz_header_read(const void *h_hdr, uint64_t n, fz_params *p, uint64_t *n_elems, uint64_t *total_bytes);
+
+/* Decompress the container d_in (device, in_bytes) into d_out (device,
+ * out_elems >= N floats).  h_hdr is an optional host copy of the first 128
+ * bytes of the container (NULL: the library copies it from the device).
+ * Synchronises `stream` at the end to report validation errors.
+ * Returns FZ_OK, FZ_ERR_CORRUPT, FZ_ERR_CAPACITY, ... */
+int fz_decompress(fz_ctx *ctx, const void *d_in, uint64_t in_bytes, const void *h_hdr, float *d_out,
+                  uint64_t out_elems, void *stream);
+
+/* Human-readable text for a status code (static storage). */
+const char *fz_strerror(int status);
+
+/* Per-stage timing.  When enabled, compress/decompress record HIP events
+ * around each kernel on the call's stream; fz_stage_times then returns the
+ * stage durations in milliseconds of the last call (count in *n).
+ * Stage names are given by fz_stage_name. */
+int fz_set_timing(fz_ctx *ctx, int enable);
+int fz_stage_times(fz_ctx *ctx, float *h_ms, int max, int *n);
+const char *fz_stage_name(fz_ctx *ctx, int i);
+
+/* Stage dump for parity checks: the 1024-bin code histogram of the last
+ * successful fz_compress call on this context (Sec. 3.2). */
+int fz_last_histogram(fz_ctx *ctx, uint32_t *h_hist);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FZ_H */

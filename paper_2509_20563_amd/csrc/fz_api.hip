@@ -1,0 +1,508 @@
+// Host implementation of the fz C ABI (include/fz.h): argument validation,
+// scratch management, kernel sequencing on the caller's stream, and the
+// container header on the host side.
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/fz.h"
+#include "fz_common.h"
+#include "fz_kernels.h"
+
+using namespace fz;
+
+namespace {
+
+constexpr int kMaxStages = 16;
+
+template <class T>
+hipError_t grow(T*& p, uint64_t& cap, uint64_t need) {
+    if (need <= cap && p) return hipSuccess;
+    if (p) hipFree(p);
+    p = nullptr;
+    cap = 0;
+    hipError_t e = hipMalloc((void**)&p, sizeof(T) * (need ? need : 1));
+    if (e == hipSuccess) cap = need;
+    return e;
+}
+
+}  // namespace
+
+struct fz_ctx {
+    int device = 0;
+    int n_cu = 256;
+    Misc* misc = nullptr;
+    Misc* h_misc = nullptr;  // pinned
+    uint8_t* h_hdr = nullptr;  // pinned, 128 B
+    uint32_t* hist = nullptr;
+    uint32_t* cw = nullptr;
+    uint16_t* lut = nullptr;
+    uint16_t* codes = nullptr;
+    uint64_t codes_cap = 0;
+    uint32_t* opos = nullptr;
+    int32_t* oval = nullptr;
+    uint32_t* ppos = nullptr;
+    uint32_t* pbits = nullptr;
+    uint64_t opos_cap = 0, oval_cap = 0, ppos_cap = 0, pbits_cap = 0;
+    uint64_t* qdesc = nullptr;
+    uint64_t* edesc = nullptr;
+    uint64_t* tstart = nullptr;
+    uint32_t* tfirst = nullptr;
+    uint32_t* tlast = nullptr;
+    uint64_t qdesc_cap = 0, edesc_cap = 0, tstart_cap = 0, tfirst_cap = 0, tlast_cap = 0;
+    uint64_t* off = nullptr;
+    uint32_t* ofirst = nullptr;
+    uint64_t* sdesc = nullptr;
+    uint64_t off_cap = 0, ofirst_cap = 0, sdesc_cap = 0;
+    // timing
+    bool timing = false;
+    hipEvent_t ev[kMaxStages + 1] = {};
+    int nev = 0;
+    const char* names[kMaxStages] = {};
+    float ms[kMaxStages] = {};
+    int nstages = 0;
+    bool have_hist = false;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
+    }
+};
+
+int make_geom(uint32_t ndim, const uint64_t dims[3], Geom* g) {
+    if (ndim < 1 || ndim > 3) return FZ_ERR_ARG;
+    Geom r = {};
+    r.ndim = ndim;
+    uint64_t n[3];
+    for (int a = 0; a < 3; a++) {
+        n[a] = (a < (int)ndim) ? dims[a] : 1;
+        if (n[a] < 1 || n[a] > 0xFFFFFFFFull) return FZ_ERR_ARG;
+        r.n[a] = (uint32_t)n[a];
+    }
+    if (ndim == 1) { r.bs[0] = 512; r.bs[1] = 1; r.bs[2] = 1; }
+    else if (ndim == 2) { r.bs[0] = 32; r.bs[1] = 16; r.bs[2] = 1; }
+    else { r.bs[0] = 8; r.bs[1] = 8; r.bs[2] = 8; }
+    uint64_t nb = 1;
+    for (int a = 0; a < 3; a++) {
+        uint64_t k = (n[a] + r.bs[a] - 1) / r.bs[a];
+        r.nb[a] = (uint32_t)k;
+        nb *= k;
+        if (nb > (1ull << 23)) return FZ_ERR_ARG;  // positions must fit u32
+    }
+    r.nblocks = (uint32_t)nb;
+    r.N = n[0] * n[1] * n[2];
+    *g = r;
+    return FZ_OK;
+}
+
+int check_params(const fz_params* p, Geom* g) {
+    if (!p) return FZ_ERR_ARG;
+    int rc = make_geom(p->ndim, p->dims, g);
+    if (rc) return rc;
+    if (p->eb_mode != FZ_EB_ABS && p->eb_mode != FZ_EB_REL) return FZ_ERR_ARG;
+    if (!(p->eb > 0.0) || !__builtin_isfinite(p->eb)) return FZ_ERR_EB;
+    if (p->pred != FZ_PRED_LORENZO1) return FZ_ERR_UNSUPPORTED;
+    if (p->radius != 0 && p->radius != (uint32_t)kRadius) return FZ_ERR_UNSUPPORTED;
+    return FZ_OK;
+}
+
+// Output bytes a call may write: the verbatim container, or the packed
+// sections the kernels write before the verbatim decision (code lengths,
+// chunk table and a stream of at most 12 bits per value).
+uint64_t bound_of(const Geom& g) {
+    const uint64_t verbatim = (uint64_t)kHdr + 4 * g.N;
+    const uint64_t packed = make_layout(g.nblocks, (12 * g.N + 31) / 32, 0, 0).total;
+    return align16(verbatim > packed ? verbatim : packed);
+}
+
+int ensure(fz_ctx* c, const Geom& g) {
+    const uint64_t nb = g.nblocks;
+    const uint64_t ntiles = (nb + kTileBlocks - 1) / kTileBlocks;
+    const uint64_t stage = g.N / 2 + 64;
+    const uint64_t stiles = (nb + 1023) / 1024;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = grow(c->codes, c->codes_cap, nb * kBlockElems);
+    if (e == hipSuccess) e = grow(c->opos, c->opos_cap, stage);
+    if (e == hipSuccess) e = grow(c->oval, c->oval_cap, stage);
+    if (e == hipSuccess) e = grow(c->ppos, c->ppos_cap, stage);
+    if (e == hipSuccess) e = grow(c->pbits, c->pbits_cap, stage);
+    if (e == hipSuccess) e = grow(c->qdesc, c->qdesc_cap, ntiles);
+    if (e == hipSuccess) e = grow(c->edesc, c->edesc_cap, ntiles);
+    if (e == hipSuccess) e = grow(c->tstart, c->tstart_cap, ntiles);
+    if (e == hipSuccess) e = grow(c->tfirst, c->tfirst_cap, ntiles);
+    if (e == hipSuccess) e = grow(c->tlast, c->tlast_cap, ntiles);
+    if (e == hipSuccess) e = grow(c->off, c->off_cap, nb);
+    if (e == hipSuccess) e = grow(c->ofirst, c->ofirst_cap, nb);
+    if (e == hipSuccess) e = grow(c->sdesc, c->sdesc_cap, stiles);
+    return e == hipSuccess ? FZ_OK : FZ_ERR_NOMEM;
+}
+
+// Stage timing helpers (events on the call's stream).
+void t_begin(fz_ctx* c, hipStream_t st) {
+    c->nev = 0;
+    c->nstages = 0;
+    if (!c->timing) return;
+    hipEventRecord(c->ev[0], st);
+    c->nev = 1;
+}
+void t_mark(fz_ctx* c, hipStream_t st, const char* name) {
+    if (!c->timing || c->nev > kMaxStages) return;
+    hipEventRecord(c->ev[c->nev], st);
+    c->names[c->nev - 1] = name;
+    c->nev++;
+}
+void t_end(fz_ctx* c) {
+    if (!c->timing) return;
+    c->nstages = c->nev - 1;
+    for (int i = 0; i < c->nstages; i++) {
+        float m = 0.0f;
+        hipEventElapsedTime(&m, c->ev[i], c->ev[i + 1]);
+        c->ms[i] = m;
+    }
+}
+
+void st32(uint8_t* h, int o, uint32_t v) { for (int k = 0; k < 4; k++) h[o + k] = (uint8_t)(v >> (8 * k)); }
+void st64(uint8_t* h, int o, uint64_t v) { for (int k = 0; k < 8; k++) h[o + k] = (uint8_t)(v >> (8 * k)); }
+uint32_t ld32(const uint8_t* h, int o) {
+    uint32_t v = 0;
+    for (int k = 0; k < 4; k++) v |= (uint32_t)h[o + k] << (8 * k);
+    return v;
+}
+uint64_t ld64(const uint8_t* h, int o) {
+    uint64_t v = 0;
+    for (int k = 0; k < 8; k++) v |= (uint64_t)h[o + k] << (8 * k);
+    return v;
+}
+double bits_f64(uint64_t u) {
+    double d;
+    memcpy(&d, &u, 8);
+    return d;
+}
+uint64_t f64_bits(double d) {
+    uint64_t u;
+    memcpy(&u, &d, 8);
+    return u;
+}
+
+int flags_status(uint32_t f) {
+    if (f & F_NONFINITE) return FZ_ERR_NONFINITE;
+    if (f & F_EB) return FZ_ERR_EB;
+    if (f & (F_INTERNAL | F_TIMEOUT)) return FZ_ERR_INTERNAL;
+    if (f & F_CORRUPT) return FZ_ERR_CORRUPT;
+    return FZ_OK;
+}
+
+struct Parsed {
+    fz_params p;
+    Geom g;
+    int verbatim;
+    double eb_abs;
+    uint64_t total, nblocks, nout, npat, words, bits;
+};
+
+int parse_header(const uint8_t* h, uint64_t n, Parsed* r) {
+    if (!h || n < (uint64_t)kHdr) return FZ_ERR_CORRUPT;
+    if (ld32(h, 0) != kMagic || (h[4] | (h[5] << 8)) != kVersion) return FZ_ERR_CORRUPT;
+    const int flags = h[6] | (h[7] << 8);
+    if (flags & ~1) return FZ_ERR_CORRUPT;
+    memset(r, 0, sizeof(*r));
+    r->verbatim = flags & 1;
+    r->p.ndim = ld32(h, 8);
+    r->p.pred = ld32(h, 12);
+    r->p.dims[0] = ld64(h, 16);
+    r->p.dims[1] = ld64(h, 24);
+    r->p.dims[2] = ld64(h, 32);
+    r->p.eb_mode = ld32(h, 40);
+    r->p.radius = ld32(h, 44);
+    r->p.eb = bits_f64(ld64(h, 48));
+    r->eb_abs = bits_f64(ld64(h, 56));
+    r->total = ld64(h, 64);
+    r->nblocks = ld32(h, 72);
+    r->nout = ld32(h, 76);
+    r->npat = ld32(h, 80);
+    r->words = ld32(h, 84);
+    r->bits = ld64(h, 88);
+    if (make_geom(r->p.ndim, r->p.dims, &r->g) != FZ_OK) return FZ_ERR_CORRUPT;
+    if (r->p.pred != FZ_PRED_LORENZO1 || r->p.radius != (uint32_t)kRadius) return FZ_ERR_CORRUPT;
+    if (r->p.eb_mode > 1) return FZ_ERR_CORRUPT;
+    if (r->verbatim) {
+        if (r->total != (uint64_t)kHdr + 4 * r->g.N) return FZ_ERR_CORRUPT;
+        return FZ_OK;
+    }
+    if (!(r->eb_abs >= 1e-300 && r->eb_abs <= 1e300)) return FZ_ERR_CORRUPT;
+    if (r->nblocks != r->g.nblocks || r->words != (r->bits + 31) / 32) return FZ_ERR_CORRUPT;
+    if (r->nout > r->g.N || r->npat > r->g.N) return FZ_ERR_CORRUPT;
+    const Layout L = make_layout(r->nblocks, r->words, r->nout, r->npat);
+    if (L.total != r->total) return FZ_ERR_CORRUPT;
+    return FZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fz_ctx_create(fz_ctx** out, int device, uint64_t max_elems) {
+    if (!out) return FZ_ERR_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FZ_ERR_ARG;
+    fz_ctx* c = new (std::nothrow) fz_ctx();
+    if (!c) return FZ_ERR_NOMEM;
+    c->device = device;
+    DeviceGuard dg(device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->n_cu = prop.multiProcessorCount;
+    bool ok = hipMalloc((void**)&c->misc, sizeof(Misc)) == hipSuccess &&
+              hipMalloc((void**)&c->hist, sizeof(uint32_t) * kBins) == hipSuccess &&
+              hipMalloc((void**)&c->cw, sizeof(uint32_t) * kBins) == hipSuccess &&
+              hipMalloc((void**)&c->lut, sizeof(uint16_t) * kLut) == hipSuccess &&
+              hipHostMalloc((void**)&c->h_misc, sizeof(Misc), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc((void**)&c->h_hdr, kHdr, hipHostMallocDefault) == hipSuccess;
+    for (int i = 0; ok && i <= kMaxStages; i++) ok = hipEventCreate(&c->ev[i]) == hipSuccess;
+    if (ok && max_elems) {
+        uint64_t dims[3] = {max_elems, 1, 1};
+        Geom g;
+        // a dense 3D field of max_elems values needs about max_elems/512 blocks
+        if (make_geom(1, dims, &g) == FZ_OK) ok = ensure(c, g) == FZ_OK;
+    }
+    if (!ok) {
+        fz_ctx_destroy(c);
+        return FZ_ERR_NOMEM;
+    }
+    *out = c;
+    return FZ_OK;
+}
+
+void fz_ctx_destroy(fz_ctx* c) {
+    if (!c) return;
+    DeviceGuard dg(c->device);
+    hipFree(c->misc);
+    hipFree(c->hist);
+    hipFree(c->cw);
+    hipFree(c->lut);
+    hipFree(c->codes);
+    hipFree(c->opos);
+    hipFree(c->oval);
+    hipFree(c->ppos);
+    hipFree(c->pbits);
+    hipFree(c->qdesc);
+    hipFree(c->edesc);
+    hipFree(c->tstart);
+    hipFree(c->tfirst);
+    hipFree(c->tlast);
+    hipFree(c->off);
+    hipFree(c->ofirst);
+    hipFree(c->sdesc);
+    if (c->h_misc) hipHostFree(c->h_misc);
+    if (c->h_hdr) hipHostFree(c->h_hdr);
+    for (int i = 0; i <= kMaxStages; i++)
+        if (c->ev[i]) hipEventDestroy(c->ev[i]);
+    delete c;
+}
+
+uint64_t fz_compress_bound(const fz_params* p) {
+    Geom g;
+    if (check_params(p, &g) != FZ_OK) return 0;
+    return bound_of(g);
+}
+
+int fz_compress(fz_ctx* c, const fz_params* p, const float* d_in, void* d_out, uint64_t out_cap,
+                uint64_t* h_out_bytes, void* stream) {
+    if (h_out_bytes) *h_out_bytes = 0;
+    if (!c || !d_in || !d_out || !h_out_bytes) return FZ_ERR_ARG;
+    Geom g;
+    int rc = check_params(p, &g);
+    if (rc) return rc;
+    if (((uintptr_t)d_in & 3) || ((uintptr_t)d_out & 15)) return FZ_ERR_ARG;
+    if (out_cap < bound_of(g)) return FZ_ERR_CAPACITY;
+    DeviceGuard dg(c->device);
+    rc = ensure(c, g);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    uint8_t* out = (uint8_t*)d_out;
+    const uint32_t ntiles = (g.nblocks + kTileBlocks - 1) / kTileBlocks;
+    const int vec = (((uintptr_t)d_in & 15) == 0) && (g.ndim == 1 || (g.n[0] & 3) == 0);
+    const uint64_t stage = g.N / 2 + 64;
+    c->have_hist = false;
+
+    t_begin(c, st);
+    launch_reset(st, c->misc, c->hist, c->qdesc, ntiles, c->edesc, ntiles);
+    t_mark(c, st, "reset");
+    if (p->eb_mode == FZ_EB_REL) {
+        uint64_t work = (g.N + 4 * 256 - 1) / (4 * 256);
+        uint64_t grid = work < (uint64_t)c->n_cu * 16 ? work : (uint64_t)c->n_cu * 16;
+        if (grid < 1) grid = 1;
+        launch_minmax(st, d_in, g.N, (((uintptr_t)d_in & 15) == 0), c->misc, (int)grid);
+        t_mark(c, st, "minmax");
+    }
+    {
+        uint64_t grid = ntiles < (uint64_t)c->n_cu * 8 ? ntiles : (uint64_t)c->n_cu * 8;
+        launch_quant(st, (int)grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, c->qdesc, ntiles,
+                     c->opos, c->oval, stage, c->ppos, c->pbits, stage);
+        t_mark(c, st, "quant");
+    }
+    launch_codebook(st, c->hist, out + kHdr, c->cw, c->misc);
+    t_mark(c, st, "codebook");
+    launch_encode(st, c->codes, g, c->cw, c->misc, c->edesc, ntiles, out, c->tstart, c->tfirst, c->tlast);
+    t_mark(c, st, "encode");
+    launch_finalize(st, g, p->eb_mode, p->eb, c->misc, out, c->tstart, c->tfirst, c->tlast, ntiles, c->opos,
+                    c->oval, c->ppos, c->pbits);
+    t_mark(c, st, "finalize");
+    if (hipMemcpyAsync(c->h_misc, c->misc, sizeof(Misc), hipMemcpyDeviceToHost, st) != hipSuccess) return FZ_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
+    if (hipGetLastError() != hipSuccess) return FZ_ERR_HIP;
+    t_end(c);
+    const Misc m = *c->h_misc;
+    rc = flags_status(m.flags & ~(uint32_t)F_CORRUPT);
+    if (rc) return rc;
+    c->have_hist = true;
+    if (m.verbatim) {
+        double eb_abs;
+        resolve_eb(p->eb_mode, p->eb, m.mm_lo, m.mm_hi, &eb_abs);
+        uint8_t* h = c->h_hdr;
+        memset(h, 0, kHdr);
+        st32(h, 0, kMagic);
+        h[4] = (uint8_t)kVersion;
+        h[5] = (uint8_t)(kVersion >> 8);
+        h[6] = 1;
+        st32(h, 8, g.ndim);
+        st32(h, 12, 0);
+        st64(h, 16, g.n[0]);
+        st64(h, 24, g.n[1]);
+        st64(h, 32, g.n[2]);
+        st32(h, 40, p->eb_mode);
+        st32(h, 44, kRadius);
+        st64(h, 48, f64_bits(p->eb));
+        st64(h, 56, f64_bits(eb_abs));
+        st64(h, 64, (uint64_t)kHdr + 4 * g.N);
+        if (hipMemcpyAsync(out, h, kHdr, hipMemcpyHostToDevice, st) != hipSuccess) return FZ_ERR_HIP;
+        if (hipMemcpyAsync(out + kHdr, d_in, 4 * g.N, hipMemcpyDeviceToDevice, st) != hipSuccess) return FZ_ERR_HIP;
+        if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
+        *h_out_bytes = (uint64_t)kHdr + 4 * g.N;
+        return FZ_OK;
+    }
+    *h_out_bytes = m.total_bytes;
+    return FZ_OK;
+}
+
+int fz_header_read(const void* h_hdr, uint64_t n, fz_params* p, uint64_t* n_elems, uint64_t* total_bytes) {
+    Parsed r;
+    int rc = parse_header((const uint8_t*)h_hdr, n, &r);
+    if (rc) return rc;
+    if (p) *p = r.p;
+    if (n_elems) *n_elems = r.g.N;
+    if (total_bytes) *total_bytes = r.total;
+    return FZ_OK;
+}
+
+int fz_decompress(fz_ctx* c, const void* d_in, uint64_t in_bytes, const void* h_hdr, float* d_out,
+                  uint64_t out_elems, void* stream) {
+    if (!c || !d_in || !d_out) return FZ_ERR_ARG;
+    if (((uintptr_t)d_in & 15) || ((uintptr_t)d_out & 3)) return FZ_ERR_ARG;
+    if (in_bytes < (uint64_t)kHdr) return FZ_ERR_CORRUPT;
+    DeviceGuard dg(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    const uint8_t* in = (const uint8_t*)d_in;
+    const uint8_t* hh = (const uint8_t*)h_hdr;
+    if (!hh) {
+        if (hipMemcpyAsync(c->h_hdr, in, kHdr, hipMemcpyDeviceToHost, st) != hipSuccess) return FZ_ERR_HIP;
+        if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
+        hh = c->h_hdr;
+    }
+    Parsed r;
+    int rc = parse_header(hh, kHdr, &r);
+    if (rc) return rc;
+    if (r.total > in_bytes) return FZ_ERR_CORRUPT;
+    const Geom& g = r.g;
+    if (out_elems < g.N) return FZ_ERR_CAPACITY;
+    t_begin(c, st);
+    if (r.verbatim) {
+        if (hipMemcpyAsync(d_out, in + kHdr, 4 * g.N, hipMemcpyDeviceToDevice, st) != hipSuccess) return FZ_ERR_HIP;
+        t_mark(c, st, "copy");
+        if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
+        t_end(c);
+        return FZ_OK;
+    }
+    rc = ensure(c, g);
+    if (rc) return rc;
+    const Layout L = make_layout(r.nblocks, r.words, r.nout, r.npat);
+    const uint32_t stiles = (g.nblocks + 1023) / 1024;
+    const int vec = (((uintptr_t)d_out & 15) == 0) && (g.ndim == 1 || (g.n[0] & 3) == 0);
+    launch_reset(st, c->misc, c->hist, c->sdesc, stiles, nullptr, 0);
+    t_mark(c, st, "reset");
+    launch_lut(st, in + L.lens, c->lut, c->misc);
+    t_mark(c, st, "lut");
+    launch_scan_chunks(st, (const uint16_t*)(in + L.chunks), g.nblocks, c->off, c->sdesc, c->misc, r.bits);
+    t_mark(c, st, "scan");
+    launch_decode(st, g, (const uint32_t*)(in + L.stream), r.words, c->off, (const uint16_t*)(in + L.chunks),
+                  c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->ofirst, r.nout,
+                  2.0 * r.eb_abs, d_out, vec, c->misc);
+    t_mark(c, st, "decode");
+    launch_patch(st, g, (const uint32_t*)(in + L.ppos), (const uint32_t*)(in + L.pbits), r.npat, d_out, c->misc);
+    t_mark(c, st, "patch");
+    if (hipMemcpyAsync(c->h_misc, c->misc, sizeof(Misc), hipMemcpyDeviceToHost, st) != hipSuccess) return FZ_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
+    if (hipGetLastError() != hipSuccess) return FZ_ERR_HIP;
+    t_end(c);
+    const Misc m = *c->h_misc;
+    rc = flags_status(m.flags);
+    if (rc) return rc;
+    if (m.code0_count != r.nout) return FZ_ERR_CORRUPT;
+    return FZ_OK;
+}
+
+const char* fz_strerror(int s) {
+    switch (s) {
+        case FZ_OK: return "ok";
+        case FZ_ERR_ARG: return "invalid argument";
+        case FZ_ERR_EB: return "invalid error bound";
+        case FZ_ERR_NONFINITE: return "field holds NaN or infinity";
+        case FZ_ERR_CAPACITY: return "output buffer too small";
+        case FZ_ERR_CORRUPT: return "corrupt container";
+        case FZ_ERR_HIP: return "HIP runtime error";
+        case FZ_ERR_NOMEM: return "out of memory";
+        case FZ_ERR_UNSUPPORTED: return "unsupported option";
+        case FZ_ERR_INTERNAL: return "internal consistency check failed";
+        default: return "unknown status";
+    }
+}
+
+int fz_set_timing(fz_ctx* c, int enable) {
+    if (!c) return FZ_ERR_ARG;
+    c->timing = enable != 0;
+    return FZ_OK;
+}
+
+int fz_stage_times(fz_ctx* c, float* h_ms, int max, int* n) {
+    if (!c || (!h_ms && max > 0)) return FZ_ERR_ARG;
+    int k = c->nstages < max ? c->nstages : max;
+    for (int i = 0; i < k; i++) h_ms[i] = c->ms[i];
+    if (n) *n = c->nstages;
+    return FZ_OK;
+}
+
+const char* fz_stage_name(fz_ctx* c, int i) {
+    if (!c || i < 0 || i >= c->nstages) return "";
+    return c->names[i];
+}
+
+int fz_last_histogram(fz_ctx* c, uint32_t* h_hist) {
+    if (!c || !h_hist) return FZ_ERR_ARG;
+    if (!c->have_hist) return FZ_ERR_ARG;
+    DeviceGuard dg(c->device);
+    if (hipMemcpy(h_hist, c->hist, sizeof(uint32_t) * kBins, hipMemcpyDeviceToHost) != hipSuccess) return FZ_ERR_HIP;
+    return FZ_OK;
+}
+
+}  // extern "C"

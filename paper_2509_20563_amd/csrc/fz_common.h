@@ -1,0 +1,271 @@
+// Internal definitions shared by the HIP translation units of libfz.
+// Geometry of the blocked field, device scratch layout, and device helpers
+// (ordered float encoding, decoupled look-back, canonical Huffman ranks).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fz {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------- constants
+constexpr int kRadius = 512;      // residuals -511..511 map to codes 1..1023
+constexpr int kBins = 1024;       // code 0 marks an outlier
+constexpr int kLmax = 12;         // longest Huffman codeword, LUT index width
+constexpr int kLut = 1 << kLmax;  // decode table entries
+constexpr int kHdr = 128;         // container header bytes
+constexpr int kBlockElems = 512;  // values per full block
+constexpr int kSegs = 64;         // 8-value segments per block
+constexpr int kTileBlocks = 4;    // blocks per workgroup tile (256 threads)
+constexpr uint32_t kMagic = 0x314D5A46u;  // "FZM1"
+constexpr uint16_t kVersion = 1;
+
+// flag bits raised by kernels in Misc::flags
+enum : uint32_t {
+    F_NONFINITE = 1u,
+    F_EB = 2u,
+    F_OVERFLOW = 4u,   // outlier/patch staging full: the container goes verbatim
+    F_CORRUPT = 8u,
+    F_INTERNAL = 16u,
+    F_TIMEOUT = 32u,   // a bounded look-back wait gave up
+};
+
+// Per-call device scratch, cleared by k_reset.
+struct Misc {
+    uint32_t flags;
+    uint32_t mm_lo, mm_hi;     // order-preserving encodings of min and max
+    uint32_t qtile_ctr;        // dynamic tile counters (look-back order)
+    uint32_t etile_ctr;
+    uint32_t stile_ctr;
+    uint32_t code0_count;      // decode: outlier codes seen
+    uint32_t pad0;
+    uint64_t total_bits_cb;    // sum hist[c] * len[c]
+    uint64_t total_bits_enc;   // end of the last encoded tile
+    uint64_t n_out;            // outliers (inclusive count of the last tile)
+    uint64_t n_pat;            // lossless patches
+    uint64_t total_bytes;      // container size (non-verbatim)
+    uint64_t verbatim;         // 1 when the packed container is not smaller
+    double eb_abs;
+    uint64_t pad1[3];
+};
+
+// Field geometry: dims, block shape, block grid.
+struct Geom {
+    uint32_t ndim;
+    uint32_t n[3];   // extents (unused axes 1)
+    uint32_t bs[3];  // block extents: 1D 512; 2D 32x16; 3D 8x8x8
+    uint32_t nb[3];  // blocks per axis
+    uint32_t nblocks;
+    uint64_t N;
+};
+
+// Block coordinates and real extents of block b.
+struct BlockInfo {
+    uint32_t bx, by, bz;
+    uint32_t ex, ey, ez;
+};
+
+__host__ __device__ inline BlockInfo block_info(const Geom& g, uint32_t b) {
+    BlockInfo r;
+    r.bx = b % g.nb[0];
+    uint32_t t = b / g.nb[0];
+    r.by = t % g.nb[1];
+    r.bz = t / g.nb[1];
+    uint32_t x0 = r.bx * g.bs[0], y0 = r.by * g.bs[1], z0 = r.bz * g.bs[2];
+    r.ex = min(g.bs[0], g.n[0] - x0);
+    r.ey = min(g.bs[1], g.n[1] - y0);
+    r.ez = min(g.bs[2], g.n[2] - z0);
+    return r;
+}
+
+// Segment s (0..63) of a block = 8 consecutive values along x:
+//   3D: row (ly, lz) = (s % 8, s / 8), x from 0;  2D: x from 8 * (s % 4), ly = s / 4;
+//   1D: x from 8 * s.  In-block offset of value i of segment s is 8 * s + i.
+template <int ND>
+__host__ __device__ inline void seg_coords(uint32_t s, uint32_t& lx0, uint32_t& ly, uint32_t& lz) {
+    if (ND == 3) { lx0 = 0; ly = s & 7; lz = s >> 3; }
+    else if (ND == 2) { lx0 = 8 * (s & 3); ly = s >> 2; lz = 0; }
+    else { lx0 = 8 * s; ly = 0; lz = 0; }
+}
+
+// Row-major index of the first value of segment s in block (bi), and the
+// number of real values in the segment (0..8).
+template <int ND>
+__host__ __device__ inline uint64_t seg_index(const Geom& g, const BlockInfo& bi, uint32_t s, uint32_t& nvalid) {
+    uint32_t lx0, ly, lz;
+    seg_coords<ND>(s, lx0, ly, lz);
+    if (ly >= bi.ey || lz >= bi.ez || lx0 >= bi.ex) {
+        nvalid = 0;
+        return 0;
+    }
+    nvalid = min(8u, bi.ex - lx0);
+    uint64_t x = (uint64_t)bi.bx * g.bs[0] + lx0;
+    uint64_t y = (uint64_t)bi.by * g.bs[1] + ly;
+    uint64_t z = (uint64_t)bi.bz * g.bs[2] + lz;
+    return x + (uint64_t)g.n[0] * (y + (uint64_t)g.n[1] * z);
+}
+
+// Container section offsets (each 16-byte aligned).
+struct Layout {
+    uint64_t lens, chunks, stream, opos, oval, ppos, pbits, total;
+};
+
+__host__ __device__ inline uint64_t align16(uint64_t v) { return (v + 15) & ~15ull; }
+
+__host__ __device__ inline Layout make_layout(uint64_t nblocks, uint64_t words, uint64_t nout, uint64_t npat) {
+    Layout L;
+    L.lens = kHdr;
+    L.chunks = L.lens + kBins / 2;
+    L.stream = align16(L.chunks + 2 * nblocks);
+    L.opos = align16(L.stream + 4 * words);
+    L.oval = align16(L.opos + 4 * nout);
+    L.ppos = align16(L.oval + 4 * nout);
+    L.pbits = align16(L.ppos + 4 * npat);
+    L.total = align16(L.pbits + 4 * npat);
+    return L;
+}
+
+// ------------------------------------------------------- device helpers
+// Order-preserving map float -> u32 (unsigned compare = float compare).
+__device__ inline uint32_t ord_f32(float f) {
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ inline float unord_f32(uint32_t o) {
+    uint32_t u = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+}
+
+// Absolute bound from the mode: absolute, or eb times the value range
+// (range 0 -> eb).  Returns false when the bound is out of [1e-300, 1e300].
+__host__ __device__ inline bool resolve_eb(uint32_t mode, double eb, uint32_t mm_lo, uint32_t mm_hi, double* eb_abs) {
+    double e = eb;
+    if (mode == 1) {
+        double range = (double)unord_f32(mm_hi) - (double)unord_f32(mm_lo);
+        e = (range > 0.0) ? eb * range : eb;
+    }
+    *eb_abs = e;
+    return e >= 1e-300 && e <= 1e300;
+}
+
+// Decoupled look-back (single-pass prefix scan over tiles taken in order
+// from an atomic counter).  desc[t] holds status (2 high bits: 1 = tile
+// aggregate, 2 = inclusive prefix) and a 62-bit payload combined by Op.
+// Called by one thread per tile; returns the exclusive prefix.  The wait
+// on a predecessor is bounded: after the spin limit the tile raises
+// F_TIMEOUT and proceeds, so every wave always exits.
+constexpr uint64_t kStAgg = 1ull << 62;
+constexpr uint64_t kStInc = 2ull << 62;
+constexpr uint64_t kPayload = (1ull << 62) - 1;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+template <class Op>
+__device__ inline uint64_t lookback(uint64_t* desc, uint32_t t, uint64_t agg, Op op, uint32_t* flags) {
+    if (t == 0) {
+        __hip_atomic_store(&desc[0], kStInc | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return 0;
+    }
+    __hip_atomic_store(&desc[t], kStAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t excl = 0;
+    int64_t j = (int64_t)t - 1;
+    uint32_t spins = 0;
+    while (j >= 0) {
+        uint64_t d = __hip_atomic_load(&desc[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t st = d >> 62;
+        if (st == 0) {
+            if (++spins > kSpinLimit) {
+                atomicOr(flags, F_TIMEOUT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl = op(d & kPayload, excl);
+        if (st == 2) break;
+        --j;
+    }
+    __hip_atomic_store(&desc[t], kStInc | op(excl, agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return excl;
+}
+
+struct OpAdd {
+    __device__ uint64_t operator()(uint64_t a, uint64_t b) const { return (a + b) & kPayload; }
+};
+
+// Two saturating 31-bit counters in one payload (outliers low, patches high).
+struct OpPair31 {
+    __device__ uint64_t operator()(uint64_t a, uint64_t b) const {
+        const uint64_t m = (1ull << 31) - 1;
+        uint64_t lo = (a & m) + (b & m);
+        uint64_t hi = (a >> 31) + (b >> 31);
+        if (lo > m) lo = m;
+        if (hi > m) hi = m;
+        return lo | (hi << 31);
+    }
+};
+
+// Wave-level inclusive scan (64 lanes).
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// Canonical Huffman code assignment inside one 1024-thread workgroup:
+// thread t owns symbol t with length len (0 = unused).  Symbols are ordered
+// by (length, symbol); each gets the first code of its length plus its rank.
+// Produces code[t] and, in shared memory, count[L], first[L] and the
+// symbols sorted by (length, symbol) (sorted[offset[L] + rank]).
+struct CanonShared {
+    uint32_t wave_cnt[kLmax + 1][16];
+    uint32_t count[kLmax + 2];
+    uint32_t first[kLmax + 2];
+    uint32_t offset[kLmax + 2];
+    uint16_t sorted[kBins];
+};
+
+__device__ inline uint32_t canonical_code(uint32_t len, CanonShared& sh) {
+    const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    uint32_t myrank = 0;
+    for (int L = 1; L <= kLmax; L++) {
+        uint64_t m = __ballot(len == (uint32_t)L);
+        if (lane == 0) sh.wave_cnt[L][wave] = __popcll(m);
+        if (len == (uint32_t)L) myrank = __popcll(m & ((1ull << lane) - 1));
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint32_t code = 0, off = 0;
+        for (int L = 1; L <= kLmax; L++) {
+            uint32_t c = 0;
+            for (int w = 0; w < 16; w++) {
+                uint32_t v = sh.wave_cnt[L][w];
+                sh.wave_cnt[L][w] = c;  // exclusive prefix over waves
+                c += v;
+            }
+            sh.count[L] = c;
+            sh.first[L] = code;
+            sh.offset[L] = off;
+            code = (code + c) << 1;
+            off += c;
+        }
+    }
+    __syncthreads();
+    uint32_t code = 0;
+    if (len > 0) {
+        uint32_t r = sh.wave_cnt[len][wave] + myrank;
+        code = sh.first[len] + r;
+        sh.sorted[sh.offset[len] + r] = (uint16_t)t;
+    }
+    __syncthreads();
+    return code;
+}
+
+}  // namespace fz

@@ -1,0 +1,378 @@
+// Decompression (FZModules Sec. 1 and Sec. 3.3.1 describe it as Huffman
+// decoding of the quantisation codes plus scattering of the outliers into
+// the reconstruction; the inverse of the Lorenzo predictor is a prefix sum):
+//   k_lut          - validates the code lengths, builds a 4096-entry table
+//   k_scan_chunks  - exclusive scan of the per-block bit counts
+//   k_decode       - one lane per block: table-driven Huffman decode from a
+//                    per-lane window staged in LDS, outlier overwrite,
+//                    in-block prefix sums (inverse Lorenzo), dequantisation,
+//                    row stores - codes never leave registers
+//   k_patch        - lossless patches written over the reconstruction
+#include "fz_common.h"
+#include "fz_kernels.h"
+
+namespace fz {
+
+// ----------------------------------------------------------- decode table
+// Entry for the 12-bit prefix v: (length << 10) | symbol of the codeword
+// that v starts with.  The lengths must describe a complete code (Kraft sum
+// exactly 1, every length 1..12, at least two symbols).
+__global__ __launch_bounds__(1024) void k_lut(const uint8_t* __restrict__ lensp, uint16_t* __restrict__ lut,
+                                              Misc* misc) {
+    __shared__ CanonShared cs;
+    __shared__ uint32_t rk[16], ru[16], rb[16];
+    const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    uint32_t len = (lensp[t >> 1] >> (4 * (t & 1))) & 15u;
+    const uint32_t bad = len > (uint32_t)kLmax ? 1u : 0u;
+    uint32_t kr = (len && !bad) ? (1u << (kLmax - len)) : 0u;
+    uint32_t used = len ? 1u : 0u;
+    uint32_t bb = bad;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        kr += __shfl_xor(kr, d, 64);
+        used += __shfl_xor(used, d, 64);
+        bb += __shfl_xor(bb, d, 64);
+    }
+    if (lane == 0) {
+        rk[wave] = kr;
+        ru[wave] = used;
+        rb[wave] = bb;
+    }
+    __syncthreads();
+    uint32_t K = 0, U = 0, B = 0;
+    for (int w = 0; w < 16; w++) {
+        K += rk[w];
+        U += ru[w];
+        B += rb[w];
+    }
+    const bool ok = B == 0 && K == (uint32_t)kLut && U >= 2;
+    if (!ok) {
+        if (t == 0) atomicOr(&misc->flags, F_CORRUPT);
+        for (uint32_t v = t; v < (uint32_t)kLut; v += 1024) lut[v] = 0;
+        return;
+    }
+    canonical_code(len, cs);
+    for (uint32_t v = t; v < (uint32_t)kLut; v += 1024) {
+        uint16_t e = 0;
+        for (int L = 1; L <= kLmax; L++) {
+            const uint32_t c = cs.count[L];
+            if (!c) continue;
+            const uint32_t end = (cs.first[L] + c) << (kLmax - L);
+            if (v < end) {
+                const uint32_t idx = (v >> (kLmax - L)) - cs.first[L];
+                e = (uint16_t)((L << 10) | cs.sorted[cs.offset[L] + idx]);
+                break;
+            }
+        }
+        lut[v] = e;
+    }
+}
+
+// ------------------------------------------------------ chunk offset scan
+constexpr int kScanTile = 1024;
+
+__global__ __launch_bounds__(256) void k_scan_chunks(const uint16_t* __restrict__ chunks, uint32_t nblocks,
+                                                     uint64_t* __restrict__ off, uint64_t* desc, Misc* misc,
+                                                     uint64_t stream_bits, uint32_t ntiles) {
+    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_G;
+    const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    if (t == 0) s_tile = atomicAdd(&misc->stile_ctr, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    if (tile >= ntiles) return;
+    const uint64_t base = (uint64_t)tile * kScanTile + 4 * t;
+    uint32_t v[4];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        v[k] = (base + k < nblocks) ? chunks[base + k] : 0u;
+        sum += v[k];
+    }
+    const uint32_t incl = wave_incl_scan(sum);
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t wpre = 0, T = 0;
+    for (uint32_t w = 0; w < 4; w++) {
+        if (w < wave) wpre += wsum[w];
+        T += wsum[w];
+    }
+    if (t == 0) {
+        const uint64_t G = lookback(desc, tile, (uint64_t)T, OpAdd(), &misc->flags);
+        s_G = G;
+        if (tile == ntiles - 1 && G + T != stream_bits) atomicOr(&misc->flags, F_CORRUPT);
+    }
+    __syncthreads();
+    uint64_t p = s_G + wpre + incl - sum;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        if (base + k < nblocks) off[base + k] = p;
+        p += v[k];
+    }
+}
+
+// ----------------------------------------------------------------- decode
+constexpr int kWin = 20;  // words staged per lane and round (5 x 16 B)
+
+struct LaneStream {
+    const uint32_t* stream;
+    uint64_t nwords;
+    uint32_t* win;   // this lane's window in LDS
+    uint64_t aw;     // first staged word (multiple of 4)
+    uint32_t rel;    // bit position relative to aw * 32
+
+    // Stage the words holding the next 32 codewords (at most 384 bits).
+    __device__ __forceinline__ void stage(uint64_t bitpos) {
+        aw = (bitpos >> 5) & ~3ull;
+        rel = (uint32_t)(bitpos - aw * 32);
+        uint4* w4 = reinterpret_cast<uint4*>(win);
+        if (aw + kWin <= nwords) {
+            const uint4* s4 = reinterpret_cast<const uint4*>(stream + aw);
+#pragma unroll
+            for (int k = 0; k < kWin / 4; k++) w4[k] = s4[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < kWin; k++) win[k] = (aw + k < nwords) ? stream[aw + k] : 0u;
+        }
+    }
+    __device__ __forceinline__ uint64_t bitpos() const { return aw * 32 + rel; }
+};
+
+template <int ND>
+__global__ __launch_bounds__(256) void k_decode(Geom g, const uint32_t* __restrict__ stream, uint64_t nwords,
+                                                const uint64_t* __restrict__ off, const uint16_t* __restrict__ chunks,
+                                                const uint16_t* __restrict__ lut_g, const uint32_t* __restrict__ opos,
+                                                const int32_t* __restrict__ oval,
+                                                const uint32_t* __restrict__ ofirst, uint64_t n_out, double e2,
+                                                float* __restrict__ out, int vec, Misc* misc) {
+    __shared__ uint16_t LUT[kLut];
+    __shared__ uint32_t WIN[256 * kWin];
+    const uint32_t t = threadIdx.x;
+    for (uint32_t i = t; i < (uint32_t)kLut; i += 256) LUT[i] = lut_g[i];
+    __syncthreads();
+    const uint32_t b = blockIdx.x * 256 + t;
+    if (b >= g.nblocks) return;
+    const BlockInfo info = block_info(g, b);
+    const uint64_t start = off[b];
+    LaneStream ls;
+    ls.stream = stream;
+    ls.nwords = nwords;
+    ls.win = &WIN[t * kWin];
+    uint32_t optr = ~0u;
+    uint32_t code0 = 0;
+    bool bad = false;
+    const uint32_t pos_b = b * kBlockElems;
+    (void)pos_b;
+
+    // decode one codeword; outliers (code 0) take their residual from the
+    // list, starting at the block's first outlier (ofirst, valid only for
+    // blocks that have outliers: every use is bounds- and position-checked)
+    auto next = [&](uint32_t pos) -> int32_t {
+        const uint32_t wi = ls.rel >> 5, sh = ls.rel & 31;
+        const uint32_t w0 = ls.win[wi], w1 = ls.win[wi + 1];
+        const uint64_t v = (((uint64_t)w0 << 32) | w1) << sh;
+        const uint32_t e = LUT[(uint32_t)(v >> (64 - kLmax))];
+        ls.rel += e >> 10;
+        const uint32_t sym = e & 1023u;
+        if (sym) return (int32_t)sym - kRadius;
+        code0++;
+        if (optr == ~0u) optr = ofirst[b];
+        int32_t d = 0;
+        if (optr < n_out && opos[optr] == pos) d = oval[optr];
+        else bad = true;
+        optr++;
+        return d;
+    };
+    auto deq = [&](int32_t q) -> float { return (float)((double)q * e2); };
+    auto store8 = [&](uint64_t idx, const float* v, uint32_t nvalid) {
+        if (nvalid == 8 && vec) {
+            f32x4* p = reinterpret_cast<f32x4*>(out + idx);
+            f32x4 a = {v[0], v[1], v[2], v[3]};
+            f32x4 c = {v[4], v[5], v[6], v[7]};
+            __builtin_nontemporal_store(a, p);
+            __builtin_nontemporal_store(c, p + 1);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; i++)
+                if (i < (int)nvalid) out[idx + i] = v[i];
+        }
+    };
+
+    ls.aw = 0;
+    ls.rel = 0;
+    uint64_t bp = start;
+    if (ND == 3) {
+        int32_t qp[64];
+#pragma unroll
+        for (int i = 0; i < 64; i++) qp[i] = 0;
+        const uint64_t x0 = (uint64_t)info.bx * 8;
+        for (uint32_t z = 0; z < info.ez; z++) {
+            int32_t pr[8];
+#pragma unroll
+            for (int i = 0; i < 8; i++) pr[i] = 0;
+#pragma unroll
+            for (int half = 0; half < 2; half++) {
+                ls.stage(bp);
+#pragma unroll
+                for (int yy = 0; yy < 4; yy++) {
+                    const int y = half * 4 + yy;
+                    if ((uint32_t)y < info.ey) {
+                        int32_t rs = 0;
+                        float v[8];
+#pragma unroll
+                        for (int x = 0; x < 8; x++) {
+                            int32_t d = 0;
+                            if ((uint32_t)x < info.ex) d = next(pos_b + x + 8 * y + 64 * z);
+                            rs += d;
+                            pr[x] += rs;
+                            qp[y * 8 + x] += pr[x];
+                            v[x] = deq(qp[y * 8 + x]);
+                        }
+                        const uint64_t yg = (uint64_t)info.by * 8 + y, zg = (uint64_t)info.bz * 8 + z;
+                        store8(x0 + (uint64_t)g.n[0] * (yg + (uint64_t)g.n[1] * zg), v, info.ex);
+                    }
+                }
+                bp = ls.bitpos();
+            }
+        }
+    } else if (ND == 2) {
+        int32_t qp[32];
+#pragma unroll
+        for (int i = 0; i < 32; i++) qp[i] = 0;
+        for (uint32_t y = 0; y < info.ey; y++) {
+            ls.stage(bp);
+            int32_t rs = 0;
+            const uint64_t row = (uint64_t)info.bx * 32 + (uint64_t)g.n[0] * ((uint64_t)info.by * 16 + y);
+#pragma unroll
+            for (int x8 = 0; x8 < 4; x8++) {
+                float v[8];
+#pragma unroll
+                for (int i = 0; i < 8; i++) {
+                    const int x = x8 * 8 + i;
+                    int32_t d = 0;
+                    if ((uint32_t)x < info.ex) d = next(pos_b + x + 32 * y);
+                    rs += d;
+                    qp[x] += rs;
+                    v[i] = deq(qp[x]);
+                }
+                if ((uint32_t)(x8 * 8) < info.ex) store8(row + x8 * 8, v, min(8u, info.ex - x8 * 8));
+            }
+            bp = ls.bitpos();
+        }
+    } else {
+        int32_t acc = 0;
+        const uint64_t row = (uint64_t)b * kBlockElems;
+        for (uint32_t r = 0; r * 32 < info.ex; r++) {
+            ls.stage(bp);
+#pragma unroll
+            for (int k8 = 0; k8 < 4; k8++) {
+                float v[8];
+#pragma unroll
+                for (int i = 0; i < 8; i++) {
+                    const uint32_t idx = r * 32 + k8 * 8 + i;
+                    int32_t d = 0;
+                    if (idx < info.ex) d = next(pos_b + idx);
+                    acc += d;
+                    v[i] = deq(acc);
+                }
+                const uint32_t i0 = r * 32 + k8 * 8;
+                if (i0 < info.ex) store8(row + i0, v, min(8u, info.ex - i0));
+            }
+            bp = ls.bitpos();
+        }
+    }
+    if (bp - start != chunks[b]) bad = true;
+    if (bad) atomicOr(&misc->flags, F_CORRUPT);
+    uint32_t c = code0;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
+    if ((t & 63) == 0 && c) atomicAdd(&misc->code0_count, c);
+}
+
+// ------------------------------------------------------ outlier block index
+// ofirst[b] = index of the first outlier of block b (blocks with outliers).
+__global__ __launch_bounds__(256) void k_outlier_index(const uint32_t* __restrict__ opos, uint64_t n_out,
+                                                       uint32_t nblocks, uint32_t* __restrict__ ofirst) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_out; i += stride) {
+        const uint32_t b = opos[i] >> 9;
+        if (b < nblocks && (i == 0 || (opos[i - 1] >> 9) != b)) ofirst[b] = (uint32_t)i;
+    }
+}
+
+// ----------------------------------------------------------------- patches
+template <int ND>
+__global__ __launch_bounds__(256) void k_patch(Geom g, const uint32_t* __restrict__ ppos,
+                                               const uint32_t* __restrict__ pbits, uint64_t n_pat,
+                                               float* __restrict__ out, Misc* misc) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pat; i += stride) {
+        const uint32_t pos = ppos[i];
+        const uint32_t b = pos >> 9, local = pos & 511u;
+        bool ok = b < g.nblocks && (i == 0 || ppos[i - 1] < pos);
+        if (ok) {
+            const BlockInfo info = block_info(g, b);
+            uint32_t lx, ly, lz;
+            if (ND == 3) { lx = local & 7; ly = (local >> 3) & 7; lz = local >> 6; }
+            else if (ND == 2) { lx = local & 31; ly = local >> 5; lz = 0; }
+            else { lx = local; ly = 0; lz = 0; }
+            ok = lx < info.ex && ly < info.ey && lz < info.ez;
+            if (ok) {
+                const uint64_t x = (uint64_t)info.bx * g.bs[0] + lx;
+                const uint64_t y = (uint64_t)info.by * g.bs[1] + ly;
+                const uint64_t z = (uint64_t)info.bz * g.bs[2] + lz;
+                out[x + (uint64_t)g.n[0] * (y + (uint64_t)g.n[1] * z)] = __uint_as_float(pbits[i]);
+            }
+        }
+        if (!ok) atomicOr(&misc->flags, F_CORRUPT);
+    }
+}
+
+// ------------------------------------------------------------- launchers
+void launch_lut(hipStream_t st, const uint8_t* lens_packed, uint16_t* lut, Misc* misc) {
+    hipLaunchKernelGGL(k_lut, dim3(1), dim3(1024), 0, st, lens_packed, lut, misc);
+}
+
+void launch_scan_chunks(hipStream_t st, const uint16_t* chunks, uint32_t nblocks, uint64_t* off, uint64_t* desc,
+                        Misc* misc, uint64_t stream_bits) {
+    const uint32_t ntiles = (nblocks + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_chunks, dim3(ntiles), dim3(256), 0, st, chunks, nblocks, off, desc, misc,
+                       stream_bits, ntiles);
+}
+
+void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,
+                   const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
+                   const int32_t* oval, uint32_t* ofirst, uint64_t n_out, double e2, float* out, int vec,
+                   Misc* misc) {
+    if (n_out) {
+        uint64_t og = (n_out + 255) / 256;
+        if (og > 4096) og = 4096;
+        hipLaunchKernelGGL(k_outlier_index, dim3((uint32_t)og), dim3(256), 0, st, opos, n_out, g.nblocks, ofirst);
+    }
+    const uint32_t grid = (g.nblocks + 255) / 256;
+    if (g.ndim == 3)
+        hipLaunchKernelGGL(k_decode<3>, dim3(grid), dim3(256), 0, st, g, stream, stream_words, off, chunks, lut,
+                           opos, oval, ofirst, n_out, e2, out, vec, misc);
+    else if (g.ndim == 2)
+        hipLaunchKernelGGL(k_decode<2>, dim3(grid), dim3(256), 0, st, g, stream, stream_words, off, chunks, lut,
+                           opos, oval, ofirst, n_out, e2, out, vec, misc);
+    else
+        hipLaunchKernelGGL(k_decode<1>, dim3(grid), dim3(256), 0, st, g, stream, stream_words, off, chunks, lut,
+                           opos, oval, ofirst, n_out, e2, out, vec, misc);
+}
+
+void launch_patch(hipStream_t st, const Geom& g, const uint32_t* ppos, const uint32_t* pbits, uint64_t n_pat,
+                  float* out, Misc* misc) {
+    if (n_pat == 0) return;
+    uint64_t grid = (n_pat + 255) / 256;
+    if (grid > 4096) grid = 4096;
+    if (g.ndim == 3)
+        hipLaunchKernelGGL(k_patch<3>, dim3((uint32_t)grid), dim3(256), 0, st, g, ppos, pbits, n_pat, out, misc);
+    else if (g.ndim == 2)
+        hipLaunchKernelGGL(k_patch<2>, dim3((uint32_t)grid), dim3(256), 0, st, g, ppos, pbits, n_pat, out, misc);
+    else
+        hipLaunchKernelGGL(k_patch<1>, dim3((uint32_t)grid), dim3(256), 0, st, g, ppos, pbits, n_pat, out, misc);
+}
+
+}  // namespace fz

@@ -1,0 +1,358 @@
+// Huffman stages of compression (FZModules Sec. 3.2: the Huffman encoder
+// builds its code from the histogram of quantisation codes; FZMod-Default
+// runs this on the CPU, here it runs on the GPU):
+//   k_codebook - length-limited minimum-redundancy code lengths by
+//                package-merge in one workgroup, canonical codewords;
+//   k_encode   - chunked encoding (chunk = block), bit offsets by
+//                decoupled look-back, words assembled in LDS;
+//   k_finalize - tile-boundary words, outlier/patch sections, header.
+#include "fz_common.h"
+#include "fz_kernels.h"
+
+namespace fz {
+
+// ------------------------------------------------------------ codebook
+// Package-merge (Larmore & Hirschberg): leaves = used symbols sorted by
+// (count, symbol); list[kLmax] = leaves; list[l] = merge(leaves,
+// packages of list[l+1]) with equal weights putting the leaf first; select
+// the first 2n-2 items of list[1], each selected package standing for the
+// next two items one level deeper.  A symbol's length is the number of
+// levels at which it is selected.  Leaves keep their sorted order in every
+// list, so a level is summarised by a bitmask of leaf positions.
+__global__ __launch_bounds__(1024) void k_codebook(const uint32_t* __restrict__ hist, uint8_t* __restrict__ out_lens,
+                                                   uint32_t* __restrict__ cw, Misc* misc) {
+    __shared__ uint64_t key[kBins];
+    __shared__ uint64_t la[2 * kBins], lb[2 * kBins];
+    __shared__ uint32_t mask[kLmax + 1][64];
+    __shared__ uint32_t klev[kLmax + 2];
+    __shared__ uint8_t slen[kBins];
+    __shared__ uint32_t s_first_unused;
+    __shared__ uint64_t red[16];
+    __shared__ CanonShared cs;
+
+    const uint32_t t = threadIdx.x;
+    const uint32_t h = hist[t];
+    slen[t] = 0;
+    key[t] = h ? (((uint64_t)h << 10) | t) : ~0ull;
+    if (t == 0) s_first_unused = kBins;
+    const int n = __syncthreads_count(h > 0);
+
+    if (n == 1) {
+        if (h == 0) atomicMin(&s_first_unused, t);
+        __syncthreads();
+        if (h > 0) slen[t] = 1;
+        if (t == s_first_unused) slen[t] = 1;
+    } else if (n >= 2) {
+        // bitonic sort of (count << 10 | symbol), unused symbols last
+        for (uint32_t k = 2; k <= (uint32_t)kBins; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                __syncthreads();
+                const uint32_t ixj = t ^ j;
+                if (ixj > t) {
+                    uint64_t a = key[t], b = key[ixj];
+                    const bool up = (t & k) == 0;
+                    if ((a > b) == up) {
+                        key[t] = b;
+                        key[ixj] = a;
+                    }
+                }
+            }
+        }
+        for (int l = 0; l <= kLmax; l++)
+            if (t < 64) mask[l][t] = 0;
+        __syncthreads();
+        const uint64_t wleaf = (t < (uint32_t)n) ? (key[t] >> 10) : 0;
+        if (t < (uint32_t)n) {
+            la[t] = wleaf;
+            atomicOr(&mask[kLmax][t >> 5], 1u << (t & 31));
+        }
+        uint64_t* cur = la;
+        uint64_t* nxt = lb;
+        uint32_t len_cur = n;
+        __syncthreads();
+        for (int l = kLmax - 1; l >= 1; l--) {
+            const uint32_t np = len_cur / 2;
+            if (t < (uint32_t)n) {
+                // packages strictly lighter than this leaf come before it
+                uint32_t lo = 0, hi = np;
+                while (lo < hi) {
+                    uint32_t mid = (lo + hi) >> 1;
+                    if (cur[2 * mid] + cur[2 * mid + 1] < wleaf) lo = mid + 1;
+                    else hi = mid;
+                }
+                const uint32_t r = t + lo;
+                nxt[r] = wleaf;
+                atomicOr(&mask[l][r >> 5], 1u << (r & 31));
+            }
+            if (t < np) {
+                const uint64_t pw = cur[2 * t] + cur[2 * t + 1];
+                // leaves not heavier than this package come before it
+                uint32_t lo = 0, hi = (uint32_t)n;
+                while (lo < hi) {
+                    uint32_t mid = (lo + hi) >> 1;
+                    if ((key[mid] >> 10) <= pw) lo = mid + 1;
+                    else hi = mid;
+                }
+                nxt[t + lo] = pw;
+            }
+            __syncthreads();
+            uint64_t* tmp = cur;
+            cur = nxt;
+            nxt = tmp;
+            len_cur = (uint32_t)n + np;
+        }
+        if (t == 0) {
+            uint32_t take = 2 * (uint32_t)n - 2;
+            for (int l = 1; l <= kLmax; l++) {
+                if (take > 2 * kBins - 1) take = 2 * kBins - 1;
+                uint32_t k = 0;
+                const uint32_t full = take >> 5;
+                for (uint32_t w = 0; w < full; w++) k += __popc(mask[l][w]);
+                if (take & 31) k += __popc(mask[l][full] & ((1u << (take & 31)) - 1u));
+                klev[l] = k;
+                take = 2 * (take - k);
+            }
+        }
+        __syncthreads();
+        if (t < (uint32_t)n) {
+            uint32_t L = 0;
+            for (int l = 1; l <= kLmax; l++) L += (t < klev[l]) ? 1u : 0u;
+            slen[key[t] & 1023] = (uint8_t)L;
+        }
+    }
+    __syncthreads();
+    const uint32_t len = slen[t];
+    const uint32_t code = canonical_code(len, cs);
+    cw[t] = code | (len << 16);
+    // total stream bits = sum count * length
+    uint64_t v = (uint64_t)h * len;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+    if ((t & 63) == 0) red[t >> 6] = v;
+    if (t < 512) out_lens[t] = (uint8_t)(slen[2 * t] | (slen[2 * t + 1] << 4));
+    __syncthreads();
+    if (t == 0) {
+        uint64_t s = 0;
+        for (int w = 0; w < 16; w++) s += red[w];
+        misc->total_bits_cb = s;
+    }
+}
+
+// --------------------------------------------------------------- encode
+// Append `len` bits of `code` at bit position nb of a 128-bit string held
+// most-significant-bit first in (hi, lo).
+__device__ __forceinline__ void append_bits(uint64_t& hi, uint64_t& lo, uint32_t& nb, uint32_t code, uint32_t len) {
+    // the codeword occupies bits [nb, nb + len): as a 128-bit value it is
+    // code << (128 - nb - len); both halves are formed with in-range shifts
+    const uint32_t end = nb + len;
+    const uint32_t sh = 128 - end;  // 32..127
+    const uint64_t c = code;
+    const bool upper = sh >= 64;
+    hi |= upper ? (c << ((sh - 64) & 63)) : (c >> ((64 - sh) & 63));
+    lo |= upper ? 0ull : (c << (sh & 63));
+    nb = end;
+}
+
+constexpr int kEncWords = kTileBlocks * kBlockElems * kLmax / 32 + 8;
+
+// One workgroup encodes one tile of 4 blocks (thread = block*64 + segment).
+template <int ND>
+__global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ codes, Geom g,
+                                                const uint32_t* __restrict__ cw_g, Misc* misc, uint64_t* desc,
+                                                uint32_t ntiles, uint8_t* __restrict__ out, uint64_t off_chunks,
+                                                uint64_t off_stream, uint64_t* __restrict__ tstart,
+                                                uint32_t* __restrict__ tfirst, uint32_t* __restrict__ tlast) {
+    __shared__ uint32_t CW[kBins];
+    __shared__ uint32_t W[kEncWords];
+    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_G;
+
+    const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (uint32_t i = t; i < (uint32_t)kBins; i += 256) CW[i] = cw_g[i];
+    for (uint32_t i = t; i < (uint32_t)kEncWords; i += 256) W[i] = 0;
+    if (t == 0) s_tile = atomicAdd(&misc->etile_ctr, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    if (tile >= ntiles) return;
+
+    const uint32_t s = t & 63;
+    const uint32_t b = tile * kTileBlocks + wave;
+    uint32_t nv = 0;
+    uint4 pk = make_uint4(0, 0, 0, 0);
+    if (b < g.nblocks) {
+        BlockInfo info = block_info(g, b);
+        seg_index<ND>(g, info, s, nv);
+        if (nv) pk = *reinterpret_cast<const uint4*>(&codes[(uint64_t)b * kBlockElems + s * 8]);
+    }
+    const uint32_t c8[8] = {pk.x & 0xFFFFu, pk.x >> 16, pk.y & 0xFFFFu, pk.y >> 16,
+                            pk.z & 0xFFFFu, pk.z >> 16, pk.w & 0xFFFFu, pk.w >> 16};
+    uint64_t hi = 0, lo = 0;
+    uint32_t nb = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        if (i < (int)nv) {
+            const uint32_t e = CW[c8[i]];
+            append_bits(hi, lo, nb, e & 0xFFFFu, e >> 16);
+        }
+    }
+    // bit offsets: wave scan (one wave = one block), then across the tile
+    const uint32_t incl = wave_incl_scan(nb);
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t wpre = 0, T = 0;
+    for (uint32_t w = 0; w < 4; w++) {
+        if (w < wave) wpre += wsum[w];
+        T += wsum[w];
+    }
+    if (lane == 63 && b < g.nblocks) {
+        uint16_t* chunks = reinterpret_cast<uint16_t*>(out + off_chunks);
+        chunks[b] = (uint16_t)incl;
+    }
+    if (t == 0) {
+        const uint64_t G = lookback(desc, tile, (uint64_t)T, OpAdd(), &misc->flags);
+        s_G = G;
+        tstart[tile] = G;
+        if (tile == ntiles - 1) misc->total_bits_enc = G + T;
+        else if (T < 32) atomicOr(&misc->flags, F_INTERNAL);
+    }
+    __syncthreads();
+    const uint64_t G = s_G;
+    const uint32_t sh = (uint32_t)(G & 31);
+    // place this thread's bits into the tile's word buffer
+    if (nb) {
+        const uint32_t p = sh + wpre + incl - nb;
+        const uint32_t o = p & 31, w0 = p >> 5;
+        const uint32_t s0 = (uint32_t)(hi >> 32), s1 = (uint32_t)hi, s2 = (uint32_t)(lo >> 32), s3 = (uint32_t)lo;
+        const uint32_t o0 = s0 >> o;
+        const uint32_t o1 = __builtin_amdgcn_alignbit(s0, s1, o);
+        const uint32_t o2 = __builtin_amdgcn_alignbit(s1, s2, o);
+        const uint32_t o3 = __builtin_amdgcn_alignbit(s2, s3, o);
+        if (o0) atomicOr(&W[w0], o0);
+        if (o1) atomicOr(&W[w0 + 1], o1);
+        if (o2) atomicOr(&W[w0 + 2], o2);
+        if (o3) atomicOr(&W[w0 + 3], o3);
+    }
+    __syncthreads();
+    const uint32_t nwords = (sh + T + 31) >> 5;
+    const bool last_partial = ((sh + T) & 31) != 0 && tile != ntiles - 1;
+    uint32_t* stream = reinterpret_cast<uint32_t*>(out + off_stream);
+    const uint64_t wbase = G >> 5;
+    for (uint32_t w = t; w < nwords; w += 256) {
+        const uint32_t v = W[w];
+        if (w == 0 && sh != 0) tfirst[tile] = v;
+        else if (w == nwords - 1 && last_partial) tlast[tile] = v;
+        else stream[wbase + w] = v;
+    }
+}
+
+// ------------------------------------------------------------- finalize
+// Layout from the device-side counts; boundary words shared by two tiles;
+// outlier and patch sections; zero padding; header.  When the packed
+// container would not be smaller than the raw floats (or staging
+// overflowed) only the verbatim decision is recorded for the host.
+__global__ __launch_bounds__(256) void k_finalize(Geom g, uint32_t mode, double eb, Misc* misc, uint8_t* out,
+                                                  const uint64_t* __restrict__ tstart,
+                                                  const uint32_t* __restrict__ tfirst,
+                                                  const uint32_t* __restrict__ tlast, uint32_t ntiles,
+                                                  const uint32_t* __restrict__ opos, const int32_t* __restrict__ oval,
+                                                  const uint32_t* __restrict__ ppos,
+                                                  const uint32_t* __restrict__ pbits) {
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint32_t flags = misc->flags;
+    const uint64_t bits = misc->total_bits_enc;
+    const uint64_t words = (bits + 31) / 32;
+    const uint64_t nout = misc->n_out, npat = misc->n_pat;
+    const Layout L = make_layout(g.nblocks, words, nout, npat);
+    const bool verbatim = (flags & F_OVERFLOW) || L.total >= (uint64_t)kHdr + 4 * g.N;
+    if (gid == 0) {
+        if (bits != misc->total_bits_cb) atomicOr(&misc->flags, F_INTERNAL);
+        misc->verbatim = verbatim ? 1 : 0;
+        misc->total_bytes = verbatim ? (uint64_t)kHdr + 4 * g.N : L.total;
+    }
+    if (verbatim || (flags & (F_NONFINITE | F_EB | F_INTERNAL | F_TIMEOUT))) return;
+
+    uint32_t* stream = reinterpret_cast<uint32_t*>(out + L.stream);
+    for (uint64_t i = gid + 1; i < ntiles; i += stride) {
+        const uint64_t G = tstart[i];
+        if (G & 31) stream[G >> 5] = tlast[i - 1] | tfirst[i];
+    }
+    uint32_t* o_pos = reinterpret_cast<uint32_t*>(out + L.opos);
+    int32_t* o_val = reinterpret_cast<int32_t*>(out + L.oval);
+    for (uint64_t i = gid; i < nout; i += stride) {
+        o_pos[i] = opos[i];
+        o_val[i] = oval[i];
+    }
+    uint32_t* p_pos = reinterpret_cast<uint32_t*>(out + L.ppos);
+    uint32_t* p_bits = reinterpret_cast<uint32_t*>(out + L.pbits);
+    for (uint64_t i = gid; i < npat; i += stride) {
+        p_pos[i] = ppos[i];
+        p_bits[i] = pbits[i];
+    }
+    if (gid == 0) {
+        // zero padding between and after sections
+        const uint64_t ends[6] = {L.chunks + 2 * (uint64_t)g.nblocks, L.stream + 4 * words, L.opos + 4 * nout,
+                                  L.oval + 4 * nout, L.ppos + 4 * npat, L.pbits + 4 * npat};
+        const uint64_t starts[6] = {L.stream, L.opos, L.oval, L.ppos, L.pbits, L.total};
+        for (int k = 0; k < 6; k++)
+            for (uint64_t a = ends[k]; a < starts[k]; a++) out[a] = 0;
+        // header
+        double eb_abs;
+        resolve_eb(mode, eb, misc->mm_lo, misc->mm_hi, &eb_abs);
+        uint8_t h[kHdr];
+        for (int k = 0; k < kHdr; k++) h[k] = 0;
+        auto st32 = [&](int o, uint32_t v) { for (int k = 0; k < 4; k++) h[o + k] = (uint8_t)(v >> (8 * k)); };
+        auto st64 = [&](int o, uint64_t v) { for (int k = 0; k < 8; k++) h[o + k] = (uint8_t)(v >> (8 * k)); };
+        st32(0, kMagic);
+        h[4] = (uint8_t)kVersion;
+        h[5] = (uint8_t)(kVersion >> 8);
+        st32(8, g.ndim);
+        st32(12, 0);
+        st64(16, g.ndim >= 1 ? g.n[0] : 1);
+        st64(24, g.ndim >= 2 ? g.n[1] : 1);
+        st64(32, g.ndim >= 3 ? g.n[2] : 1);
+        st32(40, mode);
+        st32(44, kRadius);
+        st64(48, __double_as_longlong(eb));
+        st64(56, __double_as_longlong(eb_abs));
+        st64(64, L.total);
+        st32(72, g.nblocks);
+        st32(76, (uint32_t)nout);
+        st32(80, (uint32_t)npat);
+        st32(84, (uint32_t)words);
+        st64(88, bits);
+        uint4* dst = reinterpret_cast<uint4*>(out);
+        const uint4* src = reinterpret_cast<const uint4*>(h);
+        for (int k = 0; k < kHdr / 16; k++) dst[k] = src[k];
+    }
+}
+
+// ------------------------------------------------------------ launchers
+void launch_codebook(hipStream_t st, const uint32_t* hist, uint8_t* out_lens, uint32_t* cw, Misc* misc) {
+    hipLaunchKernelGGL(k_codebook, dim3(1), dim3(1024), 0, st, hist, out_lens, cw, misc);
+}
+
+void launch_encode(hipStream_t st, const uint16_t* codes, const Geom& g, const uint32_t* cw, Misc* misc,
+                   uint64_t* desc, uint32_t ntiles, uint8_t* out, uint64_t* tstart, uint32_t* tfirst,
+                   uint32_t* tlast) {
+    const Layout L = make_layout(g.nblocks, 0, 0, 0);
+    if (g.ndim == 3)
+        hipLaunchKernelGGL(k_encode<3>, dim3(ntiles), dim3(256), 0, st, codes, g, cw, misc, desc, ntiles, out,
+                           L.chunks, L.stream, tstart, tfirst, tlast);
+    else if (g.ndim == 2)
+        hipLaunchKernelGGL(k_encode<2>, dim3(ntiles), dim3(256), 0, st, codes, g, cw, misc, desc, ntiles, out,
+                           L.chunks, L.stream, tstart, tfirst, tlast);
+    else
+        hipLaunchKernelGGL(k_encode<1>, dim3(ntiles), dim3(256), 0, st, codes, g, cw, misc, desc, ntiles, out,
+                           L.chunks, L.stream, tstart, tfirst, tlast);
+}
+
+void launch_finalize(hipStream_t st, const Geom& g, uint32_t mode, double eb, Misc* misc, uint8_t* out,
+                     const uint64_t* tstart, const uint32_t* tfirst, const uint32_t* tlast, uint32_t ntiles,
+                     const uint32_t* opos, const int32_t* oval, const uint32_t* ppos, const uint32_t* pbits) {
+    hipLaunchKernelGGL(k_finalize, dim3(512), dim3(256), 0, st, g, mode, eb, misc, out, tstart, tfirst, tlast,
+                       ntiles, opos, oval, ppos, pbits);
+}
+
+}  // namespace fz

@@ -1,0 +1,380 @@
+// Compression front end: scratch reset, value-range reduction and the fused
+// prequantisation + block-local Lorenzo + post-quantisation + histogram +
+// outlier/patch gather kernel (FZModules Sec. 3.1 dual quantisation and
+// outliers; Sec. 3.2 relative error bound and code histogram).
+#include "fz_common.h"
+#include "fz_kernels.h"
+
+namespace fz {
+
+// --------------------------------------------------------------- reset
+// Clears the per-call scratch: Misc, the global histogram and the look-back
+// descriptors (a fill kernel rather than a memset node, so the sequence can
+// be captured in a graph).
+__global__ void k_reset(Misc* misc, uint32_t* hist, uint64_t* d1, uint32_t n1, uint64_t* d2, uint32_t n2) {
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    if (gid == 0) {
+        Misc m = {};
+        m.mm_lo = 0xFFFFFFFFu;
+        m.mm_hi = 0u;
+        *misc = m;
+    }
+    for (uint32_t i = gid; i < (uint32_t)kBins; i += stride) hist[i] = 0;
+    for (uint32_t i = gid; i < n1; i += stride) d1[i] = 0;
+    for (uint32_t i = gid; i < n2; i += stride) d2[i] = 0;
+}
+
+// -------------------------------------------------------------- min/max
+// One pass over the field: min and max (exact, order-preserving atomics)
+// and a non-finite check.  Needed only for the value-range relative bound.
+__global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, uint64_t N, int vec, Misc* misc) {
+    float lo = __builtin_huge_valf(), hi = -__builtin_huge_valf();
+    bool bad = false;
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t tail = 0;
+    if (vec) {
+        const f32x4* x4 = reinterpret_cast<const f32x4*>(x);
+        const uint64_t n4 = N / 4;
+        for (uint64_t i = gid; i < n4; i += stride) {
+            f32x4 v = __builtin_nontemporal_load(&x4[i]);
+            bad |= !(__builtin_isfinite(v.x) && __builtin_isfinite(v.y) && __builtin_isfinite(v.z) &&
+                     __builtin_isfinite(v.w));
+            lo = fminf(lo, fminf(fminf(v.x, v.y), fminf(v.z, v.w)));
+            hi = fmaxf(hi, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
+        }
+        tail = n4 * 4;
+    }
+    for (uint64_t i = tail + gid; i < N; i += stride) {
+        float v = x[i];
+        bad |= !__builtin_isfinite(v);
+        lo = fminf(lo, v);
+        hi = fmaxf(hi, v);
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        lo = fminf(lo, __shfl_xor(lo, d, 64));
+        hi = fmaxf(hi, __shfl_xor(hi, d, 64));
+    }
+    __shared__ float slo[4], shi[4];
+    __shared__ int sbad;
+    if (threadIdx.x == 0) sbad = 0;
+    __syncthreads();
+    if (bad) sbad = 1;
+    if ((threadIdx.x & 63) == 0) {
+        slo[threadIdx.x >> 6] = lo;
+        shi[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; w++) {
+            lo = fminf(lo, slo[w]);
+            hi = fmaxf(hi, shi[w]);
+        }
+        if (lo <= hi) {
+            atomicMin(&misc->mm_lo, ord_f32(lo));
+            atomicMax(&misc->mm_hi, ord_f32(hi));
+        }
+        if (sbad) atomicOr(&misc->flags, F_NONFINITE);
+    }
+}
+
+// ------------------------------------------------ prequantisation helper
+// q = rint(x / 2eb) via x * (1 / 2eb) in double, round half to even.
+// Patch when |t| >= 2^24 (q = 0) or when float(q * 2eb) misses the bound.
+__device__ __forceinline__ int32_t prequant1(float xv, double e2, double inv, double eb_abs, bool& patch) {
+    double t = (double)xv * inv;
+    if (fabs(t) >= 16777216.0) {
+        patch = true;
+        return 0;
+    }
+    double r = __builtin_rint(t);
+    float xh = (float)(r * e2);
+    patch = fabs((double)xv - (double)xh) > eb_abs;
+    return (int32_t)r;
+}
+
+// Load-phase thread mapping: which (block-in-tile, segment) a thread loads,
+// chosen so that consecutive lanes read consecutive addresses.
+template <int ND>
+__device__ __forceinline__ void load_map(uint32_t t, uint32_t& bi, uint32_t& s) {
+    if (ND == 3) { bi = t & 3; s = t >> 2; }                              // 4 blocks x 32 B per row
+    else if (ND == 2) { bi = (t >> 2) & 3; s = (t & 3) | ((t >> 4) << 2); }  // 512 B per row
+    else { bi = t >> 6; s = t & 63; }                                     // contiguous
+}
+
+// ------------------------------------------- fused Lorenzo quantisation
+// One workgroup (256 threads) handles a tile of 4 consecutive blocks per
+// iteration; workgroups take tiles from an atomic counter, so outliers and
+// patches can be placed in block order by a decoupled look-back.
+//   phase A (load mapping): 8 values per thread -> q, patch mask -> LDS
+//   phase B (thread = block*64 + segment): Lorenzo residual from LDS, codes
+//     (block-major, u16), histogram, outlier/patch positions.
+template <int ND>
+__global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom g, uint32_t mode, double eb,
+                                               int vec, Misc* misc, uint32_t* __restrict__ hist_g,
+                                               uint16_t* __restrict__ codes, uint64_t* desc, uint32_t ntiles,
+                                               uint32_t* __restrict__ opos, int32_t* __restrict__ oval,
+                                               uint64_t ocap, uint32_t* __restrict__ ppos,
+                                               uint32_t* __restrict__ pbits, uint64_t pcap) {
+    __shared__ int32_t Q[kTileBlocks * kBlockElems];
+    __shared__ uint8_t PM[kTileBlocks * kSegs];
+    __shared__ uint32_t H[kBins];
+    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_excl;
+
+    const uint32_t t = threadIdx.x;
+    const uint32_t lane = t & 63, wave = t >> 6;
+    double eb_abs;
+    if (!resolve_eb(mode, eb, misc->mm_lo, misc->mm_hi, &eb_abs)) {
+        if (blockIdx.x == 0 && t == 0) atomicOr(&misc->flags, F_EB);
+        return;
+    }
+    const double e2 = 2.0 * eb_abs;
+    const double inv = 1.0 / e2;
+    for (uint32_t i = t; i < (uint32_t)kBins; i += 256) H[i] = 0;
+
+    for (;;) {
+        if (t == 0) s_tile = atomicAdd(&misc->qtile_ctr, 1u);
+        __syncthreads();
+        const uint32_t tile = s_tile;
+        if (tile >= ntiles) break;
+
+        // ---------------- phase A: load + prequantise
+        {
+            uint32_t bi, s;
+            load_map<ND>(t, bi, s);
+            const uint32_t b = tile * kTileBlocks + bi;
+            int32_t q[8];
+            uint32_t pm = 0;
+            bool bad = false;
+#pragma unroll
+            for (int i = 0; i < 8; i++) q[i] = 0;
+            if (b < g.nblocks) {
+                BlockInfo info = block_info(g, b);
+                uint32_t nv;
+                uint64_t base = seg_index<ND>(g, info, s, nv);
+                float v[8];
+                if (nv == 8 && vec) {
+                    const f32x4* p = reinterpret_cast<const f32x4*>(x + base);
+                    f32x4 a = __builtin_nontemporal_load(p);
+                    f32x4 c = __builtin_nontemporal_load(p + 1);
+                    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+                    v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 8; i++) v[i] = (i < (int)nv) ? x[base + i] : 0.0f;
+                }
+#pragma unroll
+                for (int i = 0; i < 8; i++) {
+                    if (i < (int)nv) {
+                        bad |= !__builtin_isfinite(v[i]);
+                        bool p;
+                        q[i] = prequant1(v[i], e2, inv, eb_abs, p);
+                        pm |= (p ? 1u : 0u) << i;
+                    }
+                }
+            }
+            if (bad) atomicOr(&misc->flags, F_NONFINITE);
+            int4* dst = reinterpret_cast<int4*>(&Q[(bi * kSegs + s) * 8]);
+            dst[0] = make_int4(q[0], q[1], q[2], q[3]);
+            dst[1] = make_int4(q[4], q[5], q[6], q[7]);
+            PM[bi * kSegs + s] = (uint8_t)pm;
+        }
+        __syncthreads();
+
+        // ---------------- phase B: Lorenzo residual, codes, histogram
+        const uint32_t bi = t >> 6, s = t & 63;
+        const uint32_t b = tile * kTileBlocks + bi;
+        const int32_t* Qb = &Q[bi * kBlockElems];
+        int32_t d[8];
+        {
+            int32_t r0[8];
+            const int4* src = reinterpret_cast<const int4*>(&Qb[s * 8]);
+            int4 a = src[0], c = src[1];
+            r0[0] = a.x; r0[1] = a.y; r0[2] = a.z; r0[3] = a.w;
+            r0[4] = c.x; r0[5] = c.y; r0[6] = c.z; r0[7] = c.w;
+            if (ND == 3) {
+                const uint32_t ly = s & 7, lz = s >> 3;
+                // dx of a row: q[i] - q[i-1], q[-1] = 0 (block face)
+                auto row = [&](uint32_t ss, int32_t* r) {
+                    const int4* p = reinterpret_cast<const int4*>(&Qb[ss * 8]);
+                    int4 u = p[0], w = p[1];
+                    r[0] = u.x; r[1] = u.y; r[2] = u.z; r[3] = u.w;
+                    r[4] = w.x; r[5] = w.y; r[6] = w.z; r[7] = w.w;
+                };
+                int32_t ry[8], rz[8], ryz[8];
+                const int32_t my = ly > 0 ? 1 : 0, mz = lz > 0 ? 1 : 0;
+                row(ly > 0 ? s - 1 : s, ry);
+                row(lz > 0 ? s - 8 : s, rz);
+                row((ly > 0 && lz > 0) ? s - 9 : s, ryz);
+#pragma unroll
+                for (int i = 7; i >= 0; i--) {
+                    int32_t dx0 = r0[i] - (i ? r0[i - 1] : 0);
+                    int32_t dxy = ry[i] - (i ? ry[i - 1] : 0);
+                    int32_t dxz = rz[i] - (i ? rz[i - 1] : 0);
+                    int32_t dxyz = ryz[i] - (i ? ryz[i - 1] : 0);
+                    d[i] = dx0 - my * dxy - mz * dxz + (my & mz) * dxyz;
+                }
+            } else if (ND == 2) {
+                const uint32_t sx = s & 3, ly = s >> 2;
+                const int32_t left = sx ? Qb[(s - 1) * 8 + 7] : 0;
+                int32_t up[8], upleft = 0;
+                const int32_t my = ly > 0 ? 1 : 0;
+                {
+                    const uint32_t su = ly > 0 ? s - 4 : s;
+                    const int4* p = reinterpret_cast<const int4*>(&Qb[su * 8]);
+                    int4 u = p[0], w = p[1];
+                    up[0] = u.x; up[1] = u.y; up[2] = u.z; up[3] = u.w;
+                    up[4] = w.x; up[5] = w.y; up[6] = w.z; up[7] = w.w;
+                    upleft = (sx && ly > 0) ? Qb[(su - 1) * 8 + 7] : 0;
+                }
+#pragma unroll
+                for (int i = 7; i >= 0; i--) {
+                    int32_t dx0 = r0[i] - (i ? r0[i - 1] : left);
+                    int32_t dxu = up[i] - (i ? up[i - 1] : upleft);
+                    d[i] = dx0 - my * dxu;
+                }
+            } else {
+                const int32_t left = s ? Qb[(s - 1) * 8 + 7] : 0;
+#pragma unroll
+                for (int i = 7; i >= 0; i--) d[i] = r0[i] - (i ? r0[i - 1] : left);
+            }
+        }
+
+        uint32_t nv = 0;
+        uint64_t base = 0;
+        if (b < g.nblocks) {
+            BlockInfo info = block_info(g, b);
+            base = seg_index<ND>(g, info, s, nv);
+        }
+        uint32_t code[8];
+        uint32_t omask = 0;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            int32_t v = d[i];
+            uint32_t c = (v > -kRadius && v < kRadius) ? (uint32_t)(v + kRadius) : 0u;
+            code[i] = c;
+            if (i < (int)nv && c == 0) omask |= 1u << i;
+        }
+        if (b < g.nblocks) {
+            uint4 pk;
+            pk.x = code[0] | (code[1] << 16);
+            pk.y = code[2] | (code[3] << 16);
+            pk.z = code[4] | (code[5] << 16);
+            pk.w = code[6] | (code[7] << 16);
+            *reinterpret_cast<uint4*>(&codes[(uint64_t)b * kBlockElems + s * 8]) = pk;
+        }
+        // histogram: peel the two codes most lanes share with one LDS add
+        // each, then add the remaining lanes individually.
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const bool valid = i < (int)nv;
+            uint32_t c = valid ? code[i] : 0xFFFFFFFFu;
+            uint64_t vm = __ballot(valid);
+            bool done = !valid;
+#pragma unroll
+            for (int r = 0; r < 2; r++) {
+                uint64_t rem = __ballot(!done);
+                if (rem == 0) break;
+                const int lead = __ffsll((long long)rem) - 1;
+                const uint32_t cand = __shfl(c, lead, 64);
+                const uint64_t m = __ballot(!done && c == cand);
+                if ((int)lane == lead) atomicAdd(&H[cand], (uint32_t)__popcll(m));
+                if (c == cand) done = true;
+            }
+            if (!done) atomicAdd(&H[c], 1u);
+            (void)vm;
+        }
+
+        // ---------------- outliers and patches in block order
+        const uint32_t pmask = PM[t] & ((1u << nv) - 1u);
+        const uint32_t no = __popc(omask), np = __popc(pmask);
+        const uint32_t packed = no | (np << 16);
+        const uint32_t incl = wave_incl_scan(packed);
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        uint32_t wpre = 0, tot = 0;
+        for (uint32_t w = 0; w < 4; w++) {
+            uint32_t v = wsum[w];
+            if (w < wave) wpre += v;
+            tot += v;
+        }
+        const uint32_t excl_local = wpre + incl - packed;
+        if (t == 0) {
+            const uint64_t agg = (uint64_t)(tot & 0xFFFFu) | ((uint64_t)(tot >> 16) << 31);
+            s_excl = lookback(desc, tile, agg, OpPair31(), &misc->flags);
+            if (tile == ntiles - 1) {
+                const uint64_t incl_all = OpPair31()(s_excl, agg);
+                misc->n_out = incl_all & ((1ull << 31) - 1);
+                misc->n_pat = incl_all >> 31;
+            }
+        }
+        __syncthreads();
+        const uint64_t ex = s_excl;
+        if (omask | pmask) {
+            uint64_t oi = (ex & ((1ull << 31) - 1)) + (excl_local & 0xFFFFu);
+            uint64_t pi = (ex >> 31) + (excl_local >> 16);
+            const uint32_t pos0 = b * kBlockElems + s * 8;
+            bool ovf = false;
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                if (omask & (1u << i)) {
+                    if (oi < ocap) {
+                        opos[oi] = pos0 + i;
+                        oval[oi] = d[i];
+                    } else {
+                        ovf = true;
+                    }
+                    oi++;
+                }
+                if (pmask & (1u << i)) {
+                    if (pi < pcap) {
+                        ppos[pi] = pos0 + i;
+                        pbits[pi] = __float_as_uint(x[base + i]);
+                    } else {
+                        ovf = true;
+                    }
+                    pi++;
+                }
+            }
+            if (ovf) atomicOr(&misc->flags, F_OVERFLOW);
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < (uint32_t)kBins; i += 256)
+        if (H[i]) atomicAdd(&hist_g[i], H[i]);
+}
+
+// ------------------------------------------------------------ launchers
+void launch_reset(hipStream_t st, Misc* misc, uint32_t* hist, uint64_t* d1, uint32_t n1, uint64_t* d2,
+                  uint32_t n2) {
+    uint32_t n = n1 > n2 ? n1 : n2;
+    uint32_t grid = (n + 255) / 256;
+    if (grid < 4) grid = 4;
+    if (grid > 1024) grid = 1024;
+    hipLaunchKernelGGL(k_reset, dim3(grid), dim3(256), 0, st, misc, hist, d1, n1, d2, n2);
+}
+
+void launch_minmax(hipStream_t st, const float* x, uint64_t N, int vec, Misc* misc, int grid) {
+    hipLaunchKernelGGL(k_minmax, dim3(grid), dim3(256), 0, st, x, N, vec, misc);
+}
+
+void launch_quant(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
+                  Misc* misc, uint32_t* hist, uint16_t* codes, uint64_t* desc, uint32_t ntiles, uint32_t* opos,
+                  int32_t* oval, uint64_t ocap, uint32_t* ppos, uint32_t* pbits, uint64_t pcap) {
+    if (g.ndim == 3)
+        hipLaunchKernelGGL(k_quant<3>, dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, hist, codes, desc,
+                           ntiles, opos, oval, ocap, ppos, pbits, pcap);
+    else if (g.ndim == 2)
+        hipLaunchKernelGGL(k_quant<2>, dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, hist, codes, desc,
+                           ntiles, opos, oval, ocap, ppos, pbits, pcap);
+    else
+        hipLaunchKernelGGL(k_quant<1>, dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, hist, codes, desc,
+                           ntiles, opos, oval, ocap, ppos, pbits, pcap);
+}
+
+}  // namespace fz

@@ -1,0 +1,237 @@
+"""Python binding of libfz (include/fz.h): argument marshalling only.
+
+Every step of compression and decompression runs in the library's HIP
+kernels; PyTorch supplies device memory and the current HIP stream.  There is
+no fallback: if libfz.so is missing or cannot be loaded, every call raises.
+
+Field tensors are float32, C-contiguous, on a ROCm device, shape
+(nz, ny, nx), (ny, nx) or (nx,) - the library's dims[0] is the last axis.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfz.so")
+HEADER_PATH = os.path.join(os.path.dirname(HERE), "include", "fz.h")
+
+EB_ABS, EB_REL = 0, 1
+HDR_BYTES = 128
+
+STATUS = {
+    0: "FZ_OK", -1: "FZ_ERR_ARG", -2: "FZ_ERR_EB", -3: "FZ_ERR_NONFINITE", -4: "FZ_ERR_CAPACITY",
+    -5: "FZ_ERR_CORRUPT", -6: "FZ_ERR_HIP", -7: "FZ_ERR_NOMEM", -8: "FZ_ERR_UNSUPPORTED", -9: "FZ_ERR_INTERNAL",
+}
+
+
+class FZError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__(f"{what}: {STATUS.get(code, code)} ({_strerror(code)})")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_uint32), ("dims", ctypes.c_uint64 * 3), ("eb_mode", ctypes.c_uint32),
+                ("eb", ctypes.c_double), ("pred", ctypes.c_uint32), ("radius", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libfz.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FileNotFoundError(f"{LIB_PATH} is missing; build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+    P = ctypes.POINTER(Params)
+    L.fz_ctx_create.argtypes = [ctypes.POINTER(vp), i32, u64]
+    L.fz_ctx_create.restype = i32
+    L.fz_ctx_destroy.argtypes = [vp]
+    L.fz_ctx_destroy.restype = None
+    L.fz_compress_bound.argtypes = [P]
+    L.fz_compress_bound.restype = u64
+    L.fz_compress.argtypes = [vp, P, vp, vp, u64, ctypes.POINTER(u64), vp]
+    L.fz_compress.restype = i32
+    L.fz_header_read.argtypes = [vp, u64, P, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+    L.fz_header_read.restype = i32
+    L.fz_decompress.argtypes = [vp, vp, u64, vp, vp, u64, vp]
+    L.fz_decompress.restype = i32
+    L.fz_strerror.argtypes = [i32]
+    L.fz_strerror.restype = ctypes.c_char_p
+    L.fz_set_timing.argtypes = [vp, i32]
+    L.fz_set_timing.restype = i32
+    L.fz_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)]
+    L.fz_stage_times.restype = i32
+    L.fz_stage_name.argtypes = [vp, i32]
+    L.fz_stage_name.restype = ctypes.c_char_p
+    L.fz_last_histogram.argtypes = [vp, vp]
+    L.fz_last_histogram.restype = i32
+    _lib = L
+    return L
+
+
+def declared_functions() -> list[str]:
+    """Names of the functions include/fz.h declares."""
+    with open(HEADER_PATH) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fz_[a-z_0-9]+)\s*\(", text)))
+
+
+def _strerror(code: int) -> str:
+    try:
+        return lib().fz_strerror(code).decode()
+    except Exception:
+        return "?"
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise FZError(rc, what)
+
+
+def params_for(shape, eb: float, mode: int = EB_REL) -> Params:
+    nd = len(shape)
+    if nd < 1 or nd > 3:
+        raise ValueError("fields have 1 to 3 dimensions")
+    dims = list(reversed([int(s) for s in shape])) + [1] * (3 - nd)
+    return Params(nd, (ctypes.c_uint64 * 3)(*dims), int(mode), float(eb), 0, 512)
+
+
+def header_fields(hdr: bytes) -> dict:
+    """Counts recorded in a container header (little-endian fields of the
+    128-byte header described in include/fz.h)."""
+    b = bytes(hdr[:HDR_BYTES])
+
+    def u(o, n):
+        return int.from_bytes(b[o:o + n], "little")
+
+    return dict(flags=u(6, 2), ndim=u(8, 4), dims=(u(16, 8), u(24, 8), u(32, 8)), eb_mode=u(40, 4),
+                eb=ctypes.c_double.from_buffer_copy(b[48:56]).value,
+                eb_abs=ctypes.c_double.from_buffer_copy(b[56:64]).value, total=u(64, 8),
+                nblocks=u(72, 4), n_outliers=u(76, 4), n_patches=u(80, 4), stream_words=u(84, 4),
+                stream_bits=u(88, 8))
+
+
+def shape_of(p: Params):
+    return tuple(reversed([int(p.dims[a]) for a in range(p.ndim)]))
+
+
+def _stream_handle(device: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Context:
+    """An fz context bound to one device; owns the library's scratch memory."""
+
+    def __init__(self, device: int | torch.device = 0, max_elems: int = 0):
+        if isinstance(device, torch.device):
+            device = device.index or 0
+        self.device = torch.device("cuda", int(device))
+        h = ctypes.c_void_p()
+        _check(lib().fz_ctx_create(ctypes.byref(h), int(device), int(max_elems)), "fz_ctx_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fz_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # ---------------------------------------------------------------- compress
+    def compress_bound(self, shape) -> int:
+        return int(lib().fz_compress_bound(ctypes.byref(params_for(shape, 1.0))))
+
+    def compress(self, x: torch.Tensor, eb: float, mode: int = EB_REL, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Compress a float32 device field; returns a uint8 device tensor (view of `out`)."""
+        if x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous():
+            raise ValueError("x must be a contiguous float32 device tensor")
+        p = params_for(x.shape, eb, mode)
+        cap = self.compress_bound(x.shape)
+        if cap == 0:
+            raise FZError(-1, "fz_compress_bound")
+        if out is None:
+            out = torch.empty(cap, dtype=torch.uint8, device=x.device)
+        n = ctypes.c_uint64(0)
+        rc = lib().fz_compress(self._h, ctypes.byref(p), ctypes.c_void_p(x.data_ptr()),
+                               ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(n),
+                               _stream_handle(x.device))
+        _check(rc, "fz_compress")
+        return out[: n.value]
+
+    # -------------------------------------------------------------- decompress
+    @staticmethod
+    def read_header(hdr: bytes):
+        """(params, n_elems, total_bytes) from a host copy of the header."""
+        buf = (ctypes.c_uint8 * HDR_BYTES).from_buffer_copy(bytes(hdr[:HDR_BYTES]).ljust(HDR_BYTES, b"\0"))
+        p = Params()
+        n = ctypes.c_uint64()
+        tot = ctypes.c_uint64()
+        _check(lib().fz_header_read(buf, len(hdr), ctypes.byref(p), ctypes.byref(n), ctypes.byref(tot)),
+               "fz_header_read")
+        return p, n.value, tot.value
+
+    def decompress(self, buf: torch.Tensor, header: bytes | None = None, out: torch.Tensor | None = None):
+        """Decompress a uint8 device container; returns a float32 device field."""
+        if buf.dtype != torch.uint8 or not buf.is_cuda or not buf.is_contiguous():
+            raise ValueError("buf must be a contiguous uint8 device tensor")
+        if header is None:
+            header = buf[:HDR_BYTES].cpu().numpy().tobytes()
+        p, n, _ = self.read_header(header)
+        if out is None:
+            out = torch.empty(shape_of(p), dtype=torch.float32, device=buf.device)
+        h = (ctypes.c_uint8 * HDR_BYTES).from_buffer_copy(bytes(header[:HDR_BYTES]))
+        rc = lib().fz_decompress(self._h, ctypes.c_void_p(buf.data_ptr()), buf.numel(), h,
+                                 ctypes.c_void_p(out.data_ptr()), out.numel(), _stream_handle(buf.device))
+        _check(rc, "fz_decompress")
+        return out
+
+    # ------------------------------------------------------------ diagnostics
+    def set_timing(self, on: bool = True):
+        _check(lib().fz_set_timing(self._h, 1 if on else 0), "fz_set_timing")
+
+    def stage_times(self) -> list[tuple[str, float]]:
+        ms = (ctypes.c_float * 16)()
+        n = ctypes.c_int()
+        _check(lib().fz_stage_times(self._h, ms, 16, ctypes.byref(n)), "fz_stage_times")
+        return [(lib().fz_stage_name(self._h, i).decode(), float(ms[i])) for i in range(min(n.value, 16))]
+
+    def last_histogram(self):
+        import numpy as np
+        h = np.zeros(1024, np.uint32)
+        _check(lib().fz_last_histogram(self._h, h.ctypes.data_as(ctypes.c_void_p)), "fz_last_histogram")
+        return h
+
+
+_default: dict[int, Context] = {}
+
+
+def context(device: int = 0) -> Context:
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def compress(x: torch.Tensor, eb: float, mode: int = EB_REL) -> torch.Tensor:
+    return context(x.device.index or 0).compress(x, eb, mode)
+
+
+def decompress(buf: torch.Tensor, header: bytes | None = None) -> torch.Tensor:
+    return context(buf.device.index or 0).decompress(buf, header)
