@@ -34,13 +34,17 @@ LINK_GBPS = 35.7  # the paper's measured GPU-to-host bandwidth on its H100 node 
 
 def stage_bytes(stage: str, n: int, nblocks: int, h: dict, total: int) -> float:
     """Algorithmic bytes one launch of a stage must move (see the design notes)."""
+    ntiles = (nblocks + 3) // 4
     side = 8 * (h["n_outliers"] + h["n_patches"])
     stream = 4 * h["stream_words"]
     return {
         "minmax": 4 * n,
         "quant": 4 * n + 2 * n + side,
-        "encode": 2 * n + stream + 2 * nblocks,
-        "finalize": 2 * side,
+        "encode_len": 2 * n + 2 * nblocks,
+        "encode_write": 2 * n + stream,
+        "scan_counts": 4 * ntiles + 8 * ntiles,
+        "scan_bits": 4 * ntiles + 8 * ntiles,
+        "finalize": 2 * side + 12 * ntiles,
         "lut": 512,
         "scan": 2 * nblocks + 8 * nblocks,
         "decode": stream + 2 * nblocks + 8 * h["n_outliers"] + 4 * n,

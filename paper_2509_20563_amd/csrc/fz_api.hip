@@ -40,21 +40,30 @@ struct fz_ctx {
     uint16_t* lut = nullptr;
     uint16_t* codes = nullptr;
     uint64_t codes_cap = 0;
+    // per-tile outlier / patch staging (2048 slots per 4-block tile)
     uint32_t* opos = nullptr;
     int32_t* oval = nullptr;
     uint32_t* ppos = nullptr;
     uint32_t* pbits = nullptr;
     uint64_t opos_cap = 0, oval_cap = 0, ppos_cap = 0, pbits_cap = 0;
-    uint64_t* qdesc = nullptr;
-    uint64_t* edesc = nullptr;
-    uint64_t* tstart = nullptr;
+    // per-tile counts and prefixes
+    uint32_t* tile_cnt = nullptr;
+    uint64_t* tile_off = nullptr;
+    uint32_t* tile_bits = nullptr;
+    uint64_t* tile_start = nullptr;
     uint32_t* tfirst = nullptr;
     uint32_t* tlast = nullptr;
-    uint64_t qdesc_cap = 0, edesc_cap = 0, tstart_cap = 0, tfirst_cap = 0, tlast_cap = 0;
+    uint64_t tile_cnt_cap = 0, tile_off_cap = 0, tile_bits_cap = 0, tile_start_cap = 0, tfirst_cap = 0,
+             tlast_cap = 0;
+    // look-back descriptors of the three scans
+    uint64_t* desc_cnt = nullptr;
+    uint64_t* desc_bits = nullptr;
+    uint64_t* desc_chunks = nullptr;
+    uint64_t desc_cnt_cap = 0, desc_bits_cap = 0, desc_chunks_cap = 0;
+    // decode
     uint64_t* off = nullptr;
     uint32_t* ofirst = nullptr;
-    uint64_t* sdesc = nullptr;
-    uint64_t off_cap = 0, ofirst_cap = 0, sdesc_cap = 0;
+    uint64_t off_cap = 0, ofirst_cap = 0;
     // timing
     bool timing = false;
     hipEvent_t ev[kMaxStages + 1] = {};
@@ -128,22 +137,26 @@ uint64_t bound_of(const Geom& g) {
 int ensure(fz_ctx* c, const Geom& g) {
     const uint64_t nb = g.nblocks;
     const uint64_t ntiles = (nb + kTileBlocks - 1) / kTileBlocks;
-    const uint64_t stage = g.N / 2 + 64;
-    const uint64_t stiles = (nb + 1023) / 1024;
+    const uint64_t slots = ntiles * kTileBlocks * kBlockElems;
+    const uint64_t sd_tiles = scan_tiles((uint32_t)ntiles);
+    const uint64_t sd_blocks = scan_tiles((uint32_t)nb);
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = grow(c->codes, c->codes_cap, nb * kBlockElems);
-    if (e == hipSuccess) e = grow(c->opos, c->opos_cap, stage);
-    if (e == hipSuccess) e = grow(c->oval, c->oval_cap, stage);
-    if (e == hipSuccess) e = grow(c->ppos, c->ppos_cap, stage);
-    if (e == hipSuccess) e = grow(c->pbits, c->pbits_cap, stage);
-    if (e == hipSuccess) e = grow(c->qdesc, c->qdesc_cap, ntiles);
-    if (e == hipSuccess) e = grow(c->edesc, c->edesc_cap, ntiles);
-    if (e == hipSuccess) e = grow(c->tstart, c->tstart_cap, ntiles);
+    if (e == hipSuccess) e = grow(c->opos, c->opos_cap, slots);
+    if (e == hipSuccess) e = grow(c->oval, c->oval_cap, slots);
+    if (e == hipSuccess) e = grow(c->ppos, c->ppos_cap, slots);
+    if (e == hipSuccess) e = grow(c->pbits, c->pbits_cap, slots);
+    if (e == hipSuccess) e = grow(c->tile_cnt, c->tile_cnt_cap, ntiles);
+    if (e == hipSuccess) e = grow(c->tile_off, c->tile_off_cap, ntiles);
+    if (e == hipSuccess) e = grow(c->tile_bits, c->tile_bits_cap, ntiles);
+    if (e == hipSuccess) e = grow(c->tile_start, c->tile_start_cap, ntiles);
     if (e == hipSuccess) e = grow(c->tfirst, c->tfirst_cap, ntiles);
     if (e == hipSuccess) e = grow(c->tlast, c->tlast_cap, ntiles);
+    if (e == hipSuccess) e = grow(c->desc_cnt, c->desc_cnt_cap, sd_tiles);
+    if (e == hipSuccess) e = grow(c->desc_bits, c->desc_bits_cap, sd_tiles);
+    if (e == hipSuccess) e = grow(c->desc_chunks, c->desc_chunks_cap, sd_blocks);
     if (e == hipSuccess) e = grow(c->off, c->off_cap, nb);
     if (e == hipSuccess) e = grow(c->ofirst, c->ofirst_cap, nb);
-    if (e == hipSuccess) e = grow(c->sdesc, c->sdesc_cap, stiles);
     return e == hipSuccess ? FZ_OK : FZ_ERR_NOMEM;
 }
 
@@ -296,14 +309,17 @@ void fz_ctx_destroy(fz_ctx* c) {
     hipFree(c->oval);
     hipFree(c->ppos);
     hipFree(c->pbits);
-    hipFree(c->qdesc);
-    hipFree(c->edesc);
-    hipFree(c->tstart);
+    hipFree(c->tile_cnt);
+    hipFree(c->tile_off);
+    hipFree(c->tile_bits);
+    hipFree(c->tile_start);
     hipFree(c->tfirst);
     hipFree(c->tlast);
+    hipFree(c->desc_cnt);
+    hipFree(c->desc_bits);
+    hipFree(c->desc_chunks);
     hipFree(c->off);
     hipFree(c->ofirst);
-    hipFree(c->sdesc);
     if (c->h_misc) hipHostFree(c->h_misc);
     if (c->h_hdr) hipHostFree(c->h_hdr);
     for (int i = 0; i <= kMaxStages; i++)
@@ -333,31 +349,35 @@ int fz_compress(fz_ctx* c, const fz_params* p, const float* d_in, void* d_out, u
     uint8_t* out = (uint8_t*)d_out;
     const uint32_t ntiles = (g.nblocks + kTileBlocks - 1) / kTileBlocks;
     const int vec = (((uintptr_t)d_in & 15) == 0) && (g.ndim == 1 || (g.n[0] & 3) == 0);
-    const uint64_t stage = g.N / 2 + 64;
+    const uint32_t sd_tiles = scan_tiles(ntiles);
+    const int grid = (int)(ntiles < (uint32_t)c->n_cu * 8 ? ntiles : (uint32_t)c->n_cu * 8);
     c->have_hist = false;
 
     t_begin(c, st);
-    launch_reset(st, c->misc, c->hist, c->qdesc, ntiles, c->edesc, ntiles);
+    launch_reset(st, c->misc, c->hist, c->desc_cnt, sd_tiles, c->desc_bits, sd_tiles);
     t_mark(c, st, "reset");
     if (p->eb_mode == FZ_EB_REL) {
-        uint64_t work = (g.N + 4 * 256 - 1) / (4 * 256);
-        uint64_t grid = work < (uint64_t)c->n_cu * 16 ? work : (uint64_t)c->n_cu * 16;
-        if (grid < 1) grid = 1;
-        launch_minmax(st, d_in, g.N, (((uintptr_t)d_in & 15) == 0), c->misc, (int)grid);
+        uint64_t work = (g.N + 16 * 256 - 1) / (16 * 256);
+        uint64_t mgrid = work < (uint64_t)c->n_cu * 16 ? work : (uint64_t)c->n_cu * 16;
+        if (mgrid < 1) mgrid = 1;
+        launch_minmax(st, d_in, g.N, (((uintptr_t)d_in & 15) == 0), c->misc, (int)mgrid);
         t_mark(c, st, "minmax");
     }
-    {
-        uint64_t grid = ntiles < (uint64_t)c->n_cu * 8 ? ntiles : (uint64_t)c->n_cu * 8;
-        launch_quant(st, (int)grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, c->qdesc, ntiles,
-                     c->opos, c->oval, stage, c->ppos, c->pbits, stage);
-        t_mark(c, st, "quant");
-    }
+    launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt, c->opos,
+                 c->oval, c->ppos, c->pbits);
+    t_mark(c, st, "quant");
+    launch_scan(st, SCAN_COUNTS, c->tile_cnt, ntiles, c->tile_off, c->desc_cnt, &c->misc->qtile_ctr, c->misc, 0);
+    t_mark(c, st, "scan_counts");
     launch_codebook(st, c->hist, out + kHdr, c->cw, c->misc);
     t_mark(c, st, "codebook");
-    launch_encode(st, c->codes, g, c->cw, c->misc, c->edesc, ntiles, out, c->tstart, c->tfirst, c->tlast);
-    t_mark(c, st, "encode");
-    launch_finalize(st, g, p->eb_mode, p->eb, c->misc, out, c->tstart, c->tfirst, c->tlast, ntiles, c->opos,
-                    c->oval, c->ppos, c->pbits);
+    launch_encode_len(st, grid, c->codes, g, c->cw, ntiles, out, c->tile_bits);
+    t_mark(c, st, "encode_len");
+    launch_scan(st, SCAN_BITS, c->tile_bits, ntiles, c->tile_start, c->desc_bits, &c->misc->etile_ctr, c->misc, 0);
+    t_mark(c, st, "scan_bits");
+    launch_encode_write(st, grid, c->codes, g, c->cw, c->misc, ntiles, out, c->tile_start, c->tfirst, c->tlast);
+    t_mark(c, st, "encode_write");
+    launch_finalize(st, g, p->eb_mode, p->eb, c->misc, out, ntiles, c->tile_start, c->tfirst, c->tlast, c->tile_cnt,
+                    c->tile_off, c->opos, c->oval, c->ppos, c->pbits);
     t_mark(c, st, "finalize");
     if (hipMemcpyAsync(c->h_misc, c->misc, sizeof(Misc), hipMemcpyDeviceToHost, st) != hipSuccess) return FZ_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
@@ -437,13 +457,14 @@ int fz_decompress(fz_ctx* c, const void* d_in, uint64_t in_bytes, const void* h_
     rc = ensure(c, g);
     if (rc) return rc;
     const Layout L = make_layout(r.nblocks, r.words, r.nout, r.npat);
-    const uint32_t stiles = (g.nblocks + 1023) / 1024;
+    const uint32_t stiles = scan_tiles(g.nblocks);
     const int vec = (((uintptr_t)d_out & 15) == 0) && (g.ndim == 1 || (g.n[0] & 3) == 0);
-    launch_reset(st, c->misc, c->hist, c->sdesc, stiles, nullptr, 0);
+    launch_reset(st, c->misc, c->hist, c->desc_chunks, stiles, nullptr, 0);
     t_mark(c, st, "reset");
     launch_lut(st, in + L.lens, c->lut, c->misc);
     t_mark(c, st, "lut");
-    launch_scan_chunks(st, (const uint16_t*)(in + L.chunks), g.nblocks, c->off, c->sdesc, c->misc, r.bits);
+    launch_scan(st, SCAN_CHUNKS, in + L.chunks, g.nblocks, c->off, c->desc_chunks, &c->misc->stile_ctr, c->misc,
+                r.bits);
     t_mark(c, st, "scan");
     launch_decode(st, g, (const uint32_t*)(in + L.stream), r.words, c->off, (const uint16_t*)(in + L.chunks),
                   c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->ofirst, r.nout,

@@ -22,11 +22,14 @@ constexpr int kTileBlocks = 4;    // blocks per workgroup tile (256 threads)
 constexpr uint32_t kMagic = 0x314D5A46u;  // "FZM1"
 constexpr uint16_t kVersion = 1;
 
+// prefix-scan kinds (fz_scan.hip)
+enum { SCAN_COUNTS = 0, SCAN_BITS = 1, SCAN_CHUNKS = 2 };
+
 // flag bits raised by kernels in Misc::flags
 enum : uint32_t {
     F_NONFINITE = 1u,
     F_EB = 2u,
-    F_OVERFLOW = 4u,   // outlier/patch staging full: the container goes verbatim
+    F_OVERFLOW = 4u,   // outlier/patch totals saturate: the container goes verbatim
     F_CORRUPT = 8u,
     F_INTERNAL = 16u,
     F_TIMEOUT = 32u,   // a bounded look-back wait gave up
@@ -154,47 +157,67 @@ __host__ __device__ inline bool resolve_eb(uint32_t mode, double eb, uint32_t mm
 
 // Decoupled look-back (single-pass prefix scan over tiles taken in order
 // from an atomic counter).  desc[t] holds status (2 high bits: 1 = tile
-// aggregate, 2 = inclusive prefix) and a 62-bit payload combined by Op.
-// Called by one thread per tile; returns the exclusive prefix.  The wait
-// on a predecessor is bounded: after the spin limit the tile raises
-// F_TIMEOUT and proceeds, so every wave always exits.
+// aggregate, 2 = inclusive prefix) and a 62-bit payload combined by Op
+// (associative and commutative).  Executed by one whole wave: lane i reads
+// the descriptor of tile t-1-i, so one round trip covers 64 predecessors;
+// the payloads up to the nearest inclusive one are reduced across the wave.
+// The wait on a predecessor is bounded: after the spin limit the tile
+// raises F_TIMEOUT and proceeds, so every wave always exits.  Returns the
+// exclusive prefix in every lane.
 constexpr uint64_t kStAgg = 1ull << 62;
 constexpr uint64_t kStInc = 2ull << 62;
 constexpr uint64_t kPayload = (1ull << 62) - 1;
 constexpr uint32_t kSpinLimit = 1u << 22;
 
 template <class Op>
+__device__ inline uint64_t wave_reduce64(uint64_t v, Op op) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = op(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+template <class Op>
 __device__ inline uint64_t lookback(uint64_t* desc, uint32_t t, uint64_t agg, Op op, uint32_t* flags) {
+    const int lane = threadIdx.x & 63;
     if (t == 0) {
-        __hip_atomic_store(&desc[0], kStInc | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0) __hip_atomic_store(&desc[0], kStInc | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return 0;
     }
-    __hip_atomic_store(&desc[t], kStAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0) __hip_atomic_store(&desc[t], kStAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint64_t excl = 0;
-    int64_t j = (int64_t)t - 1;
+    int64_t base = (int64_t)t - 1;
     uint32_t spins = 0;
-    while (j >= 0) {
-        uint64_t d = __hip_atomic_load(&desc[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint64_t st = d >> 62;
-        if (st == 0) {
+    for (;;) {
+        const int64_t j = base - lane;
+        // before tile 0 there is an implicit inclusive prefix of 0
+        const uint64_t d =
+            j >= 0 ? __hip_atomic_load(&desc[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kStInc;
+        const uint32_t st = (uint32_t)(d >> 62);
+        const uint64_t inc = __ballot(st == 2);
+        const uint64_t notready = __ballot(st == 0);
+        const int first = inc ? __ffsll((long long)inc) - 1 : 64;
+        const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
+        if (notready & need) {
             if (++spins > kSpinLimit) {
-                atomicOr(flags, F_TIMEOUT);
+                if (lane == 0) atomicOr(flags, F_TIMEOUT);
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        excl = op(d & kPayload, excl);
-        if (st == 2) break;
-        --j;
+        const uint64_t v = wave_reduce64(lane <= first ? (d & kPayload) : 0ull, op);
+        excl = op(excl, v);
+        if (first < 64) break;
+        base -= 64;
     }
-    __hip_atomic_store(&desc[t], kStInc | op(excl, agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0) __hip_atomic_store(&desc[t], kStInc | op(excl, agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return excl;
 }
 
 struct OpAdd {
     __device__ uint64_t operator()(uint64_t a, uint64_t b) const { return (a + b) & kPayload; }
 };
+
 
 // Two saturating 31-bit counters in one payload (outliers low, patches high).
 struct OpPair31 {

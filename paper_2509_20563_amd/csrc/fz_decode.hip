@@ -2,7 +2,6 @@
 // decoding of the quantisation codes plus scattering of the outliers into
 // the reconstruction; the inverse of the Lorenzo predictor is a prefix sum):
 //   k_lut          - validates the code lengths, builds a 4096-entry table
-//   k_scan_chunks  - exclusive scan of the per-block bit counts
 //   k_decode       - one lane per block: table-driven Huffman decode from a
 //                    per-lane window staged in LDS, outlier overwrite,
 //                    in-block prefix sums (inverse Lorenzo), dequantisation,
@@ -68,50 +67,6 @@ __global__ __launch_bounds__(1024) void k_lut(const uint8_t* __restrict__ lensp,
     }
 }
 
-// ------------------------------------------------------ chunk offset scan
-constexpr int kScanTile = 1024;
-
-__global__ __launch_bounds__(256) void k_scan_chunks(const uint16_t* __restrict__ chunks, uint32_t nblocks,
-                                                     uint64_t* __restrict__ off, uint64_t* desc, Misc* misc,
-                                                     uint64_t stream_bits, uint32_t ntiles) {
-    __shared__ uint32_t wsum[4];
-    __shared__ uint32_t s_tile;
-    __shared__ uint64_t s_G;
-    const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    if (t == 0) s_tile = atomicAdd(&misc->stile_ctr, 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    if (tile >= ntiles) return;
-    const uint64_t base = (uint64_t)tile * kScanTile + 4 * t;
-    uint32_t v[4];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-        v[k] = (base + k < nblocks) ? chunks[base + k] : 0u;
-        sum += v[k];
-    }
-    const uint32_t incl = wave_incl_scan(sum);
-    if (lane == 63) wsum[wave] = incl;
-    __syncthreads();
-    uint32_t wpre = 0, T = 0;
-    for (uint32_t w = 0; w < 4; w++) {
-        if (w < wave) wpre += wsum[w];
-        T += wsum[w];
-    }
-    if (t == 0) {
-        const uint64_t G = lookback(desc, tile, (uint64_t)T, OpAdd(), &misc->flags);
-        s_G = G;
-        if (tile == ntiles - 1 && G + T != stream_bits) atomicOr(&misc->flags, F_CORRUPT);
-    }
-    __syncthreads();
-    uint64_t p = s_G + wpre + incl - sum;
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-        if (base + k < nblocks) off[base + k] = p;
-        p += v[k];
-    }
-}
-
 // ----------------------------------------------------------------- decode
 constexpr int kWin = 20;  // words staged per lane and round (5 x 16 B)
 
@@ -151,23 +106,33 @@ __global__ __launch_bounds__(256) void k_decode(Geom g, const uint32_t* __restri
     const uint32_t t = threadIdx.x;
     for (uint32_t i = t; i < (uint32_t)kLut; i += 256) LUT[i] = lut_g[i];
     __syncthreads();
-    const uint32_t b = blockIdx.x * 256 + t;
-    if (b >= g.nblocks) return;
+    const uint32_t b0 = blockIdx.x * 256 + t;
+    const bool active = b0 < g.nblocks;
+    const uint32_t b = active ? b0 : g.nblocks - 1;  // inactive lanes idle until the final reduction
     const BlockInfo info = block_info(g, b);
     const uint64_t start = off[b];
     LaneStream ls;
     ls.stream = stream;
     ls.nwords = nwords;
     ls.win = &WIN[t * kWin];
-    uint32_t optr = ~0u;
     uint32_t code0 = 0;
     bool bad = false;
     const uint32_t pos_b = b * kBlockElems;
-    (void)pos_b;
+    // the block's outliers are consecutive in the position-sorted list,
+    // starting at ofirst[b] (meaningful only for blocks that have outliers:
+    // every use is bounds- and position-checked); the next one is kept
+    // prefetched in registers
+    uint32_t optr = 0, npos = 0xFFFFFFFFu;
+    int32_t nval = 0;
+    if (n_out) {
+        optr = ofirst[b];
+        if (optr < n_out) {
+            npos = opos[optr];
+            nval = oval[optr];
+        }
+    }
 
-    // decode one codeword; outliers (code 0) take their residual from the
-    // list, starting at the block's first outlier (ofirst, valid only for
-    // blocks that have outliers: every use is bounds- and position-checked)
+    // decode one codeword; code 0 takes the next outlier residual
     auto next = [&](uint32_t pos) -> int32_t {
         const uint32_t wi = ls.rel >> 5, sh = ls.rel & 31;
         const uint32_t w0 = ls.win[wi], w1 = ls.win[wi + 1];
@@ -177,11 +142,17 @@ __global__ __launch_bounds__(256) void k_decode(Geom g, const uint32_t* __restri
         const uint32_t sym = e & 1023u;
         if (sym) return (int32_t)sym - kRadius;
         code0++;
-        if (optr == ~0u) optr = ofirst[b];
-        int32_t d = 0;
-        if (optr < n_out && opos[optr] == pos) d = oval[optr];
-        else bad = true;
+        int32_t d = nval;
+        if (npos != pos) {
+            bad = true;
+            d = 0;
+        }
         optr++;
+        npos = 0xFFFFFFFFu;
+        if (optr < n_out) {
+            npos = opos[optr];
+            nval = oval[optr];
+        }
         return d;
     };
     auto deq = [&](int32_t q) -> float { return (float)((double)q * e2); };
@@ -202,7 +173,9 @@ __global__ __launch_bounds__(256) void k_decode(Geom g, const uint32_t* __restri
     ls.aw = 0;
     ls.rel = 0;
     uint64_t bp = start;
-    if (ND == 3) {
+    if (!active) {
+        // nothing to decode
+    } else if (ND == 3) {
         int32_t qp[64];
 #pragma unroll
         for (int i = 0; i < 64; i++) qp[i] = 0;
@@ -282,9 +255,9 @@ __global__ __launch_bounds__(256) void k_decode(Geom g, const uint32_t* __restri
             bp = ls.bitpos();
         }
     }
-    if (bp - start != chunks[b]) bad = true;
+    if (active && bp - start != chunks[b]) bad = true;
     if (bad) atomicOr(&misc->flags, F_CORRUPT);
-    uint32_t c = code0;
+    uint32_t c = active ? code0 : 0u;
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
     if ((t & 63) == 0 && c) atomicAdd(&misc->code0_count, c);
@@ -332,13 +305,6 @@ __global__ __launch_bounds__(256) void k_patch(Geom g, const uint32_t* __restric
 // ------------------------------------------------------------- launchers
 void launch_lut(hipStream_t st, const uint8_t* lens_packed, uint16_t* lut, Misc* misc) {
     hipLaunchKernelGGL(k_lut, dim3(1), dim3(1024), 0, st, lens_packed, lut, misc);
-}
-
-void launch_scan_chunks(hipStream_t st, const uint16_t* chunks, uint32_t nblocks, uint64_t* off, uint64_t* desc,
-                        Misc* misc, uint64_t stream_bits) {
-    const uint32_t ntiles = (nblocks + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(k_scan_chunks, dim3(ntiles), dim3(256), 0, st, chunks, nblocks, off, desc, misc,
-                       stream_bits, ntiles);
 }
 
 void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,

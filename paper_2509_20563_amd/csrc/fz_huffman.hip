@@ -3,8 +3,9 @@
 // runs this on the CPU, here it runs on the GPU):
 //   k_codebook - length-limited minimum-redundancy code lengths by
 //                package-merge in one workgroup, canonical codewords;
-//   k_encode   - chunked encoding (chunk = block), bit offsets by
-//                decoupled look-back, words assembled in LDS;
+//   k_encode_len / k_encode_write - chunked encoding (chunk = block) in
+//                two passes around a scan of per-tile bit counts, words
+//                assembled in LDS;
 //   k_finalize - tile-boundary words, outlier/patch sections, header.
 #include "fz_common.h"
 #include "fz_kernels.h"
@@ -155,29 +156,14 @@ __device__ __forceinline__ void append_bits(uint64_t& hi, uint64_t& lo, uint32_t
 
 constexpr int kEncWords = kTileBlocks * kBlockElems * kLmax / 32 + 8;
 
-// One workgroup encodes one tile of 4 blocks (thread = block*64 + segment).
+// Pass 1: bits per block (written to the container's chunk table) and per
+// 4-block tile.  Pass 2, after a scan of the tile totals: the bits
+// themselves at known offsets.  Tiles are assigned statically (grid-stride),
+// thread = block*64 + segment, so the two passes see the same tiles and the
+// only cross-tile dependency is the scan between them.
 template <int ND>
-__global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ codes, Geom g,
-                                                const uint32_t* __restrict__ cw_g, Misc* misc, uint64_t* desc,
-                                                uint32_t ntiles, uint8_t* __restrict__ out, uint64_t off_chunks,
-                                                uint64_t off_stream, uint64_t* __restrict__ tstart,
-                                                uint32_t* __restrict__ tfirst, uint32_t* __restrict__ tlast) {
-    __shared__ uint32_t CW[kBins];
-    __shared__ uint32_t W[kEncWords];
-    __shared__ uint32_t wsum[4];
-    __shared__ uint32_t s_tile;
-    __shared__ uint64_t s_G;
-
-    const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    for (uint32_t i = t; i < (uint32_t)kBins; i += 256) CW[i] = cw_g[i];
-    for (uint32_t i = t; i < (uint32_t)kEncWords; i += 256) W[i] = 0;
-    if (t == 0) s_tile = atomicAdd(&misc->etile_ctr, 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    if (tile >= ntiles) return;
-
-    const uint32_t s = t & 63;
-    const uint32_t b = tile * kTileBlocks + wave;
+__device__ __forceinline__ uint32_t load_codes(const uint16_t* __restrict__ codes, const Geom& g, uint32_t b,
+                                               uint32_t s, uint32_t c8[8]) {
     uint32_t nv = 0;
     uint4 pk = make_uint4(0, 0, 0, 0);
     if (b < g.nblocks) {
@@ -185,76 +171,121 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ cod
         seg_index<ND>(g, info, s, nv);
         if (nv) pk = *reinterpret_cast<const uint4*>(&codes[(uint64_t)b * kBlockElems + s * 8]);
     }
-    const uint32_t c8[8] = {pk.x & 0xFFFFu, pk.x >> 16, pk.y & 0xFFFFu, pk.y >> 16,
-                            pk.z & 0xFFFFu, pk.z >> 16, pk.w & 0xFFFFu, pk.w >> 16};
-    uint64_t hi = 0, lo = 0;
-    uint32_t nb = 0;
+    c8[0] = pk.x & 0xFFFFu; c8[1] = pk.x >> 16; c8[2] = pk.y & 0xFFFFu; c8[3] = pk.y >> 16;
+    c8[4] = pk.z & 0xFFFFu; c8[5] = pk.z >> 16; c8[6] = pk.w & 0xFFFFu; c8[7] = pk.w >> 16;
+    return nv;
+}
+
+template <int ND>
+__global__ __launch_bounds__(256) void k_encode_len(const uint16_t* __restrict__ codes, Geom g,
+                                                    const uint32_t* __restrict__ cw_g, uint32_t ntiles,
+                                                    uint16_t* __restrict__ chunks, uint32_t* __restrict__ tile_bits) {
+    __shared__ uint8_t LEN[kBins];
+    __shared__ uint32_t wsum[4];
+    const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (uint32_t i = t; i < (uint32_t)kBins; i += 256) LEN[i] = (uint8_t)(cw_g[i] >> 16);
+    __syncthreads();
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t b = tile * kTileBlocks + wave;
+        uint32_t c8[8];
+        const uint32_t nv = load_codes<ND>(codes, g, b, t & 63, c8);
+        uint32_t nb = 0;
 #pragma unroll
-    for (int i = 0; i < 8; i++) {
-        if (i < (int)nv) {
-            const uint32_t e = CW[c8[i]];
-            append_bits(hi, lo, nb, e & 0xFFFFu, e >> 16);
+        for (int i = 0; i < 8; i++) nb += (i < (int)nv) ? LEN[c8[i]] : 0u;
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) nb += __shfl_xor(nb, d, 64);
+        if (lane == 0) {
+            if (b < g.nblocks) chunks[b] = (uint16_t)nb;
+            wsum[wave] = nb;
         }
+        __syncthreads();
+        if (t == 0) tile_bits[tile] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        __syncthreads();
     }
-    // bit offsets: wave scan (one wave = one block), then across the tile
-    const uint32_t incl = wave_incl_scan(nb);
-    if (lane == 63) wsum[wave] = incl;
+}
+
+template <int ND>
+__global__ __launch_bounds__(256) void k_encode_write(const uint16_t* __restrict__ codes, Geom g,
+                                                      const uint32_t* __restrict__ cw_g, uint32_t ntiles,
+                                                      const uint64_t* __restrict__ tile_start, Misc* misc,
+                                                      uint32_t* __restrict__ stream, uint32_t* __restrict__ tfirst,
+                                                      uint32_t* __restrict__ tlast) {
+    __shared__ uint32_t CW[kBins];
+    __shared__ uint32_t W[kEncWords];
+    __shared__ uint32_t wsum[4];
+
+    const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (uint32_t i = t; i < (uint32_t)kBins; i += 256) CW[i] = cw_g[i];
+    for (uint32_t i = t; i < (uint32_t)kEncWords; i += 256) W[i] = 0;
     __syncthreads();
-    uint32_t wpre = 0, T = 0;
-    for (uint32_t w = 0; w < 4; w++) {
-        if (w < wave) wpre += wsum[w];
-        T += wsum[w];
-    }
-    if (lane == 63 && b < g.nblocks) {
-        uint16_t* chunks = reinterpret_cast<uint16_t*>(out + off_chunks);
-        chunks[b] = (uint16_t)incl;
-    }
-    if (t == 0) {
-        const uint64_t G = lookback(desc, tile, (uint64_t)T, OpAdd(), &misc->flags);
-        s_G = G;
-        tstart[tile] = G;
-        if (tile == ntiles - 1) misc->total_bits_enc = G + T;
-        else if (T < 32) atomicOr(&misc->flags, F_INTERNAL);
-    }
-    __syncthreads();
-    const uint64_t G = s_G;
-    const uint32_t sh = (uint32_t)(G & 31);
-    // place this thread's bits into the tile's word buffer
-    if (nb) {
-        const uint32_t p = sh + wpre + incl - nb;
-        const uint32_t o = p & 31, w0 = p >> 5;
-        const uint32_t s0 = (uint32_t)(hi >> 32), s1 = (uint32_t)hi, s2 = (uint32_t)(lo >> 32), s3 = (uint32_t)lo;
-        const uint32_t o0 = s0 >> o;
-        const uint32_t o1 = __builtin_amdgcn_alignbit(s0, s1, o);
-        const uint32_t o2 = __builtin_amdgcn_alignbit(s1, s2, o);
-        const uint32_t o3 = __builtin_amdgcn_alignbit(s2, s3, o);
-        if (o0) atomicOr(&W[w0], o0);
-        if (o1) atomicOr(&W[w0 + 1], o1);
-        if (o2) atomicOr(&W[w0 + 2], o2);
-        if (o3) atomicOr(&W[w0 + 3], o3);
-    }
-    __syncthreads();
-    const uint32_t nwords = (sh + T + 31) >> 5;
-    const bool last_partial = ((sh + T) & 31) != 0 && tile != ntiles - 1;
-    uint32_t* stream = reinterpret_cast<uint32_t*>(out + off_stream);
-    const uint64_t wbase = G >> 5;
-    for (uint32_t w = t; w < nwords; w += 256) {
-        const uint32_t v = W[w];
-        if (w == 0 && sh != 0) tfirst[tile] = v;
-        else if (w == nwords - 1 && last_partial) tlast[tile] = v;
-        else stream[wbase + w] = v;
+
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t b = tile * kTileBlocks + wave;
+        uint32_t c8[8];
+        const uint32_t nv = load_codes<ND>(codes, g, b, t & 63, c8);
+        uint64_t hi = 0, lo = 0;
+        uint32_t nb = 0;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            if (i < (int)nv) {
+                const uint32_t e = CW[c8[i]];
+                append_bits(hi, lo, nb, e & 0xFFFFu, e >> 16);
+            }
+        }
+        const uint32_t incl = wave_incl_scan(nb);
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        uint32_t wpre = 0, T = 0;
+        for (uint32_t w = 0; w < 4; w++) {
+            if (w < wave) wpre += wsum[w];
+            T += wsum[w];
+        }
+        const uint64_t G = tile_start[tile];
+        const uint32_t sh = (uint32_t)(G & 31);
+        if (t == 0 && tile != ntiles - 1 && T < 32) atomicOr(&misc->flags, F_INTERNAL);
+        if (nb) {
+            const uint32_t p = sh + wpre + incl - nb;
+            const uint32_t o = p & 31, w0 = p >> 5;
+            const uint32_t s0 = (uint32_t)(hi >> 32), s1 = (uint32_t)hi, s2 = (uint32_t)(lo >> 32),
+                           s3 = (uint32_t)lo;
+            const uint32_t o0 = s0 >> o;
+            const uint32_t o1 = __builtin_amdgcn_alignbit(s0, s1, o);
+            const uint32_t o2 = __builtin_amdgcn_alignbit(s1, s2, o);
+            const uint32_t o3 = __builtin_amdgcn_alignbit(s2, s3, o);
+            if (o0) atomicOr(&W[w0], o0);
+            if (o1) atomicOr(&W[w0 + 1], o1);
+            if (o2) atomicOr(&W[w0 + 2], o2);
+            if (o3) atomicOr(&W[w0 + 3], o3);
+        }
+        __syncthreads();
+        // interior words go to the stream; the partial first and last words
+        // are shared with the neighbouring tiles and merged by k_finalize
+        const uint32_t nwords = (sh + T + 31) >> 5;
+        const bool last_partial = ((sh + T) & 31) != 0 && tile != ntiles - 1;
+        const uint64_t wbase = G >> 5;
+        for (uint32_t w = t; w < nwords; w += 256) {
+            const uint32_t v = W[w];
+            W[w] = 0;
+            if (w == 0 && sh != 0) tfirst[tile] = v;
+            else if (w == nwords - 1 && last_partial) tlast[tile] = v;
+            else stream[wbase + w] = v;
+        }
+        __syncthreads();
     }
 }
 
 // ------------------------------------------------------------- finalize
 // Layout from the device-side counts; boundary words shared by two tiles;
-// outlier and patch sections; zero padding; header.  When the packed
-// container would not be smaller than the raw floats (or staging
-// overflowed) only the verbatim decision is recorded for the host.
+// outlier and patch sections compacted from the per-tile staging slots in
+// tile order (= position order); zero padding; header.  When the packed
+// container would not be smaller than the raw floats only the verbatim
+// decision is recorded for the host.
 __global__ __launch_bounds__(256) void k_finalize(Geom g, uint32_t mode, double eb, Misc* misc, uint8_t* out,
-                                                  const uint64_t* __restrict__ tstart,
+                                                  uint32_t ntiles, const uint64_t* __restrict__ tile_start,
                                                   const uint32_t* __restrict__ tfirst,
-                                                  const uint32_t* __restrict__ tlast, uint32_t ntiles,
+                                                  const uint32_t* __restrict__ tlast,
+                                                  const uint32_t* __restrict__ tile_cnt,
+                                                  const uint64_t* __restrict__ tile_off,
                                                   const uint32_t* __restrict__ opos, const int32_t* __restrict__ oval,
                                                   const uint32_t* __restrict__ ppos,
                                                   const uint32_t* __restrict__ pbits) {
@@ -275,20 +306,32 @@ __global__ __launch_bounds__(256) void k_finalize(Geom g, uint32_t mode, double 
 
     uint32_t* stream = reinterpret_cast<uint32_t*>(out + L.stream);
     for (uint64_t i = gid + 1; i < ntiles; i += stride) {
-        const uint64_t G = tstart[i];
+        const uint64_t G = tile_start[i];
         if (G & 31) stream[G >> 5] = tlast[i - 1] | tfirst[i];
     }
     uint32_t* o_pos = reinterpret_cast<uint32_t*>(out + L.opos);
     int32_t* o_val = reinterpret_cast<int32_t*>(out + L.oval);
-    for (uint64_t i = gid; i < nout; i += stride) {
-        o_pos[i] = opos[i];
-        o_val[i] = oval[i];
-    }
     uint32_t* p_pos = reinterpret_cast<uint32_t*>(out + L.ppos);
     uint32_t* p_bits = reinterpret_cast<uint32_t*>(out + L.pbits);
-    for (uint64_t i = gid; i < npat; i += stride) {
-        p_pos[i] = ppos[i];
-        p_bits[i] = pbits[i];
+    if (nout | npat) {
+        const uint32_t lane = threadIdx.x & 63;
+        const uint64_t wid = gid >> 6, nw = stride >> 6;
+        const uint64_t m31 = (1ull << 31) - 1;
+        for (uint64_t tile = wid; tile < ntiles; tile += nw) {
+            const uint32_t c = tile_cnt[tile];
+            if (!c) continue;
+            const uint64_t off = tile_off[tile];
+            const uint64_t slot = tile * (uint64_t)(kTileBlocks * kBlockElems);
+            const uint32_t co = c & 0xFFFFu, cp = c >> 16;
+            for (uint32_t j = lane; j < co; j += 64) {
+                o_pos[(off & m31) + j] = opos[slot + j];
+                o_val[(off & m31) + j] = oval[slot + j];
+            }
+            for (uint32_t j = lane; j < cp; j += 64) {
+                p_pos[(off >> 31) + j] = ppos[slot + j];
+                p_bits[(off >> 31) + j] = pbits[slot + j];
+            }
+        }
     }
     if (gid == 0) {
         // zero padding between and after sections
@@ -309,9 +352,9 @@ __global__ __launch_bounds__(256) void k_finalize(Geom g, uint32_t mode, double 
         h[5] = (uint8_t)(kVersion >> 8);
         st32(8, g.ndim);
         st32(12, 0);
-        st64(16, g.ndim >= 1 ? g.n[0] : 1);
-        st64(24, g.ndim >= 2 ? g.n[1] : 1);
-        st64(32, g.ndim >= 3 ? g.n[2] : 1);
+        st64(16, g.n[0]);
+        st64(24, g.n[1]);
+        st64(32, g.n[2]);
         st32(40, mode);
         st32(44, kRadius);
         st64(48, __double_as_longlong(eb));
@@ -333,26 +376,40 @@ void launch_codebook(hipStream_t st, const uint32_t* hist, uint8_t* out_lens, ui
     hipLaunchKernelGGL(k_codebook, dim3(1), dim3(1024), 0, st, hist, out_lens, cw, misc);
 }
 
-void launch_encode(hipStream_t st, const uint16_t* codes, const Geom& g, const uint32_t* cw, Misc* misc,
-                   uint64_t* desc, uint32_t ntiles, uint8_t* out, uint64_t* tstart, uint32_t* tfirst,
-                   uint32_t* tlast) {
+void launch_encode_len(hipStream_t st, int grid, const uint16_t* codes, const Geom& g, const uint32_t* cw,
+                       uint32_t ntiles, uint8_t* out, uint32_t* tile_bits) {
     const Layout L = make_layout(g.nblocks, 0, 0, 0);
+    uint16_t* chunks = reinterpret_cast<uint16_t*>(out + L.chunks);
     if (g.ndim == 3)
-        hipLaunchKernelGGL(k_encode<3>, dim3(ntiles), dim3(256), 0, st, codes, g, cw, misc, desc, ntiles, out,
-                           L.chunks, L.stream, tstart, tfirst, tlast);
+        hipLaunchKernelGGL(k_encode_len<3>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, chunks, tile_bits);
     else if (g.ndim == 2)
-        hipLaunchKernelGGL(k_encode<2>, dim3(ntiles), dim3(256), 0, st, codes, g, cw, misc, desc, ntiles, out,
-                           L.chunks, L.stream, tstart, tfirst, tlast);
+        hipLaunchKernelGGL(k_encode_len<2>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, chunks, tile_bits);
     else
-        hipLaunchKernelGGL(k_encode<1>, dim3(ntiles), dim3(256), 0, st, codes, g, cw, misc, desc, ntiles, out,
-                           L.chunks, L.stream, tstart, tfirst, tlast);
+        hipLaunchKernelGGL(k_encode_len<1>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, chunks, tile_bits);
+}
+
+void launch_encode_write(hipStream_t st, int grid, const uint16_t* codes, const Geom& g, const uint32_t* cw,
+                         Misc* misc, uint32_t ntiles, uint8_t* out, const uint64_t* tile_start, uint32_t* tfirst,
+                         uint32_t* tlast) {
+    const Layout L = make_layout(g.nblocks, 0, 0, 0);
+    uint32_t* stream = reinterpret_cast<uint32_t*>(out + L.stream);
+    if (g.ndim == 3)
+        hipLaunchKernelGGL(k_encode_write<3>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, tile_start, misc,
+                           stream, tfirst, tlast);
+    else if (g.ndim == 2)
+        hipLaunchKernelGGL(k_encode_write<2>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, tile_start, misc,
+                           stream, tfirst, tlast);
+    else
+        hipLaunchKernelGGL(k_encode_write<1>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, tile_start, misc,
+                           stream, tfirst, tlast);
 }
 
 void launch_finalize(hipStream_t st, const Geom& g, uint32_t mode, double eb, Misc* misc, uint8_t* out,
-                     const uint64_t* tstart, const uint32_t* tfirst, const uint32_t* tlast, uint32_t ntiles,
-                     const uint32_t* opos, const int32_t* oval, const uint32_t* ppos, const uint32_t* pbits) {
-    hipLaunchKernelGGL(k_finalize, dim3(512), dim3(256), 0, st, g, mode, eb, misc, out, tstart, tfirst, tlast,
-                       ntiles, opos, oval, ppos, pbits);
+                     uint32_t ntiles, const uint64_t* tile_start, const uint32_t* tfirst, const uint32_t* tlast,
+                     const uint32_t* tile_cnt, const uint64_t* tile_off, const uint32_t* opos, const int32_t* oval,
+                     const uint32_t* ppos, const uint32_t* pbits) {
+    hipLaunchKernelGGL(k_finalize, dim3(1024), dim3(256), 0, st, g, mode, eb, misc, out, ntiles, tile_start, tfirst,
+                       tlast, tile_cnt, tile_off, opos, oval, ppos, pbits);
 }
 
 }  // namespace fz

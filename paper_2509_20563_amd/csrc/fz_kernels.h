@@ -1,4 +1,4 @@
-// Host-side launchers of the libfz kernels (one declaration per kernel).
+// Host-side launchers of the libfz kernels (one declaration per kernel group).
 #pragma once
 
 #include "fz_common.h"
@@ -10,22 +10,28 @@ void launch_reset(hipStream_t st, Misc* misc, uint32_t* hist, uint64_t* d1, uint
                   uint32_t n2);
 void launch_minmax(hipStream_t st, const float* x, uint64_t N, int vec, Misc* misc, int grid);
 void launch_quant(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
-                  Misc* misc, uint32_t* hist, uint16_t* codes, uint64_t* desc, uint32_t ntiles, uint32_t* opos,
-                  int32_t* oval, uint64_t ocap, uint32_t* ppos, uint32_t* pbits, uint64_t pcap);
+                  Misc* misc, uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt, uint32_t* opos,
+                  int32_t* oval, uint32_t* ppos, uint32_t* pbits);
+
+// fz_scan.hip
+void launch_scan(hipStream_t st, int kind, const void* in, uint32_t n, uint64_t* out, uint64_t* desc, uint32_t* ctr,
+                 Misc* misc, uint64_t expect);
+uint32_t scan_tiles(uint32_t n);
 
 // fz_huffman.hip
 void launch_codebook(hipStream_t st, const uint32_t* hist, uint8_t* out_lens, uint32_t* cw, Misc* misc);
-void launch_encode(hipStream_t st, const uint16_t* codes, const Geom& g, const uint32_t* cw, Misc* misc,
-                   uint64_t* desc, uint32_t ntiles, uint8_t* out, uint64_t* tstart, uint32_t* tfirst,
-                   uint32_t* tlast);
+void launch_encode_len(hipStream_t st, int grid, const uint16_t* codes, const Geom& g, const uint32_t* cw,
+                       uint32_t ntiles, uint8_t* out, uint32_t* tile_bits);
+void launch_encode_write(hipStream_t st, int grid, const uint16_t* codes, const Geom& g, const uint32_t* cw,
+                         Misc* misc, uint32_t ntiles, uint8_t* out, const uint64_t* tile_start, uint32_t* tfirst,
+                         uint32_t* tlast);
 void launch_finalize(hipStream_t st, const Geom& g, uint32_t mode, double eb, Misc* misc, uint8_t* out,
-                     const uint64_t* tstart, const uint32_t* tfirst, const uint32_t* tlast, uint32_t ntiles,
-                     const uint32_t* opos, const int32_t* oval, const uint32_t* ppos, const uint32_t* pbits);
+                     uint32_t ntiles, const uint64_t* tile_start, const uint32_t* tfirst, const uint32_t* tlast,
+                     const uint32_t* tile_cnt, const uint64_t* tile_off, const uint32_t* opos, const int32_t* oval,
+                     const uint32_t* ppos, const uint32_t* pbits);
 
 // fz_decode.hip
 void launch_lut(hipStream_t st, const uint8_t* lens_packed, uint16_t* lut, Misc* misc);
-void launch_scan_chunks(hipStream_t st, const uint16_t* chunks, uint32_t nblocks, uint64_t* off, uint64_t* desc,
-                        Misc* misc, uint64_t stream_bits);
 void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,
                    const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
                    const int32_t* oval, uint32_t* ofirst, uint64_t n_out, double e2, float* out, int vec,

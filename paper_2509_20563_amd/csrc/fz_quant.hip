@@ -35,9 +35,23 @@ __global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, uin
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     uint64_t tail = 0;
     if (vec) {
+        // four independent 16-byte loads in flight per thread and iteration
         const f32x4* x4 = reinterpret_cast<const f32x4*>(x);
         const uint64_t n4 = N / 4;
-        for (uint64_t i = gid; i < n4; i += stride) {
+        uint64_t i = gid;
+        for (; i + 3 * stride < n4; i += 4 * stride) {
+            f32x4 v[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) v[k] = __builtin_nontemporal_load(&x4[i + k * stride]);
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                bad |= !(__builtin_isfinite(v[k].x) && __builtin_isfinite(v[k].y) && __builtin_isfinite(v[k].z) &&
+                         __builtin_isfinite(v[k].w));
+                lo = fminf(lo, fminf(fminf(v[k].x, v[k].y), fminf(v[k].z, v[k].w)));
+                hi = fmaxf(hi, fmaxf(fmaxf(v[k].x, v[k].y), fmaxf(v[k].z, v[k].w)));
+            }
+        }
+        for (; i < n4; i += stride) {
             f32x4 v = __builtin_nontemporal_load(&x4[i]);
             bad |= !(__builtin_isfinite(v.x) && __builtin_isfinite(v.y) && __builtin_isfinite(v.z) &&
                      __builtin_isfinite(v.w));
@@ -106,24 +120,23 @@ __device__ __forceinline__ void load_map(uint32_t t, uint32_t& bi, uint32_t& s) 
 
 // ------------------------------------------- fused Lorenzo quantisation
 // One workgroup (256 threads) handles a tile of 4 consecutive blocks per
-// iteration; workgroups take tiles from an atomic counter, so outliers and
-// patches can be placed in block order by a decoupled look-back.
+// iteration (tiles assigned statically, grid-strided).  Outliers and
+// patches go to the tile's own staging slots with a per-tile count; the
+// container sections are compacted in order after a scan of those counts.
 //   phase A (load mapping): 8 values per thread -> q, patch mask -> LDS
 //   phase B (thread = block*64 + segment): Lorenzo residual from LDS, codes
 //     (block-major, u16), histogram, outlier/patch positions.
 template <int ND>
 __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom g, uint32_t mode, double eb,
                                                int vec, Misc* misc, uint32_t* __restrict__ hist_g,
-                                               uint16_t* __restrict__ codes, uint64_t* desc, uint32_t ntiles,
-                                               uint32_t* __restrict__ opos, int32_t* __restrict__ oval,
-                                               uint64_t ocap, uint32_t* __restrict__ ppos,
-                                               uint32_t* __restrict__ pbits, uint64_t pcap) {
+                                               uint16_t* __restrict__ codes, uint32_t ntiles,
+                                               uint32_t* __restrict__ tile_cnt, uint32_t* __restrict__ opos,
+                                               int32_t* __restrict__ oval, uint32_t* __restrict__ ppos,
+                                               uint32_t* __restrict__ pbits) {
     __shared__ int32_t Q[kTileBlocks * kBlockElems];
     __shared__ uint8_t PM[kTileBlocks * kSegs];
     __shared__ uint32_t H[kBins];
     __shared__ uint32_t wsum[4];
-    __shared__ uint32_t s_tile;
-    __shared__ uint64_t s_excl;
 
     const uint32_t t = threadIdx.x;
     const uint32_t lane = t & 63, wave = t >> 6;
@@ -136,12 +149,8 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
     const double inv = 1.0 / e2;
     for (uint32_t i = t; i < (uint32_t)kBins; i += 256) H[i] = 0;
 
-    for (;;) {
-        if (t == 0) s_tile = atomicAdd(&misc->qtile_ctr, 1u);
-        __syncthreads();
-        const uint32_t tile = s_tile;
-        if (tile >= ntiles) break;
-
+    // static tile assignment: no counter, no cross-tile dependency
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         // ---------------- phase A: load + prequantise
         {
             uint32_t bi, s;
@@ -303,44 +312,27 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
             tot += v;
         }
         const uint32_t excl_local = wpre + incl - packed;
-        if (t == 0) {
-            const uint64_t agg = (uint64_t)(tot & 0xFFFFu) | ((uint64_t)(tot >> 16) << 31);
-            s_excl = lookback(desc, tile, agg, OpPair31(), &misc->flags);
-            if (tile == ntiles - 1) {
-                const uint64_t incl_all = OpPair31()(s_excl, agg);
-                misc->n_out = incl_all & ((1ull << 31) - 1);
-                misc->n_pat = incl_all >> 31;
-            }
-        }
-        __syncthreads();
-        const uint64_t ex = s_excl;
+        if (t == 0) tile_cnt[tile] = tot;
+        // each tile owns staging slots [tile * 2048, tile * 2048 + 2048) for
+        // outliers and for patches, in position order inside the tile
         if (omask | pmask) {
-            uint64_t oi = (ex & ((1ull << 31) - 1)) + (excl_local & 0xFFFFu);
-            uint64_t pi = (ex >> 31) + (excl_local >> 16);
+            const uint64_t slot = (uint64_t)tile * kTileBlocks * kBlockElems;
+            uint64_t oi = slot + (excl_local & 0xFFFFu);
+            uint64_t pi = slot + (excl_local >> 16);
             const uint32_t pos0 = b * kBlockElems + s * 8;
-            bool ovf = false;
 #pragma unroll
             for (int i = 0; i < 8; i++) {
                 if (omask & (1u << i)) {
-                    if (oi < ocap) {
-                        opos[oi] = pos0 + i;
-                        oval[oi] = d[i];
-                    } else {
-                        ovf = true;
-                    }
+                    opos[oi] = pos0 + i;
+                    oval[oi] = d[i];
                     oi++;
                 }
                 if (pmask & (1u << i)) {
-                    if (pi < pcap) {
-                        ppos[pi] = pos0 + i;
-                        pbits[pi] = __float_as_uint(x[base + i]);
-                    } else {
-                        ovf = true;
-                    }
+                    ppos[pi] = pos0 + i;
+                    pbits[pi] = __float_as_uint(x[base + i]);
                     pi++;
                 }
             }
-            if (ovf) atomicOr(&misc->flags, F_OVERFLOW);
         }
         __syncthreads();
     }
@@ -364,17 +356,17 @@ void launch_minmax(hipStream_t st, const float* x, uint64_t N, int vec, Misc* mi
 }
 
 void launch_quant(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
-                  Misc* misc, uint32_t* hist, uint16_t* codes, uint64_t* desc, uint32_t ntiles, uint32_t* opos,
-                  int32_t* oval, uint64_t ocap, uint32_t* ppos, uint32_t* pbits, uint64_t pcap) {
+                  Misc* misc, uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt, uint32_t* opos,
+                  int32_t* oval, uint32_t* ppos, uint32_t* pbits) {
     if (g.ndim == 3)
-        hipLaunchKernelGGL(k_quant<3>, dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, hist, codes, desc,
-                           ntiles, opos, oval, ocap, ppos, pbits, pcap);
+        hipLaunchKernelGGL(k_quant<3>, dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, hist, codes, ntiles,
+                           tile_cnt, opos, oval, ppos, pbits);
     else if (g.ndim == 2)
-        hipLaunchKernelGGL(k_quant<2>, dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, hist, codes, desc,
-                           ntiles, opos, oval, ocap, ppos, pbits, pcap);
+        hipLaunchKernelGGL(k_quant<2>, dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, hist, codes, ntiles,
+                           tile_cnt, opos, oval, ppos, pbits);
     else
-        hipLaunchKernelGGL(k_quant<1>, dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, hist, codes, desc,
-                           ntiles, opos, oval, ocap, ppos, pbits, pcap);
+        hipLaunchKernelGGL(k_quant<1>, dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, hist, codes, ntiles,
+                           tile_cnt, opos, oval, ppos, pbits);
 }
 
 }  // namespace fz

@@ -1,0 +1,123 @@
+// Exclusive prefix scans over per-tile or per-block counts, single pass
+// with decoupled look-back (one workgroup per 1024 entries, so a 512^3 field
+// needs 64 workgroups and one counter atomic each):
+//   SCAN_COUNTS - packed (outliers | patches << 16) per quantisation tile ->
+//                 packed prefix (outliers: 31 bits, patches: 31 bits above)
+//   SCAN_BITS   - encoded bits per encoder tile -> bit offset of each tile
+//   SCAN_CHUNKS - u16 bit count per block (container) -> bit offset per block
+#include <type_traits>
+
+#include "fz_common.h"
+#include "fz_kernels.h"
+
+namespace fz {
+
+constexpr int kScanTile = 1024;  // entries per workgroup (256 threads x 4)
+
+template <class Op>
+__device__ inline uint64_t wave_incl_scan64(uint64_t v, Op op) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v = op(o, v);
+    }
+    return v;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void k_scan(const void* __restrict__ in, uint32_t n, uint64_t* __restrict__ out,
+                                              uint64_t* desc, uint32_t* ctr, uint32_t ntiles, Misc* misc,
+                                              uint64_t expect) {
+    using Op = typename std::conditional<KIND == SCAN_COUNTS, OpPair31, OpAdd>::type;
+    const Op op;
+    __shared__ uint64_t wsum[4];
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_excl;
+    const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    if (t == 0) s_tile = atomicAdd(ctr, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    if (tile >= ntiles) return;
+    const uint64_t base = (uint64_t)tile * kScanTile + 4 * t;
+    uint64_t v[4];
+    uint64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        uint64_t e = 0;
+        if (base + k < n) {
+            if (KIND == SCAN_COUNTS) {
+                const uint32_t c = static_cast<const uint32_t*>(in)[base + k];
+                e = (uint64_t)(c & 0xFFFFu) | ((uint64_t)(c >> 16) << 31);
+            } else if (KIND == SCAN_BITS) {
+                e = static_cast<const uint32_t*>(in)[base + k];
+            } else {
+                e = static_cast<const uint16_t*>(in)[base + k];
+            }
+        }
+        v[k] = e;
+        sum = op(sum, e);
+    }
+    const uint64_t incl = wave_incl_scan64(sum, op);
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint64_t wpre = 0, T = 0;
+    for (uint32_t w = 0; w < 4; w++) {
+        if (w < wave) wpre = op(wpre, wsum[w]);
+        T = op(T, wsum[w]);
+    }
+    if (wave == 0) {
+        const uint64_t ex = lookback(desc, tile, T, op, &misc->flags);
+        if (lane == 0) {
+            s_excl = ex;
+            if (tile == ntiles - 1) {
+                const uint64_t total = op(ex, T);
+                if (KIND == SCAN_COUNTS) {
+                    const uint64_t m = (1ull << 31) - 1;
+                    misc->n_out = total & m;
+                    misc->n_pat = total >> 31;
+                    if ((total & m) == m || (total >> 31) == m) atomicOr(&misc->flags, F_OVERFLOW);
+                } else if (KIND == SCAN_BITS) {
+                    misc->total_bits_enc = total;
+                } else if (total != expect) {
+                    atomicOr(&misc->flags, F_CORRUPT);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // exclusive prefix of this thread's first entry: the wave-exclusive part
+    // (exact: no field saturates inside one tile), earlier waves, the tile
+    uint64_t excl_wave;
+    if (KIND == SCAN_COUNTS) {
+        const uint64_t m = (1ull << 31) - 1;
+        excl_wave = ((incl & m) - (sum & m)) | (((incl >> 31) - (sum >> 31)) << 31);
+    } else {
+        excl_wave = incl - sum;
+    }
+    uint64_t p = op(op(s_excl, wpre), excl_wave);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        if (base + k < n) out[base + k] = p;
+        p = op(p, v[k]);
+    }
+}
+
+void launch_scan(hipStream_t st, int kind, const void* in, uint32_t n, uint64_t* out, uint64_t* desc, uint32_t* ctr,
+                 Misc* misc, uint64_t expect) {
+    const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
+    if (ntiles == 0) return;
+    if (kind == SCAN_COUNTS)
+        hipLaunchKernelGGL(k_scan<SCAN_COUNTS>, dim3(ntiles), dim3(256), 0, st, in, n, out, desc, ctr, ntiles, misc,
+                           expect);
+    else if (kind == SCAN_BITS)
+        hipLaunchKernelGGL(k_scan<SCAN_BITS>, dim3(ntiles), dim3(256), 0, st, in, n, out, desc, ctr, ntiles, misc,
+                           expect);
+    else
+        hipLaunchKernelGGL(k_scan<SCAN_CHUNKS>, dim3(ntiles), dim3(256), 0, st, in, n, out, desc, ctr, ntiles, misc,
+                           expect);
+}
+
+uint32_t scan_tiles(uint32_t n) { return (n + kScanTile - 1) / kScanTile; }
+
+}  // namespace fz
