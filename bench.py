@@ -77,6 +77,12 @@ def main():
     x_host = fields.grf(shape, alpha=3.0, seed=2)
     dev = torch.device("cuda", 0)
     x = torch.from_numpy(x_host).to(dev)
+    # a plain device copy of the field (4N bytes read, 4N written): the
+    # reference kernel against which HBM byte counters are calibrated
+    calib = torch.empty_like(x)
+    calib.copy_(x)
+    torch.cuda.synchronize()
+    del calib
     ctx = fz.Context(0, max_elems=n)
     cap = ctx.compress_bound(shape)
     outs = [torch.empty(cap, dtype=torch.uint8, device=dev) for _ in EBS]

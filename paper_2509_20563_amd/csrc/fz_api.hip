@@ -110,6 +110,8 @@ int make_geom(uint32_t ndim, const uint64_t dims[3], Geom* g) {
     }
     r.nblocks = (uint32_t)nb;
     r.N = n[0] * n[1] * n[2];
+    r.dnb0 = make_fastdiv(r.nb[0]);
+    r.dnb1 = make_fastdiv(r.nb[1]);
     *g = r;
     return FZ_OK;
 }

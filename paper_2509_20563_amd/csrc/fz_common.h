@@ -54,6 +54,30 @@ struct Misc {
     uint64_t pad1[3];
 };
 
+// Unsigned division by a runtime constant d <= 2^23 for numerators <= 2^23:
+// q = (umulhi(n, m) + n) >> l with l = ceil(log2 d), m = 2^32 (2^l - d) / d + 1
+// (Granlund & Montgomery; the sum cannot overflow for these ranges).
+struct FastDiv {
+    uint32_t m, l;
+};
+
+__host__ inline FastDiv make_fastdiv(uint32_t d) {
+    uint32_t l = 0;
+    while ((1ull << l) < d) l++;
+    FastDiv f;
+    f.m = (uint32_t)((((1ull << 32) * ((1ull << l) - d)) / d) + 1);
+    f.l = l;
+    return f;
+}
+
+__host__ __device__ inline uint32_t fdiv(uint32_t n, FastDiv f) {
+#ifdef __HIP_DEVICE_COMPILE__
+    return (__umulhi(n, f.m) + n) >> f.l;
+#else
+    return (uint32_t)(((((uint64_t)n * f.m) >> 32) + n) >> f.l);
+#endif
+}
+
 // Field geometry: dims, block shape, block grid.
 struct Geom {
     uint32_t ndim;
@@ -62,6 +86,7 @@ struct Geom {
     uint32_t nb[3];  // blocks per axis
     uint32_t nblocks;
     uint64_t N;
+    FastDiv dnb0, dnb1;  // division by nb[0] and nb[1]
 };
 
 // Block coordinates and real extents of block b.
@@ -72,10 +97,10 @@ struct BlockInfo {
 
 __host__ __device__ inline BlockInfo block_info(const Geom& g, uint32_t b) {
     BlockInfo r;
-    r.bx = b % g.nb[0];
-    uint32_t t = b / g.nb[0];
-    r.by = t % g.nb[1];
-    r.bz = t / g.nb[1];
+    const uint32_t t = fdiv(b, g.dnb0);
+    r.bx = b - t * g.nb[0];
+    r.bz = fdiv(t, g.dnb1);
+    r.by = t - r.bz * g.nb[1];
     uint32_t x0 = r.bx * g.bs[0], y0 = r.by * g.bs[1], z0 = r.bz * g.bs[2];
     r.ex = min(g.bs[0], g.n[0] - x0);
     r.ey = min(g.bs[1], g.n[1] - y0);
@@ -231,14 +256,40 @@ struct OpPair31 {
     }
 };
 
-// Wave-level inclusive scan (64 lanes).
-__device__ inline uint32_t wave_incl_scan(uint32_t v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t o = __shfl_up(v, d, 64);
-        if (lane >= d) v += o;
-    }
+// DPP data movement (gfx9 wave64): row_shr:k shifts within rows of 16
+// lanes, row_bcast:15 / row_bcast:31 pass a row's last lane to later rows.
+// Lanes with no source, or in rows outside ROWMASK, receive 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWMASK, 0xf, false);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+    const uint32_t lo = dpp32<CTRL, ROWMASK>((uint32_t)v);
+    const uint32_t hi = dpp32<CTRL, ROWMASK>((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Wave-level inclusive scan (64 lanes, all active): Hillis-Steele inside
+// each row of 16 lanes, then row totals carried across rows.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    v += dpp32<0x111, 0xf>(v);
+    v += dpp32<0x112, 0xf>(v);
+    v += dpp32<0x114, 0xf>(v);
+    v += dpp32<0x118, 0xf>(v);
+    v += dpp32<0x142, 0xa>(v);
+    v += dpp32<0x143, 0xc>(v);
+    return v;
+}
+
+template <class Op>
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v, Op op) {
+    v = op(dpp64<0x111, 0xf>(v), v);
+    v = op(dpp64<0x112, 0xf>(v), v);
+    v = op(dpp64<0x114, 0xf>(v), v);
+    v = op(dpp64<0x118, 0xf>(v), v);
+    v = op(dpp64<0x142, 0xa>(v), v);
+    v = op(dpp64<0x143, 0xc>(v), v);
     return v;
 }
 

@@ -182,7 +182,8 @@ __global__ __launch_bounds__(256) void k_encode_len(const uint16_t* __restrict__
                                                     uint16_t* __restrict__ chunks, uint32_t* __restrict__ tile_bits) {
     __shared__ uint8_t LEN[kBins];
     __shared__ uint32_t wsum[4];
-    const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const uint32_t t = threadIdx.x, lane = t & 63;
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 6));
     for (uint32_t i = t; i < (uint32_t)kBins; i += 256) LEN[i] = (uint8_t)(cw_g[i] >> 16);
     __syncthreads();
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -192,8 +193,7 @@ __global__ __launch_bounds__(256) void k_encode_len(const uint16_t* __restrict__
         uint32_t nb = 0;
 #pragma unroll
         for (int i = 0; i < 8; i++) nb += (i < (int)nv) ? LEN[c8[i]] : 0u;
-#pragma unroll
-        for (int d = 32; d > 0; d >>= 1) nb += __shfl_xor(nb, d, 64);
+        nb = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(nb), 63);
         if (lane == 0) {
             if (b < g.nblocks) chunks[b] = (uint16_t)nb;
             wsum[wave] = nb;
@@ -214,7 +214,8 @@ __global__ __launch_bounds__(256) void k_encode_write(const uint16_t* __restrict
     __shared__ uint32_t W[kEncWords];
     __shared__ uint32_t wsum[4];
 
-    const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const uint32_t t = threadIdx.x, lane = t & 63;
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 6));
     for (uint32_t i = t; i < (uint32_t)kBins; i += 256) CW[i] = cw_g[i];
     for (uint32_t i = t; i < (uint32_t)kEncWords; i += 256) W[i] = 0;
     __syncthreads();

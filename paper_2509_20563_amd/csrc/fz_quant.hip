@@ -120,12 +120,22 @@ __device__ __forceinline__ void load_map(uint32_t t, uint32_t& bi, uint32_t& s) 
 
 // ------------------------------------------- fused Lorenzo quantisation
 // One workgroup (256 threads) handles a tile of 4 consecutive blocks per
-// iteration (tiles assigned statically, grid-strided).  Outliers and
-// patches go to the tile's own staging slots with a per-tile count; the
-// container sections are compacted in order after a scan of those counts.
+// iteration (tiles assigned statically, grid-strided).
 //   phase A (load mapping): 8 values per thread -> q, patch mask -> LDS
-//   phase B (thread = block*64 + segment): Lorenzo residual from LDS, codes
-//     (block-major, u16), histogram, outlier/patch positions.
+//   phase B (wave = block, lane = segment): Lorenzo residual from LDS rows
+//     (neighbours outside the block read a zero row), codes (block-major,
+//     u16), histogram, outlier/patch bookkeeping (only in waves that have
+//     any).  Outliers and patches go to the tile's own staging slots with a
+//     per-tile count; the container sections are compacted in order after
+//     a scan of those counts.
+template <int ND>
+__device__ __forceinline__ void read_row(const int32_t* Q, uint32_t off, int32_t r[8]) {
+    const int4* p = reinterpret_cast<const int4*>(&Q[off]);
+    const int4 a = p[0], c = p[1];
+    r[0] = a.x; r[1] = a.y; r[2] = a.z; r[3] = a.w;
+    r[4] = c.x; r[5] = c.y; r[6] = c.z; r[7] = c.w;
+}
+
 template <int ND>
 __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom g, uint32_t mode, double eb,
                                                int vec, Misc* misc, uint32_t* __restrict__ hist_g,
@@ -133,13 +143,18 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
                                                uint32_t* __restrict__ tile_cnt, uint32_t* __restrict__ opos,
                                                int32_t* __restrict__ oval, uint32_t* __restrict__ ppos,
                                                uint32_t* __restrict__ pbits) {
-    __shared__ int32_t Q[kTileBlocks * kBlockElems];
+    // q per block, regions padded by 8 words so the load-mapped writes of
+    // four blocks do not fall into the same banks; one extra zero row
+    constexpr int kQStride = kBlockElems + 8;
+    constexpr uint32_t kZero = kTileBlocks * kQStride;
+    __shared__ int32_t Q[kTileBlocks * kQStride + 8];
     __shared__ uint8_t PM[kTileBlocks * kSegs];
     __shared__ uint32_t H[kBins];
     __shared__ uint32_t wsum[4];
 
     const uint32_t t = threadIdx.x;
-    const uint32_t lane = t & 63, wave = t >> 6;
+    const uint32_t lane = t & 63;
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 6));
     double eb_abs;
     if (!resolve_eb(mode, eb, misc->mm_lo, misc->mm_hi, &eb_abs)) {
         if (blockIdx.x == 0 && t == 0) atomicOr(&misc->flags, F_EB);
@@ -148,8 +163,8 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
     const double e2 = 2.0 * eb_abs;
     const double inv = 1.0 / e2;
     for (uint32_t i = t; i < (uint32_t)kBins; i += 256) H[i] = 0;
+    if (t < 8) Q[kZero + t] = 0;
 
-    // static tile assignment: no counter, no cross-tile dependency
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         // ---------------- phase A: load + prequantise
         {
@@ -162,14 +177,14 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
 #pragma unroll
             for (int i = 0; i < 8; i++) q[i] = 0;
             if (b < g.nblocks) {
-                BlockInfo info = block_info(g, b);
+                const BlockInfo info = block_info(g, b);
                 uint32_t nv;
-                uint64_t base = seg_index<ND>(g, info, s, nv);
+                const uint64_t base = seg_index<ND>(g, info, s, nv);
                 float v[8];
                 if (nv == 8 && vec) {
                     const f32x4* p = reinterpret_cast<const f32x4*>(x + base);
-                    f32x4 a = __builtin_nontemporal_load(p);
-                    f32x4 c = __builtin_nontemporal_load(p + 1);
+                    const f32x4 a = __builtin_nontemporal_load(p);
+                    const f32x4 c = __builtin_nontemporal_load(p + 1);
                     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
                     v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
                 } else {
@@ -178,97 +193,73 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
                 }
 #pragma unroll
                 for (int i = 0; i < 8; i++) {
+                    bool p;
+                    const int32_t qi = prequant1(v[i], e2, inv, eb_abs, p);
                     if (i < (int)nv) {
                         bad |= !__builtin_isfinite(v[i]);
-                        bool p;
-                        q[i] = prequant1(v[i], e2, inv, eb_abs, p);
+                        q[i] = qi;
                         pm |= (p ? 1u : 0u) << i;
                     }
                 }
             }
             if (bad) atomicOr(&misc->flags, F_NONFINITE);
-            int4* dst = reinterpret_cast<int4*>(&Q[(bi * kSegs + s) * 8]);
+            int4* dst = reinterpret_cast<int4*>(&Q[bi * kQStride + s * 8]);
             dst[0] = make_int4(q[0], q[1], q[2], q[3]);
             dst[1] = make_int4(q[4], q[5], q[6], q[7]);
             PM[bi * kSegs + s] = (uint8_t)pm;
         }
         __syncthreads();
 
-        // ---------------- phase B: Lorenzo residual, codes, histogram
-        const uint32_t bi = t >> 6, s = t & 63;
-        const uint32_t b = tile * kTileBlocks + bi;
-        const int32_t* Qb = &Q[bi * kBlockElems];
+        // ---------------- phase B: wave = block, lane = segment
+        const uint32_t s = lane;
+        const uint32_t b = tile * kTileBlocks + wave;  // wave-uniform
+        const bool blk = b < g.nblocks;
+        const uint32_t Qb = wave * kQStride;
+        uint32_t nv = 0;  // real values in this segment
         int32_t d[8];
         {
-            int32_t r0[8];
-            const int4* src = reinterpret_cast<const int4*>(&Qb[s * 8]);
-            int4 a = src[0], c = src[1];
-            r0[0] = a.x; r0[1] = a.y; r0[2] = a.z; r0[3] = a.w;
-            r0[4] = c.x; r0[5] = c.y; r0[6] = c.z; r0[7] = c.w;
+            const BlockInfo info = block_info(g, blk ? b : 0);
+            int32_t r0[8], A[8];
+            int32_t am1 = 0;  // A[-1]: the left neighbour term along x
+            read_row<ND>(Q, Qb + s * 8, r0);
             if (ND == 3) {
                 const uint32_t ly = s & 7, lz = s >> 3;
-                // dx of a row: q[i] - q[i-1], q[-1] = 0 (block face)
-                auto row = [&](uint32_t ss, int32_t* r) {
-                    const int4* p = reinterpret_cast<const int4*>(&Qb[ss * 8]);
-                    int4 u = p[0], w = p[1];
-                    r[0] = u.x; r[1] = u.y; r[2] = u.z; r[3] = u.w;
-                    r[4] = w.x; r[5] = w.y; r[6] = w.z; r[7] = w.w;
-                };
+                nv = (blk && ly < info.ey && lz < info.ez) ? info.ex : 0u;
                 int32_t ry[8], rz[8], ryz[8];
-                const int32_t my = ly > 0 ? 1 : 0, mz = lz > 0 ? 1 : 0;
-                row(ly > 0 ? s - 1 : s, ry);
-                row(lz > 0 ? s - 8 : s, rz);
-                row((ly > 0 && lz > 0) ? s - 9 : s, ryz);
+                read_row<ND>(Q, ly ? Qb + (s - 1) * 8 : kZero, ry);
+                read_row<ND>(Q, lz ? Qb + (s - 8) * 8 : kZero, rz);
+                read_row<ND>(Q, (ly && lz) ? Qb + (s - 9) * 8 : kZero, ryz);
 #pragma unroll
-                for (int i = 7; i >= 0; i--) {
-                    int32_t dx0 = r0[i] - (i ? r0[i - 1] : 0);
-                    int32_t dxy = ry[i] - (i ? ry[i - 1] : 0);
-                    int32_t dxz = rz[i] - (i ? rz[i - 1] : 0);
-                    int32_t dxyz = ryz[i] - (i ? ryz[i - 1] : 0);
-                    d[i] = dx0 - my * dxy - mz * dxz + (my & mz) * dxyz;
-                }
+                for (int i = 0; i < 8; i++) A[i] = (r0[i] - ry[i]) - (rz[i] - ryz[i]);
             } else if (ND == 2) {
                 const uint32_t sx = s & 3, ly = s >> 2;
-                const int32_t left = sx ? Qb[(s - 1) * 8 + 7] : 0;
-                int32_t up[8], upleft = 0;
-                const int32_t my = ly > 0 ? 1 : 0;
-                {
-                    const uint32_t su = ly > 0 ? s - 4 : s;
-                    const int4* p = reinterpret_cast<const int4*>(&Qb[su * 8]);
-                    int4 u = p[0], w = p[1];
-                    up[0] = u.x; up[1] = u.y; up[2] = u.z; up[3] = u.w;
-                    up[4] = w.x; up[5] = w.y; up[6] = w.z; up[7] = w.w;
-                    upleft = (sx && ly > 0) ? Qb[(su - 1) * 8 + 7] : 0;
-                }
+                nv = (blk && ly < info.ey && 8 * sx < info.ex) ? min(8u, info.ex - 8 * sx) : 0u;
+                int32_t up[8];
+                read_row<ND>(Q, ly ? Qb + (s - 4) * 8 : kZero, up);
+                const int32_t left = Q[sx ? Qb + (s - 1) * 8 + 7 : kZero];
+                const int32_t upleft = Q[(sx && ly) ? Qb + (s - 5) * 8 + 7 : kZero];
+                am1 = left - upleft;
 #pragma unroll
-                for (int i = 7; i >= 0; i--) {
-                    int32_t dx0 = r0[i] - (i ? r0[i - 1] : left);
-                    int32_t dxu = up[i] - (i ? up[i - 1] : upleft);
-                    d[i] = dx0 - my * dxu;
-                }
+                for (int i = 0; i < 8; i++) A[i] = r0[i] - up[i];
             } else {
-                const int32_t left = s ? Qb[(s - 1) * 8 + 7] : 0;
+                nv = (blk && 8 * s < info.ex) ? min(8u, info.ex - 8 * s) : 0u;
+                am1 = Q[s ? Qb + (s - 1) * 8 + 7 : kZero];
 #pragma unroll
-                for (int i = 7; i >= 0; i--) d[i] = r0[i] - (i ? r0[i - 1] : left);
+                for (int i = 0; i < 8; i++) A[i] = r0[i];
             }
+#pragma unroll
+            for (int i = 7; i >= 0; i--) d[i] = A[i] - (i ? A[i - 1] : am1);
         }
-
-        uint32_t nv = 0;
-        uint64_t base = 0;
-        if (b < g.nblocks) {
-            BlockInfo info = block_info(g, b);
-            base = seg_index<ND>(g, info, s, nv);
-        }
+        // codes: residuals in (-512, 512) -> residual + 512, otherwise 0
         uint32_t code[8];
-        uint32_t omask = 0;
+        uint32_t cmin = 0xFFFFFFFFu;
 #pragma unroll
         for (int i = 0; i < 8; i++) {
-            int32_t v = d[i];
-            uint32_t c = (v > -kRadius && v < kRadius) ? (uint32_t)(v + kRadius) : 0u;
-            code[i] = c;
-            if (i < (int)nv && c == 0) omask |= 1u << i;
+            const uint32_t u = (uint32_t)(d[i] + (kRadius - 1));
+            code[i] = u < (uint32_t)(2 * kRadius - 1) ? u + 1 : 0u;
+            if (i < (int)nv) cmin = min(cmin, code[i]);
         }
-        if (b < g.nblocks) {
+        if (blk) {
             uint4 pk;
             pk.x = code[0] | (code[1] << 16);
             pk.y = code[2] | (code[3] << 16);
@@ -276,50 +267,59 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
             pk.w = code[6] | (code[7] << 16);
             *reinterpret_cast<uint4*>(&codes[(uint64_t)b * kBlockElems + s * 8]) = pk;
         }
-        // histogram: peel the two codes most lanes share with one LDS add
-        // each, then add the remaining lanes individually.
+        // histogram: lane 0's code is added once for every lane sharing it,
+        // the other lanes add their own
+        if (blk) {
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
-            const bool valid = i < (int)nv;
-            uint32_t c = valid ? code[i] : 0xFFFFFFFFu;
-            uint64_t vm = __ballot(valid);
-            bool done = !valid;
-#pragma unroll
-            for (int r = 0; r < 2; r++) {
-                uint64_t rem = __ballot(!done);
-                if (rem == 0) break;
-                const int lead = __ffsll((long long)rem) - 1;
-                const uint32_t cand = __shfl(c, lead, 64);
-                const uint64_t m = __ballot(!done && c == cand);
-                if ((int)lane == lead) atomicAdd(&H[cand], (uint32_t)__popcll(m));
-                if (c == cand) done = true;
+            for (int i = 0; i < 8; i++) {
+                const uint32_t c = (i < (int)nv) ? code[i] : 0xFFFFu;
+                const uint32_t cand = (uint32_t)__builtin_amdgcn_readfirstlane((int)c);
+                const uint64_t m = __ballot(c == cand);
+                if (lane == 0 && cand != 0xFFFFu) atomicAdd(&H[cand], (uint32_t)__popcll(m));
+                if (c != cand && c != 0xFFFFu) atomicAdd(&H[c], 1u);
             }
-            if (!done) atomicAdd(&H[c], 1u);
-            (void)vm;
         }
 
-        // ---------------- outliers and patches in block order
-        const uint32_t pmask = PM[t] & ((1u << nv) - 1u);
-        const uint32_t no = __popc(omask), np = __popc(pmask);
-        const uint32_t packed = no | (np << 16);
-        const uint32_t incl = wave_incl_scan(packed);
-        if (lane == 63) wsum[wave] = incl;
+        // ---------------- outliers and patches (block order inside the tile)
+        const uint32_t pm_lane = PM[t] & ((1u << nv) - 1u);
+        const bool has = (cmin == 0) || pm_lane;
+        uint32_t packed = 0, incl = 0;
+        if (__ballot(has)) {
+            uint32_t omask = 0;
+#pragma unroll
+            for (int i = 0; i < 8; i++)
+                if (i < (int)nv && code[i] == 0) omask |= 1u << i;
+            packed = __popc(omask) | (__popc(pm_lane) << 16);
+            incl = wave_incl_scan(packed);
+            if (lane == 63) wsum[wave] = incl;
+            if (omask | pm_lane) {
+                // positions go to this tile's staging slots after the barrier
+                code[0] = omask;  // keep the masks; codes are no longer needed
+            }
+        } else if (lane == 0) {
+            wsum[wave] = 0;
+        }
         __syncthreads();
         uint32_t wpre = 0, tot = 0;
+#pragma unroll
         for (uint32_t w = 0; w < 4; w++) {
-            uint32_t v = wsum[w];
-            if (w < wave) wpre += v;
+            const uint32_t v = wsum[w];
+            wpre += (w < wave) ? v : 0u;
             tot += v;
         }
-        const uint32_t excl_local = wpre + incl - packed;
         if (t == 0) tile_cnt[tile] = tot;
-        // each tile owns staging slots [tile * 2048, tile * 2048 + 2048) for
-        // outliers and for patches, in position order inside the tile
-        if (omask | pmask) {
+        if (packed) {
+            const uint32_t omask = code[0];
+            const uint32_t excl_local = wpre + incl - packed;
             const uint64_t slot = (uint64_t)tile * kTileBlocks * kBlockElems;
             uint64_t oi = slot + (excl_local & 0xFFFFu);
             uint64_t pi = slot + (excl_local >> 16);
             const uint32_t pos0 = b * kBlockElems + s * 8;
+            uint64_t base = 0;
+            if (pm_lane) {
+                uint32_t nvv;
+                base = seg_index<ND>(g, block_info(g, b), s, nvv);
+            }
 #pragma unroll
             for (int i = 0; i < 8; i++) {
                 if (omask & (1u << i)) {
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
                     oval[oi] = d[i];
                     oi++;
                 }
-                if (pmask & (1u << i)) {
+                if (pm_lane & (1u << i)) {
                     ppos[pi] = pos0 + i;
                     pbits[pi] = __float_as_uint(x[base + i]);
                     pi++;

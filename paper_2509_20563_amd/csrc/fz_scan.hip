@@ -14,17 +14,6 @@ namespace fz {
 
 constexpr int kScanTile = 1024;  // entries per workgroup (256 threads x 4)
 
-template <class Op>
-__device__ inline uint64_t wave_incl_scan64(uint64_t v, Op op) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint64_t o = __shfl_up(v, d, 64);
-        if (lane >= d) v = op(o, v);
-    }
-    return v;
-}
-
 template <int KIND>
 __global__ __launch_bounds__(256) void k_scan(const void* __restrict__ in, uint32_t n, uint64_t* __restrict__ out,
                                               uint64_t* desc, uint32_t* ctr, uint32_t ntiles, Misc* misc,
