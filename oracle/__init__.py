@@ -58,6 +58,13 @@ def lib():
         L.orc_decompress.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_uint64]
         L.orc_stage_codes.argtypes = [vp, ctypes.c_int, u64p, ctypes.c_int, ctypes.c_double, vp, vp,
                                       vp, ctypes.POINTER(ctypes.c_double)]
+        L.orc_residual.argtypes = [vp, ctypes.c_int, u64p, ctypes.c_int, vp, vp]
+        L.orc_residual.restype = None
+        L.orc_residual_inverse.argtypes = [vp, ctypes.c_int, u64p, ctypes.c_int, vp, vp]
+        L.orc_residual_inverse.restype = None
+        L.orc_compress_ex.argtypes = [vp, ctypes.c_int, u64p, ctypes.c_int, ctypes.c_double, ctypes.c_int, vp, vp,
+                                      ctypes.c_uint64, u64p]
+        L.orc_trial.argtypes = [vp, ctypes.c_int, u64p, ctypes.c_int, ctypes.c_double, vp, vp]
         L.orc_encode_symbols.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_int, vp]
         L.orc_encode_symbols.restype = ctypes.c_uint64
         _lib = L
@@ -138,17 +145,68 @@ def compress_bound(shape):
     return int(lib().orc_compress_bound(nd, d))
 
 
-def compress(x, eb, mode=1):
-    """Compress a float32 field; returns the container as bytes.  mode 0 = absolute, 1 = relative."""
+P0, P1, P2, P_SELECTED, P_TRIAL = 0, 1, 2, 3, 4
+
+
+def nblocks_of(shape):
+    nd = len(shape)
+    bs = {1: (512,), 2: (16, 32), 3: (8, 8, 8)}[nd]
+    n = 1
+    for s, b in zip(shape, bs):
+        n *= -(-s // b)
+    return n
+
+
+def compress(x, eb, mode=1, pred=P0, choice=None):
+    """Compress a float32 field; returns the container as bytes.  mode 0 =
+    absolute, 1 = relative; pred 0/1/2 = that predictor everywhere, 3 = the
+    per-block choice given, 4 = per-block choice by exhaustive trial."""
     x = np.ascontiguousarray(x, dtype=np.float32)
     nd, d = dims_of(x.shape)
     cap = compress_bound(x.shape)
     out = np.zeros(max(cap, HDR), np.uint8)
     n = ctypes.c_uint64(0)
-    rc = lib().orc_compress(_ptr(x), nd, d, int(mode), float(eb), _ptr(out), out.size, ctypes.byref(n))
+    ch = None
+    if pred == P_SELECTED:
+        ch = np.ascontiguousarray(choice, dtype=np.uint8)
+        assert ch.size == nblocks_of(x.shape)
+    rc = lib().orc_compress_ex(_ptr(x), nd, d, int(mode), float(eb), int(pred),
+                               _ptr(ch) if ch is not None else None, _ptr(out), out.size, ctypes.byref(n))
     if rc:
         raise OracleError(rc)
     return out[: n.value].tobytes()
+
+
+def residual(q, p):
+    """Residual field with predictor p in every block; (delta, coef[nblocks, 4])."""
+    q = np.ascontiguousarray(q, dtype=np.int32)
+    nd, d = dims_of(q.shape)
+    delta = np.empty_like(q)
+    coef = np.zeros((nblocks_of(q.shape), 4), np.int32)
+    lib().orc_residual(_ptr(q), nd, d, int(p), _ptr(delta), _ptr(coef))
+    return delta, coef
+
+
+def residual_inverse(delta, p, coef=None):
+    delta = np.ascontiguousarray(delta, dtype=np.int32)
+    nd, d = dims_of(delta.shape)
+    q = np.empty_like(delta)
+    cf = None if coef is None else np.ascontiguousarray(coef, dtype=np.int32)
+    lib().orc_residual_inverse(_ptr(delta), nd, d, int(p), _ptr(cf) if cf is not None else None, _ptr(q))
+    return q
+
+
+def trial(x, eb, mode=1):
+    """Per-block exhaustive-trial choice and the three costs (bits) per block."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    nd, d = dims_of(x.shape)
+    nb = nblocks_of(x.shape)
+    choice = np.zeros(nb, np.uint8)
+    costs = np.zeros((nb, 3), np.uint32)
+    rc = lib().orc_trial(_ptr(x), nd, d, int(mode), float(eb), _ptr(choice), _ptr(costs))
+    if rc:
+        raise OracleError(rc)
+    return choice, costs
 
 
 def header(buf):
@@ -163,7 +221,7 @@ def header(buf):
                 eb=np.frombuffer(bytes(b[48:56]), np.float64)[0],
                 eb_abs=np.frombuffer(bytes(b[56:64]), np.float64)[0],
                 total=u(64, 8), nblocks=u(72, 4), n_outliers=u(76, 4), n_patches=u(80, 4),
-                stream_words=u(84, 4), stream_bits=u(88, 8))
+                stream_words=u(84, 4), stream_bits=u(88, 8), n_reg=u(96, 4))
 
 
 def shape_of(h):

@@ -404,20 +404,190 @@ static uint64_t a16(uint64_t v) { return (v + 15) & ~15ull; }
 static uint64_t f64bits(double d) { uint64_t u; memcpy(&u, &d, 8); return u; }
 static double bitsf64(uint64_t u) { double d; memcpy(&d, &u, 8); return d; }
 
+/* ------------------------------------------------ per-block predictors
+ * A block is predicted by one of:
+ *   P0: first-order Lorenzo, the residual above (backward difference along
+ *       every axis);
+ *   P1: second-order Lorenzo, the backward difference applied twice along
+ *       every axis: weights (1, -2, 1) per axis, 27 neighbours in 3D;
+ *   P2: a linear fit over the block in integer fixed point.
+ * Neighbours outside the block are zero for P0 and P1.  (The paper names
+ * Lorenzo extrapolation and linear regression as the SZ-family predictors,
+ * Sec. 2.1, and leaves predictor choice to future "auto-selection",
+ * Sec. 5.)                                                               */
+#define ORC_P0 0
+#define ORC_P1 1
+#define ORC_P2 2
+
+static void block_coords(const geom_t *g, uint64_t b, uint64_t bc[3], int ext[3]) {
+    bc[0] = b % g->nb[0];
+    bc[1] = (b / g->nb[0]) % g->nb[1];
+    bc[2] = b / (g->nb[0] * g->nb[1]);
+    for (int a = 0; a < 3; a++) {
+        uint64_t o = bc[a] * (uint64_t)g->bs[a];
+        uint64_t e = g->n[a] - o;
+        ext[a] = (int)(e < (uint64_t)g->bs[a] ? e : (uint64_t)g->bs[a]);
+    }
+}
+
+static int32_t lorenzo2_at(const geom_t *g, const int32_t *q, uint64_t x, uint64_t y, uint64_t z) {
+    static const int w[3] = {1, -2, 1};
+    int nz = g->ndim >= 3 ? 3 : 1, ny = g->ndim >= 2 ? 3 : 1;
+    int64_t d = 0;
+    for (int dz = 0; dz < nz; dz++)
+        for (int dy = 0; dy < ny; dy++)
+            for (int dx = 0; dx < 3; dx++) {
+                int64_t c = (int64_t)w[dx] * (g->ndim >= 2 ? w[dy] : 1) * (g->ndim >= 3 ? w[dz] : 1);
+                d += c * qnb(g, q, x, y, z, dx, dy, dz);
+            }
+    return (int32_t)d;
+}
+
+/* round half away from zero; b > 0 */
+static int64_t rdiv(int64_t a, int64_t b) {
+    if (a >= 0) return (a + b / 2) / b;
+    return -((-a + b / 2) / b);
+}
+
+static int32_t clamp32(int64_t v) {
+    if (v > INT32_MAX) return INT32_MAX;
+    if (v < INT32_MIN) return INT32_MIN;
+    return (int32_t)v;
+}
+
+/* Least-squares plane over the block's real values with centred
+ * coordinates u = 2 lx - (ex - 1) (likewise v, w): the normal equations
+ * decouple, A = S0 / n, Bx = Su / sum(u^2), ...  Stored with 8 fractional
+ * bits, rounded half away from zero, clamped to int32.                   */
+static void regression_coeffs(const geom_t *g, const int32_t *q, uint64_t b, int32_t coef[4]) {
+    uint64_t bc[3];
+    int ext[3];
+    block_coords(g, b, bc, ext);
+    int64_t s0 = 0, su[3] = {0, 0, 0};
+    for (int lz = 0; lz < ext[2]; lz++)
+        for (int ly = 0; ly < ext[1]; ly++)
+            for (int lx = 0; lx < ext[0]; lx++) {
+                int64_t v = q[rm(g, bc[0] * g->bs[0] + lx, bc[1] * g->bs[1] + ly, bc[2] * g->bs[2] + lz)];
+                int l[3] = {lx, ly, lz};
+                s0 += v;
+                for (int a = 0; a < 3; a++) su[a] += (int64_t)(2 * l[a] - (ext[a] - 1)) * v;
+            }
+    int64_t n = (int64_t)ext[0] * ext[1] * ext[2];
+    coef[0] = clamp32(rdiv(s0 * 256, n));
+    for (int a = 0; a < 3; a++) {
+        /* sum of u^2 over the block: ext_a (ext_a^2 - 1) / 3 per line, times the other extents */
+        int64_t d = (int64_t)ext[a] * ((int64_t)ext[a] * ext[a] - 1) / 3 * (n / ext[a]);
+        coef[1 + a] = d > 0 ? clamp32(rdiv(su[a] * 256, d)) : 0;
+    }
+}
+
+static int32_t regression_pred(const int32_t coef[4], const int ext[3], int lx, int ly, int lz) {
+    int64_t s = (int64_t)coef[0] + (int64_t)coef[1] * (2 * lx - (ext[0] - 1)) +
+                (int64_t)coef[2] * (2 * ly - (ext[1] - 1)) + (int64_t)coef[3] * (2 * lz - (ext[2] - 1));
+    /* floor((s + 128) / 256) */
+    int64_t t = s + 128;
+    return (int32_t)(t >= 0 ? t / 256 : -((-t + 255) / 256));
+}
+
+/* residual of the value at (x, y, z) under predictor p (coef: P2 only) */
+static int32_t residual_at(const geom_t *g, const int32_t *q, uint64_t x, uint64_t y, uint64_t z, int p,
+                           const int32_t coef[4]) {
+    if (p == ORC_P1) return lorenzo2_at(g, q, x, y, z);
+    if (p == ORC_P2) {
+        int ext[3];
+        uint64_t bc[3];
+        uint64_t b = (x / g->bs[0]) + g->nb[0] * ((y / g->bs[1]) + g->nb[1] * (z / g->bs[2]));
+        block_coords(g, b, bc, ext);
+        return q[rm(g, x, y, z)] - regression_pred(coef, ext, (int)(x % g->bs[0]), (int)(y % g->bs[1]),
+                                                   (int)(z % g->bs[2]));
+    }
+    /* P0: backward difference along every axis */
+    if (g->ndim == 1) return qnb(g, q, x, y, z, 0, 0, 0) - qnb(g, q, x, y, z, 1, 0, 0);
+    if (g->ndim == 2)
+        return qnb(g, q, x, y, z, 0, 0, 0) - qnb(g, q, x, y, z, 1, 0, 0) - qnb(g, q, x, y, z, 0, 1, 0) +
+               qnb(g, q, x, y, z, 1, 1, 0);
+    return qnb(g, q, x, y, z, 0, 0, 0) - qnb(g, q, x, y, z, 1, 0, 0) - qnb(g, q, x, y, z, 0, 1, 0) -
+           qnb(g, q, x, y, z, 0, 0, 1) + qnb(g, q, x, y, z, 1, 1, 0) + qnb(g, q, x, y, z, 1, 0, 1) +
+           qnb(g, q, x, y, z, 0, 1, 1) - qnb(g, q, x, y, z, 1, 1, 1);
+}
+
+/* Inverse for one block, in place on a row-major field: residuals in,
+ * grid values out.  P0: inclusive prefix sums along x, then y, then z;
+ * P1: the same done twice per axis; P2: add the plane back.              */
+static void block_inverse(const geom_t *g, int32_t *a, uint64_t b, int p, const int32_t coef[4]) {
+    uint64_t bc[3];
+    int ext[3];
+    block_coords(g, b, bc, ext);
+    uint64_t o[3] = {bc[0] * g->bs[0], bc[1] * g->bs[1], bc[2] * g->bs[2]};
+    if (p == ORC_P2) {
+        for (int lz = 0; lz < ext[2]; lz++)
+            for (int ly = 0; ly < ext[1]; ly++)
+                for (int lx = 0; lx < ext[0]; lx++)
+                    a[rm(g, o[0] + lx, o[1] + ly, o[2] + lz)] += regression_pred(coef, ext, lx, ly, lz);
+        return;
+    }
+    int passes = (p == ORC_P1) ? 2 : 1;
+    for (int axis = 0; axis < 3; axis++)
+        for (int rep = 0; rep < passes; rep++)
+            for (int lz = 0; lz < ext[2]; lz++)
+                for (int ly = 0; ly < ext[1]; ly++)
+                    for (int lx = 0; lx < ext[0]; lx++) {
+                        int l[3] = {lx, ly, lz};
+                        if (l[axis] == 0) continue;
+                        int m[3] = {lx, ly, lz};
+                        m[axis] -= 1;
+                        a[rm(g, o[0] + lx, o[1] + ly, o[2] + lz)] += a[rm(g, o[0] + m[0], o[1] + m[1], o[2] + m[2])];
+                    }
+}
+
+/* Residual fields for tests: every block with predictor p (P2 coefficients
+ * written to coef[4 * nblocks] when coef is not NULL). */
+void orc_residual(const int32_t *q, int ndim, const uint64_t dims[3], int p, int32_t *delta, int32_t *coef) {
+    geom_t g;
+    if (make_geom(ndim, dims, &g) != ORC_OK) return;
+    int32_t *cf = (int32_t *)calloc(4 * g.nblocks, sizeof(int32_t));
+    if (p == ORC_P2)
+        for (uint64_t b = 0; b < g.nblocks; b++) regression_coeffs(&g, q, b, cf + 4 * b);
+    for (uint64_t z = 0; z < g.n[2]; z++)
+        for (uint64_t y = 0; y < g.n[1]; y++)
+            for (uint64_t x = 0; x < g.n[0]; x++) {
+                uint64_t b = (x / g.bs[0]) + g.nb[0] * ((y / g.bs[1]) + g.nb[1] * (z / g.bs[2]));
+                delta[rm(&g, x, y, z)] = residual_at(&g, q, x, y, z, p, cf + 4 * b);
+            }
+    if (coef) memcpy(coef, cf, sizeof(int32_t) * 4 * g.nblocks);
+    free(cf);
+}
+
+void orc_residual_inverse(const int32_t *delta, int ndim, const uint64_t dims[3], int p, const int32_t *coef,
+                          int32_t *q) {
+    geom_t g;
+    if (make_geom(ndim, dims, &g) != ORC_OK) return;
+    memcpy(q, delta, sizeof(int32_t) * g.N);
+    for (uint64_t b = 0; b < g.nblocks; b++) block_inverse(&g, q, b, p, coef ? coef + 4 * b : NULL);
+}
+
 /* ---------------------------------------------------------- container layout
- * header (128 B) | code lengths, 4 bits each, 512 B | chunk bits u16[nblocks]
- * | stream u32[words] | outlier pos u32[] | outlier residual i32[] |
- * patch pos u32[] | patch float bits u32[]; every section starts on a
- * 16-byte boundary and padding is zero.  Verbatim container: header with
- * flag bit 0 set, then the raw floats in row-major order.                */
+ * header (128 B) | code lengths, 4 bits each, 512 B | [predictor map,
+ * 2 bits per block, when the predictor is chosen per block] | [regression
+ * coefficients, i32[4] per P2 block in block order] | chunk bits
+ * u16[nblocks] | stream u32[words] | outlier pos u32[] | outlier residual
+ * i32[] | patch pos u32[] | patch float bits u32[]; every section starts
+ * on a 16-byte boundary and padding is zero.  Verbatim container: header
+ * with flag bit 0 set, then the raw floats in row-major order.
+ * Header predictor field: 0, 1, 2 = P0, P1, P2 for every block; 3 = chosen
+ * per block by the learned selector; 4 = chosen per block by exhaustive
+ * trial (3 and 4 carry the map).                                          */
 typedef struct {
-    uint64_t lens, chunks, stream, opos, oval, ppos, pbits, total;
+    uint64_t lens, map, coef, chunks, stream, opos, oval, ppos, pbits, total;
 } layout_t;
 
-static layout_t make_layout(uint64_t nblocks, uint64_t words, uint64_t nout, uint64_t npat) {
+static layout_t make_layout(uint64_t nblocks, int has_map, uint64_t nreg, uint64_t words, uint64_t nout,
+                            uint64_t npat) {
     layout_t L;
     L.lens = ORC_HDR;
-    L.chunks = L.lens + ORC_NBINS / 2;
+    L.map = L.lens + ORC_NBINS / 2;
+    L.coef = a16(L.map + (has_map ? (nblocks + 3) / 4 : 0));
+    L.chunks = a16(L.coef + 16 * nreg);
     L.stream = a16(L.chunks + 2 * nblocks);
     L.opos = a16(L.stream + 4 * words);
     L.oval = a16(L.opos + 4 * nout);
@@ -435,13 +605,13 @@ uint64_t orc_compress_bound(int ndim, const uint64_t dims[3]) {
 
 static void write_header(uint8_t *h, const geom_t *g, int flags, int mode, double eb, double eb_abs,
                          uint64_t total, uint64_t nblocks, uint64_t nout, uint64_t npat,
-                         uint64_t words, uint64_t bits) {
+                         uint64_t words, uint64_t bits, int pred, uint64_t nreg) {
     memset(h, 0, ORC_HDR);
     st32(h + 0, ORC_MAGIC);
     st16(h + 4, ORC_VERSION);
     st16(h + 6, (uint16_t)flags);
     st32(h + 8, (uint32_t)g->ndim);
-    st32(h + 12, 0); /* predictor: first-order Lorenzo */
+    st32(h + 12, (uint32_t)pred);
     st64(h + 16, g->n[0]);
     st64(h + 24, g->n[1]);
     st64(h + 32, g->n[2]);
@@ -455,38 +625,111 @@ static void write_header(uint8_t *h, const geom_t *g, int flags, int mode, doubl
     st32(h + 80, (uint32_t)npat);
     st32(h + 84, (uint32_t)words);
     st64(h + 88, bits);
+    st32(h + 96, (uint32_t)nreg);
 }
 
-/* ---------------------------------------------------------------- compress */
-int orc_compress(const float *x, int ndim, const uint64_t dims[3], int mode, double eb,
-                 uint8_t *out, uint64_t cap, uint64_t *out_bytes) {
+/* Codes of every value in block-major order for the given per-block
+ * predictors; residuals kept for the outlier list; P2 coefficients per
+ * block (zero for other blocks). */
+static void block_codes(const geom_t *g, const int32_t *q, const elem_ref *refs, const uint8_t *bp,
+                        const int32_t *cf, uint16_t *codes, int32_t *res) {
+    for (uint64_t k = 0; k < g->N; k++) {
+        uint64_t idx = refs[k].idx;
+        uint64_t x = idx % g->n[0], y = (idx / g->n[0]) % g->n[1], z = idx / (g->n[0] * g->n[1]);
+        uint64_t b = refs[k].pos / ORC_BLOCK_ELEMS;
+        int32_t d = residual_at(g, q, x, y, z, bp[b], cf + 4 * b);
+        res[k] = d;
+        codes[k] = postquant(d);
+    }
+}
+
+/* ---------------------------------------- exhaustive per-block trial
+ * Reference code: the Huffman code of the histogram of P0 codes over the
+ * whole field (a code that does not occur there costs 13 bits).  For every
+ * block and predictor: cost = sum of reference code lengths + 64 bits per
+ * outlier (its position and residual) + 128 bits of coefficients for P2.
+ * The block takes the cheapest predictor, ties to the lower index.        */
+static void trial_choose(const geom_t *g, const int32_t *q, const elem_ref *refs, const uint32_t *bcount,
+                         uint8_t *choice, uint32_t *costs) {
+    uint16_t *codes = (uint16_t *)malloc(sizeof(uint16_t) * g->N);
+    int32_t *res = (int32_t *)malloc(sizeof(int32_t) * g->N);
+    int32_t *cf = (int32_t *)calloc(4 * g->nblocks, sizeof(int32_t));
+    uint8_t *bp = (uint8_t *)calloc(g->nblocks, 1);
+    uint32_t hist[ORC_NBINS];
+    uint8_t len[ORC_NBINS];
+    block_codes(g, q, refs, bp, cf, codes, res);
+    orc_histogram(codes, g->N, hist);
+    orc_codebook(hist, len);
+    for (uint64_t b = 0; b < g->nblocks; b++) regression_coeffs(g, q, b, cf + 4 * b);
+    uint64_t *cost = (uint64_t *)calloc(3 * g->nblocks, sizeof(uint64_t));
+    for (int p = 0; p < 3; p++) {
+        memset(bp, p, g->nblocks);
+        block_codes(g, q, refs, bp, cf, codes, res);
+        uint64_t k = 0;
+        for (uint64_t b = 0; b < g->nblocks; b++) {
+            uint64_t c = (p == ORC_P2) ? 128 : 0;
+            for (uint32_t e = 0; e < bcount[b]; e++, k++) {
+                c += len[codes[k]] ? len[codes[k]] : (ORC_LMAX + 1);
+                if (codes[k] == 0) c += 64;
+            }
+            cost[3 * b + p] = c;
+        }
+    }
+    for (uint64_t b = 0; b < g->nblocks; b++) {
+        int best = 0;
+        for (int p = 1; p < 3; p++)
+            if (cost[3 * b + p] < cost[3 * b + best]) best = p;
+        choice[b] = (uint8_t)best;
+        if (costs)
+            for (int p = 0; p < 3; p++) costs[3 * b + p] = (uint32_t)cost[3 * b + p];
+    }
+    free(codes); free(res); free(cf); free(bp); free(cost);
+}
+
+/* ---------------------------------------------------------------- compress
+ * pred: 0, 1, 2 = that predictor for every block; 3 = per-block choice
+ * given in choice_in (by the learned selector); 4 = per-block choice by
+ * exhaustive trial.                                                       */
+int orc_compress_ex(const float *x, int ndim, const uint64_t dims[3], int mode, double eb, int pred,
+                    const uint8_t *choice_in, uint8_t *out, uint64_t cap, uint64_t *out_bytes) {
     geom_t g;
     int rc = make_geom(ndim, dims, &g);
     if (rc) return rc;
+    if (pred < 0 || pred > 4 || (pred == 3 && !choice_in)) return ORC_ERR_ARG;
     if (cap < ORC_HDR + 4 * g.N) return ORC_ERR_CAPACITY;
     double eb_abs;
     rc = orc_eb_abs(x, g.N, mode, eb, &eb_abs);
     if (rc) return rc;
-    double e2 = 2.0 * eb_abs;
 
     int32_t *q = (int32_t *)malloc(sizeof(int32_t) * g.N);
     uint8_t *patch = (uint8_t *)malloc(g.N);
-    int32_t *delta = (int32_t *)malloc(sizeof(int32_t) * g.N);
+    int32_t *res = (int32_t *)malloc(sizeof(int32_t) * g.N);
     elem_ref *refs = (elem_ref *)malloc(sizeof(elem_ref) * g.N);
     uint32_t *bcount = (uint32_t *)malloc(sizeof(uint32_t) * g.nblocks);
     uint16_t *codes = (uint16_t *)malloc(sizeof(uint16_t) * g.N);
-    if (!q || !patch || !delta || !refs || !bcount || !codes) {
-        free(q); free(patch); free(delta); free(refs); free(bcount); free(codes);
+    uint8_t *bp = (uint8_t *)malloc(g.nblocks);
+    int32_t *cf = (int32_t *)calloc(4 * g.nblocks, sizeof(int32_t));
+    if (!q || !patch || !res || !refs || !bcount || !codes || !bp || !cf) {
+        free(q); free(patch); free(res); free(refs); free(bcount); free(codes); free(bp); free(cf);
         return ORC_ERR_NOMEM;
     }
     orc_prequant(x, g.N, eb_abs, q, patch);
-    orc_lorenzo1(q, ndim, dims, delta);
     block_major_order(&g, refs, bcount);
+    if (pred <= 2) memset(bp, pred, g.nblocks);
+    else if (pred == 3) memcpy(bp, choice_in, g.nblocks);
+    else trial_choose(&g, q, refs, bcount, bp, NULL);
+    uint64_t nreg = 0;
+    for (uint64_t b = 0; b < g.nblocks; b++) {
+        if (bp[b] > ORC_P2) bp[b] = ORC_P0;
+        if (bp[b] == ORC_P2) {
+            regression_coeffs(&g, q, b, cf + 4 * b);
+            nreg++;
+        }
+    }
+    block_codes(&g, q, refs, bp, cf, codes, res);
 
-    /* codes, outliers and patches in block-major order */
     uint64_t nout = 0, npat = 0;
     for (uint64_t k = 0; k < g.N; k++) {
-        codes[k] = postquant(delta[refs[k].idx]);
         if (codes[k] == 0) nout++;
         if (patch[refs[k].idx]) npat++;
     }
@@ -500,18 +743,26 @@ int orc_compress(const float *x, int ndim, const uint64_t dims[3], int mode, dou
     uint64_t bits = 0;
     for (int s = 0; s < ORC_NBINS; s++) bits += (uint64_t)hist[s] * len[s];
     uint64_t words = (bits + 31) / 32;
-    layout_t L = make_layout(g.nblocks, words, nout, npat);
+    int has_map = pred >= 3;
+    layout_t L = make_layout(g.nblocks, has_map, nreg, words, nout, npat);
 
     if (L.total >= ORC_HDR + 4 * g.N) {
-        /* verbatim */
-        write_header(out, &g, 1, mode, eb, eb_abs, ORC_HDR + 4 * g.N, 0, 0, 0, 0, 0);
+        write_header(out, &g, 1, mode, eb, eb_abs, ORC_HDR + 4 * g.N, 0, 0, 0, 0, 0, pred, 0);
         for (uint64_t i = 0; i < g.N; i++) memcpy(out + ORC_HDR + 4 * i, &x[i], 4);
         *out_bytes = ORC_HDR + 4 * g.N;
     } else {
         memset(out, 0, L.total);
-        write_header(out, &g, 0, mode, eb, eb_abs, L.total, g.nblocks, nout, npat, words, bits);
+        write_header(out, &g, 0, mode, eb, eb_abs, L.total, g.nblocks, nout, npat, words, bits, pred, nreg);
         for (int s = 0; s < ORC_NBINS; s++)
             out[L.lens + s / 2] |= (uint8_t)((len[s] & 15) << (4 * (s % 2)));
+        if (has_map)
+            for (uint64_t b = 0; b < g.nblocks; b++) out[L.map + b / 4] |= (uint8_t)(bp[b] << (2 * (b % 4)));
+        uint64_t ir = 0;
+        for (uint64_t b = 0; b < g.nblocks; b++)
+            if (bp[b] == ORC_P2) {
+                for (int k = 0; k < 4; k++) st32(out + L.coef + 16 * ir + 4 * k, (uint32_t)cf[4 * b + k]);
+                ir++;
+            }
         uint32_t *stream = (uint32_t *)calloc(words + 1, sizeof(uint32_t));
         bitw bw = {stream, 0};
         uint64_t k = 0, io = 0, ip = 0;
@@ -521,7 +772,7 @@ int orc_compress(const float *x, int ndim, const uint64_t dims[3], int mode, dou
                 put_bits(&bw, cw[codes[k]], len[codes[k]]);
                 if (codes[k] == 0) {
                     st32(out + L.opos + 4 * io, refs[k].pos);
-                    st32(out + L.oval + 4 * io, (uint32_t)delta[refs[k].idx]);
+                    st32(out + L.oval + 4 * io, (uint32_t)res[k]);
                     io++;
                 }
                 if (patch[refs[k].idx]) {
@@ -538,8 +789,33 @@ int orc_compress(const float *x, int ndim, const uint64_t dims[3], int mode, dou
         free(stream);
         *out_bytes = L.total;
     }
-    (void)e2;
-    free(q); free(patch); free(delta); free(refs); free(bcount); free(codes);
+    free(q); free(patch); free(res); free(refs); free(bcount); free(codes); free(bp); free(cf);
+    return ORC_OK;
+}
+
+int orc_compress(const float *x, int ndim, const uint64_t dims[3], int mode, double eb,
+                 uint8_t *out, uint64_t cap, uint64_t *out_bytes) {
+    return orc_compress_ex(x, ndim, dims, mode, eb, 0, NULL, out, cap, out_bytes);
+}
+
+/* Per-block trial choices (and the three costs per block) for tests and
+ * for training labels. */
+int orc_trial(const float *x, int ndim, const uint64_t dims[3], int mode, double eb, uint8_t *choice,
+              uint32_t *costs) {
+    geom_t g;
+    int rc = make_geom(ndim, dims, &g);
+    if (rc) return rc;
+    double eb_abs;
+    rc = orc_eb_abs(x, g.N, mode, eb, &eb_abs);
+    if (rc) return rc;
+    int32_t *q = (int32_t *)malloc(sizeof(int32_t) * g.N);
+    uint8_t *patch = (uint8_t *)malloc(g.N);
+    elem_ref *refs = (elem_ref *)malloc(sizeof(elem_ref) * g.N);
+    uint32_t *bcount = (uint32_t *)malloc(sizeof(uint32_t) * g.nblocks);
+    orc_prequant(x, g.N, eb_abs, q, patch);
+    block_major_order(&g, refs, bcount);
+    trial_choose(&g, q, refs, bcount, choice, costs);
+    free(q); free(patch); free(refs); free(bcount);
     return ORC_OK;
 }
 
@@ -570,7 +846,8 @@ int orc_decompress(const uint8_t *in, uint64_t n, float *out, uint64_t out_elems
     if (rc) return rc;
     geom_t g;
     if (make_geom(ndim, dims, &g) != ORC_OK) return ORC_ERR_CORRUPT;
-    if (ld32(in + 12) != 0 || ld32(in + 44) != ORC_RADIUS) return ORC_ERR_UNSUPPORTED;
+    int pred = (int)ld32(in + 12);
+    if (pred > 4 || ld32(in + 44) != ORC_RADIUS) return ORC_ERR_UNSUPPORTED;
     if (out_elems < g.N) return ORC_ERR_CAPACITY;
     uint64_t total = ld64(in + 64);
     if (total > n) return ORC_ERR_CORRUPT;
@@ -581,10 +858,27 @@ int orc_decompress(const uint8_t *in, uint64_t n, float *out, uint64_t out_elems
     }
     if (!(eb_abs >= 1e-300 && eb_abs <= 1e300)) return ORC_ERR_CORRUPT;
     uint64_t nblocks = ld32(in + 72), nout = ld32(in + 76), npat = ld32(in + 80);
-    uint64_t words = ld32(in + 84), bits = ld64(in + 88);
+    uint64_t words = ld32(in + 84), bits = ld64(in + 88), nreg = ld32(in + 96);
     if (nblocks != g.nblocks || words != (bits + 31) / 32) return ORC_ERR_CORRUPT;
-    layout_t L = make_layout(nblocks, words, nout, npat);
+    int has_map = pred >= 3;
+    if (nreg > g.nblocks) return ORC_ERR_CORRUPT;
+    layout_t L = make_layout(nblocks, has_map, nreg, words, nout, npat);
     if (L.total != total) return ORC_ERR_CORRUPT;
+
+    /* per-block predictors and coefficients */
+    uint8_t *bp = (uint8_t *)malloc(g.nblocks);
+    int32_t *cf = (int32_t *)calloc(4 * g.nblocks, sizeof(int32_t));
+    uint64_t ir = 0;
+    for (uint64_t b = 0; b < g.nblocks; b++) {
+        bp[b] = has_map ? (uint8_t)((in[L.map + b / 4] >> (2 * (b % 4))) & 3) : (uint8_t)pred;
+        if (bp[b] > ORC_P2) { free(bp); free(cf); return ORC_ERR_CORRUPT; }
+        if (bp[b] == ORC_P2) {
+            if (ir >= nreg) { free(bp); free(cf); return ORC_ERR_CORRUPT; }
+            for (int k = 0; k < 4; k++) cf[4 * b + k] = (int32_t)ld32(in + L.coef + 16 * ir + 4 * k);
+            ir++;
+        }
+    }
+    if (ir != nreg) { free(bp); free(cf); return ORC_ERR_CORRUPT; }
 
     uint8_t len[ORC_NBINS];
     for (int s = 0; s < ORC_NBINS; s++) len[s] = (in[L.lens + s / 2] >> (4 * (s % 2))) & 15;
@@ -592,12 +886,12 @@ int orc_decompress(const uint8_t *in, uint64_t n, float *out, uint64_t out_elems
     uint64_t kraft = 0;
     int used = 0;
     for (int s = 0; s < ORC_NBINS; s++) {
-        if (len[s] > ORC_LMAX) return ORC_ERR_CORRUPT;
+        if (len[s] > ORC_LMAX) { free(bp); free(cf); return ORC_ERR_CORRUPT; }
         if (len[s]) { kraft += 1ull << (ORC_LMAX - len[s]); used++; }
     }
-    if (used < 2 || kraft != (1ull << ORC_LMAX)) return ORC_ERR_CORRUPT;
+    if (used < 2 || kraft != (1ull << ORC_LMAX)) { free(bp); free(cf); return ORC_ERR_CORRUPT; }
     uint32_t first[ORC_LMAX + 2], count[ORC_LMAX + 2];
-    int symidx[ORC_LMAX + 2][ORC_NBINS];
+    static int symidx[ORC_LMAX + 2][ORC_NBINS];
     uint32_t cw[ORC_NBINS];
     orc_canonical(len, ORC_NBINS, cw);
     for (int L2 = 0; L2 <= ORC_LMAX + 1; L2++) { first[L2] = 0xFFFFFFFFu; count[L2] = 0; }
@@ -608,16 +902,14 @@ int orc_decompress(const uint8_t *in, uint64_t n, float *out, uint64_t out_elems
                 symidx[L2][count[L2]++] = s;
             }
 
-    geom_t *gp = &g;
     elem_ref *refs = (elem_ref *)malloc(sizeof(elem_ref) * g.N);
     uint32_t *bcount = (uint32_t *)malloc(sizeof(uint32_t) * g.nblocks);
-    int32_t *delta = (int32_t *)malloc(sizeof(int32_t) * g.N);
-    int32_t *q = (int32_t *)malloc(sizeof(int32_t) * g.N);
-    if (!refs || !bcount || !delta || !q) {
-        free(refs); free(bcount); free(delta); free(q);
+    int32_t *a = (int32_t *)malloc(sizeof(int32_t) * g.N);
+    if (!refs || !bcount || !a) {
+        free(refs); free(bcount); free(a); free(bp); free(cf);
         return ORC_ERR_NOMEM;
     }
-    block_major_order(gp, refs, bcount);
+    block_major_order(&g, refs, bcount);
     const uint8_t *stream = in + L.stream;
     uint64_t bitpos = 0, k = 0, io = 0;
     rc = ORC_OK;
@@ -648,15 +940,15 @@ int orc_decompress(const uint8_t *in, uint64_t n, float *out, uint64_t out_elems
             } else {
                 d = sym - ORC_RADIUS;
             }
-            delta[refs[k].idx] = d;
+            a[refs[k].idx] = d;
         }
         if (rc == ORC_OK && bitpos - start != ld16(in + L.chunks + 2 * b)) rc = ORC_ERR_CORRUPT;
     }
     if (rc == ORC_OK && (io != nout || bitpos != bits)) rc = ORC_ERR_CORRUPT;
     if (rc == ORC_OK) {
-        orc_lorenzo1_inverse(delta, ndim, dims, q);
+        for (uint64_t b = 0; b < g.nblocks; b++) block_inverse(&g, a, b, bp[b], cf + 4 * b);
         double e2 = 2.0 * eb_abs;
-        for (uint64_t i = 0; i < g.N; i++) out[i] = dequant(q[i], e2);
+        for (uint64_t i = 0; i < g.N; i++) out[i] = dequant(a[i], e2);
         /* lossless patches: positions ascending, each names a real element */
         uint64_t kk = 0;
         uint32_t last = 0;
@@ -670,7 +962,7 @@ int orc_decompress(const uint8_t *in, uint64_t n, float *out, uint64_t out_elems
             memcpy(&out[refs[kk].idx], &fb, 4);
         }
     }
-    free(refs); free(bcount); free(delta); free(q);
+    free(refs); free(bcount); free(a); free(bp); free(cf);
     return rc;
 }
 

@@ -68,12 +68,16 @@ __global__ __launch_bounds__(1024) void k_lut(const uint8_t* __restrict__ lensp,
 }
 
 // ----------------------------------------------------------------- decode
-constexpr int kWin = 20;  // words staged per lane and round (5 x 16 B)
+constexpr int kWin = 20;      // words staged per lane and round (5 x 16 B)
+constexpr int kDecLanes = 256;
 
+// A lane's window of the stream in LDS, column-major across the workgroup:
+// word k of lane l is at k * 256 + l, so lanes reading their own word k land
+// in distinct banks whatever k each lane is at.
 struct LaneStream {
     const uint32_t* stream;
     uint64_t nwords;
-    uint32_t* win;   // this lane's window in LDS
+    uint32_t* win;   // &WIN[lane]
     uint64_t aw;     // first staged word (multiple of 4)
     uint32_t rel;    // bit position relative to aw * 32
 
@@ -81,28 +85,58 @@ struct LaneStream {
     __device__ __forceinline__ void stage(uint64_t bitpos) {
         aw = (bitpos >> 5) & ~3ull;
         rel = (uint32_t)(bitpos - aw * 32);
-        uint4* w4 = reinterpret_cast<uint4*>(win);
+        uint32_t w[kWin];
         if (aw + kWin <= nwords) {
             const uint4* s4 = reinterpret_cast<const uint4*>(stream + aw);
 #pragma unroll
-            for (int k = 0; k < kWin / 4; k++) w4[k] = s4[k];
+            for (int k = 0; k < kWin / 4; k++) {
+                const uint4 v = s4[k];
+                w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
+            }
         } else {
 #pragma unroll
-            for (int k = 0; k < kWin; k++) win[k] = (aw + k < nwords) ? stream[aw + k] : 0u;
+            for (int k = 0; k < kWin; k++) w[k] = (aw + k < nwords) ? stream[aw + k] : 0u;
         }
+#pragma unroll
+        for (int k = 0; k < kWin; k++) win[k * kDecLanes] = w[k];
+    }
+    // the 64 stream bits starting at the current position, MSB first
+    __device__ __forceinline__ uint64_t peek64() const {
+        const uint32_t wi = rel >> 5, sh = rel & 31;
+        const uint32_t w0 = win[wi * kDecLanes], w1 = win[(wi + 1) * kDecLanes];
+        return (((uint64_t)w0 << 32) | w1) << sh;
     }
     __device__ __forceinline__ uint64_t bitpos() const { return aw * 32 + rel; }
 };
 
+// The block's outliers are read four at a time from the position-sorted
+// list into registers (positions p, residuals v); past the end of the list
+// positions read as 0xFFFFFFFF.
+__device__ __forceinline__ void load_outliers(const uint32_t* __restrict__ opos, const int32_t* __restrict__ oval,
+                                              uint64_t n, uint32_t i, uint4& p, int4& v) {
+    if ((uint64_t)i + 4 <= n) {
+        p = *reinterpret_cast<const uint4*>(opos + i);
+        v = *reinterpret_cast<const int4*>(oval + i);
+    } else {
+        p.x = (uint64_t)i < n ? opos[i] : 0xFFFFFFFFu;
+        p.y = (uint64_t)i + 1 < n ? opos[i + 1] : 0xFFFFFFFFu;
+        p.z = (uint64_t)i + 2 < n ? opos[i + 2] : 0xFFFFFFFFu;
+        p.w = 0xFFFFFFFFu;
+        v.x = (uint64_t)i < n ? oval[i] : 0;
+        v.y = (uint64_t)i + 1 < n ? oval[i + 1] : 0;
+        v.z = (uint64_t)i + 2 < n ? oval[i + 2] : 0;
+        v.w = 0;
+    }
+}
+
 template <int ND>
-__global__ __launch_bounds__(256) void k_decode(Geom g, const uint32_t* __restrict__ stream, uint64_t nwords,
-                                                const uint64_t* __restrict__ off, const uint16_t* __restrict__ chunks,
-                                                const uint16_t* __restrict__ lut_g, const uint32_t* __restrict__ opos,
-                                                const int32_t* __restrict__ oval,
-                                                const uint32_t* __restrict__ ofirst, uint64_t n_out, double e2,
-                                                float* __restrict__ out, int vec, Misc* misc) {
+__global__ __launch_bounds__(256) void k_decode(
+    Geom g, const uint32_t* __restrict__ stream, uint64_t nwords, const uint64_t* __restrict__ off,
+    const uint16_t* __restrict__ chunks, const uint16_t* __restrict__ lut_g, const uint32_t* __restrict__ opos,
+    const int32_t* __restrict__ oval, const uint32_t* __restrict__ ofirst, uint64_t n_out, double e2,
+    float* __restrict__ out, int vec, Misc* misc) {
     __shared__ uint16_t LUT[kLut];
-    __shared__ uint32_t WIN[256 * kWin];
+    __shared__ uint32_t WIN[kDecLanes * kWin];
     const uint32_t t = threadIdx.x;
     for (uint32_t i = t; i < (uint32_t)kLut; i += 256) LUT[i] = lut_g[i];
     __syncthreads();
@@ -114,44 +148,39 @@ __global__ __launch_bounds__(256) void k_decode(Geom g, const uint32_t* __restri
     LaneStream ls;
     ls.stream = stream;
     ls.nwords = nwords;
-    ls.win = &WIN[t * kWin];
+    ls.win = &WIN[t];
     uint32_t code0 = 0;
     bool bad = false;
     const uint32_t pos_b = b * kBlockElems;
     // the block's outliers are consecutive in the position-sorted list,
     // starting at ofirst[b] (meaningful only for blocks that have outliers:
-    // every use is bounds- and position-checked); the next one is kept
-    // prefetched in registers
-    uint32_t optr = 0, npos = 0xFFFFFFFFu;
-    int32_t nval = 0;
+    // every use is bounds- and position-checked)
+    uint32_t onext = 0, ok = 0;
+    uint4 op4 = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+    int4 ov4 = make_int4(0, 0, 0, 0);
     if (n_out) {
-        optr = ofirst[b];
-        if (optr < n_out) {
-            npos = opos[optr];
-            nval = oval[optr];
-        }
+        onext = ofirst[b];
+        load_outliers(opos, oval, n_out, onext, op4, ov4);
     }
 
     // decode one codeword; code 0 takes the next outlier residual
     auto next = [&](uint32_t pos) -> int32_t {
-        const uint32_t wi = ls.rel >> 5, sh = ls.rel & 31;
-        const uint32_t w0 = ls.win[wi], w1 = ls.win[wi + 1];
-        const uint64_t v = (((uint64_t)w0 << 32) | w1) << sh;
+        const uint64_t v = ls.peek64();
         const uint32_t e = LUT[(uint32_t)(v >> (64 - kLmax))];
         ls.rel += e >> 10;
         const uint32_t sym = e & 1023u;
         if (sym) return (int32_t)sym - kRadius;
         code0++;
-        int32_t d = nval;
-        if (npos != pos) {
+        const uint32_t pk = ok == 0 ? op4.x : ok == 1 ? op4.y : ok == 2 ? op4.z : op4.w;
+        int32_t d = ok == 0 ? ov4.x : ok == 1 ? ov4.y : ok == 2 ? ov4.z : ov4.w;
+        if (pk != pos) {
             bad = true;
             d = 0;
         }
-        optr++;
-        npos = 0xFFFFFFFFu;
-        if (optr < n_out) {
-            npos = opos[optr];
-            nval = oval[optr];
+        if (++ok == 4) {
+            onext += 4;
+            ok = 0;
+            load_outliers(opos, oval, n_out, onext, op4, ov4);
         }
         return d;
     };

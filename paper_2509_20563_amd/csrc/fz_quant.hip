@@ -98,14 +98,12 @@ __global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, uin
 // q = rint(x / 2eb) via x * (1 / 2eb) in double, round half to even.
 // Patch when |t| >= 2^24 (q = 0) or when float(q * 2eb) misses the bound.
 __device__ __forceinline__ int32_t prequant1(float xv, double e2, double inv, double eb_abs, bool& patch) {
-    double t = (double)xv * inv;
-    if (fabs(t) >= 16777216.0) {
-        patch = true;
-        return 0;
-    }
-    double r = __builtin_rint(t);
-    float xh = (float)(r * e2);
-    patch = fabs((double)xv - (double)xh) > eb_abs;
+    const double xd = (double)xv;
+    const double t = xd * inv;
+    const bool big = fabs(t) >= 16777216.0;
+    const double r = __builtin_rint(big ? 0.0 : t);  // branch-free: q = 0 when out of range
+    const float xh = (float)(r * e2);
+    patch = big || (fabs(xd - (double)xh) > eb_abs);
     return (int32_t)r;
 }
 
@@ -165,48 +163,68 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
     for (uint32_t i = t; i < (uint32_t)kBins; i += 256) H[i] = 0;
     if (t < 8) Q[kZero + t] = 0;
 
+    // load-phase lane constants (the same for every tile): block in tile,
+    // segment, segment coordinates and the segment's row-major offset from
+    // its block origin (indices fit in 32 bits: N <= 2^32)
+    uint32_t la_bi, la_s, la_lx0, la_ly, la_lz;
+    load_map<ND>(t, la_bi, la_s);
+    seg_coords<ND>(la_s, la_lx0, la_ly, la_lz);
+    const uint32_t la_rowoff = la_lx0 + g.n[0] * (la_ly + g.n[1] * la_lz);
+    // phase-B lane (segment = lane) offset, for reloading patched values
+    uint32_t lb_lx0, lb_ly, lb_lz;
+    seg_coords<ND>(lane, lb_lx0, lb_ly, lb_lz);
+    const uint32_t lb_rowoff = lb_lx0 + g.n[0] * (lb_ly + g.n[1] * lb_lz);
+
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         // ---------------- phase A: load + prequantise
         {
-            uint32_t bi, s;
-            load_map<ND>(t, bi, s);
-            const uint32_t b = tile * kTileBlocks + bi;
+            // the tile's four block origins and extents are wave-uniform
+            // (scalar); each lane picks its block's entry
+            uint32_t org[kTileBlocks], ex[kTileBlocks], ey[kTileBlocks], ez[kTileBlocks];
+#pragma unroll
+            for (int k = 0; k < kTileBlocks; k++) {
+                const uint32_t bk = tile * kTileBlocks + k;
+                const bool ok = bk < g.nblocks;
+                const BlockInfo ik = block_info(g, ok ? bk : 0);
+                org[k] = ik.bx * g.bs[0] + g.n[0] * (ik.by * g.bs[1] + g.n[1] * (ik.bz * g.bs[2]));
+                ex[k] = ok ? ik.ex : 0u;
+                ey[k] = ik.ey;
+                ez[k] = ik.ez;
+            }
+            auto pick = [&](const uint32_t* a) {
+                return la_bi == 0 ? a[0] : la_bi == 1 ? a[1] : la_bi == 2 ? a[2] : a[3];
+            };
+            const uint32_t bex = pick(ex), bey = pick(ey), bez = pick(ez);
+            const uint32_t nv = (la_ly < bey && la_lz < bez && la_lx0 < bex) ? min(8u, bex - la_lx0) : 0u;
+            const uint32_t base = pick(org) + la_rowoff;
             int32_t q[8];
             uint32_t pm = 0;
             bool bad = false;
+            float v[8];
+            if (nv == 8 && vec) {
+                const f32x4* p = reinterpret_cast<const f32x4*>(x + base);
+                const f32x4 a = __builtin_nontemporal_load(p);
+                const f32x4 c = __builtin_nontemporal_load(p + 1);
+                v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+                v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
+            } else {
 #pragma unroll
-            for (int i = 0; i < 8; i++) q[i] = 0;
-            if (b < g.nblocks) {
-                const BlockInfo info = block_info(g, b);
-                uint32_t nv;
-                const uint64_t base = seg_index<ND>(g, info, s, nv);
-                float v[8];
-                if (nv == 8 && vec) {
-                    const f32x4* p = reinterpret_cast<const f32x4*>(x + base);
-                    const f32x4 a = __builtin_nontemporal_load(p);
-                    const f32x4 c = __builtin_nontemporal_load(p + 1);
-                    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-                    v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
-                } else {
+                for (int i = 0; i < 8; i++) v[i] = (i < (int)nv) ? x[base + i] : 0.0f;
+            }
 #pragma unroll
-                    for (int i = 0; i < 8; i++) v[i] = (i < (int)nv) ? x[base + i] : 0.0f;
-                }
-#pragma unroll
-                for (int i = 0; i < 8; i++) {
-                    bool p;
-                    const int32_t qi = prequant1(v[i], e2, inv, eb_abs, p);
-                    if (i < (int)nv) {
-                        bad |= !__builtin_isfinite(v[i]);
-                        q[i] = qi;
-                        pm |= (p ? 1u : 0u) << i;
-                    }
-                }
+            for (int i = 0; i < 8; i++) {
+                bool p;
+                const int32_t qi = prequant1(v[i], e2, inv, eb_abs, p);
+                const bool valid = i < (int)nv;
+                bad |= valid && !__builtin_isfinite(v[i]);
+                q[i] = valid ? qi : 0;
+                pm |= (valid && p ? 1u : 0u) << i;
             }
             if (bad) atomicOr(&misc->flags, F_NONFINITE);
-            int4* dst = reinterpret_cast<int4*>(&Q[bi * kQStride + s * 8]);
+            int4* dst = reinterpret_cast<int4*>(&Q[la_bi * kQStride + la_s * 8]);
             dst[0] = make_int4(q[0], q[1], q[2], q[3]);
             dst[1] = make_int4(q[4], q[5], q[6], q[7]);
-            PM[bi * kSegs + s] = (uint8_t)pm;
+            PM[la_bi * kSegs + la_s] = (uint8_t)pm;
         }
         __syncthreads();
 
@@ -315,11 +333,9 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
             uint64_t oi = slot + (excl_local & 0xFFFFu);
             uint64_t pi = slot + (excl_local >> 16);
             const uint32_t pos0 = b * kBlockElems + s * 8;
-            uint64_t base = 0;
-            if (pm_lane) {
-                uint32_t nvv;
-                base = seg_index<ND>(g, block_info(g, b), s, nvv);
-            }
+            const BlockInfo ib = block_info(g, b);
+            const uint32_t base = ib.bx * g.bs[0] + g.n[0] * (ib.by * g.bs[1] + g.n[1] * (ib.bz * g.bs[2])) +
+                                  lb_rowoff;
 #pragma unroll
             for (int i = 0; i < 8; i++) {
                 if (omask & (1u << i)) {
