@@ -25,7 +25,9 @@
  *    are serialised by that thread; two contexts may run concurrently.
  *
  * Container ("FZM1", little-endian): a 128-byte header, the code lengths
- * (4 bits per symbol, 1024 symbols), one u16 bit count per block, the
+ * (4 bits per symbol, 1024 symbols), [the predictor map, 2 bits per block,
+ * for the AUTO predictor modes], [the regression coefficients, int32[4] per
+ * regression block in block order], one u16 bit count per block, the
  * bit-contiguous Huffman stream (u32 words, most significant bit first), the
  * outliers (u32 position[], i32 residual[]) and the lossless patches
  * (u32 position[], u32 float bits[]), each section 16-byte aligned.  When
@@ -48,8 +50,30 @@ typedef struct fz_ctx fz_ctx;
  * FZ_EB_REL: |x - x_hat| <= eb * (max(x) - min(x)); a constant field uses eb. */
 enum { FZ_EB_ABS = 0, FZ_EB_REL = 1 };
 
-/* Predictors.  FZ_PRED_LORENZO1: block-local first-order Lorenzo (Sec. 3.1). */
-enum { FZ_PRED_LORENZO1 = 0 };
+/* Predictors, per block of 8x8x8 (2D: 32x16, 1D: 512) values.  The paper's
+ * pipeline uses the first-order Lorenzo predictor (Sec. 3.1); it names
+ * higher-order Lorenzo and linear regression as the SZ-family predictors
+ * (Sec. 2.1) and leaves choosing among them per block to future work
+ * (Sec. 5).  Neighbours outside the block count as zero.
+ *  FZ_PRED_LORENZO1   first-order Lorenzo for every block
+ *  FZ_PRED_LORENZO2   second-order Lorenzo (weights 1, -2, 1 per axis)
+ *  FZ_PRED_REGRESSION linear fit per block, 4 int32 coefficients with 8
+ *                     fractional bits stored per block
+ *  FZ_PRED_AUTO_MLP   per block, chosen by the learned selector (not yet
+ *                     available: FZ_ERR_UNSUPPORTED)
+ *  FZ_PRED_AUTO_TRIAL per block, the predictor whose codes cost the fewest
+ *                     bits under the Huffman code of the first-order
+ *                     histogram (+64 bits per outlier, +128 for the
+ *                     coefficients); ties go to the lower number.
+ * The AUTO modes store a 2-bit map of the choice in the container, so
+ * decompression never repeats the choice. */
+enum {
+    FZ_PRED_LORENZO1 = 0,
+    FZ_PRED_LORENZO2 = 1,
+    FZ_PRED_REGRESSION = 2,
+    FZ_PRED_AUTO_MLP = 3,
+    FZ_PRED_AUTO_TRIAL = 4
+};
 
 enum {
     FZ_OK = 0,
@@ -69,7 +93,7 @@ typedef struct {
     uint64_t dims[3];  /* extents, dims[0] fastest; unused axes = 1  */
     uint32_t eb_mode;  /* FZ_EB_ABS or FZ_EB_REL                      */
     double eb;         /* > 0 and finite                              */
-    uint32_t pred;     /* FZ_PRED_LORENZO1                            */
+    uint32_t pred;     /* FZ_PRED_*                                   */
     uint32_t radius;   /* quantisation radius; 512 (1024 code bins)   */
 } fz_params;
 
@@ -83,8 +107,8 @@ void fz_ctx_destroy(fz_ctx *ctx);
 
 /* Bytes the output buffer of fz_compress must hold for these parameters:
  * the larger of the verbatim container (128 + 4 N) and the packed sections
- * written before the verbatim decision (about 656 + N / 256 + 1.5 N), rounded
- * up to 16.  0 if the parameters are invalid. */
+ * written before the verbatim decision (about 656 + 3 N / 64 + 1.5 N),
+ * rounded up to 16.  0 if the parameters are invalid. */
 uint64_t fz_compress_bound(const fz_params *p);
 
 /* Compress the field d_in (N floats, device) into d_out (device, out_cap

@@ -64,6 +64,18 @@ struct fz_ctx {
     uint64_t* off = nullptr;
     uint32_t* ofirst = nullptr;
     uint64_t off_cap = 0, ofirst_cap = 0;
+    // per-block predictors: choice, index among regression blocks,
+    // coefficients, trial costs, the reference code of the trial, the
+    // map-scan descriptors and the residual field of the mapped decoder
+    uint8_t* bpred = nullptr;
+    uint64_t* reg_idx = nullptr;
+    int32_t* coef = nullptr;
+    uint32_t* costs = nullptr;
+    uint32_t* cw_ref = nullptr;  // kBins entries
+    uint8_t* lens_ref = nullptr;  // kBins / 2 bytes
+    uint64_t* desc_pmap = nullptr;
+    int32_t* res = nullptr;
+    uint64_t bpred_cap = 0, reg_idx_cap = 0, coef_cap = 0, costs_cap = 0, desc_pmap_cap = 0, res_cap = 0;
     // timing
     bool timing = false;
     hipEvent_t ev[kMaxStages + 1] = {};
@@ -122,7 +134,8 @@ int check_params(const fz_params* p, Geom* g) {
     if (rc) return rc;
     if (p->eb_mode != FZ_EB_ABS && p->eb_mode != FZ_EB_REL) return FZ_ERR_ARG;
     if (!(p->eb > 0.0) || !__builtin_isfinite(p->eb)) return FZ_ERR_EB;
-    if (p->pred != FZ_PRED_LORENZO1) return FZ_ERR_UNSUPPORTED;
+    if (p->pred > FZ_PRED_AUTO_TRIAL) return FZ_ERR_ARG;
+    if (p->pred == FZ_PRED_AUTO_MLP) return FZ_ERR_UNSUPPORTED;
     if (p->radius != 0 && p->radius != (uint32_t)kRadius) return FZ_ERR_UNSUPPORTED;
     return FZ_OK;
 }
@@ -132,7 +145,7 @@ int check_params(const fz_params* p, Geom* g) {
 // chunk table and a stream of at most 12 bits per value).
 uint64_t bound_of(const Geom& g) {
     const uint64_t verbatim = (uint64_t)kHdr + 4 * g.N;
-    const uint64_t packed = make_layout(g.nblocks, (12 * g.N + 31) / 32, 0, 0).total;
+    const uint64_t packed = make_layout(g.nblocks, true, g.nblocks, (12 * g.N + 31) / 32, 0, 0).total;
     return align16(verbatim > packed ? verbatim : packed);
 }
 
@@ -159,6 +172,19 @@ int ensure(fz_ctx* c, const Geom& g) {
     if (e == hipSuccess) e = grow(c->desc_chunks, c->desc_chunks_cap, sd_blocks);
     if (e == hipSuccess) e = grow(c->off, c->off_cap, nb);
     if (e == hipSuccess) e = grow(c->ofirst, c->ofirst_cap, nb);
+    return e == hipSuccess ? FZ_OK : FZ_ERR_NOMEM;
+}
+
+// Scratch of the per-block predictor modes (not needed by the default path).
+int ensure_pred(fz_ctx* c, const Geom& g, bool decode) {
+    const uint64_t nb = g.nblocks;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = grow(c->bpred, c->bpred_cap, nb);
+    if (e == hipSuccess) e = grow(c->reg_idx, c->reg_idx_cap, nb);
+    if (e == hipSuccess) e = grow(c->coef, c->coef_cap, 4 * nb);
+    if (e == hipSuccess) e = grow(c->costs, c->costs_cap, 3 * nb);
+    if (e == hipSuccess) e = grow(c->desc_pmap, c->desc_pmap_cap, scan_tiles((uint32_t)nb));
+    if (e == hipSuccess && decode) e = grow(c->res, c->res_cap, nb * kBlockElems);
     return e == hipSuccess ? FZ_OK : FZ_ERR_NOMEM;
 }
 
@@ -222,7 +248,7 @@ struct Parsed {
     Geom g;
     int verbatim;
     double eb_abs;
-    uint64_t total, nblocks, nout, npat, words, bits;
+    uint64_t total, nblocks, nout, npat, words, bits, nreg;
 };
 
 int parse_header(const uint8_t* h, uint64_t n, Parsed* r) {
@@ -247,8 +273,9 @@ int parse_header(const uint8_t* h, uint64_t n, Parsed* r) {
     r->npat = ld32(h, 80);
     r->words = ld32(h, 84);
     r->bits = ld64(h, 88);
+    r->nreg = ld32(h, 96);
     if (make_geom(r->p.ndim, r->p.dims, &r->g) != FZ_OK) return FZ_ERR_CORRUPT;
-    if (r->p.pred != FZ_PRED_LORENZO1 || r->p.radius != (uint32_t)kRadius) return FZ_ERR_CORRUPT;
+    if (r->p.pred > FZ_PRED_AUTO_TRIAL || r->p.radius != (uint32_t)kRadius) return FZ_ERR_CORRUPT;
     if (r->p.eb_mode > 1) return FZ_ERR_CORRUPT;
     if (r->verbatim) {
         if (r->total != (uint64_t)kHdr + 4 * r->g.N) return FZ_ERR_CORRUPT;
@@ -257,7 +284,13 @@ int parse_header(const uint8_t* h, uint64_t n, Parsed* r) {
     if (!(r->eb_abs >= 1e-300 && r->eb_abs <= 1e300)) return FZ_ERR_CORRUPT;
     if (r->nblocks != r->g.nblocks || r->words != (r->bits + 31) / 32) return FZ_ERR_CORRUPT;
     if (r->nout > r->g.N || r->npat > r->g.N) return FZ_ERR_CORRUPT;
-    const Layout L = make_layout(r->nblocks, r->words, r->nout, r->npat);
+    // regression coefficients: every block (P2), none (P0, P1), or the
+    // blocks the map selects (counted again on the device)
+    const uint32_t pred = r->p.pred;
+    if ((pred == FZ_PRED_REGRESSION && r->nreg != r->nblocks) || (pred < FZ_PRED_REGRESSION && r->nreg) ||
+        r->nreg > r->nblocks)
+        return FZ_ERR_CORRUPT;
+    const Layout L = make_layout(r->nblocks, pred_has_map(pred), r->nreg, r->words, r->nout, r->npat);
     if (L.total != r->total) return FZ_ERR_CORRUPT;
     return FZ_OK;
 }
@@ -281,6 +314,8 @@ int fz_ctx_create(fz_ctx** out, int device, uint64_t max_elems) {
     bool ok = hipMalloc((void**)&c->misc, sizeof(Misc)) == hipSuccess &&
               hipMalloc((void**)&c->hist, sizeof(uint32_t) * kBins) == hipSuccess &&
               hipMalloc((void**)&c->cw, sizeof(uint32_t) * kBins) == hipSuccess &&
+              hipMalloc((void**)&c->cw_ref, sizeof(uint32_t) * kBins) == hipSuccess &&
+              hipMalloc((void**)&c->lens_ref, kBins / 2) == hipSuccess &&
               hipMalloc((void**)&c->lut, sizeof(uint16_t) * kLut) == hipSuccess &&
               hipHostMalloc((void**)&c->h_misc, sizeof(Misc), hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc((void**)&c->h_hdr, kHdr, hipHostMallocDefault) == hipSuccess;
@@ -322,6 +357,14 @@ void fz_ctx_destroy(fz_ctx* c) {
     hipFree(c->desc_chunks);
     hipFree(c->off);
     hipFree(c->ofirst);
+    hipFree(c->bpred);
+    hipFree(c->reg_idx);
+    hipFree(c->coef);
+    hipFree(c->costs);
+    hipFree(c->cw_ref);
+    hipFree(c->lens_ref);
+    hipFree(c->desc_pmap);
+    hipFree(c->res);
     if (c->h_misc) hipHostFree(c->h_misc);
     if (c->h_hdr) hipHostFree(c->h_hdr);
     for (int i = 0; i <= kMaxStages; i++)
@@ -347,6 +390,12 @@ int fz_compress(fz_ctx* c, const fz_params* p, const float* d_in, void* d_out, u
     DeviceGuard dg(c->device);
     rc = ensure(c, g);
     if (rc) return rc;
+    const uint32_t pred = p->pred;
+    const bool has_map = pred_has_map(pred);
+    if (pred != FZ_PRED_LORENZO1) {
+        rc = ensure_pred(c, g, false);
+        if (rc) return rc;
+    }
     hipStream_t st = (hipStream_t)stream;
     uint8_t* out = (uint8_t*)d_out;
     const uint32_t ntiles = (g.nblocks + kTileBlocks - 1) / kTileBlocks;
@@ -355,8 +404,14 @@ int fz_compress(fz_ctx* c, const fz_params* p, const float* d_in, void* d_out, u
     const int grid = (int)(ntiles < (uint32_t)c->n_cu * 8 ? ntiles : (uint32_t)c->n_cu * 8);
     c->have_hist = false;
 
+    // section offsets known before the map: fixed predictors; a mapped
+    // container gets them from the map scan
+    const uint64_t nreg_fixed = pred == FZ_PRED_REGRESSION ? g.nblocks : 0;
+    const Layout L0 = make_layout(g.nblocks, has_map, nreg_fixed, 0, 0, 0);
+    const uint32_t sd_blocks = has_map ? scan_tiles(g.nblocks) : 0;
     t_begin(c, st);
-    launch_reset(st, c->misc, c->hist, c->desc_cnt, sd_tiles, c->desc_bits, sd_tiles);
+    launch_reset(st, c->misc, c->hist, c->desc_cnt, sd_tiles, c->desc_bits, sd_tiles, c->desc_pmap, sd_blocks,
+                 L0.chunks, L0.stream, nreg_fixed);
     t_mark(c, st, "reset");
     if (p->eb_mode == FZ_EB_REL) {
         uint64_t work = (g.N + 16 * 256 - 1) / (16 * 256);
@@ -365,21 +420,36 @@ int fz_compress(fz_ctx* c, const fz_params* p, const float* d_in, void* d_out, u
         launch_minmax(st, d_in, g.N, (((uintptr_t)d_in & 15) == 0), c->misc, (int)mgrid);
         t_mark(c, st, "minmax");
     }
+    if (pred == FZ_PRED_AUTO_TRIAL) {
+        // reference code: the Huffman code of the first-order Lorenzo
+        // histogram; then every block tries the three predictors
+        launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt,
+                     c->opos, c->oval, c->ppos, c->pbits, 0, nullptr, nullptr);
+        launch_codebook(st, c->hist, c->lens_ref, c->cw_ref, c->misc);
+        launch_trial(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, ntiles, c->cw_ref, c->bpred, c->costs);
+        launch_fill32(st, c->hist, kBins, 0);
+        t_mark(c, st, "trial");
+    }
+    if (has_map) {
+        launch_scan(st, SCAN_PMAP, c->bpred, g.nblocks, c->reg_idx, c->desc_pmap, &c->misc->mtile_ctr, c->misc, 0);
+        t_mark(c, st, "scan_map");
+    }
+    const int fixed = has_map ? -1 : (int)pred;
     launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt, c->opos,
-                 c->oval, c->ppos, c->pbits);
+                 c->oval, c->ppos, c->pbits, fixed, c->bpred, c->coef);
     t_mark(c, st, "quant");
     launch_scan(st, SCAN_COUNTS, c->tile_cnt, ntiles, c->tile_off, c->desc_cnt, &c->misc->qtile_ctr, c->misc, 0);
     t_mark(c, st, "scan_counts");
     launch_codebook(st, c->hist, out + kHdr, c->cw, c->misc);
     t_mark(c, st, "codebook");
-    launch_encode_len(st, grid, c->codes, g, c->cw, ntiles, out, c->tile_bits);
+    launch_encode_len(st, grid, c->codes, g, c->cw, ntiles, out, c->misc, c->tile_bits);
     t_mark(c, st, "encode_len");
     launch_scan(st, SCAN_BITS, c->tile_bits, ntiles, c->tile_start, c->desc_bits, &c->misc->etile_ctr, c->misc, 0);
     t_mark(c, st, "scan_bits");
     launch_encode_write(st, grid, c->codes, g, c->cw, c->misc, ntiles, out, c->tile_start, c->tfirst, c->tlast);
     t_mark(c, st, "encode_write");
-    launch_finalize(st, g, p->eb_mode, p->eb, c->misc, out, ntiles, c->tile_start, c->tfirst, c->tlast, c->tile_cnt,
-                    c->tile_off, c->opos, c->oval, c->ppos, c->pbits);
+    launch_finalize(st, g, p->eb_mode, p->eb, pred, c->misc, out, ntiles, c->tile_start, c->tfirst, c->tlast,
+                    c->tile_cnt, c->tile_off, c->opos, c->oval, c->ppos, c->pbits, c->bpred, c->reg_idx, c->coef);
     t_mark(c, st, "finalize");
     if (hipMemcpyAsync(c->h_misc, c->misc, sizeof(Misc), hipMemcpyDeviceToHost, st) != hipSuccess) return FZ_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
@@ -399,7 +469,7 @@ int fz_compress(fz_ctx* c, const fz_params* p, const float* d_in, void* d_out, u
         h[5] = (uint8_t)(kVersion >> 8);
         h[6] = 1;
         st32(h, 8, g.ndim);
-        st32(h, 12, 0);
+        st32(h, 12, pred);
         st64(h, 16, g.n[0]);
         st64(h, 24, g.n[1]);
         st64(h, 32, g.n[2]);
@@ -458,19 +528,38 @@ int fz_decompress(fz_ctx* c, const void* d_in, uint64_t in_bytes, const void* h_
     }
     rc = ensure(c, g);
     if (rc) return rc;
-    const Layout L = make_layout(r.nblocks, r.words, r.nout, r.npat);
+    const uint32_t pred = r.p.pred;
+    const bool has_map = pred_has_map(pred);
+    if (pred != FZ_PRED_LORENZO1) {
+        rc = ensure_pred(c, g, true);
+        if (rc) return rc;
+    }
+    const Layout L = make_layout(r.nblocks, has_map, r.nreg, r.words, r.nout, r.npat);
     const uint32_t stiles = scan_tiles(g.nblocks);
     const int vec = (((uintptr_t)d_out & 15) == 0) && (g.ndim == 1 || (g.n[0] & 3) == 0);
-    launch_reset(st, c->misc, c->hist, c->desc_chunks, stiles, nullptr, 0);
+    launch_reset(st, c->misc, c->hist, c->desc_chunks, stiles, has_map ? c->desc_pmap : nullptr,
+                 has_map ? stiles : 0, nullptr, 0, L.chunks, L.stream, r.nreg);
     t_mark(c, st, "reset");
     launch_lut(st, in + L.lens, c->lut, c->misc);
     t_mark(c, st, "lut");
     launch_scan(st, SCAN_CHUNKS, in + L.chunks, g.nblocks, c->off, c->desc_chunks, &c->misc->stile_ctr, c->misc,
                 r.bits);
     t_mark(c, st, "scan");
-    launch_decode(st, g, (const uint32_t*)(in + L.stream), r.words, c->off, (const uint16_t*)(in + L.chunks),
-                  c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->ofirst, r.nout,
-                  2.0 * r.eb_abs, d_out, vec, c->misc);
+    if (pred == FZ_PRED_LORENZO1) {
+        launch_decode(st, g, (const uint32_t*)(in + L.stream), r.words, c->off, (const uint16_t*)(in + L.chunks),
+                      c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->ofirst, r.nout,
+                      2.0 * r.eb_abs, d_out, vec, c->misc);
+    } else {
+        if (has_map) {
+            launch_map_unpack(st, in + L.map, g.nblocks, c->bpred, c->misc);
+            launch_scan(st, SCAN_PMAP, c->bpred, g.nblocks, c->reg_idx, c->desc_pmap, &c->misc->mtile_ctr, c->misc,
+                        0);
+        }
+        launch_decode_pred(st, g, (const uint32_t*)(in + L.stream), r.words, c->off, (const uint16_t*)(in + L.chunks),
+                           c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->ofirst, r.nout,
+                           c->res, has_map ? -1 : (int)pred, c->bpred, c->reg_idx, (const int32_t*)(in + L.coef),
+                           r.nreg, 2.0 * r.eb_abs, d_out, vec, c->misc);
+    }
     t_mark(c, st, "decode");
     launch_patch(st, g, (const uint32_t*)(in + L.ppos), (const uint32_t*)(in + L.pbits), r.npat, d_out, c->misc);
     t_mark(c, st, "patch");
@@ -482,6 +571,7 @@ int fz_decompress(fz_ctx* c, const void* d_in, uint64_t in_bytes, const void* h_
     rc = flags_status(m.flags);
     if (rc) return rc;
     if (m.code0_count != r.nout) return FZ_ERR_CORRUPT;
+    if (has_map && m.nreg != r.nreg) return FZ_ERR_CORRUPT;
     return FZ_OK;
 }
 

@@ -23,7 +23,7 @@ constexpr uint32_t kMagic = 0x314D5A46u;  // "FZM1"
 constexpr uint16_t kVersion = 1;
 
 // prefix-scan kinds (fz_scan.hip)
-enum { SCAN_COUNTS = 0, SCAN_BITS = 1, SCAN_CHUNKS = 2 };
+enum { SCAN_COUNTS = 0, SCAN_BITS = 1, SCAN_CHUNKS = 2, SCAN_PMAP = 3 };
 
 // flag bits raised by kernels in Misc::flags
 enum : uint32_t {
@@ -43,7 +43,7 @@ struct Misc {
     uint32_t etile_ctr;
     uint32_t stile_ctr;
     uint32_t code0_count;      // decode: outlier codes seen
-    uint32_t pad0;
+    uint32_t mtile_ctr;        // predictor-map scan
     uint64_t total_bits_cb;    // sum hist[c] * len[c]
     uint64_t total_bits_enc;   // end of the last encoded tile
     uint64_t n_out;            // outliers (inclusive count of the last tile)
@@ -51,7 +51,10 @@ struct Misc {
     uint64_t total_bytes;      // container size (non-verbatim)
     uint64_t verbatim;         // 1 when the packed container is not smaller
     double eb_abs;
-    uint64_t pad1[3];
+    uint64_t off_chunks;       // container offsets of the chunk table and
+    uint64_t off_stream;       // the stream (depend on the map/coefficients)
+    uint64_t nreg;             // blocks predicted by regression
+    uint64_t pad1[2];
 };
 
 // Unsigned division by a runtime constant d <= 2^23 for numerators <= 2^23:
@@ -135,17 +138,23 @@ __host__ __device__ inline uint64_t seg_index(const Geom& g, const BlockInfo& bi
     return x + (uint64_t)g.n[0] * (y + (uint64_t)g.n[1] * z);
 }
 
-// Container section offsets (each 16-byte aligned).
+// Container section offsets (each 16-byte aligned): header, code lengths,
+// [predictor map, 2 bits per block, when predictors are chosen per block],
+// [regression coefficients, 4 x i32 per regression block], chunk table,
+// stream, outlier positions, outlier residuals, patch positions, patch bits.
 struct Layout {
-    uint64_t lens, chunks, stream, opos, oval, ppos, pbits, total;
+    uint64_t lens, map, coef, chunks, stream, opos, oval, ppos, pbits, total;
 };
 
 __host__ __device__ inline uint64_t align16(uint64_t v) { return (v + 15) & ~15ull; }
 
-__host__ __device__ inline Layout make_layout(uint64_t nblocks, uint64_t words, uint64_t nout, uint64_t npat) {
+__host__ __device__ inline Layout make_layout(uint64_t nblocks, bool has_map, uint64_t nreg, uint64_t words,
+                                              uint64_t nout, uint64_t npat) {
     Layout L;
     L.lens = kHdr;
-    L.chunks = L.lens + kBins / 2;
+    L.map = L.lens + kBins / 2;
+    L.coef = align16(L.map + (has_map ? (nblocks + 3) / 4 : 0));
+    L.chunks = align16(L.coef + 16 * nreg);
     L.stream = align16(L.chunks + 2 * nblocks);
     L.opos = align16(L.stream + 4 * words);
     L.oval = align16(L.opos + 4 * nout);
@@ -154,6 +163,11 @@ __host__ __device__ inline Layout make_layout(uint64_t nblocks, uint64_t words, 
     L.total = align16(L.pbits + 4 * npat);
     return L;
 }
+
+// Predictor modes (header field): 0, 1, 2 = that predictor in every block;
+// 3 = chosen per block by the learned selector, 4 = by exhaustive trial.
+constexpr uint32_t kPredSelected = 3, kPredTrial = 4;
+__host__ __device__ inline bool pred_has_map(uint32_t pred) { return pred >= kPredSelected; }
 
 // ------------------------------------------------------- device helpers
 // Order-preserving map float -> u32 (unsigned compare = float compare).

@@ -115,8 +115,9 @@ struct LaneStream {
 __device__ __forceinline__ void load_outliers(const uint32_t* __restrict__ opos, const int32_t* __restrict__ oval,
                                               uint64_t n, uint32_t i, uint4& p, int4& v) {
     if ((uint64_t)i + 4 <= n) {
-        p = *reinterpret_cast<const uint4*>(opos + i);
-        v = *reinterpret_cast<const int4*>(oval + i);
+        // the list start is only 4-byte aligned: four dword loads
+        p = make_uint4(opos[i], opos[i + 1], opos[i + 2], opos[i + 3]);
+        v = make_int4(oval[i], oval[i + 1], oval[i + 2], oval[i + 3]);
     } else {
         p.x = (uint64_t)i < n ? opos[i] : 0xFFFFFFFFu;
         p.y = (uint64_t)i + 1 < n ? opos[i + 1] : 0xFFFFFFFFu;
@@ -292,6 +293,205 @@ __global__ __launch_bounds__(256) void k_decode(
     if ((t & 63) == 0 && c) atomicAdd(&misc->code0_count, c);
 }
 
+// ---------------------------------------------- per-block predictor decode
+// Containers whose blocks use the second-order Lorenzo or regression
+// predictor decode in two steps: residuals per block to scratch (lane per
+// block, same Huffman and outlier handling as k_decode), then one wave per
+// block applies that block's inverse in LDS and writes the field.
+
+// 2-bit predictor map of the container -> one byte per block
+__global__ __launch_bounds__(256) void k_map_unpack(const uint8_t* __restrict__ map, uint32_t nblocks,
+                                                    uint8_t* __restrict__ bpred, Misc* misc) {
+    const uint32_t b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= nblocks) return;
+    const uint8_t v = (uint8_t)((map[b >> 2] >> (2 * (b & 3))) & 3u);
+    if (v > 2) atomicOr(&misc->flags, F_CORRUPT);
+    bpred[b] = v > 2 ? 0 : v;
+}
+
+template <int ND>
+__global__ __launch_bounds__(256) void k_decode_res(Geom g, const uint32_t* __restrict__ stream, uint64_t nwords,
+                                                    const uint64_t* __restrict__ off,
+                                                    const uint16_t* __restrict__ chunks,
+                                                    const uint16_t* __restrict__ lut_g,
+                                                    const uint32_t* __restrict__ opos, const int32_t* __restrict__ oval,
+                                                    const uint32_t* __restrict__ ofirst, uint64_t n_out,
+                                                    int32_t* __restrict__ res, Misc* misc) {
+    __shared__ uint16_t LUT[kLut];
+    __shared__ uint32_t WIN[kDecLanes * kWin];
+    const uint32_t t = threadIdx.x;
+    for (uint32_t i = t; i < (uint32_t)kLut; i += 256) LUT[i] = lut_g[i];
+    __syncthreads();
+    const uint32_t b0 = blockIdx.x * 256 + t;
+    const bool active = b0 < g.nblocks;
+    const uint32_t b = active ? b0 : g.nblocks - 1;
+    const BlockInfo info = block_info(g, b);
+    const uint64_t start = off[b];
+    LaneStream ls;
+    ls.stream = stream;
+    ls.nwords = nwords;
+    ls.win = &WIN[t];
+    uint32_t code0 = 0;
+    bool bad = false;
+    const uint32_t pos_b = b * kBlockElems;
+    uint32_t onext = 0, ok = 0;
+    uint4 op4 = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+    int4 ov4 = make_int4(0, 0, 0, 0);
+    if (n_out) {
+        onext = ofirst[b];
+        load_outliers(opos, oval, n_out, onext, op4, ov4);
+    }
+    uint64_t bp = start;
+    if (active) {
+        ls.stage(bp);
+        uint32_t cnt = 0;
+        for (uint32_t lz = 0; lz < info.ez; lz++)
+            for (uint32_t ly = 0; ly < info.ey; ly++)
+                for (uint32_t lx = 0; lx < info.ex; lx++) {
+                    if (cnt == 32) {
+                        bp = ls.bitpos();
+                        ls.stage(bp);
+                        cnt = 0;
+                    }
+                    const uint32_t pos = pos_b + lx + g.bs[0] * (ly + g.bs[1] * lz);
+                    const uint64_t v = ls.peek64();
+                    const uint32_t e = LUT[(uint32_t)(v >> (64 - kLmax))];
+                    ls.rel += e >> 10;
+                    const uint32_t sym = e & 1023u;
+                    int32_t d = (int32_t)sym - kRadius;
+                    if (!sym) {
+                        code0++;
+                        const uint32_t pk = ok == 0 ? op4.x : ok == 1 ? op4.y : ok == 2 ? op4.z : op4.w;
+                        d = ok == 0 ? ov4.x : ok == 1 ? ov4.y : ok == 2 ? ov4.z : ov4.w;
+                        if (pk != pos) {
+                            bad = true;
+                            d = 0;
+                        }
+                        if (++ok == 4) {
+                            onext += 4;
+                            ok = 0;
+                            load_outliers(opos, oval, n_out, onext, op4, ov4);
+                        }
+                    }
+                    res[pos] = d;
+                    cnt++;
+                }
+        bp = ls.bitpos();
+    }
+    if (active && bp - start != chunks[b]) bad = true;
+    if (bad) atomicOr(&misc->flags, F_CORRUPT);
+    uint32_t c = active ? code0 : 0u;
+#pragma unroll
+    for (int dd = 32; dd > 0; dd >>= 1) c += __shfl_xor(c, dd, 64);
+    if ((t & 63) == 0 && c) atomicAdd(&misc->code0_count, c);
+}
+
+// One wave (workgroup of 64) per block: residuals -> grid values in LDS by
+// the block's inverse, then dequantised row stores.
+template <int ND>
+__global__ __launch_bounds__(64) void k_inverse(Geom g, const int32_t* __restrict__ res, int fixed_pred,
+                                                const uint8_t* __restrict__ bpred,
+                                                const uint64_t* __restrict__ reg_idx,
+                                                const int32_t* __restrict__ coefs, uint64_t nreg, double e2,
+                                                float* __restrict__ out, int vec, Misc* misc) {
+    __shared__ int32_t A[kBlockElems];
+    const uint32_t b = blockIdx.x;
+    const uint32_t lane = threadIdx.x;
+    const BlockInfo info = block_info(g, b);
+    const uint32_t p = fixed_pred >= 0 ? (uint32_t)fixed_pred : bpred[b];
+    const int32_t* rb = res + (uint64_t)b * kBlockElems;
+    {
+        const int4* src = reinterpret_cast<const int4*>(rb + 8 * lane);
+        int4* dst = reinterpret_cast<int4*>(&A[8 * lane]);
+        dst[0] = src[0];
+        dst[1] = src[1];
+    }
+    __syncthreads();
+    const uint32_t bs0 = g.bs[0], bs1 = g.bs[1];
+    const uint32_t ext[3] = {info.ex, info.ey, info.ez};
+    if (p <= 1) {
+        // inclusive prefix sums along x, y, z (twice each for the second order)
+        const int passes = p == 1 ? 2 : 1;
+        for (int axis = 0; axis < (int)ND; axis++) {
+            const uint32_t len = ext[axis];
+            const uint32_t stride = axis == 0 ? 1 : (axis == 1 ? bs0 : bs0 * bs1);
+            const uint32_t nlines = kBlockElems / (axis == 0 ? bs0 : (axis == 1 ? bs1 : 8));
+            if (ND == 1) {
+                // one line of 512: lane-local prefix over 8, wave scan of totals
+                for (int rep = 0; rep < passes; rep++) {
+                    int32_t v[8];
+                    int32_t acc = 0;
+#pragma unroll
+                    for (int i = 0; i < 8; i++) {
+                        acc += A[8 * lane + i];
+                        v[i] = acc;
+                    }
+                    const int32_t incl = (int32_t)wave_incl_scan((uint32_t)acc);
+                    const int32_t excl = incl - acc;
+#pragma unroll
+                    for (int i = 0; i < 8; i++) A[8 * lane + i] = v[i] + excl;
+                    __syncthreads();
+                }
+            } else {
+                for (uint32_t line = lane; line < nlines; line += 64) {
+                    // base of this line: the remaining coordinates
+                    uint32_t base;
+                    if (axis == 0) base = line * bs0;
+                    else if (axis == 1) base = (line % bs0) + (line / bs0) * bs0 * bs1;
+                    else base = line;
+                    for (int rep = 0; rep < passes; rep++) {
+                        int32_t acc = 0;
+                        for (uint32_t i = 0; i < len; i++) {
+                            acc += A[base + i * stride];
+                            A[base + i * stride] = acc;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    } else {
+        // regression: add the fixed-point plane back
+        // a map that selects more regression blocks than the container
+        // holds coefficients for is corrupt (checked again on the host)
+        const uint64_t r = fixed_pred >= 0 ? b : reg_idx[b];
+        int4 c = make_int4(0, 0, 0, 0);
+        if (r < nreg) c = reinterpret_cast<const int4*>(coefs)[r];
+        else if (lane == 0) atomicOr(&misc->flags, F_CORRUPT);
+        for (uint32_t k = lane; k < kBlockElems; k += 64) {
+            const uint32_t lx = k % bs0, ly = (k / bs0) % bs1, lz = k / (bs0 * bs1);
+            if (lx < info.ex && ly < info.ey && lz < info.ez) {
+                const int64_t sum = (int64_t)c.x + (int64_t)c.y * (2 * (int32_t)lx - ((int32_t)info.ex - 1)) +
+                                    (int64_t)c.z * (2 * (int32_t)ly - ((int32_t)info.ey - 1)) +
+                                    (int64_t)c.w * (2 * (int32_t)lz - ((int32_t)info.ez - 1)) + 128;
+                A[k] += (int32_t)(sum >> 8);
+            }
+        }
+        __syncthreads();
+    }
+    // dequantise and store: lane = segment of 8 values along x
+    uint32_t lx0, ly, lz;
+    seg_coords<ND>(lane, lx0, ly, lz);
+    if (ly < info.ey && lz < info.ez && lx0 < info.ex) {
+        const uint32_t nv = min(8u, info.ex - lx0);
+        const uint64_t idx = ((uint64_t)info.bx * g.bs[0] + lx0) +
+                             (uint64_t)g.n[0] * (((uint64_t)info.by * g.bs[1] + ly) +
+                                                 (uint64_t)g.n[1] * ((uint64_t)info.bz * g.bs[2] + lz));
+        float v[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) v[i] = (float)((double)A[8 * lane + i] * e2);
+        if (nv == 8 && vec) {
+            f32x4* q4 = reinterpret_cast<f32x4*>(out + idx);
+            const f32x4 a = {v[0], v[1], v[2], v[3]};
+            const f32x4 c = {v[4], v[5], v[6], v[7]};
+            q4[0] = a;
+            q4[1] = c;
+        } else {
+            for (uint32_t i = 0; i < nv; i++) out[idx + i] = v[i];
+        }
+    }
+}
+
 // ------------------------------------------------------ outlier block index
 // ofirst[b] = index of the first outlier of block b (blocks with outliers).
 __global__ __launch_bounds__(256) void k_outlier_index(const uint32_t* __restrict__ opos, uint64_t n_out,
@@ -355,6 +555,36 @@ void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64
     else
         hipLaunchKernelGGL(k_decode<1>, dim3(grid), dim3(256), 0, st, g, stream, stream_words, off, chunks, lut,
                            opos, oval, ofirst, n_out, e2, out, vec, misc);
+}
+
+void launch_map_unpack(hipStream_t st, const uint8_t* map, uint32_t nblocks, uint8_t* bpred, Misc* misc) {
+    hipLaunchKernelGGL(k_map_unpack, dim3((nblocks + 255) / 256), dim3(256), 0, st, map, nblocks, bpred, misc);
+}
+
+void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,
+                        const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
+                        const int32_t* oval, uint32_t* ofirst, uint64_t n_out, int32_t* res, int fixed_pred,
+                        const uint8_t* bpred, const uint64_t* reg_idx, const int32_t* coefs, uint64_t nreg, double e2,
+                        float* out, int vec, Misc* misc) {
+    if (n_out) {
+        uint64_t og = (n_out + 255) / 256;
+        if (og > 4096) og = 4096;
+        hipLaunchKernelGGL(k_outlier_index, dim3((uint32_t)og), dim3(256), 0, st, opos, n_out, g.nblocks, ofirst);
+    }
+    const uint32_t grid = (g.nblocks + 255) / 256;
+#define FZ_DRES(NDV)                                                                                              \
+    hipLaunchKernelGGL(k_decode_res<NDV>, dim3(grid), dim3(256), 0, st, g, stream, stream_words, off, chunks, lut, \
+                       opos, oval, ofirst, n_out, res, misc);                                                      \
+    hipLaunchKernelGGL(k_inverse<NDV>, dim3(g.nblocks), dim3(64), 0, st, g, res, fixed_pred, bpred, reg_idx, coefs, \
+                       nreg, e2, out, vec, misc)
+    if (g.ndim == 3) {
+        FZ_DRES(3);
+    } else if (g.ndim == 2) {
+        FZ_DRES(2);
+    } else {
+        FZ_DRES(1);
+    }
+#undef FZ_DRES
 }
 
 void launch_patch(hipStream_t st, const Geom& g, const uint32_t* ppos, const uint32_t* pbits, uint64_t n_pat,

@@ -179,9 +179,11 @@ __device__ __forceinline__ uint32_t load_codes(const uint16_t* __restrict__ code
 template <int ND>
 __global__ __launch_bounds__(256) void k_encode_len(const uint16_t* __restrict__ codes, Geom g,
                                                     const uint32_t* __restrict__ cw_g, uint32_t ntiles,
-                                                    uint16_t* __restrict__ chunks, uint32_t* __restrict__ tile_bits) {
+                                                    uint8_t* __restrict__ out, const Misc* misc,
+                                                    uint32_t* __restrict__ tile_bits) {
     __shared__ uint8_t LEN[kBins];
     __shared__ uint32_t wsum[4];
+    uint16_t* chunks = reinterpret_cast<uint16_t*>(out + misc->off_chunks);
     const uint32_t t = threadIdx.x, lane = t & 63;
     const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 6));
     for (uint32_t i = t; i < (uint32_t)kBins; i += 256) LEN[i] = (uint8_t)(cw_g[i] >> 16);
@@ -208,11 +210,12 @@ template <int ND>
 __global__ __launch_bounds__(256) void k_encode_write(const uint16_t* __restrict__ codes, Geom g,
                                                       const uint32_t* __restrict__ cw_g, uint32_t ntiles,
                                                       const uint64_t* __restrict__ tile_start, Misc* misc,
-                                                      uint32_t* __restrict__ stream, uint32_t* __restrict__ tfirst,
+                                                      uint8_t* __restrict__ out, uint32_t* __restrict__ tfirst,
                                                       uint32_t* __restrict__ tlast) {
     __shared__ uint32_t CW[kBins];
     __shared__ uint32_t W[kEncWords];
     __shared__ uint32_t wsum[4];
+    uint32_t* stream = reinterpret_cast<uint32_t*>(out + misc->off_stream);
 
     const uint32_t t = threadIdx.x, lane = t & 63;
     const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 6));
@@ -281,30 +284,50 @@ __global__ __launch_bounds__(256) void k_encode_write(const uint16_t* __restrict
 // tile order (= position order); zero padding; header.  When the packed
 // container would not be smaller than the raw floats only the verbatim
 // decision is recorded for the host.
-__global__ __launch_bounds__(256) void k_finalize(Geom g, uint32_t mode, double eb, Misc* misc, uint8_t* out,
-                                                  uint32_t ntiles, const uint64_t* __restrict__ tile_start,
+__global__ __launch_bounds__(256) void k_finalize(Geom g, uint32_t mode, double eb, uint32_t pred, Misc* misc,
+                                                  uint8_t* out, uint32_t ntiles, const uint64_t* __restrict__ tile_start,
                                                   const uint32_t* __restrict__ tfirst,
                                                   const uint32_t* __restrict__ tlast,
                                                   const uint32_t* __restrict__ tile_cnt,
                                                   const uint64_t* __restrict__ tile_off,
                                                   const uint32_t* __restrict__ opos, const int32_t* __restrict__ oval,
                                                   const uint32_t* __restrict__ ppos,
-                                                  const uint32_t* __restrict__ pbits) {
+                                                  const uint32_t* __restrict__ pbits, const uint8_t* __restrict__ bpred,
+                                                  const uint64_t* __restrict__ reg_idx,
+                                                  const int32_t* __restrict__ coef) {
     const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint32_t flags = misc->flags;
     const uint64_t bits = misc->total_bits_enc;
     const uint64_t words = (bits + 31) / 32;
-    const uint64_t nout = misc->n_out, npat = misc->n_pat;
-    const Layout L = make_layout(g.nblocks, words, nout, npat);
+    const uint64_t nout = misc->n_out, npat = misc->n_pat, nreg = misc->nreg;
+    const bool has_map = pred_has_map(pred);
+    const Layout L = make_layout(g.nblocks, has_map, nreg, words, nout, npat);
     const bool verbatim = (flags & F_OVERFLOW) || L.total >= (uint64_t)kHdr + 4 * g.N;
     if (gid == 0) {
-        if (bits != misc->total_bits_cb) atomicOr(&misc->flags, F_INTERNAL);
+        if (bits != misc->total_bits_cb || L.chunks != misc->off_chunks) atomicOr(&misc->flags, F_INTERNAL);
         misc->verbatim = verbatim ? 1 : 0;
         misc->total_bytes = verbatim ? (uint64_t)kHdr + 4 * g.N : L.total;
     }
     if (verbatim || (flags & (F_NONFINITE | F_EB | F_INTERNAL | F_TIMEOUT))) return;
 
+    // predictor map (2 bits per block) and regression coefficients
+    if (has_map)
+        for (uint64_t i = gid; i < ((uint64_t)g.nblocks + 3) / 4; i += stride) {
+            uint8_t v = 0;
+            for (int k = 0; k < 4; k++) {
+                const uint64_t b = 4 * i + k;
+                if (b < g.nblocks) v |= (uint8_t)((bpred[b] & 3) << (2 * k));
+            }
+            out[L.map + i] = v;
+        }
+    if (nreg)
+        for (uint64_t b = gid; b < g.nblocks; b += stride) {
+            const bool reg = pred == 2 || (has_map && bpred[b] == 2);
+            if (!reg) continue;
+            const uint64_t r = pred == 2 ? b : reg_idx[b];
+            reinterpret_cast<int4*>(out + L.coef)[r] = reinterpret_cast<const int4*>(coef)[b];
+        }
     uint32_t* stream = reinterpret_cast<uint32_t*>(out + L.stream);
     for (uint64_t i = gid + 1; i < ntiles; i += stride) {
         const uint64_t G = tile_start[i];
@@ -336,10 +359,11 @@ __global__ __launch_bounds__(256) void k_finalize(Geom g, uint32_t mode, double 
     }
     if (gid == 0) {
         // zero padding between and after sections
-        const uint64_t ends[6] = {L.chunks + 2 * (uint64_t)g.nblocks, L.stream + 4 * words, L.opos + 4 * nout,
+        const uint64_t ends[8] = {L.map + (has_map ? ((uint64_t)g.nblocks + 3) / 4 : 0), L.coef + 16 * nreg,
+                                  L.chunks + 2 * (uint64_t)g.nblocks, L.stream + 4 * words, L.opos + 4 * nout,
                                   L.oval + 4 * nout, L.ppos + 4 * npat, L.pbits + 4 * npat};
-        const uint64_t starts[6] = {L.stream, L.opos, L.oval, L.ppos, L.pbits, L.total};
-        for (int k = 0; k < 6; k++)
+        const uint64_t starts[8] = {L.coef, L.chunks, L.stream, L.opos, L.oval, L.ppos, L.pbits, L.total};
+        for (int k = 0; k < 8; k++)
             for (uint64_t a = ends[k]; a < starts[k]; a++) out[a] = 0;
         // header
         double eb_abs;
@@ -352,7 +376,7 @@ __global__ __launch_bounds__(256) void k_finalize(Geom g, uint32_t mode, double 
         h[4] = (uint8_t)kVersion;
         h[5] = (uint8_t)(kVersion >> 8);
         st32(8, g.ndim);
-        st32(12, 0);
+        st32(12, pred);
         st64(16, g.n[0]);
         st64(24, g.n[1]);
         st64(32, g.n[2]);
@@ -366,6 +390,7 @@ __global__ __launch_bounds__(256) void k_finalize(Geom g, uint32_t mode, double 
         st32(80, (uint32_t)npat);
         st32(84, (uint32_t)words);
         st64(88, bits);
+        st32(96, (uint32_t)nreg);
         uint4* dst = reinterpret_cast<uint4*>(out);
         const uint4* src = reinterpret_cast<const uint4*>(h);
         for (int k = 0; k < kHdr / 16; k++) dst[k] = src[k];
@@ -378,39 +403,36 @@ void launch_codebook(hipStream_t st, const uint32_t* hist, uint8_t* out_lens, ui
 }
 
 void launch_encode_len(hipStream_t st, int grid, const uint16_t* codes, const Geom& g, const uint32_t* cw,
-                       uint32_t ntiles, uint8_t* out, uint32_t* tile_bits) {
-    const Layout L = make_layout(g.nblocks, 0, 0, 0);
-    uint16_t* chunks = reinterpret_cast<uint16_t*>(out + L.chunks);
+                       uint32_t ntiles, uint8_t* out, const Misc* misc, uint32_t* tile_bits) {
     if (g.ndim == 3)
-        hipLaunchKernelGGL(k_encode_len<3>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, chunks, tile_bits);
+        hipLaunchKernelGGL(k_encode_len<3>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, out, misc, tile_bits);
     else if (g.ndim == 2)
-        hipLaunchKernelGGL(k_encode_len<2>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, chunks, tile_bits);
+        hipLaunchKernelGGL(k_encode_len<2>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, out, misc, tile_bits);
     else
-        hipLaunchKernelGGL(k_encode_len<1>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, chunks, tile_bits);
+        hipLaunchKernelGGL(k_encode_len<1>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, out, misc, tile_bits);
 }
 
 void launch_encode_write(hipStream_t st, int grid, const uint16_t* codes, const Geom& g, const uint32_t* cw,
                          Misc* misc, uint32_t ntiles, uint8_t* out, const uint64_t* tile_start, uint32_t* tfirst,
                          uint32_t* tlast) {
-    const Layout L = make_layout(g.nblocks, 0, 0, 0);
-    uint32_t* stream = reinterpret_cast<uint32_t*>(out + L.stream);
     if (g.ndim == 3)
         hipLaunchKernelGGL(k_encode_write<3>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, tile_start, misc,
-                           stream, tfirst, tlast);
+                           out, tfirst, tlast);
     else if (g.ndim == 2)
         hipLaunchKernelGGL(k_encode_write<2>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, tile_start, misc,
-                           stream, tfirst, tlast);
+                           out, tfirst, tlast);
     else
         hipLaunchKernelGGL(k_encode_write<1>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, tile_start, misc,
-                           stream, tfirst, tlast);
+                           out, tfirst, tlast);
 }
 
-void launch_finalize(hipStream_t st, const Geom& g, uint32_t mode, double eb, Misc* misc, uint8_t* out,
-                     uint32_t ntiles, const uint64_t* tile_start, const uint32_t* tfirst, const uint32_t* tlast,
-                     const uint32_t* tile_cnt, const uint64_t* tile_off, const uint32_t* opos, const int32_t* oval,
-                     const uint32_t* ppos, const uint32_t* pbits) {
-    hipLaunchKernelGGL(k_finalize, dim3(1024), dim3(256), 0, st, g, mode, eb, misc, out, ntiles, tile_start, tfirst,
-                       tlast, tile_cnt, tile_off, opos, oval, ppos, pbits);
+void launch_finalize(hipStream_t st, const Geom& g, uint32_t mode, double eb, uint32_t pred, Misc* misc,
+                     uint8_t* out, uint32_t ntiles, const uint64_t* tile_start, const uint32_t* tfirst,
+                     const uint32_t* tlast, const uint32_t* tile_cnt, const uint64_t* tile_off, const uint32_t* opos,
+                     const int32_t* oval, const uint32_t* ppos, const uint32_t* pbits, const uint8_t* bpred,
+                     const uint64_t* reg_idx, const int32_t* coef) {
+    hipLaunchKernelGGL(k_finalize, dim3(1024), dim3(256), 0, st, g, mode, eb, pred, misc, out, ntiles, tile_start,
+                       tfirst, tlast, tile_cnt, tile_off, opos, oval, ppos, pbits, bpred, reg_idx, coef);
 }
 
 }  // namespace fz

@@ -7,11 +7,15 @@ namespace fz {
 
 // fz_quant.hip
 void launch_reset(hipStream_t st, Misc* misc, uint32_t* hist, uint64_t* d1, uint32_t n1, uint64_t* d2,
-                  uint32_t n2);
+                  uint32_t n2, uint64_t* d3, uint32_t n3, uint64_t off_chunks, uint64_t off_stream, uint64_t nreg);
+void launch_fill32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v);
 void launch_minmax(hipStream_t st, const float* x, uint64_t N, int vec, Misc* misc, int grid);
 void launch_quant(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
                   Misc* misc, uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt, uint32_t* opos,
-                  int32_t* oval, uint32_t* ppos, uint32_t* pbits);
+                  int32_t* oval, uint32_t* ppos, uint32_t* pbits, int fixed_pred, const uint8_t* bpred,
+                  int32_t* coef);
+void launch_trial(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
+                  Misc* misc, uint32_t ntiles, const uint32_t* cw_ref, uint8_t* choice, uint32_t* costs);
 
 // fz_scan.hip
 void launch_scan(hipStream_t st, int kind, const void* in, uint32_t n, uint64_t* out, uint64_t* desc, uint32_t* ctr,
@@ -21,14 +25,15 @@ uint32_t scan_tiles(uint32_t n);
 // fz_huffman.hip
 void launch_codebook(hipStream_t st, const uint32_t* hist, uint8_t* out_lens, uint32_t* cw, Misc* misc);
 void launch_encode_len(hipStream_t st, int grid, const uint16_t* codes, const Geom& g, const uint32_t* cw,
-                       uint32_t ntiles, uint8_t* out, uint32_t* tile_bits);
+                       uint32_t ntiles, uint8_t* out, const Misc* misc, uint32_t* tile_bits);
 void launch_encode_write(hipStream_t st, int grid, const uint16_t* codes, const Geom& g, const uint32_t* cw,
                          Misc* misc, uint32_t ntiles, uint8_t* out, const uint64_t* tile_start, uint32_t* tfirst,
                          uint32_t* tlast);
-void launch_finalize(hipStream_t st, const Geom& g, uint32_t mode, double eb, Misc* misc, uint8_t* out,
-                     uint32_t ntiles, const uint64_t* tile_start, const uint32_t* tfirst, const uint32_t* tlast,
-                     const uint32_t* tile_cnt, const uint64_t* tile_off, const uint32_t* opos, const int32_t* oval,
-                     const uint32_t* ppos, const uint32_t* pbits);
+void launch_finalize(hipStream_t st, const Geom& g, uint32_t mode, double eb, uint32_t pred, Misc* misc,
+                     uint8_t* out, uint32_t ntiles, const uint64_t* tile_start, const uint32_t* tfirst,
+                     const uint32_t* tlast, const uint32_t* tile_cnt, const uint64_t* tile_off, const uint32_t* opos,
+                     const int32_t* oval, const uint32_t* ppos, const uint32_t* pbits, const uint8_t* bpred,
+                     const uint64_t* reg_idx, const int32_t* coef);
 
 // fz_decode.hip
 void launch_lut(hipStream_t st, const uint8_t* lens_packed, uint16_t* lut, Misc* misc);
@@ -36,6 +41,12 @@ void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64
                    const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
                    const int32_t* oval, uint32_t* ofirst, uint64_t n_out, double e2, float* out, int vec,
                    Misc* misc);
+void launch_map_unpack(hipStream_t st, const uint8_t* map, uint32_t nblocks, uint8_t* bpred, Misc* misc);
+void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,
+                        const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
+                        const int32_t* oval, uint32_t* ofirst, uint64_t n_out, int32_t* res, int fixed_pred,
+                        const uint8_t* bpred, const uint64_t* reg_idx, const int32_t* coefs, uint64_t nreg, double e2,
+                        float* out, int vec, Misc* misc);
 void launch_patch(hipStream_t st, const Geom& g, const uint32_t* ppos, const uint32_t* pbits, uint64_t n_pat,
                   float* out, Misc* misc);
 

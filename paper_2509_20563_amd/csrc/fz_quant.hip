@@ -11,18 +11,23 @@ namespace fz {
 // Clears the per-call scratch: Misc, the global histogram and the look-back
 // descriptors (a fill kernel rather than a memset node, so the sequence can
 // be captured in a graph).
-__global__ void k_reset(Misc* misc, uint32_t* hist, uint64_t* d1, uint32_t n1, uint64_t* d2, uint32_t n2) {
+__global__ void k_reset(Misc* misc, uint32_t* hist, uint64_t* d1, uint32_t n1, uint64_t* d2, uint32_t n2,
+                        uint64_t* d3, uint32_t n3, uint64_t off_chunks, uint64_t off_stream, uint64_t nreg) {
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t stride = gridDim.x * blockDim.x;
     if (gid == 0) {
         Misc m = {};
         m.mm_lo = 0xFFFFFFFFu;
         m.mm_hi = 0u;
+        m.off_chunks = off_chunks;
+        m.off_stream = off_stream;
+        m.nreg = nreg;
         *misc = m;
     }
     for (uint32_t i = gid; i < (uint32_t)kBins; i += stride) hist[i] = 0;
     for (uint32_t i = gid; i < n1; i += stride) d1[i] = 0;
     for (uint32_t i = gid; i < n2; i += stride) d2[i] = 0;
+    for (uint32_t i = gid; i < n3; i += stride) d3[i] = 0;
 }
 
 // -------------------------------------------------------------- min/max
@@ -134,13 +139,23 @@ __device__ __forceinline__ void read_row(const int32_t* Q, uint32_t off, int32_t
     r[4] = c.x; r[5] = c.y; r[6] = c.z; r[7] = c.w;
 }
 
-template <int ND>
+// MODE: kQuantP0 (first-order Lorenzo everywhere), kQuantPred (predictor
+// per block: fixed_pred >= 0 for every block, else bpred[b]), kQuantTrial
+// (no codes: per-block cost of each predictor under a reference code,
+// cheapest predictor -> choice[b], the three costs -> costs[3 b + p]).
+constexpr int kQuantP0 = 0, kQuantPred = 1, kQuantTrial = 2;
+
+template <int ND, int MODE>
 __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom g, uint32_t mode, double eb,
                                                int vec, Misc* misc, uint32_t* __restrict__ hist_g,
                                                uint16_t* __restrict__ codes, uint32_t ntiles,
                                                uint32_t* __restrict__ tile_cnt, uint32_t* __restrict__ opos,
                                                int32_t* __restrict__ oval, uint32_t* __restrict__ ppos,
-                                               uint32_t* __restrict__ pbits) {
+                                               uint32_t* __restrict__ pbits, int fixed_pred,
+                                               const uint8_t* __restrict__ bpred, int32_t* __restrict__ coef,
+                                               const uint32_t* __restrict__ cw_ref, uint8_t* __restrict__ choice,
+                                               uint32_t* __restrict__ costs) {
+    constexpr bool PRED = MODE != kQuantP0;
     // q per block, regions padded by 8 words so the load-mapped writes of
     // four blocks do not fall into the same banks; one extra zero row
     constexpr int kQStride = kBlockElems + 8;
@@ -149,6 +164,7 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
     __shared__ uint8_t PM[kTileBlocks * kSegs];
     __shared__ uint32_t H[kBins];
     __shared__ uint32_t wsum[4];
+    __shared__ uint8_t LREF[kBins];
 
     const uint32_t t = threadIdx.x;
     const uint32_t lane = t & 63;
@@ -161,6 +177,13 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
     const double e2 = 2.0 * eb_abs;
     const double inv = 1.0 / e2;
     for (uint32_t i = t; i < (uint32_t)kBins; i += 256) H[i] = 0;
+    if (MODE == kQuantTrial) {
+        // reference code lengths; an unused code counts as kLmax + 1 bits
+        for (uint32_t i = t; i < (uint32_t)kBins; i += 256) {
+            const uint32_t l = cw_ref[i] >> 16;
+            LREF[i] = (uint8_t)(l ? l : kLmax + 1);
+        }
+    }
     if (t < 8) Q[kZero + t] = 0;
 
     // load-phase lane constants (the same for every tile): block in tile,
@@ -237,36 +260,164 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
         int32_t d[8];
         {
             const BlockInfo info = block_info(g, blk ? b : 0);
-            int32_t r0[8], A[8];
-            int32_t am1 = 0;  // A[-1]: the left neighbour term along x
-            read_row<ND>(Q, Qb + s * 8, r0);
-            if (ND == 3) {
-                const uint32_t ly = s & 7, lz = s >> 3;
-                nv = (blk && ly < info.ey && lz < info.ez) ? info.ex : 0u;
-                int32_t ry[8], rz[8], ryz[8];
-                read_row<ND>(Q, ly ? Qb + (s - 1) * 8 : kZero, ry);
-                read_row<ND>(Q, lz ? Qb + (s - 8) * 8 : kZero, rz);
-                read_row<ND>(Q, (ly && lz) ? Qb + (s - 9) * 8 : kZero, ryz);
+            uint32_t lx0, ly, lz;
+            seg_coords<ND>(s, lx0, ly, lz);
+            nv = (blk && ly < info.ey && lz < info.ez && lx0 < info.ex) ? min(8u, info.ex - lx0) : 0u;
+            auto residual = [&](const uint32_t pr) {
+            if (pr == 0) {
+                // first-order Lorenzo: A = residual along y/z of the rows,
+                // then the backward difference along x
+                int32_t r0[8], A[8];
+                int32_t am1 = 0;  // A[-1]: the left neighbour term along x
+                read_row<ND>(Q, Qb + s * 8, r0);
+                if (ND == 3) {
+                    int32_t ry[8], rz[8], ryz[8];
+                    read_row<ND>(Q, ly ? Qb + (s - 1) * 8 : kZero, ry);
+                    read_row<ND>(Q, lz ? Qb + (s - 8) * 8 : kZero, rz);
+                    read_row<ND>(Q, (ly && lz) ? Qb + (s - 9) * 8 : kZero, ryz);
 #pragma unroll
-                for (int i = 0; i < 8; i++) A[i] = (r0[i] - ry[i]) - (rz[i] - ryz[i]);
-            } else if (ND == 2) {
-                const uint32_t sx = s & 3, ly = s >> 2;
-                nv = (blk && ly < info.ey && 8 * sx < info.ex) ? min(8u, info.ex - 8 * sx) : 0u;
-                int32_t up[8];
-                read_row<ND>(Q, ly ? Qb + (s - 4) * 8 : kZero, up);
-                const int32_t left = Q[sx ? Qb + (s - 1) * 8 + 7 : kZero];
-                const int32_t upleft = Q[(sx && ly) ? Qb + (s - 5) * 8 + 7 : kZero];
-                am1 = left - upleft;
+                    for (int i = 0; i < 8; i++) A[i] = (r0[i] - ry[i]) - (rz[i] - ryz[i]);
+                } else if (ND == 2) {
+                    const uint32_t sx = s & 3;
+                    int32_t up[8];
+                    read_row<ND>(Q, ly ? Qb + (s - 4) * 8 : kZero, up);
+                    const int32_t left = Q[sx ? Qb + (s - 1) * 8 + 7 : kZero];
+                    const int32_t upleft = Q[(sx && ly) ? Qb + (s - 5) * 8 + 7 : kZero];
+                    am1 = left - upleft;
 #pragma unroll
-                for (int i = 0; i < 8; i++) A[i] = r0[i] - up[i];
-            } else {
-                nv = (blk && 8 * s < info.ex) ? min(8u, info.ex - 8 * s) : 0u;
-                am1 = Q[s ? Qb + (s - 1) * 8 + 7 : kZero];
+                    for (int i = 0; i < 8; i++) A[i] = r0[i] - up[i];
+                } else {
+                    am1 = Q[s ? Qb + (s - 1) * 8 + 7 : kZero];
 #pragma unroll
-                for (int i = 0; i < 8; i++) A[i] = r0[i];
+                    for (int i = 0; i < 8; i++) A[i] = r0[i];
+                }
+#pragma unroll
+                for (int i = 7; i >= 0; i--) d[i] = A[i] - (i ? A[i - 1] : am1);
+            } else if (PRED && pr == 1) {
+                // second-order Lorenzo: weights (1, -2, 1) per axis; rows
+                // combined first (R), then the second difference along x
+                int32_t R[8], rr[8];
+                int32_t rm1 = 0, rm2 = 0;  // R[-1], R[-2]
+#pragma unroll
+                for (int i = 0; i < 8; i++) R[i] = 0;
+                if (ND == 3) {
+#pragma unroll
+                    for (int c = 0; c < 3; c++)
+#pragma unroll
+                        for (int a = 0; a < 3; a++) {
+                            const int32_t w = (a == 1 ? -2 : 1) * (c == 1 ? -2 : 1);
+                            read_row<ND>(Q, (ly >= (uint32_t)a && lz >= (uint32_t)c) ? Qb + (s - a - 8 * c) * 8 : kZero,
+                                         rr);
+#pragma unroll
+                            for (int i = 0; i < 8; i++) R[i] += w * rr[i];
+                        }
+                } else if (ND == 2) {
+                    const uint32_t sx = s & 3;
+#pragma unroll
+                    for (int a = 0; a < 3; a++) {
+                        const int32_t w = a == 1 ? -2 : 1;
+                        const bool in = ly >= (uint32_t)a;
+                        read_row<ND>(Q, in ? Qb + (s - 4 * a) * 8 : kZero, rr);
+#pragma unroll
+                        for (int i = 0; i < 8; i++) R[i] += w * rr[i];
+                        const uint32_t lo = (sx && in) ? Qb + (s - 4 * a - 1) * 8 : kZero;
+                        rm2 += w * Q[lo + (lo == kZero ? 0 : 6)];
+                        rm1 += w * Q[lo + (lo == kZero ? 0 : 7)];
+                    }
+                } else {
+                    read_row<ND>(Q, Qb + s * 8, R);
+                    rm2 = Q[s ? Qb + (s - 1) * 8 + 6 : kZero];
+                    rm1 = Q[s ? Qb + (s - 1) * 8 + 7 : kZero];
+                }
+#pragma unroll
+                for (int i = 7; i >= 0; i--) {
+                    const int32_t p1 = i >= 1 ? R[i - 1] : rm1;
+                    const int32_t p2 = i >= 2 ? R[i - 2] : (i == 1 ? rm1 : rm2);
+                    d[i] = R[i] - 2 * p1 + p2;
+                }
+            } else if (PRED) {
+                // linear regression: wave-reduced sums over the block's real
+                // values with centred coordinates, fixed point (8 bits)
+                int32_t r0[8];
+                read_row<ND>(Q, Qb + s * 8, r0);
+                const int32_t v = 2 * (int32_t)ly - ((int32_t)info.ey - 1);
+                const int32_t w = 2 * (int32_t)lz - ((int32_t)info.ez - 1);
+                int64_t s0 = 0, su = 0;
+#pragma unroll
+                for (int i = 0; i < 8; i++)
+                    if (i < (int)nv) {
+                        const int32_t u = 2 * (int32_t)(lx0 + i) - ((int32_t)info.ex - 1);
+                        s0 += r0[i];
+                        su += (int64_t)u * r0[i];
+                    }
+                const int64_t sv = s0 * v, sw = s0 * w;
+                auto wsum64 = [&](int64_t a) -> int64_t {
+                    const uint64_t r = wave_incl_scan64((uint64_t)a, [](uint64_t x, uint64_t y) { return x + y; });
+                    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)r, 63);
+                    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(r >> 32), 63);
+                    return (int64_t)(((uint64_t)hi << 32) | lo);
+                };
+                const int64_t S0 = wsum64(s0), SU = wsum64(su), SV = wsum64(sv), SW = wsum64(sw);
+                const int64_t n = (int64_t)info.ex * info.ey * info.ez;
+                auto rdiv = [](int64_t a, int64_t q) -> int64_t {
+                    return a >= 0 ? (a + q / 2) / q : -((-a + q / 2) / q);
+                };
+                auto clamp32 = [](int64_t a) -> int32_t {
+                    return a > INT32_MAX ? INT32_MAX : (a < INT32_MIN ? INT32_MIN : (int32_t)a);
+                };
+                auto dsum = [&](int64_t e) -> int64_t { return e * (e * e - 1) / 3 * (n / e); };
+                const int64_t dx = dsum(info.ex), dy = dsum(info.ey), dz = dsum(info.ez);
+                const int32_t cA = clamp32(rdiv(S0 * 256, n));
+                const int32_t cX = dx > 0 ? clamp32(rdiv(SU * 256, dx)) : 0;
+                const int32_t cY = (ND >= 2 && dy > 0) ? clamp32(rdiv(SV * 256, dy)) : 0;
+                const int32_t cZ = (ND >= 3 && dz > 0) ? clamp32(rdiv(SW * 256, dz)) : 0;
+                if (MODE == kQuantPred && lane == 0 && blk) {
+                    int4* cp = reinterpret_cast<int4*>(coef + 4 * (uint64_t)b);
+                    *cp = make_int4(cA, cX, cY, cZ);
+                }
+                const int64_t base = (int64_t)cA + (int64_t)cY * v + (int64_t)cZ * w + 128;
+#pragma unroll
+                for (int i = 0; i < 8; i++) {
+                    const int32_t u = 2 * (int32_t)(lx0 + i) - ((int32_t)info.ex - 1);
+                    const int32_t pred = (int32_t)((base + (int64_t)cX * u) >> 8);
+                    d[i] = r0[i] - pred;
+                }
             }
+            };
+            if (MODE == kQuantTrial) {
+                // cost of each predictor: reference code bits + 64 per
+                // outlier (+ 128 bits of coefficients for the regression)
+                uint32_t cst[3];
 #pragma unroll
-            for (int i = 7; i >= 0; i--) d[i] = A[i] - (i ? A[i - 1] : am1);
+                for (uint32_t pr = 0; pr < 3; pr++) {
+                    residual(pr);
+                    uint32_t c = 0;
+#pragma unroll
+                    for (int i = 0; i < 8; i++) {
+                        const uint32_t u = (uint32_t)(d[i] + (kRadius - 1));
+                        const uint32_t cd = u < (uint32_t)(2 * kRadius - 1) ? u + 1 : 0u;
+                        c += (i < (int)nv) ? (uint32_t)LREF[cd] + (cd ? 0u : 64u) : 0u;
+                    }
+                    cst[pr] = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(c), 63) + (pr == 2 ? 128u : 0u);
+                }
+                if (lane == 0 && blk) {
+                    uint32_t best = 0;
+                    if (cst[1] < cst[best]) best = 1;
+                    if (cst[2] < cst[best]) best = 2;
+                    choice[b] = (uint8_t)best;
+                    if (costs) {
+                        costs[3 * (uint64_t)b] = cst[0];
+                        costs[3 * (uint64_t)b + 1] = cst[1];
+                        costs[3 * (uint64_t)b + 2] = cst[2];
+                    }
+                }
+            } else {
+                residual(PRED ? (fixed_pred >= 0 ? (uint32_t)fixed_pred : (blk ? (uint32_t)bpred[b] : 0u)) : 0u);
+            }
+        }
+        if (MODE == kQuantTrial) {
+            __syncthreads();
+            continue;
         }
         // codes: residuals in (-512, 512) -> residual + 512, otherwise 0
         uint32_t code[8];
@@ -352,6 +503,7 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
         }
         __syncthreads();
     }
+    if (MODE == kQuantTrial) return;
     __syncthreads();
     for (uint32_t i = t; i < (uint32_t)kBins; i += 256)
         if (H[i]) atomicAdd(&hist_g[i], H[i]);
@@ -359,30 +511,64 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
 
 // ------------------------------------------------------------ launchers
 void launch_reset(hipStream_t st, Misc* misc, uint32_t* hist, uint64_t* d1, uint32_t n1, uint64_t* d2,
-                  uint32_t n2) {
+                  uint32_t n2, uint64_t* d3, uint32_t n3, uint64_t off_chunks, uint64_t off_stream, uint64_t nreg) {
     uint32_t n = n1 > n2 ? n1 : n2;
+    if (n3 > n) n = n3;
     uint32_t grid = (n + 255) / 256;
     if (grid < 4) grid = 4;
     if (grid > 1024) grid = 1024;
-    hipLaunchKernelGGL(k_reset, dim3(grid), dim3(256), 0, st, misc, hist, d1, n1, d2, n2);
+    hipLaunchKernelGGL(k_reset, dim3(grid), dim3(256), 0, st, misc, hist, d1, n1, d2, n2, d3, n3, off_chunks,
+                       off_stream, nreg);
 }
 
 void launch_minmax(hipStream_t st, const float* x, uint64_t N, int vec, Misc* misc, int grid) {
     hipLaunchKernelGGL(k_minmax, dim3(grid), dim3(256), 0, st, x, N, vec, misc);
 }
 
+#define FZ_QUANT(NDV, MV)                                                                                        \
+    hipLaunchKernelGGL((k_quant<NDV, MV>), dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, hist, codes, \
+                       ntiles, tile_cnt, opos, oval, ppos, pbits, fixed_pred, bpred, coef, cw_ref, choice, costs)
+
 void launch_quant(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
                   Misc* misc, uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt, uint32_t* opos,
-                  int32_t* oval, uint32_t* ppos, uint32_t* pbits) {
-    if (g.ndim == 3)
-        hipLaunchKernelGGL(k_quant<3>, dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, hist, codes, ntiles,
-                           tile_cnt, opos, oval, ppos, pbits);
-    else if (g.ndim == 2)
-        hipLaunchKernelGGL(k_quant<2>, dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, hist, codes, ntiles,
-                           tile_cnt, opos, oval, ppos, pbits);
-    else
-        hipLaunchKernelGGL(k_quant<1>, dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, hist, codes, ntiles,
-                           tile_cnt, opos, oval, ppos, pbits);
+                  int32_t* oval, uint32_t* ppos, uint32_t* pbits, int fixed_pred, const uint8_t* bpred,
+                  int32_t* coef) {
+    const uint32_t* cw_ref = nullptr;
+    uint8_t* choice = nullptr;
+    uint32_t* costs = nullptr;
+    const bool pred = fixed_pred != 0;
+    if (g.ndim == 3) {
+        if (pred) FZ_QUANT(3, kQuantPred); else FZ_QUANT(3, kQuantP0);
+    } else if (g.ndim == 2) {
+        if (pred) FZ_QUANT(2, kQuantPred); else FZ_QUANT(2, kQuantP0);
+    } else {
+        if (pred) FZ_QUANT(1, kQuantPred); else FZ_QUANT(1, kQuantP0);
+    }
+}
+
+void launch_trial(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
+                  Misc* misc, uint32_t ntiles, const uint32_t* cw_ref, uint8_t* choice, uint32_t* costs) {
+    uint32_t* hist = nullptr;
+    uint16_t* codes = nullptr;
+    uint32_t *tile_cnt = nullptr, *opos = nullptr, *ppos = nullptr, *pbits = nullptr;
+    int32_t *oval = nullptr, *coef = nullptr;
+    const uint8_t* bpred = nullptr;
+    const int fixed_pred = -1;
+    if (g.ndim == 3) FZ_QUANT(3, kQuantTrial);
+    else if (g.ndim == 2) FZ_QUANT(2, kQuantTrial);
+    else FZ_QUANT(1, kQuantTrial);
+}
+#undef FZ_QUANT
+
+__global__ void k_fill32(uint32_t* p, uint64_t n, uint32_t v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+void launch_fill32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v) {
+    uint64_t grid = (n + 255) / 256;
+    if (grid > 1024) grid = 1024;
+    if (grid) hipLaunchKernelGGL(k_fill32, dim3((uint32_t)grid), dim3(256), 0, st, p, n, v);
 }
 
 }  // namespace fz

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libfz.so")
 HEADER_PATH = os.path.join(os.path.dirname(HERE), "include", "fz.h")
 
 EB_ABS, EB_REL = 0, 1
+PRED_LORENZO1, PRED_LORENZO2, PRED_REGRESSION, PRED_AUTO_MLP, PRED_AUTO_TRIAL = 0, 1, 2, 3, 4
 HDR_BYTES = 128
 
 STATUS = {
@@ -98,12 +99,12 @@ def _check(rc: int, what: str):
         raise FZError(rc, what)
 
 
-def params_for(shape, eb: float, mode: int = EB_REL) -> Params:
+def params_for(shape, eb: float, mode: int = EB_REL, pred: int = PRED_LORENZO1) -> Params:
     nd = len(shape)
     if nd < 1 or nd > 3:
         raise ValueError("fields have 1 to 3 dimensions")
     dims = list(reversed([int(s) for s in shape])) + [1] * (3 - nd)
-    return Params(nd, (ctypes.c_uint64 * 3)(*dims), int(mode), float(eb), 0, 512)
+    return Params(nd, (ctypes.c_uint64 * 3)(*dims), int(mode), float(eb), int(pred), 512)
 
 
 def header_fields(hdr: bytes) -> dict:
@@ -118,7 +119,7 @@ def header_fields(hdr: bytes) -> dict:
                 eb=ctypes.c_double.from_buffer_copy(b[48:56]).value,
                 eb_abs=ctypes.c_double.from_buffer_copy(b[56:64]).value, total=u(64, 8),
                 nblocks=u(72, 4), n_outliers=u(76, 4), n_patches=u(80, 4), stream_words=u(84, 4),
-                stream_bits=u(88, 8))
+                stream_bits=u(88, 8), pred=u(12, 4), n_reg=u(96, 4))
 
 
 def shape_of(p: Params):
@@ -159,11 +160,12 @@ class Context:
     def compress_bound(self, shape) -> int:
         return int(lib().fz_compress_bound(ctypes.byref(params_for(shape, 1.0))))
 
-    def compress(self, x: torch.Tensor, eb: float, mode: int = EB_REL, out: torch.Tensor | None = None) -> torch.Tensor:
+    def compress(self, x: torch.Tensor, eb: float, mode: int = EB_REL, out: torch.Tensor | None = None,
+                 pred: int = PRED_LORENZO1) -> torch.Tensor:
         """Compress a float32 device field; returns a uint8 device tensor (view of `out`)."""
         if x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous():
             raise ValueError("x must be a contiguous float32 device tensor")
-        p = params_for(x.shape, eb, mode)
+        p = params_for(x.shape, eb, mode, pred)
         cap = self.compress_bound(x.shape)
         if cap == 0:
             raise FZError(-1, "fz_compress_bound")
