@@ -67,6 +67,16 @@ def lib():
         L.orc_trial.argtypes = [vp, ctypes.c_int, u64p, ctypes.c_int, ctypes.c_double, vp, vp]
         L.orc_encode_symbols.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_int, vp]
         L.orc_encode_symbols.restype = ctypes.c_uint64
+        L.orc_features.argtypes = [vp, ctypes.c_int, u64p, ctypes.c_int, ctypes.c_double, vp]
+        L.orc_features_q.argtypes = [vp, ctypes.c_int, u64p, vp]
+        L.orc_mlp_nparam.argtypes = []
+        L.orc_mlp_infer.argtypes = [vp, vp, ctypes.c_uint64, vp, vp]
+        L.orc_mlp_infer.restype = None
+        L.orc_mlp_loss_grad.argtypes = [vp, vp, vp, ctypes.c_uint64, vp]
+        L.orc_mlp_loss_grad.restype = ctypes.c_double
+        L.orc_adam_step.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double]
+        L.orc_adam_step.restype = None
         _lib = L
     return _lib
 
@@ -271,3 +281,76 @@ def encode_symbols(syms, lengths):
     words = np.zeros(nbits_max // 32 + 2, np.uint32)
     nb = lib().orc_encode_symbols(_ptr(syms), syms.size, _ptr(lengths), lengths.size, _ptr(words))
     return words[: (nb + 31) // 32], int(nb)
+
+
+# ------------------------------------------------------------ selector
+NFEAT, NHID, NOUT = 16, 64, 3
+OFF = {}
+_o = 0
+for _name, _n in (("mu", NFEAT), ("rs", NFEAT), ("W1", NHID * NFEAT), ("b1", NHID), ("W2", NHID * NHID),
+                  ("b2", NHID), ("W3", NOUT * NHID), ("b3", NOUT)):
+    OFF[_name] = (_o, _n)
+    _o += _n
+NPARAM = _o
+
+
+def features(x, eb, mode=1):
+    """Block features (nblocks, 16) float32 of a float32 field."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    nd, d = dims_of(x.shape)
+    f = np.zeros((nblocks_of(x.shape), NFEAT), np.float32)
+    rc = lib().orc_features(_ptr(x), nd, d, int(mode), float(eb), _ptr(f))
+    if rc:
+        raise OracleError(rc)
+    return f
+
+
+def features_q(q):
+    """Block features of a grid-value field q (int32)."""
+    q = np.ascontiguousarray(q, dtype=np.int32)
+    nd, d = dims_of(q.shape)
+    f = np.zeros((nblocks_of(q.shape), NFEAT), np.float32)
+    rc = lib().orc_features_q(_ptr(q), nd, d, _ptr(f))
+    if rc:
+        raise OracleError(rc)
+    return f
+
+
+def pack_params(**parts):
+    """Parameter vector from named parts (missing parts are zero)."""
+    w = np.zeros(NPARAM, np.float64)
+    for k, v in parts.items():
+        o, n = OFF[k]
+        w[o:o + n] = np.asarray(v, np.float64).reshape(-1)
+    return w
+
+
+def mlp_infer(w, feat):
+    """float32 inference: (y (n, 3) float32, choice (n,) uint8)."""
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    assert w.size == NPARAM
+    feat = np.ascontiguousarray(feat, dtype=np.float32).reshape(-1, NFEAT)
+    n = feat.shape[0]
+    y = np.zeros((n, NOUT), np.float32)
+    ch = np.zeros(n, np.uint8)
+    lib().orc_mlp_infer(_ptr(w), _ptr(feat), n, _ptr(y), _ptr(ch))
+    return y, ch
+
+
+def mlp_loss_grad(w, feat, target, with_grad=True):
+    """Double-precision MSE loss and gradient (NPARAM,)."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    feat = np.ascontiguousarray(feat, dtype=np.float32).reshape(-1, NFEAT)
+    target = np.ascontiguousarray(target, dtype=np.float64).reshape(-1, NOUT)
+    g = np.zeros(NPARAM, np.float64) if with_grad else None
+    loss = lib().orc_mlp_loss_grad(_ptr(w), _ptr(feat), _ptr(target), feat.shape[0],
+                                   _ptr(g) if g is not None else None)
+    return loss, g
+
+
+def adam_step(w, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step in place on float64 arrays."""
+    for a in (w, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    lib().orc_adam_step(_ptr(w), _ptr(m), _ptr(v), _ptr(g), int(t), lr, b1, b2, eps)

@@ -1004,3 +1004,280 @@ uint64_t orc_encode_symbols(const uint16_t *syms, uint64_t n, const uint8_t *len
     free(cw);
     return bw.nbits;
 }
+
+/* ------------------------------------------------ block features
+ * Sixteen statistics of each block's prequantised values q (its real
+ * points only), the input of the learned predictor selector.  The paper
+ * leaves automatic predictor choice to future work (Sec. 5); this feature
+ * set (version 1) is this project's reading.  Every feature is built from
+ * exact integer sums with the same IEEE operations on any machine: one
+ * double division, rounding to float, then plog2(1 + v), the
+ * piecewise-linear base-2 logarithm read from the float's bits (integer
+ * subtraction, one int-to-float rounding, a multiplication by 2^-23).
+ *   0      plog2(1 + variance of q)
+ *   1      plog2(1 + max q - min q)
+ *   2, 3, 4   plog2(1 + mean |first difference|) along x, y, z
+ *   5, 6, 7   plog2(1 + mean |second difference|) along x, y, z
+ *   8, 9, 10  plog2(1 + mean |mixed difference|) in xy, yz, xz
+ *   11     plog2(1 + mean |first-order Lorenzo residual|)
+ *   12     plog2(1 + max |first-order Lorenzo residual|)
+ *   13     fraction of first-order residuals outside the code range
+ *   14     plog2(1 + mean |second-order Lorenzo residual|)
+ *   15     plog2(1 + mean |regression residual|)
+ * Differences use point pairs (triples) inside the block; a mean over no
+ * pairs is 0.  Lorenzo residuals take neighbours outside the block as 0,
+ * exactly as the predictors do.                                          */
+#define ORC_NFEAT 16
+
+static float plog2_1p(double v) {
+    float f = (float)v;
+    float a = 1.0f + f;
+    uint32_t u;
+    memcpy(&u, &a, 4);
+    return (float)(int32_t)(u - 0x3F800000u) * (1.0f / 8388608.0f);
+}
+
+static double mean_of(int64_t s, int64_t n) { return n > 0 ? (double)s / (double)n : 0.0; }
+
+static void block_features(const geom_t *g, const int32_t *q, uint64_t b, float *f) {
+    uint64_t bc[3];
+    int ext[3];
+    block_coords(g, b, bc, ext);
+    uint64_t o[3] = {bc[0] * g->bs[0], bc[1] * g->bs[1], bc[2] * g->bs[2]};
+    int64_t n = (int64_t)ext[0] * ext[1] * ext[2];
+    int64_t s1 = 0, s2 = 0, lo = INT64_MAX, hi = INT64_MIN;
+    int64_t d1[3] = {0, 0, 0}, c1[3] = {0, 0, 0}, d2[3] = {0, 0, 0}, c2[3] = {0, 0, 0};
+    int64_t dm[3] = {0, 0, 0}, cm[3] = {0, 0, 0};
+    int64_t r0 = 0, r0max = 0, nout = 0, r1 = 0, r2 = 0;
+    int32_t coef[4];
+    regression_coeffs(g, q, b, coef);
+#define Q(lx, ly, lz) ((int64_t)q[rm(g, o[0] + (lx), o[1] + (ly), o[2] + (lz))])
+    for (int lz = 0; lz < ext[2]; lz++)
+        for (int ly = 0; ly < ext[1]; ly++)
+            for (int lx = 0; lx < ext[0]; lx++) {
+                int64_t v = Q(lx, ly, lz);
+                int l[3] = {lx, ly, lz};
+                s1 += v;
+                s2 += v * v;
+                if (v < lo) lo = v;
+                if (v > hi) hi = v;
+                for (int a = 0; a < 3; a++) {
+                    int e[3] = {0, 0, 0};
+                    e[a] = 1;
+                    if (l[a] >= 1) {
+                        d1[a] += llabs(v - Q(lx - e[0], ly - e[1], lz - e[2]));
+                        c1[a]++;
+                    }
+                    if (l[a] >= 2) {
+                        d2[a] += llabs(v - 2 * Q(lx - e[0], ly - e[1], lz - e[2]) +
+                                       Q(lx - 2 * e[0], ly - 2 * e[1], lz - 2 * e[2]));
+                        c2[a]++;
+                    }
+                }
+                /* mixed differences: xy, yz, xz */
+                int pa[3][2] = {{0, 1}, {1, 2}, {0, 2}};
+                for (int m = 0; m < 3; m++) {
+                    int a0 = pa[m][0], a1 = pa[m][1];
+                    if (l[a0] >= 1 && l[a1] >= 1) {
+                        int e0[3] = {0, 0, 0}, e1[3] = {0, 0, 0};
+                        e0[a0] = 1;
+                        e1[a1] = 1;
+                        dm[m] += llabs(v - Q(lx - e0[0], ly - e0[1], lz - e0[2]) -
+                                       Q(lx - e1[0], ly - e1[1], lz - e1[2]) +
+                                       Q(lx - e0[0] - e1[0], ly - e0[1] - e1[1], lz - e0[2] - e1[2]));
+                        cm[m]++;
+                    }
+                }
+                uint64_t x = o[0] + lx, y = o[1] + ly, z = o[2] + lz;
+                int64_t d0 = residual_at(g, q, x, y, z, ORC_P0, coef);
+                int64_t ad0 = llabs(d0);
+                r0 += ad0;
+                if (ad0 > r0max) r0max = ad0;
+                if (d0 <= -ORC_RADIUS || d0 >= ORC_RADIUS) nout++;
+                r1 += llabs((int64_t)residual_at(g, q, x, y, z, ORC_P1, coef));
+                r2 += llabs((int64_t)residual_at(g, q, x, y, z, ORC_P2, coef));
+            }
+#undef Q
+    double m = (double)s1 / (double)n;
+    double var = (double)s2 / (double)n - m * m;
+    if (var < 0.0) var = 0.0;
+    f[0] = plog2_1p(var);
+    f[1] = plog2_1p((double)(hi - lo));
+    for (int a = 0; a < 3; a++) {
+        f[2 + a] = plog2_1p(mean_of(d1[a], c1[a]));
+        f[5 + a] = plog2_1p(mean_of(d2[a], c2[a]));
+        f[8 + a] = plog2_1p(mean_of(dm[a], cm[a]));
+    }
+    f[11] = plog2_1p(mean_of(r0, n));
+    f[12] = plog2_1p((double)r0max);
+    f[13] = (float)((double)nout / (double)n);
+    f[14] = plog2_1p(mean_of(r1, n));
+    f[15] = plog2_1p(mean_of(r2, n));
+}
+
+/* Features of every block (block order), f[16 * nblocks]. */
+int orc_features(const float *x, int ndim, const uint64_t dims[3], int mode, double eb, float *feat) {
+    geom_t g;
+    int rc = make_geom(ndim, dims, &g);
+    if (rc) return rc;
+    double eb_abs;
+    rc = orc_eb_abs(x, g.N, mode, eb, &eb_abs);
+    if (rc) return rc;
+    int32_t *q = (int32_t *)malloc(sizeof(int32_t) * g.N);
+    uint8_t *patch = (uint8_t *)malloc(g.N);
+    if (!q || !patch) { free(q); free(patch); return ORC_ERR_NOMEM; }
+    orc_prequant(x, g.N, eb_abs, q, patch);
+    for (uint64_t b = 0; b < g.nblocks; b++) block_features(&g, q, b, feat + ORC_NFEAT * b);
+    free(q);
+    free(patch);
+    return ORC_OK;
+}
+
+/* Same, from a grid-value field q (tests). */
+int orc_features_q(const int32_t *q, int ndim, const uint64_t dims[3], float *feat) {
+    geom_t g;
+    int rc = make_geom(ndim, dims, &g);
+    if (rc) return rc;
+    for (uint64_t b = 0; b < g.nblocks; b++) block_features(&g, q, b, feat + ORC_NFEAT * b);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------ selector network
+ * A multilayer perceptron 16 -> 64 -> 64 -> 3 with ReLU hidden layers
+ * predicts log2(1 + bits) of each predictor for a block from its
+ * standardised features; the block takes the predictor with the smallest
+ * prediction, ties to the lower index.  Parameter vector (floats, in this
+ * order): mu[16], rs[16] (standardisation z = (f - mu) * rs), W1[64][16],
+ * b1[64], W2[64][64], b2[64], W3[3][64], b3[3].
+ * Inference is in float with every product and sum rounded separately
+ * (no fused multiply-add), dot products summed in index order starting
+ * from the bias, so that any IEEE machine gets the same bits.            */
+#define ORC_H 64
+#define ORC_NOUT 3
+#define OFF_MU 0
+#define OFF_RS (OFF_MU + ORC_NFEAT)
+#define OFF_W1 (OFF_RS + ORC_NFEAT)
+#define OFF_B1 (OFF_W1 + ORC_H * ORC_NFEAT)
+#define OFF_W2 (OFF_B1 + ORC_H)
+#define OFF_B2 (OFF_W2 + ORC_H * ORC_H)
+#define OFF_W3 (OFF_B2 + ORC_H)
+#define OFF_B3 (OFF_W3 + ORC_NOUT * ORC_H)
+#define ORC_NPARAM (OFF_B3 + ORC_NOUT)
+
+int orc_mlp_nparam(void) { return ORC_NPARAM; }
+
+void orc_mlp_infer(const float *w, const float *feat, uint64_t n, float *y, uint8_t *choice) {
+    for (uint64_t s = 0; s < n; s++) {
+        const float *f = feat + ORC_NFEAT * s;
+        float z[ORC_NFEAT], h1[ORC_H], h2[ORC_H], o[ORC_NOUT];
+        for (int i = 0; i < ORC_NFEAT; i++) {
+            float d = f[i] - w[OFF_MU + i];
+            z[i] = d * w[OFF_RS + i];
+        }
+        for (int j = 0; j < ORC_H; j++) {
+            float acc = w[OFF_B1 + j];
+            for (int i = 0; i < ORC_NFEAT; i++) {
+                float p = w[OFF_W1 + ORC_NFEAT * j + i] * z[i];
+                acc = acc + p;
+            }
+            h1[j] = acc > 0.0f ? acc : 0.0f;
+        }
+        for (int j = 0; j < ORC_H; j++) {
+            float acc = w[OFF_B2 + j];
+            for (int i = 0; i < ORC_H; i++) {
+                float p = w[OFF_W2 + ORC_H * j + i] * h1[i];
+                acc = acc + p;
+            }
+            h2[j] = acc > 0.0f ? acc : 0.0f;
+        }
+        for (int k = 0; k < ORC_NOUT; k++) {
+            float acc = w[OFF_B3 + k];
+            for (int i = 0; i < ORC_H; i++) {
+                float p = w[OFF_W3 + ORC_H * k + i] * h2[i];
+                acc = acc + p;
+            }
+            o[k] = acc;
+        }
+        int best = 0;
+        for (int k = 1; k < ORC_NOUT; k++)
+            if (o[k] < o[best]) best = k;
+        if (y)
+            for (int k = 0; k < ORC_NOUT; k++) y[ORC_NOUT * s + k] = o[k];
+        if (choice) choice[s] = (uint8_t)best;
+    }
+}
+
+/* Mean squared error over n samples and the three outputs, and its
+ * gradient with respect to every parameter (mu and rs get 0: they are set
+ * from the training features, not learned), in double by plain
+ * backpropagation:
+ *   L = 1 / (3 n) * sum_s sum_k (y_sk - t_sk)^2
+ *   dL/dy = 2 (y - t) / (3 n); dL/dW = delta^T * activations; ReLU passes
+ *   the gradient where its input is > 0.                                 */
+double orc_mlp_loss_grad(const double *w, const float *feat, const double *target, uint64_t n, double *grad) {
+    double loss = 0.0;
+    if (grad) memset(grad, 0, sizeof(double) * ORC_NPARAM);
+    for (uint64_t s = 0; s < n; s++) {
+        const float *f = feat + ORC_NFEAT * s;
+        double z[ORC_NFEAT], a1[ORC_H], h1[ORC_H], a2[ORC_H], h2[ORC_H], dy[ORC_NOUT];
+        double dh2[ORC_H], dh1[ORC_H];
+        for (int i = 0; i < ORC_NFEAT; i++) z[i] = ((double)f[i] - w[OFF_MU + i]) * w[OFF_RS + i];
+        for (int j = 0; j < ORC_H; j++) {
+            double acc = w[OFF_B1 + j];
+            for (int i = 0; i < ORC_NFEAT; i++) acc += w[OFF_W1 + ORC_NFEAT * j + i] * z[i];
+            a1[j] = acc;
+            h1[j] = acc > 0.0 ? acc : 0.0;
+        }
+        for (int j = 0; j < ORC_H; j++) {
+            double acc = w[OFF_B2 + j];
+            for (int i = 0; i < ORC_H; i++) acc += w[OFF_W2 + ORC_H * j + i] * h1[i];
+            a2[j] = acc;
+            h2[j] = acc > 0.0 ? acc : 0.0;
+        }
+        for (int k = 0; k < ORC_NOUT; k++) {
+            double acc = w[OFF_B3 + k];
+            for (int i = 0; i < ORC_H; i++) acc += w[OFF_W3 + ORC_H * k + i] * h2[i];
+            double e = acc - target[ORC_NOUT * s + k];
+            loss += e * e;
+            dy[k] = 2.0 * e / (3.0 * (double)n);
+        }
+        if (!grad) continue;
+        for (int k = 0; k < ORC_NOUT; k++) {
+            grad[OFF_B3 + k] += dy[k];
+            for (int i = 0; i < ORC_H; i++) grad[OFF_W3 + ORC_H * k + i] += dy[k] * h2[i];
+        }
+        for (int i = 0; i < ORC_H; i++) {
+            double acc = 0.0;
+            for (int k = 0; k < ORC_NOUT; k++) acc += dy[k] * w[OFF_W3 + ORC_H * k + i];
+            dh2[i] = a2[i] > 0.0 ? acc : 0.0;
+        }
+        for (int j = 0; j < ORC_H; j++) {
+            grad[OFF_B2 + j] += dh2[j];
+            for (int i = 0; i < ORC_H; i++) grad[OFF_W2 + ORC_H * j + i] += dh2[j] * h1[i];
+        }
+        for (int i = 0; i < ORC_H; i++) {
+            double acc = 0.0;
+            for (int j = 0; j < ORC_H; j++) acc += dh2[j] * w[OFF_W2 + ORC_H * j + i];
+            dh1[i] = a1[i] > 0.0 ? acc : 0.0;
+        }
+        for (int j = 0; j < ORC_H; j++) {
+            grad[OFF_B1 + j] += dh1[j];
+            for (int i = 0; i < ORC_NFEAT; i++) grad[OFF_W1 + ORC_NFEAT * j + i] += dh1[j] * z[i];
+        }
+    }
+    return loss / (3.0 * (double)n);
+}
+
+/* One Adam step (Kingma and Ba) on the learned parameters (W1 onwards),
+ * step number t >= 1:
+ *   m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) g^2
+ *   w -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)           */
+void orc_adam_step(double *w, double *m, double *v, const double *g, int t, double lr, double b1, double b2,
+                   double eps) {
+    double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
+    for (int i = OFF_W1; i < ORC_NPARAM; i++) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        w[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
+}

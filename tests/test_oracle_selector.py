@@ -1,0 +1,225 @@
+"""Pins of the oracle's block features, selector network and training
+arithmetic against closed forms, hand-built networks, finite differences
+and the first Adam step."""
+import numpy as np
+import pytest
+
+import oracle
+
+F = oracle.NFEAT
+
+
+def _plog2_1p(v):
+    # piecewise-linear log2 of (1 + v): exponent + mantissa fraction of the
+    # float 1 + v, the sum rounded to float as one int-to-float conversion
+    a = np.float32(1.0) + np.float32(v)
+    m, e = np.frexp(np.float64(a))  # a = m 2^e, m in [0.5, 1)
+    exact = (e - 1) + (2 * m - 1)  # multiple of 2^-23
+    return np.float32(np.float32(exact * 2.0 ** 23) * np.float32(2.0 ** -23))
+
+
+def test_plog2_closed_forms():
+    q = np.zeros((8, 8, 8), np.int32)
+    for v, want in [(0, 0.0), (1, 1.0), (2, 1.5), (3, 2.0), (5.25, 2.5625), (7, 3.0), (1023, 10.0)]:
+        assert _plog2_1p(v) == want
+    f = oracle.features_q(q)
+    assert np.all(f == 0)
+
+
+def test_ramp_x_3d():
+    """q = lx in every 8^3 block: variance 63/12, range 7, unit first
+    differences along x only, no curvature, exact plane fit."""
+    lx = np.arange(16, dtype=np.int32) % 8
+    q = np.broadcast_to(lx, (8, 16, 16)).copy()
+    f = oracle.features_q(q)
+    assert f.shape == (4, F)
+    for b in range(4):
+        assert f[b, 0] == _plog2_1p(63 / 12) == 2.5625
+        assert f[b, 1] == 3.0
+        assert f[b, 2] == 1.0 and f[b, 3] == 0 and f[b, 4] == 0
+        assert np.all(f[b, 5:11] == 0)
+        assert f[b, 15] == 0.0  # the regression plane fits exactly
+
+
+def test_quadratic_y_2d():
+    """q = ly^2 (2D, 32x16 blocks): first differences 2 ly - 1 have mean 15
+    along y, second differences are 2, nothing along x."""
+    ly = np.arange(16, dtype=np.int64) ** 2
+    q = np.broadcast_to(ly[:, None], (16, 32)).astype(np.int32).copy()
+    f = oracle.features_q(q)
+    assert f.shape == (1, F)
+    assert f[0, 2] == 0.0 and f[0, 3] == _plog2_1p(15.0)
+    assert f[0, 5] == 0.0 and f[0, 6] == _plog2_1p(2.0) == 1.5
+    assert f[0, 4] == 0 and f[0, 7] == 0 and np.all(f[0, 8:11] == 0)
+
+
+def test_mixed_difference_xy():
+    """q = lx * ly: the mixed xy difference is 1 everywhere it is defined,
+    the yz and xz ones vanish."""
+    l = np.arange(8)
+    q = np.broadcast_to(l[None, :, None] * l[None, None, :], (8, 8, 8)).astype(np.int32).copy()
+    f = oracle.features_q(q)
+    assert f[0, 8] == 1.0 and f[0, 9] == 0 and f[0, 10] == 0
+
+
+def test_constant_block_residual_features():
+    """A constant c: only the block's first point has a first-order residual
+    (c, zero outside the block); the plane fits exactly; c >= 512 is one
+    outlier in 512 values."""
+    for c in (3, 700, -900):
+        q = np.full((8, 8, 8), c, np.int32)
+        f = oracle.features_q(q)[0]
+        assert f[0] == 0 and f[1] == 0
+        assert f[11] == _plog2_1p(abs(c) / 512)
+        assert f[12] == _plog2_1p(abs(c))
+        assert f[13] == np.float32((abs(c) >= 512) / 512)
+        assert f[15] == 0.0
+
+
+def test_residual_features_match_residual_fields():
+    """Residual features of random blocks equal the means of the oracle's
+    own residual fields (pinned elsewhere), block by block, ragged edges
+    included."""
+    r = np.random.default_rng(5)
+    for shape in [(11, 13, 9), (20, 45), (1100,)]:
+        q = r.integers(-2000, 2000, size=shape).astype(np.int32)
+        f = oracle.features_q(q)
+        d0, _ = oracle.residual(q, oracle.P0)
+        d1, _ = oracle.residual(q, oracle.P1)
+        d2, _ = oracle.residual(q, oracle.P2)
+        bs = {1: (512,), 2: (16, 32), 3: (8, 8, 8)}[len(shape)]
+        nb = [-(-s // b) for s, b in zip(shape, bs)]
+        k = 0
+        for idx in np.ndindex(*nb):
+            sl = tuple(slice(i * b, (i + 1) * b) for i, b in zip(idx, bs))
+            blk = q[sl].astype(np.int64)
+            assert f[k, 11] == _plog2_1p(np.abs(d0[sl]).astype(np.int64).sum() / blk.size)
+            assert f[k, 12] == _plog2_1p(np.abs(d0[sl]).max())
+            assert f[k, 13] == np.float32(np.count_nonzero(np.abs(d0[sl]) >= 512) / blk.size)
+            assert f[k, 14] == _plog2_1p(np.abs(d1[sl]).astype(np.int64).sum() / blk.size)
+            assert f[k, 15] == _plog2_1p(np.abs(d2[sl]).astype(np.int64).sum() / blk.size)
+            assert f[k, 1] == _plog2_1p(blk.max() - blk.min())
+            k += 1
+        # block order: x fastest (numpy's last axis)
+        assert k == f.shape[0]
+
+
+def test_features_from_field_use_prequantised_values():
+    x = (np.arange(8, dtype=np.float32)[None, None, :] * np.ones((8, 8, 1), np.float32)) * 0.02
+    f = oracle.features(x, 0.01, 0)  # step 0.02: q = lx
+    assert f[0, 0] == 2.5625 and f[0, 2] == 1.0
+
+
+def _net_permutation():
+    """z = f; h1_j = relu(z_j) (j < 16); h2_j = h1_{(j + 1) mod 16}
+    (j < 16); y_k = h2 at index (11, 14, 15)[k] - 1 (mod 16)."""
+    W1 = np.zeros((64, 16))
+    W1[np.arange(16), np.arange(16)] = 1
+    W2 = np.zeros((64, 64))
+    W2[np.arange(16), (np.arange(16) + 1) % 16] = 1
+    W3 = np.zeros((3, 64))
+    for k, i in enumerate((11, 14, 15)):
+        W3[k, (i - 1) % 16] = 1
+    return oracle.pack_params(mu=np.zeros(16), rs=np.ones(16), W1=W1, W2=W2, W3=W3)
+
+
+def test_mlp_permutation_network():
+    r = np.random.default_rng(1)
+    feat = r.uniform(0, 10, size=(50, 16)).astype(np.float32)
+    y, ch = oracle.mlp_infer(_net_permutation(), feat)
+    want = feat[:, [11, 14, 15]]
+    assert np.array_equal(y, want)
+    assert np.array_equal(ch, np.argmin(want, axis=1))
+
+
+def test_mlp_bias_only_ties_lowest():
+    feat = np.ones((3, 16), np.float32)
+    for b3, c in [((1, 1, 0), 2), ((0, 0, 1), 0), ((2, 1, 1), 1), ((5, 5, 5), 0)]:
+        y, ch = oracle.mlp_infer(oracle.pack_params(b3=b3), feat)
+        assert np.all(ch == c) and np.all(y == np.float32(b3))
+
+
+def test_mlp_standardisation_and_relu():
+    """mu/rs shift and scale; a negative pre-activation is cut by the ReLU."""
+    W1 = np.zeros((64, 16))
+    W1[0, 3] = 1.0
+    W1[1, 3] = -1.0
+    W2 = np.zeros((64, 64))
+    W2[0, 0] = 1.0
+    W2[1, 1] = 1.0
+    W3 = np.zeros((3, 64))
+    W3[0, 0] = 1.0
+    W3[1, 1] = 1.0
+    mu = np.zeros(16)
+    mu[3] = 2.0
+    rs = np.ones(16)
+    rs[3] = 0.5
+    w = oracle.pack_params(mu=mu, rs=rs, W1=W1, W2=W2, W3=W3, b3=(0, 0, 0.25))
+    feat = np.zeros((2, 16), np.float32)
+    feat[0, 3] = 6.0  # z = 2: y = (2, 0, .25)
+    feat[1, 3] = 0.0  # z = -1: y = (0, 1, .25)
+    y, ch = oracle.mlp_infer(w, feat)
+    assert y.tolist() == [[2.0, 0.0, 0.25], [0.0, 1.0, 0.25]]
+    assert ch.tolist() == [1, 0]
+
+
+def _random_net(seed):
+    r = np.random.default_rng(seed)
+    w = r.normal(0, 0.3, oracle.NPARAM)
+    o, n = oracle.OFF["mu"]
+    w[o:o + n] = r.uniform(0, 1, n)
+    o, n = oracle.OFF["rs"]
+    w[o:o + n] = r.uniform(0.5, 2, n)
+    return w
+
+
+def test_loss_closed_form_zero_weights():
+    feat = np.random.default_rng(2).uniform(0, 5, (7, 16)).astype(np.float32)
+    t = np.random.default_rng(3).uniform(0, 12, (7, 3))
+    b3 = np.array([1.0, 2.0, 3.0])
+    loss, g = oracle.mlp_loss_grad(oracle.pack_params(b3=b3), feat, t)
+    assert loss == pytest.approx(np.mean((b3[None, :] - t) ** 2), rel=1e-14)
+    o, n = oracle.OFF["b3"]
+    assert np.allclose(g[o:o + n], 2 * (b3[None, :] - t).sum(0) / (3 * 7), rtol=1e-13)
+
+
+def test_gradient_matches_central_differences():
+    """Every learned parameter of a random network: backpropagated
+    gradient against central differences of the loss."""
+    w = _random_net(7)
+    feat = np.random.default_rng(8).uniform(0, 4, (6, 16)).astype(np.float32)
+    t = np.random.default_rng(9).uniform(0, 10, (6, 3))
+    _, g = oracle.mlp_loss_grad(w, feat, t)
+    h = 1e-6
+    o1 = oracle.OFF["W1"][0]
+    fd = np.zeros(oracle.NPARAM)
+    for i in range(o1, oracle.NPARAM):
+        wp = w.copy()
+        wp[i] += h
+        wm = w.copy()
+        wm[i] -= h
+        fd[i] = (oracle.mlp_loss_grad(wp, feat, t, False)[0] - oracle.mlp_loss_grad(wm, feat, t, False)[0]) / (2 * h)
+    assert np.all(g[:o1] == 0)
+    err = np.abs(g[o1:] - fd[o1:])
+    assert err.max() <= 1e-6 * max(1.0, np.abs(fd).max())
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        o, n = oracle.OFF[name]
+        assert np.any(g[o:o + n] != 0), name
+
+
+def test_adam_first_step_closed_form():
+    """First Adam step: bias corrections make m_hat = g and v_hat = g^2, so
+    every learned weight moves by -lr g / (|g| + eps); mu and rs stay."""
+    w = _random_net(3)
+    g = np.random.default_rng(4).normal(0, 1, oracle.NPARAM)
+    m = np.zeros(oracle.NPARAM)
+    v = np.zeros(oracle.NPARAM)
+    w1 = w.copy()
+    oracle.adam_step(w1, m, v, g, 1, lr=1e-3)
+    o1 = oracle.OFF["W1"][0]
+    assert np.array_equal(w1[:o1], w[:o1])
+    assert np.allclose(w1[o1:] - w[o1:], -1e-3 * g[o1:] / (np.abs(g[o1:]) + 1e-8), rtol=1e-9, atol=1e-15)
+    # second step with the same gradient: m_hat = g, v_hat = g^2 again
+    w2 = w1.copy()
+    oracle.adam_step(w2, m, v, g, 2, lr=1e-3)
+    assert np.allclose(w2[o1:] - w1[o1:], -1e-3 * g[o1:] / (np.abs(g[o1:]) + 1e-8), rtol=1e-9, atol=1e-15)
