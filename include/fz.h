@@ -59,8 +59,9 @@ enum { FZ_EB_ABS = 0, FZ_EB_REL = 1 };
  *  FZ_PRED_LORENZO2   second-order Lorenzo (weights 1, -2, 1 per axis)
  *  FZ_PRED_REGRESSION linear fit per block, 4 int32 coefficients with 8
  *                     fractional bits stored per block
- *  FZ_PRED_AUTO_MLP   per block, chosen by the learned selector (not yet
- *                     available: FZ_ERR_UNSUPPORTED)
+ *  FZ_PRED_AUTO_MLP   per block, chosen by the learned selector network
+ *                     (fz_selector_set / fz_selector_load first, else
+ *                     FZ_ERR_UNSUPPORTED)
  *  FZ_PRED_AUTO_TRIAL per block, the predictor whose codes cost the fewest
  *                     bits under the Huffman code of the first-order
  *                     histogram (+64 bits per outlier, +128 for the
@@ -144,6 +145,62 @@ const char *fz_stage_name(fz_ctx *ctx, int i);
 /* Stage dump for parity checks: the 1024-bin code histogram of the last
  * successful fz_compress call on this context (Sec. 3.2). */
 int fz_last_histogram(fz_ctx *ctx, uint32_t *h_hist);
+
+/* ------------------------------------------------ per-block predictor choice
+ * The paper leaves choosing a predictor per block automatically to future
+ * work (Sec. 5); these calls expose the pieces of that choice.
+ *
+ * Block order: x fastest, then y, then z (block index = bx + nbx (by + nby
+ * bz)); edge blocks are truncated. */
+#define FZ_FEATURES 16          /* features per block                      */
+#define FZ_SELECTOR_PARAMS 5475 /* floats in the selector's parameter set  */
+
+/* Blocks of a field with these dims (0 if invalid). */
+uint64_t fz_block_count(const fz_params *p);
+
+/* The 16 features (version 1) of every block of d_in, computed from the
+ * prequantised values at p's error bound, to d_feat (device, row-major
+ * [nblocks][16] float32, feat_cap >= 16 nblocks floats):
+ *  0 plog2(1 + variance), 1 plog2(1 + max - min),
+ *  2-4 plog2(1 + mean |first difference|) along x, y, z,
+ *  5-7 the same for second differences, 8-10 for mixed differences in xy,
+ *  yz, xz, 11 plog2(1 + mean |first-order residual|), 12 plog2(1 + max
+ *  |first-order residual|), 13 outlier fraction of the first-order
+ *  residuals, 14 plog2(1 + mean |second-order residual|), 15 plog2(1 +
+ *  mean |regression residual|); plog2(1 + v) is the piecewise-linear
+ *  base-2 logarithm read from the bits of the float 1 + v.  Bit-identical
+ *  on any IEEE machine.  Synchronises `stream`. */
+int fz_block_features(fz_ctx *ctx, const fz_params *p, const float *d_in, float *d_feat, uint64_t feat_cap,
+                      void *stream);
+
+/* Run the selector network on every block: d_choice[b] (device, nblocks
+ * bytes) = predictor 0, 1 or 2; d_y (device, nullable, [nblocks][3]
+ * float32) = the network's predicted log2(1 + bits) per predictor.
+ * FZ_ERR_UNSUPPORTED without a selector.  Synchronises `stream`. */
+int fz_block_select(fz_ctx *ctx, const fz_params *p, const float *d_in, uint8_t *d_choice, float *d_y,
+                    void *stream);
+
+/* Exhaustive trial (the FZ_PRED_AUTO_TRIAL choice): d_choice[b] and the
+ * three costs in bits d_costs[3 b + p] (device, nullable).  Synchronises
+ * `stream`. */
+int fz_block_trial(fz_ctx *ctx, const fz_params *p, const float *d_in, uint8_t *d_choice, uint32_t *d_costs,
+                   void *stream);
+
+/* Selector parameters, host float32[FZ_SELECTOR_PARAMS] in this order:
+ * mu[16], rs[16] (standardisation z = (f - mu) * rs), W1[64][16], b1[64],
+ * W2[64][64], b2[64], W3[3][64], b3[3]; hidden layers use ReLU; every dot
+ * product is summed in index order from its bias with separately rounded
+ * products and sums, so that a given parameter set picks the same
+ * predictors on any IEEE machine.  set copies them to the device (all
+ * must be finite); get returns FZ_ERR_UNSUPPORTED if none is set. */
+int fz_selector_set(fz_ctx *ctx, const float *h_params, uint64_t n);
+int fz_selector_get(fz_ctx *ctx, float *h_params, uint64_t n);
+
+/* Selector files: 8 bytes "FZSEL\0\0\0", u32 feature-set version (1),
+ * u32 parameter count, then the parameters (little-endian float32).
+ * load returns FZ_ERR_CORRUPT for a file of another format or version. */
+int fz_selector_save(fz_ctx *ctx, const char *path);
+int fz_selector_load(fz_ctx *ctx, const char *path);
 
 #ifdef __cplusplus
 }

@@ -1,6 +1,7 @@
 // Host implementation of the fz C ABI (include/fz.h): argument validation,
 // scratch management, kernel sequencing on the caller's stream, and the
 // container header on the host side.
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -84,6 +85,9 @@ struct fz_ctx {
     float ms[kMaxStages] = {};
     int nstages = 0;
     bool have_hist = false;
+    // selector network parameters (device copy, kSelectorParams floats)
+    float* sel = nullptr;
+    bool have_sel = false;
 };
 
 namespace {
@@ -135,7 +139,6 @@ int check_params(const fz_params* p, Geom* g) {
     if (p->eb_mode != FZ_EB_ABS && p->eb_mode != FZ_EB_REL) return FZ_ERR_ARG;
     if (!(p->eb > 0.0) || !__builtin_isfinite(p->eb)) return FZ_ERR_EB;
     if (p->pred > FZ_PRED_AUTO_TRIAL) return FZ_ERR_ARG;
-    if (p->pred == FZ_PRED_AUTO_MLP) return FZ_ERR_UNSUPPORTED;
     if (p->radius != 0 && p->radius != (uint32_t)kRadius) return FZ_ERR_UNSUPPORTED;
     return FZ_OK;
 }
@@ -316,6 +319,7 @@ int fz_ctx_create(fz_ctx** out, int device, uint64_t max_elems) {
               hipMalloc((void**)&c->cw, sizeof(uint32_t) * kBins) == hipSuccess &&
               hipMalloc((void**)&c->cw_ref, sizeof(uint32_t) * kBins) == hipSuccess &&
               hipMalloc((void**)&c->lens_ref, kBins / 2) == hipSuccess &&
+              hipMalloc((void**)&c->sel, sizeof(float) * kSelectorParams) == hipSuccess &&
               hipMalloc((void**)&c->lut, sizeof(uint16_t) * kLut) == hipSuccess &&
               hipHostMalloc((void**)&c->h_misc, sizeof(Misc), hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc((void**)&c->h_hdr, kHdr, hipHostMallocDefault) == hipSuccess;
@@ -363,6 +367,7 @@ void fz_ctx_destroy(fz_ctx* c) {
     hipFree(c->costs);
     hipFree(c->cw_ref);
     hipFree(c->lens_ref);
+    hipFree(c->sel);
     hipFree(c->desc_pmap);
     hipFree(c->res);
     if (c->h_misc) hipHostFree(c->h_misc);
@@ -392,6 +397,7 @@ int fz_compress(fz_ctx* c, const fz_params* p, const float* d_in, void* d_out, u
     if (rc) return rc;
     const uint32_t pred = p->pred;
     const bool has_map = pred_has_map(pred);
+    if (pred == FZ_PRED_AUTO_MLP && !c->have_sel) return FZ_ERR_UNSUPPORTED;
     if (pred != FZ_PRED_LORENZO1) {
         rc = ensure_pred(c, g, false);
         if (rc) return rc;
@@ -429,6 +435,10 @@ int fz_compress(fz_ctx* c, const fz_params* p, const float* d_in, void* d_out, u
         launch_trial(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, ntiles, c->cw_ref, c->bpred, c->costs);
         launch_fill32(st, c->hist, kBins, 0);
         t_mark(c, st, "trial");
+    } else if (pred == FZ_PRED_AUTO_MLP) {
+        launch_features(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, ntiles, c->sel, nullptr, nullptr,
+                        c->bpred);
+        t_mark(c, st, "select");
     }
     if (has_map) {
         launch_scan(st, SCAN_PMAP, c->bpred, g.nblocks, c->reg_idx, c->desc_pmap, &c->misc->mtile_ctr, c->misc, 0);
@@ -573,6 +583,164 @@ int fz_decompress(fz_ctx* c, const void* d_in, uint64_t in_bytes, const void* h_
     if (m.code0_count != r.nout) return FZ_ERR_CORRUPT;
     if (has_map && m.nreg != r.nreg) return FZ_ERR_CORRUPT;
     return FZ_OK;
+}
+
+uint64_t fz_block_count(const fz_params* p) {
+    Geom g;
+    if (!p || make_geom(p->ndim, p->dims, &g) != FZ_OK) return 0;
+    return g.nblocks;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Shared set-up of the per-block analysis calls: validation, scratch, the
+// reset and (relative bound) the value range.  Returns the geometry.
+int analysis_begin(fz_ctx* c, const fz_params* p, const float* d_in, hipStream_t st, Geom* g, int* vec,
+                   uint32_t* ntiles, int* grid) {
+    if (!c || !d_in || ((uintptr_t)d_in & 3)) return FZ_ERR_ARG;
+    int rc = check_params(p, g);
+    if (rc) return rc;
+    rc = ensure(c, *g);
+    if (rc) return rc;
+    rc = ensure_pred(c, *g, false);
+    if (rc) return rc;
+    *ntiles = (g->nblocks + kTileBlocks - 1) / kTileBlocks;
+    *vec = (((uintptr_t)d_in & 15) == 0) && (g->ndim == 1 || (g->n[0] & 3) == 0);
+    *grid = (int)(*ntiles < (uint32_t)c->n_cu * 8 ? *ntiles : (uint32_t)c->n_cu * 8);
+    c->have_hist = false;
+    t_begin(c, st);
+    launch_reset(st, c->misc, c->hist, nullptr, 0, nullptr, 0, nullptr, 0, 0, 0, 0);
+    if (p->eb_mode == FZ_EB_REL) {
+        uint64_t work = (g->N + 16 * 256 - 1) / (16 * 256);
+        uint64_t mgrid = work < (uint64_t)c->n_cu * 16 ? work : (uint64_t)c->n_cu * 16;
+        if (mgrid < 1) mgrid = 1;
+        launch_minmax(st, d_in, g->N, (((uintptr_t)d_in & 15) == 0), c->misc, (int)mgrid);
+    }
+    return FZ_OK;
+}
+
+int analysis_end(fz_ctx* c, hipStream_t st) {
+    if (hipMemcpyAsync(c->h_misc, c->misc, sizeof(Misc), hipMemcpyDeviceToHost, st) != hipSuccess) return FZ_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
+    if (hipGetLastError() != hipSuccess) return FZ_ERR_HIP;
+    t_end(c);
+    return flags_status(c->h_misc->flags);
+}
+
+}  // namespace
+
+extern "C" {
+
+int fz_block_features(fz_ctx* c, const fz_params* p, const float* d_in, float* d_feat, uint64_t feat_cap,
+                      void* stream) {
+    Geom g;
+    int vec, grid;
+    uint32_t ntiles;
+    if (!c || !d_feat || ((uintptr_t)d_feat & 3)) return FZ_ERR_ARG;
+    DeviceGuard dg(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    int rc = analysis_begin(c, p, d_in, st, &g, &vec, &ntiles, &grid);
+    if (rc) return rc;
+    if (feat_cap < (uint64_t)g.nblocks * kNFeat) return FZ_ERR_CAPACITY;
+    launch_features(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, ntiles, nullptr, d_feat, nullptr, nullptr);
+    t_mark(c, st, "features");
+    return analysis_end(c, st);
+}
+
+int fz_block_select(fz_ctx* c, const fz_params* p, const float* d_in, uint8_t* d_choice, float* d_y,
+                    void* stream) {
+    Geom g;
+    int vec, grid;
+    uint32_t ntiles;
+    if (!c || !d_choice || ((uintptr_t)d_y & 3)) return FZ_ERR_ARG;
+    if (!c->have_sel) return FZ_ERR_UNSUPPORTED;
+    DeviceGuard dg(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    int rc = analysis_begin(c, p, d_in, st, &g, &vec, &ntiles, &grid);
+    if (rc) return rc;
+    launch_features(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, ntiles, c->sel, nullptr, d_y, d_choice);
+    t_mark(c, st, "select");
+    return analysis_end(c, st);
+}
+
+int fz_block_trial(fz_ctx* c, const fz_params* p, const float* d_in, uint8_t* d_choice, uint32_t* d_costs,
+                   void* stream) {
+    Geom g;
+    int vec, grid;
+    uint32_t ntiles;
+    if (!c || !d_choice || ((uintptr_t)d_costs & 3)) return FZ_ERR_ARG;
+    DeviceGuard dg(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    int rc = analysis_begin(c, p, d_in, st, &g, &vec, &ntiles, &grid);
+    if (rc) return rc;
+    launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt, c->opos,
+                 c->oval, c->ppos, c->pbits, 0, nullptr, nullptr);
+    launch_codebook(st, c->hist, c->lens_ref, c->cw_ref, c->misc);
+    launch_trial(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, ntiles, c->cw_ref, d_choice, d_costs);
+    t_mark(c, st, "trial");
+    return analysis_end(c, st);
+}
+
+int fz_selector_set(fz_ctx* c, const float* h_params, uint64_t n) {
+    if (!c || !h_params || n != (uint64_t)kSelectorParams) return FZ_ERR_ARG;
+    for (uint64_t i = 0; i < n; i++)
+        if (!__builtin_isfinite(h_params[i])) return FZ_ERR_ARG;
+    DeviceGuard dg(c->device);
+    if (hipMemcpy(c->sel, h_params, sizeof(float) * n, hipMemcpyHostToDevice) != hipSuccess) return FZ_ERR_HIP;
+    c->have_sel = true;
+    return FZ_OK;
+}
+
+int fz_selector_get(fz_ctx* c, float* h_params, uint64_t n) {
+    if (!c || !h_params || n != (uint64_t)kSelectorParams) return FZ_ERR_ARG;
+    if (!c->have_sel) return FZ_ERR_UNSUPPORTED;
+    DeviceGuard dg(c->device);
+    if (hipMemcpy(h_params, c->sel, sizeof(float) * n, hipMemcpyDeviceToHost) != hipSuccess) return FZ_ERR_HIP;
+    return FZ_OK;
+}
+
+// Selector file: "FZSEL\0\0\0", u32 feature-set version, u32 parameter
+// count, then the parameters as little-endian float32.
+int fz_selector_save(fz_ctx* c, const char* path) {
+    if (!c || !path) return FZ_ERR_ARG;
+    float* h = (float*)malloc(sizeof(float) * kSelectorParams);
+    if (!h) return FZ_ERR_NOMEM;
+    int rc = fz_selector_get(c, h, kSelectorParams);
+    if (rc == FZ_OK) {
+        FILE* f = fopen(path, "wb");
+        if (!f) {
+            rc = FZ_ERR_ARG;
+        } else {
+            const char magic[8] = {'F', 'Z', 'S', 'E', 'L', 0, 0, 0};
+            const uint32_t hdr[2] = {kFeatureVersion, (uint32_t)kSelectorParams};
+            bool ok = fwrite(magic, 1, 8, f) == 8 && fwrite(hdr, 4, 2, f) == 2 &&
+                      fwrite(h, sizeof(float), kSelectorParams, f) == (size_t)kSelectorParams;
+            ok = (fclose(f) == 0) && ok;
+            if (!ok) rc = FZ_ERR_ARG;
+        }
+    }
+    free(h);
+    return rc;
+}
+
+int fz_selector_load(fz_ctx* c, const char* path) {
+    if (!c || !path) return FZ_ERR_ARG;
+    FILE* f = fopen(path, "rb");
+    if (!f) return FZ_ERR_ARG;
+    char magic[8];
+    uint32_t hdr[2];
+    float* h = (float*)malloc(sizeof(float) * kSelectorParams);
+    int rc = FZ_ERR_CORRUPT;
+    if (h && fread(magic, 1, 8, f) == 8 && memcmp(magic, "FZSEL\0\0\0", 8) == 0 && fread(hdr, 4, 2, f) == 2 &&
+        hdr[0] == kFeatureVersion && hdr[1] == (uint32_t)kSelectorParams &&
+        fread(h, sizeof(float), kSelectorParams, f) == (size_t)kSelectorParams)
+        rc = fz_selector_set(c, h, kSelectorParams);
+    if (!h) rc = FZ_ERR_NOMEM;
+    fclose(f);
+    free(h);
+    return rc == FZ_ERR_ARG ? FZ_ERR_CORRUPT : rc;
 }
 
 const char* fz_strerror(int s) {

@@ -20,6 +20,13 @@ constexpr int kBlockElems = 512;  // values per full block
 constexpr int kSegs = 64;         // 8-value segments per block
 constexpr int kTileBlocks = 4;    // blocks per workgroup tile (256 threads)
 constexpr uint32_t kMagic = 0x314D5A46u;  // "FZM1"
+// block-feature selector network: 16 features, two hidden layers of 64,
+// one output per predictor
+constexpr int kNFeat = 16;
+constexpr uint32_t kFeatureVersion = 1;
+constexpr int kNHid = 64;
+constexpr int kNOut = 3;
+constexpr int kSelectorParams = 2 * kNFeat + kNHid * kNFeat + kNHid + kNHid * kNHid + kNHid + kNOut * kNHid + kNOut;
 constexpr uint16_t kVersion = 1;
 
 // prefix-scan kinds (fz_scan.hip)

@@ -16,6 +16,8 @@ void launch_quant(hipStream_t st, int grid, const float* x, const Geom& g, uint3
                   int32_t* coef);
 void launch_trial(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
                   Misc* misc, uint32_t ntiles, const uint32_t* cw_ref, uint8_t* choice, uint32_t* costs);
+void launch_features(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
+                     Misc* misc, uint32_t ntiles, const float* sel, float* feat, float* yout, uint8_t* choice);
 
 // fz_scan.hip
 void launch_scan(hipStream_t st, int kind, const void* in, uint32_t n, uint64_t* out, uint64_t* desc, uint32_t* ctr,

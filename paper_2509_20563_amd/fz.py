@@ -22,6 +22,8 @@ HEADER_PATH = os.path.join(os.path.dirname(HERE), "include", "fz.h")
 EB_ABS, EB_REL = 0, 1
 PRED_LORENZO1, PRED_LORENZO2, PRED_REGRESSION, PRED_AUTO_MLP, PRED_AUTO_TRIAL = 0, 1, 2, 3, 4
 HDR_BYTES = 128
+NFEAT = 16
+SELECTOR_PARAMS = 5475
 
 STATUS = {
     0: "FZ_OK", -1: "FZ_ERR_ARG", -2: "FZ_ERR_EB", -3: "FZ_ERR_NONFINITE", -4: "FZ_ERR_CAPACITY",
@@ -75,6 +77,22 @@ def lib() -> ctypes.CDLL:
     L.fz_stage_name.restype = ctypes.c_char_p
     L.fz_last_histogram.argtypes = [vp, vp]
     L.fz_last_histogram.restype = i32
+    L.fz_block_count.argtypes = [P]
+    L.fz_block_count.restype = u64
+    L.fz_block_features.argtypes = [vp, P, vp, vp, u64, vp]
+    L.fz_block_features.restype = i32
+    L.fz_block_select.argtypes = [vp, P, vp, vp, vp, vp]
+    L.fz_block_select.restype = i32
+    L.fz_block_trial.argtypes = [vp, P, vp, vp, vp, vp]
+    L.fz_block_trial.restype = i32
+    L.fz_selector_set.argtypes = [vp, vp, u64]
+    L.fz_selector_set.restype = i32
+    L.fz_selector_get.argtypes = [vp, vp, u64]
+    L.fz_selector_get.restype = i32
+    L.fz_selector_save.argtypes = [vp, ctypes.c_char_p]
+    L.fz_selector_save.restype = i32
+    L.fz_selector_load.argtypes = [vp, ctypes.c_char_p]
+    L.fz_selector_load.restype = i32
     _lib = L
     return L
 
@@ -214,6 +232,61 @@ class Context:
         n = ctypes.c_int()
         _check(lib().fz_stage_times(self._h, ms, 16, ctypes.byref(n)), "fz_stage_times")
         return [(lib().fz_stage_name(self._h, i).decode(), float(ms[i])) for i in range(min(n.value, 16))]
+
+    # ------------------------------------------------- per-block predictors
+    def block_count(self, shape) -> int:
+        return int(lib().fz_block_count(ctypes.byref(params_for(shape, 1.0))))
+
+    def _field_args(self, x, eb, mode):
+        if x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous():
+            raise ValueError("x must be a contiguous float32 device tensor")
+        return params_for(x.shape, eb, mode), self.block_count(x.shape)
+
+    def block_features(self, x: torch.Tensor, eb: float, mode: int = EB_REL) -> torch.Tensor:
+        """(nblocks, 16) float32 device tensor of block features."""
+        p, nb = self._field_args(x, eb, mode)
+        f = torch.empty((nb, NFEAT), dtype=torch.float32, device=x.device)
+        _check(lib().fz_block_features(self._h, ctypes.byref(p), ctypes.c_void_p(x.data_ptr()),
+                                       ctypes.c_void_p(f.data_ptr()), f.numel(), _stream_handle(x.device)),
+               "fz_block_features")
+        return f
+
+    def block_select(self, x: torch.Tensor, eb: float, mode: int = EB_REL):
+        """(choice uint8 (nblocks,), predictions float32 (nblocks, 3)) by the selector."""
+        p, nb = self._field_args(x, eb, mode)
+        ch = torch.empty(nb, dtype=torch.uint8, device=x.device)
+        y = torch.empty((nb, 3), dtype=torch.float32, device=x.device)
+        _check(lib().fz_block_select(self._h, ctypes.byref(p), ctypes.c_void_p(x.data_ptr()),
+                                     ctypes.c_void_p(ch.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                     _stream_handle(x.device)), "fz_block_select")
+        return ch, y
+
+    def block_trial(self, x: torch.Tensor, eb: float, mode: int = EB_REL):
+        """(choice uint8 (nblocks,), costs int32 (nblocks, 3) in bits) by exhaustive trial."""
+        p, nb = self._field_args(x, eb, mode)
+        ch = torch.empty(nb, dtype=torch.uint8, device=x.device)
+        costs = torch.empty((nb, 3), dtype=torch.int32, device=x.device)
+        _check(lib().fz_block_trial(self._h, ctypes.byref(p), ctypes.c_void_p(x.data_ptr()),
+                                    ctypes.c_void_p(ch.data_ptr()), ctypes.c_void_p(costs.data_ptr()),
+                                    _stream_handle(x.device)), "fz_block_trial")
+        return ch, costs
+
+    def selector_set(self, params):
+        import numpy as np
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        _check(lib().fz_selector_set(self._h, a.ctypes.data_as(ctypes.c_void_p), a.size), "fz_selector_set")
+
+    def selector_get(self):
+        import numpy as np
+        a = np.zeros(SELECTOR_PARAMS, np.float32)
+        _check(lib().fz_selector_get(self._h, a.ctypes.data_as(ctypes.c_void_p), a.size), "fz_selector_get")
+        return a
+
+    def selector_save(self, path: str):
+        _check(lib().fz_selector_save(self._h, os.fsencode(path)), "fz_selector_save")
+
+    def selector_load(self, path: str):
+        _check(lib().fz_selector_load(self._h, os.fsencode(path)), "fz_selector_load")
 
     def last_histogram(self):
         import numpy as np

@@ -89,10 +89,3 @@ def test_mixed_modes_one_context(fz, ctx):
     x = fields.grf((40, 48, 56), seed=4)
     for pred in (0, P2, PT, P1, 0, PT):
         _check(fz, ctx, x, 1e-3, 1, pred, f"mixed {pred}")
-
-
-def test_selector_mode_unsupported(fz, ctx):
-    x = torch.zeros((16, 16, 16), device="cuda")
-    with pytest.raises(fz.FZError) as e:
-        ctx.compress(x, 1e-3, 1, pred=3)
-    assert e.value.code == -8
