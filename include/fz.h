@@ -202,6 +202,38 @@ int fz_selector_get(fz_ctx *ctx, float *h_params, uint64_t n);
 int fz_selector_save(fz_ctx *ctx, const char *path);
 int fz_selector_load(fz_ctx *ctx, const char *path);
 
+/* Training of the selector (on the device, fp32). */
+typedef struct {
+    uint32_t epochs; /* passes over the samples (>= 1)                      */
+    uint32_t batch;  /* minibatch size, 1 .. 2^20 (4096 is the default use) */
+    float lr;        /* Adam step size (1e-3)                               */
+    float beta1;     /* Adam moment decays (0.9, 0.999), in [0, 1)          */
+    float beta2;
+    float eps;       /* Adam epsilon (1e-8), > 0                            */
+    uint64_t seed;   /* initial weights and minibatch order                 */
+} fz_train_params;
+
+/* Fit the selector to n samples (blocks): d_feat [n][16] float32 from
+ * fz_block_features and d_costs [n][3] uint32 bits per predictor from
+ * fz_block_trial, both device.  Targets are log2(1 + bits).  mu and rs
+ * are set to the features' mean and inverse standard deviation (rs = 1
+ * for a constant feature); weights start He-normal from the seed (biases
+ * 0); each epoch visits the samples in a seeded shuffled order in
+ * minibatches, one Adam step per minibatch on the mean squared error.
+ * h_loss (host, nullable, epochs floats) receives each epoch's mean
+ * minibatch loss.  On success the trained network becomes the context's
+ * selector.  Allocates device memory for the duration of the call;
+ * synchronises `stream`. */
+int fz_selector_train(fz_ctx *ctx, const float *d_feat, const uint32_t *d_costs, uint64_t n,
+                      const fz_train_params *tp, float *h_loss, void *stream);
+
+/* Gradient of the mean squared error of the context's selector over n
+ * samples (1 .. 2^20; d_feat [n][16], d_target [n][3] float32, device) to
+ * h_grad (host, FZ_SELECTOR_PARAMS floats; 0 for mu and rs) and the loss
+ * to *h_loss (nullable).  For gradient checks.  Synchronises `stream`. */
+int fz_selector_grad(fz_ctx *ctx, const float *d_feat, const float *d_target, uint64_t n, float *h_grad,
+                     float *h_loss, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

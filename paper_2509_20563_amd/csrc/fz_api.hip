@@ -1,6 +1,7 @@
 // Host implementation of the fz C ABI (include/fz.h): argument validation,
 // scratch management, kernel sequencing on the caller's stream, and the
 // container header on the host side.
+#include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -698,6 +699,151 @@ int fz_selector_get(fz_ctx* c, float* h_params, uint64_t n) {
     if (!c->have_sel) return FZ_ERR_UNSUPPORTED;
     DeviceGuard dg(c->device);
     if (hipMemcpy(h_params, c->sel, sizeof(float) * n, hipMemcpyDeviceToHost) != hipSuccess) return FZ_ERR_HIP;
+    return FZ_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// splitmix64 (Steele, Lea and Flood 2014): the generator of the selector's
+// initial weights and of the minibatch order
+uint64_t splitmix64(uint64_t& s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+double uniform01(uint64_t& s) { return ((splitmix64(s) >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+
+// He-normal initial weights (standard deviation sqrt(2 / fan-in), by the
+// Box-Muller transform), zero biases, mu = 0 and rs = 1.
+void he_init(float* w, uint64_t seed) {
+    uint64_t s = seed;
+    for (int i = 0; i < kSelectorParams; i++) w[i] = 0.0f;
+    for (int i = 0; i < kNFeat; i++) w[kNFeat + i] = 1.0f;
+    struct T { int off, n, fan; } ts[3] = {{2 * kNFeat, kNHid * kNFeat, kNFeat},
+                                          {2 * kNFeat + kNHid * kNFeat + kNHid, kNHid * kNHid, kNHid},
+                                          {2 * kNFeat + kNHid * kNFeat + kNHid + kNHid * kNHid + kNHid, kNOut * kNHid, kNHid}};
+    for (const T& t : ts) {
+        const double sd = sqrt(2.0 / t.fan);
+        for (int i = 0; i < t.n; i++) {
+            const double u1 = uniform01(s), u2 = uniform01(s);
+            w[t.off + i] = (float)(sd * sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
+        }
+    }
+}
+
+struct TrainBufs {
+    TrainScratch s = {};
+    float *w = nullptr, *m = nullptr, *v = nullptr, *tgt = nullptr, *loss = nullptr;
+    uint32_t* idx = nullptr;
+    ~TrainBufs() {
+        float* fs[] = {s.Z, s.H1, s.H2, s.DY, s.DH1, s.DH2, s.SE, s.grad, w, m, v, tgt, loss};
+        for (float* f : fs) hipFree(f);
+        hipFree(idx);
+    }
+    bool alloc_batch(uint32_t B) {
+        return hipMalloc((void**)&s.Z, sizeof(float) * B * kNFeat) == hipSuccess &&
+               hipMalloc((void**)&s.H1, sizeof(float) * B * kNHid) == hipSuccess &&
+               hipMalloc((void**)&s.H2, sizeof(float) * B * kNHid) == hipSuccess &&
+               hipMalloc((void**)&s.DY, sizeof(float) * B * kNOut) == hipSuccess &&
+               hipMalloc((void**)&s.DH1, sizeof(float) * B * kNHid) == hipSuccess &&
+               hipMalloc((void**)&s.DH2, sizeof(float) * B * kNHid) == hipSuccess &&
+               hipMalloc((void**)&s.SE, sizeof(float) * B) == hipSuccess &&
+               hipMalloc((void**)&s.grad, sizeof(float) * kSelectorParams) == hipSuccess &&
+               hipMalloc((void**)&w, sizeof(float) * kSelectorParams) == hipSuccess;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int fz_selector_train(fz_ctx* c, const float* d_feat, const uint32_t* d_costs, uint64_t n,
+                      const fz_train_params* tp, float* h_loss, void* stream) {
+    if (!c || !d_feat || !d_costs || !tp || n < 1 || n > (1ull << 31)) return FZ_ERR_ARG;
+    if (tp->epochs < 1 || tp->batch < 1 || tp->batch > (1u << 20) || !(tp->lr > 0.0f) || !(tp->beta1 >= 0.0f) ||
+        !(tp->beta1 < 1.0f) || !(tp->beta2 >= 0.0f) || !(tp->beta2 < 1.0f) || !(tp->eps > 0.0f))
+        return FZ_ERR_ARG;
+    DeviceGuard dg(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    const uint32_t B = (uint32_t)(tp->batch < n ? tp->batch : n);
+    const uint64_t nbatch = (n + B - 1) / B;
+    TrainBufs tb;
+    if (!tb.alloc_batch(B) || hipMalloc((void**)&tb.m, sizeof(float) * kSelectorParams) != hipSuccess ||
+        hipMalloc((void**)&tb.v, sizeof(float) * kSelectorParams) != hipSuccess ||
+        hipMalloc((void**)&tb.tgt, sizeof(float) * 3 * n) != hipSuccess ||
+        hipMalloc((void**)&tb.loss, sizeof(float) * nbatch) != hipSuccess ||
+        hipMalloc((void**)&tb.idx, sizeof(uint32_t) * n) != hipSuccess)
+        return FZ_ERR_NOMEM;
+    float* hw = (float*)malloc(sizeof(float) * kSelectorParams);
+    uint32_t* perm = (uint32_t*)malloc(sizeof(uint32_t) * n);
+    float* hl = (float*)malloc(sizeof(float) * nbatch);
+    int rc = (hw && perm && hl) ? FZ_OK : FZ_ERR_NOMEM;
+    if (rc == FZ_OK) {
+        he_init(hw, tp->seed);
+        bool ok = hipMemcpyAsync(tb.w, hw, sizeof(float) * kSelectorParams, hipMemcpyHostToDevice, st) == hipSuccess;
+        launch_fill32(st, (uint32_t*)tb.m, kSelectorParams, 0);
+        launch_fill32(st, (uint32_t*)tb.v, kSelectorParams, 0);
+        launch_targets(st, d_costs, n, tb.tgt);
+        launch_feature_stats(st, d_feat, n, tb.w);
+        for (uint64_t i = 0; i < n; i++) perm[i] = (uint32_t)i;
+        uint64_t rs = tp->seed ^ 0x5DEECE66Dull;
+        int step = 0;
+        for (uint32_t e = 0; ok && e < tp->epochs; e++) {
+            // Fisher-Yates shuffle of the sample order
+            for (uint64_t i = n - 1; i > 0; i--) {
+                const uint64_t j = splitmix64(rs) % (i + 1);
+                const uint32_t t = perm[i];
+                perm[i] = perm[j];
+                perm[j] = t;
+            }
+            ok = hipMemcpyAsync(tb.idx, perm, sizeof(uint32_t) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+            for (uint64_t bi = 0; ok && bi < nbatch; bi++) {
+                const uint64_t start = bi * B;
+                const uint32_t nb = (uint32_t)(n - start < B ? n - start : B);
+                launch_train_batch(st, tb.w, d_feat, tb.tgt, tb.idx + start, nb, tb.s, tb.loss + bi);
+                launch_adam(st, tb.w, tb.m, tb.v, tb.s.grad, ++step, tp->lr, tp->beta1, tp->beta2, tp->eps);
+            }
+            ok = ok && hipMemcpyAsync(hl, tb.loss, sizeof(float) * nbatch, hipMemcpyDeviceToHost, st) == hipSuccess &&
+                 hipStreamSynchronize(st) == hipSuccess;
+            if (ok && h_loss) {
+                double a = 0.0;
+                for (uint64_t bi = 0; bi < nbatch; bi++) a += hl[bi];
+                h_loss[e] = (float)(a / (double)nbatch);
+            }
+        }
+        ok = ok && hipMemcpyAsync(hw, tb.w, sizeof(float) * kSelectorParams, hipMemcpyDeviceToHost, st) == hipSuccess &&
+             hipStreamSynchronize(st) == hipSuccess && hipGetLastError() == hipSuccess;
+        if (!ok) rc = FZ_ERR_HIP;
+        for (int i = 0; rc == FZ_OK && i < kSelectorParams; i++)
+            if (!__builtin_isfinite(hw[i])) rc = FZ_ERR_INTERNAL;
+        if (rc == FZ_OK) rc = fz_selector_set(c, hw, kSelectorParams);
+    }
+    free(hw);
+    free(perm);
+    free(hl);
+    return rc;
+}
+
+int fz_selector_grad(fz_ctx* c, const float* d_feat, const float* d_target, uint64_t n, float* h_grad,
+                     float* h_loss, void* stream) {
+    if (!c || !d_feat || !d_target || !h_grad || n < 1 || n > (1u << 20)) return FZ_ERR_ARG;
+    if (!c->have_sel) return FZ_ERR_UNSUPPORTED;
+    DeviceGuard dg(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    TrainBufs tb;
+    if (!tb.alloc_batch((uint32_t)n) || hipMalloc((void**)&tb.loss, sizeof(float)) != hipSuccess) return FZ_ERR_NOMEM;
+    float loss = 0.0f;
+    bool ok = hipMemcpyAsync(tb.w, c->sel, sizeof(float) * kSelectorParams, hipMemcpyDeviceToDevice, st) == hipSuccess;
+    launch_train_batch(st, tb.w, d_feat, d_target, nullptr, (uint32_t)n, tb.s, tb.loss);
+    ok = ok && hipMemcpyAsync(h_grad, tb.s.grad, sizeof(float) * kSelectorParams, hipMemcpyDeviceToHost, st) == hipSuccess &&
+         hipMemcpyAsync(&loss, tb.loss, sizeof(float), hipMemcpyDeviceToHost, st) == hipSuccess &&
+         hipStreamSynchronize(st) == hipSuccess && hipGetLastError() == hipSuccess;
+    if (!ok) return FZ_ERR_HIP;
+    if (h_loss) *h_loss = loss;
     return FZ_OK;
 }
 

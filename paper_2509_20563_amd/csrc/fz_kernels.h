@@ -37,6 +37,17 @@ void launch_finalize(hipStream_t st, const Geom& g, uint32_t mode, double eb, ui
                      const int32_t* oval, const uint32_t* ppos, const uint32_t* pbits, const uint8_t* bpred,
                      const uint64_t* reg_idx, const int32_t* coef);
 
+// fz_train.hip: selector training (device scratch of one minibatch)
+struct TrainScratch {
+    float *Z, *H1, *H2, *DY, *DH1, *DH2, *SE, *grad;
+};
+void launch_targets(hipStream_t st, const uint32_t* costs, uint64_t n, float* t);
+void launch_feature_stats(hipStream_t st, const float* feat, uint64_t n, float* w);
+void launch_train_batch(hipStream_t st, const float* w, const float* feat, const float* tgt, const uint32_t* idx,
+                        uint32_t B, TrainScratch& s, float* loss_out);
+void launch_adam(hipStream_t st, float* w, float* m, float* v, const float* g, int t, float lr, float b1, float b2,
+                 float eps);
+
 // fz_decode.hip
 void launch_lut(hipStream_t st, const uint8_t* lens_packed, uint16_t* lut, Misc* misc);
 void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,

@@ -37,6 +37,12 @@ class FZError(RuntimeError):
         super().__init__(f"{what}: {STATUS.get(code, code)} ({_strerror(code)})")
 
 
+class TrainParams(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_uint32), ("batch", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
 class Params(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_uint32), ("dims", ctypes.c_uint64 * 3), ("eb_mode", ctypes.c_uint32),
                 ("eb", ctypes.c_double), ("pred", ctypes.c_uint32), ("radius", ctypes.c_uint32)]
@@ -93,6 +99,10 @@ def lib() -> ctypes.CDLL:
     L.fz_selector_save.restype = i32
     L.fz_selector_load.argtypes = [vp, ctypes.c_char_p]
     L.fz_selector_load.restype = i32
+    L.fz_selector_train.argtypes = [vp, vp, vp, u64, ctypes.POINTER(TrainParams), vp, vp]
+    L.fz_selector_train.restype = i32
+    L.fz_selector_grad.argtypes = [vp, vp, vp, u64, vp, vp, vp]
+    L.fz_selector_grad.restype = i32
     _lib = L
     return L
 
@@ -281,6 +291,40 @@ class Context:
         a = np.zeros(SELECTOR_PARAMS, np.float32)
         _check(lib().fz_selector_get(self._h, a.ctypes.data_as(ctypes.c_void_p), a.size), "fz_selector_get")
         return a
+
+    def selector_train(self, feat: torch.Tensor, costs: torch.Tensor, epochs: int = 10, batch: int = 4096,
+                       lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+                       seed: int = 0):
+        """Train the selector on device features (n, 16) and trial costs (n, 3); returns the
+        mean minibatch loss of every epoch."""
+        import numpy as np
+        if feat.dtype != torch.float32 or not feat.is_cuda or not feat.is_contiguous() or feat.shape[-1] != NFEAT:
+            raise ValueError("feat must be a contiguous (n, 16) float32 device tensor")
+        if costs.dtype not in (torch.int32,) or not costs.is_cuda or not costs.is_contiguous():
+            raise ValueError("costs must be a contiguous (n, 3) int32 device tensor")
+        n = feat.shape[0]
+        if costs.shape != (n, 3):
+            raise ValueError("costs must be (n, 3)")
+        tp = TrainParams(int(epochs), int(batch), float(lr), float(beta1), float(beta2), float(eps), int(seed))
+        loss = np.zeros(int(epochs), np.float32)
+        _check(lib().fz_selector_train(self._h, ctypes.c_void_p(feat.data_ptr()), ctypes.c_void_p(costs.data_ptr()),
+                                       n, ctypes.byref(tp), loss.ctypes.data_as(ctypes.c_void_p),
+                                       _stream_handle(feat.device)), "fz_selector_train")
+        return loss
+
+    def selector_grad(self, feat: torch.Tensor, target: torch.Tensor):
+        """(gradient (5475,) float32, loss) of the current selector's MSE on device samples."""
+        import numpy as np
+        if feat.dtype != torch.float32 or target.dtype != torch.float32:
+            raise ValueError("float32 tensors")
+        feat = feat.contiguous()
+        target = target.contiguous()
+        g = np.zeros(SELECTOR_PARAMS, np.float32)
+        loss = ctypes.c_float()
+        _check(lib().fz_selector_grad(self._h, ctypes.c_void_p(feat.data_ptr()), ctypes.c_void_p(target.data_ptr()),
+                                      feat.shape[0], g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss),
+                                      _stream_handle(feat.device)), "fz_selector_grad")
+        return g, loss.value
 
     def selector_save(self, path: str):
         _check(lib().fz_selector_save(self._h, os.fsencode(path)), "fz_selector_save")

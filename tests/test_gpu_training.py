@@ -1,0 +1,77 @@
+"""Selector training on the GPU: fp32 gradients against the oracle's fp64
+backpropagation, a training run that lowers the loss, and the trained
+selector's compression ratio against exhaustive trial and plain
+first-order Lorenzo on held-out fields (training seeds are disjoint from
+evaluation seeds)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from inputs import fields
+
+pytestmark = pytest.mark.gpu
+
+TRAIN_SEEDS = (101, 102, 103, 104)
+EVAL_SEEDS = (7, 8)
+
+
+@pytest.fixture(scope="module")
+def ctx(fz):
+    return fz.Context(0)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def test_gradient_matches_oracle(fz, ctx):
+    r = np.random.default_rng(3)
+    w = np.zeros(oracle.NPARAM, np.float32)
+    w[:] = r.normal(0, 0.3, oracle.NPARAM)
+    o, n = oracle.OFF["mu"]
+    w[o:o + n] = r.uniform(0, 3, n)
+    o, n = oracle.OFF["rs"]
+    w[o:o + n] = r.uniform(0.5, 1.5, n)
+    ctx.selector_set(w)
+    feat = r.uniform(0, 6, (777, 16)).astype(np.float32)
+    tgt = r.uniform(0, 12, (777, 3)).astype(np.float32)
+    g, loss = ctx.selector_grad(torch.from_numpy(feat).cuda(), torch.from_numpy(tgt).cuda())
+    lo, go = oracle.mlp_loss_grad(w.astype(np.float64), feat, tgt.astype(np.float64))
+    assert abs(loss - lo) <= 1e-5 * lo
+    o1 = oracle.OFF["W1"][0]
+    assert np.all(g[:o1] == 0)
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        o, n = oracle.OFF[name]
+        e = _rel(g[o:o + n].astype(np.float64), go[o:o + n])
+        print(f"[gpu training] grad {name} rel err {e:.2e}", flush=True)
+        assert e <= 1e-4, name
+
+
+def _samples(fz, ctx, seeds, shape, ebs):
+    feats, costs = [], []
+    for s in seeds:
+        x = torch.from_numpy(fields.grf(shape, alpha=2.0 + 0.5 * (s % 3), seed=s)).cuda()
+        for eb in ebs:
+            feats.append(ctx.block_features(x, eb, 1))
+            costs.append(ctx.block_trial(x, eb, 1)[1])
+    return torch.cat(feats).contiguous(), torch.cat(costs).contiguous()
+
+
+def test_training_lowers_loss_and_selects_well(fz, ctx):
+    ebs = (1e-2, 1e-3, 1e-4)
+    feat, costs = _samples(fz, ctx, TRAIN_SEEDS, (96, 96, 96), ebs)
+    print(f"[gpu training] {feat.shape[0]} samples", flush=True)
+    loss = ctx.selector_train(feat, costs, epochs=30, batch=4096, seed=1)
+    print(f"[gpu training] loss first {loss[0]:.4f} last {loss[-1]:.4f}", flush=True)
+    assert np.all(np.isfinite(loss))
+    assert loss[-1] < 0.25 * loss[0]
+    # held-out fields: ratio of the network's choice against trial and P0
+    for s in EVAL_SEEDS:
+        x = torch.from_numpy(fields.grf((128, 128, 128), alpha=2.5, seed=s)).cuda()
+        for eb in ebs:
+            n_mlp = ctx.compress(x, eb, 1, pred=3).numel()
+            n_trial = ctx.compress(x, eb, 1, pred=4).numel()
+            n_p0 = ctx.compress(x, eb, 1, pred=0).numel()
+            print(f"[gpu training] seed {s} eb {eb}: bytes mlp {n_mlp} trial {n_trial} p0 {n_p0}", flush=True)
+            assert n_mlp <= n_trial / 0.98
