@@ -436,19 +436,21 @@ int fz_compress(fz_ctx* c, const fz_params* p, const float* d_in, void* d_out, u
         launch_trial(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, ntiles, c->cw_ref, c->bpred, c->costs);
         launch_fill32(st, c->hist, kBins, 0);
         t_mark(c, st, "trial");
-    } else if (pred == FZ_PRED_AUTO_MLP) {
-        launch_features(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, ntiles, c->sel, nullptr, nullptr,
-                        c->bpred);
-        t_mark(c, st, "select");
     }
+    if (pred == FZ_PRED_AUTO_MLP) {
+        // the network chooses each block's predictor inside the quantiser
+        launch_quant_select(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles,
+                            c->tile_cnt, c->opos, c->oval, c->ppos, c->pbits, c->sel, c->bpred, c->coef);
+    } else {
+        const int fixed = has_map ? -1 : (int)pred;
+        launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt,
+                     c->opos, c->oval, c->ppos, c->pbits, fixed, c->bpred, c->coef);
+    }
+    t_mark(c, st, "quant");
     if (has_map) {
         launch_scan(st, SCAN_PMAP, c->bpred, g.nblocks, c->reg_idx, c->desc_pmap, &c->misc->mtile_ctr, c->misc, 0);
         t_mark(c, st, "scan_map");
     }
-    const int fixed = has_map ? -1 : (int)pred;
-    launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt, c->opos,
-                 c->oval, c->ppos, c->pbits, fixed, c->bpred, c->coef);
-    t_mark(c, st, "quant");
     launch_scan(st, SCAN_COUNTS, c->tile_cnt, ntiles, c->tile_off, c->desc_cnt, &c->misc->qtile_ctr, c->misc, 0);
     t_mark(c, st, "scan_counts");
     launch_codebook(st, c->hist, out + kHdr, c->cw, c->misc);

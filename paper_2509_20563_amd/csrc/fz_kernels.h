@@ -16,6 +16,10 @@ void launch_quant(hipStream_t st, int grid, const float* x, const Geom& g, uint3
                   int32_t* coef);
 void launch_trial(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
                   Misc* misc, uint32_t ntiles, const uint32_t* cw_ref, uint8_t* choice, uint32_t* costs);
+void launch_quant_select(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
+                         Misc* misc, uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt,
+                         uint32_t* opos, int32_t* oval, uint32_t* ppos, uint32_t* pbits, const float* sel,
+                         uint8_t* choice, int32_t* coef);
 void launch_features(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
                      Misc* misc, uint32_t ntiles, const float* sel, float* feat, float* yout, uint8_t* choice);
 

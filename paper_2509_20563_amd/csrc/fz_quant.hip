@@ -145,8 +145,9 @@ __device__ __forceinline__ void read_row(const int32_t* Q, uint32_t off, int32_t
 // cheapest predictor -> choice[b], the three costs -> costs[3 b + p]),
 // kQuantFeat (no codes: the 16 block features -> feat[16 b + i] and, with
 // selector parameters, the network's predictions -> y[3 b + k] and its
-// choice -> choice[b]).
-constexpr int kQuantP0 = 0, kQuantPred = 1, kQuantTrial = 2, kQuantFeat = 3;
+// choice -> choice[b]), kQuantSel (the selector's choice made in the same
+// pass, then codes with the chosen predictor as in kQuantPred).
+constexpr int kQuantP0 = 0, kQuantPred = 1, kQuantTrial = 2, kQuantFeat = 3, kQuantSel = 4;
 
 // Selector network layout (floats): mu[16], rs[16], W1[64][16], b1[64],
 // W2[64][64], b2[64], W3[3][64], b3[3].
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
             LREF[i] = (uint8_t)(l ? l : kLmax + 1);
         }
     }
-    if (MODE == kQuantFeat && sel) {
+    if ((MODE == kQuantFeat || MODE == kQuantSel) && sel) {
         for (uint32_t i = t; i < (uint32_t)(kNFeat * kNHid); i += 256) {
             const uint32_t j = i / kNFeat, k = i % kNFeat;  // W1[j][k]
             W1T[k * kNHid + j] = sel[kSelW1 + i];
@@ -417,7 +418,7 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
                 const int32_t cX = dx > 0 ? clamp32(rdiv(SU * 256, dx)) : 0;
                 const int32_t cY = (ND >= 2 && dy > 0) ? clamp32(rdiv(SV * 256, dy)) : 0;
                 const int32_t cZ = (ND >= 3 && dz > 0) ? clamp32(rdiv(SW * 256, dz)) : 0;
-                if (MODE == kQuantPred && lane == 0 && blk) {
+                if ((MODE == kQuantPred || MODE == kQuantSel) && lane == 0 && blk) {
                     int4* cp = reinterpret_cast<int4*>(coef + 4 * (uint64_t)b);
                     *cp = make_int4(cA, cX, cY, cZ);
                 }
@@ -457,7 +458,7 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
                         costs[3 * (uint64_t)b + 2] = cst[2];
                     }
                 }
-            } else if (MODE == kQuantFeat) {
+            } else if (MODE == kQuantFeat || MODE == kQuantSel) {
                 // ---- block features (version 1), exact integer sums first
                 int64_t r0s = 0, r1s = 0, r2s = 0;
                 int32_t r0m = 0;
@@ -585,14 +586,13 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
                     const float y0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, yk), 0));
                     const float y1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, yk), 1));
                     const float y2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, yk), 2));
-                    if (blk && lane == 0) {
-                        uint32_t best = 0;
-                        float bv = y0;
-                        if (y1 < bv) { best = 1; bv = y1; }
-                        if (y2 < bv) best = 2;
-                        choice[b] = (uint8_t)best;
-                    }
+                    uint32_t best = 0;
+                    float bv = y0;
+                    if (y1 < bv) { best = 1; bv = y1; }
+                    if (y2 < bv) best = 2;
+                    if (blk && lane == 0) choice[b] = (uint8_t)best;
                     if (yout && blk && lane < (uint32_t)kNOut) yout[(uint64_t)b * kNOut + lane] = yk;
+                    if (MODE == kQuantSel) residual(blk ? best : 0u);
                 }
             } else {
                 residual(PRED ? (fixed_pred >= 0 ? (uint32_t)fixed_pred : (blk ? (uint32_t)bpred[b] : 0u)) : 0u);
@@ -745,6 +745,20 @@ void launch_trial(hipStream_t st, int grid, const float* x, const Geom& g, uint3
     if (g.ndim == 3) FZ_QUANT(3, kQuantTrial);
     else if (g.ndim == 2) FZ_QUANT(2, kQuantTrial);
     else FZ_QUANT(1, kQuantTrial);
+}
+
+void launch_quant_select(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
+                         Misc* misc, uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt,
+                         uint32_t* opos, int32_t* oval, uint32_t* ppos, uint32_t* pbits, const float* sel,
+                         uint8_t* choice, int32_t* coef) {
+    const uint32_t* cw_ref = nullptr;
+    const uint8_t* bpred = nullptr;
+    uint32_t* costs = nullptr;
+    float *feat = nullptr, *yout = nullptr;
+    const int fixed_pred = -1;
+    if (g.ndim == 3) FZ_QUANT(3, kQuantSel);
+    else if (g.ndim == 2) FZ_QUANT(2, kQuantSel);
+    else FZ_QUANT(1, kQuantSel);
 }
 
 void launch_features(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
