@@ -286,7 +286,8 @@ int parse_header(const uint8_t* h, uint64_t n, Parsed* r) {
         return FZ_OK;
     }
     if (!(r->eb_abs >= 1e-300 && r->eb_abs <= 1e300)) return FZ_ERR_CORRUPT;
-    if (r->nblocks != r->g.nblocks || r->words != (r->bits + 31) / 32) return FZ_ERR_CORRUPT;
+    // every value costs at least one bit, so the stream is never empty
+    if (r->nblocks != r->g.nblocks || r->words != (r->bits + 31) / 32 || r->bits < r->g.N) return FZ_ERR_CORRUPT;
     if (r->nout > r->g.N || r->npat > r->g.N) return FZ_ERR_CORRUPT;
     // regression coefficients: every block (P2), none (P0, P1), or the
     // blocks the map selects (counted again on the device)
@@ -583,7 +584,7 @@ int fz_decompress(fz_ctx* c, const void* d_in, uint64_t in_bytes, const void* h_
     const Misc m = *c->h_misc;
     rc = flags_status(m.flags);
     if (rc) return rc;
-    if (m.code0_count != r.nout) return FZ_ERR_CORRUPT;
+    if (m.code0_count != r.nout || m.ohash_dec != m.ohash_list) return FZ_ERR_CORRUPT;
     if (has_map && m.nreg != r.nreg) return FZ_ERR_CORRUPT;
     return FZ_OK;
 }

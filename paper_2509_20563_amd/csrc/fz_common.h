@@ -61,8 +61,16 @@ struct Misc {
     uint64_t off_chunks;       // container offsets of the chunk table and
     uint64_t off_stream;       // the stream (depend on the map/coefficients)
     uint64_t nreg;             // blocks predicted by regression
-    uint64_t pad1[2];
+    // decode: sums of a hash of the positions of the outlier codes met and
+    // of the positions in the outlier list (equal for a valid container)
+    uint64_t ohash_dec, ohash_list;
 };
+
+// Hash of an outlier position for the decode-side consistency sums.
+__host__ __device__ inline uint64_t pos_hash(uint32_t p) {
+    uint64_t h = ((uint64_t)p + 1) * 0x9E3779B97F4A7C15ull;
+    return h ^ (h >> 29);
+}
 
 // Unsigned division by a runtime constant d <= 2^23 for numerators <= 2^23:
 // q = (umulhi(n, m) + n) >> l with l = ceil(log2 d), m = 2^32 (2^l - d) / d + 1

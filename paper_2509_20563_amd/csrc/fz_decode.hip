@@ -3,9 +3,10 @@
 // the reconstruction; the inverse of the Lorenzo predictor is a prefix sum):
 //   k_lut          - validates the code lengths, builds a 4096-entry table
 //   k_decode       - one lane per block: table-driven Huffman decode from a
-//                    per-lane window staged in LDS, outlier overwrite,
-//                    in-block prefix sums (inverse Lorenzo), dequantisation,
-//                    row stores - codes never leave registers
+//                    register bit buffer fed through a per-lane LDS ring,
+//                    outlier overwrite, in-block prefix sums (inverse
+//                    Lorenzo), dequantisation, row stores - codes never
+//                    leave registers
 //   k_patch        - lossless patches written over the reconstruction
 #include "fz_common.h"
 #include "fz_kernels.h"
@@ -68,65 +69,140 @@ __global__ __launch_bounds__(1024) void k_lut(const uint8_t* __restrict__ lensp,
 }
 
 // ----------------------------------------------------------------- decode
-constexpr int kWin = 20;      // words staged per lane and round (5 x 16 B)
-constexpr int kDecLanes = 256;
+// Each lane decodes one block.  The lane's part of the stream flows
+//   HBM --(16-byte chunks, two chunks ahead, registers)--> LDS ring of 4
+//   chunks --(one word ahead)--> 64-bit bit buffer in registers
+// so the dependent chain per codeword is one table lookup and a shift; the
+// global loads are waited for only when a chunk is written to the ring, two
+// chunks after they were issued.
+constexpr int kDecLanes = 256;  // lanes (blocks) per workgroup
+constexpr int kRing = 16;       // ring words per lane (4 chunks of 4)
 
-// A lane's window of the stream in LDS, column-major across the workgroup:
-// word k of lane l is at k * 256 + l, so lanes reading their own word k land
-// in distinct banks whatever k each lane is at.
-struct LaneStream {
-    const uint32_t* stream;
-    uint64_t nwords;
-    uint32_t* win;   // &WIN[lane]
-    uint64_t aw;     // first staged word (multiple of 4)
-    uint32_t rel;    // bit position relative to aw * 32
+struct LaneDec {
+    const uint4* chunks;  // stream as 16-byte chunks
+    uint32_t nchunks;
+    uint32_t* ring;       // &RING[lane]; ring word k at ring[k * kDecLanes]
+    uint32_t w;           // absolute index of the next word to feed
+    uint32_t nw;          // that word
+    uint64_t buf;         // next stream bits, most significant first
+    uint32_t nb;          // valid bits in buf
+    uint4 pend;           // the chunk after the ring's newest, in flight
 
-    // Stage the words holding the next 32 codewords (at most 384 bits).
-    __device__ __forceinline__ void stage(uint64_t bitpos) {
-        aw = (bitpos >> 5) & ~3ull;
-        rel = (uint32_t)(bitpos - aw * 32);
-        uint32_t w[kWin];
-        if (aw + kWin <= nwords) {
-            const uint4* s4 = reinterpret_cast<const uint4*>(stream + aw);
-#pragma unroll
-            for (int k = 0; k < kWin / 4; k++) {
-                const uint4 v = s4[k];
-                w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < kWin; k++) w[k] = (aw + k < nwords) ? stream[aw + k] : 0u;
+    __device__ __forceinline__ uint4 load_chunk(uint32_t k) const {
+        return chunks[k < nchunks ? k : nchunks - 1];
+    }
+    __device__ __forceinline__ void put_chunk(uint32_t k, const uint4& v) {
+        uint32_t* r = ring + ((k & 3) * 4) * kDecLanes;
+        r[0] = v.x;
+        r[kDecLanes] = v.y;
+        r[2 * kDecLanes] = v.z;
+        r[3 * kDecLanes] = v.w;
+    }
+    // entering chunk c: chunk c + 1 goes to the ring, chunk c + 2 is issued
+    __device__ __forceinline__ void boundary(uint32_t c) {
+        put_chunk(c + 1, pend);
+        pend = load_chunk(c + 2);
+    }
+    __device__ __forceinline__ void advance() {
+        w++;
+        if ((w & 3) == 0) boundary(w >> 2);
+        nw = ring[(w & (kRing - 1)) * kDecLanes];
+    }
+    __device__ __forceinline__ void init(uint64_t start) {
+        const uint32_t w0 = (uint32_t)(start >> 5), c = w0 >> 2;
+        // the ring holds the current chunk and the next; the one after is
+        // in flight
+        put_chunk(c, load_chunk(c));
+        put_chunk(c + 1, load_chunk(c + 1));
+        pend = load_chunk(c + 2);
+        w = w0;
+        nw = ring[(w & (kRing - 1)) * kDecLanes];
+        buf = (uint64_t)nw << 32;
+        advance();
+        buf |= nw;
+        advance();
+        const uint32_t skip = (uint32_t)(start & 31);
+        buf <<= skip;
+        nb = 64 - skip;
+    }
+    // make at least 33 bits available (two codewords of <= 12 bits follow)
+    __device__ __forceinline__ void refill() {
+        if (nb <= 32) {
+            buf |= (uint64_t)nw << (32 - nb);
+            nb += 32;
+            advance();
         }
-#pragma unroll
-        for (int k = 0; k < kWin; k++) win[k * kDecLanes] = w[k];
     }
-    // the 64 stream bits starting at the current position, MSB first
-    __device__ __forceinline__ uint64_t peek64() const {
-        const uint32_t wi = rel >> 5, sh = rel & 31;
-        const uint32_t w0 = win[wi * kDecLanes], w1 = win[(wi + 1) * kDecLanes];
-        return (((uint64_t)w0 << 32) | w1) << sh;
+    // bits consumed since `start` (init fed two words)
+    __device__ __forceinline__ uint64_t consumed(uint64_t start) const {
+        return (uint64_t)w * 32 - nb - (start & ~31ull);
     }
-    __device__ __forceinline__ uint64_t bitpos() const { return aw * 32 + rel; }
 };
 
-// The block's outliers are read four at a time from the position-sorted
-// list into registers (positions p, residuals v); past the end of the list
-// positions read as 0xFFFFFFFF.
-__device__ __forceinline__ void load_outliers(const uint32_t* __restrict__ opos, const int32_t* __restrict__ oval,
-                                              uint64_t n, uint32_t i, uint4& p, int4& v) {
-    if ((uint64_t)i + 4 <= n) {
-        // the list start is only 4-byte aligned: four dword loads
-        p = make_uint4(opos[i], opos[i + 1], opos[i + 2], opos[i + 3]);
-        v = make_int4(oval[i], oval[i + 1], oval[i + 2], oval[i + 3]);
-    } else {
-        p.x = (uint64_t)i < n ? opos[i] : 0xFFFFFFFFu;
-        p.y = (uint64_t)i + 1 < n ? opos[i + 1] : 0xFFFFFFFFu;
-        p.z = (uint64_t)i + 2 < n ? opos[i + 2] : 0xFFFFFFFFu;
-        p.w = 0xFFFFFFFFu;
-        v.x = (uint64_t)i < n ? oval[i] : 0;
-        v.y = (uint64_t)i + 1 < n ? oval[i + 1] : 0;
-        v.z = (uint64_t)i + 2 < n ? oval[i + 2] : 0;
-        v.w = 0;
+// One codeword: returns the table entry (length << 10 | symbol); a lane
+// with valid == false consumes nothing.
+__device__ __forceinline__ uint32_t dec_sym(LaneDec& ld, const uint16_t* LUT, bool valid) {
+    const uint32_t e = LUT[(uint32_t)(ld.buf >> (64 - kLmax))];
+    const uint32_t len = valid ? (e >> 10) : 0u;
+    ld.buf <<= len;
+    ld.nb -= len;
+    return e;
+}
+
+// The block's outliers: the k-th outlier code of a block takes the k-th
+// entry of the block's part of the position-sorted list.  The next value is
+// prefetched into a register; positions are checked in aggregate (a hash
+// sum over the codes met against one over the list, and sortedness of the
+// list), not one by one.
+struct OutQ {
+    const int32_t* oval;
+    uint64_t n_out;
+    uint32_t oi;    // list index of the next outlier
+    int32_t next;   // its value
+    uint64_t hash;  // sum of pos_hash over the outlier codes met
+    __device__ __forceinline__ void init(const int32_t* v, uint64_t n, uint32_t first) {
+        oval = v;
+        n_out = n;
+        oi = first;
+        hash = 0;
+        next = n ? v[first < n ? first : n - 1] : 0;
+    }
+    __device__ __forceinline__ int32_t take(uint32_t pos) {
+        const int32_t d = next;
+        hash += pos_hash(pos);
+        oi++;
+        if (n_out) next = oval[(uint64_t)oi < n_out ? oi : (uint32_t)(n_out - 1)];
+        return d;
+    }
+};
+
+// Decode one row of 8 values (the first nvalid are real) into d[].
+__device__ __forceinline__ void dec_row8(LaneDec& ld, const uint16_t* LUT, uint32_t nvalid, uint32_t pos0,
+                                         OutQ& oq, int32_t d[8]) {
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        if ((i & 1) == 0) ld.refill();
+        const bool valid = (uint32_t)i < nvalid;
+        const uint32_t e = dec_sym(ld, LUT, valid);
+        const uint32_t sym = e & 1023u;
+        d[i] = valid ? (int32_t)sym - kRadius : 0;
+        if (valid && sym == 0) d[i] = oq.take(pos0 + i);
+    }
+}
+
+// Wave totals of the outlier consistency data to Misc.
+__device__ __forceinline__ void outlier_totals(uint32_t lane, bool active, const OutQ& oq, uint32_t oi0,
+                                               Misc* misc) {
+    uint32_t c = active ? oq.oi - oi0 : 0u;
+    uint64_t h = active ? oq.hash : 0ull;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        c += __shfl_xor(c, d, 64);
+        h += __shfl_xor(h, d, 64);
+    }
+    if (lane == 0 && c) {
+        atomicAdd(&misc->code0_count, c);
+        atomicAdd((unsigned long long*)&misc->ohash_dec, (unsigned long long)h);
     }
 }
 
@@ -137,7 +213,7 @@ __global__ __launch_bounds__(256) void k_decode(
     const int32_t* __restrict__ oval, const uint32_t* __restrict__ ofirst, uint64_t n_out, double e2,
     float* __restrict__ out, int vec, Misc* misc) {
     __shared__ uint16_t LUT[kLut];
-    __shared__ uint32_t WIN[kDecLanes * kWin];
+    __shared__ uint32_t RING[kDecLanes * kRing];
     const uint32_t t = threadIdx.x;
     for (uint32_t i = t; i < (uint32_t)kLut; i += 256) LUT[i] = lut_g[i];
     __syncthreads();
@@ -146,45 +222,16 @@ __global__ __launch_bounds__(256) void k_decode(
     const uint32_t b = active ? b0 : g.nblocks - 1;  // inactive lanes idle until the final reduction
     const BlockInfo info = block_info(g, b);
     const uint64_t start = off[b];
-    LaneStream ls;
-    ls.stream = stream;
-    ls.nwords = nwords;
-    ls.win = &WIN[t];
-    uint32_t code0 = 0;
+    LaneDec ld;
+    ld.chunks = reinterpret_cast<const uint4*>(stream);
+    ld.nchunks = (uint32_t)((nwords + 3) / 4);  // >= 1: the host rejects an empty stream
+    ld.ring = &RING[t];
+    ld.init(active ? start : 0);
+    OutQ oq;
+    const uint32_t oi0 = n_out ? ofirst[b] : 0;
+    oq.init(oval, n_out, oi0);
     bool bad = false;
     const uint32_t pos_b = b * kBlockElems;
-    // the block's outliers are consecutive in the position-sorted list,
-    // starting at ofirst[b] (meaningful only for blocks that have outliers:
-    // every use is bounds- and position-checked)
-    uint32_t onext = 0, ok = 0;
-    uint4 op4 = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
-    int4 ov4 = make_int4(0, 0, 0, 0);
-    if (n_out) {
-        onext = ofirst[b];
-        load_outliers(opos, oval, n_out, onext, op4, ov4);
-    }
-
-    // decode one codeword; code 0 takes the next outlier residual
-    auto next = [&](uint32_t pos) -> int32_t {
-        const uint64_t v = ls.peek64();
-        const uint32_t e = LUT[(uint32_t)(v >> (64 - kLmax))];
-        ls.rel += e >> 10;
-        const uint32_t sym = e & 1023u;
-        if (sym) return (int32_t)sym - kRadius;
-        code0++;
-        const uint32_t pk = ok == 0 ? op4.x : ok == 1 ? op4.y : ok == 2 ? op4.z : op4.w;
-        int32_t d = ok == 0 ? ov4.x : ok == 1 ? ov4.y : ok == 2 ? ov4.z : ov4.w;
-        if (pk != pos) {
-            bad = true;
-            d = 0;
-        }
-        if (++ok == 4) {
-            onext += 4;
-            ok = 0;
-            load_outliers(opos, oval, n_out, onext, op4, ov4);
-        }
-        return d;
-    };
     auto deq = [&](int32_t q) -> float { return (float)((double)q * e2); };
     auto store8 = [&](uint64_t idx, const float* v, uint32_t nvalid) {
         if (nvalid == 8 && vec) {
@@ -200,12 +247,11 @@ __global__ __launch_bounds__(256) void k_decode(
         }
     };
 
-    ls.aw = 0;
-    ls.rel = 0;
-    uint64_t bp = start;
     if (!active) {
         // nothing to decode
     } else if (ND == 3) {
+        // q(x, y, z) = sum over the box; kept as the previous plane qp,
+        // the column sums pr of this plane and the row sum rs
         int32_t qp[64];
 #pragma unroll
         for (int i = 0; i < 64; i++) qp[i] = 0;
@@ -215,28 +261,22 @@ __global__ __launch_bounds__(256) void k_decode(
 #pragma unroll
             for (int i = 0; i < 8; i++) pr[i] = 0;
 #pragma unroll
-            for (int half = 0; half < 2; half++) {
-                ls.stage(bp);
+            for (int y = 0; y < 8; y++) {
+                if ((uint32_t)y < info.ey) {
+                    int32_t d[8];
+                    dec_row8(ld, LUT, info.ex, pos_b + 8 * y + 64 * z, oq, d);
+                    int32_t rs = 0;
+                    float v[8];
 #pragma unroll
-                for (int yy = 0; yy < 4; yy++) {
-                    const int y = half * 4 + yy;
-                    if ((uint32_t)y < info.ey) {
-                        int32_t rs = 0;
-                        float v[8];
-#pragma unroll
-                        for (int x = 0; x < 8; x++) {
-                            int32_t d = 0;
-                            if ((uint32_t)x < info.ex) d = next(pos_b + x + 8 * y + 64 * z);
-                            rs += d;
-                            pr[x] += rs;
-                            qp[y * 8 + x] += pr[x];
-                            v[x] = deq(qp[y * 8 + x]);
-                        }
-                        const uint64_t yg = (uint64_t)info.by * 8 + y, zg = (uint64_t)info.bz * 8 + z;
-                        store8(x0 + (uint64_t)g.n[0] * (yg + (uint64_t)g.n[1] * zg), v, info.ex);
+                    for (int x = 0; x < 8; x++) {
+                        rs += d[x];
+                        pr[x] += rs;
+                        qp[y * 8 + x] += pr[x];
+                        v[x] = deq(qp[y * 8 + x]);
                     }
+                    const uint64_t yg = (uint64_t)info.by * 8 + y, zg = (uint64_t)info.bz * 8 + z;
+                    store8(x0 + (uint64_t)g.n[0] * (yg + (uint64_t)g.n[1] * zg), v, info.ex);
                 }
-                bp = ls.bitpos();
             }
         }
     } else if (ND == 2) {
@@ -244,53 +284,44 @@ __global__ __launch_bounds__(256) void k_decode(
 #pragma unroll
         for (int i = 0; i < 32; i++) qp[i] = 0;
         for (uint32_t y = 0; y < info.ey; y++) {
-            ls.stage(bp);
             int32_t rs = 0;
             const uint64_t row = (uint64_t)info.bx * 32 + (uint64_t)g.n[0] * ((uint64_t)info.by * 16 + y);
 #pragma unroll
             for (int x8 = 0; x8 < 4; x8++) {
-                float v[8];
+                if ((uint32_t)(x8 * 8) < info.ex) {
+                    int32_t d[8];
+                    const uint32_t nv = min(8u, info.ex - x8 * 8);
+                    dec_row8(ld, LUT, nv, pos_b + 32 * y + 8 * x8, oq, d);
+                    float v[8];
 #pragma unroll
-                for (int i = 0; i < 8; i++) {
-                    const int x = x8 * 8 + i;
-                    int32_t d = 0;
-                    if ((uint32_t)x < info.ex) d = next(pos_b + x + 32 * y);
-                    rs += d;
-                    qp[x] += rs;
-                    v[i] = deq(qp[x]);
+                    for (int i = 0; i < 8; i++) {
+                        rs += d[i];
+                        qp[x8 * 8 + i] += rs;
+                        v[i] = deq(qp[x8 * 8 + i]);
+                    }
+                    store8(row + x8 * 8, v, nv);
                 }
-                if ((uint32_t)(x8 * 8) < info.ex) store8(row + x8 * 8, v, min(8u, info.ex - x8 * 8));
             }
-            bp = ls.bitpos();
         }
     } else {
         int32_t acc = 0;
         const uint64_t row = (uint64_t)b * kBlockElems;
-        for (uint32_t r = 0; r * 32 < info.ex; r++) {
-            ls.stage(bp);
+        for (uint32_t i0 = 0; i0 < info.ex; i0 += 8) {
+            int32_t d[8];
+            const uint32_t nv = min(8u, info.ex - i0);
+            dec_row8(ld, LUT, nv, pos_b + i0, oq, d);
+            float v[8];
 #pragma unroll
-            for (int k8 = 0; k8 < 4; k8++) {
-                float v[8];
-#pragma unroll
-                for (int i = 0; i < 8; i++) {
-                    const uint32_t idx = r * 32 + k8 * 8 + i;
-                    int32_t d = 0;
-                    if (idx < info.ex) d = next(pos_b + idx);
-                    acc += d;
-                    v[i] = deq(acc);
-                }
-                const uint32_t i0 = r * 32 + k8 * 8;
-                if (i0 < info.ex) store8(row + i0, v, min(8u, info.ex - i0));
+            for (int i = 0; i < 8; i++) {
+                acc += d[i];
+                v[i] = deq(acc);
             }
-            bp = ls.bitpos();
+            store8(row + i0, v, nv);
         }
     }
-    if (active && bp - start != chunks[b]) bad = true;
+    if (active && ld.consumed(start) != chunks[b]) bad = true;
     if (bad) atomicOr(&misc->flags, F_CORRUPT);
-    uint32_t c = active ? code0 : 0u;
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
-    if ((t & 63) == 0 && c) atomicAdd(&misc->code0_count, c);
+    outlier_totals(t & 63, active, oq, oi0, misc);
 }
 
 // ---------------------------------------------- per-block predictor decode
@@ -318,7 +349,7 @@ __global__ __launch_bounds__(256) void k_decode_res(Geom g, const uint32_t* __re
                                                     const uint32_t* __restrict__ ofirst, uint64_t n_out,
                                                     int32_t* __restrict__ res, Misc* misc) {
     __shared__ uint16_t LUT[kLut];
-    __shared__ uint32_t WIN[kDecLanes * kWin];
+    __shared__ uint32_t RING[kDecLanes * kRing];
     const uint32_t t = threadIdx.x;
     for (uint32_t i = t; i < (uint32_t)kLut; i += 256) LUT[i] = lut_g[i];
     __syncthreads();
@@ -327,63 +358,33 @@ __global__ __launch_bounds__(256) void k_decode_res(Geom g, const uint32_t* __re
     const uint32_t b = active ? b0 : g.nblocks - 1;
     const BlockInfo info = block_info(g, b);
     const uint64_t start = off[b];
-    LaneStream ls;
-    ls.stream = stream;
-    ls.nwords = nwords;
-    ls.win = &WIN[t];
-    uint32_t code0 = 0;
+    LaneDec ld;
+    ld.chunks = reinterpret_cast<const uint4*>(stream);
+    ld.nchunks = (uint32_t)((nwords + 3) / 4);  // >= 1: the host rejects an empty stream
+    ld.ring = &RING[t];
+    ld.init(active ? start : 0);
+    OutQ oq;
+    const uint32_t oi0 = n_out ? ofirst[b] : 0;
+    oq.init(oval, n_out, oi0);
     bool bad = false;
     const uint32_t pos_b = b * kBlockElems;
-    uint32_t onext = 0, ok = 0;
-    uint4 op4 = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
-    int4 ov4 = make_int4(0, 0, 0, 0);
-    if (n_out) {
-        onext = ofirst[b];
-        load_outliers(opos, oval, n_out, onext, op4, ov4);
-    }
-    uint64_t bp = start;
     if (active) {
-        ls.stage(bp);
-        uint32_t cnt = 0;
+        // rows of 8 along x in block order; residuals stored block-major
         for (uint32_t lz = 0; lz < info.ez; lz++)
             for (uint32_t ly = 0; ly < info.ey; ly++)
-                for (uint32_t lx = 0; lx < info.ex; lx++) {
-                    if (cnt == 32) {
-                        bp = ls.bitpos();
-                        ls.stage(bp);
-                        cnt = 0;
-                    }
-                    const uint32_t pos = pos_b + lx + g.bs[0] * (ly + g.bs[1] * lz);
-                    const uint64_t v = ls.peek64();
-                    const uint32_t e = LUT[(uint32_t)(v >> (64 - kLmax))];
-                    ls.rel += e >> 10;
-                    const uint32_t sym = e & 1023u;
-                    int32_t d = (int32_t)sym - kRadius;
-                    if (!sym) {
-                        code0++;
-                        const uint32_t pk = ok == 0 ? op4.x : ok == 1 ? op4.y : ok == 2 ? op4.z : op4.w;
-                        d = ok == 0 ? ov4.x : ok == 1 ? ov4.y : ok == 2 ? ov4.z : ov4.w;
-                        if (pk != pos) {
-                            bad = true;
-                            d = 0;
-                        }
-                        if (++ok == 4) {
-                            onext += 4;
-                            ok = 0;
-                            load_outliers(opos, oval, n_out, onext, op4, ov4);
-                        }
-                    }
-                    res[pos] = d;
-                    cnt++;
+                for (uint32_t lx0 = 0; lx0 < info.ex; lx0 += 8) {
+                    int32_t d[8];
+                    const uint32_t nv = min(8u, info.ex - lx0);
+                    const uint32_t pos0 = pos_b + lx0 + g.bs[0] * (ly + g.bs[1] * lz);
+                    dec_row8(ld, LUT, nv, pos0, oq, d);
+                    int4* dst = reinterpret_cast<int4*>(res + pos0);
+                    dst[0] = make_int4(d[0], d[1], d[2], d[3]);
+                    dst[1] = make_int4(d[4], d[5], d[6], d[7]);
                 }
-        bp = ls.bitpos();
     }
-    if (active && bp - start != chunks[b]) bad = true;
+    if (active && ld.consumed(start) != chunks[b]) bad = true;
     if (bad) atomicOr(&misc->flags, F_CORRUPT);
-    uint32_t c = active ? code0 : 0u;
-#pragma unroll
-    for (int dd = 32; dd > 0; dd >>= 1) c += __shfl_xor(c, dd, 64);
-    if ((t & 63) == 0 && c) atomicAdd(&misc->code0_count, c);
+    outlier_totals(t & 63, active, oq, oi0, misc);
 }
 
 // One wave (workgroup of 64) per block: residuals -> grid values in LDS by
@@ -494,13 +495,25 @@ __global__ __launch_bounds__(64) void k_inverse(Geom g, const int32_t* __restric
 
 // ------------------------------------------------------ outlier block index
 // ofirst[b] = index of the first outlier of block b (blocks with outliers).
+// First list index of each block's outliers; the list must be strictly
+// increasing; the sum of pos_hash over the list for the decode-side check.
 __global__ __launch_bounds__(256) void k_outlier_index(const uint32_t* __restrict__ opos, uint64_t n_out,
-                                                       uint32_t nblocks, uint32_t* __restrict__ ofirst) {
+                                                       uint32_t nblocks, uint32_t* __restrict__ ofirst, Misc* misc) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t h = 0;
+    bool bad = false;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_out; i += stride) {
-        const uint32_t b = opos[i] >> 9;
-        if (b < nblocks && (i == 0 || (opos[i - 1] >> 9) != b)) ofirst[b] = (uint32_t)i;
+        const uint32_t p = opos[i];
+        const uint32_t b = p >> 9;
+        const uint32_t prev = i ? opos[i - 1] : 0u;
+        bad |= (i && prev >= p) || b >= nblocks;
+        h += pos_hash(p);
+        if (b < nblocks && (i == 0 || (prev >> 9) != b)) ofirst[b] = (uint32_t)i;
     }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) h += __shfl_xor(h, d, 64);
+    if ((threadIdx.x & 63) == 0 && h) atomicAdd((unsigned long long*)&misc->ohash_list, (unsigned long long)h);
+    if (bad) atomicOr(&misc->flags, F_CORRUPT);
 }
 
 // ----------------------------------------------------------------- patches
@@ -543,7 +556,7 @@ void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64
     if (n_out) {
         uint64_t og = (n_out + 255) / 256;
         if (og > 4096) og = 4096;
-        hipLaunchKernelGGL(k_outlier_index, dim3((uint32_t)og), dim3(256), 0, st, opos, n_out, g.nblocks, ofirst);
+        hipLaunchKernelGGL(k_outlier_index, dim3((uint32_t)og), dim3(256), 0, st, opos, n_out, g.nblocks, ofirst, misc);
     }
     const uint32_t grid = (g.nblocks + 255) / 256;
     if (g.ndim == 3)
@@ -569,7 +582,7 @@ void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, u
     if (n_out) {
         uint64_t og = (n_out + 255) / 256;
         if (og > 4096) og = 4096;
-        hipLaunchKernelGGL(k_outlier_index, dim3((uint32_t)og), dim3(256), 0, st, opos, n_out, g.nblocks, ofirst);
+        hipLaunchKernelGGL(k_outlier_index, dim3((uint32_t)og), dim3(256), 0, st, opos, n_out, g.nblocks, ofirst, misc);
     }
     const uint32_t grid = (g.nblocks + 255) / 256;
 #define FZ_DRES(NDV)                                                                                              \
