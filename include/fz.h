@@ -146,6 +146,49 @@ const char *fz_stage_name(fz_ctx *ctx, int i);
  * successful fz_compress call on this context (Sec. 3.2). */
 int fz_last_histogram(fz_ctx *ctx, uint32_t *h_hist);
 
+/* ------------------------------------------------------------------ batches
+ * Many fields of any shapes, bounds and predictors in one call.  The
+ * fields' kernel sequences run as a few concurrent chains (one stream and
+ * one set of scratch per chain, fields assigned longest first), captured
+ * once into a HIP graph and replayed while the batch's description
+ * (parameters, pointers, launch knobs) stays the same; one synchronisation
+ * per call.  The paper's CUDASTF pipeline runs branches of one field's
+ * pipeline concurrently (Sec. 3.3.1); here whole fields run concurrently.
+ * Containers are identical to those of fz_compress. */
+
+/* Bytes the output of fz_compress_batch must hold: the sum of each field's
+ * fz_compress_bound rounded up to 16.  0 if any parameter set is invalid. */
+uint64_t fz_compress_batch_bound(uint32_t n, const fz_params *p);
+
+/* Compress n fields: params p[n], d_in[n] (host array of device pointers).
+ * The containers are written back to back into d_out (device, 16-byte
+ * aligned, out_cap >= fz_compress_batch_bound), each starting on a 16-byte
+ * boundary with zero bytes up to it; h_offsets (host, n + 1 entries)
+ * receives container i's start, h_offsets[n] the end of the last.  The
+ * containers go through device scratch owned by the context (the batch's
+ * bound in bytes).  Synchronises `stream` once.  The first failing field's
+ * status is returned. */
+int fz_compress_batch(fz_ctx *ctx, uint32_t n, const fz_params *p, const float *const *d_in, void *d_out,
+                      uint64_t out_cap, uint64_t *h_offsets, void *stream);
+
+/* Decompress n containers packed as fz_compress_batch writes them: d_in
+ * (device), h_offsets (host, n + 1), into d_out[n] (host array of device
+ * pointers) of out_elems[n] floats each.  Synchronises `stream` twice
+ * (headers, end). */
+int fz_decompress_batch(fz_ctx *ctx, uint32_t n, const void *d_in, const uint64_t *h_offsets, float *const *d_out,
+                        const uint64_t *out_elems, void *stream);
+
+/* Autotuner: times this batch under each chain count (1, 2, 4, 8, 16, at
+ * most n) and workgroups-per-CU setting of the quantiser and encoders (4,
+ * 8, 16) and keeps the fastest for batches of the same class (log2 of the
+ * field count and of the total value count) and for the fields' classes
+ * (dimensionality, log2 of the value count, bound mode, predictor).  These
+ * knobs never change a container.  Runs the batch (writing d_out) several
+ * times.  fz_batch_tuning reports the setting a batch would use. */
+int fz_batch_autotune(fz_ctx *ctx, uint32_t n, const fz_params *p, const float *const *d_in, void *d_out,
+                      uint64_t out_cap, void *stream);
+int fz_batch_tuning(fz_ctx *ctx, uint32_t n, const fz_params *p, uint32_t *h_chains, uint32_t *h_wg_per_cu);
+
 /* ------------------------------------------------ per-block predictor choice
  * The paper leaves choosing a predictor per block automatically to future
  * work (Sec. 5); these calls expose the pieces of that choice.

@@ -6,7 +6,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <map>
 #include <new>
+#include <vector>
 
 #include "../../include/fz.h"
 #include "fz_common.h"
@@ -28,6 +30,29 @@ hipError_t grow(T*& p, uint64_t& cap, uint64_t need) {
     if (e == hipSuccess) cap = need;
     return e;
 }
+
+// Launch configuration knobs that leave the output unchanged (the tile
+// assignment is static, so any grid gives the same container).
+constexpr int kMaxChains = 16;
+
+// A captured batch: replayed while the batch's description is unchanged.
+struct GraphCache {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint8_t> key;
+    void drop() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        key.clear();
+    }
+};
+
+struct Tune {
+    uint32_t wg_per_cu;     // quantiser / encoder / trial workgroups per CU
+    uint32_t mm_wg_per_cu;  // min/max workgroups per CU
+};
 
 }  // namespace
 
@@ -89,6 +114,30 @@ struct fz_ctx {
     // selector network parameters (device copy, kSelectorParams floats)
     float* sel = nullptr;
     bool have_sel = false;
+    // launch configuration of single calls
+    Tune tune_default = {8, 16};
+    // batches: child contexts with their own scratch and stream (one chain
+    // of fields each), staging of the containers, per-field records, the
+    // captured graph of the last batch and the autotuner's choices
+    fz_ctx* kids[kMaxChains] = {};
+    hipStream_t kstream[kMaxChains] = {};
+    hipEvent_t kev[kMaxChains + 1] = {};
+    int nkids = 0;
+    uint8_t* stage = nullptr;
+    uint64_t stage_cap = 0;
+    uint64_t* rec = nullptr;   // 5 u64 per field
+    uint64_t* offs = nullptr;  // n + 1
+    uint64_t rec_cap = 0, offs_cap = 0;
+    uint64_t* h_rec = nullptr;  // pinned copies
+    uint64_t* h_offs = nullptr;
+    uint64_t h_rec_cap = 0, h_offs_cap = 0;
+    uint8_t* hdrs = nullptr;  // gathered headers (device) and pinned copy
+    uint8_t* h_hdrs = nullptr;
+    uint64_t hdrs_cap = 0, h_hdrs_cap = 0;
+    hipStream_t cstream = nullptr;  // origin stream of graph captures
+    GraphCache gc, gd;              // compress / decompress batches
+    std::map<uint32_t, Tune> tune_field;   // per field class
+    std::map<uint32_t, uint32_t> tune_chains;  // per batch class
 };
 
 namespace {
@@ -300,6 +349,152 @@ int parse_header(const uint8_t* h, uint64_t n, Parsed* r) {
     return FZ_OK;
 }
 
+int compress_check(fz_ctx* c, const fz_params* p, const float* d_in, const void* d_out, uint64_t out_cap, Geom* g) {
+    int rc = check_params(p, g);
+    if (rc) return rc;
+    if (((uintptr_t)d_in & 3) || ((uintptr_t)d_out & 15)) return FZ_ERR_ARG;
+    if (out_cap < bound_of(*g)) return FZ_ERR_CAPACITY;
+    if (p->pred == FZ_PRED_AUTO_MLP && !c->have_sel) return FZ_ERR_UNSUPPORTED;
+    return FZ_OK;
+}
+
+int compress_prepare(fz_ctx* c, const fz_params* p, const Geom& g) {
+    int rc = ensure(c, g);
+    if (rc == FZ_OK && p->pred != FZ_PRED_LORENZO1) rc = ensure_pred(c, g, false);
+    return rc;
+}
+
+// Every kernel of one compression on `st` (no host synchronisation; the
+// container size ends in c->misc->total_bytes, the verbatim container is
+// written on the device).
+void compress_enqueue(fz_ctx* c, const fz_params* p, const Geom& g, const float* d_in, uint8_t* out, hipStream_t st,
+                      const Tune& tn, bool marks) {
+    auto mark = [&](const char* name) {
+        if (marks) t_mark(c, st, name);
+    };
+    const uint32_t pred = p->pred;
+    const bool has_map = pred_has_map(pred);
+    const uint32_t ntiles = (g.nblocks + kTileBlocks - 1) / kTileBlocks;
+    const int vec = (((uintptr_t)d_in & 15) == 0) && (g.ndim == 1 || (g.n[0] & 3) == 0);
+    const uint32_t sd_tiles = scan_tiles(ntiles);
+    const uint32_t gmax = (uint32_t)c->n_cu * tn.wg_per_cu;
+    const int grid = (int)(ntiles < gmax ? ntiles : gmax);
+    // section offsets known before the map: fixed predictors; a mapped
+    // container gets them from the map scan
+    const uint64_t nreg_fixed = pred == FZ_PRED_REGRESSION ? g.nblocks : 0;
+    const Layout L0 = make_layout(g.nblocks, has_map, nreg_fixed, 0, 0, 0);
+    const uint32_t sd_blocks = has_map ? scan_tiles(g.nblocks) : 0;
+    launch_reset(st, c->misc, c->hist, c->desc_cnt, sd_tiles, c->desc_bits, sd_tiles, c->desc_pmap, sd_blocks,
+                 L0.chunks, L0.stream, nreg_fixed);
+    mark("reset");
+    if (p->eb_mode == FZ_EB_REL) {
+        uint64_t work = (g.N + 16 * 256 - 1) / (16 * 256);
+        const uint64_t mmax = (uint64_t)c->n_cu * tn.mm_wg_per_cu;
+        uint64_t mgrid = work < mmax ? work : mmax;
+        if (mgrid < 1) mgrid = 1;
+        launch_minmax(st, d_in, g.N, (((uintptr_t)d_in & 15) == 0), c->misc, (int)mgrid);
+        mark("minmax");
+    }
+    if (pred == FZ_PRED_AUTO_TRIAL) {
+        // reference code: the Huffman code of the first-order Lorenzo
+        // histogram; then every block tries the three predictors
+        launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt,
+                     c->opos, c->oval, c->ppos, c->pbits, 0, nullptr, nullptr);
+        launch_codebook(st, c->hist, c->lens_ref, c->cw_ref, c->misc);
+        launch_trial(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, ntiles, c->cw_ref, c->bpred, c->costs);
+        launch_fill32(st, c->hist, kBins, 0);
+        mark("trial");
+    }
+    if (pred == FZ_PRED_AUTO_MLP) {
+        // the network chooses each block's predictor inside the quantiser
+        launch_quant_select(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles,
+                            c->tile_cnt, c->opos, c->oval, c->ppos, c->pbits, c->sel, c->bpred, c->coef);
+    } else {
+        const int fixed = has_map ? -1 : (int)pred;
+        launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt,
+                     c->opos, c->oval, c->ppos, c->pbits, fixed, c->bpred, c->coef);
+    }
+    mark("quant");
+    if (has_map) {
+        launch_scan(st, SCAN_PMAP, c->bpred, g.nblocks, c->reg_idx, c->desc_pmap, &c->misc->mtile_ctr, c->misc, 0);
+        mark("scan_map");
+    }
+    launch_scan(st, SCAN_COUNTS, c->tile_cnt, ntiles, c->tile_off, c->desc_cnt, &c->misc->qtile_ctr, c->misc, 0);
+    mark("scan_counts");
+    launch_codebook(st, c->hist, out + kHdr, c->cw, c->misc);
+    mark("codebook");
+    launch_encode_len(st, grid, c->codes, g, c->cw, ntiles, out, c->misc, c->tile_bits);
+    mark("encode_len");
+    launch_scan(st, SCAN_BITS, c->tile_bits, ntiles, c->tile_start, c->desc_bits, &c->misc->etile_ctr, c->misc, 0);
+    mark("scan_bits");
+    launch_encode_write(st, grid, c->codes, g, c->cw, c->misc, ntiles, out, c->tile_start, c->tfirst, c->tlast);
+    mark("encode_write");
+    launch_finalize(st, g, p->eb_mode, p->eb, pred, c->misc, out, ntiles, c->tile_start, c->tfirst, c->tlast,
+                    c->tile_cnt, c->tile_off, c->opos, c->oval, c->ppos, c->pbits, c->bpred, c->reg_idx, c->coef);
+    launch_verbatim(st, g, p->eb_mode, p->eb, pred, c->misc, d_in, out);
+    mark("finalize");
+}
+
+int decompress_prepare(fz_ctx* c, const Parsed& r) {
+    if (r.verbatim) return FZ_OK;
+    int rc = ensure(c, r.g);
+    if (rc == FZ_OK && r.p.pred != FZ_PRED_LORENZO1) rc = ensure_pred(c, r.g, true);
+    return rc;
+}
+
+// Every kernel of one decompression on `st` (no host synchronisation).
+void decompress_enqueue(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_out, hipStream_t st, bool marks) {
+    auto mark = [&](const char* name) {
+        if (marks) t_mark(c, st, name);
+    };
+    const Geom& g = r.g;
+    if (r.verbatim) {
+        launch_copy(st, in + kHdr, d_out, g.N);
+        mark("copy");
+        return;
+    }
+    const uint32_t pred = r.p.pred;
+    const bool has_map = pred_has_map(pred);
+    const Layout L = make_layout(r.nblocks, has_map, r.nreg, r.words, r.nout, r.npat);
+    const uint32_t stiles = scan_tiles(g.nblocks);
+    const int vec = (((uintptr_t)d_out & 15) == 0) && (g.ndim == 1 || (g.n[0] & 3) == 0);
+    launch_reset(st, c->misc, c->hist, c->desc_chunks, stiles, has_map ? c->desc_pmap : nullptr,
+                 has_map ? stiles : 0, nullptr, 0, L.chunks, L.stream, r.nreg);
+    mark("reset");
+    launch_lut(st, in + L.lens, c->lut, c->misc);
+    mark("lut");
+    launch_scan(st, SCAN_CHUNKS, in + L.chunks, g.nblocks, c->off, c->desc_chunks, &c->misc->stile_ctr, c->misc,
+                r.bits);
+    mark("scan");
+    if (pred == FZ_PRED_LORENZO1) {
+        launch_decode(st, g, (const uint32_t*)(in + L.stream), r.words, c->off, (const uint16_t*)(in + L.chunks),
+                      c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->ofirst, r.nout,
+                      2.0 * r.eb_abs, d_out, vec, c->misc);
+    } else {
+        if (has_map) {
+            launch_map_unpack(st, in + L.map, g.nblocks, c->bpred, c->misc);
+            launch_scan(st, SCAN_PMAP, c->bpred, g.nblocks, c->reg_idx, c->desc_pmap, &c->misc->mtile_ctr, c->misc,
+                        0);
+        }
+        launch_decode_pred(st, g, (const uint32_t*)(in + L.stream), r.words, c->off, (const uint16_t*)(in + L.chunks),
+                           c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->ofirst, r.nout,
+                           c->res, has_map ? -1 : (int)pred, c->bpred, c->reg_idx, (const int32_t*)(in + L.coef),
+                           r.nreg, 2.0 * r.eb_abs, d_out, vec, c->misc);
+    }
+    mark("decode");
+    launch_patch(st, g, (const uint32_t*)(in + L.ppos), (const uint32_t*)(in + L.pbits), r.npat, d_out, c->misc);
+    mark("patch");
+}
+
+// Validation results a decode leaves in Misc, against the header.
+int decode_status(const Misc& m, const Parsed& r) {
+    int rc = flags_status(m.flags);
+    if (rc) return rc;
+    if (m.code0_count != r.nout || m.ohash_dec != m.ohash_list) return FZ_ERR_CORRUPT;
+    if (pred_has_map(r.p.pred) && m.nreg != r.nreg) return FZ_ERR_CORRUPT;
+    return FZ_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -370,6 +565,22 @@ void fz_ctx_destroy(fz_ctx* c) {
     hipFree(c->cw_ref);
     hipFree(c->lens_ref);
     hipFree(c->sel);
+    c->gc.drop();
+    c->gd.drop();
+    for (int k = 0; k < c->nkids; k++) {
+        fz_ctx_destroy(c->kids[k]);
+        if (c->kstream[k]) hipStreamDestroy(c->kstream[k]);
+    }
+    for (int k = 0; k <= kMaxChains; k++)
+        if (c->kev[k]) hipEventDestroy(c->kev[k]);
+    if (c->cstream) hipStreamDestroy(c->cstream);
+    hipFree(c->stage);
+    hipFree(c->rec);
+    hipFree(c->offs);
+    hipFree(c->hdrs);
+    if (c->h_rec) hipHostFree(c->h_rec);
+    if (c->h_offs) hipHostFree(c->h_offs);
+    if (c->h_hdrs) hipHostFree(c->h_hdrs);
     hipFree(c->desc_pmap);
     hipFree(c->res);
     if (c->h_misc) hipHostFree(c->h_misc);
@@ -390,81 +601,15 @@ int fz_compress(fz_ctx* c, const fz_params* p, const float* d_in, void* d_out, u
     if (h_out_bytes) *h_out_bytes = 0;
     if (!c || !d_in || !d_out || !h_out_bytes) return FZ_ERR_ARG;
     Geom g;
-    int rc = check_params(p, &g);
+    int rc = compress_check(c, p, d_in, d_out, out_cap, &g);
     if (rc) return rc;
-    if (((uintptr_t)d_in & 3) || ((uintptr_t)d_out & 15)) return FZ_ERR_ARG;
-    if (out_cap < bound_of(g)) return FZ_ERR_CAPACITY;
     DeviceGuard dg(c->device);
-    rc = ensure(c, g);
+    rc = compress_prepare(c, p, g);
     if (rc) return rc;
-    const uint32_t pred = p->pred;
-    const bool has_map = pred_has_map(pred);
-    if (pred == FZ_PRED_AUTO_MLP && !c->have_sel) return FZ_ERR_UNSUPPORTED;
-    if (pred != FZ_PRED_LORENZO1) {
-        rc = ensure_pred(c, g, false);
-        if (rc) return rc;
-    }
     hipStream_t st = (hipStream_t)stream;
-    uint8_t* out = (uint8_t*)d_out;
-    const uint32_t ntiles = (g.nblocks + kTileBlocks - 1) / kTileBlocks;
-    const int vec = (((uintptr_t)d_in & 15) == 0) && (g.ndim == 1 || (g.n[0] & 3) == 0);
-    const uint32_t sd_tiles = scan_tiles(ntiles);
-    const int grid = (int)(ntiles < (uint32_t)c->n_cu * 8 ? ntiles : (uint32_t)c->n_cu * 8);
     c->have_hist = false;
-
-    // section offsets known before the map: fixed predictors; a mapped
-    // container gets them from the map scan
-    const uint64_t nreg_fixed = pred == FZ_PRED_REGRESSION ? g.nblocks : 0;
-    const Layout L0 = make_layout(g.nblocks, has_map, nreg_fixed, 0, 0, 0);
-    const uint32_t sd_blocks = has_map ? scan_tiles(g.nblocks) : 0;
     t_begin(c, st);
-    launch_reset(st, c->misc, c->hist, c->desc_cnt, sd_tiles, c->desc_bits, sd_tiles, c->desc_pmap, sd_blocks,
-                 L0.chunks, L0.stream, nreg_fixed);
-    t_mark(c, st, "reset");
-    if (p->eb_mode == FZ_EB_REL) {
-        uint64_t work = (g.N + 16 * 256 - 1) / (16 * 256);
-        uint64_t mgrid = work < (uint64_t)c->n_cu * 16 ? work : (uint64_t)c->n_cu * 16;
-        if (mgrid < 1) mgrid = 1;
-        launch_minmax(st, d_in, g.N, (((uintptr_t)d_in & 15) == 0), c->misc, (int)mgrid);
-        t_mark(c, st, "minmax");
-    }
-    if (pred == FZ_PRED_AUTO_TRIAL) {
-        // reference code: the Huffman code of the first-order Lorenzo
-        // histogram; then every block tries the three predictors
-        launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt,
-                     c->opos, c->oval, c->ppos, c->pbits, 0, nullptr, nullptr);
-        launch_codebook(st, c->hist, c->lens_ref, c->cw_ref, c->misc);
-        launch_trial(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, ntiles, c->cw_ref, c->bpred, c->costs);
-        launch_fill32(st, c->hist, kBins, 0);
-        t_mark(c, st, "trial");
-    }
-    if (pred == FZ_PRED_AUTO_MLP) {
-        // the network chooses each block's predictor inside the quantiser
-        launch_quant_select(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles,
-                            c->tile_cnt, c->opos, c->oval, c->ppos, c->pbits, c->sel, c->bpred, c->coef);
-    } else {
-        const int fixed = has_map ? -1 : (int)pred;
-        launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt,
-                     c->opos, c->oval, c->ppos, c->pbits, fixed, c->bpred, c->coef);
-    }
-    t_mark(c, st, "quant");
-    if (has_map) {
-        launch_scan(st, SCAN_PMAP, c->bpred, g.nblocks, c->reg_idx, c->desc_pmap, &c->misc->mtile_ctr, c->misc, 0);
-        t_mark(c, st, "scan_map");
-    }
-    launch_scan(st, SCAN_COUNTS, c->tile_cnt, ntiles, c->tile_off, c->desc_cnt, &c->misc->qtile_ctr, c->misc, 0);
-    t_mark(c, st, "scan_counts");
-    launch_codebook(st, c->hist, out + kHdr, c->cw, c->misc);
-    t_mark(c, st, "codebook");
-    launch_encode_len(st, grid, c->codes, g, c->cw, ntiles, out, c->misc, c->tile_bits);
-    t_mark(c, st, "encode_len");
-    launch_scan(st, SCAN_BITS, c->tile_bits, ntiles, c->tile_start, c->desc_bits, &c->misc->etile_ctr, c->misc, 0);
-    t_mark(c, st, "scan_bits");
-    launch_encode_write(st, grid, c->codes, g, c->cw, c->misc, ntiles, out, c->tile_start, c->tfirst, c->tlast);
-    t_mark(c, st, "encode_write");
-    launch_finalize(st, g, p->eb_mode, p->eb, pred, c->misc, out, ntiles, c->tile_start, c->tfirst, c->tlast,
-                    c->tile_cnt, c->tile_off, c->opos, c->oval, c->ppos, c->pbits, c->bpred, c->reg_idx, c->coef);
-    t_mark(c, st, "finalize");
+    compress_enqueue(c, p, g, d_in, (uint8_t*)d_out, st, c->tune_default, true);
     if (hipMemcpyAsync(c->h_misc, c->misc, sizeof(Misc), hipMemcpyDeviceToHost, st) != hipSuccess) return FZ_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
     if (hipGetLastError() != hipSuccess) return FZ_ERR_HIP;
@@ -473,31 +618,6 @@ int fz_compress(fz_ctx* c, const fz_params* p, const float* d_in, void* d_out, u
     rc = flags_status(m.flags & ~(uint32_t)F_CORRUPT);
     if (rc) return rc;
     c->have_hist = true;
-    if (m.verbatim) {
-        double eb_abs;
-        resolve_eb(p->eb_mode, p->eb, m.mm_lo, m.mm_hi, &eb_abs);
-        uint8_t* h = c->h_hdr;
-        memset(h, 0, kHdr);
-        st32(h, 0, kMagic);
-        h[4] = (uint8_t)kVersion;
-        h[5] = (uint8_t)(kVersion >> 8);
-        h[6] = 1;
-        st32(h, 8, g.ndim);
-        st32(h, 12, pred);
-        st64(h, 16, g.n[0]);
-        st64(h, 24, g.n[1]);
-        st64(h, 32, g.n[2]);
-        st32(h, 40, p->eb_mode);
-        st32(h, 44, kRadius);
-        st64(h, 48, f64_bits(p->eb));
-        st64(h, 56, f64_bits(eb_abs));
-        st64(h, 64, (uint64_t)kHdr + 4 * g.N);
-        if (hipMemcpyAsync(out, h, kHdr, hipMemcpyHostToDevice, st) != hipSuccess) return FZ_ERR_HIP;
-        if (hipMemcpyAsync(out + kHdr, d_in, 4 * g.N, hipMemcpyDeviceToDevice, st) != hipSuccess) return FZ_ERR_HIP;
-        if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
-        *h_out_bytes = (uint64_t)kHdr + 4 * g.N;
-        return FZ_OK;
-    }
     *h_out_bytes = m.total_bytes;
     return FZ_OK;
 }
@@ -530,63 +650,16 @@ int fz_decompress(fz_ctx* c, const void* d_in, uint64_t in_bytes, const void* h_
     int rc = parse_header(hh, kHdr, &r);
     if (rc) return rc;
     if (r.total > in_bytes) return FZ_ERR_CORRUPT;
-    const Geom& g = r.g;
-    if (out_elems < g.N) return FZ_ERR_CAPACITY;
-    t_begin(c, st);
-    if (r.verbatim) {
-        if (hipMemcpyAsync(d_out, in + kHdr, 4 * g.N, hipMemcpyDeviceToDevice, st) != hipSuccess) return FZ_ERR_HIP;
-        t_mark(c, st, "copy");
-        if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
-        t_end(c);
-        return FZ_OK;
-    }
-    rc = ensure(c, g);
+    if (out_elems < r.g.N) return FZ_ERR_CAPACITY;
+    rc = decompress_prepare(c, r);
     if (rc) return rc;
-    const uint32_t pred = r.p.pred;
-    const bool has_map = pred_has_map(pred);
-    if (pred != FZ_PRED_LORENZO1) {
-        rc = ensure_pred(c, g, true);
-        if (rc) return rc;
-    }
-    const Layout L = make_layout(r.nblocks, has_map, r.nreg, r.words, r.nout, r.npat);
-    const uint32_t stiles = scan_tiles(g.nblocks);
-    const int vec = (((uintptr_t)d_out & 15) == 0) && (g.ndim == 1 || (g.n[0] & 3) == 0);
-    launch_reset(st, c->misc, c->hist, c->desc_chunks, stiles, has_map ? c->desc_pmap : nullptr,
-                 has_map ? stiles : 0, nullptr, 0, L.chunks, L.stream, r.nreg);
-    t_mark(c, st, "reset");
-    launch_lut(st, in + L.lens, c->lut, c->misc);
-    t_mark(c, st, "lut");
-    launch_scan(st, SCAN_CHUNKS, in + L.chunks, g.nblocks, c->off, c->desc_chunks, &c->misc->stile_ctr, c->misc,
-                r.bits);
-    t_mark(c, st, "scan");
-    if (pred == FZ_PRED_LORENZO1) {
-        launch_decode(st, g, (const uint32_t*)(in + L.stream), r.words, c->off, (const uint16_t*)(in + L.chunks),
-                      c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->ofirst, r.nout,
-                      2.0 * r.eb_abs, d_out, vec, c->misc);
-    } else {
-        if (has_map) {
-            launch_map_unpack(st, in + L.map, g.nblocks, c->bpred, c->misc);
-            launch_scan(st, SCAN_PMAP, c->bpred, g.nblocks, c->reg_idx, c->desc_pmap, &c->misc->mtile_ctr, c->misc,
-                        0);
-        }
-        launch_decode_pred(st, g, (const uint32_t*)(in + L.stream), r.words, c->off, (const uint16_t*)(in + L.chunks),
-                           c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->ofirst, r.nout,
-                           c->res, has_map ? -1 : (int)pred, c->bpred, c->reg_idx, (const int32_t*)(in + L.coef),
-                           r.nreg, 2.0 * r.eb_abs, d_out, vec, c->misc);
-    }
-    t_mark(c, st, "decode");
-    launch_patch(st, g, (const uint32_t*)(in + L.ppos), (const uint32_t*)(in + L.pbits), r.npat, d_out, c->misc);
-    t_mark(c, st, "patch");
+    t_begin(c, st);
+    decompress_enqueue(c, r, in, d_out, st, true);
     if (hipMemcpyAsync(c->h_misc, c->misc, sizeof(Misc), hipMemcpyDeviceToHost, st) != hipSuccess) return FZ_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
     if (hipGetLastError() != hipSuccess) return FZ_ERR_HIP;
     t_end(c);
-    const Misc m = *c->h_misc;
-    rc = flags_status(m.flags);
-    if (rc) return rc;
-    if (m.code0_count != r.nout || m.ohash_dec != m.ohash_list) return FZ_ERR_CORRUPT;
-    if (has_map && m.nreg != r.nreg) return FZ_ERR_CORRUPT;
-    return FZ_OK;
+    return r.verbatim ? FZ_OK : decode_status(*c->h_misc, r);
 }
 
 uint64_t fz_block_count(const fz_params* p) {
@@ -847,6 +920,409 @@ int fz_selector_grad(fz_ctx* c, const float* d_feat, const float* d_target, uint
          hipStreamSynchronize(st) == hipSuccess && hipGetLastError() == hipSuccess;
     if (!ok) return FZ_ERR_HIP;
     if (h_loss) *h_loss = loss;
+    return FZ_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+hipError_t grow_pinned(void** p, uint64_t& cap, uint64_t need) {
+    if (need <= cap && *p) return hipSuccess;
+    if (*p) hipHostFree(*p);
+    *p = nullptr;
+    cap = 0;
+    hipError_t e = hipHostMalloc(p, need ? need : 1, hipHostMallocDefault);
+    if (e == hipSuccess) cap = need;
+    return e;
+}
+
+uint32_t ilog2_ceil(uint64_t v) {
+    uint32_t l = 0;
+    while ((1ull << l) < v && l < 63) l++;
+    return l;
+}
+
+// Field class of the tuning cache: dimensionality, size bucket (log2 of
+// the value count), bound mode and predictor.
+uint32_t field_class(const fz_params* p, const Geom& g) {
+    return (g.ndim << 16) | (ilog2_ceil(g.N) << 8) | (p->eb_mode << 4) | (p->pred & 15);
+}
+
+uint32_t batch_class(uint32_t n, uint64_t total) { return (ilog2_ceil(n) << 8) | ilog2_ceil(total); }
+
+int ensure_kids(fz_ctx* c, int k) {
+    if (!c->cstream && hipStreamCreateWithFlags(&c->cstream, hipStreamNonBlocking) != hipSuccess) return FZ_ERR_HIP;
+    for (int i = 0; i <= kMaxChains; i++)
+        if (!c->kev[i] && hipEventCreateWithFlags(&c->kev[i], hipEventDisableTiming) != hipSuccess) return FZ_ERR_HIP;
+    while (c->nkids < k) {
+        fz_ctx* kid = nullptr;
+        int rc = fz_ctx_create(&kid, c->device, 0);
+        if (rc) return rc;
+        if (hipStreamCreateWithFlags(&c->kstream[c->nkids], hipStreamNonBlocking) != hipSuccess) {
+            fz_ctx_destroy(kid);
+            return FZ_ERR_HIP;
+        }
+        c->kids[c->nkids++] = kid;
+    }
+    return FZ_OK;
+}
+
+// Longest-processing-time assignment of fields to K chains by value count
+// (ties by field index: deterministic).
+std::vector<std::vector<uint32_t>> assign_chains(uint32_t n, const std::vector<Geom>& g, int K) {
+    std::vector<uint32_t> order(n);
+    for (uint32_t i = 0; i < n; i++) order[i] = i;
+    for (uint32_t i = 1; i < n; i++)  // insertion sort by N descending, stable
+        for (uint32_t j = i; j > 0 && g[order[j]].N > g[order[j - 1]].N; j--) {
+            const uint32_t t = order[j];
+            order[j] = order[j - 1];
+            order[j - 1] = t;
+        }
+    std::vector<std::vector<uint32_t>> chains(K);
+    std::vector<uint64_t> load(K, 0);
+    for (uint32_t i : order) {
+        int best = 0;
+        for (int k = 1; k < K; k++)
+            if (load[k] < load[best]) best = k;
+        chains[best].push_back(i);
+        load[best] += g[i].N + 65536;
+    }
+    return chains;
+}
+
+template <class T>
+void key_put(std::vector<uint8_t>& k, const T& v) {
+    const uint8_t* b = reinterpret_cast<const uint8_t*>(&v);
+    k.insert(k.end(), b, b + sizeof(T));
+}
+
+// Every scratch pointer of a context (a captured graph holds them).
+void key_scratch(std::vector<uint8_t>& k, const fz_ctx* c) {
+    const void* ps[] = {c->misc, c->hist, c->cw, c->lut, c->codes, c->opos, c->oval, c->ppos, c->pbits,
+                        c->tile_cnt, c->tile_off, c->tile_bits, c->tile_start, c->tfirst, c->tlast, c->desc_cnt,
+                        c->desc_bits, c->desc_chunks, c->off, c->ofirst, c->bpred, c->reg_idx, c->coef, c->costs,
+                        c->cw_ref, c->lens_ref, c->desc_pmap, c->res, c->sel};
+    for (const void* q : ps) key_put(k, q);
+}
+
+Tune tune_of(fz_ctx* c, const fz_params* p, const Geom& g) {
+    auto it = c->tune_field.find(field_class(p, g));
+    return it == c->tune_field.end() ? c->tune_default : it->second;
+}
+
+int default_chains(uint32_t n) { return (int)(n < 8 ? n : 8); }
+
+int chains_of(fz_ctx* c, uint32_t n, uint64_t total) {
+    auto it = c->tune_chains.find(batch_class(n, total));
+    return it == c->tune_chains.end() ? default_chains(n) : (int)it->second;
+}
+
+struct BatchIn {
+    uint32_t n;
+    const fz_params* p;
+    const float* const* x;
+    std::vector<Geom> g;
+    std::vector<uint64_t> slot;  // staging offsets, slot[n] = total
+};
+
+int batch_check(fz_ctx* c, uint32_t n, const fz_params* p, const float* const* d_in, BatchIn* b) {
+    b->n = n;
+    b->p = p;
+    b->x = d_in;
+    b->g.resize(n);
+    b->slot.assign(n + 1, 0);
+    for (uint32_t i = 0; i < n; i++) {
+        if (!d_in[i]) return FZ_ERR_ARG;
+        int rc = check_params(&p[i], &b->g[i]);
+        if (rc) return rc;
+        if ((uintptr_t)d_in[i] & 3) return FZ_ERR_ARG;
+        if (p[i].pred == FZ_PRED_AUTO_MLP && !c->have_sel) return FZ_ERR_UNSUPPORTED;
+        b->slot[i + 1] = b->slot[i] + align16(bound_of(b->g[i]));
+    }
+    return FZ_OK;
+}
+
+// Run (capturing first if the batch differs from the cached one) a batch
+// compression with K chains and the given per-field launch knobs.
+int batch_compress_run(fz_ctx* c, const BatchIn& b, uint8_t* d_out, hipStream_t st, int K,
+                       const std::vector<Tune>& tunes) {
+    const uint32_t n = b.n;
+    int rc = ensure_kids(c, K);
+    if (rc) return rc;
+    hipError_t e = grow(c->stage, c->stage_cap, b.slot[n]);
+    if (e == hipSuccess) e = grow(c->rec, c->rec_cap, 5ull * n);
+    if (e == hipSuccess) e = grow(c->offs, c->offs_cap, (uint64_t)n + 1);
+    if (e == hipSuccess) e = grow_pinned((void**)&c->h_rec, c->h_rec_cap, 40ull * n);
+    if (e == hipSuccess) e = grow_pinned((void**)&c->h_offs, c->h_offs_cap, 8ull * (n + 1));
+    if (e != hipSuccess) return FZ_ERR_NOMEM;
+    const auto chains = assign_chains(n, b.g, K);
+    bool need_sel = false;
+    for (uint32_t i = 0; i < n; i++) need_sel |= b.p[i].pred == FZ_PRED_AUTO_MLP;
+    for (int k = 0; k < K; k++) {
+        fz_ctx* kid = c->kids[k];
+        if (need_sel) {
+            if (hipMemcpy(kid->sel, c->sel, sizeof(float) * kSelectorParams, hipMemcpyDeviceToDevice) != hipSuccess)
+                return FZ_ERR_HIP;
+            kid->have_sel = true;
+        }
+        for (uint32_t i : chains[k]) {
+            rc = compress_prepare(kid, &b.p[i], b.g[i]);
+            if (rc) return rc;
+        }
+    }
+    std::vector<uint8_t> key;
+    key_put(key, n);
+    key_put(key, K);
+    key_put(key, d_out);
+    key_put(key, c->stage);
+    key_put(key, c->rec);
+    for (uint32_t i = 0; i < n; i++) {
+        key_put(key, b.p[i]);
+        key_put(key, b.x[i]);
+        key_put(key, tunes[i]);
+    }
+    for (int k = 0; k < K; k++) key_scratch(key, c->kids[k]);  // scratch may have moved
+    if (key != c->gc.key || !c->gc.exec) {
+        c->gc.drop();
+        hipStream_t cs = c->cstream;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return FZ_ERR_HIP;
+        hipEventRecord(c->kev[kMaxChains], cs);
+        for (int k = 0; k < K; k++) hipStreamWaitEvent(c->kstream[k], c->kev[kMaxChains], 0);
+        for (int k = 0; k < K; k++)
+            for (uint32_t i : chains[k]) {
+                compress_enqueue(c->kids[k], &b.p[i], b.g[i], b.x[i], c->stage + b.slot[i], c->kstream[k], tunes[i],
+                                 false);
+                launch_field_record(c->kstream[k], c->kids[k]->misc, b.slot[i], c->rec + 3ull * i, 0);
+            }
+        for (int k = 0; k < K; k++) {
+            hipEventRecord(c->kev[k], c->kstream[k]);
+            hipStreamWaitEvent(cs, c->kev[k], 0);
+        }
+        launch_pack(cs, c->stage, c->rec, c->offs, n, d_out);
+        hipMemcpyAsync(c->h_rec, c->rec, 24ull * n, hipMemcpyDeviceToHost, cs);
+        hipMemcpyAsync(c->h_offs, c->offs, 8ull * (n + 1), hipMemcpyDeviceToHost, cs);
+        hipGraph_t graph = nullptr;
+        if (hipStreamEndCapture(cs, &graph) != hipSuccess || !graph) {
+            hipGetLastError();
+            return FZ_ERR_HIP;
+        }
+        c->gc.graph = graph;
+        if (hipGraphInstantiate(&c->gc.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            c->gc.drop();
+            return FZ_ERR_HIP;
+        }
+        c->gc.key = key;
+    }
+    if (hipGraphLaunch(c->gc.exec, st) != hipSuccess) return FZ_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
+    if (hipGetLastError() != hipSuccess) return FZ_ERR_HIP;
+    for (uint32_t i = 0; i < n; i++) {
+        rc = flags_status((uint32_t)c->h_rec[3 * i + 2] & ~(uint32_t)F_CORRUPT);
+        if (rc) return rc;
+    }
+    return FZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t fz_compress_batch_bound(uint32_t n, const fz_params* p) {
+    if (!n || !p) return 0;
+    uint64_t t = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        Geom g;
+        if (check_params(&p[i], &g) != FZ_OK) return 0;
+        t += align16(bound_of(g));
+    }
+    return t;
+}
+
+int fz_compress_batch(fz_ctx* c, uint32_t n, const fz_params* p, const float* const* d_in, void* d_out,
+                      uint64_t out_cap, uint64_t* h_offsets, void* stream) {
+    if (!c || !n || !p || !d_in || !d_out || !h_offsets || ((uintptr_t)d_out & 15)) return FZ_ERR_ARG;
+    BatchIn b;
+    int rc = batch_check(c, n, p, d_in, &b);
+    if (rc) return rc;
+    if (out_cap < b.slot[n]) return FZ_ERR_CAPACITY;
+    DeviceGuard dg(c->device);
+    std::vector<Tune> tunes(n);
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        tunes[i] = tune_of(c, &p[i], b.g[i]);
+        total += b.g[i].N;
+    }
+    rc = batch_compress_run(c, b, (uint8_t*)d_out, (hipStream_t)stream, chains_of(c, n, total), tunes);
+    if (rc) return rc;
+    for (uint32_t i = 0; i <= n; i++) h_offsets[i] = c->h_offs[i];
+    return FZ_OK;
+}
+
+int fz_batch_autotune(fz_ctx* c, uint32_t n, const fz_params* p, const float* const* d_in, void* d_out,
+                      uint64_t out_cap, void* stream) {
+    if (!c || !n || !p || !d_in || !d_out || ((uintptr_t)d_out & 15)) return FZ_ERR_ARG;
+    BatchIn b;
+    int rc = batch_check(c, n, p, d_in, &b);
+    if (rc) return rc;
+    if (out_cap < b.slot[n]) return FZ_ERR_CAPACITY;
+    DeviceGuard dg(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return FZ_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return FZ_ERR_HIP;
+    }
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < n; i++) total += b.g[i].N;
+    const int ks[] = {1, 2, 4, 8, 16};
+    const uint32_t wgs[] = {4, 8, 16};
+    float best = 1e30f;
+    int bestk = default_chains(n);
+    uint32_t bestw = c->tune_default.wg_per_cu;
+    for (int K : ks) {
+        if (K > (int)n || K > kMaxChains) continue;
+        for (uint32_t w : wgs) {
+            std::vector<Tune> tunes(n, Tune{w, c->tune_default.mm_wg_per_cu});
+            rc = batch_compress_run(c, b, (uint8_t*)d_out, st, K, tunes);  // capture + warm-up
+            if (rc) break;
+            hipEventRecord(e0, st);
+            for (int r = 0; r < 3 && rc == FZ_OK; r++)
+                if (hipGraphLaunch(c->gc.exec, st) != hipSuccess) rc = FZ_ERR_HIP;
+            hipEventRecord(e1, st);
+            if (rc || hipEventSynchronize(e1) != hipSuccess) {
+                rc = rc ? rc : FZ_ERR_HIP;
+                break;
+            }
+            float ms = 0.0f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                bestk = K;
+                bestw = w;
+            }
+        }
+        if (rc) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    c->tune_chains[batch_class(n, total)] = (uint32_t)bestk;
+    for (uint32_t i = 0; i < n; i++) c->tune_field[field_class(&p[i], b.g[i])] = Tune{bestw, c->tune_default.mm_wg_per_cu};
+    return FZ_OK;
+}
+
+int fz_batch_tuning(fz_ctx* c, uint32_t n, const fz_params* p, uint32_t* h_chains, uint32_t* h_wg_per_cu) {
+    if (!c || !n || !p) return FZ_ERR_ARG;
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        Geom g;
+        if (check_params(&p[i], &g) != FZ_OK) return FZ_ERR_ARG;
+        total += g.N;
+        if (h_wg_per_cu) h_wg_per_cu[i] = tune_of(c, &p[i], g).wg_per_cu;
+    }
+    if (h_chains) *h_chains = (uint32_t)chains_of(c, n, total);
+    return FZ_OK;
+}
+
+int fz_decompress_batch(fz_ctx* c, uint32_t n, const void* d_in, const uint64_t* h_offsets, float* const* d_out,
+                        const uint64_t* out_elems, void* stream) {
+    if (!c || !n || !d_in || !h_offsets || !d_out || !out_elems || ((uintptr_t)d_in & 15)) return FZ_ERR_ARG;
+    for (uint32_t i = 0; i < n; i++) {
+        if (!d_out[i] || ((uintptr_t)d_out[i] & 3)) return FZ_ERR_ARG;
+        if ((h_offsets[i] & 15) || h_offsets[i + 1] < h_offsets[i] + kHdr) return FZ_ERR_CORRUPT;
+    }
+    DeviceGuard dg(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    const uint8_t* in = (const uint8_t*)d_in;
+    hipError_t e = grow(c->offs, c->offs_cap, (uint64_t)n + 1);
+    if (e == hipSuccess) e = grow(c->hdrs, c->hdrs_cap, (uint64_t)kHdr * n);
+    if (e == hipSuccess) e = grow(c->rec, c->rec_cap, 5ull * n);
+    if (e == hipSuccess) e = grow_pinned((void**)&c->h_hdrs, c->h_hdrs_cap, (uint64_t)kHdr * n);
+    if (e == hipSuccess) e = grow_pinned((void**)&c->h_offs, c->h_offs_cap, 8ull * (n + 1));
+    if (e == hipSuccess) e = grow_pinned((void**)&c->h_rec, c->h_rec_cap, 40ull * n);
+    if (e != hipSuccess) return FZ_ERR_NOMEM;
+    // headers: one gather, one copy, one synchronisation
+    for (uint32_t i = 0; i <= n; i++) c->h_offs[i] = h_offsets[i];
+    if (hipMemcpyAsync(c->offs, c->h_offs, 8ull * (n + 1), hipMemcpyHostToDevice, st) != hipSuccess) return FZ_ERR_HIP;
+    launch_gather_headers(st, in, c->offs, n, c->hdrs);
+    if (hipMemcpyAsync(c->h_hdrs, c->hdrs, (uint64_t)kHdr * n, hipMemcpyDeviceToHost, st) != hipSuccess)
+        return FZ_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
+    std::vector<Parsed> r(n);
+    std::vector<Geom> g(n);
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        int rc = parse_header(c->h_hdrs + (uint64_t)kHdr * i, kHdr, &r[i]);
+        if (rc) return rc;
+        if (r[i].total > h_offsets[i + 1] - h_offsets[i]) return FZ_ERR_CORRUPT;
+        if (out_elems[i] < r[i].g.N) return FZ_ERR_CAPACITY;
+        g[i] = r[i].g;
+        total += g[i].N;
+    }
+    const int K = chains_of(c, n, total);
+    int rc = ensure_kids(c, K);
+    if (rc) return rc;
+    const auto chains = assign_chains(n, g, K);
+    for (int k = 0; k < K; k++)
+        for (uint32_t i : chains[k]) {
+            rc = decompress_prepare(c->kids[k], r[i]);
+            if (rc) return rc;
+        }
+    std::vector<uint8_t> key;
+    key_put(key, n);
+    key_put(key, K);
+    key_put(key, d_in);
+    key.insert(key.end(), c->h_hdrs, c->h_hdrs + (uint64_t)kHdr * n);
+    for (uint32_t i = 0; i < n; i++) {
+        key_put(key, h_offsets[i]);
+        key_put(key, d_out[i]);
+    }
+    for (int k = 0; k < K; k++) key_scratch(key, c->kids[k]);
+    if (key != c->gd.key || !c->gd.exec) {
+        c->gd.drop();
+        hipStream_t cs = c->cstream;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return FZ_ERR_HIP;
+        hipEventRecord(c->kev[kMaxChains], cs);
+        for (int k = 0; k < K; k++) hipStreamWaitEvent(c->kstream[k], c->kev[kMaxChains], 0);
+        for (int k = 0; k < K; k++)
+            for (uint32_t i : chains[k]) {
+                decompress_enqueue(c->kids[k], r[i], in + h_offsets[i], d_out[i], c->kstream[k], false);
+                if (!r[i].verbatim) launch_field_record(c->kstream[k], c->kids[k]->misc, 0, c->rec + 5ull * i, 1);
+            }
+        for (int k = 0; k < K; k++) {
+            hipEventRecord(c->kev[k], c->kstream[k]);
+            hipStreamWaitEvent(cs, c->kev[k], 0);
+        }
+        hipMemcpyAsync(c->h_rec, c->rec, 40ull * n, hipMemcpyDeviceToHost, cs);
+        hipGraph_t graph = nullptr;
+        if (hipStreamEndCapture(cs, &graph) != hipSuccess || !graph) {
+            hipGetLastError();
+            return FZ_ERR_HIP;
+        }
+        c->gd.graph = graph;
+        if (hipGraphInstantiate(&c->gd.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            c->gd.drop();
+            return FZ_ERR_HIP;
+        }
+        c->gd.key = key;
+    }
+    if (hipGraphLaunch(c->gd.exec, st) != hipSuccess) return FZ_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
+    if (hipGetLastError() != hipSuccess) return FZ_ERR_HIP;
+    for (uint32_t i = 0; i < n; i++) {
+        if (r[i].verbatim) continue;
+        Misc m = {};
+        const uint64_t* q = c->h_rec + 5ull * i;
+        m.flags = (uint32_t)q[0];
+        m.code0_count = (uint32_t)q[1];
+        m.nreg = q[2];
+        m.ohash_dec = q[3];
+        m.ohash_list = q[4];
+        rc = decode_status(m, r[i]);
+        if (rc) return rc;
+    }
     return FZ_OK;
 }
 

@@ -545,6 +545,30 @@ __global__ __launch_bounds__(256) void k_patch(Geom g, const uint32_t* __restric
 }
 
 // ------------------------------------------------------------- launchers
+// Verbatim container: the raw floats.
+__global__ __launch_bounds__(256) void k_copy(const uint8_t* __restrict__ src, float* __restrict__ dst, uint64_t n,
+                                              int vec) {
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const float* s = reinterpret_cast<const float*>(src);
+    if (vec) {
+        const f32x4* s4 = reinterpret_cast<const f32x4*>(s);
+        f32x4* d4 = reinterpret_cast<f32x4*>(dst);
+        for (uint64_t i = gid; i < n / 4; i += stride) d4[i] = s4[i];
+        for (uint64_t i = (n & ~3ull) + gid; i < n; i += stride) dst[i] = s[i];
+    } else {
+        for (uint64_t i = gid; i < n; i += stride) dst[i] = s[i];
+    }
+}
+
+void launch_copy(hipStream_t st, const uint8_t* src, float* dst, uint64_t n) {
+    const int vec = (((uintptr_t)src | (uintptr_t)dst) & 15) == 0;
+    uint64_t grid = (n / 4 + 255) / 256;
+    if (grid > 2048) grid = 2048;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_copy, dim3((uint32_t)grid), dim3(256), 0, st, src, dst, n, vec);
+}
+
 void launch_lut(hipStream_t st, const uint8_t* lens_packed, uint16_t* lut, Misc* misc) {
     hipLaunchKernelGGL(k_lut, dim3(1), dim3(1024), 0, st, lens_packed, lut, misc);
 }

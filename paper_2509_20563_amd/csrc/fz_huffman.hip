@@ -397,7 +397,57 @@ __global__ __launch_bounds__(256) void k_finalize(Geom g, uint32_t mode, double 
     }
 }
 
+// -------------------------------------------------------------- verbatim
+// When k_finalize chose the verbatim container: header (flag bit 0) and the
+// raw floats.  Nothing happens otherwise, or after an error.
+__global__ __launch_bounds__(256) void k_verbatim(Geom g, uint32_t mode, double eb, uint32_t pred, const Misc* misc,
+                                                  const float* __restrict__ x, uint8_t* __restrict__ out, int vec) {
+    if (!misc->verbatim || (misc->flags & (F_NONFINITE | F_EB | F_INTERNAL | F_TIMEOUT))) return;
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    if (gid == 0) {
+        double eb_abs;
+        resolve_eb(mode, eb, misc->mm_lo, misc->mm_hi, &eb_abs);
+        uint8_t h[kHdr];
+        for (int k = 0; k < kHdr; k++) h[k] = 0;
+        auto st32 = [&](int o, uint32_t v) { for (int k = 0; k < 4; k++) h[o + k] = (uint8_t)(v >> (8 * k)); };
+        auto st64 = [&](int o, uint64_t v) { for (int k = 0; k < 8; k++) h[o + k] = (uint8_t)(v >> (8 * k)); };
+        st32(0, kMagic);
+        h[4] = (uint8_t)kVersion;
+        h[5] = (uint8_t)(kVersion >> 8);
+        h[6] = 1;
+        st32(8, g.ndim);
+        st32(12, pred);
+        st64(16, g.n[0]);
+        st64(24, g.n[1]);
+        st64(32, g.n[2]);
+        st32(40, mode);
+        st32(44, kRadius);
+        st64(48, __double_as_longlong(eb));
+        st64(56, __double_as_longlong(eb_abs));
+        st64(64, (uint64_t)kHdr + 4 * g.N);
+        uint4* dst = reinterpret_cast<uint4*>(out);
+        const uint4* src = reinterpret_cast<const uint4*>(h);
+        for (int k = 0; k < kHdr / 16; k++) dst[k] = src[k];
+    }
+    float* o = reinterpret_cast<float*>(out + kHdr);
+    if (vec) {
+        const f32x4* x4 = reinterpret_cast<const f32x4*>(x);
+        f32x4* o4 = reinterpret_cast<f32x4*>(o);
+        for (uint64_t i = gid; i < g.N / 4; i += stride) o4[i] = x4[i];
+        for (uint64_t i = (g.N & ~3ull) + gid; i < g.N; i += stride) o[i] = x[i];
+    } else {
+        for (uint64_t i = gid; i < g.N; i += stride) o[i] = x[i];
+    }
+}
+
 // ------------------------------------------------------------ launchers
+void launch_verbatim(hipStream_t st, const Geom& g, uint32_t mode, double eb, uint32_t pred, const Misc* misc,
+                     const float* x, uint8_t* out) {
+    const int vec = ((uintptr_t)x & 15) == 0;
+    hipLaunchKernelGGL(k_verbatim, dim3(1024), dim3(256), 0, st, g, mode, eb, pred, misc, x, out, vec);
+}
+
 void launch_codebook(hipStream_t st, const uint32_t* hist, uint8_t* out_lens, uint32_t* cw, Misc* misc) {
     hipLaunchKernelGGL(k_codebook, dim3(1), dim3(1024), 0, st, hist, out_lens, cw, misc);
 }

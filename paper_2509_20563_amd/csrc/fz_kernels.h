@@ -52,7 +52,16 @@ void launch_train_batch(hipStream_t st, const float* w, const float* feat, const
 void launch_adam(hipStream_t st, float* w, float* m, float* v, const float* g, int t, float lr, float b1, float b2,
                  float eps);
 
+void launch_verbatim(hipStream_t st, const Geom& g, uint32_t mode, double eb, uint32_t pred, const Misc* misc,
+                     const float* x, uint8_t* out);
+
+// fz_batch.hip
+void launch_field_record(hipStream_t st, const Misc* misc, uint64_t slot, uint64_t* rec, int decode);
+void launch_pack(hipStream_t st, const uint8_t* stage, const uint64_t* rec, uint64_t* offs, uint32_t n, uint8_t* out);
+void launch_gather_headers(hipStream_t st, const uint8_t* in, const uint64_t* offs, uint32_t n, uint8_t* hdr);
+
 // fz_decode.hip
+void launch_copy(hipStream_t st, const uint8_t* src, float* dst, uint64_t n);
 void launch_lut(hipStream_t st, const uint8_t* lens_packed, uint16_t* lut, Misc* misc);
 void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,
                    const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,

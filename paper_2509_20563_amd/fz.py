@@ -99,6 +99,17 @@ def lib() -> ctypes.CDLL:
     L.fz_selector_save.restype = i32
     L.fz_selector_load.argtypes = [vp, ctypes.c_char_p]
     L.fz_selector_load.restype = i32
+    PP = ctypes.POINTER(Params)
+    L.fz_compress_batch_bound.argtypes = [ctypes.c_uint32, PP]
+    L.fz_compress_batch_bound.restype = u64
+    L.fz_compress_batch.argtypes = [vp, ctypes.c_uint32, PP, vp, vp, u64, vp, vp]
+    L.fz_compress_batch.restype = i32
+    L.fz_decompress_batch.argtypes = [vp, ctypes.c_uint32, vp, vp, vp, vp, vp]
+    L.fz_decompress_batch.restype = i32
+    L.fz_batch_autotune.argtypes = [vp, ctypes.c_uint32, PP, vp, vp, u64, vp]
+    L.fz_batch_autotune.restype = i32
+    L.fz_batch_tuning.argtypes = [vp, ctypes.c_uint32, PP, vp, vp]
+    L.fz_batch_tuning.restype = i32
     L.fz_selector_train.argtypes = [vp, vp, vp, u64, ctypes.POINTER(TrainParams), vp, vp]
     L.fz_selector_train.restype = i32
     L.fz_selector_grad.argtypes = [vp, vp, vp, u64, vp, vp, vp]
@@ -242,6 +253,74 @@ class Context:
         n = ctypes.c_int()
         _check(lib().fz_stage_times(self._h, ms, 16, ctypes.byref(n)), "fz_stage_times")
         return [(lib().fz_stage_name(self._h, i).decode(), float(ms[i])) for i in range(min(n.value, 16))]
+
+    # -------------------------------------------------------------- batches
+    @staticmethod
+    def _batch_params(xs, ebs, modes, preds):
+        n = len(xs)
+        P = (Params * n)()
+        for i, x in enumerate(xs):
+            if x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous():
+                raise ValueError("fields must be contiguous float32 device tensors")
+            P[i] = params_for(x.shape, ebs[i], modes[i], preds[i])
+        return P
+
+    def compress_batch_bound(self, shapes, preds=None) -> int:
+        n = len(shapes)
+        P = (Params * n)()
+        for i, sh in enumerate(shapes):
+            P[i] = params_for(sh, 1.0, EB_REL, 0 if preds is None else preds[i])
+        return int(lib().fz_compress_batch_bound(n, P))
+
+    def compress_batch(self, xs, ebs, modes=None, preds=None, out: torch.Tensor | None = None):
+        """Compress a list of fields in one call: (packed uint8 device tensor, offsets list)."""
+        n = len(xs)
+        modes = [EB_REL] * n if modes is None else list(modes)
+        preds = [PRED_LORENZO1] * n if preds is None else list(preds)
+        P = self._batch_params(xs, list(ebs), modes, preds)
+        cap = int(lib().fz_compress_batch_bound(n, P))
+        if cap == 0:
+            raise FZError(-1, "fz_compress_batch_bound")
+        if out is None:
+            out = torch.empty(cap, dtype=torch.uint8, device=xs[0].device)
+        ptrs = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        offs = (ctypes.c_uint64 * (n + 1))()
+        _check(lib().fz_compress_batch(self._h, n, P, ptrs, ctypes.c_void_p(out.data_ptr()), out.numel(), offs,
+                                       _stream_handle(xs[0].device)), "fz_compress_batch")
+        return out[: offs[n]], list(offs)
+
+    def decompress_batch(self, buf: torch.Tensor, offsets, outs):
+        """Decompress a packed batch into the given float32 device tensors."""
+        n = len(outs)
+        offs = (ctypes.c_uint64 * (n + 1))(*[int(o) for o in offsets])
+        ptrs = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        ne = (ctypes.c_uint64 * n)(*[o.numel() for o in outs])
+        _check(lib().fz_decompress_batch(self._h, n, ctypes.c_void_p(buf.data_ptr()), offs, ptrs, ne,
+                                         _stream_handle(buf.device)), "fz_decompress_batch")
+        return outs
+
+    def batch_autotune(self, xs, ebs, modes=None, preds=None):
+        n = len(xs)
+        modes = [EB_REL] * n if modes is None else list(modes)
+        preds = [PRED_LORENZO1] * n if preds is None else list(preds)
+        P = self._batch_params(xs, list(ebs), modes, preds)
+        cap = int(lib().fz_compress_batch_bound(n, P))
+        out = torch.empty(cap, dtype=torch.uint8, device=xs[0].device)
+        ptrs = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        _check(lib().fz_batch_autotune(self._h, n, P, ptrs, ctypes.c_void_p(out.data_ptr()), cap,
+                                       _stream_handle(xs[0].device)), "fz_batch_autotune")
+        return self.batch_tuning(xs, ebs, modes, preds)
+
+    def batch_tuning(self, xs, ebs, modes=None, preds=None):
+        """(chains, workgroups per CU of each field) the batch would run with."""
+        n = len(xs)
+        modes = [EB_REL] * n if modes is None else list(modes)
+        preds = [PRED_LORENZO1] * n if preds is None else list(preds)
+        P = self._batch_params(xs, list(ebs), modes, preds)
+        k = ctypes.c_uint32()
+        w = (ctypes.c_uint32 * n)()
+        _check(lib().fz_batch_tuning(self._h, n, P, ctypes.byref(k), w), "fz_batch_tuning")
+        return k.value, list(w)
 
     # ------------------------------------------------- per-block predictors
     def block_count(self, shape) -> int:

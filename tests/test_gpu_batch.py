@@ -1,0 +1,111 @@
+"""Batched compression (one graph-captured call for many uneven fields):
+every container equals the single-call container (and the oracle's, for
+the small ones), packing and padding are right, graph replays and
+re-captures give the same bytes, the autotuner never changes a container,
+and batch decompression matches single decompression."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from inputs import fields
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(fz):
+    return fz.Context(0)
+
+
+def _small_batch():
+    out = []
+    for i, (f, eb) in enumerate(fields.batch_2d(n_fields=6, seed=900, hmin=40, hmax=300, wmin=30, wmax=260)):
+        out.append((f, eb, 1, 0))
+    out.append((fields.grf((24, 40, 33), seed=3), 1e-3, 1, 0))
+    out.append((fields.sorted_positions(5003, seed=4), 1e-4, 1, 0))
+    out.append((fields.random_small((10, 11, 13), 5, "noise"), 1e-7, 1, 0))  # verbatim, 1430 values
+    out.append((fields.grf((30, 31, 17), seed=6), 2e-4, 0, 4))              # trial predictor, abs bound
+    out.append((fields.grf((64, 70), seed=7), 1e-3, 1, 2))                  # regression
+    return out
+
+
+def _run(fz, ctx, batch):
+    xs = [torch.from_numpy(np.ascontiguousarray(f)).cuda() for f, _, _, _ in batch]
+    packed, offs = ctx.compress_batch(xs, [b[1] for b in batch], [b[2] for b in batch], [b[3] for b in batch])
+    return xs, packed, offs
+
+
+def test_batch_matches_single_and_oracle(fz, ctx):
+    batch = _small_batch()
+    print(f"[gpu batch] {len(batch)} fields", flush=True)
+    xs, packed, offs = _run(fz, ctx, batch)
+    host = packed.cpu().numpy()
+    assert offs[0] == 0 and all(o % 16 == 0 for o in offs)
+    for i, (f, eb, mode, pred) in enumerate(batch):
+        single = ctx.compress(xs[i], eb, mode, pred=pred).cpu().numpy().tobytes()
+        got = host[offs[i]:offs[i + 1]].tobytes()
+        assert got[:len(single)] == single, f"field {i}"
+        assert all(b == 0 for b in got[len(single):]), f"field {i} padding"
+        assert len(got) == (len(single) + 15) // 16 * 16
+        assert single == oracle.compress(f, eb, mode, pred=pred), f"field {i} vs oracle"
+
+
+def test_batch_replay_and_recapture(fz, ctx):
+    batch = _small_batch()
+    _, p1, o1 = _run(fz, ctx, batch)
+    a = p1.cpu().numpy().tobytes()
+    _, p2, o2 = _run(fz, ctx, batch)  # same description: graph replay
+    assert o1 == o2 and p2.cpu().numpy().tobytes() == a
+    batch[2] = (batch[2][0], batch[2][1] * 2, 1, 0)  # another bound: new capture
+    xs, p3, o3 = _run(fz, ctx, batch)
+    single = ctx.compress(xs[2], batch[2][1], 1).cpu().numpy().tobytes()
+    assert p3.cpu().numpy()[o3[2]:o3[2] + len(single)].tobytes() == single
+
+
+def test_batch_decompress(fz, ctx):
+    batch = _small_batch()
+    xs, packed, offs = _run(fz, ctx, batch)
+    outs = [torch.empty_like(x) for x in xs]
+    ctx.decompress_batch(packed, offs, outs)
+    for i, x in enumerate(xs):
+        c = packed[offs[i]:offs[i + 1]]
+        ref = ctx.decompress(c).cpu().numpy()
+        assert np.array_equal(outs[i].cpu().numpy().view(np.uint32), ref.view(np.uint32)), f"field {i}"
+    # replay of the decompression graph
+    outs2 = [torch.zeros_like(x) for x in xs]
+    ctx.decompress_batch(packed, offs, outs2)
+    for a, b in zip(outs, outs2):
+        assert torch.equal(a, b)
+
+
+def test_autotune_keeps_containers(fz, ctx):
+    batch = _small_batch()
+    xs, p0, o0 = _run(fz, ctx, batch)
+    ref = p0.cpu().numpy().tobytes()
+    k, w = ctx.batch_autotune(xs, [b[1] for b in batch], [b[2] for b in batch], [b[3] for b in batch])
+    print(f"[gpu batch] tuned chains {k} wg/cu {w}", flush=True)
+    assert 1 <= k <= 16 and all(v in (4, 8, 16) for v in w)
+    _, p1, o1 = _run(fz, ctx, batch)
+    assert o1 == o0 and p1.cpu().numpy().tobytes() == ref
+
+
+def test_batch_error_reported(fz, ctx):
+    batch = _small_batch()
+    bad = batch[1][0].copy()
+    bad.flat[7] = np.inf
+    batch[1] = (bad, batch[1][1], 1, 0)
+    with pytest.raises(fz.FZError) as e:
+        _run(fz, ctx, batch)
+    assert e.value.code == -3
+
+
+def test_batch_2d_config_subset(fz, ctx):
+    """Sixteen fields of the uneven 2D batch (shapes up to 3600 x 1800,
+    per-field offsets, scales and bounds): batch equals single calls."""
+    batch = [(f, eb, 1, 0) for f, eb in fields.batch_2d(n_fields=16)]
+    xs, packed, offs = _run(fz, ctx, batch)
+    host = packed.cpu().numpy()
+    for i, (f, eb, mode, pred) in enumerate(batch):
+        single = ctx.compress(xs[i], eb, mode).cpu().numpy().tobytes()
+        assert host[offs[i]:offs[i] + len(single)].tobytes() == single, f"field {i}"
