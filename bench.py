@@ -13,6 +13,16 @@ Per-stage times come from HIP events the library records on the stream
 the kernels run on, inside the timed region.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+
+Other workloads (not the headline line; same JSON keys):
+  --workload selector   1024^3 k^-11/3 field + 64 tanh fronts + 1% log-normal
+                        spikes at rel 1e-4: compress with first-order Lorenzo,
+                        exhaustive per-block trial and the learned selector
+                        (trained first on disjoint seeds, outside the timing)
+  --workload batch2d    64 uneven 2D fields (per-field offset, scale, bound):
+                        one graph-captured batch call vs per-field calls
+  --workload batchmixed 256 mixed 1D/2D/3D fields: batched first-order Lorenzo
+                        vs batched learned selector
 """
 from __future__ import annotations
 
@@ -58,7 +68,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--shape", type=str, default="512,512,512")
+    ap.add_argument("--shape", type=str, default=None)
+    ap.add_argument("--workload", default="roundtrip", choices=["roundtrip", "selector", "batch2d", "batchmixed"])
+    ap.add_argument("--fields", type=int, default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see the design notes on sharding)",
@@ -71,7 +83,9 @@ def main():
     from inputs import fields
     from paper_2509_20563_amd import fz, metrics
 
-    shape = tuple(int(s) for s in args.shape.split(","))
+    if args.workload != "roundtrip":
+        return {"selector": bench_selector, "batch2d": bench_batch2d, "batchmixed": bench_batchmixed}[args.workload](args)
+    shape = tuple(int(s) for s in (args.shape or "512,512,512").split(","))
     n = int(np.prod(shape))
     print(f"[bench] generating {shape} k^-3 field", file=sys.stderr, flush=True)
     x_host = fields.grf(shape, alpha=3.0, seed=2)
@@ -210,6 +224,176 @@ def cpu_baseline(x_host):
             "sample": f"first {sample.shape[0]} z-planes ({'x'.join(map(str, sample.shape))}) of the same field, "
                       f"compress + decompress at rel eb 1e-2/1e-3/1e-4, single-threaded C oracle",
             "seconds": round(dt, 2)}
+
+
+# ------------------------------------------------------------------ helpers
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / steps
+
+
+def _line(metric, value, unit, args, ms, config, higher=True, **extra):
+    d = {"metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1, "steps": args.steps,
+         "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": higher, "scaling": "weak",
+         "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": config}
+    d.update(extra)
+    print(json.dumps(d), flush=True)
+
+
+def train_selector(ctx, fz, device, seeds=(101, 102, 103, 104), edge=128, ebs=(1e-2, 1e-3, 1e-4), epochs=30):
+    """Train the context's selector on fronts/spikes fields of seeds disjoint
+    from the evaluation fields; returns (seconds, first loss, last loss, samples)."""
+    import torch
+    from inputs import fields_gpu
+    feats, costs = [], []
+    for sd in seeds:
+        x = fields_gpu.fronts_spikes((edge, edge, edge), seed=sd, n_fronts=8, device=device)
+        for eb in ebs:
+            feats.append(ctx.block_features(x, eb, fz.EB_REL))
+            costs.append(ctx.block_trial(x, eb, fz.EB_REL)[1])
+    f = torch.cat(feats).contiguous()
+    c = torch.cat(costs).contiguous()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    loss = ctx.selector_train(f, c, epochs=epochs, batch=4096, seed=1)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t, float(loss[0]), float(loss[-1]), int(f.shape[0])
+
+
+def bench_selector(args):
+    import torch
+    from inputs import fields_gpu
+    from paper_2509_20563_amd import fz, metrics
+    dev = torch.device("cuda", 0)
+    shape = tuple(int(s) for s in (args.shape or "1024,1024,1024").split(","))
+    ctx = fz.Context(0)
+    print("[bench] training the selector", file=sys.stderr, flush=True)
+    tsec, l0, l1, ns = train_selector(ctx, fz, dev)
+    print(f"[bench] generating {shape} fronts/spikes field", file=sys.stderr, flush=True)
+    x = fields_gpu.fronts_spikes(shape, seed=3, device=dev)
+    n = x.numel()
+    eb = 1e-4
+    out = torch.empty(ctx.compress_bound(shape), dtype=torch.uint8, device=dev)
+    res = {}
+    for name, pred in (("lorenzo1", fz.PRED_LORENZO1), ("trial", fz.PRED_AUTO_TRIAL), ("selector", fz.PRED_AUTO_MLP)):
+        print(f"[bench] {name}", file=sys.stderr, flush=True)
+        sizes = []
+        dt = _timed(lambda: sizes.append(ctx.compress(x, eb, fz.EB_REL, out=out, pred=pred).numel()),
+                    args.steps, args.warmup)
+        c = out[: sizes[-1]]
+        y = ctx.decompress(c)
+        h = fz.header_fields(c[:128].cpu().numpy().tobytes())
+        err = (y.double() - x.double()).abs().max().item()
+        res[name] = {"compress_gbps": round(metrics.throughput_gbps(n, dt), 2), "bytes": sizes[-1],
+                     "cr": round(metrics.compression_ratio(n, sizes[-1]), 4),
+                     "max_err_over_eb": err / h["eb_abs"], "ms": round(dt * 1e3, 3)}
+        del y
+    sel, tri, p0 = res["selector"], res["trial"], res["lorenzo1"]
+    _line("learned per-block predictor selector: compress GB/s; CR vs exhaustive trial", sel["compress_gbps"],
+          "GB/s", args, sel["ms"],
+          {"workload": f"{'x'.join(map(str, shape))} k^-11/3 field + 64 tanh fronts + 1% log-normal spikes, "
+                       "rel eb 1e-4, 8^3 blocks choose first/second-order Lorenzo or regression", "n_values": n},
+          modes=res, cr_selector_over_trial=round(sel["cr"] / tri["cr"], 4),
+          speed_selector_over_trial=round(sel["compress_gbps"] / tri["compress_gbps"], 3),
+          cr_gain_over_lorenzo1=round(sel["cr"] / p0["cr"], 4),
+          training={"seconds": round(tsec, 2), "samples": ns, "loss_first_epoch": l0, "loss_last_epoch": l1,
+                    "fields": "4 fronts/spikes fields 128^3, seeds 101-104 (evaluation seed 3), rel 1e-2/1e-3/1e-4"})
+
+
+def _bench_batch(args, fz, ctx, batch, label, preds=None):
+    import torch
+    from paper_2509_20563_amd import metrics
+    xs = [f for f, _ in batch]
+    ebs = [eb for _, eb in batch]
+    nf = len(xs)
+    preds = preds or [fz.PRED_LORENZO1] * nf
+    n = sum(x.numel() for x in xs)
+    modes = [fz.EB_REL] * nf
+    print(f"[bench] {label}: autotune", file=sys.stderr, flush=True)
+    k, w = ctx.batch_autotune(xs, ebs, modes, preds)
+    out = torch.empty(ctx.compress_batch_bound([x.shape for x in xs], preds), dtype=torch.uint8, device=xs[0].device)
+    holder = {}
+
+    def run_batch():
+        holder["packed"], holder["offs"] = ctx.compress_batch(xs, ebs, modes, preds, out=out)
+
+    print(f"[bench] {label}: batched", file=sys.stderr, flush=True)
+    tb = _timed(run_batch, args.steps, args.warmup)
+    packed, offs = holder["packed"], holder["offs"]
+    singles = [torch.empty(ctx.compress_bound(x.shape), dtype=torch.uint8, device=x.device) for x in xs]
+
+    def run_single():
+        for i, x in enumerate(xs):
+            ctx.compress(x, ebs[i], fz.EB_REL, out=singles[i], pred=preds[i])
+
+    print(f"[bench] {label}: per-field calls", file=sys.stderr, flush=True)
+    ts = _timed(run_single, args.steps, args.warmup)
+    recs = [torch.empty_like(x) for x in xs]
+    td = _timed(lambda: ctx.decompress_batch(packed, offs, recs), args.steps, args.warmup)
+    hdrs = [packed[offs[i]:offs[i] + 128].cpu().numpy().tobytes() for i in range(nf)]
+
+    def run_single_d():
+        for i in range(nf):
+            ctx.decompress(packed[offs[i]:offs[i + 1]], header=hdrs[i], out=recs[i])
+
+    tsd = _timed(run_single_d, args.steps, args.warmup)
+    worst = 0.0
+    for i in range(nf):
+        h = fz.header_fields(hdrs[i])
+        worst = max(worst, (recs[i].double() - xs[i].double()).abs().max().item() / h["eb_abs"])
+    return {"n_fields": nf, "n_values": n, "bytes_in": 4 * n, "bytes_out": int(offs[-1]),
+            "cr": round(metrics.compression_ratio(n, int(offs[-1])), 4),
+            "tuned_chains": k, "tuned_wg_per_cu": sorted(set(w)),
+            "batch_compress_gbps": round(4 * n / tb / 1e9, 2), "per_field_compress_gbps": round(4 * n / ts / 1e9, 2),
+            "batch_decompress_gbps": round(4 * n / td / 1e9, 2),
+            "per_field_decompress_gbps": round(4 * n / tsd / 1e9, 2),
+            "compress_speedup_batch_over_per_field": round(ts / tb, 3), "max_err_over_eb": worst,
+            "ms_batch_compress": round(tb * 1e3, 3)}
+
+
+def bench_batch2d(args):
+    import torch
+    from inputs import fields_gpu
+    from paper_2509_20563_amd import fz
+    dev = torch.device("cuda", 0)
+    nf = args.fields or 64
+    print(f"[bench] generating {nf} uneven 2D fields", file=sys.stderr, flush=True)
+    batch = fields_gpu.batch_2d(n_fields=nf, device=dev)
+    ctx = fz.Context(0)
+    r = _bench_batch(args, fz, ctx, batch, "batch2d")
+    _line("batched compress GB/s of uneven 2D fields (one graph-captured call) vs per-field calls",
+          r["batch_compress_gbps"], "GB/s", args, r["ms_batch_compress"],
+          {"workload": f"{nf} 2D k^-3 fields, height 256-3600, width 256-1800, per-field offset/scale "
+                       "log-uniform 1e-3..1e3 and rel eb log-uniform 1e-5..1e-2, first-order Lorenzo",
+           "n_values": r["n_values"]}, batch=r)
+
+
+def bench_batchmixed(args):
+    import torch
+    from inputs import fields_gpu
+    from paper_2509_20563_amd import fz
+    dev = torch.device("cuda", 0)
+    nf = args.fields or 256
+    ctx = fz.Context(0)
+    print("[bench] training the selector", file=sys.stderr, flush=True)
+    tsec, l0, l1, ns = train_selector(ctx, fz, dev)
+    print(f"[bench] generating {nf} mixed fields", file=sys.stderr, flush=True)
+    batch = fields_gpu.batch_mixed(n_fields=nf, device=dev)
+    r0 = _bench_batch(args, fz, ctx, batch, "batchmixed lorenzo1")
+    r1 = _bench_batch(args, fz, ctx, batch, "batchmixed selector", preds=[fz.PRED_AUTO_MLP] * nf)
+    _line("batched compress GB/s of a mixed 1D/2D/3D batch with the learned selector; CR vs first-order Lorenzo",
+          r1["batch_compress_gbps"], "GB/s", args, r1["ms_batch_compress"],
+          {"workload": f"{nf} fields: 1D sorted positions 1M-64M values, 2D k^-3 (as the 2D batch), 3D 64^3-384^3 "
+                       "k^-3..k^-5; rel eb log-uniform 1e-5..1e-2", "n_values": r1["n_values"]},
+          selector=r1, lorenzo1=r0, cr_gain_over_lorenzo1=round(r1["cr"] / r0["cr"], 4),
+          training={"seconds": round(tsec, 2), "samples": ns, "loss_first_epoch": l0, "loss_last_epoch": l1})
 
 
 if __name__ == "__main__":

@@ -90,7 +90,8 @@ struct fz_ctx {
     // decode
     uint64_t* off = nullptr;
     uint32_t* ofirst = nullptr;
-    uint64_t off_cap = 0, ofirst_cap = 0;
+    uint32_t* oend = nullptr;
+    uint64_t off_cap = 0, ofirst_cap = 0, oend_cap = 0;
     // per-block predictors: choice, index among regression blocks,
     // coefficients, trial costs, the reference code of the trial, the
     // map-scan descriptors and the residual field of the mapped decoder
@@ -225,6 +226,7 @@ int ensure(fz_ctx* c, const Geom& g) {
     if (e == hipSuccess) e = grow(c->desc_chunks, c->desc_chunks_cap, sd_blocks);
     if (e == hipSuccess) e = grow(c->off, c->off_cap, nb);
     if (e == hipSuccess) e = grow(c->ofirst, c->ofirst_cap, nb);
+    if (e == hipSuccess) e = grow(c->oend, c->oend_cap, nb);
     return e == hipSuccess ? FZ_OK : FZ_ERR_NOMEM;
 }
 
@@ -468,8 +470,8 @@ void decompress_enqueue(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_
     mark("scan");
     if (pred == FZ_PRED_LORENZO1) {
         launch_decode(st, g, (const uint32_t*)(in + L.stream), r.words, c->off, (const uint16_t*)(in + L.chunks),
-                      c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->ofirst, r.nout,
-                      2.0 * r.eb_abs, d_out, vec, c->misc);
+                      c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->ofirst, c->oend,
+                      r.nout, 2.0 * r.eb_abs, d_out, vec, c->misc);
     } else {
         if (has_map) {
             launch_map_unpack(st, in + L.map, g.nblocks, c->bpred, c->misc);
@@ -477,8 +479,8 @@ void decompress_enqueue(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_
                         0);
         }
         launch_decode_pred(st, g, (const uint32_t*)(in + L.stream), r.words, c->off, (const uint16_t*)(in + L.chunks),
-                           c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->ofirst, r.nout,
-                           c->res, has_map ? -1 : (int)pred, c->bpred, c->reg_idx, (const int32_t*)(in + L.coef),
+                           c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->ofirst, c->oend,
+                           r.nout, c->res, has_map ? -1 : (int)pred, c->bpred, c->reg_idx, (const int32_t*)(in + L.coef),
                            r.nreg, 2.0 * r.eb_abs, d_out, vec, c->misc);
     }
     mark("decode");
@@ -558,6 +560,7 @@ void fz_ctx_destroy(fz_ctx* c) {
     hipFree(c->desc_chunks);
     hipFree(c->off);
     hipFree(c->ofirst);
+    hipFree(c->oend);
     hipFree(c->bpred);
     hipFree(c->reg_idx);
     hipFree(c->coef);
@@ -1001,7 +1004,7 @@ void key_put(std::vector<uint8_t>& k, const T& v) {
 void key_scratch(std::vector<uint8_t>& k, const fz_ctx* c) {
     const void* ps[] = {c->misc, c->hist, c->cw, c->lut, c->codes, c->opos, c->oval, c->ppos, c->pbits,
                         c->tile_cnt, c->tile_off, c->tile_bits, c->tile_start, c->tfirst, c->tlast, c->desc_cnt,
-                        c->desc_bits, c->desc_chunks, c->off, c->ofirst, c->bpred, c->reg_idx, c->coef, c->costs,
+                        c->desc_bits, c->desc_chunks, c->off, c->ofirst, c->oend, c->bpred, c->reg_idx, c->coef, c->costs,
                         c->cw_ref, c->lens_ref, c->desc_pmap, c->res, c->sel};
     for (const void* q : ps) key_put(k, q);
 }

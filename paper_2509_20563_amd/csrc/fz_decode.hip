@@ -206,21 +206,27 @@ __device__ __forceinline__ void outlier_totals(uint32_t lane, bool active, const
     }
 }
 
+// Blocks the fast kernels take (full blocks) are skipped when skip is set.
+__device__ __forceinline__ bool is_interior(const BlockInfo& bi, const uint32_t ib[3]) {
+    return bi.bx < ib[0] && bi.by < ib[1] && bi.bz < ib[2];
+}
+
 template <int ND>
 __global__ __launch_bounds__(256) void k_decode(
     Geom g, const uint32_t* __restrict__ stream, uint64_t nwords, const uint64_t* __restrict__ off,
     const uint16_t* __restrict__ chunks, const uint16_t* __restrict__ lut_g, const uint32_t* __restrict__ opos,
     const int32_t* __restrict__ oval, const uint32_t* __restrict__ ofirst, uint64_t n_out, double e2,
-    float* __restrict__ out, int vec, Misc* misc) {
+    float* __restrict__ out, int vec, Misc* misc, int skip, uint32_t ib0, uint32_t ib1, uint32_t ib2) {
     __shared__ uint16_t LUT[kLut];
     __shared__ uint32_t RING[kDecLanes * kRing];
     const uint32_t t = threadIdx.x;
     for (uint32_t i = t; i < (uint32_t)kLut; i += 256) LUT[i] = lut_g[i];
     __syncthreads();
     const uint32_t b0 = blockIdx.x * 256 + t;
-    const bool active = b0 < g.nblocks;
-    const uint32_t b = active ? b0 : g.nblocks - 1;  // inactive lanes idle until the final reduction
+    const uint32_t b = b0 < g.nblocks ? b0 : g.nblocks - 1;  // inactive lanes idle until the final reduction
     const BlockInfo info = block_info(g, b);
+    const uint32_t ib[3] = {ib0, ib1, ib2};
+    const bool active = b0 < g.nblocks && !(skip && is_interior(info, ib));
     const uint64_t start = off[b];
     LaneDec ld;
     ld.chunks = reinterpret_cast<const uint4*>(stream);
@@ -324,6 +330,295 @@ __global__ __launch_bounds__(256) void k_decode(
     outlier_totals(t & 63, active, oq, oi0, misc);
 }
 
+// ------------------------------------------------ fast decode of full blocks
+// Full (interior) blocks of a field whose rows are 16-byte aligned.  The
+// lanes of a wave move through their blocks in lockstep, 8 codewords (one
+// row) at a time, and every lane issues exactly one 16-byte stream load and
+// one 16-byte outlier-value load per row, real or a dummy, landed in its
+// LDS rings two rows later.  With a fixed number of memory operations per
+// row, each wait covers only data requested two rows earlier; the codeword
+// chain itself touches LDS and registers only.  Rings hold 4 chunks: a
+// chunk is fetched only when the chunk it replaces can no longer be read.
+constexpr int kORing = 16;  // outlier values per lane in LDS
+
+struct FastDec {
+    const uint4* S;       // stream chunks
+    uint32_t nch;         // number of stream chunks (>= 1)
+    uint32_t* sr;         // &SRING[lane]; ring word k at sr[k * kDecLanes]
+    uint32_t w, nw;       // next word to feed; its value
+    uint64_t buf;         // bits, most significant first
+    uint32_t nb;          // valid bits in buf
+    uint32_t sF, sEnd;    // next chunk to fetch; last chunk worth fetching
+    uint4 sX[2];          // chunks in flight (by row parity) and their
+    uint32_t sXi[2];      // indices (~0: dummy)
+    const uint4* O;       // outlier values as chunks (16-byte aligned list)
+    uint32_t och;         // number of outlier chunks
+    const int32_t* oval;
+    uint64_t n_out;
+    uint32_t* orr;        // &ORING[lane]
+    uint32_t oi, oend;    // next outlier index, end of the block's outliers
+    uint32_t oF, oL;      // next outlier chunk to fetch; values < oL landed
+    uint4 oX[2];
+    uint32_t oXi[2];
+    uint64_t hash;
+
+    __device__ __forceinline__ void sput(uint32_t k, const uint4& v) {
+        uint32_t* r = sr + ((k & 3) * 4) * kDecLanes;
+        r[0] = v.x;
+        r[kDecLanes] = v.y;
+        r[2 * kDecLanes] = v.z;
+        r[3 * kDecLanes] = v.w;
+    }
+    __device__ __forceinline__ void oput(uint32_t k, const uint4& v) {
+        uint32_t* r = orr + ((k & 3) * 4) * kDecLanes;
+        r[0] = v.x;
+        r[kDecLanes] = v.y;
+        r[2 * kDecLanes] = v.z;
+        r[3 * kDecLanes] = v.w;
+    }
+    __device__ __forceinline__ uint4 sload(uint32_t k) const { return S[k < nch ? k : nch - 1]; }
+
+    __device__ __forceinline__ void init(uint64_t start, uint32_t bits, const int32_t* ov, uint64_t nout,
+                                         uint32_t first, uint32_t count) {
+        const uint32_t w0 = (uint32_t)(start >> 5), c0 = w0 >> 2;
+        const uint4 a = sload(c0), b = sload(c0 + 1), c = sload(c0 + 2);
+        oval = ov;
+        n_out = nout;
+        oi = first;
+        oend = first + count;
+        const uint32_t q0 = first >> 2;
+        const bool any = count != 0 && nout != 0;
+        och = (uint32_t)((nout + 3) / 4);
+        const uint32_t qa = q0 < och ? q0 : och - 1, qb = q0 + 1 < och ? q0 + 1 : och - 1;
+        const uint4 oa = any ? O[qa] : S[0], ob = any ? O[qb] : S[0];
+        sput(c0, a);
+        sput(c0 + 1, b);
+        sput(c0 + 2, c);
+        sF = c0 + 3;
+        sEnd = (uint32_t)((start + bits) >> 7) + 1;
+        oput(q0, oa);
+        oput(q0 + 1, ob);
+        oF = q0 + 2;
+        oL = any ? 4 * (q0 + 2) : 0;
+        sXi[0] = sXi[1] = oXi[0] = oXi[1] = 0xFFFFFFFFu;
+        hash = 0;
+        w = w0;
+        nw = sr[(w & (kRing - 1)) * kDecLanes];
+        buf = (uint64_t)nw << 32;
+        w++;
+        nw = sr[(w & (kRing - 1)) * kDecLanes];
+        buf |= nw;
+        w++;
+        nw = sr[(w & (kRing - 1)) * kDecLanes];
+        const uint32_t skip = (uint32_t)(start & 31);
+        buf <<= skip;
+        nb = 64 - skip;
+    }
+    // row prologue for row parity P: land what row - 2 fetched, fetch anew
+    template <int P>
+    __device__ __forceinline__ void row_io() {
+        if (sXi[P] != 0xFFFFFFFFu) sput(sXi[P], sX[P]);
+        if (oXi[P] != 0xFFFFFFFFu) {
+            oput(oXi[P], oX[P]);
+            oL = 4 * (oXi[P] + 1);
+        }
+        const bool sreal = sF <= (w >> 2) + 3 && sF <= sEnd;
+        sX[P] = sload(sreal ? sF : 0);
+        sXi[P] = sreal ? sF : 0xFFFFFFFFu;
+        sF += sreal ? 1u : 0u;
+        const bool oreal = oF <= (oi >> 2) + 3 && 4 * oF < oend;
+        const uint4* osrc = oreal ? &O[oF] : &S[0];
+        oX[P] = *osrc;
+        oXi[P] = oreal ? oF : 0xFFFFFFFFu;
+        oF += oreal ? 1u : 0u;
+    }
+    __device__ __forceinline__ void refill() {
+        const bool need = nb <= 32;
+        buf |= need ? ((uint64_t)nw << ((32 - nb) & 63)) : 0ull;
+        nb += need ? 32u : 0u;
+        w += need ? 1u : 0u;
+        nw = sr[(w & (kRing - 1)) * kDecLanes];
+    }
+    // 8 codewords of one row.  An outlier value not landed yet (a burst,
+    // or a corrupt container) is fetched after the row by the whole wave,
+    // so no global load sits inside the codeword loop.
+    __device__ __forceinline__ void row8(const uint16_t* LUT, uint32_t pos0, int32_t d[8]) {
+        uint32_t mmask = 0, m0 = 0;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            if ((i & 1) == 0) refill();
+            const uint32_t e = LUT[(uint32_t)(buf >> (64 - kLmax))];
+            const uint32_t len = e >> 10;
+            buf <<= len;
+            nb -= len;
+            const uint32_t sym = e & 1023u;
+            d[i] = (int32_t)sym - kRadius;
+            if (sym == 0) {
+                hash += pos_hash(pos0 + i);
+                if (oi < oL) {
+                    d[i] = (int32_t)orr[(oi & (kORing - 1)) * kDecLanes];
+                } else {
+                    m0 = mmask ? m0 : oi;
+                    mmask |= 1u << i;
+                    d[i] = 0;
+                }
+                oi++;
+            }
+        }
+        if (__ballot(mmask != 0)) {
+#pragma unroll
+            for (int i = 0; i < 8; i++)
+                if (mmask & (1u << i)) {
+                    const uint32_t k = m0 + __popc(mmask & ((1u << i) - 1u));
+                    d[i] = n_out ? oval[(uint64_t)k < n_out ? k : (uint32_t)(n_out - 1)] : 0;
+                }
+            // wait here (vmcnt 0), so that rows without a miss carry no wait
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+        }
+    }
+    __device__ __forceinline__ uint64_t consumed(uint64_t start) const {
+        return (uint64_t)w * 32 - nb - (start & ~31ull);
+    }
+};
+
+// RES = false: inverse Lorenzo, dequantisation and rows of floats;
+// RES = true: residuals (int32, block-major) for the mapped decoder.
+template <int ND, bool RES>
+__global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint32_t ib1, uint32_t nint,
+                                                     const uint32_t* __restrict__ stream, uint64_t nwords,
+                                                     const uint64_t* __restrict__ off,
+                                                     const uint16_t* __restrict__ chunks,
+                                                     const uint16_t* __restrict__ lut_g,
+                                                     const int32_t* __restrict__ oval,
+                                                     const uint32_t* __restrict__ ofirst,
+                                                     const uint32_t* __restrict__ oend, uint64_t n_out, double e2,
+                                                     float* __restrict__ out, int32_t* __restrict__ res, Misc* misc) {
+    __shared__ uint16_t LUT[kLut];
+    __shared__ uint32_t SRING[kDecLanes * kRing];
+    __shared__ uint32_t ORING[kDecLanes * kORing];
+    const uint32_t t = threadIdx.x;
+    for (uint32_t i = t; i < (uint32_t)kLut; i += 256) LUT[i] = lut_g[i];
+    __syncthreads();
+    const uint32_t i0 = blockIdx.x * 256 + t;
+    const bool active = i0 < nint;
+    const uint32_t ii = active ? i0 : nint - 1;
+    const uint32_t ibx = ii % ib0, r1 = ii / ib0, iby = r1 % ib1, ibz = r1 / ib1;
+    const uint32_t b = ibx + g.nb[0] * (iby + g.nb[1] * ibz);
+    const uint64_t start = off[b];
+    const uint32_t bits = chunks[b];
+    const uint32_t first = n_out ? ofirst[b] : 0, count = n_out ? oend[b] - first : 0;
+    FastDec fd;
+    fd.S = reinterpret_cast<const uint4*>(stream);
+    fd.nch = (uint32_t)((nwords + 3) / 4);
+    fd.sr = &SRING[t];
+    fd.orr = &ORING[t];
+    fd.O = reinterpret_cast<const uint4*>(oval);
+    fd.init(start, bits, oval, n_out, first, count);
+    const uint32_t pos_b = b * kBlockElems;
+    auto deq = [&](int32_t q) -> float { return (float)((double)q * e2); };
+    auto store8 = [&](uint64_t idx, const int32_t* q) {
+        f32x4* p = reinterpret_cast<f32x4*>(out + idx);
+        const f32x4 a = {deq(q[0]), deq(q[1]), deq(q[2]), deq(q[3])};
+        const f32x4 c = {deq(q[4]), deq(q[5]), deq(q[6]), deq(q[7])};
+        __builtin_nontemporal_store(a, p);
+        __builtin_nontemporal_store(c, p + 1);
+    };
+    auto store_res = [&](uint32_t pos0, const int32_t* d) {
+        int4* dst = reinterpret_cast<int4*>(res + pos0);
+        dst[0] = make_int4(d[0], d[1], d[2], d[3]);
+        dst[1] = make_int4(d[4], d[5], d[6], d[7]);
+    };
+    if (ND == 3) {
+        const uint64_t x0 = (uint64_t)ibx * 8;
+        int32_t qp[64];
+#pragma unroll
+        for (int i = 0; i < 64; i++) qp[i] = 0;
+        for (uint32_t z = 0; z < 8; z++) {
+            int32_t pr[8];
+#pragma unroll
+            for (int i = 0; i < 8; i++) pr[i] = 0;
+#pragma unroll
+            for (int y = 0; y < 8; y++) {
+                if (y & 1) fd.row_io<1>(); else fd.row_io<0>();
+                int32_t d[8];
+                const uint32_t pos0 = pos_b + 8 * y + 64 * z;
+                fd.row8(LUT, pos0, d);
+                if (RES) {
+                    store_res(pos0, d);
+                } else {
+                    int32_t rs = 0, q[8];
+#pragma unroll
+                    for (int x = 0; x < 8; x++) {
+                        rs += d[x];
+                        pr[x] += rs;
+                        qp[y * 8 + x] += pr[x];
+                        q[x] = qp[y * 8 + x];
+                    }
+                    const uint64_t yg = (uint64_t)iby * 8 + y, zg = (uint64_t)ibz * 8 + z;
+                    store8(x0 + (uint64_t)g.n[0] * (yg + (uint64_t)g.n[1] * zg), q);
+                }
+            }
+        }
+    } else if (ND == 2) {
+        int32_t qp[32];
+#pragma unroll
+        for (int i = 0; i < 32; i++) qp[i] = 0;
+        for (uint32_t y = 0; y < 16; y++) {
+            int32_t rs = 0;
+            const uint64_t row = (uint64_t)ibx * 32 + (uint64_t)g.n[0] * ((uint64_t)iby * 16 + y);
+#pragma unroll
+            for (int x8 = 0; x8 < 4; x8++) {
+                if (x8 & 1) fd.row_io<1>(); else fd.row_io<0>();
+                int32_t d[8];
+                const uint32_t pos0 = pos_b + 32 * y + 8 * x8;
+                fd.row8(LUT, pos0, d);
+                if (RES) {
+                    store_res(pos0, d);
+                } else {
+                    int32_t q[8];
+#pragma unroll
+                    for (int i = 0; i < 8; i++) {
+                        rs += d[i];
+                        qp[x8 * 8 + i] += rs;
+                        q[i] = qp[x8 * 8 + i];
+                    }
+                    store8(row + x8 * 8, q);
+                }
+            }
+        }
+    } else {
+        int32_t acc = 0;
+        const uint64_t row = (uint64_t)b * kBlockElems;
+        for (uint32_t s2 = 0; s2 < 32; s2++) {
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                if (h) fd.row_io<1>(); else fd.row_io<0>();
+                int32_t d[8];
+                const uint32_t i0s = 16 * s2 + 8 * h;
+                fd.row8(LUT, pos_b + i0s, d);
+                if (RES) {
+                    store_res(pos_b + i0s, d);
+                } else {
+                    int32_t q[8];
+#pragma unroll
+                    for (int i = 0; i < 8; i++) {
+                        acc += d[i];
+                        q[i] = acc;
+                    }
+                    store8(row + i0s, q);
+                }
+            }
+        }
+    }
+    bool bad = false;
+    if (active && (fd.consumed(start) != bits || fd.oi != first + count)) bad = true;
+    if (bad) atomicOr(&misc->flags, F_CORRUPT);
+    OutQ oq;
+    oq.oi = fd.oi;
+    oq.hash = fd.hash;
+    outlier_totals(t & 63, active, oq, first, misc);
+}
+
 // ---------------------------------------------- per-block predictor decode
 // Containers whose blocks use the second-order Lorenzo or regression
 // predictor decode in two steps: residuals per block to scratch (lane per
@@ -347,16 +642,18 @@ __global__ __launch_bounds__(256) void k_decode_res(Geom g, const uint32_t* __re
                                                     const uint16_t* __restrict__ lut_g,
                                                     const uint32_t* __restrict__ opos, const int32_t* __restrict__ oval,
                                                     const uint32_t* __restrict__ ofirst, uint64_t n_out,
-                                                    int32_t* __restrict__ res, Misc* misc) {
+                                                    int32_t* __restrict__ res, Misc* misc, int skip, uint32_t ib0,
+                                                    uint32_t ib1, uint32_t ib2) {
     __shared__ uint16_t LUT[kLut];
     __shared__ uint32_t RING[kDecLanes * kRing];
     const uint32_t t = threadIdx.x;
     for (uint32_t i = t; i < (uint32_t)kLut; i += 256) LUT[i] = lut_g[i];
     __syncthreads();
     const uint32_t b0 = blockIdx.x * 256 + t;
-    const bool active = b0 < g.nblocks;
-    const uint32_t b = active ? b0 : g.nblocks - 1;
+    const uint32_t b = b0 < g.nblocks ? b0 : g.nblocks - 1;
     const BlockInfo info = block_info(g, b);
+    const uint32_t ib[3] = {ib0, ib1, ib2};
+    const bool active = b0 < g.nblocks && !(skip && is_interior(info, ib));
     const uint64_t start = off[b];
     LaneDec ld;
     ld.chunks = reinterpret_cast<const uint4*>(stream);
@@ -497,8 +794,11 @@ __global__ __launch_bounds__(64) void k_inverse(Geom g, const int32_t* __restric
 // ofirst[b] = index of the first outlier of block b (blocks with outliers).
 // First list index of each block's outliers; the list must be strictly
 // increasing; the sum of pos_hash over the list for the decode-side check.
+// (ofirst, oend: one past the block's last outlier; both zero for a block
+// without outliers, cleared beforehand)
 __global__ __launch_bounds__(256) void k_outlier_index(const uint32_t* __restrict__ opos, uint64_t n_out,
-                                                       uint32_t nblocks, uint32_t* __restrict__ ofirst, Misc* misc) {
+                                                       uint32_t nblocks, uint32_t* __restrict__ ofirst,
+                                                       uint32_t* __restrict__ oend, Misc* misc) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     uint64_t h = 0;
     bool bad = false;
@@ -509,6 +809,7 @@ __global__ __launch_bounds__(256) void k_outlier_index(const uint32_t* __restric
         bad |= (i && prev >= p) || b >= nblocks;
         h += pos_hash(p);
         if (b < nblocks && (i == 0 || (prev >> 9) != b)) ofirst[b] = (uint32_t)i;
+        if (b < nblocks && (i + 1 == n_out || (opos[i + 1] >> 9) != b)) oend[b] = (uint32_t)(i + 1);
     }
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) h += __shfl_xor(h, d, 64);
@@ -573,25 +874,62 @@ void launch_lut(hipStream_t st, const uint8_t* lens_packed, uint16_t* lut, Misc*
     hipLaunchKernelGGL(k_lut, dim3(1), dim3(1024), 0, st, lens_packed, lut, misc);
 }
 
+namespace {
+// Full blocks per axis (the fast kernels' domain).
+struct Interior {
+    uint32_t ib[3];
+    uint32_t n;
+};
+Interior interior_of(const Geom& g) {
+    Interior r;
+    uint64_t n = 1;
+    for (int a = 0; a < 3; a++) {
+        r.ib[a] = a < (int)g.ndim ? g.n[a] / g.bs[a] : 1u;
+        n *= r.ib[a];
+    }
+    r.n = (uint32_t)n;
+    return r;
+}
+
+void outlier_index(hipStream_t st, const Geom& g, const uint32_t* opos, uint64_t n_out, uint32_t* ofirst,
+                   uint32_t* oend, Misc* misc) {
+    if (!n_out) return;
+    launch_fill32(st, ofirst, g.nblocks, 0);
+    launch_fill32(st, oend, g.nblocks, 0);
+    uint64_t og = (n_out + 255) / 256;
+    if (og > 4096) og = 4096;
+    hipLaunchKernelGGL(k_outlier_index, dim3((uint32_t)og), dim3(256), 0, st, opos, n_out, g.nblocks, ofirst, oend,
+                       misc);
+}
+}  // namespace
+
 void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,
                    const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
-                   const int32_t* oval, uint32_t* ofirst, uint64_t n_out, double e2, float* out, int vec,
-                   Misc* misc) {
-    if (n_out) {
-        uint64_t og = (n_out + 255) / 256;
-        if (og > 4096) og = 4096;
-        hipLaunchKernelGGL(k_outlier_index, dim3((uint32_t)og), dim3(256), 0, st, opos, n_out, g.nblocks, ofirst, misc);
+                   const int32_t* oval, uint32_t* ofirst, uint32_t* oend, uint64_t n_out, double e2, float* out,
+                   int vec, Misc* misc) {
+    outlier_index(st, g, opos, n_out, ofirst, oend, misc);
+    const Interior I = interior_of(g);
+    const bool fast = vec && I.n > 0;
+    if (fast) {
+        const uint32_t fg = (I.n + 255) / 256;
+#define FZ_FAST(NDV)                                                                                                \
+    hipLaunchKernelGGL((k_decode_fast<NDV, false>), dim3(fg), dim3(256), 0, st, g, I.ib[0], I.ib[1], I.n, stream,  \
+                       stream_words, off, chunks, lut, oval, ofirst, oend, n_out, e2, out, (int32_t*)nullptr, misc)
+        if (g.ndim == 3) FZ_FAST(3);
+        else if (g.ndim == 2) FZ_FAST(2);
+        else FZ_FAST(1);
+#undef FZ_FAST
     }
+    if (fast && I.n == g.nblocks) return;
     const uint32_t grid = (g.nblocks + 255) / 256;
-    if (g.ndim == 3)
-        hipLaunchKernelGGL(k_decode<3>, dim3(grid), dim3(256), 0, st, g, stream, stream_words, off, chunks, lut,
-                           opos, oval, ofirst, n_out, e2, out, vec, misc);
-    else if (g.ndim == 2)
-        hipLaunchKernelGGL(k_decode<2>, dim3(grid), dim3(256), 0, st, g, stream, stream_words, off, chunks, lut,
-                           opos, oval, ofirst, n_out, e2, out, vec, misc);
-    else
-        hipLaunchKernelGGL(k_decode<1>, dim3(grid), dim3(256), 0, st, g, stream, stream_words, off, chunks, lut,
-                           opos, oval, ofirst, n_out, e2, out, vec, misc);
+    const int skip = fast ? 1 : 0;
+#define FZ_GEN(NDV)                                                                                                 \
+    hipLaunchKernelGGL(k_decode<NDV>, dim3(grid), dim3(256), 0, st, g, stream, stream_words, off, chunks, lut, opos, \
+                       oval, ofirst, n_out, e2, out, vec, misc, skip, I.ib[0], I.ib[1], I.ib[2])
+    if (g.ndim == 3) FZ_GEN(3);
+    else if (g.ndim == 2) FZ_GEN(2);
+    else FZ_GEN(1);
+#undef FZ_GEN
 }
 
 void launch_map_unpack(hipStream_t st, const uint8_t* map, uint32_t nblocks, uint8_t* bpred, Misc* misc) {
@@ -600,18 +938,27 @@ void launch_map_unpack(hipStream_t st, const uint8_t* map, uint32_t nblocks, uin
 
 void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,
                         const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
-                        const int32_t* oval, uint32_t* ofirst, uint64_t n_out, int32_t* res, int fixed_pred,
-                        const uint8_t* bpred, const uint64_t* reg_idx, const int32_t* coefs, uint64_t nreg, double e2,
-                        float* out, int vec, Misc* misc) {
-    if (n_out) {
-        uint64_t og = (n_out + 255) / 256;
-        if (og > 4096) og = 4096;
-        hipLaunchKernelGGL(k_outlier_index, dim3((uint32_t)og), dim3(256), 0, st, opos, n_out, g.nblocks, ofirst, misc);
+                        const int32_t* oval, uint32_t* ofirst, uint32_t* oend, uint64_t n_out, int32_t* res,
+                        int fixed_pred, const uint8_t* bpred, const uint64_t* reg_idx, const int32_t* coefs,
+                        uint64_t nreg, double e2, float* out, int vec, Misc* misc) {
+    outlier_index(st, g, opos, n_out, ofirst, oend, misc);
+    const Interior I = interior_of(g);
+    if (I.n) {
+        const uint32_t fg = (I.n + 255) / 256;
+#define FZ_FAST(NDV)                                                                                               \
+    hipLaunchKernelGGL((k_decode_fast<NDV, true>), dim3(fg), dim3(256), 0, st, g, I.ib[0], I.ib[1], I.n, stream,  \
+                       stream_words, off, chunks, lut, oval, ofirst, oend, n_out, e2, (float*)nullptr, res, misc)
+        if (g.ndim == 3) FZ_FAST(3);
+        else if (g.ndim == 2) FZ_FAST(2);
+        else FZ_FAST(1);
+#undef FZ_FAST
     }
     const uint32_t grid = (g.nblocks + 255) / 256;
-#define FZ_DRES(NDV)                                                                                              \
-    hipLaunchKernelGGL(k_decode_res<NDV>, dim3(grid), dim3(256), 0, st, g, stream, stream_words, off, chunks, lut, \
-                       opos, oval, ofirst, n_out, res, misc);                                                      \
+    const int skip = I.n ? 1 : 0;
+#define FZ_DRES(NDV)                                                                                                \
+    if (I.n != g.nblocks)                                                                                           \
+        hipLaunchKernelGGL(k_decode_res<NDV>, dim3(grid), dim3(256), 0, st, g, stream, stream_words, off, chunks,   \
+                           lut, opos, oval, ofirst, n_out, res, misc, skip, I.ib[0], I.ib[1], I.ib[2]);            \
     hipLaunchKernelGGL(k_inverse<NDV>, dim3(g.nblocks), dim3(64), 0, st, g, res, fixed_pred, bpred, reg_idx, coefs, \
                        nreg, e2, out, vec, misc)
     if (g.ndim == 3) {

@@ -65,14 +65,14 @@ void launch_copy(hipStream_t st, const uint8_t* src, float* dst, uint64_t n);
 void launch_lut(hipStream_t st, const uint8_t* lens_packed, uint16_t* lut, Misc* misc);
 void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,
                    const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
-                   const int32_t* oval, uint32_t* ofirst, uint64_t n_out, double e2, float* out, int vec,
-                   Misc* misc);
+                   const int32_t* oval, uint32_t* ofirst, uint32_t* oend, uint64_t n_out, double e2, float* out,
+                   int vec, Misc* misc);
 void launch_map_unpack(hipStream_t st, const uint8_t* map, uint32_t nblocks, uint8_t* bpred, Misc* misc);
 void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,
                         const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
-                        const int32_t* oval, uint32_t* ofirst, uint64_t n_out, int32_t* res, int fixed_pred,
-                        const uint8_t* bpred, const uint64_t* reg_idx, const int32_t* coefs, uint64_t nreg, double e2,
-                        float* out, int vec, Misc* misc);
+                        const int32_t* oval, uint32_t* ofirst, uint32_t* oend, uint64_t n_out, int32_t* res,
+                        int fixed_pred, const uint8_t* bpred, const uint64_t* reg_idx, const int32_t* coefs,
+                        uint64_t nreg, double e2, float* out, int vec, Misc* misc);
 void launch_patch(hipStream_t st, const Geom& g, const uint32_t* ppos, const uint32_t* pbits, uint64_t n_pat,
                   float* out, Misc* misc);
 
