@@ -50,10 +50,8 @@ def stage_bytes(stage: str, n: int, nblocks: int, h: dict, total: int) -> float:
     return {
         "minmax": 4 * n,
         "quant": 4 * n + 2 * n + side,
-        "encode_len": 2 * n + 2 * nblocks,
-        "encode_write": 2 * n + stream,
+        "encode": 2 * n + 2 * nblocks + stream,
         "scan_counts": 4 * ntiles + 8 * ntiles,
-        "scan_bits": 4 * ntiles + 8 * ntiles,
         "finalize": 2 * side + 12 * ntiles,
         "lut": 512,
         "scan": 2 * nblocks + 8 * nblocks,

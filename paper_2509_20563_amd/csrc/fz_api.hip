@@ -222,7 +222,7 @@ int ensure(fz_ctx* c, const Geom& g) {
     if (e == hipSuccess) e = grow(c->tfirst, c->tfirst_cap, ntiles);
     if (e == hipSuccess) e = grow(c->tlast, c->tlast_cap, ntiles);
     if (e == hipSuccess) e = grow(c->desc_cnt, c->desc_cnt_cap, sd_tiles);
-    if (e == hipSuccess) e = grow(c->desc_bits, c->desc_bits_cap, sd_tiles);
+    if (e == hipSuccess) e = grow(c->desc_bits, c->desc_bits_cap, encode_groups((uint32_t)ntiles));
     if (e == hipSuccess) e = grow(c->desc_chunks, c->desc_chunks_cap, sd_blocks);
     if (e == hipSuccess) e = grow(c->off, c->off_cap, nb);
     if (e == hipSuccess) e = grow(c->ofirst, c->ofirst_cap, nb);
@@ -386,7 +386,8 @@ void compress_enqueue(fz_ctx* c, const fz_params* p, const Geom& g, const float*
     const uint64_t nreg_fixed = pred == FZ_PRED_REGRESSION ? g.nblocks : 0;
     const Layout L0 = make_layout(g.nblocks, has_map, nreg_fixed, 0, 0, 0);
     const uint32_t sd_blocks = has_map ? scan_tiles(g.nblocks) : 0;
-    launch_reset(st, c->misc, c->hist, c->desc_cnt, sd_tiles, c->desc_bits, sd_tiles, c->desc_pmap, sd_blocks,
+    launch_reset(st, c->misc, c->hist, c->desc_cnt, sd_tiles, c->desc_bits, encode_groups(ntiles), c->desc_pmap,
+                 sd_blocks,
                  L0.chunks, L0.stream, nreg_fixed);
     mark("reset");
     if (p->eb_mode == FZ_EB_REL) {
@@ -425,12 +426,9 @@ void compress_enqueue(fz_ctx* c, const fz_params* p, const Geom& g, const float*
     mark("scan_counts");
     launch_codebook(st, c->hist, out + kHdr, c->cw, c->misc);
     mark("codebook");
-    launch_encode_len(st, grid, c->codes, g, c->cw, ntiles, out, c->misc, c->tile_bits);
-    mark("encode_len");
-    launch_scan(st, SCAN_BITS, c->tile_bits, ntiles, c->tile_start, c->desc_bits, &c->misc->etile_ctr, c->misc, 0);
-    mark("scan_bits");
-    launch_encode_write(st, grid, c->codes, g, c->cw, c->misc, ntiles, out, c->tile_start, c->tfirst, c->tlast);
-    mark("encode_write");
+    launch_encode(st, grid, c->codes, g, c->cw, c->misc, ntiles, out, c->desc_bits, c->tile_start, c->tfirst,
+                  c->tlast);
+    mark("encode");
     launch_finalize(st, g, p->eb_mode, p->eb, pred, c->misc, out, ntiles, c->tile_start, c->tfirst, c->tlast,
                     c->tile_cnt, c->tile_off, c->opos, c->oval, c->ppos, c->pbits, c->bpred, c->reg_idx, c->coef);
     launch_verbatim(st, g, p->eb_mode, p->eb, pred, c->misc, d_in, out);

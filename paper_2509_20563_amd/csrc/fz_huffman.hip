@@ -278,6 +278,119 @@ __global__ __launch_bounds__(256) void k_encode_write(const uint16_t* __restrict
     }
 }
 
+// Single pass over the codes.  A workgroup takes kEncTiles consecutive
+// 4-block tiles: it reads their codes once (kept in registers), writes the
+// chunk table, publishes the group's bit count and obtains the group's
+// stream offset by a decoupled look-back over groups, then writes the bits
+// tile by tile.  A group publishes its count before it waits, and waits
+// only on groups with lower workgroup index (dispatched before it), so the
+// chain never waits on a workgroup that is not running; the wait is bounded
+// anyway (F_TIMEOUT).
+constexpr uint32_t kEncTiles = 8;
+
+template <int ND>
+__global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ codes, Geom g,
+                                                const uint32_t* __restrict__ cw_g, uint32_t ntiles, Misc* misc,
+                                                uint8_t* __restrict__ out, uint64_t* desc,
+                                                uint64_t* __restrict__ tile_start, uint32_t* __restrict__ tfirst,
+                                                uint32_t* __restrict__ tlast) {
+    __shared__ uint32_t CW[kBins];
+    __shared__ uint32_t W[kEncWords];
+    __shared__ uint32_t wsum[kEncTiles][4];
+    __shared__ uint64_t s_excl;
+    uint16_t* chunks = reinterpret_cast<uint16_t*>(out + misc->off_chunks);
+    uint32_t* stream = reinterpret_cast<uint32_t*>(out + misc->off_stream);
+    const uint32_t t = threadIdx.x, lane = t & 63;
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 6));
+    for (uint32_t i = t; i < (uint32_t)kBins; i += 256) CW[i] = cw_g[i];
+    for (uint32_t i = t; i < (uint32_t)kEncWords; i += 256) W[i] = 0;
+    __syncthreads();
+    const uint32_t grp = blockIdx.x;
+    const uint32_t tile0 = grp * kEncTiles;
+    // pass over the group's codes: lengths, chunk table, tile totals
+    uint32_t c8[kEncTiles][8];
+    uint32_t nvs[kEncTiles], nbs[kEncTiles];
+#pragma unroll
+    for (uint32_t k = 0; k < kEncTiles; k++) {
+        const uint32_t b = (tile0 + k) * kTileBlocks + wave;
+        nvs[k] = (tile0 + k < ntiles) ? load_codes<ND>(codes, g, b, lane, c8[k]) : 0u;
+        uint32_t nb = 0;
+#pragma unroll
+        for (int i = 0; i < 8; i++) nb += (i < (int)nvs[k]) ? (CW[c8[k][i]] >> 16) : 0u;
+        nbs[k] = nb;
+        const uint32_t incl = wave_incl_scan(nb);
+        if (lane == 63) {
+            wsum[k][wave] = incl;
+            if (tile0 + k < ntiles && b < g.nblocks) chunks[b] = (uint16_t)incl;
+        }
+    }
+    __syncthreads();
+    uint64_t gsum = 0;
+    for (uint32_t k = 0; k < kEncTiles; k++) gsum += wsum[k][0] + wsum[k][1] + wsum[k][2] + wsum[k][3];
+    if (wave == 0) {
+        const uint64_t ex = lookback(desc, grp, gsum, OpAdd(), &misc->flags);
+        if (lane == 0) {
+            s_excl = ex;
+            if (tile0 + kEncTiles >= ntiles) misc->total_bits_enc = ex + gsum;
+        }
+    }
+    __syncthreads();
+    uint64_t G = s_excl;
+#pragma unroll
+    for (uint32_t k = 0; k < kEncTiles; k++) {
+        const uint32_t tile = tile0 + k;
+        if (tile >= ntiles) break;  // uniform
+        uint32_t wpre = 0, T = 0;
+        for (uint32_t w = 0; w < 4; w++) {
+            if (w < wave) wpre += wsum[k][w];
+            T += wsum[k][w];
+        }
+        if (t == 0) {
+            tile_start[tile] = G;  // k_finalize merges the shared boundary words
+            if (tile != ntiles - 1 && T < 32) atomicOr(&misc->flags, F_INTERNAL);
+        }
+        uint64_t hi = 0, lo = 0;
+        uint32_t nb = 0;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            if (i < (int)nvs[k]) {
+                const uint32_t e = CW[c8[k][i]];
+                append_bits(hi, lo, nb, e & 0xFFFFu, e >> 16);
+            }
+        }
+        const uint32_t sh = (uint32_t)(G & 31);
+        if (nb) {
+            const uint32_t p = sh + wpre + wave_incl_scan(nb) - nb;
+            const uint32_t o = p & 31, w0 = p >> 5;
+            const uint32_t s0 = (uint32_t)(hi >> 32), s1 = (uint32_t)hi, s2 = (uint32_t)(lo >> 32),
+                           s3 = (uint32_t)lo;
+            const uint32_t o0 = s0 >> o;
+            const uint32_t o1 = __builtin_amdgcn_alignbit(s0, s1, o);
+            const uint32_t o2 = __builtin_amdgcn_alignbit(s1, s2, o);
+            const uint32_t o3 = __builtin_amdgcn_alignbit(s2, s3, o);
+            if (o0) atomicOr(&W[w0], o0);
+            if (o1) atomicOr(&W[w0 + 1], o1);
+            if (o2) atomicOr(&W[w0 + 2], o2);
+            if (o3) atomicOr(&W[w0 + 3], o3);
+        }
+        __syncthreads();
+        // interior words go to the stream; the partial first and last words
+        // are shared with the neighbouring tiles and merged by k_finalize
+        const uint32_t nwords = (sh + T + 31) >> 5;
+        const bool last_partial = ((sh + T) & 31) != 0 && tile != ntiles - 1;
+        const uint64_t wbase = G >> 5;
+        for (uint32_t w = t; w < nwords; w += 256) {
+            const uint32_t v = W[w];
+            W[w] = 0;
+            if (w == 0 && sh != 0) tfirst[tile] = v;
+            else if (w == nwords - 1 && last_partial) tlast[tile] = v;
+            else stream[wbase + w] = v;
+        }
+        __syncthreads();
+        G += T;
+    }
+}
+
 // ------------------------------------------------------------- finalize
 // Layout from the device-side counts; boundary words shared by two tiles;
 // outlier and patch sections compacted from the per-tile staging slots in
@@ -475,6 +588,24 @@ void launch_encode_write(hipStream_t st, int grid, const uint16_t* codes, const 
         hipLaunchKernelGGL(k_encode_write<1>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, tile_start, misc,
                            out, tfirst, tlast);
 }
+
+void launch_encode(hipStream_t st, int grid, const uint16_t* codes, const Geom& g, const uint32_t* cw, Misc* misc,
+                   uint32_t ntiles, uint8_t* out, uint64_t* desc, uint64_t* tile_start, uint32_t* tfirst,
+                   uint32_t* tlast) {
+    (void)grid;  // one workgroup per group of tiles
+    const uint32_t groups = (ntiles + kEncTiles - 1) / kEncTiles;
+    if (g.ndim == 3)
+        hipLaunchKernelGGL(k_encode<3>, dim3(groups), dim3(256), 0, st, codes, g, cw, ntiles, misc, out, desc,
+                           tile_start, tfirst, tlast);
+    else if (g.ndim == 2)
+        hipLaunchKernelGGL(k_encode<2>, dim3(groups), dim3(256), 0, st, codes, g, cw, ntiles, misc, out, desc,
+                           tile_start, tfirst, tlast);
+    else
+        hipLaunchKernelGGL(k_encode<1>, dim3(groups), dim3(256), 0, st, codes, g, cw, ntiles, misc, out, desc,
+                           tile_start, tfirst, tlast);
+}
+
+uint32_t encode_groups(uint32_t ntiles) { return (ntiles + kEncTiles - 1) / kEncTiles; }
 
 void launch_finalize(hipStream_t st, const Geom& g, uint32_t mode, double eb, uint32_t pred, Misc* misc,
                      uint8_t* out, uint32_t ntiles, const uint64_t* tile_start, const uint32_t* tfirst,

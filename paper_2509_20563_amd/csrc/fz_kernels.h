@@ -35,6 +35,10 @@ void launch_encode_len(hipStream_t st, int grid, const uint16_t* codes, const Ge
 void launch_encode_write(hipStream_t st, int grid, const uint16_t* codes, const Geom& g, const uint32_t* cw,
                          Misc* misc, uint32_t ntiles, uint8_t* out, const uint64_t* tile_start, uint32_t* tfirst,
                          uint32_t* tlast);
+void launch_encode(hipStream_t st, int grid, const uint16_t* codes, const Geom& g, const uint32_t* cw, Misc* misc,
+                   uint32_t ntiles, uint8_t* out, uint64_t* desc, uint64_t* tile_start, uint32_t* tfirst,
+                   uint32_t* tlast);
+uint32_t encode_groups(uint32_t ntiles);
 void launch_finalize(hipStream_t st, const Geom& g, uint32_t mode, double eb, uint32_t pred, Misc* misc,
                      uint8_t* out, uint32_t ntiles, const uint64_t* tile_start, const uint32_t* tfirst,
                      const uint32_t* tlast, const uint32_t* tile_cnt, const uint64_t* tile_off, const uint32_t* opos,

@@ -155,8 +155,7 @@ def test_stage_timing(fz, ctx):
     ctx.set_timing(True)
     c = ctx.compress(x, 1e-3, 1)
     names = [n for n, _ in ctx.stage_times()]
-    assert names == ["reset", "minmax", "quant", "scan_counts", "codebook", "encode_len", "scan_bits",
-                     "encode_write", "finalize"]
+    assert names == ["reset", "minmax", "quant", "scan_counts", "codebook", "encode", "finalize"]
     ctx.decompress(c)
     names = [n for n, _ in ctx.stage_times()]
     assert names == ["reset", "lut", "scan", "decode", "patch"]
