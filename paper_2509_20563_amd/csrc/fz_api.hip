@@ -76,11 +76,10 @@ struct fz_ctx {
     // per-tile counts and prefixes
     uint32_t* tile_cnt = nullptr;
     uint64_t* tile_off = nullptr;
-    uint32_t* tile_bits = nullptr;
     uint64_t* tile_start = nullptr;
     uint32_t* tfirst = nullptr;
     uint32_t* tlast = nullptr;
-    uint64_t tile_cnt_cap = 0, tile_off_cap = 0, tile_bits_cap = 0, tile_start_cap = 0, tfirst_cap = 0,
+    uint64_t tile_cnt_cap = 0, tile_off_cap = 0, tile_start_cap = 0, tfirst_cap = 0,
              tlast_cap = 0;
     // look-back descriptors of the three scans
     uint64_t* desc_cnt = nullptr;
@@ -217,7 +216,6 @@ int ensure(fz_ctx* c, const Geom& g) {
     if (e == hipSuccess) e = grow(c->pbits, c->pbits_cap, slots);
     if (e == hipSuccess) e = grow(c->tile_cnt, c->tile_cnt_cap, ntiles);
     if (e == hipSuccess) e = grow(c->tile_off, c->tile_off_cap, ntiles);
-    if (e == hipSuccess) e = grow(c->tile_bits, c->tile_bits_cap, ntiles);
     if (e == hipSuccess) e = grow(c->tile_start, c->tile_start_cap, ntiles);
     if (e == hipSuccess) e = grow(c->tfirst, c->tfirst_cap, ntiles);
     if (e == hipSuccess) e = grow(c->tlast, c->tlast_cap, ntiles);
@@ -549,7 +547,6 @@ void fz_ctx_destroy(fz_ctx* c) {
     hipFree(c->pbits);
     hipFree(c->tile_cnt);
     hipFree(c->tile_off);
-    hipFree(c->tile_bits);
     hipFree(c->tile_start);
     hipFree(c->tfirst);
     hipFree(c->tlast);
@@ -1001,7 +998,7 @@ void key_put(std::vector<uint8_t>& k, const T& v) {
 // Every scratch pointer of a context (a captured graph holds them).
 void key_scratch(std::vector<uint8_t>& k, const fz_ctx* c) {
     const void* ps[] = {c->misc, c->hist, c->cw, c->lut, c->codes, c->opos, c->oval, c->ppos, c->pbits,
-                        c->tile_cnt, c->tile_off, c->tile_bits, c->tile_start, c->tfirst, c->tlast, c->desc_cnt,
+                        c->tile_cnt, c->tile_off, c->tile_start, c->tfirst, c->tlast, c->desc_cnt,
                         c->desc_bits, c->desc_chunks, c->off, c->ofirst, c->oend, c->bpred, c->reg_idx, c->coef, c->costs,
                         c->cw_ref, c->lens_ref, c->desc_pmap, c->res, c->sel};
     for (const void* q : ps) key_put(k, q);

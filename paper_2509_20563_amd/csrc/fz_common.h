@@ -30,7 +30,7 @@ constexpr int kSelectorParams = 2 * kNFeat + kNHid * kNFeat + kNHid + kNHid * kN
 constexpr uint16_t kVersion = 1;
 
 // prefix-scan kinds (fz_scan.hip)
-enum { SCAN_COUNTS = 0, SCAN_BITS = 1, SCAN_CHUNKS = 2, SCAN_PMAP = 3 };
+enum { SCAN_COUNTS = 0, SCAN_CHUNKS = 2, SCAN_PMAP = 3 };
 
 // flag bits raised by kernels in Misc::flags
 enum : uint32_t {
@@ -47,7 +47,7 @@ struct Misc {
     uint32_t flags;
     uint32_t mm_lo, mm_hi;     // order-preserving encodings of min and max
     uint32_t qtile_ctr;        // dynamic tile counters (look-back order)
-    uint32_t etile_ctr;
+    uint32_t pad0;
     uint32_t stile_ctr;
     uint32_t code0_count;      // decode: outlier codes seen
     uint32_t mtile_ctr;        // predictor-map scan

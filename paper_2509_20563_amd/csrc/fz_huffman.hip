@@ -3,9 +3,9 @@
 // runs this on the CPU, here it runs on the GPU):
 //   k_codebook - length-limited minimum-redundancy code lengths by
 //                package-merge in one workgroup, canonical codewords;
-//   k_encode_len / k_encode_write - chunked encoding (chunk = block) in
-//                two passes around a scan of per-tile bit counts, words
-//                assembled in LDS;
+//   k_encode   - chunked encoding (chunk = block) in one pass over the
+//                codes, stream offsets by a look-back over tile groups,
+//                words assembled in LDS;
 //   k_finalize - tile-boundary words, outlier/patch sections, header.
 #include "fz_common.h"
 #include "fz_kernels.h"
@@ -156,11 +156,6 @@ __device__ __forceinline__ void append_bits(uint64_t& hi, uint64_t& lo, uint32_t
 
 constexpr int kEncWords = kTileBlocks * kBlockElems * kLmax / 32 + 8;
 
-// Pass 1: bits per block (written to the container's chunk table) and per
-// 4-block tile.  Pass 2, after a scan of the tile totals: the bits
-// themselves at known offsets.  Tiles are assigned statically (grid-stride),
-// thread = block*64 + segment, so the two passes see the same tiles and the
-// only cross-tile dependency is the scan between them.
 template <int ND>
 __device__ __forceinline__ uint32_t load_codes(const uint16_t* __restrict__ codes, const Geom& g, uint32_t b,
                                                uint32_t s, uint32_t c8[8]) {
@@ -174,108 +169,6 @@ __device__ __forceinline__ uint32_t load_codes(const uint16_t* __restrict__ code
     c8[0] = pk.x & 0xFFFFu; c8[1] = pk.x >> 16; c8[2] = pk.y & 0xFFFFu; c8[3] = pk.y >> 16;
     c8[4] = pk.z & 0xFFFFu; c8[5] = pk.z >> 16; c8[6] = pk.w & 0xFFFFu; c8[7] = pk.w >> 16;
     return nv;
-}
-
-template <int ND>
-__global__ __launch_bounds__(256) void k_encode_len(const uint16_t* __restrict__ codes, Geom g,
-                                                    const uint32_t* __restrict__ cw_g, uint32_t ntiles,
-                                                    uint8_t* __restrict__ out, const Misc* misc,
-                                                    uint32_t* __restrict__ tile_bits) {
-    __shared__ uint8_t LEN[kBins];
-    __shared__ uint32_t wsum[4];
-    uint16_t* chunks = reinterpret_cast<uint16_t*>(out + misc->off_chunks);
-    const uint32_t t = threadIdx.x, lane = t & 63;
-    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 6));
-    for (uint32_t i = t; i < (uint32_t)kBins; i += 256) LEN[i] = (uint8_t)(cw_g[i] >> 16);
-    __syncthreads();
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t b = tile * kTileBlocks + wave;
-        uint32_t c8[8];
-        const uint32_t nv = load_codes<ND>(codes, g, b, t & 63, c8);
-        uint32_t nb = 0;
-#pragma unroll
-        for (int i = 0; i < 8; i++) nb += (i < (int)nv) ? LEN[c8[i]] : 0u;
-        nb = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(nb), 63);
-        if (lane == 0) {
-            if (b < g.nblocks) chunks[b] = (uint16_t)nb;
-            wsum[wave] = nb;
-        }
-        __syncthreads();
-        if (t == 0) tile_bits[tile] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-        __syncthreads();
-    }
-}
-
-template <int ND>
-__global__ __launch_bounds__(256) void k_encode_write(const uint16_t* __restrict__ codes, Geom g,
-                                                      const uint32_t* __restrict__ cw_g, uint32_t ntiles,
-                                                      const uint64_t* __restrict__ tile_start, Misc* misc,
-                                                      uint8_t* __restrict__ out, uint32_t* __restrict__ tfirst,
-                                                      uint32_t* __restrict__ tlast) {
-    __shared__ uint32_t CW[kBins];
-    __shared__ uint32_t W[kEncWords];
-    __shared__ uint32_t wsum[4];
-    uint32_t* stream = reinterpret_cast<uint32_t*>(out + misc->off_stream);
-
-    const uint32_t t = threadIdx.x, lane = t & 63;
-    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 6));
-    for (uint32_t i = t; i < (uint32_t)kBins; i += 256) CW[i] = cw_g[i];
-    for (uint32_t i = t; i < (uint32_t)kEncWords; i += 256) W[i] = 0;
-    __syncthreads();
-
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t b = tile * kTileBlocks + wave;
-        uint32_t c8[8];
-        const uint32_t nv = load_codes<ND>(codes, g, b, t & 63, c8);
-        uint64_t hi = 0, lo = 0;
-        uint32_t nb = 0;
-#pragma unroll
-        for (int i = 0; i < 8; i++) {
-            if (i < (int)nv) {
-                const uint32_t e = CW[c8[i]];
-                append_bits(hi, lo, nb, e & 0xFFFFu, e >> 16);
-            }
-        }
-        const uint32_t incl = wave_incl_scan(nb);
-        if (lane == 63) wsum[wave] = incl;
-        __syncthreads();
-        uint32_t wpre = 0, T = 0;
-        for (uint32_t w = 0; w < 4; w++) {
-            if (w < wave) wpre += wsum[w];
-            T += wsum[w];
-        }
-        const uint64_t G = tile_start[tile];
-        const uint32_t sh = (uint32_t)(G & 31);
-        if (t == 0 && tile != ntiles - 1 && T < 32) atomicOr(&misc->flags, F_INTERNAL);
-        if (nb) {
-            const uint32_t p = sh + wpre + incl - nb;
-            const uint32_t o = p & 31, w0 = p >> 5;
-            const uint32_t s0 = (uint32_t)(hi >> 32), s1 = (uint32_t)hi, s2 = (uint32_t)(lo >> 32),
-                           s3 = (uint32_t)lo;
-            const uint32_t o0 = s0 >> o;
-            const uint32_t o1 = __builtin_amdgcn_alignbit(s0, s1, o);
-            const uint32_t o2 = __builtin_amdgcn_alignbit(s1, s2, o);
-            const uint32_t o3 = __builtin_amdgcn_alignbit(s2, s3, o);
-            if (o0) atomicOr(&W[w0], o0);
-            if (o1) atomicOr(&W[w0 + 1], o1);
-            if (o2) atomicOr(&W[w0 + 2], o2);
-            if (o3) atomicOr(&W[w0 + 3], o3);
-        }
-        __syncthreads();
-        // interior words go to the stream; the partial first and last words
-        // are shared with the neighbouring tiles and merged by k_finalize
-        const uint32_t nwords = (sh + T + 31) >> 5;
-        const bool last_partial = ((sh + T) & 31) != 0 && tile != ntiles - 1;
-        const uint64_t wbase = G >> 5;
-        for (uint32_t w = t; w < nwords; w += 256) {
-            const uint32_t v = W[w];
-            W[w] = 0;
-            if (w == 0 && sh != 0) tfirst[tile] = v;
-            else if (w == nwords - 1 && last_partial) tlast[tile] = v;
-            else stream[wbase + w] = v;
-        }
-        __syncthreads();
-    }
 }
 
 // Single pass over the codes.  A workgroup takes kEncTiles consecutive
@@ -563,30 +456,6 @@ void launch_verbatim(hipStream_t st, const Geom& g, uint32_t mode, double eb, ui
 
 void launch_codebook(hipStream_t st, const uint32_t* hist, uint8_t* out_lens, uint32_t* cw, Misc* misc) {
     hipLaunchKernelGGL(k_codebook, dim3(1), dim3(1024), 0, st, hist, out_lens, cw, misc);
-}
-
-void launch_encode_len(hipStream_t st, int grid, const uint16_t* codes, const Geom& g, const uint32_t* cw,
-                       uint32_t ntiles, uint8_t* out, const Misc* misc, uint32_t* tile_bits) {
-    if (g.ndim == 3)
-        hipLaunchKernelGGL(k_encode_len<3>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, out, misc, tile_bits);
-    else if (g.ndim == 2)
-        hipLaunchKernelGGL(k_encode_len<2>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, out, misc, tile_bits);
-    else
-        hipLaunchKernelGGL(k_encode_len<1>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, out, misc, tile_bits);
-}
-
-void launch_encode_write(hipStream_t st, int grid, const uint16_t* codes, const Geom& g, const uint32_t* cw,
-                         Misc* misc, uint32_t ntiles, uint8_t* out, const uint64_t* tile_start, uint32_t* tfirst,
-                         uint32_t* tlast) {
-    if (g.ndim == 3)
-        hipLaunchKernelGGL(k_encode_write<3>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, tile_start, misc,
-                           out, tfirst, tlast);
-    else if (g.ndim == 2)
-        hipLaunchKernelGGL(k_encode_write<2>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, tile_start, misc,
-                           out, tfirst, tlast);
-    else
-        hipLaunchKernelGGL(k_encode_write<1>, dim3(grid), dim3(256), 0, st, codes, g, cw, ntiles, tile_start, misc,
-                           out, tfirst, tlast);
 }
 
 void launch_encode(hipStream_t st, int grid, const uint16_t* codes, const Geom& g, const uint32_t* cw, Misc* misc,

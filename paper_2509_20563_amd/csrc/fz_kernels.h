@@ -30,11 +30,6 @@ uint32_t scan_tiles(uint32_t n);
 
 // fz_huffman.hip
 void launch_codebook(hipStream_t st, const uint32_t* hist, uint8_t* out_lens, uint32_t* cw, Misc* misc);
-void launch_encode_len(hipStream_t st, int grid, const uint16_t* codes, const Geom& g, const uint32_t* cw,
-                       uint32_t ntiles, uint8_t* out, const Misc* misc, uint32_t* tile_bits);
-void launch_encode_write(hipStream_t st, int grid, const uint16_t* codes, const Geom& g, const uint32_t* cw,
-                         Misc* misc, uint32_t ntiles, uint8_t* out, const uint64_t* tile_start, uint32_t* tfirst,
-                         uint32_t* tlast);
 void launch_encode(hipStream_t st, int grid, const uint16_t* codes, const Geom& g, const uint32_t* cw, Misc* misc,
                    uint32_t ntiles, uint8_t* out, uint64_t* desc, uint64_t* tile_start, uint32_t* tfirst,
                    uint32_t* tlast);

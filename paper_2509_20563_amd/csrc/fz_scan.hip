@@ -3,7 +3,6 @@
 // needs 64 workgroups and one counter atomic each):
 //   SCAN_COUNTS - packed (outliers | patches << 16) per quantisation tile ->
 //                 packed prefix (outliers: 31 bits, patches: 31 bits above)
-//   SCAN_BITS   - encoded bits per encoder tile -> bit offset of each tile
 //   SCAN_CHUNKS - u16 bit count per block (container) -> bit offset per block
 //   SCAN_PMAP   - per-block predictor (u8) -> index of each regression block
 //                 among the regression blocks; sets the section offsets
@@ -40,8 +39,6 @@ __global__ __launch_bounds__(256) void k_scan(const void* __restrict__ in, uint3
             if (KIND == SCAN_COUNTS) {
                 const uint32_t c = static_cast<const uint32_t*>(in)[base + k];
                 e = (uint64_t)(c & 0xFFFFu) | ((uint64_t)(c >> 16) << 31);
-            } else if (KIND == SCAN_BITS) {
-                e = static_cast<const uint32_t*>(in)[base + k];
             } else if (KIND == SCAN_PMAP) {
                 e = static_cast<const uint8_t*>(in)[base + k] == 2 ? 1u : 0u;
             } else {
@@ -70,8 +67,6 @@ __global__ __launch_bounds__(256) void k_scan(const void* __restrict__ in, uint3
                     misc->n_out = total & m;
                     misc->n_pat = total >> 31;
                     if ((total & m) == m || (total >> 31) == m) atomicOr(&misc->flags, F_OVERFLOW);
-                } else if (KIND == SCAN_BITS) {
-                    misc->total_bits_enc = total;
                 } else if (KIND == SCAN_PMAP) {
                     // regression blocks decide where the chunk table starts
                     const Layout L = make_layout(n, true, total, 0, 0, 0);
@@ -108,9 +103,6 @@ void launch_scan(hipStream_t st, int kind, const void* in, uint32_t n, uint64_t*
     if (ntiles == 0) return;
     if (kind == SCAN_COUNTS)
         hipLaunchKernelGGL(k_scan<SCAN_COUNTS>, dim3(ntiles), dim3(256), 0, st, in, n, out, desc, ctr, ntiles, misc,
-                           expect);
-    else if (kind == SCAN_BITS)
-        hipLaunchKernelGGL(k_scan<SCAN_BITS>, dim3(ntiles), dim3(256), 0, st, in, n, out, desc, ctr, ntiles, misc,
                            expect);
     else if (kind == SCAN_PMAP)
         hipLaunchKernelGGL(k_scan<SCAN_PMAP>, dim3(ntiles), dim3(256), 0, st, in, n, out, desc, ctr, ntiles, misc,
