@@ -481,9 +481,10 @@ struct FastDec {
     }
 };
 
-// RES = false: inverse Lorenzo, dequantisation and rows of floats;
-// RES = true: residuals (int32, block-major) for the mapped decoder.
-template <int ND, bool RES>
+// RES = false: inverse Lorenzo, dequantisation and rows of floats (two
+// float4 stores per row when VEC, rows 16-byte aligned; else eight dword
+// stores); RES = true: residuals (int32, block-major) for the mapped decoder.
+template <int ND, bool RES, bool VEC>
 __global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint32_t ib1, uint32_t nint,
                                                      const uint32_t* __restrict__ stream, uint64_t nwords,
                                                      const uint64_t* __restrict__ off,
@@ -517,11 +518,16 @@ __global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint3
     const uint32_t pos_b = b * kBlockElems;
     auto deq = [&](int32_t q) -> float { return (float)((double)q * e2); };
     auto store8 = [&](uint64_t idx, const int32_t* q) {
-        f32x4* p = reinterpret_cast<f32x4*>(out + idx);
-        const f32x4 a = {deq(q[0]), deq(q[1]), deq(q[2]), deq(q[3])};
-        const f32x4 c = {deq(q[4]), deq(q[5]), deq(q[6]), deq(q[7])};
-        __builtin_nontemporal_store(a, p);
-        __builtin_nontemporal_store(c, p + 1);
+        if (VEC) {
+            f32x4* p = reinterpret_cast<f32x4*>(out + idx);
+            const f32x4 a = {deq(q[0]), deq(q[1]), deq(q[2]), deq(q[3])};
+            const f32x4 c = {deq(q[4]), deq(q[5]), deq(q[6]), deq(q[7])};
+            __builtin_nontemporal_store(a, p);
+            __builtin_nontemporal_store(c, p + 1);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; i++) __builtin_nontemporal_store(deq(q[i]), out + idx + i);
+        }
     };
     auto store_res = [&](uint32_t pos0, const int32_t* d) {
         int4* dst = reinterpret_cast<int4*>(res + pos0);
@@ -909,15 +915,21 @@ void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64
                    int vec, Misc* misc) {
     outlier_index(st, g, opos, n_out, ofirst, oend, misc);
     const Interior I = interior_of(g);
-    const bool fast = vec && I.n > 0;
+    const bool fast = I.n > 0;
     if (fast) {
         const uint32_t fg = (I.n + 255) / 256;
-#define FZ_FAST(NDV)                                                                                                \
-    hipLaunchKernelGGL((k_decode_fast<NDV, false>), dim3(fg), dim3(256), 0, st, g, I.ib[0], I.ib[1], I.n, stream,  \
+#define FZ_FAST(NDV, V)                                                                                               \
+    hipLaunchKernelGGL((k_decode_fast<NDV, false, V>), dim3(fg), dim3(256), 0, st, g, I.ib[0], I.ib[1], I.n, stream, \
                        stream_words, off, chunks, lut, oval, ofirst, oend, n_out, e2, out, (int32_t*)nullptr, misc)
-        if (g.ndim == 3) FZ_FAST(3);
-        else if (g.ndim == 2) FZ_FAST(2);
-        else FZ_FAST(1);
+        if (vec) {
+            if (g.ndim == 3) FZ_FAST(3, true);
+            else if (g.ndim == 2) FZ_FAST(2, true);
+            else FZ_FAST(1, true);
+        } else {
+            if (g.ndim == 3) FZ_FAST(3, false);
+            else if (g.ndim == 2) FZ_FAST(2, false);
+            else FZ_FAST(1, false);
+        }
 #undef FZ_FAST
     }
     if (fast && I.n == g.nblocks) return;
@@ -946,7 +958,8 @@ void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, u
     if (I.n) {
         const uint32_t fg = (I.n + 255) / 256;
 #define FZ_FAST(NDV)                                                                                               \
-    hipLaunchKernelGGL((k_decode_fast<NDV, true>), dim3(fg), dim3(256), 0, st, g, I.ib[0], I.ib[1], I.n, stream,  \
+    hipLaunchKernelGGL((k_decode_fast<NDV, true, false>), dim3(fg), dim3(256), 0, st, g, I.ib[0], I.ib[1], I.n,     \
+                       stream,                                                                                      \
                        stream_words, off, chunks, lut, oval, ofirst, oend, n_out, e2, (float*)nullptr, res, misc)
         if (g.ndim == 3) FZ_FAST(3);
         else if (g.ndim == 2) FZ_FAST(2);
