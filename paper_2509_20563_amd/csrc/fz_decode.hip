@@ -133,9 +133,10 @@ struct LaneDec {
             advance();
         }
     }
-    // bits consumed since `start` (init fed two words)
+    // bits consumed since `start`: the words fed so far end at bit 32 w,
+    // nb of them are still buffered
     __device__ __forceinline__ uint64_t consumed(uint64_t start) const {
-        return (uint64_t)w * 32 - nb - (start & ~31ull);
+        return (uint64_t)w * 32 - nb - start;
     }
 };
 
@@ -477,7 +478,7 @@ struct FastDec {
         }
     }
     __device__ __forceinline__ uint64_t consumed(uint64_t start) const {
-        return (uint64_t)w * 32 - nb - (start & ~31ull);
+        return (uint64_t)w * 32 - nb - start;
     }
 };
 

@@ -245,42 +245,53 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
     seg_coords<ND>(lane, lb_lx0, lb_ly, lb_lz);
     const uint32_t lb_rowoff = lb_lx0 + g.n[0] * (lb_ly + g.n[1] * lb_lz);
 
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        // ---------------- phase A: load + prequantise
-        {
-            // the tile's four block origins and extents are wave-uniform
-            // (scalar); each lane picks its block's entry
-            uint32_t org[kTileBlocks], ex[kTileBlocks], ey[kTileBlocks], ez[kTileBlocks];
+    // phase-A source of a tile for this lane: first index and real values
+    auto tile_src = [&](uint32_t tile, uint32_t& base, uint32_t& nv) {
+        const uint32_t bk = tile * kTileBlocks + la_bi;
+        const bool ok = bk < g.nblocks;
+        const BlockInfo ik = block_info(g, ok ? bk : 0);
+        nv = (ok && la_ly < ik.ey && la_lz < ik.ez && la_lx0 < ik.ex) ? min(8u, ik.ex - la_lx0) : 0u;
+        base = ik.bx * g.bs[0] + g.n[0] * (ik.by * g.bs[1] + g.n[1] * (ik.bz * g.bs[2])) + la_rowoff;
+    };
+    auto tile_load = [&](uint32_t base, uint32_t nv, float v[8]) {
+        if (nv == 8 && vec) {
+            const f32x4* p = reinterpret_cast<const f32x4*>(x + base);
+            const f32x4 a = __builtin_nontemporal_load(p);
+            const f32x4 c = __builtin_nontemporal_load(p + 1);
+            v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+            v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
+        } else {
 #pragma unroll
-            for (int k = 0; k < kTileBlocks; k++) {
-                const uint32_t bk = tile * kTileBlocks + k;
-                const bool ok = bk < g.nblocks;
-                const BlockInfo ik = block_info(g, ok ? bk : 0);
-                org[k] = ik.bx * g.bs[0] + g.n[0] * (ik.by * g.bs[1] + g.n[1] * (ik.bz * g.bs[2]));
-                ex[k] = ok ? ik.ex : 0u;
-                ey[k] = ik.ey;
-                ez[k] = ik.ez;
+            for (int i = 0; i < 8; i++) v[i] = (i < (int)nv) ? x[base + i] : 0.0f;
+        }
+    };
+    // the values of the workgroup's next tile are loaded one tile ahead,
+    // so their latency overlaps the current tile's phase B
+    uint32_t pf_nv = 0;
+    float pf[8];
+    {
+        uint32_t base = 0;
+        if (blockIdx.x < ntiles) tile_src(blockIdx.x, base, pf_nv);
+        tile_load(base, blockIdx.x < ntiles ? pf_nv : 0u, pf);
+    }
+
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        // ---------------- phase A: prequantise (values loaded a tile ago)
+        {
+            const uint32_t nv = pf_nv;
+            float v[8];
+#pragma unroll
+            for (int i = 0; i < 8; i++) v[i] = pf[i];
+            {
+                const uint32_t nt = tile + gridDim.x;
+                uint32_t base = 0;
+                if (nt < ntiles) tile_src(nt, base, pf_nv);
+                else pf_nv = 0;
+                tile_load(base, pf_nv, pf);
             }
-            auto pick = [&](const uint32_t* a) {
-                return la_bi == 0 ? a[0] : la_bi == 1 ? a[1] : la_bi == 2 ? a[2] : a[3];
-            };
-            const uint32_t bex = pick(ex), bey = pick(ey), bez = pick(ez);
-            const uint32_t nv = (la_ly < bey && la_lz < bez && la_lx0 < bex) ? min(8u, bex - la_lx0) : 0u;
-            const uint32_t base = pick(org) + la_rowoff;
             int32_t q[8];
             uint32_t pm = 0;
             bool bad = false;
-            float v[8];
-            if (nv == 8 && vec) {
-                const f32x4* p = reinterpret_cast<const f32x4*>(x + base);
-                const f32x4 a = __builtin_nontemporal_load(p);
-                const f32x4 c = __builtin_nontemporal_load(p + 1);
-                v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-                v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
-            } else {
-#pragma unroll
-                for (int i = 0; i < 8; i++) v[i] = (i < (int)nv) ? x[base + i] : 0.0f;
-            }
 #pragma unroll
             for (int i = 0; i < 8; i++) {
                 bool p;
