@@ -252,8 +252,10 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ cod
             }
         }
         const uint32_t sh = (uint32_t)(G & 31);
+        // the scan runs with every lane active (lanes with no bits add 0)
+        const uint32_t incl = wave_incl_scan(nb);
         if (nb) {
-            const uint32_t p = sh + wpre + wave_incl_scan(nb) - nb;
+            const uint32_t p = sh + wpre + incl - nb;
             const uint32_t o = p & 31, w0 = p >> 5;
             const uint32_t s0 = (uint32_t)(hi >> 32), s1 = (uint32_t)hi, s2 = (uint32_t)(lo >> 32),
                            s3 = (uint32_t)lo;
