@@ -245,7 +245,7 @@ def _line(metric, value, unit, args, ms, config, higher=True, **extra):
     print(json.dumps(d), flush=True)
 
 
-def train_selector(ctx, fz, device, seeds=(101, 102, 103, 104), edge=128, ebs=(1e-2, 1e-3, 1e-4), epochs=30):
+def train_selector(ctx, fz, device, seeds=(101, 102, 103, 104), edge=128, ebs=(1e-2, 1e-3, 1e-4), epochs=200):
     """Train the context's selector on fronts/spikes fields of seeds disjoint
     from the evaluation fields; returns (seconds, first loss, last loss, samples)."""
     import torch
@@ -260,7 +260,7 @@ def train_selector(ctx, fz, device, seeds=(101, 102, 103, 104), edge=128, ebs=(1
     c = torch.cat(costs).contiguous()
     torch.cuda.synchronize()
     t = time.perf_counter()
-    loss = ctx.selector_train(f, c, epochs=epochs, batch=4096, seed=1)
+    loss = ctx.selector_train(f, c, epochs=epochs, batch=1024, seed=1)
     torch.cuda.synchronize()
     return time.perf_counter() - t, float(loss[0]), float(loss[-1]), int(f.shape[0])
 

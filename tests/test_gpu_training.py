@@ -62,7 +62,7 @@ def test_training_lowers_loss_and_selects_well(fz, ctx):
     ebs = (1e-2, 1e-3, 1e-4)
     feat, costs = _samples(fz, ctx, TRAIN_SEEDS, (96, 96, 96), ebs)
     print(f"[gpu training] {feat.shape[0]} samples", flush=True)
-    loss = ctx.selector_train(feat, costs, epochs=30, batch=4096, seed=1)
+    loss = ctx.selector_train(feat, costs, epochs=200, batch=1024, seed=1)
     print(f"[gpu training] loss first {loss[0]:.4f} last {loss[-1]:.4f}", flush=True)
     assert np.all(np.isfinite(loss))
     assert loss[-1] < 0.25 * loss[0]
