@@ -42,6 +42,41 @@ SHAPE = (512, 512, 512)
 LINK_GBPS = 35.7  # the paper's measured GPU-to-host bandwidth on its H100 node (Table 1), for Eq. (1)
 
 
+# stage -> (kernel as rocprofv3 names it on the 512^3 first-order Lorenzo
+# workload, the source file that holds it)
+STAGE_KERNEL = {
+    "compress:minmax": ("fz::k_minmax", "fz_quant.hip"),
+    "compress:quant": ("fz::k_quant<3, 0>", "fz_quant.hip"),
+    "compress:encode": ("fz::k_encode<3>", "fz_huffman.hip"),
+    "compress:finalize": ("fz::k_finalize", "fz_huffman.hip"),
+    "decompress:oindex": ("fz::k_outlier_index", "fz_decode.hip"),
+    "decompress:decode": ("fz::k_decode_fast<3, false, true>", "fz_decode.hip"),
+}
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_512cubed_grf_lorenzo1.md")
+
+
+def source_digest(fname: str) -> str:
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2509_20563_amd", "csrc", fname), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(stage: str):
+    """HBM bytes per launch of a stage's kernel from the committed PMC
+    summary (calibrated FETCH_SIZE + WRITE_SIZE), or None when there is
+    none or the kernel's source changed since the counters were taken."""
+    if stage not in STAGE_KERNEL or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    kern, src = STAGE_KERNEL[stage]
+    digest = source_digest(src)
+    with open(TRAFFIC_PROFILE) as f:
+        for line in f:
+            cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 7 and cells[0] == kern:
+                return int(float(cells[4])) if cells[6] == digest else None
+    return None
+
+
 def stage_bytes(stage: str, n: int, nblocks: int, h: dict, total: int) -> float:
     """Algorithmic bytes one launch of a stage must move (see the design notes)."""
     ntiles = (nblocks + 3) // 4
@@ -55,7 +90,8 @@ def stage_bytes(stage: str, n: int, nblocks: int, h: dict, total: int) -> float:
         "finalize": 2 * side + 12 * ntiles,
         "lut": 512,
         "scan": 2 * nblocks + 8 * nblocks,
-        "decode": stream + 2 * nblocks + 8 * h["n_outliers"] + 4 * n,
+        "oindex": 4 * h["n_outliers"] + (8 * nblocks if h["n_outliers"] else 0),
+        "decode": stream + 10 * nblocks + 4 * h["n_outliers"] + (8 * nblocks if h["n_outliers"] else 0) + 4 * n,
         "patch": 8 * h["n_patches"] + 4 * h["n_patches"],
     }.get(stage, 0.0)
 
@@ -177,7 +213,7 @@ def main():
     bytes_per_launch = dom["bytes"] / dom["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": measured_traffic(dom_name),
                 "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": int(bytes_per_launch)}
     stage_summary = {k: {"avg_ms": round(v["ms"] / v["launches"], 4),
                          "gbps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}

@@ -10,6 +10,7 @@ from the numpy versions; tests that compare against the CPU oracle use
 from __future__ import annotations
 
 import math
+import sys
 
 import torch
 
@@ -20,9 +21,25 @@ def _gen(seed: int, device) -> torch.Generator:
     return g
 
 
+def _pow2(n: int) -> int:
+    return 1 << max(0, (int(n) - 1).bit_length())
+
+
 def grf(shape, alpha=3.0, seed=2, device="cuda") -> torch.Tensor:
-    """P(k) ~ k^-alpha Gaussian random field scaled to [0, 1], float32."""
+    """P(k) ~ k^-alpha Gaussian random field scaled to [0, 1], float32.
+
+    The periodic field is synthesised on the power-of-two grid that covers
+    ``shape`` and cropped (the FFT library builds kernels for each new
+    length at run time; power-of-two lengths are precompiled)."""
     shape = tuple(int(s) for s in shape)
+    full = tuple(_pow2(s) for s in shape)
+    f = _grf_periodic(full, alpha, seed, device)
+    f = f[tuple(slice(0, s) for s in shape)]
+    lo, hi = f.min(), f.max()
+    return ((f - lo) / (hi - lo)).contiguous() if hi > lo else torch.zeros(shape, device=device)
+
+
+def _grf_periodic(shape, alpha, seed, device) -> torch.Tensor:
     g = _gen(seed, device)
     noise = torch.randn(shape, generator=g, device=device, dtype=torch.float32)
     spec = torch.fft.rfftn(noise)
@@ -39,8 +56,7 @@ def grf(shape, alpha=3.0, seed=2, device="cuda") -> torch.Tensor:
     del amp, k2
     f = torch.fft.irfftn(spec, s=shape)
     del spec
-    lo, hi = f.min(), f.max()
-    return ((f - lo) / (hi - lo)).contiguous() if hi > lo else torch.zeros_like(f)
+    return f
 
 
 def fronts_spikes(shape=(1024, 1024, 1024), seed=3, n_fronts=64, spike_frac=0.01, spike_sigma=2.0,
@@ -97,6 +113,8 @@ def batch_2d(n_fields=64, seed=4000, hmin=256, hmax=3600, wmin=256, wmax=1800, d
         eb = _log_uniform(g, 1e-5, 1e-2, device)
         f = (off + scale * grf((h, w), alpha=3.0, seed=seed + 100000 + i, device=device).double()).float()
         out.append((f.contiguous(), eb))
+        if (i + 1) % 16 == 0:
+            print(f"[fields_gpu] {i + 1}/{n_fields} fields", file=sys.stderr, flush=True)
     return out
 
 
@@ -124,4 +142,6 @@ def batch_mixed(n_fields=256, seed=5000, max_1d=1 << 26, max_3d_edge=384, device
             a = 3.0 + 2.0 * float(torch.rand(1, generator=g, device=device))
             f = grf((e, e, e), alpha=a, seed=seed + 100000 + i, device=device)
         out.append((f.contiguous(), eb))
+        if (i + 1) % 16 == 0:
+            print(f"[fields_gpu] {i + 1}/{n_fields} fields", file=sys.stderr, flush=True)
     return out

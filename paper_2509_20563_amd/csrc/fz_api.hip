@@ -115,7 +115,9 @@ struct fz_ctx {
     float* sel = nullptr;
     bool have_sel = false;
     // launch configuration of single calls
-    Tune tune_default = {8, 16};
+    // min/max: two workgroups per CU stream the field at close to full
+    // bandwidth with few same-address atomics (which serialise at ~12 ns)
+    Tune tune_default = {8, 2};
     // batches: child contexts with their own scratch and stream (one chain
     // of fields each), staging of the containers, per-field records, the
     // captured graph of the last batch and the autotuner's choices
@@ -349,6 +351,14 @@ int parse_header(const uint8_t* h, uint64_t n, Parsed* r) {
     return FZ_OK;
 }
 
+// Min/max grid: at least 16 values per thread, at most wg_per_cu per CU.
+int minmax_grid(const fz_ctx* c, uint64_t N, uint32_t wg_per_cu) {
+    const uint64_t work = (N + 16 * 256 - 1) / (16 * 256);
+    const uint64_t mmax = (uint64_t)c->n_cu * wg_per_cu;
+    const uint64_t mgrid = work < mmax ? work : mmax;
+    return (int)(mgrid < 1 ? 1 : mgrid);
+}
+
 int compress_check(fz_ctx* c, const fz_params* p, const float* d_in, const void* d_out, uint64_t out_cap, Geom* g) {
     int rc = check_params(p, g);
     if (rc) return rc;
@@ -389,11 +399,7 @@ void compress_enqueue(fz_ctx* c, const fz_params* p, const Geom& g, const float*
                  L0.chunks, L0.stream, nreg_fixed);
     mark("reset");
     if (p->eb_mode == FZ_EB_REL) {
-        uint64_t work = (g.N + 16 * 256 - 1) / (16 * 256);
-        const uint64_t mmax = (uint64_t)c->n_cu * tn.mm_wg_per_cu;
-        uint64_t mgrid = work < mmax ? work : mmax;
-        if (mgrid < 1) mgrid = 1;
-        launch_minmax(st, d_in, g.N, (((uintptr_t)d_in & 15) == 0), c->misc, (int)mgrid);
+        launch_minmax(st, d_in, g.N, (((uintptr_t)d_in & 15) == 0), c->misc, minmax_grid(c, g.N, tn.mm_wg_per_cu));
         mark("minmax");
     }
     if (pred == FZ_PRED_AUTO_TRIAL) {
@@ -403,7 +409,7 @@ void compress_enqueue(fz_ctx* c, const fz_params* p, const Geom& g, const float*
                      c->opos, c->oval, c->ppos, c->pbits, 0, nullptr, nullptr);
         launch_codebook(st, c->hist, c->lens_ref, c->cw_ref, c->misc);
         launch_trial(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, ntiles, c->cw_ref, c->bpred, c->costs);
-        launch_fill32(st, c->hist, kBins, 0);
+        launch_fill32(st, c->hist, kHistCopies * kBins, 0);
         mark("trial");
     }
     if (pred == FZ_PRED_AUTO_MLP) {
@@ -464,6 +470,8 @@ void decompress_enqueue(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_
     launch_scan(st, SCAN_CHUNKS, in + L.chunks, g.nblocks, c->off, c->desc_chunks, &c->misc->stile_ctr, c->misc,
                 r.bits);
     mark("scan");
+    launch_outlier_index(st, g, (const uint32_t*)(in + L.opos), r.nout, c->ofirst, c->oend, c->misc);
+    mark("oindex");
     if (pred == FZ_PRED_LORENZO1) {
         launch_decode(st, g, (const uint32_t*)(in + L.stream), r.words, c->off, (const uint16_t*)(in + L.chunks),
                       c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->ofirst, c->oend,
@@ -510,7 +518,7 @@ int fz_ctx_create(fz_ctx** out, int device, uint64_t max_elems) {
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->n_cu = prop.multiProcessorCount;
     bool ok = hipMalloc((void**)&c->misc, sizeof(Misc)) == hipSuccess &&
-              hipMalloc((void**)&c->hist, sizeof(uint32_t) * kBins) == hipSuccess &&
+              hipMalloc((void**)&c->hist, sizeof(uint32_t) * kHistCopies * kBins) == hipSuccess &&
               hipMalloc((void**)&c->cw, sizeof(uint32_t) * kBins) == hipSuccess &&
               hipMalloc((void**)&c->cw_ref, sizeof(uint32_t) * kBins) == hipSuccess &&
               hipMalloc((void**)&c->lens_ref, kBins / 2) == hipSuccess &&
@@ -688,10 +696,8 @@ int analysis_begin(fz_ctx* c, const fz_params* p, const float* d_in, hipStream_t
     t_begin(c, st);
     launch_reset(st, c->misc, c->hist, nullptr, 0, nullptr, 0, nullptr, 0, 0, 0, 0);
     if (p->eb_mode == FZ_EB_REL) {
-        uint64_t work = (g->N + 16 * 256 - 1) / (16 * 256);
-        uint64_t mgrid = work < (uint64_t)c->n_cu * 16 ? work : (uint64_t)c->n_cu * 16;
-        if (mgrid < 1) mgrid = 1;
-        launch_minmax(st, d_in, g->N, (((uintptr_t)d_in & 15) == 0), c->misc, (int)mgrid);
+        launch_minmax(st, d_in, g->N, (((uintptr_t)d_in & 15) == 0), c->misc,
+                      minmax_grid(c, g->N, c->tune_default.mm_wg_per_cu));
     }
     return FZ_OK;
 }

@@ -13,6 +13,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // ------------------------------------------------------------- constants
 constexpr int kRadius = 512;      // residuals -511..511 map to codes 1..1023
 constexpr int kBins = 1024;       // code 0 marks an outlier
+// Copies of the global code histogram: workgroup w adds into copy
+// w % kHistCopies, so at most 1/kHistCopies of the workgroups chain their
+// atomics on one address; the codebook kernel sums the copies.
+constexpr int kHistCopies = 16;
 constexpr int kLmax = 12;         // longest Huffman codeword, LUT index width
 constexpr int kLut = 1 << kLmax;  // decode table entries
 constexpr int kHdr = 128;         // container header bytes
@@ -344,20 +348,26 @@ __device__ inline uint32_t canonical_code(uint32_t len, CanonShared& sh) {
         if (len == (uint32_t)L) myrank = __popcll(m & ((1ull << lane) - 1));
     }
     __syncthreads();
-    if (t == 0) {
-        uint32_t code = 0, off = 0;
-        for (int L = 1; L <= kLmax; L++) {
-            uint32_t c = 0;
+    if (wave == 0) {
+        // lane L (1..kLmax): exclusive prefix of its length's counts over
+        // the waves; then first code and sorted offset per length, in order
+        uint32_t c = 0;
+        if (lane >= 1 && lane <= (uint32_t)kLmax)
             for (int w = 0; w < 16; w++) {
-                uint32_t v = sh.wave_cnt[L][w];
-                sh.wave_cnt[L][w] = c;  // exclusive prefix over waves
+                const uint32_t v = sh.wave_cnt[lane][w];
+                sh.wave_cnt[lane][w] = c;
                 c += v;
             }
-            sh.count[L] = c;
-            sh.first[L] = code;
-            sh.offset[L] = off;
-            code = (code + c) << 1;
-            off += c;
+        uint32_t code = 0, off = 0;
+        for (int L = 1; L <= kLmax; L++) {
+            const uint32_t cL = (uint32_t)__shfl((int)c, L, 64);
+            if (lane == (uint32_t)L) {
+                sh.count[L] = cL;
+                sh.first[L] = code;
+                sh.offset[L] = off;
+            }
+            code = (code + cL) << 1;
+            off += cL;
         }
     }
     __syncthreads();

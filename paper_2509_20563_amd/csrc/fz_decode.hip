@@ -191,8 +191,9 @@ __device__ __forceinline__ void dec_row8(LaneDec& ld, const uint16_t* LUT, uint3
     }
 }
 
-// Wave totals of the outlier consistency data to Misc.
-__device__ __forceinline__ void outlier_totals(uint32_t lane, bool active, const OutQ& oq, uint32_t oi0,
+// Workgroup totals of the outlier consistency data to Misc (called by all
+// 256 threads; one pair of atomics per workgroup).
+__device__ __forceinline__ void outlier_totals(uint32_t t, bool active, const OutQ& oq, uint32_t oi0,
                                                Misc* misc) {
     uint32_t c = active ? oq.oi - oi0 : 0u;
     uint64_t h = active ? oq.hash : 0ull;
@@ -201,9 +202,20 @@ __device__ __forceinline__ void outlier_totals(uint32_t lane, bool active, const
         c += __shfl_xor(c, d, 64);
         h += __shfl_xor(h, d, 64);
     }
-    if (lane == 0 && c) {
-        atomicAdd(&misc->code0_count, c);
-        atomicAdd((unsigned long long*)&misc->ohash_dec, (unsigned long long)h);
+    __shared__ uint32_t sc[4];
+    __shared__ uint64_t sh[4];
+    if ((t & 63) == 0) {
+        sc[t >> 6] = c;
+        sh[t >> 6] = h;
+    }
+    __syncthreads();
+    if (t == 0) {
+        c = sc[0] + sc[1] + sc[2] + sc[3];
+        h = sh[0] + sh[1] + sh[2] + sh[3];
+        if (c) {
+            atomicAdd(&misc->code0_count, c);
+            atomicAdd((unsigned long long*)&misc->ohash_dec, (unsigned long long)h);
+        }
     }
 }
 
@@ -328,7 +340,7 @@ __global__ __launch_bounds__(256) void k_decode(
     }
     if (active && ld.consumed(start) != chunks[b]) bad = true;
     if (bad) atomicOr(&misc->flags, F_CORRUPT);
-    outlier_totals(t & 63, active, oq, oi0, misc);
+    outlier_totals(t, active, oq, oi0, misc);
 }
 
 // ------------------------------------------------ fast decode of full blocks
@@ -623,7 +635,7 @@ __global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint3
     OutQ oq;
     oq.oi = fd.oi;
     oq.hash = fd.hash;
-    outlier_totals(t & 63, active, oq, first, misc);
+    outlier_totals(t, active, oq, first, misc);
 }
 
 // ---------------------------------------------- per-block predictor decode
@@ -688,7 +700,7 @@ __global__ __launch_bounds__(256) void k_decode_res(Geom g, const uint32_t* __re
     }
     if (active && ld.consumed(start) != chunks[b]) bad = true;
     if (bad) atomicOr(&misc->flags, F_CORRUPT);
-    outlier_totals(t & 63, active, oq, oi0, misc);
+    outlier_totals(t, active, oq, oi0, misc);
 }
 
 // One wave (workgroup of 64) per block: residuals -> grid values in LDS by
@@ -798,30 +810,63 @@ __global__ __launch_bounds__(64) void k_inverse(Geom g, const int32_t* __restric
 }
 
 // ------------------------------------------------------ outlier block index
-// ofirst[b] = index of the first outlier of block b (blocks with outliers).
-// First list index of each block's outliers; the list must be strictly
-// increasing; the sum of pos_hash over the list for the decode-side check.
-// (ofirst, oend: one past the block's last outlier; both zero for a block
-// without outliers, cleared beforehand)
+// First list index of each block's outliers (ofirst) and one past its last
+// (oend), both left at zero for a block without outliers (cleared
+// beforehand); the list must be strictly increasing; the sum of pos_hash
+// over the list for the decode-side check.  Each thread takes groups of 4
+// consecutive entries (one 16-byte load when the list is aligned), its
+// neighbours at the group edges by two scalar loads that hit the cache
+// lines of the adjacent lanes; the workgroup reduces its hash and flag and
+// adds them with one atomic each (few workgroups, so few same-address
+// atomics: these serialise at the memory side).
+__device__ __forceinline__ void outlier_entry(uint64_t i, uint32_t p, bool has_prev, uint32_t prev, bool has_next,
+                                              uint32_t next, uint32_t nblocks, uint32_t* __restrict__ ofirst,
+                                              uint32_t* __restrict__ oend, uint64_t& h, bool& bad) {
+    const uint32_t b = p >> 9;
+    bad |= (has_prev && prev >= p) || b >= nblocks;
+    h += pos_hash(p);
+    if (b < nblocks && (!has_prev || (prev >> 9) != b)) ofirst[b] = (uint32_t)i;
+    if (b < nblocks && (!has_next || (next >> 9) != b)) oend[b] = (uint32_t)(i + 1);
+}
+
 __global__ __launch_bounds__(256) void k_outlier_index(const uint32_t* __restrict__ opos, uint64_t n_out,
                                                        uint32_t nblocks, uint32_t* __restrict__ ofirst,
-                                                       uint32_t* __restrict__ oend, Misc* misc) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+                                                       uint32_t* __restrict__ oend, int vec, Misc* misc) {
+    const uint32_t t = threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    const uint64_t ngroups = (n_out + 3) / 4;
     uint64_t h = 0;
     bool bad = false;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_out; i += stride) {
-        const uint32_t p = opos[i];
-        const uint32_t b = p >> 9;
-        const uint32_t prev = i ? opos[i - 1] : 0u;
-        bad |= (i && prev >= p) || b >= nblocks;
-        h += pos_hash(p);
-        if (b < nblocks && (i == 0 || (prev >> 9) != b)) ofirst[b] = (uint32_t)i;
-        if (b < nblocks && (i + 1 == n_out || (opos[i + 1] >> 9) != b)) oend[b] = (uint32_t)(i + 1);
+    for (uint64_t q = (uint64_t)blockIdx.x * 256 + t; q < ngroups; q += stride) {
+        const uint64_t i0 = 4 * q;
+        uint32_t v[4];
+        if (vec && i0 + 4 <= n_out) {
+            const uint4 a = *reinterpret_cast<const uint4*>(opos + i0);
+            v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; k++) v[k] = i0 + k < n_out ? opos[i0 + k] : 0u;
+        }
+        const uint32_t prev = i0 ? opos[i0 - 1] : 0u;
+        const uint32_t next = i0 + 4 < n_out ? opos[i0 + 4] : 0u;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const uint64_t i = i0 + k;
+            if (i < n_out)
+                outlier_entry(i, v[k], i > 0, k ? v[k - 1] : prev, i + 1 < n_out, k < 3 ? v[k + 1] : next, nblocks,
+                              ofirst, oend, h, bad);
+        }
     }
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) h += __shfl_xor(h, d, 64);
-    if ((threadIdx.x & 63) == 0 && h) atomicAdd((unsigned long long*)&misc->ohash_list, (unsigned long long)h);
-    if (bad) atomicOr(&misc->flags, F_CORRUPT);
+    __shared__ uint64_t sh[4];
+    if ((t & 63) == 0) sh[t >> 6] = h;
+    const int any_bad = __syncthreads_or(bad ? 1 : 0);
+    if (t == 0) {
+        const uint64_t hs = sh[0] + sh[1] + sh[2] + sh[3];
+        if (hs) atomicAdd((unsigned long long*)&misc->ohash_list, (unsigned long long)hs);
+        if (any_bad) atomicOr(&misc->flags, F_CORRUPT);
+    }
 }
 
 // ----------------------------------------------------------------- patches
@@ -898,23 +943,26 @@ Interior interior_of(const Geom& g) {
     return r;
 }
 
-void outlier_index(hipStream_t st, const Geom& g, const uint32_t* opos, uint64_t n_out, uint32_t* ofirst,
-                   uint32_t* oend, Misc* misc) {
+}  // namespace
+
+// Outlier list index and list hash (before either decoder).
+void launch_outlier_index(hipStream_t st, const Geom& g, const uint32_t* opos, uint64_t n_out, uint32_t* ofirst,
+                          uint32_t* oend, Misc* misc) {
     if (!n_out) return;
     launch_fill32(st, ofirst, g.nblocks, 0);
     launch_fill32(st, oend, g.nblocks, 0);
-    uint64_t og = (n_out + 255) / 256;
-    if (og > 4096) og = 4096;
+    // about 16 groups of 4 entries per thread, at most 1024 workgroups
+    uint64_t og = (n_out + 4 * 16 * 256 - 1) / (4 * 16 * 256);
+    if (og > 1024) og = 1024;
+    const int vec = ((uintptr_t)opos & 15) == 0;
     hipLaunchKernelGGL(k_outlier_index, dim3((uint32_t)og), dim3(256), 0, st, opos, n_out, g.nblocks, ofirst, oend,
-                       misc);
+                       vec, misc);
 }
-}  // namespace
 
 void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,
                    const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
                    const int32_t* oval, uint32_t* ofirst, uint32_t* oend, uint64_t n_out, double e2, float* out,
                    int vec, Misc* misc) {
-    outlier_index(st, g, opos, n_out, ofirst, oend, misc);
     const Interior I = interior_of(g);
     const bool fast = I.n > 0;
     if (fast) {
@@ -954,7 +1002,6 @@ void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, u
                         const int32_t* oval, uint32_t* ofirst, uint32_t* oend, uint64_t n_out, int32_t* res,
                         int fixed_pred, const uint8_t* bpred, const uint64_t* reg_idx, const int32_t* coefs,
                         uint64_t nreg, double e2, float* out, int vec, Misc* misc) {
-    outlier_index(st, g, opos, n_out, ofirst, oend, misc);
     const Interior I = interior_of(g);
     if (I.n) {
         const uint32_t fg = (I.n + 255) / 256;

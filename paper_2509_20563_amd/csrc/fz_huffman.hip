@@ -20,7 +20,7 @@ namespace fz {
 // next two items one level deeper.  A symbol's length is the number of
 // levels at which it is selected.  Leaves keep their sorted order in every
 // list, so a level is summarised by a bitmask of leaf positions.
-__global__ __launch_bounds__(1024) void k_codebook(const uint32_t* __restrict__ hist, uint8_t* __restrict__ out_lens,
+__global__ __launch_bounds__(1024) void k_codebook(uint32_t* __restrict__ hist, uint8_t* __restrict__ out_lens,
                                                    uint32_t* __restrict__ cw, Misc* misc) {
     __shared__ uint64_t key[kBins];
     __shared__ uint64_t la[2 * kBins], lb[2 * kBins];
@@ -32,7 +32,14 @@ __global__ __launch_bounds__(1024) void k_codebook(const uint32_t* __restrict__ 
     __shared__ CanonShared cs;
 
     const uint32_t t = threadIdx.x;
-    const uint32_t h = hist[t];
+    // sum the histogram copies; copy 0 keeps the total, the others are
+    // cleared
+    uint32_t h = 0;
+#pragma unroll
+    for (int k = 0; k < kHistCopies; k++) h += hist[k * kBins + t];
+    hist[t] = h;
+#pragma unroll
+    for (int k = 1; k < kHistCopies; k++) hist[k * kBins + t] = 0;
     slen[t] = 0;
     key[t] = h ? (((uint64_t)h << 10) | t) : ~0ull;
     if (t == 0) s_first_unused = kBins;
@@ -44,21 +51,29 @@ __global__ __launch_bounds__(1024) void k_codebook(const uint32_t* __restrict__ 
         if (h > 0) slen[t] = 1;
         if (t == s_first_unused) slen[t] = 1;
     } else if (n >= 2) {
-        // bitonic sort of (count << 10 | symbol), unused symbols last
+        // bitonic sort of (count << 10 | symbol), unused symbols last; a
+        // thread keeps its key in a register: partners closer than 64 are
+        // exchanged inside the wave, farther ones through two alternating
+        // LDS buffers (one barrier per such stage)
+        uint64_t v = key[t];
+        int buf = 0;
         for (uint32_t k = 2; k <= (uint32_t)kBins; k <<= 1) {
             for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                __syncthreads();
-                const uint32_t ixj = t ^ j;
-                if (ixj > t) {
-                    uint64_t a = key[t], b = key[ixj];
-                    const bool up = (t & k) == 0;
-                    if ((a > b) == up) {
-                        key[t] = b;
-                        key[ixj] = a;
-                    }
+                uint64_t o;
+                if (j >= 64) {
+                    uint64_t* kb = buf ? lb : la;
+                    kb[t] = v;
+                    __syncthreads();
+                    o = kb[t ^ j];
+                    buf ^= 1;
+                } else {
+                    o = __shfl_xor(v, (int)j, 64);
                 }
+                const bool keep_min = ((t & j) == 0) == ((t & k) == 0);
+                v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
             }
         }
+        key[t] = v;
         for (int l = 0; l <= kLmax; l++)
             if (t < 64) mask[l][t] = 0;
         __syncthreads();
@@ -102,15 +117,19 @@ __global__ __launch_bounds__(1024) void k_codebook(const uint32_t* __restrict__ 
             nxt = tmp;
             len_cur = (uint32_t)n + np;
         }
-        if (t == 0) {
+        if (t < 64) {
+            // leaves among the first `take` items of each level: lane =
+            // 32-item word of the level's bitmask, popcounts summed over
+            // the wave
             uint32_t take = 2 * (uint32_t)n - 2;
             for (int l = 1; l <= kLmax; l++) {
                 if (take > 2 * kBins - 1) take = 2 * kBins - 1;
-                uint32_t k = 0;
-                const uint32_t full = take >> 5;
-                for (uint32_t w = 0; w < full; w++) k += __popc(mask[l][w]);
-                if (take & 31) k += __popc(mask[l][full] & ((1u << (take & 31)) - 1u));
-                klev[l] = k;
+                const uint32_t w0 = 32 * t;
+                const uint32_t w = mask[l][t];
+                uint32_t k = take <= w0 ? 0u : (uint32_t)__popc(take - w0 >= 32 ? w : (w & ((1u << (take - w0)) - 1u)));
+#pragma unroll
+                for (int d = 32; d > 0; d >>= 1) k += __shfl_xor(k, d, 64);
+                if (t == 0) klev[l] = k;
                 take = 2 * (take - k);
             }
         }
@@ -140,25 +159,21 @@ __global__ __launch_bounds__(1024) void k_codebook(const uint32_t* __restrict__ 
 }
 
 // --------------------------------------------------------------- encode
-// Append `len` bits of `code` at bit position nb of a 128-bit string held
-// most-significant-bit first in (hi, lo).
-__device__ __forceinline__ void append_bits(uint64_t& hi, uint64_t& lo, uint32_t& nb, uint32_t code, uint32_t len) {
-    // the codeword occupies bits [nb, nb + len): as a 128-bit value it is
-    // code << (128 - nb - len); both halves are formed with in-range shifts
-    const uint32_t end = nb + len;
-    const uint32_t sh = 128 - end;  // 32..127
-    const uint64_t c = code;
+// (hi, lo) |= v << sh as 128-bit values, sh in [0, 127], the result fits.
+__device__ __forceinline__ void or_shl128(uint64_t& hi, uint64_t& lo, uint64_t v, uint32_t sh) {
     const bool upper = sh >= 64;
-    hi |= upper ? (c << ((sh - 64) & 63)) : (c >> ((64 - sh) & 63));
-    lo |= upper ? 0ull : (c << (sh & 63));
-    nb = end;
+    const uint32_t s = sh & 63;
+    hi |= upper ? (v << s) : (s ? (v >> ((64 - s) & 63)) : 0ull);
+    lo |= upper ? 0ull : (v << s);
 }
 
 constexpr int kEncWords = kTileBlocks * kBlockElems * kLmax / 32 + 8;
 
+// The (codeword | length << 16) entries of a lane's 8 codes (0 past the
+// block's real values) and their bit count.
 template <int ND>
-__device__ __forceinline__ uint32_t load_codes(const uint16_t* __restrict__ codes, const Geom& g, uint32_t b,
-                                               uint32_t s, uint32_t c8[8]) {
+__device__ __forceinline__ uint32_t load_entries(const uint16_t* __restrict__ codes, const Geom& g, uint32_t b,
+                                                 uint32_t s, const uint32_t* CW, uint32_t e8[8]) {
     uint32_t nv = 0;
     uint4 pk = make_uint4(0, 0, 0, 0);
     if (b < g.nblocks) {
@@ -166,9 +181,15 @@ __device__ __forceinline__ uint32_t load_codes(const uint16_t* __restrict__ code
         seg_index<ND>(g, info, s, nv);
         if (nv) pk = *reinterpret_cast<const uint4*>(&codes[(uint64_t)b * kBlockElems + s * 8]);
     }
-    c8[0] = pk.x & 0xFFFFu; c8[1] = pk.x >> 16; c8[2] = pk.y & 0xFFFFu; c8[3] = pk.y >> 16;
-    c8[4] = pk.z & 0xFFFFu; c8[5] = pk.z >> 16; c8[6] = pk.w & 0xFFFFu; c8[7] = pk.w >> 16;
-    return nv;
+    const uint32_t c8[8] = {pk.x & 0xFFFFu, pk.x >> 16, pk.y & 0xFFFFu, pk.y >> 16,
+                            pk.z & 0xFFFFu, pk.z >> 16, pk.w & 0xFFFFu, pk.w >> 16};
+    uint32_t nb = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        e8[i] = i < (int)nv ? CW[c8[i] & (kBins - 1)] : 0u;
+        nb += e8[i] >> 16;
+    }
+    return nb;
 }
 
 // Single pass over the codes.  A workgroup takes kEncTiles consecutive
@@ -188,7 +209,7 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ cod
                                                 uint64_t* __restrict__ tile_start, uint32_t* __restrict__ tfirst,
                                                 uint32_t* __restrict__ tlast) {
     __shared__ uint32_t CW[kBins];
-    __shared__ uint32_t W[kEncWords];
+    __shared__ uint32_t W[2][kEncWords];  // alternate tiles: one barrier per tile
     __shared__ uint32_t wsum[kEncTiles][4];
     __shared__ uint64_t s_excl;
     uint16_t* chunks = reinterpret_cast<uint16_t*>(out + misc->off_chunks);
@@ -196,21 +217,22 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ cod
     const uint32_t t = threadIdx.x, lane = t & 63;
     const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 6));
     for (uint32_t i = t; i < (uint32_t)kBins; i += 256) CW[i] = cw_g[i];
-    for (uint32_t i = t; i < (uint32_t)kEncWords; i += 256) W[i] = 0;
+    for (uint32_t i = t; i < (uint32_t)(2 * kEncWords); i += 256) (&W[0][0])[i] = 0;
     __syncthreads();
     const uint32_t grp = blockIdx.x;
     const uint32_t tile0 = grp * kEncTiles;
-    // pass over the group's codes: lengths, chunk table, tile totals
-    uint32_t c8[kEncTiles][8];
-    uint32_t nvs[kEncTiles], nbs[kEncTiles];
+    // pass over the group's codes: codeword entries, chunk table, tile totals
+    uint32_t e8[kEncTiles][8];
 #pragma unroll
     for (uint32_t k = 0; k < kEncTiles; k++) {
         const uint32_t b = (tile0 + k) * kTileBlocks + wave;
-        nvs[k] = (tile0 + k < ntiles) ? load_codes<ND>(codes, g, b, lane, c8[k]) : 0u;
         uint32_t nb = 0;
+        if (tile0 + k < ntiles) {
+            nb = load_entries<ND>(codes, g, b, lane, CW, e8[k]);
+        } else {
 #pragma unroll
-        for (int i = 0; i < 8; i++) nb += (i < (int)nvs[k]) ? (CW[c8[k][i]] >> 16) : 0u;
-        nbs[k] = nb;
+            for (int i = 0; i < 8; i++) e8[k][i] = 0;
+        }
         const uint32_t incl = wave_incl_scan(nb);
         if (lane == 63) {
             wsum[k][wave] = incl;
@@ -233,6 +255,7 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ cod
     for (uint32_t k = 0; k < kEncTiles; k++) {
         const uint32_t tile = tile0 + k;
         if (tile >= ntiles) break;  // uniform
+        uint32_t* Wk = W[k & 1];
         uint32_t wpre = 0, T = 0;
         for (uint32_t w = 0; w < 4; w++) {
             if (w < wave) wpre += wsum[k][w];
@@ -242,46 +265,56 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ cod
             tile_start[tile] = G;  // k_finalize merges the shared boundary words
             if (tile != ntiles - 1 && T < 32) atomicOr(&misc->flags, F_INTERNAL);
         }
-        uint64_t hi = 0, lo = 0;
-        uint32_t nb = 0;
+        // the lane's bit string as two shift-or chains of 4 codewords
+        // (at most 48 bits each)
+        uint64_t a0 = 0, a1 = 0;
+        uint32_t n0 = 0, n1 = 0;
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
-            if (i < (int)nvs[k]) {
-                const uint32_t e = CW[c8[k][i]];
-                append_bits(hi, lo, nb, e & 0xFFFFu, e >> 16);
-            }
+        for (int i = 0; i < 4; i++) {
+            const uint32_t e = e8[k][i], l = e >> 16;
+            a0 = (a0 << l) | (e & 0xFFFFu);
+            n0 += l;
         }
+#pragma unroll
+        for (int i = 4; i < 8; i++) {
+            const uint32_t e = e8[k][i], l = e >> 16;
+            a1 = (a1 << l) | (e & 0xFFFFu);
+            n1 += l;
+        }
+        const uint32_t nb = n0 + n1;
         const uint32_t sh = (uint32_t)(G & 31);
         // the scan runs with every lane active (lanes with no bits add 0)
         const uint32_t incl = wave_incl_scan(nb);
         if (nb) {
+            // place the string at bit o of word w0, most significant first:
+            // 128-bit window (hi, lo) = words w0 .. w0 + 3 (o + nb <= 127)
             const uint32_t p = sh + wpre + incl - nb;
             const uint32_t o = p & 31, w0 = p >> 5;
-            const uint32_t s0 = (uint32_t)(hi >> 32), s1 = (uint32_t)hi, s2 = (uint32_t)(lo >> 32),
-                           s3 = (uint32_t)lo;
-            const uint32_t o0 = s0 >> o;
-            const uint32_t o1 = __builtin_amdgcn_alignbit(s0, s1, o);
-            const uint32_t o2 = __builtin_amdgcn_alignbit(s1, s2, o);
-            const uint32_t o3 = __builtin_amdgcn_alignbit(s2, s3, o);
-            if (o0) atomicOr(&W[w0], o0);
-            if (o1) atomicOr(&W[w0 + 1], o1);
-            if (o2) atomicOr(&W[w0 + 2], o2);
-            if (o3) atomicOr(&W[w0 + 3], o3);
+            uint64_t hi = 0, lo = 0;
+            or_shl128(hi, lo, a0, (128 - o - n0) & 127);  // a0 = 0 when n0 = 0
+            or_shl128(hi, lo, a1, 128 - o - nb);
+            const uint32_t o0 = (uint32_t)(hi >> 32), o1 = (uint32_t)hi, o2 = (uint32_t)(lo >> 32),
+                           o3 = (uint32_t)lo;
+            if (o0) atomicOr(&Wk[w0], o0);
+            if (o1) atomicOr(&Wk[w0 + 1], o1);
+            if (o2) atomicOr(&Wk[w0 + 2], o2);
+            if (o3) atomicOr(&Wk[w0 + 3], o3);
         }
         __syncthreads();
         // interior words go to the stream; the partial first and last words
-        // are shared with the neighbouring tiles and merged by k_finalize
+        // are shared with the neighbouring tiles and merged by k_finalize;
+        // the buffer is cleared for the tile after next (the barrier of the
+        // next tile separates the two)
         const uint32_t nwords = (sh + T + 31) >> 5;
         const bool last_partial = ((sh + T) & 31) != 0 && tile != ntiles - 1;
         const uint64_t wbase = G >> 5;
         for (uint32_t w = t; w < nwords; w += 256) {
-            const uint32_t v = W[w];
-            W[w] = 0;
+            const uint32_t v = Wk[w];
+            Wk[w] = 0;
             if (w == 0 && sh != 0) tfirst[tile] = v;
             else if (w == nwords - 1 && last_partial) tlast[tile] = v;
             else stream[wbase + w] = v;
         }
-        __syncthreads();
         G += T;
     }
 }
@@ -355,13 +388,42 @@ __global__ __launch_bounds__(256) void k_finalize(Geom g, uint32_t mode, double 
             const uint64_t off = tile_off[tile];
             const uint64_t slot = tile * (uint64_t)(kTileBlocks * kBlockElems);
             const uint32_t co = c & 0xFFFFu, cp = c >> 16;
-            for (uint32_t j = lane; j < co; j += 64) {
-                o_pos[(off & m31) + j] = opos[slot + j];
-                o_val[(off & m31) + j] = oval[slot + j];
+            // four entries per lane and pass, all loads issued before the
+            // stores (the copy is latency-bound otherwise)
+            for (uint32_t j0 = 0; j0 < co; j0 += 256) {
+                uint32_t a[4];
+                int32_t v[4];
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const uint32_t j = j0 + lane + 64 * k;
+                    a[k] = j < co ? opos[slot + j] : 0u;
+                    v[k] = j < co ? oval[slot + j] : 0;
+                }
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const uint32_t j = j0 + lane + 64 * k;
+                    if (j < co) {
+                        o_pos[(off & m31) + j] = a[k];
+                        o_val[(off & m31) + j] = v[k];
+                    }
+                }
             }
-            for (uint32_t j = lane; j < cp; j += 64) {
-                p_pos[(off >> 31) + j] = ppos[slot + j];
-                p_bits[(off >> 31) + j] = pbits[slot + j];
+            for (uint32_t j0 = 0; j0 < cp; j0 += 256) {
+                uint32_t a[4], v[4];
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const uint32_t j = j0 + lane + 64 * k;
+                    a[k] = j < cp ? ppos[slot + j] : 0u;
+                    v[k] = j < cp ? pbits[slot + j] : 0u;
+                }
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const uint32_t j = j0 + lane + 64 * k;
+                    if (j < cp) {
+                        p_pos[(off >> 31) + j] = a[k];
+                        p_bits[(off >> 31) + j] = v[k];
+                    }
+                }
             }
         }
     }
@@ -456,7 +518,7 @@ void launch_verbatim(hipStream_t st, const Geom& g, uint32_t mode, double eb, ui
     hipLaunchKernelGGL(k_verbatim, dim3(1024), dim3(256), 0, st, g, mode, eb, pred, misc, x, out, vec);
 }
 
-void launch_codebook(hipStream_t st, const uint32_t* hist, uint8_t* out_lens, uint32_t* cw, Misc* misc) {
+void launch_codebook(hipStream_t st, uint32_t* hist, uint8_t* out_lens, uint32_t* cw, Misc* misc) {
     hipLaunchKernelGGL(k_codebook, dim3(1), dim3(1024), 0, st, hist, out_lens, cw, misc);
 }
 
@@ -483,7 +545,11 @@ void launch_finalize(hipStream_t st, const Geom& g, uint32_t mode, double eb, ui
                      const uint32_t* tlast, const uint32_t* tile_cnt, const uint64_t* tile_off, const uint32_t* opos,
                      const int32_t* oval, const uint32_t* ppos, const uint32_t* pbits, const uint8_t* bpred,
                      const uint64_t* reg_idx, const int32_t* coef) {
-    hipLaunchKernelGGL(k_finalize, dim3(1024), dim3(256), 0, st, g, mode, eb, pred, misc, out, ntiles, tile_start,
+    // about four tiles per wave for the outlier/patch compaction
+    uint32_t grid = (ntiles + 15) / 16;
+    if (grid < 1024) grid = 1024;
+    if (grid > 8192) grid = 8192;
+    hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(256), 0, st, g, mode, eb, pred, misc, out, ntiles, tile_start,
                        tfirst, tlast, tile_cnt, tile_off, opos, oval, ppos, pbits, bpred, reg_idx, coef);
 }
 

@@ -29,7 +29,7 @@ void launch_scan(hipStream_t st, int kind, const void* in, uint32_t n, uint64_t*
 uint32_t scan_tiles(uint32_t n);
 
 // fz_huffman.hip
-void launch_codebook(hipStream_t st, const uint32_t* hist, uint8_t* out_lens, uint32_t* cw, Misc* misc);
+void launch_codebook(hipStream_t st, uint32_t* hist, uint8_t* out_lens, uint32_t* cw, Misc* misc);
 void launch_encode(hipStream_t st, int grid, const uint16_t* codes, const Geom& g, const uint32_t* cw, Misc* misc,
                    uint32_t ntiles, uint8_t* out, uint64_t* desc, uint64_t* tile_start, uint32_t* tfirst,
                    uint32_t* tlast);
@@ -62,6 +62,8 @@ void launch_gather_headers(hipStream_t st, const uint8_t* in, const uint64_t* of
 // fz_decode.hip
 void launch_copy(hipStream_t st, const uint8_t* src, float* dst, uint64_t n);
 void launch_lut(hipStream_t st, const uint8_t* lens_packed, uint16_t* lut, Misc* misc);
+void launch_outlier_index(hipStream_t st, const Geom& g, const uint32_t* opos, uint64_t n_out, uint32_t* ofirst,
+                          uint32_t* oend, Misc* misc);
 void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,
                    const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
                    const int32_t* oval, uint32_t* ofirst, uint32_t* oend, uint64_t n_out, double e2, float* out,

@@ -24,7 +24,7 @@ __global__ void k_reset(Misc* misc, uint32_t* hist, uint64_t* d1, uint32_t n1, u
         m.nreg = nreg;
         *misc = m;
     }
-    for (uint32_t i = gid; i < (uint32_t)kBins; i += stride) hist[i] = 0;
+    for (uint32_t i = gid; i < (uint32_t)(kHistCopies * kBins); i += stride) hist[i] = 0;
     for (uint32_t i = gid; i < n1; i += stride) d1[i] = 0;
     for (uint32_t i = gid; i < n2; i += stride) d2[i] = 0;
     for (uint32_t i = gid; i < n3; i += stride) d3[i] = 0;
@@ -265,8 +265,10 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
             for (int i = 0; i < 8; i++) v[i] = (i < (int)nv) ? x[base + i] : 0.0f;
         }
     };
-    // the values of the workgroup's next tile are loaded one tile ahead,
-    // so their latency overlaps the current tile's phase B
+    // the values of the workgroup's next tile are loaded one tile ahead:
+    // issued right after phase A's barrier, consumed by the next phase A,
+    // so their latency overlaps phase B (issued earlier, the waits for the
+    // current values would also cover them)
     uint32_t pf_nv = 0;
     float pf[8];
     {
@@ -282,13 +284,6 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
             float v[8];
 #pragma unroll
             for (int i = 0; i < 8; i++) v[i] = pf[i];
-            {
-                const uint32_t nt = tile + gridDim.x;
-                uint32_t base = 0;
-                if (nt < ntiles) tile_src(nt, base, pf_nv);
-                else pf_nv = 0;
-                tile_load(base, pf_nv, pf);
-            }
             int32_t q[8];
             uint32_t pm = 0;
             bool bad = false;
@@ -308,6 +303,13 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
             PM[la_bi * kSegs + la_s] = (uint8_t)pm;
         }
         __syncthreads();
+        {
+            const uint32_t nt = tile + gridDim.x;
+            uint32_t base = 0;
+            if (nt < ntiles) tile_src(nt, base, pf_nv);
+            else pf_nv = 0;
+            tile_load(base, pf_nv, pf);
+        }
 
         // ---------------- phase B: wave = block, lane = segment
         const uint32_t s = lane;
@@ -700,7 +702,7 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
     if (MODE == kQuantTrial || MODE == kQuantFeat) return;
     __syncthreads();
     for (uint32_t i = t; i < (uint32_t)kBins; i += 256)
-        if (H[i]) atomicAdd(&hist_g[i], H[i]);
+        if (H[i]) atomicAdd(&hist_g[(blockIdx.x % kHistCopies) * kBins + i], H[i]);
 }
 
 // ------------------------------------------------------------ launchers

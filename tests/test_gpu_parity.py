@@ -158,5 +158,5 @@ def test_stage_timing(fz, ctx):
     assert names == ["reset", "minmax", "quant", "scan_counts", "codebook", "encode", "finalize"]
     ctx.decompress(c)
     names = [n for n, _ in ctx.stage_times()]
-    assert names == ["reset", "lut", "scan", "decode", "patch"]
+    assert names == ["reset", "lut", "scan", "oindex", "decode", "patch"]
     ctx.set_timing(False)
