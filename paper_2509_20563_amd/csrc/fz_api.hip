@@ -67,12 +67,11 @@ struct fz_ctx {
     uint16_t* lut = nullptr;
     uint16_t* codes = nullptr;
     uint64_t codes_cap = 0;
-    // per-tile outlier / patch staging (2048 slots per 4-block tile)
-    uint32_t* opos = nullptr;
-    int32_t* oval = nullptr;
-    uint32_t* ppos = nullptr;
-    uint32_t* pbits = nullptr;
-    uint64_t opos_cap = 0, oval_cap = 0, ppos_cap = 0, pbits_cap = 0;
+    // per-tile outlier / patch staging, (position, value) pairs (2048 slots
+    // per 4-block tile)
+    uint2* ostage = nullptr;
+    uint2* pstage = nullptr;
+    uint64_t ostage_cap = 0, pstage_cap = 0;
     // per-tile counts and prefixes
     uint32_t* tile_cnt = nullptr;
     uint64_t* tile_off = nullptr;
@@ -88,9 +87,9 @@ struct fz_ctx {
     uint64_t desc_cnt_cap = 0, desc_bits_cap = 0, desc_chunks_cap = 0;
     // decode
     uint64_t* off = nullptr;
-    uint32_t* ofirst = nullptr;
-    uint32_t* oend = nullptr;
-    uint64_t off_cap = 0, ofirst_cap = 0, oend_cap = 0;
+    // (first, end) outlier index per block, cleared by the reset kernel
+    uint2* oidx = nullptr;
+    uint64_t off_cap = 0, oidx_cap = 0;
     // per-block predictors: choice, index among regression blocks,
     // coefficients, trial costs, the reference code of the trial, the
     // map-scan descriptors and the residual field of the mapped decoder
@@ -212,10 +211,8 @@ int ensure(fz_ctx* c, const Geom& g) {
     const uint64_t sd_blocks = scan_tiles((uint32_t)nb);
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = grow(c->codes, c->codes_cap, nb * kBlockElems);
-    if (e == hipSuccess) e = grow(c->opos, c->opos_cap, slots);
-    if (e == hipSuccess) e = grow(c->oval, c->oval_cap, slots);
-    if (e == hipSuccess) e = grow(c->ppos, c->ppos_cap, slots);
-    if (e == hipSuccess) e = grow(c->pbits, c->pbits_cap, slots);
+    if (e == hipSuccess) e = grow(c->ostage, c->ostage_cap, slots);
+    if (e == hipSuccess) e = grow(c->pstage, c->pstage_cap, slots);
     if (e == hipSuccess) e = grow(c->tile_cnt, c->tile_cnt_cap, ntiles);
     if (e == hipSuccess) e = grow(c->tile_off, c->tile_off_cap, ntiles);
     if (e == hipSuccess) e = grow(c->tile_start, c->tile_start_cap, ntiles);
@@ -225,8 +222,7 @@ int ensure(fz_ctx* c, const Geom& g) {
     if (e == hipSuccess) e = grow(c->desc_bits, c->desc_bits_cap, encode_groups((uint32_t)ntiles));
     if (e == hipSuccess) e = grow(c->desc_chunks, c->desc_chunks_cap, sd_blocks);
     if (e == hipSuccess) e = grow(c->off, c->off_cap, nb);
-    if (e == hipSuccess) e = grow(c->ofirst, c->ofirst_cap, nb);
-    if (e == hipSuccess) e = grow(c->oend, c->oend_cap, nb);
+    if (e == hipSuccess) e = grow(c->oidx, c->oidx_cap, nb);
     return e == hipSuccess ? FZ_OK : FZ_ERR_NOMEM;
 }
 
@@ -406,7 +402,7 @@ void compress_enqueue(fz_ctx* c, const fz_params* p, const Geom& g, const float*
         // reference code: the Huffman code of the first-order Lorenzo
         // histogram; then every block tries the three predictors
         launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt,
-                     c->opos, c->oval, c->ppos, c->pbits, 0, nullptr, nullptr);
+                     c->ostage, c->pstage, 0, nullptr, nullptr);
         launch_codebook(st, c->hist, c->lens_ref, c->cw_ref, c->misc);
         launch_trial(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, ntiles, c->cw_ref, c->bpred, c->costs);
         launch_fill32(st, c->hist, kHistCopies * kBins, 0);
@@ -415,11 +411,11 @@ void compress_enqueue(fz_ctx* c, const fz_params* p, const Geom& g, const float*
     if (pred == FZ_PRED_AUTO_MLP) {
         // the network chooses each block's predictor inside the quantiser
         launch_quant_select(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles,
-                            c->tile_cnt, c->opos, c->oval, c->ppos, c->pbits, c->sel, c->bpred, c->coef);
+                            c->tile_cnt, c->ostage, c->pstage, c->sel, c->bpred, c->coef);
     } else {
         const int fixed = has_map ? -1 : (int)pred;
         launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt,
-                     c->opos, c->oval, c->ppos, c->pbits, fixed, c->bpred, c->coef);
+                     c->ostage, c->pstage, fixed, c->bpred, c->coef);
     }
     mark("quant");
     if (has_map) {
@@ -434,8 +430,7 @@ void compress_enqueue(fz_ctx* c, const fz_params* p, const Geom& g, const float*
                   c->tlast);
     mark("encode");
     launch_finalize(st, g, p->eb_mode, p->eb, pred, c->misc, out, ntiles, c->tile_start, c->tfirst, c->tlast,
-                    c->tile_cnt, c->tile_off, c->opos, c->oval, c->ppos, c->pbits, c->bpred, c->reg_idx, c->coef);
-    launch_verbatim(st, g, p->eb_mode, p->eb, pred, c->misc, d_in, out);
+                    c->tile_cnt, c->tile_off, c->ostage, c->pstage, c->bpred, c->reg_idx, c->coef, d_in);
     mark("finalize");
 }
 
@@ -462,19 +457,21 @@ void decompress_enqueue(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_
     const Layout L = make_layout(r.nblocks, has_map, r.nreg, r.words, r.nout, r.npat);
     const uint32_t stiles = scan_tiles(g.nblocks);
     const int vec = (((uintptr_t)d_out & 15) == 0) && (g.ndim == 1 || (g.n[0] & 3) == 0);
+    // the reset also clears the per-block outlier index
     launch_reset(st, c->misc, c->hist, c->desc_chunks, stiles, has_map ? c->desc_pmap : nullptr,
-                 has_map ? stiles : 0, nullptr, 0, L.chunks, L.stream, r.nreg);
+                 has_map ? stiles : 0, r.nout ? reinterpret_cast<uint64_t*>(c->oidx) : nullptr,
+                 r.nout ? (uint32_t)g.nblocks : 0u, L.chunks, L.stream, r.nreg);
     mark("reset");
     launch_lut(st, in + L.lens, c->lut, c->misc);
     mark("lut");
     launch_scan(st, SCAN_CHUNKS, in + L.chunks, g.nblocks, c->off, c->desc_chunks, &c->misc->stile_ctr, c->misc,
                 r.bits);
     mark("scan");
-    launch_outlier_index(st, g, (const uint32_t*)(in + L.opos), r.nout, c->ofirst, c->oend, c->misc);
+    launch_outlier_index(st, g, (const uint32_t*)(in + L.opos), r.nout, c->oidx, c->misc);
     mark("oindex");
     if (pred == FZ_PRED_LORENZO1) {
         launch_decode(st, g, (const uint32_t*)(in + L.stream), r.words, c->off, (const uint16_t*)(in + L.chunks),
-                      c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->ofirst, c->oend,
+                      c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->oidx,
                       r.nout, 2.0 * r.eb_abs, d_out, vec, c->misc);
     } else {
         if (has_map) {
@@ -483,7 +480,7 @@ void decompress_enqueue(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_
                         0);
         }
         launch_decode_pred(st, g, (const uint32_t*)(in + L.stream), r.words, c->off, (const uint16_t*)(in + L.chunks),
-                           c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->ofirst, c->oend,
+                           c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->oidx,
                            r.nout, c->res, has_map ? -1 : (int)pred, c->bpred, c->reg_idx, (const int32_t*)(in + L.coef),
                            r.nreg, 2.0 * r.eb_abs, d_out, vec, c->misc);
     }
@@ -549,10 +546,8 @@ void fz_ctx_destroy(fz_ctx* c) {
     hipFree(c->cw);
     hipFree(c->lut);
     hipFree(c->codes);
-    hipFree(c->opos);
-    hipFree(c->oval);
-    hipFree(c->ppos);
-    hipFree(c->pbits);
+    hipFree(c->ostage);
+    hipFree(c->pstage);
     hipFree(c->tile_cnt);
     hipFree(c->tile_off);
     hipFree(c->tile_start);
@@ -562,8 +557,7 @@ void fz_ctx_destroy(fz_ctx* c) {
     hipFree(c->desc_bits);
     hipFree(c->desc_chunks);
     hipFree(c->off);
-    hipFree(c->ofirst);
-    hipFree(c->oend);
+    hipFree(c->oidx);
     hipFree(c->bpred);
     hipFree(c->reg_idx);
     hipFree(c->coef);
@@ -756,8 +750,8 @@ int fz_block_trial(fz_ctx* c, const fz_params* p, const float* d_in, uint8_t* d_
     hipStream_t st = (hipStream_t)stream;
     int rc = analysis_begin(c, p, d_in, st, &g, &vec, &ntiles, &grid);
     if (rc) return rc;
-    launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt, c->opos,
-                 c->oval, c->ppos, c->pbits, 0, nullptr, nullptr);
+    launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt, c->ostage,
+                 c->pstage, 0, nullptr, nullptr);
     launch_codebook(st, c->hist, c->lens_ref, c->cw_ref, c->misc);
     launch_trial(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, ntiles, c->cw_ref, d_choice, d_costs);
     t_mark(c, st, "trial");
@@ -1003,9 +997,9 @@ void key_put(std::vector<uint8_t>& k, const T& v) {
 
 // Every scratch pointer of a context (a captured graph holds them).
 void key_scratch(std::vector<uint8_t>& k, const fz_ctx* c) {
-    const void* ps[] = {c->misc, c->hist, c->cw, c->lut, c->codes, c->opos, c->oval, c->ppos, c->pbits,
+    const void* ps[] = {c->misc, c->hist, c->cw, c->lut, c->codes, c->ostage, c->pstage,
                         c->tile_cnt, c->tile_off, c->tile_start, c->tfirst, c->tlast, c->desc_cnt,
-                        c->desc_bits, c->desc_chunks, c->off, c->ofirst, c->oend, c->bpred, c->reg_idx, c->coef, c->costs,
+                        c->desc_bits, c->desc_chunks, c->off, c->oidx, c->bpred, c->reg_idx, c->coef, c->costs,
                         c->cw_ref, c->lens_ref, c->desc_pmap, c->res, c->sel};
     for (const void* q : ps) key_put(k, q);
 }

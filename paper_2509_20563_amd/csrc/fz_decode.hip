@@ -192,9 +192,11 @@ __device__ __forceinline__ void dec_row8(LaneDec& ld, const uint16_t* LUT, uint3
 }
 
 // Workgroup totals of the outlier consistency data to Misc (called by all
-// 256 threads; one pair of atomics per workgroup).
+// 256 threads at the end of a decoder; one pair of atomics per workgroup).
+// `red` is LDS the caller no longer needs (12 words), reused after a
+// barrier.
 __device__ __forceinline__ void outlier_totals(uint32_t t, bool active, const OutQ& oq, uint32_t oi0,
-                                               Misc* misc) {
+                                               Misc* misc, uint32_t* red) {
     uint32_t c = active ? oq.oi - oi0 : 0u;
     uint64_t h = active ? oq.hash : 0ull;
 #pragma unroll
@@ -202,16 +204,21 @@ __device__ __forceinline__ void outlier_totals(uint32_t t, bool active, const Ou
         c += __shfl_xor(c, d, 64);
         h += __shfl_xor(h, d, 64);
     }
-    __shared__ uint32_t sc[4];
-    __shared__ uint64_t sh[4];
+    __syncthreads();
     if ((t & 63) == 0) {
-        sc[t >> 6] = c;
-        sh[t >> 6] = h;
+        const uint32_t w = t >> 6;
+        red[3 * w] = c;
+        red[3 * w + 1] = (uint32_t)h;
+        red[3 * w + 2] = (uint32_t)(h >> 32);
     }
     __syncthreads();
     if (t == 0) {
-        c = sc[0] + sc[1] + sc[2] + sc[3];
-        h = sh[0] + sh[1] + sh[2] + sh[3];
+        c = 0;
+        h = 0;
+        for (int w = 0; w < 4; w++) {
+            c += red[3 * w];
+            h += ((uint64_t)red[3 * w + 2] << 32) | red[3 * w + 1];
+        }
         if (c) {
             atomicAdd(&misc->code0_count, c);
             atomicAdd((unsigned long long*)&misc->ohash_dec, (unsigned long long)h);
@@ -228,7 +235,7 @@ template <int ND>
 __global__ __launch_bounds__(256) void k_decode(
     Geom g, const uint32_t* __restrict__ stream, uint64_t nwords, const uint64_t* __restrict__ off,
     const uint16_t* __restrict__ chunks, const uint16_t* __restrict__ lut_g, const uint32_t* __restrict__ opos,
-    const int32_t* __restrict__ oval, const uint32_t* __restrict__ ofirst, uint64_t n_out, double e2,
+    const int32_t* __restrict__ oval, const uint2* __restrict__ oidx, uint64_t n_out, double e2,
     float* __restrict__ out, int vec, Misc* misc, int skip, uint32_t ib0, uint32_t ib1, uint32_t ib2) {
     __shared__ uint16_t LUT[kLut];
     __shared__ uint32_t RING[kDecLanes * kRing];
@@ -247,7 +254,7 @@ __global__ __launch_bounds__(256) void k_decode(
     ld.ring = &RING[t];
     ld.init(active ? start : 0);
     OutQ oq;
-    const uint32_t oi0 = n_out ? ofirst[b] : 0;
+    const uint32_t oi0 = n_out ? oidx[b].x : 0;
     oq.init(oval, n_out, oi0);
     bool bad = false;
     const uint32_t pos_b = b * kBlockElems;
@@ -340,7 +347,7 @@ __global__ __launch_bounds__(256) void k_decode(
     }
     if (active && ld.consumed(start) != chunks[b]) bad = true;
     if (bad) atomicOr(&misc->flags, F_CORRUPT);
-    outlier_totals(t, active, oq, oi0, misc);
+    outlier_totals(t, active, oq, oi0, misc, reinterpret_cast<uint32_t*>(LUT));
 }
 
 // ------------------------------------------------ fast decode of full blocks
@@ -504,8 +511,7 @@ __global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint3
                                                      const uint16_t* __restrict__ chunks,
                                                      const uint16_t* __restrict__ lut_g,
                                                      const int32_t* __restrict__ oval,
-                                                     const uint32_t* __restrict__ ofirst,
-                                                     const uint32_t* __restrict__ oend, uint64_t n_out, double e2,
+                                                     const uint2* __restrict__ oidx, uint64_t n_out, double e2,
                                                      float* __restrict__ out, int32_t* __restrict__ res, Misc* misc) {
     __shared__ uint16_t LUT[kLut];
     __shared__ uint32_t SRING[kDecLanes * kRing];
@@ -520,7 +526,8 @@ __global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint3
     const uint32_t b = ibx + g.nb[0] * (iby + g.nb[1] * ibz);
     const uint64_t start = off[b];
     const uint32_t bits = chunks[b];
-    const uint32_t first = n_out ? ofirst[b] : 0, count = n_out ? oend[b] - first : 0;
+    const uint2 oe = n_out ? oidx[b] : make_uint2(0u, 0u);
+    const uint32_t first = oe.x, count = oe.y - oe.x;
     FastDec fd;
     fd.S = reinterpret_cast<const uint4*>(stream);
     fd.nch = (uint32_t)((nwords + 3) / 4);
@@ -635,7 +642,7 @@ __global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint3
     OutQ oq;
     oq.oi = fd.oi;
     oq.hash = fd.hash;
-    outlier_totals(t, active, oq, first, misc);
+    outlier_totals(t, active, oq, first, misc, reinterpret_cast<uint32_t*>(LUT));
 }
 
 // ---------------------------------------------- per-block predictor decode
@@ -660,7 +667,7 @@ __global__ __launch_bounds__(256) void k_decode_res(Geom g, const uint32_t* __re
                                                     const uint16_t* __restrict__ chunks,
                                                     const uint16_t* __restrict__ lut_g,
                                                     const uint32_t* __restrict__ opos, const int32_t* __restrict__ oval,
-                                                    const uint32_t* __restrict__ ofirst, uint64_t n_out,
+                                                    const uint2* __restrict__ oidx, uint64_t n_out,
                                                     int32_t* __restrict__ res, Misc* misc, int skip, uint32_t ib0,
                                                     uint32_t ib1, uint32_t ib2) {
     __shared__ uint16_t LUT[kLut];
@@ -680,7 +687,7 @@ __global__ __launch_bounds__(256) void k_decode_res(Geom g, const uint32_t* __re
     ld.ring = &RING[t];
     ld.init(active ? start : 0);
     OutQ oq;
-    const uint32_t oi0 = n_out ? ofirst[b] : 0;
+    const uint32_t oi0 = n_out ? oidx[b].x : 0;
     oq.init(oval, n_out, oi0);
     bool bad = false;
     const uint32_t pos_b = b * kBlockElems;
@@ -700,7 +707,7 @@ __global__ __launch_bounds__(256) void k_decode_res(Geom g, const uint32_t* __re
     }
     if (active && ld.consumed(start) != chunks[b]) bad = true;
     if (bad) atomicOr(&misc->flags, F_CORRUPT);
-    outlier_totals(t, active, oq, oi0, misc);
+    outlier_totals(t, active, oq, oi0, misc, reinterpret_cast<uint32_t*>(LUT));
 }
 
 // One wave (workgroup of 64) per block: residuals -> grid values in LDS by
@@ -810,9 +817,9 @@ __global__ __launch_bounds__(64) void k_inverse(Geom g, const int32_t* __restric
 }
 
 // ------------------------------------------------------ outlier block index
-// First list index of each block's outliers (ofirst) and one past its last
-// (oend), both left at zero for a block without outliers (cleared
-// beforehand); the list must be strictly increasing; the sum of pos_hash
+// Per block, the list index of its first outlier (oidx[b].x) and one past
+// its last (oidx[b].y), both left at zero for a block without outliers
+// (cleared beforehand); the list must be strictly increasing; the sum of pos_hash
 // over the list for the decode-side check.  Each thread takes groups of 4
 // consecutive entries (one 16-byte load when the list is aligned), its
 // neighbours at the group edges by two scalar loads that hit the cache
@@ -820,18 +827,18 @@ __global__ __launch_bounds__(64) void k_inverse(Geom g, const int32_t* __restric
 // adds them with one atomic each (few workgroups, so few same-address
 // atomics: these serialise at the memory side).
 __device__ __forceinline__ void outlier_entry(uint64_t i, uint32_t p, bool has_prev, uint32_t prev, bool has_next,
-                                              uint32_t next, uint32_t nblocks, uint32_t* __restrict__ ofirst,
-                                              uint32_t* __restrict__ oend, uint64_t& h, bool& bad) {
+                                              uint32_t next, uint32_t nblocks, uint2* __restrict__ oidx, uint64_t& h,
+                                              bool& bad) {
     const uint32_t b = p >> 9;
     bad |= (has_prev && prev >= p) || b >= nblocks;
     h += pos_hash(p);
-    if (b < nblocks && (!has_prev || (prev >> 9) != b)) ofirst[b] = (uint32_t)i;
-    if (b < nblocks && (!has_next || (next >> 9) != b)) oend[b] = (uint32_t)(i + 1);
+    if (b < nblocks && (!has_prev || (prev >> 9) != b)) oidx[b].x = (uint32_t)i;
+    if (b < nblocks && (!has_next || (next >> 9) != b)) oidx[b].y = (uint32_t)(i + 1);
 }
 
 __global__ __launch_bounds__(256) void k_outlier_index(const uint32_t* __restrict__ opos, uint64_t n_out,
-                                                       uint32_t nblocks, uint32_t* __restrict__ ofirst,
-                                                       uint32_t* __restrict__ oend, int vec, Misc* misc) {
+                                                       uint32_t nblocks, uint2* __restrict__ oidx, int vec,
+                                                       Misc* misc) {
     const uint32_t t = threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * 256;
     const uint64_t ngroups = (n_out + 3) / 4;
@@ -854,7 +861,7 @@ __global__ __launch_bounds__(256) void k_outlier_index(const uint32_t* __restric
             const uint64_t i = i0 + k;
             if (i < n_out)
                 outlier_entry(i, v[k], i > 0, k ? v[k - 1] : prev, i + 1 < n_out, k < 3 ? v[k + 1] : next, nblocks,
-                              ofirst, oend, h, bad);
+                              oidx, h, bad);
         }
     }
 #pragma unroll
@@ -946,22 +953,21 @@ Interior interior_of(const Geom& g) {
 }  // namespace
 
 // Outlier list index and list hash (before either decoder).
-void launch_outlier_index(hipStream_t st, const Geom& g, const uint32_t* opos, uint64_t n_out, uint32_t* ofirst,
-                          uint32_t* oend, Misc* misc) {
+void launch_outlier_index(hipStream_t st, const Geom& g, const uint32_t* opos, uint64_t n_out, uint2* oidx,
+                          Misc* misc) {
+    // ofirst and oend were cleared by the call's reset kernel
     if (!n_out) return;
-    launch_fill32(st, ofirst, g.nblocks, 0);
-    launch_fill32(st, oend, g.nblocks, 0);
     // about 16 groups of 4 entries per thread, at most 1024 workgroups
     uint64_t og = (n_out + 4 * 16 * 256 - 1) / (4 * 16 * 256);
     if (og > 1024) og = 1024;
     const int vec = ((uintptr_t)opos & 15) == 0;
-    hipLaunchKernelGGL(k_outlier_index, dim3((uint32_t)og), dim3(256), 0, st, opos, n_out, g.nblocks, ofirst, oend,
+    hipLaunchKernelGGL(k_outlier_index, dim3((uint32_t)og), dim3(256), 0, st, opos, n_out, g.nblocks, oidx,
                        vec, misc);
 }
 
 void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,
                    const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
-                   const int32_t* oval, uint32_t* ofirst, uint32_t* oend, uint64_t n_out, double e2, float* out,
+                   const int32_t* oval, const uint2* oidx, uint64_t n_out, double e2, float* out,
                    int vec, Misc* misc) {
     const Interior I = interior_of(g);
     const bool fast = I.n > 0;
@@ -969,7 +975,7 @@ void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64
         const uint32_t fg = (I.n + 255) / 256;
 #define FZ_FAST(NDV, V)                                                                                               \
     hipLaunchKernelGGL((k_decode_fast<NDV, false, V>), dim3(fg), dim3(256), 0, st, g, I.ib[0], I.ib[1], I.n, stream, \
-                       stream_words, off, chunks, lut, oval, ofirst, oend, n_out, e2, out, (int32_t*)nullptr, misc)
+                       stream_words, off, chunks, lut, oval, oidx, n_out, e2, out, (int32_t*)nullptr, misc)
         if (vec) {
             if (g.ndim == 3) FZ_FAST(3, true);
             else if (g.ndim == 2) FZ_FAST(2, true);
@@ -986,7 +992,7 @@ void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64
     const int skip = fast ? 1 : 0;
 #define FZ_GEN(NDV)                                                                                                 \
     hipLaunchKernelGGL(k_decode<NDV>, dim3(grid), dim3(256), 0, st, g, stream, stream_words, off, chunks, lut, opos, \
-                       oval, ofirst, n_out, e2, out, vec, misc, skip, I.ib[0], I.ib[1], I.ib[2])
+                       oval, oidx, n_out, e2, out, vec, misc, skip, I.ib[0], I.ib[1], I.ib[2])
     if (g.ndim == 3) FZ_GEN(3);
     else if (g.ndim == 2) FZ_GEN(2);
     else FZ_GEN(1);
@@ -999,7 +1005,7 @@ void launch_map_unpack(hipStream_t st, const uint8_t* map, uint32_t nblocks, uin
 
 void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,
                         const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
-                        const int32_t* oval, uint32_t* ofirst, uint32_t* oend, uint64_t n_out, int32_t* res,
+                        const int32_t* oval, const uint2* oidx, uint64_t n_out, int32_t* res,
                         int fixed_pred, const uint8_t* bpred, const uint64_t* reg_idx, const int32_t* coefs,
                         uint64_t nreg, double e2, float* out, int vec, Misc* misc) {
     const Interior I = interior_of(g);
@@ -1008,7 +1014,7 @@ void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, u
 #define FZ_FAST(NDV)                                                                                               \
     hipLaunchKernelGGL((k_decode_fast<NDV, true, false>), dim3(fg), dim3(256), 0, st, g, I.ib[0], I.ib[1], I.n,     \
                        stream,                                                                                      \
-                       stream_words, off, chunks, lut, oval, ofirst, oend, n_out, e2, (float*)nullptr, res, misc)
+                       stream_words, off, chunks, lut, oval, oidx, n_out, e2, (float*)nullptr, res, misc)
         if (g.ndim == 3) FZ_FAST(3);
         else if (g.ndim == 2) FZ_FAST(2);
         else FZ_FAST(1);
@@ -1019,7 +1025,7 @@ void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, u
 #define FZ_DRES(NDV)                                                                                                \
     if (I.n != g.nblocks)                                                                                           \
         hipLaunchKernelGGL(k_decode_res<NDV>, dim3(grid), dim3(256), 0, st, g, stream, stream_words, off, chunks,   \
-                           lut, opos, oval, ofirst, n_out, res, misc, skip, I.ib[0], I.ib[1], I.ib[2]);            \
+                           lut, opos, oval, oidx, n_out, res, misc, skip, I.ib[0], I.ib[1], I.ib[2]);            \
     hipLaunchKernelGGL(k_inverse<NDV>, dim3(g.nblocks), dim3(64), 0, st, g, res, fixed_pred, bpred, reg_idx, coefs, \
                        nreg, e2, out, vec, misc)
     if (g.ndim == 3) {

@@ -6,7 +6,8 @@
 //   k_encode   - chunked encoding (chunk = block) in one pass over the
 //                codes, stream offsets by a look-back over tile groups,
 //                words assembled in LDS;
-//   k_finalize - tile-boundary words, outlier/patch sections, header.
+//   k_finalize - tile-boundary words, outlier/patch sections, header, or
+//                the verbatim container.
 #include "fz_common.h"
 #include "fz_kernels.h"
 
@@ -319,6 +320,48 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ cod
     }
 }
 
+// -------------------------------------------------------------- verbatim
+// The verbatim container: header (flag bit 0) and the raw floats, written by
+// the whole finalize grid.
+__device__ void write_verbatim(const Geom& g, uint32_t mode, double eb, uint32_t pred, const Misc* misc,
+                               const float* __restrict__ x, uint8_t* __restrict__ out, int vec, uint64_t gid,
+                               uint64_t stride) {
+    if (gid == 0) {
+        double eb_abs;
+        resolve_eb(mode, eb, misc->mm_lo, misc->mm_hi, &eb_abs);
+        uint8_t h[kHdr];
+        for (int k = 0; k < kHdr; k++) h[k] = 0;
+        auto st32 = [&](int o, uint32_t v) { for (int k = 0; k < 4; k++) h[o + k] = (uint8_t)(v >> (8 * k)); };
+        auto st64 = [&](int o, uint64_t v) { for (int k = 0; k < 8; k++) h[o + k] = (uint8_t)(v >> (8 * k)); };
+        st32(0, kMagic);
+        h[4] = (uint8_t)kVersion;
+        h[5] = (uint8_t)(kVersion >> 8);
+        h[6] = 1;
+        st32(8, g.ndim);
+        st32(12, pred);
+        st64(16, g.n[0]);
+        st64(24, g.n[1]);
+        st64(32, g.n[2]);
+        st32(40, mode);
+        st32(44, kRadius);
+        st64(48, __double_as_longlong(eb));
+        st64(56, __double_as_longlong(eb_abs));
+        st64(64, (uint64_t)kHdr + 4 * g.N);
+        uint4* dst = reinterpret_cast<uint4*>(out);
+        const uint4* src = reinterpret_cast<const uint4*>(h);
+        for (int k = 0; k < kHdr / 16; k++) dst[k] = src[k];
+    }
+    float* o = reinterpret_cast<float*>(out + kHdr);
+    if (vec) {
+        const f32x4* x4 = reinterpret_cast<const f32x4*>(x);
+        f32x4* o4 = reinterpret_cast<f32x4*>(o);
+        for (uint64_t i = gid; i < g.N / 4; i += stride) o4[i] = x4[i];
+        for (uint64_t i = (g.N & ~3ull) + gid; i < g.N; i += stride) o[i] = x[i];
+    } else {
+        for (uint64_t i = gid; i < g.N; i += stride) o[i] = x[i];
+    }
+}
+
 // ------------------------------------------------------------- finalize
 // Layout from the device-side counts; boundary words shared by two tiles;
 // outlier and patch sections compacted from the per-tile staging slots in
@@ -331,11 +374,11 @@ __global__ __launch_bounds__(256) void k_finalize(Geom g, uint32_t mode, double 
                                                   const uint32_t* __restrict__ tlast,
                                                   const uint32_t* __restrict__ tile_cnt,
                                                   const uint64_t* __restrict__ tile_off,
-                                                  const uint32_t* __restrict__ opos, const int32_t* __restrict__ oval,
-                                                  const uint32_t* __restrict__ ppos,
-                                                  const uint32_t* __restrict__ pbits, const uint8_t* __restrict__ bpred,
+                                                  const uint2* __restrict__ ostage, const uint2* __restrict__ pstage,
+                                                  const uint8_t* __restrict__ bpred,
                                                   const uint64_t* __restrict__ reg_idx,
-                                                  const int32_t* __restrict__ coef) {
+                                                  const int32_t* __restrict__ coef, const float* __restrict__ x,
+                                                  int xvec) {
     const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint32_t flags = misc->flags;
@@ -350,7 +393,11 @@ __global__ __launch_bounds__(256) void k_finalize(Geom g, uint32_t mode, double 
         misc->verbatim = verbatim ? 1 : 0;
         misc->total_bytes = verbatim ? (uint64_t)kHdr + 4 * g.N : L.total;
     }
-    if (verbatim || (flags & (F_NONFINITE | F_EB | F_INTERNAL | F_TIMEOUT))) return;
+    if (flags & (F_NONFINITE | F_EB | F_INTERNAL | F_TIMEOUT)) return;
+    if (verbatim) {
+        write_verbatim(g, mode, eb, pred, misc, x, out, xvec, gid, stride);
+        return;
+    }
 
     // predictor map (2 bits per block) and regression coefficients
     if (has_map)
@@ -391,37 +438,34 @@ __global__ __launch_bounds__(256) void k_finalize(Geom g, uint32_t mode, double 
             // four entries per lane and pass, all loads issued before the
             // stores (the copy is latency-bound otherwise)
             for (uint32_t j0 = 0; j0 < co; j0 += 256) {
-                uint32_t a[4];
-                int32_t v[4];
+                uint2 a[4];
 #pragma unroll
                 for (int k = 0; k < 4; k++) {
                     const uint32_t j = j0 + lane + 64 * k;
-                    a[k] = j < co ? opos[slot + j] : 0u;
-                    v[k] = j < co ? oval[slot + j] : 0;
+                    a[k] = j < co ? ostage[slot + j] : make_uint2(0, 0);
                 }
 #pragma unroll
                 for (int k = 0; k < 4; k++) {
                     const uint32_t j = j0 + lane + 64 * k;
                     if (j < co) {
-                        o_pos[(off & m31) + j] = a[k];
-                        o_val[(off & m31) + j] = v[k];
+                        o_pos[(off & m31) + j] = a[k].x;
+                        o_val[(off & m31) + j] = (int32_t)a[k].y;
                     }
                 }
             }
             for (uint32_t j0 = 0; j0 < cp; j0 += 256) {
-                uint32_t a[4], v[4];
+                uint2 a[4];
 #pragma unroll
                 for (int k = 0; k < 4; k++) {
                     const uint32_t j = j0 + lane + 64 * k;
-                    a[k] = j < cp ? ppos[slot + j] : 0u;
-                    v[k] = j < cp ? pbits[slot + j] : 0u;
+                    a[k] = j < cp ? pstage[slot + j] : make_uint2(0, 0);
                 }
 #pragma unroll
                 for (int k = 0; k < 4; k++) {
                     const uint32_t j = j0 + lane + 64 * k;
                     if (j < cp) {
-                        p_pos[(off >> 31) + j] = a[k];
-                        p_bits[(off >> 31) + j] = v[k];
+                        p_pos[(off >> 31) + j] = a[k].x;
+                        p_bits[(off >> 31) + j] = a[k].y;
                     }
                 }
             }
@@ -467,57 +511,7 @@ __global__ __launch_bounds__(256) void k_finalize(Geom g, uint32_t mode, double 
     }
 }
 
-// -------------------------------------------------------------- verbatim
-// When k_finalize chose the verbatim container: header (flag bit 0) and the
-// raw floats.  Nothing happens otherwise, or after an error.
-__global__ __launch_bounds__(256) void k_verbatim(Geom g, uint32_t mode, double eb, uint32_t pred, const Misc* misc,
-                                                  const float* __restrict__ x, uint8_t* __restrict__ out, int vec) {
-    if (!misc->verbatim || (misc->flags & (F_NONFINITE | F_EB | F_INTERNAL | F_TIMEOUT))) return;
-    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    if (gid == 0) {
-        double eb_abs;
-        resolve_eb(mode, eb, misc->mm_lo, misc->mm_hi, &eb_abs);
-        uint8_t h[kHdr];
-        for (int k = 0; k < kHdr; k++) h[k] = 0;
-        auto st32 = [&](int o, uint32_t v) { for (int k = 0; k < 4; k++) h[o + k] = (uint8_t)(v >> (8 * k)); };
-        auto st64 = [&](int o, uint64_t v) { for (int k = 0; k < 8; k++) h[o + k] = (uint8_t)(v >> (8 * k)); };
-        st32(0, kMagic);
-        h[4] = (uint8_t)kVersion;
-        h[5] = (uint8_t)(kVersion >> 8);
-        h[6] = 1;
-        st32(8, g.ndim);
-        st32(12, pred);
-        st64(16, g.n[0]);
-        st64(24, g.n[1]);
-        st64(32, g.n[2]);
-        st32(40, mode);
-        st32(44, kRadius);
-        st64(48, __double_as_longlong(eb));
-        st64(56, __double_as_longlong(eb_abs));
-        st64(64, (uint64_t)kHdr + 4 * g.N);
-        uint4* dst = reinterpret_cast<uint4*>(out);
-        const uint4* src = reinterpret_cast<const uint4*>(h);
-        for (int k = 0; k < kHdr / 16; k++) dst[k] = src[k];
-    }
-    float* o = reinterpret_cast<float*>(out + kHdr);
-    if (vec) {
-        const f32x4* x4 = reinterpret_cast<const f32x4*>(x);
-        f32x4* o4 = reinterpret_cast<f32x4*>(o);
-        for (uint64_t i = gid; i < g.N / 4; i += stride) o4[i] = x4[i];
-        for (uint64_t i = (g.N & ~3ull) + gid; i < g.N; i += stride) o[i] = x[i];
-    } else {
-        for (uint64_t i = gid; i < g.N; i += stride) o[i] = x[i];
-    }
-}
-
 // ------------------------------------------------------------ launchers
-void launch_verbatim(hipStream_t st, const Geom& g, uint32_t mode, double eb, uint32_t pred, const Misc* misc,
-                     const float* x, uint8_t* out) {
-    const int vec = ((uintptr_t)x & 15) == 0;
-    hipLaunchKernelGGL(k_verbatim, dim3(1024), dim3(256), 0, st, g, mode, eb, pred, misc, x, out, vec);
-}
-
 void launch_codebook(hipStream_t st, uint32_t* hist, uint8_t* out_lens, uint32_t* cw, Misc* misc) {
     hipLaunchKernelGGL(k_codebook, dim3(1), dim3(1024), 0, st, hist, out_lens, cw, misc);
 }
@@ -542,15 +536,16 @@ uint32_t encode_groups(uint32_t ntiles) { return (ntiles + kEncTiles - 1) / kEnc
 
 void launch_finalize(hipStream_t st, const Geom& g, uint32_t mode, double eb, uint32_t pred, Misc* misc,
                      uint8_t* out, uint32_t ntiles, const uint64_t* tile_start, const uint32_t* tfirst,
-                     const uint32_t* tlast, const uint32_t* tile_cnt, const uint64_t* tile_off, const uint32_t* opos,
-                     const int32_t* oval, const uint32_t* ppos, const uint32_t* pbits, const uint8_t* bpred,
-                     const uint64_t* reg_idx, const int32_t* coef) {
+                     const uint32_t* tlast, const uint32_t* tile_cnt, const uint64_t* tile_off, const uint2* ostage,
+                     const uint2* pstage, const uint8_t* bpred, const uint64_t* reg_idx, const int32_t* coef,
+                     const float* x) {
     // about four tiles per wave for the outlier/patch compaction
     uint32_t grid = (ntiles + 15) / 16;
     if (grid < 1024) grid = 1024;
     if (grid > 8192) grid = 8192;
     hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(256), 0, st, g, mode, eb, pred, misc, out, ntiles, tile_start,
-                       tfirst, tlast, tile_cnt, tile_off, opos, oval, ppos, pbits, bpred, reg_idx, coef);
+                       tfirst, tlast, tile_cnt, tile_off, ostage, pstage, bpred, reg_idx, coef, x,
+                       (int)(((uintptr_t)x & 15) == 0));
 }
 
 }  // namespace fz

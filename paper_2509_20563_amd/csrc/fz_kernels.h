@@ -11,14 +11,14 @@ void launch_reset(hipStream_t st, Misc* misc, uint32_t* hist, uint64_t* d1, uint
 void launch_fill32(hipStream_t st, uint32_t* p, uint64_t n, uint32_t v);
 void launch_minmax(hipStream_t st, const float* x, uint64_t N, int vec, Misc* misc, int grid);
 void launch_quant(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
-                  Misc* misc, uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt, uint32_t* opos,
-                  int32_t* oval, uint32_t* ppos, uint32_t* pbits, int fixed_pred, const uint8_t* bpred,
+                  Misc* misc, uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt, uint2* ostage,
+                  uint2* pstage, int fixed_pred, const uint8_t* bpred,
                   int32_t* coef);
 void launch_trial(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
                   Misc* misc, uint32_t ntiles, const uint32_t* cw_ref, uint8_t* choice, uint32_t* costs);
 void launch_quant_select(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
                          Misc* misc, uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt,
-                         uint32_t* opos, int32_t* oval, uint32_t* ppos, uint32_t* pbits, const float* sel,
+                         uint2* ostage, uint2* pstage, const float* sel,
                          uint8_t* choice, int32_t* coef);
 void launch_features(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
                      Misc* misc, uint32_t ntiles, const float* sel, float* feat, float* yout, uint8_t* choice);
@@ -36,9 +36,9 @@ void launch_encode(hipStream_t st, int grid, const uint16_t* codes, const Geom& 
 uint32_t encode_groups(uint32_t ntiles);
 void launch_finalize(hipStream_t st, const Geom& g, uint32_t mode, double eb, uint32_t pred, Misc* misc,
                      uint8_t* out, uint32_t ntiles, const uint64_t* tile_start, const uint32_t* tfirst,
-                     const uint32_t* tlast, const uint32_t* tile_cnt, const uint64_t* tile_off, const uint32_t* opos,
-                     const int32_t* oval, const uint32_t* ppos, const uint32_t* pbits, const uint8_t* bpred,
-                     const uint64_t* reg_idx, const int32_t* coef);
+                     const uint32_t* tlast, const uint32_t* tile_cnt, const uint64_t* tile_off, const uint2* ostage,
+                     const uint2* pstage, const uint8_t* bpred, const uint64_t* reg_idx, const int32_t* coef,
+                     const float* x);
 
 // fz_train.hip: selector training (device scratch of one minibatch)
 struct TrainScratch {
@@ -51,8 +51,6 @@ void launch_train_batch(hipStream_t st, const float* w, const float* feat, const
 void launch_adam(hipStream_t st, float* w, float* m, float* v, const float* g, int t, float lr, float b1, float b2,
                  float eps);
 
-void launch_verbatim(hipStream_t st, const Geom& g, uint32_t mode, double eb, uint32_t pred, const Misc* misc,
-                     const float* x, uint8_t* out);
 
 // fz_batch.hip
 void launch_field_record(hipStream_t st, const Misc* misc, uint64_t slot, uint64_t* rec, int decode);
@@ -62,16 +60,16 @@ void launch_gather_headers(hipStream_t st, const uint8_t* in, const uint64_t* of
 // fz_decode.hip
 void launch_copy(hipStream_t st, const uint8_t* src, float* dst, uint64_t n);
 void launch_lut(hipStream_t st, const uint8_t* lens_packed, uint16_t* lut, Misc* misc);
-void launch_outlier_index(hipStream_t st, const Geom& g, const uint32_t* opos, uint64_t n_out, uint32_t* ofirst,
-                          uint32_t* oend, Misc* misc);
+void launch_outlier_index(hipStream_t st, const Geom& g, const uint32_t* opos, uint64_t n_out, uint2* oidx,
+                          Misc* misc);
 void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,
                    const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
-                   const int32_t* oval, uint32_t* ofirst, uint32_t* oend, uint64_t n_out, double e2, float* out,
+                   const int32_t* oval, const uint2* oidx, uint64_t n_out, double e2, float* out,
                    int vec, Misc* misc);
 void launch_map_unpack(hipStream_t st, const uint8_t* map, uint32_t nblocks, uint8_t* bpred, Misc* misc);
 void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,
                         const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
-                        const int32_t* oval, uint32_t* ofirst, uint32_t* oend, uint64_t n_out, int32_t* res,
+                        const int32_t* oval, const uint2* oidx, uint64_t n_out, int32_t* res,
                         int fixed_pred, const uint8_t* bpred, const uint64_t* reg_idx, const int32_t* coefs,
                         uint64_t nreg, double e2, float* out, int vec, Misc* misc);
 void launch_patch(hipStream_t st, const Geom& g, const uint32_t* ppos, const uint32_t* pbits, uint64_t n_pat,

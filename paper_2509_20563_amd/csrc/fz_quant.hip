@@ -102,14 +102,18 @@ __global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, uin
 // ------------------------------------------------ prequantisation helper
 // q = rint(x / 2eb) via x * (1 / 2eb) in double, round half to even.
 // Patch when |t| >= 2^24 (q = 0) or when float(q * 2eb) misses the bound.
+// Out of range, r and xh are meaningless but discarded: the value is a
+// patch with q = 0 either way (the conversion of such r is the hardware's
+// clamping one).
 __device__ __forceinline__ int32_t prequant1(float xv, double e2, double inv, double eb_abs, bool& patch) {
     const double xd = (double)xv;
     const double t = xd * inv;
     const bool big = fabs(t) >= 16777216.0;
-    const double r = __builtin_rint(big ? 0.0 : t);  // branch-free: q = 0 when out of range
+    const double r = __builtin_rint(t);
     const float xh = (float)(r * e2);
     patch = big || (fabs(xd - (double)xh) > eb_abs);
-    return (int32_t)r;
+    const int32_t q = (int32_t)r;
+    return big ? 0 : q;
 }
 
 // Load-phase thread mapping: which (block-in-tile, segment) a thread loads,
@@ -181,9 +185,8 @@ template <int ND, int MODE>
 __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom g, uint32_t mode, double eb,
                                                int vec, Misc* misc, uint32_t* __restrict__ hist_g,
                                                uint16_t* __restrict__ codes, uint32_t ntiles,
-                                               uint32_t* __restrict__ tile_cnt, uint32_t* __restrict__ opos,
-                                               int32_t* __restrict__ oval, uint32_t* __restrict__ ppos,
-                                               uint32_t* __restrict__ pbits, int fixed_pred,
+                                               uint32_t* __restrict__ tile_cnt, uint2* __restrict__ ostage,
+                                               uint2* __restrict__ pstage, int fixed_pred,
                                                const uint8_t* __restrict__ bpred, int32_t* __restrict__ coef,
                                                const uint32_t* __restrict__ cw_ref, uint8_t* __restrict__ choice,
                                                uint32_t* __restrict__ costs, const float* __restrict__ sel,
@@ -213,6 +216,9 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
     }
     const double e2 = 2.0 * eb_abs;
     const double inv = 1.0 / e2;
+    // under the value-range bound the min/max pass has already flagged
+    // non-finite input; the absolute bound has no such pass
+    const bool check_finite = mode != 1;
     for (uint32_t i = t; i < (uint32_t)kBins; i += 256) H[i] = 0;
     if (MODE == kQuantTrial) {
         // reference code lengths; an unused code counts as kLmax + 1 bits
@@ -292,7 +298,7 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
                 bool p;
                 const int32_t qi = prequant1(v[i], e2, inv, eb_abs, p);
                 const bool valid = i < (int)nv;
-                bad |= valid && !__builtin_isfinite(v[i]);
+                bad |= check_finite && valid && !__builtin_isfinite(v[i]);
                 q[i] = valid ? qi : 0;
                 pm |= (valid && p ? 1u : 0u) << i;
             }
@@ -632,17 +638,20 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
             pk.w = code[6] | (code[7] << 16);
             *reinterpret_cast<uint4*>(&codes[(uint64_t)b * kBlockElems + s * 8]) = pk;
         }
-        // histogram: lane 0's code is added once for every lane sharing it,
-        // the other lanes add their own
+        // histogram: one candidate code per wave (lane 0's first): its
+        // matches are counted by ballots and added once; every other valid
+        // code is added by its lane
         if (blk) {
+            const uint32_t cand = (uint32_t)__builtin_amdgcn_readfirstlane((int)code[0]);
+            uint32_t nmatch = 0;
 #pragma unroll
             for (int i = 0; i < 8; i++) {
-                const uint32_t c = (i < (int)nv) ? code[i] : 0xFFFFu;
-                const uint32_t cand = (uint32_t)__builtin_amdgcn_readfirstlane((int)c);
-                const uint64_t m = __ballot(c == cand);
-                if (lane == 0 && cand != 0xFFFFu) atomicAdd(&H[cand], (uint32_t)__popcll(m));
-                if (c != cand && c != 0xFFFFu) atomicAdd(&H[c], 1u);
+                const bool valid = i < (int)nv;
+                const bool match = valid && code[i] == cand;
+                nmatch += (uint32_t)__popcll(__ballot(match));
+                if (valid && !match) atomicAdd(&H[code[i]], 1u);
             }
+            if (lane == 0 && nmatch) atomicAdd(&H[cand], nmatch);
         }
 
         // ---------------- outliers and patches (block order inside the tile)
@@ -677,24 +686,16 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
             const uint32_t omask = code[0];
             const uint32_t excl_local = wpre + incl - packed;
             const uint64_t slot = (uint64_t)tile * kTileBlocks * kBlockElems;
-            uint64_t oi = slot + (excl_local & 0xFFFFu);
-            uint64_t pi = slot + (excl_local >> 16);
+            uint2* op = ostage + slot + (excl_local & 0xFFFFu);
+            uint2* pp = pstage + slot + (excl_local >> 16);
             const uint32_t pos0 = b * kBlockElems + s * 8;
             const BlockInfo ib = block_info(g, b);
             const uint32_t base = ib.bx * g.bs[0] + g.n[0] * (ib.by * g.bs[1] + g.n[1] * (ib.bz * g.bs[2])) +
                                   lb_rowoff;
 #pragma unroll
             for (int i = 0; i < 8; i++) {
-                if (omask & (1u << i)) {
-                    opos[oi] = pos0 + i;
-                    oval[oi] = d[i];
-                    oi++;
-                }
-                if (pm_lane & (1u << i)) {
-                    ppos[pi] = pos0 + i;
-                    pbits[pi] = __float_as_uint(x[base + i]);
-                    pi++;
-                }
+                if (omask & (1u << i)) *op++ = make_uint2(pos0 + i, (uint32_t)d[i]);
+                if (pm_lane & (1u << i)) *pp++ = make_uint2(pos0 + i, __float_as_uint(x[base + i]));
             }
         }
         __syncthreads();
@@ -723,13 +724,12 @@ void launch_minmax(hipStream_t st, const float* x, uint64_t N, int vec, Misc* mi
 
 #define FZ_QUANT(NDV, MV)                                                                                        \
     hipLaunchKernelGGL((k_quant<NDV, MV>), dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, hist, codes, \
-                       ntiles, tile_cnt, opos, oval, ppos, pbits, fixed_pred, bpred, coef, cw_ref, choice, costs, \
-                       sel, feat, yout)
+                       ntiles, tile_cnt, ostage, pstage, fixed_pred, bpred, coef, cw_ref, choice, costs, sel, feat, \
+                       yout)
 
 void launch_quant(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
-                  Misc* misc, uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt, uint32_t* opos,
-                  int32_t* oval, uint32_t* ppos, uint32_t* pbits, int fixed_pred, const uint8_t* bpred,
-                  int32_t* coef) {
+                  Misc* misc, uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt, uint2* ostage,
+                  uint2* pstage, int fixed_pred, const uint8_t* bpred, int32_t* coef) {
     const uint32_t* cw_ref = nullptr;
     uint8_t* choice = nullptr;
     uint32_t* costs = nullptr;
@@ -749,8 +749,9 @@ void launch_trial(hipStream_t st, int grid, const float* x, const Geom& g, uint3
                   Misc* misc, uint32_t ntiles, const uint32_t* cw_ref, uint8_t* choice, uint32_t* costs) {
     uint32_t* hist = nullptr;
     uint16_t* codes = nullptr;
-    uint32_t *tile_cnt = nullptr, *opos = nullptr, *ppos = nullptr, *pbits = nullptr;
-    int32_t *oval = nullptr, *coef = nullptr;
+    uint32_t* tile_cnt = nullptr;
+    uint2 *ostage = nullptr, *pstage = nullptr;
+    int32_t* coef = nullptr;
     const uint8_t* bpred = nullptr;
     const int fixed_pred = -1;
     const float* sel = nullptr;
@@ -762,8 +763,7 @@ void launch_trial(hipStream_t st, int grid, const float* x, const Geom& g, uint3
 
 void launch_quant_select(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
                          Misc* misc, uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt,
-                         uint32_t* opos, int32_t* oval, uint32_t* ppos, uint32_t* pbits, const float* sel,
-                         uint8_t* choice, int32_t* coef) {
+                         uint2* ostage, uint2* pstage, const float* sel, uint8_t* choice, int32_t* coef) {
     const uint32_t* cw_ref = nullptr;
     const uint8_t* bpred = nullptr;
     uint32_t* costs = nullptr;
@@ -778,8 +778,9 @@ void launch_features(hipStream_t st, int grid, const float* x, const Geom& g, ui
                      Misc* misc, uint32_t ntiles, const float* sel, float* feat, float* yout, uint8_t* choice) {
     uint32_t* hist = nullptr;
     uint16_t* codes = nullptr;
-    uint32_t *tile_cnt = nullptr, *opos = nullptr, *ppos = nullptr, *pbits = nullptr, *costs = nullptr;
-    int32_t *oval = nullptr, *coef = nullptr;
+    uint32_t *tile_cnt = nullptr, *costs = nullptr;
+    uint2 *ostage = nullptr, *pstage = nullptr;
+    int32_t* coef = nullptr;
     const uint8_t* bpred = nullptr;
     const uint32_t* cw_ref = nullptr;
     const int fixed_pred = -1;
