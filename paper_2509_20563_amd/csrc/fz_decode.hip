@@ -463,7 +463,7 @@ struct FastDec {
     // or a corrupt container) is fetched after the row by the whole wave,
     // so no global load sits inside the codeword loop.
     __device__ __forceinline__ void row8(const uint16_t* LUT, uint32_t pos0, int32_t d[8]) {
-        uint32_t mmask = 0, m0 = 0;
+        // the codeword chain first, without branches
 #pragma unroll
         for (int i = 0; i < 8; i++) {
             if ((i & 1) == 0) refill();
@@ -471,9 +471,16 @@ struct FastDec {
             const uint32_t len = e >> 10;
             buf <<= len;
             nb -= len;
-            const uint32_t sym = e & 1023u;
-            d[i] = (int32_t)sym - kRadius;
-            if (sym == 0) {
+            d[i] = (int32_t)(e & 1023u) - kRadius;
+        }
+        // code 0 (an outlier) is the only one that decodes to -radius: a
+        // wave whose row holds none skips the outlier handling
+        const int32_t mn = min(min(min(d[0], d[1]), min(d[2], d[3])), min(min(d[4], d[5]), min(d[6], d[7])));
+        if (!__ballot(mn == -kRadius)) return;
+        uint32_t mmask = 0, m0 = 0;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            if (d[i] == -kRadius) {
                 hash += pos_hash(pos0 + i);
                 if (oi < oL) {
                     d[i] = (int32_t)orr[(oi & (kORing - 1)) * kDecLanes];

@@ -170,24 +170,31 @@ __device__ __forceinline__ void or_shl128(uint64_t& hi, uint64_t& lo, uint64_t v
 
 constexpr int kEncWords = kTileBlocks * kBlockElems * kLmax / 32 + 8;
 
-// The (codeword | length << 16) entries of a lane's 8 codes (0 past the
-// block's real values) and their bit count.
+// A lane's 8 codes of block b, segment s (from the start of the codes when
+// the block or segment holds no values, so the load is unconditional and
+// can be issued a tile ahead), and the number of real values among them.
 template <int ND>
-__device__ __forceinline__ uint32_t load_entries(const uint16_t* __restrict__ codes, const Geom& g, uint32_t b,
-                                                 uint32_t s, const uint32_t* CW, uint32_t e8[8]) {
-    uint32_t nv = 0;
-    uint4 pk = make_uint4(0, 0, 0, 0);
+__device__ __forceinline__ uint4 load_codes(const uint16_t* __restrict__ codes, const Geom& g, uint32_t b,
+                                            uint32_t s, uint32_t& nv) {
+    nv = 0;
     if (b < g.nblocks) {
         BlockInfo info = block_info(g, b);
         seg_index<ND>(g, info, s, nv);
-        if (nv) pk = *reinterpret_cast<const uint4*>(&codes[(uint64_t)b * kBlockElems + s * 8]);
     }
+    const uint64_t at = nv ? (uint64_t)b * kBlockElems + s * 8 : 0;
+    return *reinterpret_cast<const uint4*>(&codes[at]);
+}
+
+// The (codeword | length << 16) entries of the 8 codes (0 past the real
+// values) and their bit count.
+__device__ __forceinline__ uint32_t code_entries(const uint4& pk, uint32_t nv, const uint32_t* CW, uint32_t e8[8]) {
     const uint32_t c8[8] = {pk.x & 0xFFFFu, pk.x >> 16, pk.y & 0xFFFFu, pk.y >> 16,
                             pk.z & 0xFFFFu, pk.z >> 16, pk.w & 0xFFFFu, pk.w >> 16};
     uint32_t nb = 0;
 #pragma unroll
     for (int i = 0; i < 8; i++) {
-        e8[i] = i < (int)nv ? CW[c8[i] & (kBins - 1)] : 0u;
+        const uint32_t e = CW[c8[i] & (kBins - 1)];
+        e8[i] = i < (int)nv ? e : 0u;
         nb += e8[i] >> 16;
     }
     return nb;
@@ -222,25 +229,37 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ cod
     __syncthreads();
     const uint32_t grp = blockIdx.x;
     const uint32_t tile0 = grp * kEncTiles;
-    // pass over the group's codes: codeword entries, chunk table, tile totals
+    // pass over the group's codes: codeword entries, chunk table, tile
+    // totals; each tile's codes are loaded while the previous one is
+    // processed
     uint32_t e8[kEncTiles][8];
+    uint32_t nv_next;
+    uint4 pk_next = load_codes<ND>(codes, g, tile0 < ntiles ? tile0 * kTileBlocks + wave : g.nblocks, lane, nv_next);
 #pragma unroll
     for (uint32_t k = 0; k < kEncTiles; k++) {
         const uint32_t b = (tile0 + k) * kTileBlocks + wave;
+        const uint4 pk = pk_next;
+        const uint32_t nv = nv_next;
+        if (k + 1 < kEncTiles)
+            pk_next = load_codes<ND>(codes, g, tile0 + k + 1 < ntiles ? b + kTileBlocks : g.nblocks, lane, nv_next);
         uint32_t nb = 0;
         if (tile0 + k < ntiles) {
-            nb = load_entries<ND>(codes, g, b, lane, CW, e8[k]);
+            nb = code_entries(pk, nv, CW, e8[k]);
         } else {
 #pragma unroll
             for (int i = 0; i < 8; i++) e8[k][i] = 0;
         }
         const uint32_t incl = wave_incl_scan(nb);
-        if (lane == 63) {
-            wsum[k][wave] = incl;
-            if (tile0 + k < ntiles && b < g.nblocks) chunks[b] = (uint16_t)incl;
-        }
+        if (lane == 63) wsum[k][wave] = incl;
     }
     __syncthreads();
+    // chunk table (block bit counts) from the tile totals: no store among
+    // the phase's loads, whose waits would otherwise also cover it
+    if (t < kEncTiles * 4) {
+        const uint32_t k = t >> 2, w = t & 3;
+        const uint32_t b = (tile0 + k) * kTileBlocks + w;
+        if (tile0 + k < ntiles && b < g.nblocks) chunks[b] = (uint16_t)wsum[k][w];
+    }
     uint64_t gsum = 0;
     for (uint32_t k = 0; k < kEncTiles; k++) gsum += wsum[k][0] + wsum[k][1] + wsum[k][2] + wsum[k][3];
     if (wave == 0) {
