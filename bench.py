@@ -329,13 +329,30 @@ def bench_selector(args):
                      "cr": round(metrics.compression_ratio(n, sizes[-1]), 4),
                      "max_err_over_eb": err / h["eb_abs"], "ms": round(dt * 1e3, 3)}
         del y
+    # the selection stage alone (the same min/max pass first in both): the
+    # selector's features + network pass against the trial's reference
+    # first-order pass, codebook and three-predictor cost pass
+    print("[bench] selection stage alone", file=sys.stderr, flush=True)
+    t_sel = _timed(lambda: ctx.block_select(x, eb, fz.EB_REL), args.steps, args.warmup)
+    t_tri = _timed(lambda: ctx.block_trial(x, eb, fz.EB_REL), args.steps, args.warmup)
+    # breakdown: the same pass with the features written out and no network
+    t_feat = _timed(lambda: ctx.block_features(x, eb, fz.EB_REL), args.steps, args.warmup)
+    ch_sel, _ = ctx.block_select(x, eb, fz.EB_REL)
+    ch_tri, _ = ctx.block_trial(x, eb, fz.EB_REL)
+    selection = {"selector_ms": round(t_sel * 1e3, 3), "trial_ms": round(t_tri * 1e3, 3),
+                 "features_only_ms": round(t_feat * 1e3, 3),
+                 "speed_selector_over_trial": round(t_tri / t_sel, 3),
+                 "agreement_with_trial": round(float((ch_sel == ch_tri).float().mean().item()), 4),
+                 "selector_choice_counts": [int((ch_sel == k).sum().item()) for k in range(3)],
+                 "trial_choice_counts": [int((ch_tri == k).sum().item()) for k in range(3)]}
     sel, tri, p0 = res["selector"], res["trial"], res["lorenzo1"]
     _line("learned per-block predictor selector: compress GB/s; CR vs exhaustive trial", sel["compress_gbps"],
           "GB/s", args, sel["ms"],
           {"workload": f"{'x'.join(map(str, shape))} k^-11/3 field + 64 tanh fronts + 1% log-normal spikes, "
                        "rel eb 1e-4, 8^3 blocks choose first/second-order Lorenzo or regression", "n_values": n},
           modes=res, cr_selector_over_trial=round(sel["cr"] / tri["cr"], 4),
-          speed_selector_over_trial=round(sel["compress_gbps"] / tri["compress_gbps"], 3),
+          speed_selector_over_trial_end_to_end=round(sel["compress_gbps"] / tri["compress_gbps"], 3),
+          selection_stage=selection,
           cr_gain_over_lorenzo1=round(sel["cr"] / p0["cr"], 4),
           training={"seconds": round(tsec, 2), "samples": ns, "loss_first_epoch": l0, "loss_last_epoch": l1,
                     "fields": "4 fronts/spikes fields 128^3, seeds 101-104 (evaluation seed 3), rel 1e-2/1e-3/1e-4"})

@@ -201,18 +201,21 @@ int fz_batch_tuning(fz_ctx *ctx, uint32_t n, const fz_params *p, uint32_t *h_cha
 /* Blocks of a field with these dims (0 if invalid). */
 uint64_t fz_block_count(const fz_params *p);
 
-/* The 16 features (version 1) of every block of d_in, computed from the
- * prequantised values at p's error bound, to d_feat (device, row-major
- * [nblocks][16] float32, feat_cap >= 16 nblocks floats):
+/* The 16 features (version 2) of every block of d_in, computed from the
+ * prequantised values at p's error bound over the block's sample, its first
+ * 128 positions in block-local row-major order (the lower box: z < 2 of an
+ * 8x8x8 block, y < 4 of a 32x16 block, x < 128 of a 512 block; an edge
+ * block's sample is that box cut to the block), to d_feat (device,
+ * row-major [nblocks][16] float32, feat_cap >= 16 nblocks floats):
  *  0 plog2(1 + variance), 1 plog2(1 + max - min),
  *  2-4 plog2(1 + mean |first difference|) along x, y, z,
  *  5-7 the same for second differences, 8-10 for mixed differences in xy,
- *  yz, xz, 11 plog2(1 + mean |first-order residual|), 12 plog2(1 + max
- *  |first-order residual|), 13 outlier fraction of the first-order
- *  residuals, 14 plog2(1 + mean |second-order residual|), 15 plog2(1 +
- *  mean |regression residual|); plog2(1 + v) is the piecewise-linear
- *  base-2 logarithm read from the bits of the float 1 + v.  Bit-identical
- *  on any IEEE machine.  Synchronises `stream`. */
+ *  yz, xz (pairs inside the sample), 11 plog2(1 + mean |first-order
+ *  residual|), 12 plog2(1 + max |first-order residual|), 13 outlier
+ *  fraction of the first-order residuals, 14 plog2(1 + max |q|),
+ *  15 plog2(1 + |mean q|); plog2(1 + v) is the piecewise-linear base-2
+ *  logarithm read from the bits of the float 1 + v.  Bit-identical on any
+ *  IEEE machine.  Synchronises `stream`. */
 int fz_block_features(fz_ctx *ctx, const fz_params *p, const float *d_in, float *d_feat, uint64_t feat_cap,
                       void *stream);
 
@@ -239,7 +242,7 @@ int fz_block_trial(fz_ctx *ctx, const fz_params *p, const float *d_in, uint8_t *
 int fz_selector_set(fz_ctx *ctx, const float *h_params, uint64_t n);
 int fz_selector_get(fz_ctx *ctx, float *h_params, uint64_t n);
 
-/* Selector files: 8 bytes "FZSEL\0\0\0", u32 feature-set version (1),
+/* Selector files: 8 bytes "FZSEL\0\0\0", u32 feature-set version (2),
  * u32 parameter count, then the parameters (little-endian float32).
  * load returns FZ_ERR_CORRUPT for a file of another format or version. */
 int fz_selector_save(fz_ctx *ctx, const char *path);
@@ -260,8 +263,8 @@ typedef struct {
  * fz_block_features and d_costs [n][3] uint32 bits per predictor from
  * fz_block_trial, both device.  Targets are log2(1 + bits).  mu and rs
  * are set to the features' mean and inverse standard deviation (rs = 1
- * for a constant feature); weights start He-normal from the seed (biases
- * 0); each epoch visits the samples in a seeded shuffled order in
+ * for a constant feature); each layer's weights and biases start uniform
+ * in (-1/sqrt(fan-in), 1/sqrt(fan-in)) from the seed; each epoch visits the samples in a seeded shuffled order in
  * minibatches, one Adam step per minibatch on the mean squared error.
  * h_loss (host, nullable, epochs floats) receives each epoch's mean
  * minibatch loss.  On success the trained network becomes the context's

@@ -1006,10 +1006,17 @@ uint64_t orc_encode_symbols(const uint16_t *syms, uint64_t n, const uint8_t *len
 }
 
 /* ------------------------------------------------ block features
- * Sixteen statistics of each block's prequantised values q (its real
- * points only), the input of the learned predictor selector.  The paper
- * leaves automatic predictor choice to future work (Sec. 5); this feature
- * set (version 1) is this project's reading.  Every feature is built from
+ * Sixteen statistics of a sample of each block's prequantised values q,
+ * the input of the learned predictor selector.  The paper leaves automatic
+ * predictor choice to future work (Sec. 5); this feature set (version 2)
+ * is this project's reading.  The sample is the block's first
+ * ORC_FSAMPLE = 128 positions in its row-major order (the two lowest
+ * z-planes of a 3D block, the four lowest rows of a 2D block, the first
+ * 128 values of a 1D block), real points only: a lower box of the block,
+ * so every neighbour a statistic below uses is in the sample or outside
+ * the block.  Only quantities cheaper than the predictors themselves (no
+ * second-order stencil, no regression fit), so that choosing costs less
+ * than trying.  Every feature is built from
  * exact integer sums with the same IEEE operations on any machine: one
  * double division, rounding to float, then plog2(1 + v), the
  * piecewise-linear base-2 logarithm read from the float's bits (integer
@@ -1022,12 +1029,13 @@ uint64_t orc_encode_symbols(const uint16_t *syms, uint64_t n, const uint8_t *len
  *   11     plog2(1 + mean |first-order Lorenzo residual|)
  *   12     plog2(1 + max |first-order Lorenzo residual|)
  *   13     fraction of first-order residuals outside the code range
- *   14     plog2(1 + mean |second-order Lorenzo residual|)
- *   15     plog2(1 + mean |regression residual|)
- * Differences use point pairs (triples) inside the block; a mean over no
+ *   14     plog2(1 + max |q|)
+ *   15     plog2(1 + |mean of q|)
+ * Differences use point pairs (triples) inside the sample; a mean over no
  * pairs is 0.  Lorenzo residuals take neighbours outside the block as 0,
  * exactly as the predictors do.                                          */
 #define ORC_NFEAT 16
+#define ORC_FSAMPLE 128
 
 static float plog2_1p(double v) {
     float f = (float)v;
@@ -1043,14 +1051,22 @@ static void block_features(const geom_t *g, const int32_t *q, uint64_t b, float 
     uint64_t bc[3];
     int ext[3];
     block_coords(g, b, bc, ext);
+    /* the sample: the lower box holding the first ORC_FSAMPLE row-major
+     * positions of the block */
+    {
+        int a = g->ndim - 1;
+        int span = 1;
+        for (int k = 0; k < a; k++) span *= (int)g->bs[k];
+        int lim = ORC_FSAMPLE / span;
+        if (ext[a] > lim) ext[a] = lim;
+    }
     uint64_t o[3] = {bc[0] * g->bs[0], bc[1] * g->bs[1], bc[2] * g->bs[2]};
     int64_t n = (int64_t)ext[0] * ext[1] * ext[2];
     int64_t s1 = 0, s2 = 0, lo = INT64_MAX, hi = INT64_MIN;
     int64_t d1[3] = {0, 0, 0}, c1[3] = {0, 0, 0}, d2[3] = {0, 0, 0}, c2[3] = {0, 0, 0};
     int64_t dm[3] = {0, 0, 0}, cm[3] = {0, 0, 0};
-    int64_t r0 = 0, r0max = 0, nout = 0, r1 = 0, r2 = 0;
-    int32_t coef[4];
-    regression_coeffs(g, q, b, coef);
+    int64_t r0 = 0, r0max = 0, nout = 0;
+    const int32_t coef[4] = {0, 0, 0, 0};  /* the first-order residual uses none */
 #define Q(lx, ly, lz) ((int64_t)q[rm(g, o[0] + (lx), o[1] + (ly), o[2] + (lz))])
     for (int lz = 0; lz < ext[2]; lz++)
         for (int ly = 0; ly < ext[1]; ly++)
@@ -1094,8 +1110,6 @@ static void block_features(const geom_t *g, const int32_t *q, uint64_t b, float 
                 r0 += ad0;
                 if (ad0 > r0max) r0max = ad0;
                 if (d0 <= -ORC_RADIUS || d0 >= ORC_RADIUS) nout++;
-                r1 += llabs((int64_t)residual_at(g, q, x, y, z, ORC_P1, coef));
-                r2 += llabs((int64_t)residual_at(g, q, x, y, z, ORC_P2, coef));
             }
 #undef Q
     double m = (double)s1 / (double)n;
@@ -1111,8 +1125,8 @@ static void block_features(const geom_t *g, const int32_t *q, uint64_t b, float 
     f[11] = plog2_1p(mean_of(r0, n));
     f[12] = plog2_1p((double)r0max);
     f[13] = (float)((double)nout / (double)n);
-    f[14] = plog2_1p(mean_of(r1, n));
-    f[15] = plog2_1p(mean_of(r2, n));
+    f[14] = plog2_1p((double)(llabs(lo) > llabs(hi) ? llabs(lo) : llabs(hi)));
+    f[15] = plog2_1p(fabs(m));
 }
 
 /* Features of every block (block order), f[16 * nblocks]. */

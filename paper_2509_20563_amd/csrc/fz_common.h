@@ -26,8 +26,12 @@ constexpr int kTileBlocks = 4;    // blocks per workgroup tile (256 threads)
 constexpr uint32_t kMagic = 0x314D5A46u;  // "FZM1"
 // block-feature selector network: 16 features, two hidden layers of 64,
 // one output per predictor
+// (version 2: the features are taken over a sample, the block's first 128
+// positions in row-major order = segments 0..15, the lower box of the block)
 constexpr int kNFeat = 16;
-constexpr uint32_t kFeatureVersion = 1;
+constexpr uint32_t kFeatureVersion = 2;
+constexpr int kFeatSample = 128;
+constexpr int kFeatSegs = kFeatSample / 8;
 constexpr int kNHid = 64;
 constexpr int kNOut = 3;
 constexpr int kSelectorParams = 2 * kNFeat + kNHid * kNFeat + kNHid + kNHid * kNHid + kNHid + kNOut * kNHid + kNOut;
@@ -212,6 +216,24 @@ __host__ __device__ inline bool resolve_eb(uint32_t mode, double eb, uint32_t mm
     *eb_abs = e;
     return e >= 1e-300 && e <= 1e300;
 }
+
+// ------------------------------------------------ prequantisation helper
+// q = rint(x / 2eb) via x * (1 / 2eb) in double, round half to even.
+// Patch when |t| >= 2^24 (q = 0) or when float(q * 2eb) misses the bound.
+// Out of range, r and xh are meaningless but discarded: the value is a
+// patch with q = 0 either way (the conversion of such r is the hardware's
+// clamping one).
+__device__ __forceinline__ int32_t prequant1(float xv, double e2, double inv, double eb_abs, bool& patch) {
+    const double xd = (double)xv;
+    const double t = xd * inv;
+    const bool big = fabs(t) >= 16777216.0;
+    const double r = __builtin_rint(t);
+    const float xh = (float)(r * e2);
+    patch = big || (fabs(xd - (double)xh) > eb_abs);
+    const int32_t q = (int32_t)r;
+    return big ? 0 : q;
+}
+
 
 // Decoupled look-back (single-pass prefix scan over tiles taken in order
 // from an atomic counter).  desc[t] holds status (2 high bits: 1 = tile

@@ -16,12 +16,14 @@ void launch_quant(hipStream_t st, int grid, const float* x, const Geom& g, uint3
                   int32_t* coef);
 void launch_trial(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
                   Misc* misc, uint32_t ntiles, const uint32_t* cw_ref, uint8_t* choice, uint32_t* costs);
-void launch_quant_select(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
-                         Misc* misc, uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt,
-                         uint2* ostage, uint2* pstage, const float* sel,
-                         uint8_t* choice, int32_t* coef);
+
+// fz_select.hip: the learned selector (features over each block's sample,
+// then the network; feat [nblocks][16] float, choice one byte per block)
+uint32_t feature_tiles(uint32_t nblocks);
 void launch_features(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
-                     Misc* misc, uint32_t ntiles, const float* sel, float* feat, float* yout, uint8_t* choice);
+                     Misc* misc, float* feat);
+void launch_mlp(hipStream_t st, int grid, const float* feat, uint32_t n, const float* sel, float* yout,
+                uint8_t* choice);
 
 // fz_scan.hip
 void launch_scan(hipStream_t st, int kind, const void* in, uint32_t n, uint64_t* out, uint64_t* desc, uint32_t* ctr,

@@ -99,23 +99,6 @@ __global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, uin
     }
 }
 
-// ------------------------------------------------ prequantisation helper
-// q = rint(x / 2eb) via x * (1 / 2eb) in double, round half to even.
-// Patch when |t| >= 2^24 (q = 0) or when float(q * 2eb) misses the bound.
-// Out of range, r and xh are meaningless but discarded: the value is a
-// patch with q = 0 either way (the conversion of such r is the hardware's
-// clamping one).
-__device__ __forceinline__ int32_t prequant1(float xv, double e2, double inv, double eb_abs, bool& patch) {
-    const double xd = (double)xv;
-    const double t = xd * inv;
-    const bool big = fabs(t) >= 16777216.0;
-    const double r = __builtin_rint(t);
-    const float xh = (float)(r * e2);
-    patch = big || (fabs(xd - (double)xh) > eb_abs);
-    const int32_t q = (int32_t)r;
-    return big ? 0 : q;
-}
-
 // Load-phase thread mapping: which (block-in-tile, segment) a thread loads,
 // chosen so that consecutive lanes read consecutive addresses.
 template <int ND>
@@ -146,40 +129,8 @@ __device__ __forceinline__ void read_row(const int32_t* Q, uint32_t off, int32_t
 // MODE: kQuantP0 (first-order Lorenzo everywhere), kQuantPred (predictor
 // per block: fixed_pred >= 0 for every block, else bpred[b]), kQuantTrial
 // (no codes: per-block cost of each predictor under a reference code,
-// cheapest predictor -> choice[b], the three costs -> costs[3 b + p]),
-// kQuantFeat (no codes: the 16 block features -> feat[16 b + i] and, with
-// selector parameters, the network's predictions -> y[3 b + k] and its
-// choice -> choice[b]), kQuantSel (the selector's choice made in the same
-// pass, then codes with the chosen predictor as in kQuantPred).
-constexpr int kQuantP0 = 0, kQuantPred = 1, kQuantTrial = 2, kQuantFeat = 3, kQuantSel = 4;
-
-// Selector network layout (floats): mu[16], rs[16], W1[64][16], b1[64],
-// W2[64][64], b2[64], W3[3][64], b3[3].
-constexpr int kSelMu = 0, kSelRs = kNFeat, kSelW1 = 2 * kNFeat, kSelB1 = kSelW1 + kNHid * kNFeat,
-              kSelW2 = kSelB1 + kNHid, kSelB2 = kSelW2 + kNHid * kNHid, kSelW3 = kSelB2 + kNHid,
-              kSelB3 = kSelW3 + kNOut * kNHid, kSelParams = kSelB3 + kNOut;
-static_assert(kSelParams == kSelectorParams, "selector layout");
-
-// plog2(1 + v): the piecewise-linear base-2 logarithm of the float 1 + v
-// read from its bits (exponent + mantissa fraction), deterministic on any
-// IEEE machine
-__device__ __forceinline__ float plog2_1p(double v) {
-    const float a = 1.0f + (float)v;
-    return (float)(int32_t)(__float_as_uint(a) - 0x3F800000u) * (1.0f / 8388608.0f);
-}
-
-__device__ __forceinline__ int64_t wave_sum64(int64_t a) {
-    const uint64_t r = wave_incl_scan64((uint64_t)a, [](uint64_t x, uint64_t y) { return x + y; });
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)r, 63);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(r >> 32), 63);
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-__device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
-    return v;
-}
+// cheapest predictor -> choice[b], the three costs -> costs[3 b + p]).
+constexpr int kQuantP0 = 0, kQuantPred = 1, kQuantTrial = 2;
 
 template <int ND, int MODE>
 __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom g, uint32_t mode, double eb,
@@ -189,8 +140,7 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
                                                uint2* __restrict__ pstage, int fixed_pred,
                                                const uint8_t* __restrict__ bpred, int32_t* __restrict__ coef,
                                                const uint32_t* __restrict__ cw_ref, uint8_t* __restrict__ choice,
-                                               uint32_t* __restrict__ costs, const float* __restrict__ sel,
-                                               float* __restrict__ feat, float* __restrict__ yout) {
+                                               uint32_t* __restrict__ costs) {
     constexpr bool PRED = MODE != kQuantP0;
     // q per block, regions padded by 8 words so the load-mapped writes of
     // four blocks do not fall into the same banks; one extra zero row
@@ -202,9 +152,6 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
     __shared__ uint32_t wsum[4];
     __shared__ uint8_t LREF[kBins];
     // selector network, hidden-layer weights transposed (lane = unit)
-    __shared__ float W1T[kNFeat * kNHid];
-    __shared__ float W2T[kNHid * kNHid];
-    __shared__ float HB[kTileBlocks][kNHid];
 
     const uint32_t t = threadIdx.x;
     const uint32_t lane = t & 63;
@@ -225,16 +172,6 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
         for (uint32_t i = t; i < (uint32_t)kBins; i += 256) {
             const uint32_t l = cw_ref[i] >> 16;
             LREF[i] = (uint8_t)(l ? l : kLmax + 1);
-        }
-    }
-    if ((MODE == kQuantFeat || MODE == kQuantSel) && sel) {
-        for (uint32_t i = t; i < (uint32_t)(kNFeat * kNHid); i += 256) {
-            const uint32_t j = i / kNFeat, k = i % kNFeat;  // W1[j][k]
-            W1T[k * kNHid + j] = sel[kSelW1 + i];
-        }
-        for (uint32_t i = t; i < (uint32_t)(kNHid * kNHid); i += 256) {
-            const uint32_t j = i / kNHid, k = i % kNHid;  // W2[j][k]
-            W2T[k * kNHid + j] = sel[kSelW2 + i];
         }
     }
     if (t < 8) Q[kZero + t] = 0;
@@ -437,7 +374,7 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
                 const int32_t cX = dx > 0 ? clamp32(rdiv(SU * 256, dx)) : 0;
                 const int32_t cY = (ND >= 2 && dy > 0) ? clamp32(rdiv(SV * 256, dy)) : 0;
                 const int32_t cZ = (ND >= 3 && dz > 0) ? clamp32(rdiv(SW * 256, dz)) : 0;
-                if ((MODE == kQuantPred || MODE == kQuantSel) && lane == 0 && blk) {
+                if (MODE == kQuantPred && lane == 0 && blk) {
                     int4* cp = reinterpret_cast<int4*>(coef + 4 * (uint64_t)b);
                     *cp = make_int4(cA, cX, cY, cZ);
                 }
@@ -477,147 +414,11 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
                         costs[3 * (uint64_t)b + 2] = cst[2];
                     }
                 }
-            } else if (MODE == kQuantFeat || MODE == kQuantSel) {
-                // ---- block features (version 1), exact integer sums first
-                int64_t r0s = 0, r1s = 0, r2s = 0;
-                int32_t r0m = 0;
-                uint32_t nout = 0;
-                residual(0);
-#pragma unroll
-                for (int i = 0; i < 8; i++)
-                    if (i < (int)nv) {
-                        const int64_t a = d[i] < 0 ? -(int64_t)d[i] : (int64_t)d[i];
-                        r0s += a;
-                        r0m = max(r0m, (int32_t)min(a, (int64_t)INT32_MAX));
-                        nout += (d[i] <= -kRadius || d[i] >= kRadius) ? 1u : 0u;
-                    }
-                residual(1);
-#pragma unroll
-                for (int i = 0; i < 8; i++)
-                    if (i < (int)nv) r1s += d[i] < 0 ? -(int64_t)d[i] : (int64_t)d[i];
-                residual(2);
-#pragma unroll
-                for (int i = 0; i < 8; i++)
-                    if (i < (int)nv) r2s += d[i] < 0 ? -(int64_t)d[i] : (int64_t)d[i];
-                // moments, range and differences inside the block
-                const uint32_t sy = g.bs[0], sz = g.bs[0] * g.bs[1];
-                int64_t s1 = 0, s2 = 0, d1[3] = {0, 0, 0}, d2[3] = {0, 0, 0}, dm[3] = {0, 0, 0};
-                int32_t qmax = INT32_MIN, qneg = INT32_MIN;  // max q, max -q
-                auto A = [&](int64_t v) { return v < 0 ? -v : v; };
-#pragma unroll
-                for (int i = 0; i < 8; i++)
-                    if (i < (int)nv) {
-                        const uint32_t lx = lx0 + i;
-                        const uint32_t k = Qb + s * 8 + i;
-                        const int64_t v = Q[k];
-                        s1 += v;
-                        s2 += v * v;
-                        qmax = max(qmax, (int32_t)v);
-                        qneg = max(qneg, (int32_t)(-v));
-                        const int64_t xm = lx >= 1 ? Q[k - 1] : 0, ym = ly >= 1 ? Q[k - sy] : 0,
-                                      zm = lz >= 1 ? Q[k - sz] : 0;
-                        if (lx >= 1) d1[0] += A(v - xm);
-                        if (ly >= 1) d1[1] += A(v - ym);
-                        if (lz >= 1) d1[2] += A(v - zm);
-                        if (lx >= 2) d2[0] += A(v - 2 * xm + Q[k - 2]);
-                        if (ly >= 2) d2[1] += A(v - 2 * ym + Q[k - 2 * sy]);
-                        if (lz >= 2) d2[2] += A(v - 2 * zm + Q[k - 2 * sz]);
-                        if (lx >= 1 && ly >= 1) dm[0] += A(v - xm - ym + Q[k - 1 - sy]);
-                        if (ly >= 1 && lz >= 1) dm[1] += A(v - ym - zm + Q[k - sy - sz]);
-                        if (lx >= 1 && lz >= 1) dm[2] += A(v - xm - zm + Q[k - 1 - sz]);
-                    }
-                const int64_t S1 = wave_sum64(s1), S2 = wave_sum64(s2);
-                const int64_t R0 = wave_sum64(r0s), R1 = wave_sum64(r1s), R2 = wave_sum64(r2s);
-                const int64_t NO = wave_sum64(nout);
-                int64_t D1[3], D2[3], DM[3];
-#pragma unroll
-                for (int a = 0; a < 3; a++) {
-                    D1[a] = wave_sum64(d1[a]);
-                    D2[a] = wave_sum64(d2[a]);
-                    DM[a] = wave_sum64(dm[a]);
-                }
-                const int64_t QMAX = wave_max_i32(qmax), QMIN = -(int64_t)wave_max_i32(qneg);
-                const int64_t R0M = wave_max_i32(r0m);
-                // pair counts from the extents
-                const int64_t e[3] = {(int64_t)info.ex, (int64_t)info.ey, (int64_t)info.ez};
-                const int64_t n = e[0] * e[1] * e[2];
-                auto mean = [](int64_t sum, int64_t cnt) { return cnt > 0 ? (double)sum / (double)cnt : 0.0; };
-                float f[kNFeat];
-                const double m = (double)S1 / (double)n;
-                double var = (double)S2 / (double)n - m * m;
-                if (var < 0.0) var = 0.0;
-                f[0] = plog2_1p(var);
-                f[1] = plog2_1p((double)(QMAX - QMIN));
-#pragma unroll
-                for (int a = 0; a < 3; a++) {
-                    const int64_t rest = n / e[a];
-                    f[2 + a] = plog2_1p(mean(D1[a], (e[a] - 1) * rest));
-                    f[5 + a] = plog2_1p(mean(D2[a], (e[a] >= 2 ? e[a] - 2 : 0) * rest));
-                }
-                // mixed pairs: xy, yz, xz
-                f[8] = plog2_1p(mean(DM[0], (e[0] - 1) * (e[1] - 1) * e[2]));
-                f[9] = plog2_1p(mean(DM[1], e[0] * (e[1] - 1) * (e[2] - 1)));
-                f[10] = plog2_1p(mean(DM[2], (e[0] - 1) * e[1] * (e[2] - 1)));
-                f[11] = plog2_1p(mean(R0, n));
-                f[12] = plog2_1p((double)R0M);
-                f[13] = (float)((double)NO / (double)n);
-                f[14] = plog2_1p(mean(R1, n));
-                f[15] = plog2_1p(mean(R2, n));
-                if (feat && blk && lane < (uint32_t)kNFeat) {
-                    float fv = f[0];
-#pragma unroll
-                    for (int i = 1; i < kNFeat; i++) fv = lane == (uint32_t)i ? f[i] : fv;
-                    feat[(uint64_t)b * kNFeat + lane] = fv;
-                }
-                if (sel) {
-                    // ---- selector network: lane j computes hidden unit j,
-                    // every sum in index order from the bias, no contraction
-                    float z[kNFeat];
-#pragma unroll
-                    for (int i = 0; i < kNFeat; i++) {
-                        const float dd = f[i] - sel[kSelMu + i];
-                        z[i] = dd * sel[kSelRs + i];
-                    }
-                    float acc = sel[kSelB1 + lane];
-#pragma unroll
-                    for (int i = 0; i < kNFeat; i++) {
-                        const float p = W1T[i * kNHid + lane] * z[i];
-                        acc = acc + p;
-                    }
-                    HB[wave][lane] = acc > 0.0f ? acc : 0.0f;
-                    __builtin_amdgcn_wave_barrier();
-                    float acc2 = sel[kSelB2 + lane];
-                    for (int i = 0; i < kNHid; i++) {
-                        const float p = W2T[i * kNHid + lane] * HB[wave][i];
-                        acc2 = acc2 + p;
-                    }
-                    __builtin_amdgcn_wave_barrier();
-                    HB[wave][lane] = acc2 > 0.0f ? acc2 : 0.0f;
-                    __builtin_amdgcn_wave_barrier();
-                    float yk = 0.0f;
-                    if (lane < (uint32_t)kNOut) {
-                        yk = sel[kSelB3 + lane];
-                        for (int i = 0; i < kNHid; i++) {
-                            const float p = sel[kSelW3 + lane * kNHid + i] * HB[wave][i];
-                            yk = yk + p;
-                        }
-                    }
-                    const float y0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, yk), 0));
-                    const float y1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, yk), 1));
-                    const float y2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, yk), 2));
-                    uint32_t best = 0;
-                    float bv = y0;
-                    if (y1 < bv) { best = 1; bv = y1; }
-                    if (y2 < bv) best = 2;
-                    if (blk && lane == 0) choice[b] = (uint8_t)best;
-                    if (yout && blk && lane < (uint32_t)kNOut) yout[(uint64_t)b * kNOut + lane] = yk;
-                    if (MODE == kQuantSel) residual(blk ? best : 0u);
-                }
             } else {
                 residual(PRED ? (fixed_pred >= 0 ? (uint32_t)fixed_pred : (blk ? (uint32_t)bpred[b] : 0u)) : 0u);
             }
         }
-        if (MODE == kQuantTrial || MODE == kQuantFeat) {
+        if (MODE == kQuantTrial) {
             __syncthreads();
             continue;
         }
@@ -700,7 +501,7 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
         }
         __syncthreads();
     }
-    if (MODE == kQuantTrial || MODE == kQuantFeat) return;
+    if (MODE == kQuantTrial) return;
     __syncthreads();
     for (uint32_t i = t; i < (uint32_t)kBins; i += 256)
         if (H[i]) atomicAdd(&hist_g[(blockIdx.x % kHistCopies) * kBins + i], H[i]);
@@ -724,8 +525,7 @@ void launch_minmax(hipStream_t st, const float* x, uint64_t N, int vec, Misc* mi
 
 #define FZ_QUANT(NDV, MV)                                                                                        \
     hipLaunchKernelGGL((k_quant<NDV, MV>), dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, hist, codes, \
-                       ntiles, tile_cnt, ostage, pstage, fixed_pred, bpred, coef, cw_ref, choice, costs, sel, feat, \
-                       yout)
+                       ntiles, tile_cnt, ostage, pstage, fixed_pred, bpred, coef, cw_ref, choice, costs)
 
 void launch_quant(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
                   Misc* misc, uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt, uint2* ostage,
@@ -733,8 +533,6 @@ void launch_quant(hipStream_t st, int grid, const float* x, const Geom& g, uint3
     const uint32_t* cw_ref = nullptr;
     uint8_t* choice = nullptr;
     uint32_t* costs = nullptr;
-    const float* sel = nullptr;
-    float *feat = nullptr, *yout = nullptr;
     const bool pred = fixed_pred != 0;
     if (g.ndim == 3) {
         if (pred) FZ_QUANT(3, kQuantPred); else FZ_QUANT(3, kQuantP0);
@@ -754,40 +552,11 @@ void launch_trial(hipStream_t st, int grid, const float* x, const Geom& g, uint3
     int32_t* coef = nullptr;
     const uint8_t* bpred = nullptr;
     const int fixed_pred = -1;
-    const float* sel = nullptr;
-    float *feat = nullptr, *yout = nullptr;
     if (g.ndim == 3) FZ_QUANT(3, kQuantTrial);
     else if (g.ndim == 2) FZ_QUANT(2, kQuantTrial);
     else FZ_QUANT(1, kQuantTrial);
 }
 
-void launch_quant_select(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
-                         Misc* misc, uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt,
-                         uint2* ostage, uint2* pstage, const float* sel, uint8_t* choice, int32_t* coef) {
-    const uint32_t* cw_ref = nullptr;
-    const uint8_t* bpred = nullptr;
-    uint32_t* costs = nullptr;
-    float *feat = nullptr, *yout = nullptr;
-    const int fixed_pred = -1;
-    if (g.ndim == 3) FZ_QUANT(3, kQuantSel);
-    else if (g.ndim == 2) FZ_QUANT(2, kQuantSel);
-    else FZ_QUANT(1, kQuantSel);
-}
-
-void launch_features(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
-                     Misc* misc, uint32_t ntiles, const float* sel, float* feat, float* yout, uint8_t* choice) {
-    uint32_t* hist = nullptr;
-    uint16_t* codes = nullptr;
-    uint32_t *tile_cnt = nullptr, *costs = nullptr;
-    uint2 *ostage = nullptr, *pstage = nullptr;
-    int32_t* coef = nullptr;
-    const uint8_t* bpred = nullptr;
-    const uint32_t* cw_ref = nullptr;
-    const int fixed_pred = -1;
-    if (g.ndim == 3) FZ_QUANT(3, kQuantFeat);
-    else if (g.ndim == 2) FZ_QUANT(2, kQuantFeat);
-    else FZ_QUANT(1, kQuantFeat);
-}
 #undef FZ_QUANT
 
 __global__ void k_fill32(uint32_t* p, uint64_t n, uint32_t v) {

@@ -1,0 +1,400 @@
+// Learned per-block predictor selection (the selection-only pass): the 16
+// block features over each block's 128-value sample, then the selector
+// network 16 -> 64 -> 64 -> 3 per block.  FZModules leaves the choice among
+// predictors open (Sec. 2.1 names Lorenzo and regression, Sec. 5 the
+// automatic choice as future work); the features and the network are this
+// library's reading, bit-identical to a plain sequential evaluation.
+#include "fz_common.h"
+#include "fz_kernels.h"
+
+namespace fz {
+
+namespace {
+
+constexpr int kFTile = 16;                 // blocks per feature tile: 16 x 16 sample segments = 256 threads
+constexpr int kFQS = kFeatSample + 8;      // LDS words per block row set (padded)
+constexpr uint32_t kFZero = kFTile * kFQS; // eight zero words: neighbours outside the block
+constexpr int kFSW = 17;                   // partial-sum words per lane
+
+// Load mapping of the feature pass: which (block in tile, sample segment)
+// thread t prequantises, so that consecutive lanes read consecutive
+// addresses (16 blocks side by side along x).
+template <int ND>
+__device__ __forceinline__ void fmap(uint32_t t, uint32_t& bi, uint32_t& s) {
+    if (ND == 3) { bi = t & 15; s = t >> 4; }                                // rows of 32 B
+    else if (ND == 2) { bi = (t >> 2) & 15; s = (t & 3) | ((t >> 6) << 2); }  // rows of 128 B
+    else { bi = t >> 4; s = t & 15; }                                       // 512 B per block
+}
+
+__device__ __forceinline__ void row8(const int32_t* Q, uint32_t off, int32_t r[8]) {
+    const int4* p = reinterpret_cast<const int4*>(&Q[off]);
+    const int4 a = p[0], c = p[1];
+    r[0] = a.x; r[1] = a.y; r[2] = a.z; r[3] = a.w;
+    r[4] = c.x; r[5] = c.y; r[6] = c.z; r[7] = c.w;
+}
+
+__device__ __forceinline__ int64_t shfl_i64(int64_t v, uint32_t src) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, (int)src, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)((uint64_t)v >> 32), (int)src, 64);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// LDS handoff between the lanes of one wave (LDS is in order within a
+// wave; the fences keep the compiler from moving accesses across)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// plog2(1 + v): the piecewise-linear base-2 logarithm of the float 1 + v
+// read from its bits (exponent + mantissa fraction)
+__device__ __forceinline__ float plog2_1p(double v) {
+    const float a = 1.0f + (float)v;
+    return (float)(int32_t)(__float_as_uint(a) - 0x3F800000u) * (1.0f / 8388608.0f);
+}
+
+__device__ __forceinline__ int32_t iabs(int32_t v) { return v < 0 ? -v : v; }
+
+}  // namespace
+
+// ---------------------------------------------------------- block features
+// One workgroup handles a tile of 16 consecutive blocks per iteration
+// (tiles grid-strided; the next tile's values are loaded one tile ahead).
+//   phase A: thread = (block, sample segment): 8 values -> q -> LDS
+//   phase B: wave = 4 blocks, lane = (block, segment): exact partial sums
+//     of the segment's 8 values (|q| <= 2^24 keeps every per-segment sum
+//     but that of q^2 in 32 bits), written to LDS; lane (block, k) then
+//     reduces slot k over the block's 16 segments in 64 bits and computes
+//     feature k.
+// Slots (32-bit words): 0-1 sum q^2, 2 max q, 3-5 / 6-8 |first| / |second|
+// differences along x, y, z, 9-11 |mixed| differences xy, yz, xz, 12 sum
+// |first-order residual|, 13 its max, 14 first-order outliers, 15 max -q,
+// 16 sum q.  Lane k reads word k + 1 (k >= 1) or the pair 0-1 (k = 0).
+template <int ND>
+__global__ __launch_bounds__(256) void k_features(const float* __restrict__ x, Geom g, uint32_t mode, double eb,
+                                                  int vec, Misc* misc, uint32_t ntiles, float* __restrict__ feat) {
+    __shared__ int32_t Q[kFTile * kFQS + 16];
+    __shared__ int32_t FS[256 * kFSW + 1];
+    const uint32_t t = threadIdx.x;
+    const uint32_t lane = t & 63;
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 6));
+    double eb_abs;
+    if (!resolve_eb(mode, eb, misc->mm_lo, misc->mm_hi, &eb_abs)) {
+        if (blockIdx.x == 0 && t == 0) atomicOr(&misc->flags, F_EB);
+        return;
+    }
+    const double e2 = 2.0 * eb_abs;
+    const double inv = 1.0 / e2;
+    const bool check_finite = mode != 1;
+    if (t < 16) Q[kFZero + t] = 0;
+
+    // phase-A lane constants
+    uint32_t la_bi, la_s, la_lx0, la_ly, la_lz;
+    fmap<ND>(t, la_bi, la_s);
+    seg_coords<ND>(la_s, la_lx0, la_ly, la_lz);
+    const uint32_t la_rowoff = la_lx0 + g.n[0] * (la_ly + g.n[1] * la_lz);
+    auto tile_src = [&](uint32_t tile, uint32_t& base, uint32_t& nv) {
+        const uint32_t bk = tile * kFTile + la_bi;
+        const bool ok = bk < g.nblocks;
+        const BlockInfo ik = block_info(g, ok ? bk : 0);
+        nv = (ok && la_ly < ik.ey && la_lz < ik.ez && la_lx0 < ik.ex) ? min(8u, ik.ex - la_lx0) : 0u;
+        base = ik.bx * g.bs[0] + g.n[0] * (ik.by * g.bs[1] + g.n[1] * (ik.bz * g.bs[2])) + la_rowoff;
+    };
+    auto tile_load = [&](uint32_t base, uint32_t nv, float v[8]) {
+        if (nv == 8 && vec) {
+            const f32x4* p = reinterpret_cast<const f32x4*>(x + base);
+            const f32x4 a = __builtin_nontemporal_load(p);
+            const f32x4 c = __builtin_nontemporal_load(p + 1);
+            v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+            v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; i++) v[i] = (i < (int)nv) ? x[base + i] : 0.0f;
+        }
+    };
+    uint32_t pf_nv = 0;
+    float pf[8];
+    {
+        uint32_t base = 0;
+        if (blockIdx.x < ntiles) tile_src(blockIdx.x, base, pf_nv);
+        tile_load(base, blockIdx.x < ntiles ? pf_nv : 0u, pf);
+    }
+
+    // phase-B lane constants: block of the wave's four, segment, its
+    // coordinates, the lane's partial-sum row and its group's first lane
+    const uint32_t pb_bi = wave * 4 + (lane >> 4);
+    const uint32_t s = lane & 15;
+    const uint32_t gb = lane & ~15u;
+    uint32_t lx0, ly, lz;
+    seg_coords<ND>(s, lx0, ly, lz);
+    const uint32_t Qb = pb_bi * kFQS;
+    int32_t* fs = &FS[(wave * 64 + lane) * kFSW];
+
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        // ---------------- phase A
+        {
+            const uint32_t nv = pf_nv;
+            int32_t q[8];
+            bool bad = false;
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                bool p;
+                const int32_t qi = prequant1(pf[i], e2, inv, eb_abs, p);
+                const bool valid = i < (int)nv;
+                bad |= check_finite && valid && !__builtin_isfinite(pf[i]);
+                q[i] = valid ? qi : 0;
+            }
+            if (bad) atomicOr(&misc->flags, F_NONFINITE);
+            int4* dst = reinterpret_cast<int4*>(&Q[la_bi * kFQS + la_s * 8]);
+            dst[0] = make_int4(q[0], q[1], q[2], q[3]);
+            dst[1] = make_int4(q[4], q[5], q[6], q[7]);
+        }
+        __syncthreads();
+        {
+            const uint32_t nt = tile + gridDim.x;
+            uint32_t base = 0;
+            if (nt < ntiles) tile_src(nt, base, pf_nv);
+            else pf_nv = 0;
+            tile_load(base, pf_nv, pf);
+        }
+
+        // ---------------- phase B
+        const uint32_t b = tile * kFTile + pb_bi;
+        const bool blk = b < g.nblocks;
+        const BlockInfo info = block_info(g, blk ? b : 0);
+        const uint32_t nv = (blk && ly < info.ey && lz < info.ez && lx0 < info.ex) ? min(8u, info.ex - lx0) : 0u;
+        // the segment's row and its neighbours (zeros outside the block):
+        // xm/x2 = one/two back along x, ym/y2 along y, zm along z, and the
+        // diagonal neighbours xym (x-1, y-1), yzm (y-1, z-1), xzm (x-1, z-1)
+        int32_t r0[8], xm[8], x2[8], ym[8], y2[8], zm[8], xym[8], yzm[8], xzm[8];
+        row8(Q, Qb + s * 8, r0);
+        if (ND == 3) {
+            int32_t ryz[8];
+            row8(Q, ly >= 1 ? Qb + (s - 1) * 8 : kFZero, ym);
+            row8(Q, ly >= 2 ? Qb + (s - 2) * 8 : kFZero, y2);
+            row8(Q, lz >= 1 ? Qb + (s - 8) * 8 : kFZero, zm);
+            row8(Q, (ly >= 1 && lz >= 1) ? Qb + (s - 9) * 8 : kFZero, ryz);
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                xm[i] = i >= 1 ? r0[i - 1] : 0;
+                x2[i] = i >= 2 ? r0[i - 2] : 0;
+                xym[i] = i >= 1 ? ym[i - 1] : 0;
+                xzm[i] = i >= 1 ? zm[i - 1] : 0;
+                yzm[i] = ryz[i];
+            }
+        } else {
+            // 1 and 2 D: x runs on across the segments of a row
+            const uint32_t sx = ND == 2 ? (s & 3) : s;
+            const uint32_t lo = sx >= 1 ? Qb + (s - 1) * 8 : kFZero;
+            const int32_t l6 = Q[lo + (sx >= 1 ? 6 : 0)], l7 = Q[lo + (sx >= 1 ? 7 : 0)];
+            int32_t u7 = 0;
+            if (ND == 2) {
+                row8(Q, ly >= 1 ? Qb + (s - 4) * 8 : kFZero, ym);
+                row8(Q, ly >= 2 ? Qb + (s - 8) * 8 : kFZero, y2);
+                u7 = Q[(sx >= 1 && ly >= 1) ? Qb + (s - 5) * 8 + 7 : kFZero];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; i++) ym[i] = y2[i] = 0;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                xm[i] = i >= 1 ? r0[i - 1] : l7;
+                x2[i] = i >= 2 ? r0[i - 2] : (i == 1 ? l7 : l6);
+                xym[i] = i >= 1 ? ym[i - 1] : u7;
+                zm[i] = yzm[i] = xzm[i] = 0;
+            }
+        }
+        // first-order Lorenzo residual (block-local: outside neighbours 0):
+        // A = the y/z part at each x, then the backward difference along x
+        // (A one back along x: from the left neighbours; 0 in 3 D, where a
+        // segment is a whole x row)
+        int32_t A[8], d[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) A[i] = (r0[i] - ym[i]) - (zm[i] - yzm[i]);
+#pragma unroll
+        for (int i = 0; i < 8; i++) d[i] = A[i] - (i >= 1 ? A[i - 1] : xm[0] - xym[0]);
+        int64_t s2 = 0;
+        int32_t s1 = 0, r0s = 0, r0m = 0, nout = 0, qhi = INT32_MIN, qneg = INT32_MIN;
+        int32_t d1[3] = {0, 0, 0}, d2[3] = {0, 0, 0}, dm[3] = {0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+            if (i < (int)nv) {
+                const uint32_t lx = lx0 + i;
+                const int32_t v = r0[i];
+                const int32_t a = iabs(d[i]);
+                r0s += a;
+                r0m = max(r0m, a);
+                nout += (d[i] <= -kRadius || d[i] >= kRadius) ? 1 : 0;
+                s1 += v;
+                s2 += (int64_t)v * v;
+                qhi = max(qhi, v);
+                qneg = max(qneg, -v);
+                if (lx >= 1) d1[0] += iabs(v - xm[i]);
+                if (ly >= 1) d1[1] += iabs(v - ym[i]);
+                if (lz >= 1) d1[2] += iabs(v - zm[i]);
+                if (lx >= 2) d2[0] += iabs(v - 2 * xm[i] + x2[i]);
+                if (ly >= 2) d2[1] += iabs(v - 2 * ym[i] + y2[i]);
+                if (lx >= 1 && ly >= 1) dm[0] += iabs(v - xm[i] - ym[i] + xym[i]);
+                if (ly >= 1 && lz >= 1) dm[1] += iabs(v - ym[i] - zm[i] + yzm[i]);
+                if (lx >= 1 && lz >= 1) dm[2] += iabs(v - xm[i] - zm[i] + xzm[i]);
+            }
+        fs[0] = (int32_t)(uint32_t)(uint64_t)s2;
+        fs[1] = (int32_t)(uint32_t)((uint64_t)s2 >> 32);
+        fs[2] = qhi;
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            fs[3 + a] = d1[a];
+            fs[6 + a] = d2[a];
+            fs[9 + a] = dm[a];
+        }
+        fs[12] = r0s;
+        fs[13] = r0m;
+        fs[14] = nout;
+        fs[15] = qneg;
+        fs[16] = s1;
+        wave_lds_sync();
+        // lane (block, k): slot k over the block's 16 segments
+        const uint32_t k = s;
+        const bool mx = k == 1 || k == 12 || k == 14;
+        const uint32_t wk = k == 0 ? 0u : k + 1;
+        int64_t tot = mx ? (int64_t)INT32_MIN : 0;
+#pragma unroll
+        for (int j = 0; j < kFeatSegs; j++) {
+            const int32_t* row = &FS[(wave * 64 + gb + j) * kFSW + wk];
+            const uint32_t lo = (uint32_t)row[0], hi = (uint32_t)row[1];
+            const int64_t v = k == 0 ? (int64_t)(((uint64_t)hi << 32) | lo) : (int64_t)(int32_t)lo;
+            tot = mx ? (v > tot ? v : tot) : tot + v;
+        }
+        // lanes 1 and 14 exchange max q and max -q
+        const int64_t oth = shfl_i64(tot, gb + (k == 1 ? 14 : 1));
+        // extents of the sample: the block's, the slowest axis cut
+        const int32_t e0 = ND == 1 ? min((int32_t)info.ex, kFeatSample) : (int32_t)info.ex;
+        const int32_t e1 = ND == 2 ? min((int32_t)info.ey, kFeatSample / (int32_t)g.bs[0]) : (int32_t)info.ey;
+        const int32_t e2s = ND == 3 ? min((int32_t)info.ez, kFeatSample / (int32_t)(g.bs[0] * g.bs[1]))
+                                    : (int32_t)info.ez;
+        const int32_t n = e0 * e1 * e2s;
+        // feature k = plog2(1 + num / den) (den = 1: a plain integer;
+        // den = 0: an empty difference set, mean 0)
+        auto A64 = [](int64_t v) { return v < 0 ? -v : v; };
+        int64_t num = tot;
+        int32_t den = n;
+        if (k == 1) num = tot + oth;                                   // max q - min q
+        if (k == 14) num = A64(tot) > A64(oth) ? A64(tot) : A64(oth);  // max |q|
+        if (k == 1 || k == 12 || k == 14) den = 1;
+        if (k >= 2 && k <= 7) {
+            const uint32_t a = (k - 2) % 3;
+            const int32_t ea = a == 0 ? e0 : (a == 1 ? e1 : e2s);
+            const int32_t m = k <= 4 ? ea - 1 : (ea >= 2 ? ea - 2 : 0);
+            den = m * (n / ea);
+        }
+        if (k >= 8 && k <= 10) {
+            const uint32_t mm = k - 8;  // xy, yz, xz
+            den = (mm == 1 ? e0 : e0 - 1) * (mm == 2 ? e1 : e1 - 1) * (mm == 0 ? e2s : e2s - 1);
+        }
+        const double qd = den > 0 ? (double)num / (double)den : 0.0;
+        const double mean_q = __builtin_bit_cast(double, shfl_i64(__builtin_bit_cast(int64_t, qd), gb + 15));
+        double arg = qd;
+        if (k == 0) {
+            arg = qd - mean_q * mean_q;
+            if (arg < 0.0) arg = 0.0;
+        }
+        if (k == 15) arg = fabs(qd);
+        const float fk = k == 13 ? (float)qd : plog2_1p(arg);
+        if (blk) feat[(uint64_t)b * kNFeat + k] = fk;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- network
+// Thread = block.  The parameters sit in LDS in their natural layout and
+// are read at the same address by every lane (broadcast); each dot product
+// is summed in index order from its bias with separately rounded products
+// and sums, the three outputs accumulated as the second hidden layer
+// produces its units (the same order).  Ties go to the lower predictor.
+// Parameter layout (floats): mu[16], rs[16], W1[64][16], b1[64],
+// W2[64][64], b2[64], W3[3][64], b3[3].
+constexpr int kPMu = 0, kPRs = kNFeat, kPW1 = 2 * kNFeat, kPB1 = kPW1 + kNHid * kNFeat, kPW2 = kPB1 + kNHid,
+              kPB2 = kPW2 + kNHid * kNHid, kPW3 = kPB2 + kNHid, kPB3 = kPW3 + kNOut * kNHid,
+              kPParams = kPB3 + kNOut;
+static_assert(kPParams == kSelectorParams, "selector layout");
+
+__global__ __launch_bounds__(256) void k_mlp(const float* __restrict__ feat, uint32_t n, const float* __restrict__ sel,
+                                             float* __restrict__ yout, uint8_t* __restrict__ choice) {
+    __shared__ __attribute__((aligned(16))) float P[kPParams + 1];
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kPParams; i += 256) P[i] = sel[i];
+    __syncthreads();
+    for (uint32_t b = blockIdx.x * 256 + threadIdx.x; b < n; b += gridDim.x * 256) {
+        // the parameters are re-read from LDS for every block: kept from
+        // being hoisted into registers, which would take the register file
+        asm volatile("" ::: "memory");
+        float z[kNFeat];
+        const f32x4* fp = reinterpret_cast<const f32x4*>(feat + (uint64_t)b * kNFeat);
+#pragma unroll
+        for (int q = 0; q < kNFeat / 4; q++) {
+            const f32x4 f = fp[q];
+            const float fv[4] = {f.x, f.y, f.z, f.w};
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                const int i = 4 * q + c;
+                const float dd = fv[c] - P[kPMu + i];
+                z[i] = dd * P[kPRs + i];
+            }
+        }
+        float h1[kNHid];
+#pragma unroll
+        for (int j = 0; j < kNHid; j++) {
+            float acc = P[kPB1 + j];
+#pragma unroll
+            for (int i = 0; i < kNFeat; i++) {
+                const float p = P[kPW1 + kNFeat * j + i] * z[i];
+                acc = acc + p;
+            }
+            h1[j] = acc > 0.0f ? acc : 0.0f;
+        }
+        float y0 = P[kPB3], y1 = P[kPB3 + 1], y2 = P[kPB3 + 2];
+        for (int j = 0; j < kNHid; j++) {
+            float acc = P[kPB2 + j];
+#pragma unroll
+            for (int i = 0; i < kNHid; i++) {
+                const float p = P[kPW2 + kNHid * j + i] * h1[i];
+                acc = acc + p;
+            }
+            const float h = acc > 0.0f ? acc : 0.0f;
+            const float p0 = P[kPW3 + j] * h, p1 = P[kPW3 + kNHid + j] * h, p2 = P[kPW3 + 2 * kNHid + j] * h;
+            y0 = y0 + p0;
+            y1 = y1 + p1;
+            y2 = y2 + p2;
+        }
+        uint32_t best = 0;
+        float bv = y0;
+        if (y1 < bv) { best = 1; bv = y1; }
+        if (y2 < bv) best = 2;
+        if (choice) choice[b] = (uint8_t)best;
+        if (yout) {
+            yout[3 * (uint64_t)b] = y0;
+            yout[3 * (uint64_t)b + 1] = y1;
+            yout[3 * (uint64_t)b + 2] = y2;
+        }
+    }
+}
+
+uint32_t feature_tiles(uint32_t nblocks) { return (nblocks + kFTile - 1) / kFTile; }
+
+void launch_features(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
+                     Misc* misc, float* feat) {
+    const uint32_t ntiles = feature_tiles(g.nblocks);
+    if ((uint32_t)grid > ntiles) grid = (int)ntiles;
+    if (g.ndim == 3) hipLaunchKernelGGL(k_features<3>, dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, ntiles, feat);
+    else if (g.ndim == 2) hipLaunchKernelGGL(k_features<2>, dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, ntiles, feat);
+    else hipLaunchKernelGGL(k_features<1>, dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, ntiles, feat);
+}
+
+void launch_mlp(hipStream_t st, int grid, const float* feat, uint32_t n, const float* sel, float* yout,
+                uint8_t* choice) {
+    const uint32_t need = (n + 255) / 256;
+    if ((uint32_t)grid > need) grid = (int)need;
+    hipLaunchKernelGGL(k_mlp, dim3(grid), dim3(256), 0, st, feat, n, sel, yout, choice);
+}
+
+}  // namespace fz

@@ -112,7 +112,7 @@ def test_selector_file_round_trip(fz, ctx):
         other.selector_load(path)
         assert np.array_equal(other.selector_get().view(np.uint32), w.view(np.uint32))
         raw = bytearray(open(path, "rb").read())
-        raw[8] = 2  # another feature-set version
+        raw[8] = 1  # another feature-set version (the first)
         bad = os.path.join(d, "bad.bin")
         open(bad, "wb").write(bytes(raw))
         with pytest.raises(fz.FZError) as e:

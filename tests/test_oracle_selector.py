@@ -27,8 +27,9 @@ def test_plog2_closed_forms():
 
 
 def test_ramp_x_3d():
-    """q = lx in every 8^3 block: variance 63/12, range 7, unit first
-    differences along x only, no curvature, exact plane fit."""
+    """q = lx in every 8^3 block (features over the two lowest z-planes):
+    variance 63/12, range 7, unit first differences along x only, no
+    curvature, max |q| 7, mean 3.5."""
     lx = np.arange(16, dtype=np.int32) % 8
     q = np.broadcast_to(lx, (8, 16, 16)).copy()
     f = oracle.features_q(q)
@@ -38,17 +39,19 @@ def test_ramp_x_3d():
         assert f[b, 1] == 3.0
         assert f[b, 2] == 1.0 and f[b, 3] == 0 and f[b, 4] == 0
         assert np.all(f[b, 5:11] == 0)
-        assert f[b, 15] == 0.0  # the regression plane fits exactly
+        assert f[b, 14] == _plog2_1p(7) == 3.0
+        assert f[b, 15] == _plog2_1p(3.5)
 
 
 def test_quadratic_y_2d():
-    """q = ly^2 (2D, 32x16 blocks): first differences 2 ly - 1 have mean 15
-    along y, second differences are 2, nothing along x."""
+    """q = ly^2 (2D, 32x16 blocks; features over the four lowest rows):
+    first differences 2 ly - 1 (1, 3, 5) have mean 3 along y, second
+    differences are 2, nothing along x."""
     ly = np.arange(16, dtype=np.int64) ** 2
     q = np.broadcast_to(ly[:, None], (16, 32)).astype(np.int32).copy()
     f = oracle.features_q(q)
     assert f.shape == (1, F)
-    assert f[0, 2] == 0.0 and f[0, 3] == _plog2_1p(15.0)
+    assert f[0, 2] == 0.0 and f[0, 3] == _plog2_1p(3.0) == 2.0
     assert f[0, 5] == 0.0 and f[0, 6] == _plog2_1p(2.0) == 1.5
     assert f[0, 4] == 0 and f[0, 7] == 0 and np.all(f[0, 8:11] == 0)
 
@@ -64,41 +67,42 @@ def test_mixed_difference_xy():
 
 def test_constant_block_residual_features():
     """A constant c: only the block's first point has a first-order residual
-    (c, zero outside the block); the plane fits exactly; c >= 512 is one
-    outlier in 512 values."""
+    (c, zero outside the block); c >= 512 is one outlier in the 128 sampled
+    values; max |q| and |mean| are |c|."""
     for c in (3, 700, -900):
         q = np.full((8, 8, 8), c, np.int32)
         f = oracle.features_q(q)[0]
         assert f[0] == 0 and f[1] == 0
-        assert f[11] == _plog2_1p(abs(c) / 512)
+        assert f[11] == _plog2_1p(abs(c) / 128)
         assert f[12] == _plog2_1p(abs(c))
-        assert f[13] == np.float32((abs(c) >= 512) / 512)
-        assert f[15] == 0.0
+        assert f[13] == np.float32((abs(c) >= 512) / 128)
+        assert f[14] == _plog2_1p(abs(c)) and f[15] == _plog2_1p(abs(c))
 
 
 def test_residual_features_match_residual_fields():
-    """Residual features of random blocks equal the means of the oracle's
-    own residual fields (pinned elsewhere), block by block, ragged edges
-    included."""
+    """Residual features of random blocks equal the statistics of the
+    oracle's own first-order residual field (pinned elsewhere) over each
+    block's sample, its first 128 row-major positions (a lower box), block
+    by block, ragged edges included; so do range, max |q| and |mean|."""
     r = np.random.default_rng(5)
     for shape in [(11, 13, 9), (20, 45), (1100,)]:
         q = r.integers(-2000, 2000, size=shape).astype(np.int32)
         f = oracle.features_q(q)
         d0, _ = oracle.residual(q, oracle.P0)
-        d1, _ = oracle.residual(q, oracle.P1)
-        d2, _ = oracle.residual(q, oracle.P2)
         bs = {1: (512,), 2: (16, 32), 3: (8, 8, 8)}[len(shape)]
+        keep = {1: (128,), 2: (4, 32), 3: (2, 8, 8)}[len(shape)]  # numpy axis order
         nb = [-(-s // b) for s, b in zip(shape, bs)]
         k = 0
         for idx in np.ndindex(*nb):
-            sl = tuple(slice(i * b, (i + 1) * b) for i, b in zip(idx, bs))
+            sl = tuple(slice(i * b, i * b + m) for i, b, m in zip(idx, bs, keep))
             blk = q[sl].astype(np.int64)
-            assert f[k, 11] == _plog2_1p(np.abs(d0[sl]).astype(np.int64).sum() / blk.size)
-            assert f[k, 12] == _plog2_1p(np.abs(d0[sl]).max())
-            assert f[k, 13] == np.float32(np.count_nonzero(np.abs(d0[sl]) >= 512) / blk.size)
-            assert f[k, 14] == _plog2_1p(np.abs(d1[sl]).astype(np.int64).sum() / blk.size)
-            assert f[k, 15] == _plog2_1p(np.abs(d2[sl]).astype(np.int64).sum() / blk.size)
+            res = np.abs(d0[sl]).astype(np.int64)
+            assert f[k, 11] == _plog2_1p(res.sum() / blk.size)
+            assert f[k, 12] == _plog2_1p(res.max())
+            assert f[k, 13] == np.float32(np.count_nonzero(res >= 512) / blk.size)
             assert f[k, 1] == _plog2_1p(blk.max() - blk.min())
+            assert f[k, 14] == _plog2_1p(np.abs(blk).max())
+            assert f[k, 15] == _plog2_1p(abs(blk.sum() / blk.size))
             k += 1
         # block order: x fastest (numpy's last axis)
         assert k == f.shape[0]
