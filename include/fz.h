@@ -235,8 +235,8 @@ int fz_block_trial(fz_ctx *ctx, const fz_params *p, const float *d_in, uint8_t *
 /* Selector parameters, host float32[FZ_SELECTOR_PARAMS] in this order:
  * mu[16], rs[16] (standardisation z = (f - mu) * rs), W1[64][16], b1[64],
  * W2[64][64], b2[64], W3[3][64], b3[3]; hidden layers use ReLU; every dot
- * product is summed in index order from its bias with separately rounded
- * products and sums, so that a given parameter set picks the same
+ * product is a chain of fused multiply-adds (one rounding per term) in
+ * index order from its bias, so that a given parameter set picks the same
  * predictors on any IEEE machine.  set copies them to the device (all
  * must be finite); get returns FZ_ERR_UNSUPPORTED if none is set. */
 int fz_selector_set(fz_ctx *ctx, const float *h_params, uint64_t n);

@@ -1163,9 +1163,10 @@ int orc_features_q(const int32_t *q, int ndim, const uint64_t dims[3], float *fe
  * prediction, ties to the lower index.  Parameter vector (floats, in this
  * order): mu[16], rs[16] (standardisation z = (f - mu) * rs), W1[64][16],
  * b1[64], W2[64][64], b2[64], W3[3][64], b3[3].
- * Inference is in float with every product and sum rounded separately
- * (no fused multiply-add), dot products summed in index order starting
- * from the bias, so that any IEEE machine gets the same bits.            */
+ * Inference is in float: each dot product is a chain of fused
+ * multiply-adds (one rounding per term, IEEE 754-2008 fusedMultiplyAdd,
+ * C99 fmaf) in index order starting from the bias, so that any IEEE
+ * machine gets the same bits.            */
 #define ORC_H 64
 #define ORC_NOUT 3
 #define OFF_MU 0
@@ -1190,26 +1191,17 @@ void orc_mlp_infer(const float *w, const float *feat, uint64_t n, float *y, uint
         }
         for (int j = 0; j < ORC_H; j++) {
             float acc = w[OFF_B1 + j];
-            for (int i = 0; i < ORC_NFEAT; i++) {
-                float p = w[OFF_W1 + ORC_NFEAT * j + i] * z[i];
-                acc = acc + p;
-            }
+            for (int i = 0; i < ORC_NFEAT; i++) acc = fmaf(w[OFF_W1 + ORC_NFEAT * j + i], z[i], acc);
             h1[j] = acc > 0.0f ? acc : 0.0f;
         }
         for (int j = 0; j < ORC_H; j++) {
             float acc = w[OFF_B2 + j];
-            for (int i = 0; i < ORC_H; i++) {
-                float p = w[OFF_W2 + ORC_H * j + i] * h1[i];
-                acc = acc + p;
-            }
+            for (int i = 0; i < ORC_H; i++) acc = fmaf(w[OFF_W2 + ORC_H * j + i], h1[i], acc);
             h2[j] = acc > 0.0f ? acc : 0.0f;
         }
         for (int k = 0; k < ORC_NOUT; k++) {
             float acc = w[OFF_B3 + k];
-            for (int i = 0; i < ORC_H; i++) {
-                float p = w[OFF_W3 + ORC_H * k + i] * h2[i];
-                acc = acc + p;
-            }
+            for (int i = 0; i < ORC_H; i++) acc = fmaf(w[OFF_W3 + ORC_H * k + i], h2[i], acc);
             o[k] = acc;
         }
         int best = 0;

@@ -7,6 +7,8 @@
 #include "fz_common.h"
 #include "fz_kernels.h"
 
+#include <type_traits>
+
 namespace fz {
 
 namespace {
@@ -15,6 +17,7 @@ constexpr int kFTile = 16;                 // blocks per feature tile: 16 x 16 s
 constexpr int kFQS = kFeatSample + 8;      // LDS words per block row set (padded)
 constexpr uint32_t kFZero = kFTile * kFQS; // eight zero words: neighbours outside the block
 constexpr int kFSW = 17;                   // partial-sum words per lane
+constexpr uint32_t kBias = 0x80000000u;    // q is kept in LDS as the biased word q + 2^31
 
 // Load mapping of the feature pass: which (block in tile, sample segment)
 // thread t prequantises, so that consecutive lanes read consecutive
@@ -54,7 +57,10 @@ __device__ __forceinline__ float plog2_1p(double v) {
     return (float)(int32_t)(__float_as_uint(a) - 0x3F800000u) * (1.0f / 8388608.0f);
 }
 
-__device__ __forceinline__ int32_t iabs(int32_t v) { return v < 0 ? -v : v; }
+// |a - b| + c of unsigned words (one v_sad_u32)
+__device__ __forceinline__ uint32_t usad(uint32_t a, uint32_t b, uint32_t c) {
+    return (a > b ? a - b : b - a) + c;
+}
 
 }  // namespace
 
@@ -71,7 +77,7 @@ __device__ __forceinline__ int32_t iabs(int32_t v) { return v < 0 ? -v : v; }
 // differences along x, y, z, 9-11 |mixed| differences xy, yz, xz, 12 sum
 // |first-order residual|, 13 its max, 14 first-order outliers, 15 max -q,
 // 16 sum q.  Lane k reads word k + 1 (k >= 1) or the pair 0-1 (k = 0).
-template <int ND>
+template <int ND, bool XRAG>
 __global__ __launch_bounds__(256) void k_features(const float* __restrict__ x, Geom g, uint32_t mode, double eb,
                                                   int vec, Misc* misc, uint32_t ntiles, float* __restrict__ feat) {
     __shared__ int32_t Q[kFTile * kFQS + 16];
@@ -87,7 +93,7 @@ __global__ __launch_bounds__(256) void k_features(const float* __restrict__ x, G
     const double e2 = 2.0 * eb_abs;
     const double inv = 1.0 / e2;
     const bool check_finite = mode != 1;
-    if (t < 16) Q[kFZero + t] = 0;
+    if (t < 16) Q[kFZero + t] = (int32_t)kBias;
 
     // phase-A lane constants
     uint32_t la_bi, la_s, la_lx0, la_ly, la_lz;
@@ -147,8 +153,9 @@ __global__ __launch_bounds__(256) void k_features(const float* __restrict__ x, G
             }
             if (bad) atomicOr(&misc->flags, F_NONFINITE);
             int4* dst = reinterpret_cast<int4*>(&Q[la_bi * kFQS + la_s * 8]);
-            dst[0] = make_int4(q[0], q[1], q[2], q[3]);
-            dst[1] = make_int4(q[4], q[5], q[6], q[7]);
+            auto bq = [](int32_t v) { return (int32_t)((uint32_t)v ^ kBias); };
+            dst[0] = make_int4(bq(q[0]), bq(q[1]), bq(q[2]), bq(q[3]));
+            dst[1] = make_int4(bq(q[4]), bq(q[5]), bq(q[6]), bq(q[7]));
         }
         __syncthreads();
         {
@@ -164,95 +171,134 @@ __global__ __launch_bounds__(256) void k_features(const float* __restrict__ x, G
         const bool blk = b < g.nblocks;
         const BlockInfo info = block_info(g, blk ? b : 0);
         const uint32_t nv = (blk && ly < info.ey && lz < info.ez && lx0 < info.ex) ? min(8u, info.ex - lx0) : 0u;
-        // the segment's row and its neighbours (zeros outside the block):
-        // xm/x2 = one/two back along x, ym/y2 along y, zm along z, and the
-        // diagonal neighbours xym (x-1, y-1), yzm (y-1, z-1), xzm (x-1, z-1)
-        int32_t r0[8], xm[8], x2[8], ym[8], y2[8], zm[8], xym[8], yzm[8], xzm[8];
-        row8(Q, Qb + s * 8, r0);
+        // The segment's row and its neighbours as biased words q + 2^31
+        // (the zero row holds 2^31): xm/x2 = one/two back along x, ym/y2
+        // along y, zm along z, and the diagonal neighbours xym (x-1, y-1),
+        // yzm (y-1, z-1), xzm (x-1, z-1).  The difference of two biased
+        // words is the difference of the q, and |a - b| + c of two biased
+        // words is one v_sad_u32; a sum like v + x2 is re-biased by adding
+        // 2^31 (all modulo 2^32, every true value far inside 32 bits).
+        uint32_t r0[8], xm[8], x2[8], ym[8], y2[8], zm[8], xym[8], yzm[8], xzm[8];
+        auto urow = [&](uint32_t off, uint32_t r[8]) { row8(Q, off, reinterpret_cast<int32_t*>(r)); };
+        urow(Qb + s * 8, r0);
         if (ND == 3) {
-            int32_t ryz[8];
-            row8(Q, ly >= 1 ? Qb + (s - 1) * 8 : kFZero, ym);
-            row8(Q, ly >= 2 ? Qb + (s - 2) * 8 : kFZero, y2);
-            row8(Q, lz >= 1 ? Qb + (s - 8) * 8 : kFZero, zm);
-            row8(Q, (ly >= 1 && lz >= 1) ? Qb + (s - 9) * 8 : kFZero, ryz);
+            uint32_t ryz[8];
+            urow(ly >= 1 ? Qb + (s - 1) * 8 : kFZero, ym);
+            urow(ly >= 2 ? Qb + (s - 2) * 8 : kFZero, y2);
+            urow(lz >= 1 ? Qb + (s - 8) * 8 : kFZero, zm);
+            urow((ly >= 1 && lz >= 1) ? Qb + (s - 9) * 8 : kFZero, ryz);
 #pragma unroll
             for (int i = 0; i < 8; i++) {
-                xm[i] = i >= 1 ? r0[i - 1] : 0;
-                x2[i] = i >= 2 ? r0[i - 2] : 0;
-                xym[i] = i >= 1 ? ym[i - 1] : 0;
-                xzm[i] = i >= 1 ? zm[i - 1] : 0;
+                xm[i] = i >= 1 ? r0[i - 1] : kBias;
+                x2[i] = i >= 2 ? r0[i - 2] : kBias;
+                xym[i] = i >= 1 ? ym[i - 1] : kBias;
+                xzm[i] = i >= 1 ? zm[i - 1] : kBias;
                 yzm[i] = ryz[i];
             }
         } else {
             // 1 and 2 D: x runs on across the segments of a row
             const uint32_t sx = ND == 2 ? (s & 3) : s;
             const uint32_t lo = sx >= 1 ? Qb + (s - 1) * 8 : kFZero;
-            const int32_t l6 = Q[lo + (sx >= 1 ? 6 : 0)], l7 = Q[lo + (sx >= 1 ? 7 : 0)];
-            int32_t u7 = 0;
+            const uint32_t l6 = (uint32_t)Q[lo + (sx >= 1 ? 6 : 0)], l7 = (uint32_t)Q[lo + (sx >= 1 ? 7 : 0)];
+            uint32_t u7 = kBias;
             if (ND == 2) {
-                row8(Q, ly >= 1 ? Qb + (s - 4) * 8 : kFZero, ym);
-                row8(Q, ly >= 2 ? Qb + (s - 8) * 8 : kFZero, y2);
-                u7 = Q[(sx >= 1 && ly >= 1) ? Qb + (s - 5) * 8 + 7 : kFZero];
+                urow(ly >= 1 ? Qb + (s - 4) * 8 : kFZero, ym);
+                urow(ly >= 2 ? Qb + (s - 8) * 8 : kFZero, y2);
+                u7 = (uint32_t)Q[(sx >= 1 && ly >= 1) ? Qb + (s - 5) * 8 + 7 : kFZero];
             } else {
 #pragma unroll
-                for (int i = 0; i < 8; i++) ym[i] = y2[i] = 0;
+                for (int i = 0; i < 8; i++) ym[i] = y2[i] = kBias;
             }
 #pragma unroll
             for (int i = 0; i < 8; i++) {
                 xm[i] = i >= 1 ? r0[i - 1] : l7;
                 x2[i] = i >= 2 ? r0[i - 2] : (i == 1 ? l7 : l6);
                 xym[i] = i >= 1 ? ym[i - 1] : u7;
-                zm[i] = yzm[i] = xzm[i] = 0;
+                zm[i] = yzm[i] = xzm[i] = kBias;
             }
         }
-        // first-order Lorenzo residual (block-local: outside neighbours 0):
-        // A = the y/z part at each x, then the backward difference along x
-        // (A one back along x: from the left neighbours; 0 in 3 D, where a
-        // segment is a whole x row)
-        int32_t A[8], d[8];
-#pragma unroll
-        for (int i = 0; i < 8; i++) A[i] = (r0[i] - ym[i]) - (zm[i] - yzm[i]);
-#pragma unroll
-        for (int i = 0; i < 8; i++) d[i] = A[i] - (i >= 1 ? A[i - 1] : xm[0] - xym[0]);
+        // x terms whose partner lies in the previous segment (1 and 2 D:
+        // the first value's first difference and mixed differences, the
+        // first two values' second difference) exist only when the segment
+        // is not the first of its row; in 3 D a segment is a whole x row
+        const bool xprev = ND != 3 && lx0 >= 1;
+        // Per-segment sums.  Lane conditions (y >= 1, y >= 2, z >= 1, and
+        // whether the segment holds any value at all) are applied to the
+        // finished sums; per-value validity is tested only when the field's
+        // x extent leaves partial rows (XRAG).
+        uint32_t s1 = 0, qhi = 0u, qlo = 0xFFFFFFFFu, r0s = 0, r0m = 0, nout = 0;
+        uint32_t d1x = 0, d1y = 0, d1z = 0, d2x = 0, d2y = 0, mxy = 0, myz = 0, mxz = 0;
         int64_t s2 = 0;
-        int32_t s1 = 0, r0s = 0, r0m = 0, nout = 0, qhi = INT32_MIN, qneg = INT32_MIN;
-        int32_t d1[3] = {0, 0, 0}, d2[3] = {0, 0, 0}, dm[3] = {0, 0, 0};
+        // first-order residual: A = (q + q(y-1,z-1)) - (q(y-1) + q(z-1))
+        // (biased: P - Qv + 2^31), d = A - A(x-1); A(x-1) from the left
+        // neighbours in 1 and 2 D, zero in 3 D
+        uint32_t Ab_prev = ND == 3 ? kBias : (xm[0] - xym[0]) + kBias;
+        auto body = [&](auto full_tag) {
+            constexpr bool FULL = decltype(full_tag)::value;
 #pragma unroll
-        for (int i = 0; i < 8; i++)
-            if (i < (int)nv) {
-                const uint32_t lx = lx0 + i;
-                const int32_t v = r0[i];
-                const int32_t a = iabs(d[i]);
-                r0s += a;
-                r0m = max(r0m, a);
-                nout += (d[i] <= -kRadius || d[i] >= kRadius) ? 1 : 0;
-                s1 += v;
-                s2 += (int64_t)v * v;
-                qhi = max(qhi, v);
-                qneg = max(qneg, -v);
-                if (lx >= 1) d1[0] += iabs(v - xm[i]);
-                if (ly >= 1) d1[1] += iabs(v - ym[i]);
-                if (lz >= 1) d1[2] += iabs(v - zm[i]);
-                if (lx >= 2) d2[0] += iabs(v - 2 * xm[i] + x2[i]);
-                if (ly >= 2) d2[1] += iabs(v - 2 * ym[i] + y2[i]);
-                if (lx >= 1 && ly >= 1) dm[0] += iabs(v - xm[i] - ym[i] + xym[i]);
-                if (ly >= 1 && lz >= 1) dm[1] += iabs(v - ym[i] - zm[i] + yzm[i]);
-                if (lx >= 1 && lz >= 1) dm[2] += iabs(v - xm[i] - zm[i] + xzm[i]);
+            for (int i = 0; i < 8; i++) {
+                const bool ok = FULL || i < (int)nv;
+                const uint32_t v = r0[i];
+                auto addc = [&](uint32_t& acc, uint32_t a, uint32_t b, bool c) {
+                    const uint32_t r = usad(a, b, acc);
+                    acc = c ? r : acc;
+                };
+                auto add = [&](uint32_t& acc, uint32_t a, uint32_t b) { addc(acc, a, b, ok); };
+                const uint32_t P = v + yzm[i] + kBias, Qv = ym[i] + zm[i] + kBias;
+                const uint32_t Ab = (P - Qv) + kBias;
+                const uint32_t a = usad(Ab, Ab_prev, 0u);
+                Ab_prev = Ab;
+                r0s += ok ? a : 0u;
+                r0m = max(r0m, ok ? a : 0u);
+                nout += (ok && a >= (uint32_t)kRadius) ? 1u : 0u;
+                s1 += ok ? v : kBias;  // eight biased words: the bias sums to 0 mod 2^32
+                const int32_t vs = (int32_t)(v ^ kBias);
+                s2 += (int64_t)vs * vs;  // invalid positions hold q = 0
+                qhi = max(qhi, ok ? v : 0u);
+                qlo = min(qlo, ok ? v : 0xFFFFFFFFu);
+                if (i >= 1) {
+                    add(d1x, v, xm[i]);
+                    add(mxy, v + xym[i] + kBias, xm[i] + ym[i] + kBias);
+                    if (ND == 3) add(mxz, v + xzm[i] + kBias, xm[i] + zm[i] + kBias);
+                } else if (ND != 3) {
+                    addc(d1x, v, xm[i], ok && xprev);
+                    addc(mxy, v + xym[i] + kBias, xm[i] + ym[i] + kBias, ok && xprev);
+                }
+                if (i >= 2) add(d2x, v + x2[i] + kBias, xm[i] + xm[i] + kBias);
+                else if (ND != 3) addc(d2x, v + x2[i] + kBias, xm[i] + xm[i] + kBias, ok && xprev);
+                if (ND >= 2) {
+                    add(d1y, v, ym[i]);
+                    add(d2y, v + y2[i] + kBias, ym[i] + ym[i] + kBias);
+                }
+                if (ND == 3) {
+                    add(d1z, v, zm[i]);
+                    add(myz, P, Qv);
+                }
             }
+        };
+        body(std::integral_constant<bool, !XRAG>{});
+        if (nv == 0) {  // a segment outside the block (y or z edge)
+            s1 = r0s = r0m = nout = d1x = d1y = d1z = d2x = d2y = mxy = myz = mxz = qhi = 0u;
+            qlo = 0xFFFFFFFFu;
+            s2 = 0;
+        }
         fs[0] = (int32_t)(uint32_t)(uint64_t)s2;
         fs[1] = (int32_t)(uint32_t)((uint64_t)s2 >> 32);
-        fs[2] = qhi;
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            fs[3 + a] = d1[a];
-            fs[6 + a] = d2[a];
-            fs[9 + a] = dm[a];
-        }
-        fs[12] = r0s;
-        fs[13] = r0m;
-        fs[14] = nout;
-        fs[15] = qneg;
-        fs[16] = s1;
+        fs[2] = (int32_t)(qhi ^ kBias);
+        fs[3] = (int32_t)d1x;
+        fs[4] = ly >= 1 ? (int32_t)d1y : 0;
+        fs[5] = lz >= 1 ? (int32_t)d1z : 0;
+        fs[6] = (int32_t)d2x;
+        fs[7] = ly >= 2 ? (int32_t)d2y : 0;
+        fs[8] = 0;
+        fs[9] = ly >= 1 ? (int32_t)mxy : 0;
+        fs[10] = (ly >= 1 && lz >= 1) ? (int32_t)myz : 0;
+        fs[11] = lz >= 1 ? (int32_t)mxz : 0;
+        fs[12] = (int32_t)r0s;
+        fs[13] = (int32_t)r0m;
+        fs[14] = (int32_t)nout;
+        fs[15] = -(int32_t)(qlo ^ kBias);
+        fs[16] = (int32_t)s1;
         wave_lds_sync();
         // lane (block, k): slot k over the block's 16 segments
         const uint32_t k = s;
@@ -309,11 +355,11 @@ __global__ __launch_bounds__(256) void k_features(const float* __restrict__ x, G
 // ---------------------------------------------------------------- network
 // Thread = block.  The parameters sit in LDS in their natural layout and
 // are read at the same address by every lane (broadcast); each dot product
-// is summed in index order from its bias with separately rounded products
-// and sums, the three outputs accumulated as the second hidden layer
-// produces its units (the same order).  Ties go to the lower predictor.
-// Parameter layout (floats): mu[16], rs[16], W1[64][16], b1[64],
-// W2[64][64], b2[64], W3[3][64], b3[3].
+// is a chain of fused multiply-adds (one rounding per term) in index order
+// from its bias, the three outputs accumulated while the second hidden
+// layer produces its units (the same order).  Ties go to the lower
+// predictor.  Parameter layout (floats): mu[16], rs[16], W1[64][16],
+// b1[64], W2[64][64], b2[64], W3[3][64], b3[3].
 constexpr int kPMu = 0, kPRs = kNFeat, kPW1 = 2 * kNFeat, kPB1 = kPW1 + kNHid * kNFeat, kPW2 = kPB1 + kNHid,
               kPB2 = kPW2 + kNHid * kNHid, kPW3 = kPB2 + kNHid, kPB3 = kPW3 + kNOut * kNHid,
               kPParams = kPB3 + kNOut;
@@ -346,25 +392,18 @@ __global__ __launch_bounds__(256) void k_mlp(const float* __restrict__ feat, uin
         for (int j = 0; j < kNHid; j++) {
             float acc = P[kPB1 + j];
 #pragma unroll
-            for (int i = 0; i < kNFeat; i++) {
-                const float p = P[kPW1 + kNFeat * j + i] * z[i];
-                acc = acc + p;
-            }
+            for (int i = 0; i < kNFeat; i++) acc = __builtin_fmaf(P[kPW1 + kNFeat * j + i], z[i], acc);
             h1[j] = acc > 0.0f ? acc : 0.0f;
         }
         float y0 = P[kPB3], y1 = P[kPB3 + 1], y2 = P[kPB3 + 2];
         for (int j = 0; j < kNHid; j++) {
             float acc = P[kPB2 + j];
 #pragma unroll
-            for (int i = 0; i < kNHid; i++) {
-                const float p = P[kPW2 + kNHid * j + i] * h1[i];
-                acc = acc + p;
-            }
+            for (int i = 0; i < kNHid; i++) acc = __builtin_fmaf(P[kPW2 + kNHid * j + i], h1[i], acc);
             const float h = acc > 0.0f ? acc : 0.0f;
-            const float p0 = P[kPW3 + j] * h, p1 = P[kPW3 + kNHid + j] * h, p2 = P[kPW3 + 2 * kNHid + j] * h;
-            y0 = y0 + p0;
-            y1 = y1 + p1;
-            y2 = y2 + p2;
+            y0 = __builtin_fmaf(P[kPW3 + j], h, y0);
+            y1 = __builtin_fmaf(P[kPW3 + kNHid + j], h, y1);
+            y2 = __builtin_fmaf(P[kPW3 + 2 * kNHid + j], h, y2);
         }
         uint32_t best = 0;
         float bv = y0;
@@ -385,9 +424,16 @@ void launch_features(hipStream_t st, int grid, const float* x, const Geom& g, ui
                      Misc* misc, float* feat) {
     const uint32_t ntiles = feature_tiles(g.nblocks);
     if ((uint32_t)grid > ntiles) grid = (int)ntiles;
-    if (g.ndim == 3) hipLaunchKernelGGL(k_features<3>, dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, ntiles, feat);
-    else if (g.ndim == 2) hipLaunchKernelGGL(k_features<2>, dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, ntiles, feat);
-    else hipLaunchKernelGGL(k_features<1>, dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, ntiles, feat);
+    // partial x rows exist only when the x extent is not a multiple of the
+    // block's
+    const bool xrag = (g.n[0] % g.bs[0]) != 0;
+#define FZ_FEAT(NDV, XR)                                                                                  \
+    hipLaunchKernelGGL((k_features<NDV, XR>), dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, ntiles, \
+                       feat)
+    if (g.ndim == 3) { if (xrag) FZ_FEAT(3, true); else FZ_FEAT(3, false); }
+    else if (g.ndim == 2) { if (xrag) FZ_FEAT(2, true); else FZ_FEAT(2, false); }
+    else { if (xrag) FZ_FEAT(1, true); else FZ_FEAT(1, false); }
+#undef FZ_FEAT
 }
 
 void launch_mlp(hipStream_t st, int grid, const float* feat, uint32_t n, const float* sel, float* yout,

@@ -21,6 +21,9 @@ SHAPES = [
     ("3d-wide", (16, 24, 24), "wide", 1e-3, 1),
     ("3d-abs", (40, 33, 17), "grf", 2e-4, 0),
     ("2d-ragged", (301, 777), "grf", 1e-3, 1),
+    # x a multiple of the block, y/z not: whole rows, empty segments
+    ("3d-yz-ragged", (21, 30, 48), "grf", 1e-3, 1),
+    ("2d-y-ragged", (45, 96), "grf", 1e-3, 1),
     ("1d", (100003,), "positions", 1e-4, 1),
     ("1d-tiny", (5,), "grf", 1e-2, 1),
 ]

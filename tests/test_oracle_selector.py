@@ -167,6 +167,28 @@ def test_mlp_standardisation_and_relu():
     assert ch.tolist() == [1, 0]
 
 
+def test_mlp_terms_are_fused_multiply_adds():
+    """Each term of a dot product is one fused multiply-add: with z = w =
+    1 + 2^-12 and bias -1, w z + b = 2^-11 + 2^-24 exactly (representable),
+    where a separately rounded product (1 + 2^-11, the tie to even) would
+    give 2^-11.  Passed through identity rows of layers 2 and 3."""
+    a = 1.0 + 2.0 ** -12
+    W1 = np.zeros((64, 16))
+    W1[0, 0] = a
+    W2 = np.zeros((64, 64))
+    W2[0, 0] = 1.0
+    W3 = np.zeros((3, 64))
+    W3[1, 0] = 1.0
+    b1 = np.zeros(64)
+    b1[0] = -1.0
+    w = oracle.pack_params(mu=np.zeros(16), rs=np.ones(16), W1=W1, b1=b1, W2=W2, W3=W3, b3=(0.5, 0, 0.5))
+    feat = np.zeros((1, 16), np.float32)
+    feat[0, 0] = a
+    y, ch = oracle.mlp_infer(w, feat)
+    assert y[0, 1] == np.float32(2.0 ** -11 + 2.0 ** -24)
+    assert y[0, 0] == 0.5 and y[0, 2] == 0.5 and ch[0] == 1
+
+
 def _random_net(seed):
     r = np.random.default_rng(seed)
     w = r.normal(0, 0.3, oracle.NPARAM)
