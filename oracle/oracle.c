@@ -7,8 +7,8 @@
  * generator with the HIP implementation: every step is written out here
  * again, slowly and plainly, in the order the method defines it.
  *
- * What it computes (FZModules, Sec. 3.1 "cuSZ Design", Sec. 3.2 "Modularity",
- * Sec. 3.3 pipeline "FZMod-Default"; Sec. 4.2 "Evaluation Metrics"):
+ * What it computes (FZModules: Sec. 3.1 the cuSZ design, Sec. 3.2 the module
+ * interfaces, Sec. 3.3 the FZMod-Default pipeline, Sec. 4.2 the metrics):
  *   1. error-bound resolution: absolute, or value-range relative
  *      (Sec. 3.2: the relative mode needs the data minimum and maximum);
  *   2. prequantisation of every value onto the grid of step 2*eb
@@ -16,11 +16,11 @@
  *   3. block-local first-order Lorenzo prediction on the integer grid,
  *      residual = backward difference along every axis (Sec. 3.1, 3.2);
  *   4. post-quantisation: residuals inside the radius become integer codes,
- *      the rest are stored as outliers (Sec. 3.1 "saves data as outliers
- *      if they are unpredictable"; Sec. 3.3.1 outlier handling);
+ *      the rest are stored as outliers (Sec. 3.1: unpredictable values are
+ *      kept as outliers; Sec. 3.3.1 outlier handling);
  *   5. a histogram of the codes (Sec. 3.2: the Huffman encoder needs it);
  *   6. a length-limited minimum-redundancy (Huffman) code built from the
- *      histogram, in canonical form (Sec. 3.2 "optimal compression ratio");
+ *      histogram, in canonical form (Sec. 3.2: Huffman for the best ratio);
  *   7. chunked Huffman encoding, one chunk per block (Sec. 3.3);
  *   8. the container; decoding, outlier scatter and inverse Lorenzo
  *      (prefix sums) with dequantisation (Sec. 1 and Sec. 3.3.1 describe
