@@ -107,7 +107,7 @@ def main():
     ap.add_argument("--fields", type=int, default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see the design notes on sharding)",
+        print("bench.py measures one GPU: the library has no multi-GPU path (sharding is a design note only)",
               file=sys.stderr)
         sys.exit(2)
 
