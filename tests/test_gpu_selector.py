@@ -105,6 +105,42 @@ def test_trial_choices_and_costs(fz, ctx, name, shape, kind, eb, mode):
     assert np.array_equal(ch.cpu().numpy(), cho)
 
 
+def test_selector_full_1024cubed(fz, ctx):
+    """The selector workload at its full size and in the launch configuration
+    the benchmark times (1024^3 fronts + spikes field, rel 1e-4): features and
+    network outputs of 512 sampled blocks (the first and last among them)
+    against the oracle block by block.  Features are block-local, so each
+    sampled 8^3 block goes through the oracle alone at the field's absolute
+    bound (resolved by the oracle from the whole field)."""
+    from inputs import fields_gpu
+    n, eb = 1024, 1e-4
+    print(f"[gpu selector] full {n}^3 fronts/spikes rel {eb}", flush=True)
+    x = fields_gpu.fronts_spikes((n, n, n), seed=3, device="cuda")
+    w = random_selector(n)
+    ctx.selector_set(w)
+    f = ctx.block_features(x, eb, 1)
+    ch, y = ctx.block_select(x, eb, 1)
+    nb = n // 8
+    picks = np.unique(np.concatenate([[0, nb ** 3 - 1], np.random.default_rng(11).choice(nb ** 3, 510, replace=False)]))
+    f = f[torch.from_numpy(picks).cuda()].cpu().numpy()
+    y = y[torch.from_numpy(picks).cuda()].cpu().numpy()
+    ch = ch[torch.from_numpy(picks).cuda()].cpu().numpy()
+    xh = x.cpu().numpy()
+    del x
+    e = oracle.eb_abs(xh, 1, eb)
+    fo = np.empty((picks.size, 16), np.float32)
+    for k, b in enumerate(picks):
+        bz, by, bx = b // (nb * nb), (b // nb) % nb, b % nb
+        blk = np.ascontiguousarray(xh[8 * bz:8 * bz + 8, 8 * by:8 * by + 8, 8 * bx:8 * bx + 8])
+        fo[k] = oracle.features(blk, e, 0)[0]
+    del xh
+    bad = np.nonzero(f.view(np.uint32) != fo.view(np.uint32))
+    assert bad[0].size == 0, f"{bad[0].size} features differ, first block {picks[bad[0][0]]} feature {bad[1][0]}"
+    yo, cho = oracle.mlp_infer(w, fo)
+    assert np.array_equal(y.view(np.uint32), yo.view(np.uint32)), "predictions differ"
+    assert np.array_equal(ch, cho), "choices differ"
+
+
 def test_selector_file_round_trip(fz, ctx):
     w = random_selector(99)
     ctx.selector_set(w)
