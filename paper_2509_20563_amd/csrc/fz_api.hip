@@ -1014,7 +1014,7 @@ void key_scratch(std::vector<uint8_t>& k, const fz_ctx* c) {
     const void* ps[] = {c->misc, c->hist, c->cw, c->lut, c->codes, c->ostage, c->pstage,
                         c->tile_cnt, c->tile_off, c->tile_start, c->tfirst, c->tlast, c->desc_cnt,
                         c->desc_bits, c->desc_chunks, c->off, c->oidx, c->bpred, c->reg_idx, c->coef, c->costs,
-                        c->cw_ref, c->lens_ref, c->desc_pmap, c->res, c->sel};
+                        c->cw_ref, c->lens_ref, c->desc_pmap, c->res, c->sel, c->featb};
     for (const void* q : ps) key_put(k, q);
 }
 
@@ -1089,6 +1089,9 @@ int batch_compress_run(fz_ctx* c, const BatchIn& b, uint8_t* d_out, hipStream_t 
     key_put(key, d_out);
     key_put(key, c->stage);
     key_put(key, c->rec);
+    key_put(key, c->offs);
+    key_put(key, c->h_rec);
+    key_put(key, c->h_offs);
     for (uint32_t i = 0; i < n; i++) {
         key_put(key, b.p[i]);
         key_put(key, b.x[i]);
@@ -1286,6 +1289,8 @@ int fz_decompress_batch(fz_ctx* c, uint32_t n, const void* d_in, const uint64_t*
     key_put(key, n);
     key_put(key, K);
     key_put(key, d_in);
+    key_put(key, c->rec);
+    key_put(key, c->h_rec);
     key.insert(key.end(), c->h_hdrs, c->h_hdrs + (uint64_t)kHdr * n);
     for (uint32_t i = 0; i < n; i++) {
         key_put(key, h_offsets[i]);
