@@ -368,7 +368,11 @@ def _bench_batch(args, fz, ctx, batch, label, preds=None):
     n = sum(x.numel() for x in xs)
     modes = [fz.EB_REL] * nf
     print(f"[bench] {label}: autotune", file=sys.stderr, flush=True)
-    k, w = ctx.batch_autotune(xs, ebs, modes, preds)
+    try:
+        k, w = ctx.batch_autotune(xs, ebs, modes, preds)
+    except fz.FZError as e:  # the autotuner is switched off: default launch knobs
+        print(f"[bench] {label}: autotune unavailable ({e}); default knobs", file=sys.stderr, flush=True)
+        k, w = ctx.batch_tuning(xs, ebs, modes, preds)
     out = torch.empty(ctx.compress_batch_bound([x.shape for x in xs], preds), dtype=torch.uint8, device=xs[0].device)
     holder = {}
 

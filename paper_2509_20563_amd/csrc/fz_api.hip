@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <new>
 #include <vector>
@@ -20,10 +21,15 @@ namespace {
 
 constexpr int kMaxStages = 16;
 
+// A buffer a context replaces is retired, not freed: a captured batch graph
+// may still reference it (freeing memory a live graph references and then
+// destroying or replaying that graph is a use after free in the runtime).
+void retire(fz_ctx* c, void* p, bool host);
+
 template <class T>
-hipError_t grow(T*& p, uint64_t& cap, uint64_t need) {
+hipError_t grow(fz_ctx* c, T*& p, uint64_t& cap, uint64_t need) {
     if (need <= cap && p) return hipSuccess;
-    if (p) hipFree(p);
+    retire(c, p, false);
     p = nullptr;
     cap = 0;
     hipError_t e = hipMalloc((void**)&p, sizeof(T) * (need ? need : 1));
@@ -34,19 +40,30 @@ hipError_t grow(T*& p, uint64_t& cap, uint64_t need) {
 // Launch configuration knobs that leave the output unchanged (the tile
 // assignment is static, so any grid gives the same container).
 constexpr int kMaxChains = 16;
+constexpr bool kAutotuneOff = true;
 
 // A captured batch: replayed while the batch's description is unchanged.
 struct GraphCache {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<uint8_t> key;
+    uint64_t at = 0;  // capture epoch of the owning context
     void drop() {
         if (exec) hipGraphExecDestroy(exec);
         if (graph) hipGraphDestroy(graph);
         exec = nullptr;
         graph = nullptr;
         key.clear();
+        at = 0;
     }
+};
+
+// A retired buffer and the owning context's capture epoch when it was
+// retired: graphs captured at or before that epoch may reference it.
+struct DeadBuf {
+    void* p;
+    bool host;
+    uint64_t r;
 };
 
 struct Tune {
@@ -142,9 +159,56 @@ struct fz_ctx {
     GraphCache gc, gd;              // compress / decompress batches
     std::map<uint32_t, Tune> tune_field;   // per field class
     std::map<uint32_t, uint32_t> tune_chains;  // per batch class
+    // graph bookkeeping: a chain context's root is the context whose graphs
+    // use its scratch; the root counts captures and keeps the buffers it or
+    // its chains replaced while a graph could still reference them
+    fz_ctx* root = nullptr;
+    uint64_t epoch = 0;
+    std::vector<DeadBuf> dead;
 };
 
 namespace {
+
+fz_ctx* root_of(fz_ctx* c) { return c->root ? c->root : c; }
+
+void free_buf(void* p, bool host) {
+    if (host) hipHostFree(p);
+    else hipFree(p);
+}
+
+// Free the retired buffers that no live graph can reference: those retired
+// after the capture of every live graph.
+void sweep(fz_ctx* r) {
+    uint64_t m = ~0ull;
+    if (r->gc.exec) m = std::min(m, r->gc.at);
+    if (r->gd.exec) m = std::min(m, r->gd.at);
+    size_t k = 0;
+    for (const DeadBuf& d : r->dead) {
+        if (d.r < m) free_buf(d.p, d.host);
+        else r->dead[k++] = d;
+    }
+    r->dead.resize(k);
+}
+
+void retire(fz_ctx* c, void* p, bool host) {
+    if (!p) return;
+    fz_ctx* r = root_of(c);
+    if (!r->gc.exec && !r->gd.exec) {
+        free_buf(p, host);
+        return;
+    }
+    r->dead.push_back(DeadBuf{p, host, r->epoch});
+}
+
+void drop_graph(fz_ctx* c, GraphCache& g) {
+    g.drop();
+    sweep(c);
+}
+
+void captured(fz_ctx* c, GraphCache& g) {
+    g.at = ++c->epoch;
+    sweep(c);
+}
 
 struct DeviceGuard {
     int prev = -1;
@@ -213,19 +277,19 @@ int ensure(fz_ctx* c, const Geom& g) {
     const uint64_t sd_tiles = scan_tiles((uint32_t)ntiles);
     const uint64_t sd_blocks = scan_tiles((uint32_t)nb);
     hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = grow(c->codes, c->codes_cap, nb * kBlockElems);
-    if (e == hipSuccess) e = grow(c->ostage, c->ostage_cap, slots);
-    if (e == hipSuccess) e = grow(c->pstage, c->pstage_cap, slots);
-    if (e == hipSuccess) e = grow(c->tile_cnt, c->tile_cnt_cap, ntiles);
-    if (e == hipSuccess) e = grow(c->tile_off, c->tile_off_cap, ntiles);
-    if (e == hipSuccess) e = grow(c->tile_start, c->tile_start_cap, ntiles);
-    if (e == hipSuccess) e = grow(c->tfirst, c->tfirst_cap, ntiles);
-    if (e == hipSuccess) e = grow(c->tlast, c->tlast_cap, ntiles);
-    if (e == hipSuccess) e = grow(c->desc_cnt, c->desc_cnt_cap, sd_tiles);
-    if (e == hipSuccess) e = grow(c->desc_bits, c->desc_bits_cap, encode_groups((uint32_t)ntiles));
-    if (e == hipSuccess) e = grow(c->desc_chunks, c->desc_chunks_cap, sd_blocks);
-    if (e == hipSuccess) e = grow(c->off, c->off_cap, nb);
-    if (e == hipSuccess) e = grow(c->oidx, c->oidx_cap, nb);
+    if (e == hipSuccess) e = grow(c, c->codes, c->codes_cap, nb * kBlockElems);
+    if (e == hipSuccess) e = grow(c, c->ostage, c->ostage_cap, slots);
+    if (e == hipSuccess) e = grow(c, c->pstage, c->pstage_cap, slots);
+    if (e == hipSuccess) e = grow(c, c->tile_cnt, c->tile_cnt_cap, ntiles);
+    if (e == hipSuccess) e = grow(c, c->tile_off, c->tile_off_cap, ntiles);
+    if (e == hipSuccess) e = grow(c, c->tile_start, c->tile_start_cap, ntiles);
+    if (e == hipSuccess) e = grow(c, c->tfirst, c->tfirst_cap, ntiles);
+    if (e == hipSuccess) e = grow(c, c->tlast, c->tlast_cap, ntiles);
+    if (e == hipSuccess) e = grow(c, c->desc_cnt, c->desc_cnt_cap, sd_tiles);
+    if (e == hipSuccess) e = grow(c, c->desc_bits, c->desc_bits_cap, encode_groups((uint32_t)ntiles));
+    if (e == hipSuccess) e = grow(c, c->desc_chunks, c->desc_chunks_cap, sd_blocks);
+    if (e == hipSuccess) e = grow(c, c->off, c->off_cap, nb);
+    if (e == hipSuccess) e = grow(c, c->oidx, c->oidx_cap, nb);
     return e == hipSuccess ? FZ_OK : FZ_ERR_NOMEM;
 }
 
@@ -233,12 +297,12 @@ int ensure(fz_ctx* c, const Geom& g) {
 int ensure_pred(fz_ctx* c, const Geom& g, bool decode) {
     const uint64_t nb = g.nblocks;
     hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = grow(c->bpred, c->bpred_cap, nb);
-    if (e == hipSuccess) e = grow(c->reg_idx, c->reg_idx_cap, nb);
-    if (e == hipSuccess) e = grow(c->coef, c->coef_cap, 4 * nb);
-    if (e == hipSuccess) e = grow(c->costs, c->costs_cap, 3 * nb);
-    if (e == hipSuccess) e = grow(c->desc_pmap, c->desc_pmap_cap, scan_tiles((uint32_t)nb));
-    if (e == hipSuccess && decode) e = grow(c->res, c->res_cap, nb * kBlockElems);
+    if (e == hipSuccess) e = grow(c, c->bpred, c->bpred_cap, nb);
+    if (e == hipSuccess) e = grow(c, c->reg_idx, c->reg_idx_cap, nb);
+    if (e == hipSuccess) e = grow(c, c->coef, c->coef_cap, 4 * nb);
+    if (e == hipSuccess) e = grow(c, c->costs, c->costs_cap, 3 * nb);
+    if (e == hipSuccess) e = grow(c, c->desc_pmap, c->desc_pmap_cap, scan_tiles((uint32_t)nb));
+    if (e == hipSuccess && decode) e = grow(c, c->res, c->res_cap, nb * kBlockElems);
     return e == hipSuccess ? FZ_OK : FZ_ERR_NOMEM;
 }
 
@@ -371,7 +435,7 @@ int compress_prepare(fz_ctx* c, const fz_params* p, const Geom& g) {
     int rc = ensure(c, g);
     if (rc == FZ_OK && p->pred != FZ_PRED_LORENZO1) rc = ensure_pred(c, g, false);
     if (rc == FZ_OK && p->pred == FZ_PRED_AUTO_MLP &&
-        grow(c->featb, c->featb_cap, (uint64_t)g.nblocks * kNFeat) != hipSuccess)
+        grow(c, c->featb, c->featb_cap, (uint64_t)g.nblocks * kNFeat) != hipSuccess)
         rc = FZ_ERR_NOMEM;
     return rc;
 }
@@ -550,6 +614,11 @@ int fz_ctx_create(fz_ctx** out, int device, uint64_t max_elems) {
 void fz_ctx_destroy(fz_ctx* c) {
     if (!c) return;
     DeviceGuard dg(c->device);
+    // the graphs go first: they reference the buffers freed below
+    c->gc.drop();
+    c->gd.drop();
+    for (const DeadBuf& d : c->dead) free_buf(d.p, d.host);
+    c->dead.clear();
     hipFree(c->misc);
     hipFree(c->hist);
     hipFree(c->cw);
@@ -575,8 +644,6 @@ void fz_ctx_destroy(fz_ctx* c) {
     hipFree(c->cw_ref);
     hipFree(c->lens_ref);
     hipFree(c->sel);
-    c->gc.drop();
-    c->gd.drop();
     for (int k = 0; k < c->nkids; k++) {
         fz_ctx_destroy(c->kids[k]);
         if (c->kstream[k]) hipStreamDestroy(c->kstream[k]);
@@ -745,7 +812,7 @@ int fz_block_select(fz_ctx* c, const fz_params* p, const float* d_in, uint8_t* d
     hipStream_t st = (hipStream_t)stream;
     int rc = analysis_begin(c, p, d_in, st, &g, &vec, &ntiles, &grid);
     if (rc) return rc;
-    if (grow(c->featb, c->featb_cap, (uint64_t)g.nblocks * kNFeat) != hipSuccess) return FZ_ERR_NOMEM;
+    if (grow(c, c->featb, c->featb_cap, (uint64_t)g.nblocks * kNFeat) != hipSuccess) return FZ_ERR_NOMEM;
     launch_features(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->featb);
     launch_mlp(st, grid, c->featb, g.nblocks, c->sel, d_y, d_choice);
     t_mark(c, st, "select");
@@ -939,9 +1006,9 @@ int fz_selector_grad(fz_ctx* c, const float* d_feat, const float* d_target, uint
 
 namespace {
 
-hipError_t grow_pinned(void** p, uint64_t& cap, uint64_t need) {
+hipError_t grow_pinned(fz_ctx* c, void** p, uint64_t& cap, uint64_t need) {
     if (need <= cap && *p) return hipSuccess;
-    if (*p) hipHostFree(*p);
+    retire(c, *p, true);
     *p = nullptr;
     cap = 0;
     hipError_t e = hipHostMalloc(p, need ? need : 1, hipHostMallocDefault);
@@ -975,6 +1042,7 @@ int ensure_kids(fz_ctx* c, int k) {
             fz_ctx_destroy(kid);
             return FZ_ERR_HIP;
         }
+        kid->root = c;
         c->kids[c->nkids++] = kid;
     }
     return FZ_OK;
@@ -1062,11 +1130,11 @@ int batch_compress_run(fz_ctx* c, const BatchIn& b, uint8_t* d_out, hipStream_t 
     const uint32_t n = b.n;
     int rc = ensure_kids(c, K);
     if (rc) return rc;
-    hipError_t e = grow(c->stage, c->stage_cap, b.slot[n]);
-    if (e == hipSuccess) e = grow(c->rec, c->rec_cap, 5ull * n);
-    if (e == hipSuccess) e = grow(c->offs, c->offs_cap, (uint64_t)n + 1);
-    if (e == hipSuccess) e = grow_pinned((void**)&c->h_rec, c->h_rec_cap, 40ull * n);
-    if (e == hipSuccess) e = grow_pinned((void**)&c->h_offs, c->h_offs_cap, 8ull * (n + 1));
+    hipError_t e = grow(c, c->stage, c->stage_cap, b.slot[n]);
+    if (e == hipSuccess) e = grow(c, c->rec, c->rec_cap, 5ull * n);
+    if (e == hipSuccess) e = grow(c, c->offs, c->offs_cap, (uint64_t)n + 1);
+    if (e == hipSuccess) e = grow_pinned(c, (void**)&c->h_rec, c->h_rec_cap, 40ull * n);
+    if (e == hipSuccess) e = grow_pinned(c, (void**)&c->h_offs, c->h_offs_cap, 8ull * (n + 1));
     if (e != hipSuccess) return FZ_ERR_NOMEM;
     const auto chains = assign_chains(n, b.g, K);
     bool need_sel = false;
@@ -1099,7 +1167,7 @@ int batch_compress_run(fz_ctx* c, const BatchIn& b, uint8_t* d_out, hipStream_t 
     }
     for (int k = 0; k < K; k++) key_scratch(key, c->kids[k]);  // scratch may have moved
     if (key != c->gc.key || !c->gc.exec) {
-        c->gc.drop();
+        drop_graph(c, c->gc);
         hipStream_t cs = c->cstream;
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return FZ_ERR_HIP;
         hipEventRecord(c->kev[kMaxChains], cs);
@@ -1124,10 +1192,11 @@ int batch_compress_run(fz_ctx* c, const BatchIn& b, uint8_t* d_out, hipStream_t 
         }
         c->gc.graph = graph;
         if (hipGraphInstantiate(&c->gc.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-            c->gc.drop();
+            drop_graph(c, c->gc);
             return FZ_ERR_HIP;
         }
         c->gc.key = key;
+        captured(c, c->gc);
     }
     if (hipGraphLaunch(c->gc.exec, st) != hipSuccess) return FZ_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
@@ -1177,6 +1246,10 @@ int fz_compress_batch(fz_ctx* c, uint32_t n, const fz_params* p, const float* co
 int fz_batch_autotune(fz_ctx* c, uint32_t n, const fz_params* p, const float* const* d_in, void* d_out,
                       uint64_t out_cap, void* stream) {
     if (!c || !n || !p || !d_in || !d_out || ((uintptr_t)d_out & 15)) return FZ_ERR_ARG;
+    // switched off: a run of the autotuner over twelve launch configurations
+    // ended in a host segmentation fault whose cause is not found yet; the
+    // batch calls use the default knobs meanwhile
+    if (kAutotuneOff) return FZ_ERR_UNSUPPORTED;
     BatchIn b;
     int rc = batch_check(c, n, p, d_in, &b);
     if (rc) return rc;
@@ -1251,12 +1324,12 @@ int fz_decompress_batch(fz_ctx* c, uint32_t n, const void* d_in, const uint64_t*
     DeviceGuard dg(c->device);
     hipStream_t st = (hipStream_t)stream;
     const uint8_t* in = (const uint8_t*)d_in;
-    hipError_t e = grow(c->offs, c->offs_cap, (uint64_t)n + 1);
-    if (e == hipSuccess) e = grow(c->hdrs, c->hdrs_cap, (uint64_t)kHdr * n);
-    if (e == hipSuccess) e = grow(c->rec, c->rec_cap, 5ull * n);
-    if (e == hipSuccess) e = grow_pinned((void**)&c->h_hdrs, c->h_hdrs_cap, (uint64_t)kHdr * n);
-    if (e == hipSuccess) e = grow_pinned((void**)&c->h_offs, c->h_offs_cap, 8ull * (n + 1));
-    if (e == hipSuccess) e = grow_pinned((void**)&c->h_rec, c->h_rec_cap, 40ull * n);
+    hipError_t e = grow(c, c->offs, c->offs_cap, (uint64_t)n + 1);
+    if (e == hipSuccess) e = grow(c, c->hdrs, c->hdrs_cap, (uint64_t)kHdr * n);
+    if (e == hipSuccess) e = grow(c, c->rec, c->rec_cap, 5ull * n);
+    if (e == hipSuccess) e = grow_pinned(c, (void**)&c->h_hdrs, c->h_hdrs_cap, (uint64_t)kHdr * n);
+    if (e == hipSuccess) e = grow_pinned(c, (void**)&c->h_offs, c->h_offs_cap, 8ull * (n + 1));
+    if (e == hipSuccess) e = grow_pinned(c, (void**)&c->h_rec, c->h_rec_cap, 40ull * n);
     if (e != hipSuccess) return FZ_ERR_NOMEM;
     // headers: one gather, one copy, one synchronisation
     for (uint32_t i = 0; i <= n; i++) c->h_offs[i] = h_offsets[i];
@@ -1298,7 +1371,7 @@ int fz_decompress_batch(fz_ctx* c, uint32_t n, const void* d_in, const uint64_t*
     }
     for (int k = 0; k < K; k++) key_scratch(key, c->kids[k]);
     if (key != c->gd.key || !c->gd.exec) {
-        c->gd.drop();
+        drop_graph(c, c->gd);
         hipStream_t cs = c->cstream;
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return FZ_ERR_HIP;
         hipEventRecord(c->kev[kMaxChains], cs);
@@ -1320,10 +1393,11 @@ int fz_decompress_batch(fz_ctx* c, uint32_t n, const void* d_in, const uint64_t*
         }
         c->gd.graph = graph;
         if (hipGraphInstantiate(&c->gd.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-            c->gd.drop();
+            drop_graph(c, c->gd);
             return FZ_ERR_HIP;
         }
         c->gd.key = key;
+        captured(c, c->gd);
     }
     if (hipGraphLaunch(c->gd.exec, st) != hipSuccess) return FZ_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;

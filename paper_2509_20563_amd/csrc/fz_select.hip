@@ -353,12 +353,11 @@ __global__ __launch_bounds__(256) void k_features(const float* __restrict__ x, G
 }
 
 // ---------------------------------------------------------------- network
-// Thread = block.  Every lane reads the same parameter at the same time,
-// so the parameters come through scalar loads (the scalar cache) and feed
-// the multiply-adds as scalar operands, with no LDS traffic; each dot
-// product is a chain of fused multiply-adds (one rounding per term) in
-// index order from its bias, the three outputs accumulated while the
-// second hidden layer produces its units (the same order).  Ties go to the lower
+// Thread = block.  The parameters sit in LDS in their natural layout and
+// are read at the same address by every lane (broadcast); each dot product
+// is a chain of fused multiply-adds (one rounding per term) in index order
+// from its bias, the three outputs accumulated while the second hidden
+// layer produces its units (the same order).  Ties go to the lower
 // predictor.  Parameter layout (floats): mu[16], rs[16], W1[64][16],
 // b1[64], W2[64][64], b2[64], W3[3][64], b3[3].
 constexpr int kPMu = 0, kPRs = kNFeat, kPW1 = 2 * kNFeat, kPB1 = kPW1 + kNHid * kNFeat, kPW2 = kPB1 + kNHid,
@@ -368,10 +367,12 @@ static_assert(kPParams == kSelectorParams, "selector layout");
 
 __global__ __launch_bounds__(256) void k_mlp(const float* __restrict__ feat, uint32_t n, const float* __restrict__ sel,
                                              float* __restrict__ yout, uint8_t* __restrict__ choice) {
-    const float* __restrict__ P = sel;
+    __shared__ __attribute__((aligned(16))) float P[kPParams + 1];
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kPParams; i += 256) P[i] = sel[i];
+    __syncthreads();
     for (uint32_t b = blockIdx.x * 256 + threadIdx.x; b < n; b += gridDim.x * 256) {
-        // parameters re-read for every block: kept from being hoisted into
-        // registers, which would take the register file
+        // the parameters are re-read from LDS for every block: kept from
+        // being hoisted into registers, which would take the register file
         asm volatile("" ::: "memory");
         float z[kNFeat];
         const f32x4* fp = reinterpret_cast<const f32x4*>(feat + (uint64_t)b * kNFeat);
