@@ -142,6 +142,14 @@ int fz_set_timing(fz_ctx *ctx, int enable);
 int fz_stage_times(fz_ctx *ctx, float *h_ms, int max, int *n);
 const char *fz_stage_name(fz_ctx *ctx, int i);
 
+/* Restrict the timing to one stage: with `stage` set (a stage name as
+ * fz_stage_name gives it, shorter than 32 bytes; the string is copied),
+ * calls record one event just before that stage and one after it, and
+ * fz_stage_times returns that stage alone (0 stages for a call without it);
+ * every other stage runs without events in between.  NULL restores timing
+ * of every stage.  FZ_ERR_ARG for a name of 32 bytes or more. */
+int fz_set_timing_stage(fz_ctx *ctx, const char *stage);
+
 /* Stage dump for parity checks: the 1024-bin code histogram of the last
  * successful fz_compress call on this context (Sec. 3.2). */
 int fz_last_histogram(fz_ctx *ctx, uint32_t *h_hist);

@@ -122,8 +122,9 @@ struct fz_ctx {
     // block features of the learned selector ([nblocks][16] float)
     float* featb = nullptr;
     uint64_t featb_cap = 0;
-    // timing
+    // timing (tstage: the one stage timed, empty = every stage)
     bool timing = false;
+    char tstage[32] = {};
     hipEvent_t ev[kMaxStages + 1] = {};
     int nev = 0;
     const char* names[kMaxStages] = {};
@@ -307,22 +308,30 @@ int ensure_pred(fz_ctx* c, const Geom& g, bool decode) {
 }
 
 // Stage timing helpers (events on the call's stream).
+// Every stage is timed (an event after each), or, with a stage filter set,
+// only the named stage (one event just before it, one after it).
 void t_begin(fz_ctx* c, hipStream_t st) {
     c->nev = 0;
     c->nstages = 0;
-    if (!c->timing) return;
+    if (!c->timing || c->tstage[0]) return;
+    hipEventRecord(c->ev[0], st);
+    c->nev = 1;
+}
+void t_start(fz_ctx* c, hipStream_t st, const char* name) {
+    if (!c->timing || !c->tstage[0] || c->nev != 0 || strcmp(name, c->tstage) != 0) return;
     hipEventRecord(c->ev[0], st);
     c->nev = 1;
 }
 void t_mark(fz_ctx* c, hipStream_t st, const char* name) {
     if (!c->timing || c->nev > kMaxStages) return;
+    if (c->tstage[0] && (c->nev != 1 || strcmp(name, c->tstage) != 0)) return;
     hipEventRecord(c->ev[c->nev], st);
     c->names[c->nev - 1] = name;
     c->nev++;
 }
 void t_end(fz_ctx* c) {
     if (!c->timing) return;
-    c->nstages = c->nev - 1;
+    c->nstages = c->nev > 0 ? c->nev - 1 : 0;
     for (int i = 0; i < c->nstages; i++) {
         float m = 0.0f;
         hipEventElapsedTime(&m, c->ev[i], c->ev[i + 1]);
@@ -448,6 +457,9 @@ void compress_enqueue(fz_ctx* c, const fz_params* p, const Geom& g, const float*
     auto mark = [&](const char* name) {
         if (marks) t_mark(c, st, name);
     };
+    auto start = [&](const char* name) {
+        if (marks) t_start(c, st, name);
+    };
     const uint32_t pred = p->pred;
     const bool has_map = pred_has_map(pred);
     const uint32_t ntiles = (g.nblocks + kTileBlocks - 1) / kTileBlocks;
@@ -460,17 +472,20 @@ void compress_enqueue(fz_ctx* c, const fz_params* p, const Geom& g, const float*
     const uint64_t nreg_fixed = pred == FZ_PRED_REGRESSION ? g.nblocks : 0;
     const Layout L0 = make_layout(g.nblocks, has_map, nreg_fixed, 0, 0, 0);
     const uint32_t sd_blocks = has_map ? scan_tiles(g.nblocks) : 0;
+    start("reset");
     launch_reset(st, c->misc, c->hist, c->desc_cnt, sd_tiles, c->desc_bits, encode_groups(ntiles), c->desc_pmap,
                  sd_blocks,
                  L0.chunks, L0.stream, nreg_fixed);
     mark("reset");
     if (p->eb_mode == FZ_EB_REL) {
+        start("minmax");
         launch_minmax(st, d_in, g.N, (((uintptr_t)d_in & 15) == 0), c->misc, minmax_grid(c, g.N, tn.mm_wg_per_cu));
         mark("minmax");
     }
     if (pred == FZ_PRED_AUTO_TRIAL) {
         // reference code: the Huffman code of the first-order Lorenzo
         // histogram; then every block tries the three predictors
+        start("trial");
         launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt,
                      c->ostage, c->pstage, 0, nullptr, nullptr);
         launch_codebook(st, c->hist, c->lens_ref, c->cw_ref, c->misc);
@@ -481,10 +496,12 @@ void compress_enqueue(fz_ctx* c, const fz_params* p, const Geom& g, const float*
     if (pred == FZ_PRED_AUTO_MLP) {
         // the network chooses each block's predictor from the features of
         // the block's sample (a pass over a quarter of the field)
+        start("select");
         launch_features(st, (int)gmax, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->featb);
         launch_mlp(st, (int)gmax, c->featb, g.nblocks, c->sel, nullptr, c->bpred);
         mark("select");
     }
+    start("quant");
     {
         const int fixed = has_map ? -1 : (int)pred;
         launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt,
@@ -492,16 +509,21 @@ void compress_enqueue(fz_ctx* c, const fz_params* p, const Geom& g, const float*
     }
     mark("quant");
     if (has_map) {
+        start("scan_map");
         launch_scan(st, SCAN_PMAP, c->bpred, g.nblocks, c->reg_idx, c->desc_pmap, &c->misc->mtile_ctr, c->misc, 0);
         mark("scan_map");
     }
+    start("scan_counts");
     launch_scan(st, SCAN_COUNTS, c->tile_cnt, ntiles, c->tile_off, c->desc_cnt, &c->misc->qtile_ctr, c->misc, 0);
     mark("scan_counts");
+    start("codebook");
     launch_codebook(st, c->hist, out + kHdr, c->cw, c->misc);
     mark("codebook");
+    start("encode");
     launch_encode(st, grid, c->codes, g, c->cw, c->misc, ntiles, out, c->desc_bits, c->tile_start, c->tfirst,
                   c->tlast);
     mark("encode");
+    start("finalize");
     launch_finalize(st, g, p->eb_mode, p->eb, pred, c->misc, out, ntiles, c->tile_start, c->tfirst, c->tlast,
                     c->tile_cnt, c->tile_off, c->ostage, c->pstage, c->bpred, c->reg_idx, c->coef, d_in);
     mark("finalize");
@@ -519,8 +541,12 @@ void decompress_enqueue(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_
     auto mark = [&](const char* name) {
         if (marks) t_mark(c, st, name);
     };
+    auto start = [&](const char* name) {
+        if (marks) t_start(c, st, name);
+    };
     const Geom& g = r.g;
     if (r.verbatim) {
+        start("copy");
         launch_copy(st, in + kHdr, d_out, g.N);
         mark("copy");
         return;
@@ -531,17 +557,22 @@ void decompress_enqueue(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_
     const uint32_t stiles = scan_tiles(g.nblocks);
     const int vec = (((uintptr_t)d_out & 15) == 0) && (g.ndim == 1 || (g.n[0] & 3) == 0);
     // the reset also clears the per-block outlier index
+    start("reset");
     launch_reset(st, c->misc, c->hist, c->desc_chunks, stiles, has_map ? c->desc_pmap : nullptr,
                  has_map ? stiles : 0, r.nout ? reinterpret_cast<uint64_t*>(c->oidx) : nullptr,
                  r.nout ? (uint32_t)g.nblocks : 0u, L.chunks, L.stream, r.nreg);
     mark("reset");
+    start("lut");
     launch_lut(st, in + L.lens, c->lut, c->misc);
     mark("lut");
+    start("scan");
     launch_scan(st, SCAN_CHUNKS, in + L.chunks, g.nblocks, c->off, c->desc_chunks, &c->misc->stile_ctr, c->misc,
                 r.bits);
     mark("scan");
+    start("oindex");
     launch_outlier_index(st, g, (const uint32_t*)(in + L.opos), r.nout, c->oidx, c->misc);
     mark("oindex");
+    start("decode");
     if (pred == FZ_PRED_LORENZO1) {
         launch_decode(st, g, (const uint32_t*)(in + L.stream), r.words, c->off, (const uint16_t*)(in + L.chunks),
                       c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->oidx,
@@ -558,6 +589,7 @@ void decompress_enqueue(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_
                            r.nreg, 2.0 * r.eb_abs, d_out, vec, c->misc);
     }
     mark("decode");
+    start("patch");
     launch_patch(st, g, (const uint32_t*)(in + L.ppos), (const uint32_t*)(in + L.pbits), r.npat, d_out, c->misc);
     mark("patch");
 }
@@ -796,6 +828,7 @@ int fz_block_features(fz_ctx* c, const fz_params* p, const float* d_in, float* d
     int rc = analysis_begin(c, p, d_in, st, &g, &vec, &ntiles, &grid);
     if (rc) return rc;
     if (feat_cap < (uint64_t)g.nblocks * kNFeat) return FZ_ERR_CAPACITY;
+    t_start(c, st, "features");
     launch_features(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, d_feat);
     t_mark(c, st, "features");
     return analysis_end(c, st);
@@ -813,6 +846,7 @@ int fz_block_select(fz_ctx* c, const fz_params* p, const float* d_in, uint8_t* d
     int rc = analysis_begin(c, p, d_in, st, &g, &vec, &ntiles, &grid);
     if (rc) return rc;
     if (grow(c, c->featb, c->featb_cap, (uint64_t)g.nblocks * kNFeat) != hipSuccess) return FZ_ERR_NOMEM;
+    t_start(c, st, "select");
     launch_features(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->featb);
     launch_mlp(st, grid, c->featb, g.nblocks, c->sel, d_y, d_choice);
     t_mark(c, st, "select");
@@ -829,6 +863,7 @@ int fz_block_trial(fz_ctx* c, const fz_params* p, const float* d_in, uint8_t* d_
     hipStream_t st = (hipStream_t)stream;
     int rc = analysis_begin(c, p, d_in, st, &g, &vec, &ntiles, &grid);
     if (rc) return rc;
+    t_start(c, st, "trial");
     launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt, c->ostage,
                  c->pstage, 0, nullptr, nullptr);
     launch_codebook(st, c->hist, c->lens_ref, c->cw_ref, c->misc);
@@ -1478,6 +1513,18 @@ const char* fz_strerror(int s) {
 int fz_set_timing(fz_ctx* c, int enable) {
     if (!c) return FZ_ERR_ARG;
     c->timing = enable != 0;
+    return FZ_OK;
+}
+
+int fz_set_timing_stage(fz_ctx* c, const char* stage) {
+    if (!c) return FZ_ERR_ARG;
+    if (!stage) {
+        c->tstage[0] = 0;
+        return FZ_OK;
+    }
+    const size_t n = strlen(stage);
+    if (n >= sizeof(c->tstage)) return FZ_ERR_ARG;
+    memcpy(c->tstage, stage, n + 1);
     return FZ_OK;
 }
 

@@ -77,6 +77,8 @@ def lib() -> ctypes.CDLL:
     L.fz_strerror.restype = ctypes.c_char_p
     L.fz_set_timing.argtypes = [vp, i32]
     L.fz_set_timing.restype = i32
+    L.fz_set_timing_stage.argtypes = [vp, ctypes.c_char_p]
+    L.fz_set_timing_stage.restype = i32
     L.fz_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)]
     L.fz_stage_times.restype = i32
     L.fz_stage_name.argtypes = [vp, i32]
@@ -247,6 +249,10 @@ class Context:
     # ------------------------------------------------------------ diagnostics
     def set_timing(self, on: bool = True):
         _check(lib().fz_set_timing(self._h, 1 if on else 0), "fz_set_timing")
+
+    def set_timing_stage(self, stage: str | None):
+        """Time only the named stage (None: every stage)."""
+        _check(lib().fz_set_timing_stage(self._h, None if stage is None else stage.encode()), "fz_set_timing_stage")
 
     def stage_times(self) -> list[tuple[str, float]]:
         ms = (ctypes.c_float * 16)()

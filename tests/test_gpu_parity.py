@@ -159,4 +159,19 @@ def test_stage_timing(fz, ctx):
     ctx.decompress(c)
     names = [n for n, _ in ctx.stage_times()]
     assert names == ["reset", "lut", "scan", "oindex", "decode", "patch"]
+    # one stage timed: an event before and after it, nothing for calls without it
+    ctx.set_timing_stage("decode")
+    c2 = ctx.compress(x, 1e-3, 1)
+    assert ctx.stage_times() == []
+    ctx.decompress(c2)
+    t = ctx.stage_times()
+    assert [n for n, _ in t] == ["decode"] and t[0][1] > 0
+    ctx.set_timing_stage("quant")
+    ctx.compress(x, 1e-3, 1)
+    assert [n for n, _ in ctx.stage_times()] == ["quant"]
+    with pytest.raises(fz.FZError):
+        ctx.set_timing_stage("x" * 32)
+    ctx.set_timing_stage(None)
+    ctx.compress(x, 1e-3, 1)
+    assert len(ctx.stage_times()) == 7
     ctx.set_timing(False)
