@@ -180,6 +180,9 @@ class Context:
         self.device = torch.device("cuda", int(device))
         h = ctypes.c_void_p()
         _check(lib().fz_ctx_create(ctypes.byref(h), int(device), int(max_elems)), "fz_ctx_create")
+        # marshalled arguments reused across calls (small caches)
+        self._pcache: dict = {}
+        self._hcache: dict = {}
         self._h = h
 
     def close(self):
@@ -206,11 +209,16 @@ class Context:
         """Compress a float32 device field; returns a uint8 device tensor (view of `out`)."""
         if x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous():
             raise ValueError("x must be a contiguous float32 device tensor")
-        p = params_for(x.shape, eb, mode, pred)
-        cap = self.compress_bound(x.shape)
-        if cap == 0:
-            raise FZError(-1, "fz_compress_bound")
+        key = (tuple(x.shape), float(eb), int(mode), int(pred))
+        p = self._pcache.get(key)
+        if p is None:
+            if len(self._pcache) > 256:
+                self._pcache.clear()
+            p = self._pcache[key] = params_for(x.shape, eb, mode, pred)
         if out is None:
+            cap = self.compress_bound(x.shape)
+            if cap == 0:
+                raise FZError(-1, "fz_compress_bound")
             out = torch.empty(cap, dtype=torch.uint8, device=x.device)
         n = ctypes.c_uint64(0)
         rc = lib().fz_compress(self._h, ctypes.byref(p), ctypes.c_void_p(x.data_ptr()),
@@ -237,10 +245,16 @@ class Context:
             raise ValueError("buf must be a contiguous uint8 device tensor")
         if header is None:
             header = buf[:HDR_BYTES].cpu().numpy().tobytes()
-        p, n, _ = self.read_header(header)
+        hb = bytes(header[:HDR_BYTES])
+        cached = self._hcache.get(hb)
+        if cached is None:
+            if len(self._hcache) > 256:
+                self._hcache.clear()
+            p, n, _ = self.read_header(hb)
+            cached = self._hcache[hb] = (p, n, (ctypes.c_uint8 * HDR_BYTES).from_buffer_copy(hb))
+        p, n, h = cached
         if out is None:
             out = torch.empty(shape_of(p), dtype=torch.float32, device=buf.device)
-        h = (ctypes.c_uint8 * HDR_BYTES).from_buffer_copy(bytes(header[:HDR_BYTES]))
         rc = lib().fz_decompress(self._h, ctypes.c_void_p(buf.data_ptr()), buf.numel(), h,
                                  ctypes.c_void_p(out.data_ptr()), out.numel(), _stream_handle(buf.device))
         _check(rc, "fz_decompress")
