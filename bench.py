@@ -236,9 +236,20 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": measured_traffic(dom_name),
                 "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": int(bytes_per_launch)}
+    full = per_stage(warm if warm else stages)
     stage_summary = {k: {"avg_ms": round(v["ms"] / v["launches"], 4),
                          "gbps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
-                     for k, v in sorted(per_stage(warm if warm else stages).items())}
+                     for k, v in sorted(full.items())}
+    # whole calls: every stage's algorithmic bytes over every stage's time,
+    # per direction (the kernels back to back, no host time)
+    call_roofline = {}
+    for d in ("compress", "decompress"):
+        ms = sum(v["ms"] for k, v in full.items() if k.startswith(d + ":"))
+        by = sum(v["bytes"] for k, v in full.items() if k.startswith(d + ":"))
+        if ms > 0:
+            a = by / (ms * 1e-3) / 1e9
+            call_roofline[d] = {"achieved": round(a, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                                "frac": round(a / HBM_PEAK_GBPS, 4)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -258,6 +269,7 @@ def main():
         "stages_timed_in": "the last warmup step (every stage); the timed steps time the dominant stage alone"
                            if warm else "timed steps",
         "roofline": roofline,
+        "call_roofline": call_roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
