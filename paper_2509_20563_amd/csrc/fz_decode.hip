@@ -365,9 +365,7 @@ struct FastDec {
     const uint4* S;       // stream chunks
     uint32_t nch;         // number of stream chunks (>= 1)
     uint32_t* sr;         // &SRING[lane]; ring word k at sr[k * kDecLanes]
-    uint32_t w, nw;       // next word to feed; its value
-    uint64_t buf;         // bits, most significant first
-    uint32_t nb;          // valid bits in buf
+    uint32_t w, s;        // position of the next unread bit: word, bit in it
     uint32_t sF, sEnd;    // next chunk to fetch; last chunk worth fetching
     uint4 sX[2];          // chunks in flight (by row parity) and their
     uint32_t sXi[2];      // indices (~0: dummy)
@@ -423,16 +421,7 @@ struct FastDec {
         sXi[0] = sXi[1] = oXi[0] = oXi[1] = 0xFFFFFFFFu;
         hash = 0;
         w = w0;
-        nw = sr[(w & (kRing - 1)) * kDecLanes];
-        buf = (uint64_t)nw << 32;
-        w++;
-        nw = sr[(w & (kRing - 1)) * kDecLanes];
-        buf |= nw;
-        w++;
-        nw = sr[(w & (kRing - 1)) * kDecLanes];
-        const uint32_t skip = (uint32_t)(start & 31);
-        buf <<= skip;
-        nb = 64 - skip;
+        s = (uint32_t)(start & 31);
     }
     // row prologue for row parity P: land what row - 2 fetched, fetch anew
     template <int P>
@@ -452,26 +441,42 @@ struct FastDec {
         oXi[P] = oreal ? oF : 0xFFFFFFFFu;
         oF += oreal ? 1u : 0u;
     }
-    __device__ __forceinline__ void refill() {
-        const bool need = nb <= 32;
-        buf |= need ? ((uint64_t)nw << ((32 - nb) & 63)) : 0ull;
-        nb += need ? 32u : 0u;
-        w += need ? 1u : 0u;
-        nw = sr[(w & (kRing - 1)) * kDecLanes];
+    // The 64 stream bits from the current position, most significant first,
+    // read from the three ring words that hold them (four codewords of at
+    // most 12 bits fit, so a row refills twice instead of topping up a word
+    // at a time; the words past the last codeword may hold stale ring data,
+    // which no codeword reaches).
+    __device__ __forceinline__ uint64_t window() const {
+        const uint32_t a = sr[(w & (kRing - 1)) * kDecLanes];
+        const uint32_t b = sr[((w + 1) & (kRing - 1)) * kDecLanes];
+        const uint32_t c = sr[((w + 2) & (kRing - 1)) * kDecLanes];
+        const uint64_t hi = (((uint64_t)a << 32) | b) << s;
+        return hi | ((((uint64_t)c) << s) >> 32);
+    }
+    __device__ __forceinline__ void skip(uint32_t used) {
+        s += used;
+        w += s >> 5;
+        s &= 31u;
     }
     // 8 codewords of one row.  An outlier value not landed yet (a burst,
     // or a corrupt container) is fetched after the row by the whole wave,
     // so no global load sits inside the codeword loop.
     __device__ __forceinline__ void row8(const uint16_t* LUT, uint32_t pos0, int32_t d[8]) {
-        // the codeword chain first, without branches
+        // the codeword chain first, without branches: two halves of four
+        // codewords, each from a fresh 64-bit window
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
-            if ((i & 1) == 0) refill();
-            const uint32_t e = LUT[(uint32_t)(buf >> (64 - kLmax))];
-            const uint32_t len = e >> 10;
-            buf <<= len;
-            nb -= len;
-            d[i] = (int32_t)(e & 1023u) - kRadius;
+        for (int h = 0; h < 2; h++) {
+            uint64_t buf = window();
+            uint32_t used = 0;
+#pragma unroll
+            for (int i = 4 * h; i < 4 * h + 4; i++) {
+                const uint32_t e = LUT[(uint32_t)(buf >> (64 - kLmax))];
+                const uint32_t len = e >> 10;
+                buf <<= len;
+                used += len;
+                d[i] = (int32_t)(e & 1023u) - kRadius;
+            }
+            skip(used);
         }
         // code 0 (an outlier) is the only one that decodes to -radius: a
         // wave whose row holds none skips the outlier handling
@@ -504,7 +509,7 @@ struct FastDec {
         }
     }
     __device__ __forceinline__ uint64_t consumed(uint64_t start) const {
-        return (uint64_t)w * 32 - nb - start;
+        return (uint64_t)w * 32 + s - start;
     }
 };
 
