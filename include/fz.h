@@ -146,8 +146,10 @@ const char *fz_stage_name(fz_ctx *ctx, int i);
  * fz_stage_name gives it, shorter than 32 bytes; the string is copied),
  * calls record one event just before that stage and one after it, and
  * fz_stage_times returns that stage alone (0 stages for a call without it);
- * every other stage runs without events in between.  NULL restores timing
- * of every stage.  FZ_ERR_ARG for a name of 32 bytes or more. */
+ * every other stage runs without events in between.  The name "call"
+ * times each whole call as one stage named "call": one event before its
+ * first kernel and one after its last, none in between.  NULL restores
+ * timing of every stage.  FZ_ERR_ARG for a name of 32 bytes or more. */
 int fz_set_timing_stage(fz_ctx *ctx, const char *stage);
 
 /* Stage dump for parity checks: the 1024-bin code histogram of the last

@@ -309,11 +309,14 @@ int ensure_pred(fz_ctx* c, const Geom& g, bool decode) {
 
 // Stage timing helpers (events on the call's stream).
 // Every stage is timed (an event after each), or, with a stage filter set,
-// only the named stage (one event just before it, one after it).
+// only the named stage (one event just before it, one after it), or, with
+// the filter "call", the whole call as one stage (one event before its
+// first kernel, one after its last).
+bool t_whole(const fz_ctx* c) { return strcmp(c->tstage, "call") == 0; }
 void t_begin(fz_ctx* c, hipStream_t st) {
     c->nev = 0;
     c->nstages = 0;
-    if (!c->timing || c->tstage[0]) return;
+    if (!c->timing || (c->tstage[0] && !t_whole(c))) return;
     hipEventRecord(c->ev[0], st);
     c->nev = 1;
 }
@@ -324,6 +327,13 @@ void t_start(fz_ctx* c, hipStream_t st, const char* name) {
 }
 void t_mark(fz_ctx* c, hipStream_t st, const char* name) {
     if (!c->timing || c->nev > kMaxStages) return;
+    if (c->nev >= 1 && t_whole(c)) {
+        // the end event moves to each stage's end: the last one counts
+        hipEventRecord(c->ev[1], st);
+        c->names[0] = "call";
+        c->nev = 2;
+        return;
+    }
     if (c->tstage[0] && (c->nev != 1 || strcmp(name, c->tstage) != 0)) return;
     hipEventRecord(c->ev[c->nev], st);
     c->names[c->nev - 1] = name;

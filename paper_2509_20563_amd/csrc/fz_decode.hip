@@ -14,9 +14,12 @@
 namespace fz {
 
 // ----------------------------------------------------------- decode table
-// Entry for the 12-bit prefix v: (length << 10) | symbol of the codeword
-// that v starts with.  The lengths must describe a complete code (Kraft sum
-// exactly 1, every length 1..12, at least two symbols).
+// Entry for the 12-bit prefix v: ((symbol ^ radius) << 6) | length of the
+// codeword that v starts with.  The length sits in the six bits a 64-bit
+// shift takes its amount from, so the entry itself shifts the bit buffer,
+// and bits 6..15 read as a signed 10-bit field are symbol - radius, the
+// residual.  The lengths must describe a complete code (Kraft sum exactly
+// 1, every length 1..12, at least two symbols).
 __global__ __launch_bounds__(1024) void k_lut(const uint8_t* __restrict__ lensp, uint16_t* __restrict__ lut,
                                               Misc* misc) {
     __shared__ CanonShared cs;
@@ -60,7 +63,7 @@ __global__ __launch_bounds__(1024) void k_lut(const uint8_t* __restrict__ lensp,
             const uint32_t end = (cs.first[L] + c) << (kLmax - L);
             if (v < end) {
                 const uint32_t idx = (v >> (kLmax - L)) - cs.first[L];
-                e = (uint16_t)((L << 10) | cs.sorted[cs.offset[L] + idx]);
+                e = (uint16_t)(((cs.sorted[cs.offset[L] + idx] ^ (uint32_t)kRadius) << 6) | (uint32_t)L);
                 break;
             }
         }
@@ -140,11 +143,14 @@ struct LaneDec {
     }
 };
 
-// One codeword: returns the table entry (length << 10 | symbol); a lane
-// with valid == false consumes nothing.
+// Residual of a table entry (symbol - radius; -radius for an outlier code).
+__device__ __forceinline__ int32_t entry_residual(uint32_t e) { return (int32_t)(e << 16) >> 22; }
+
+// One codeword: returns the table entry; a lane with valid == false
+// consumes nothing.
 __device__ __forceinline__ uint32_t dec_sym(LaneDec& ld, const uint16_t* LUT, bool valid) {
     const uint32_t e = LUT[(uint32_t)(ld.buf >> (64 - kLmax))];
-    const uint32_t len = valid ? (e >> 10) : 0u;
+    const uint32_t len = valid ? (e & 63u) : 0u;
     ld.buf <<= len;
     ld.nb -= len;
     return e;
@@ -185,9 +191,9 @@ __device__ __forceinline__ void dec_row8(LaneDec& ld, const uint16_t* LUT, uint3
         if ((i & 1) == 0) ld.refill();
         const bool valid = (uint32_t)i < nvalid;
         const uint32_t e = dec_sym(ld, LUT, valid);
-        const uint32_t sym = e & 1023u;
-        d[i] = valid ? (int32_t)sym - kRadius : 0;
-        if (valid && sym == 0) d[i] = oq.take(pos0 + i);
+        const int32_t r = entry_residual(e);
+        d[i] = valid ? r : 0;
+        if (valid && r == -kRadius) d[i] = oq.take(pos0 + i);
     }
 }
 
@@ -471,10 +477,9 @@ struct FastDec {
 #pragma unroll
             for (int i = 4 * h; i < 4 * h + 4; i++) {
                 const uint32_t e = LUT[(uint32_t)(buf >> (64 - kLmax))];
-                const uint32_t len = e >> 10;
-                buf <<= len;
-                used += len;
-                d[i] = (int32_t)(e & 1023u) - kRadius;
+                buf <<= (e & 63u);
+                used += e & 63u;
+                d[i] = entry_residual(e);
             }
             skip(used);
         }

@@ -171,6 +171,15 @@ def test_stage_timing(fz, ctx):
     assert [n for n, _ in ctx.stage_times()] == ["quant"]
     with pytest.raises(fz.FZError):
         ctx.set_timing_stage("x" * 32)
+    # the whole call as one stage: one event before the first kernel, one after the last
+    ctx.set_timing_stage("call")
+    c3 = ctx.compress(x, 1e-3, 1)
+    t = ctx.stage_times()
+    assert [n for n, _ in t] == ["call"] and t[0][1] > 0
+    y = ctx.decompress(c3)
+    t = ctx.stage_times()
+    assert [n for n, _ in t] == ["call"] and t[0][1] > 0
+    assert torch.equal(y, ctx.decompress(c))
     ctx.set_timing_stage(None)
     ctx.compress(x, 1e-3, 1)
     assert len(ctx.stage_times()) == 7
