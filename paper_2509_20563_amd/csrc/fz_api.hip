@@ -566,14 +566,12 @@ void decompress_enqueue(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_
     const Layout L = make_layout(r.nblocks, has_map, r.nreg, r.words, r.nout, r.npat);
     const uint32_t stiles = scan_tiles(g.nblocks);
     const int vec = (((uintptr_t)d_out & 15) == 0) && (g.ndim == 1 || (g.n[0] & 3) == 0);
-    // the reset also clears the per-block outlier index
-    start("reset");
-    launch_reset(st, c->misc, c->hist, c->desc_chunks, stiles, has_map ? c->desc_pmap : nullptr,
-                 has_map ? stiles : 0, r.nout ? reinterpret_cast<uint64_t*>(c->oidx) : nullptr,
-                 r.nout ? (uint32_t)g.nblocks : 0u, L.chunks, L.stream, r.nreg);
-    mark("reset");
+    // one launch: the reset (which also clears the per-block outlier index)
+    // and the decode table
     start("lut");
-    launch_lut(st, in + L.lens, c->lut, c->misc);
+    launch_reset_lut(st, c->misc, c->hist, c->desc_chunks, stiles, has_map ? c->desc_pmap : nullptr,
+                     has_map ? stiles : 0, r.nout ? reinterpret_cast<uint64_t*>(c->oidx) : nullptr,
+                     r.nout ? (uint32_t)g.nblocks : 0u, L.chunks, L.stream, r.nreg, in + L.lens, c->lut);
     mark("lut");
     start("scan");
     launch_scan(st, SCAN_CHUNKS, in + L.chunks, g.nblocks, c->off, c->desc_chunks, &c->misc->stile_ctr, c->misc,

@@ -235,6 +235,25 @@ __device__ __forceinline__ int32_t prequant1(float xv, double e2, double inv, do
 }
 
 
+// Per-call scratch reset: Misc (one thread) and the grid-stride clearing
+// of the histogram copies and up to three descriptor/index arrays.
+__device__ __forceinline__ void reset_misc(Misc* misc, uint64_t off_chunks, uint64_t off_stream, uint64_t nreg) {
+    Misc m = {};
+    m.mm_lo = 0xFFFFFFFFu;
+    m.mm_hi = 0u;
+    m.off_chunks = off_chunks;
+    m.off_stream = off_stream;
+    m.nreg = nreg;
+    *misc = m;
+}
+__device__ __forceinline__ void clear_scratch(uint32_t gid, uint32_t stride, uint32_t* hist, uint64_t* d1,
+                                              uint32_t n1, uint64_t* d2, uint32_t n2, uint64_t* d3, uint32_t n3) {
+    for (uint32_t i = gid; i < (uint32_t)(kHistCopies * kBins); i += stride) hist[i] = 0;
+    for (uint32_t i = gid; i < n1; i += stride) d1[i] = 0;
+    for (uint32_t i = gid; i < n2; i += stride) d2[i] = 0;
+    for (uint32_t i = gid; i < n3; i += stride) d3[i] = 0;
+}
+
 // Decoupled look-back (single-pass prefix scan over tiles taken in order
 // from an atomic counter).  desc[t] holds status (2 high bits: 1 = tile
 // aggregate, 2 = inclusive prefix) and a 62-bit payload combined by Op

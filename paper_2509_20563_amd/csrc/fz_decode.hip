@@ -1,7 +1,8 @@
 // Decompression (FZModules Sec. 1 and Sec. 3.3.1 describe it as Huffman
 // decoding of the quantisation codes plus scattering of the outliers into
 // the reconstruction; the inverse of the Lorenzo predictor is a prefix sum):
-//   k_lut          - validates the code lengths, builds a 4096-entry table
+//   k_reset_lut    - per-call reset; validates the code lengths, builds a
+//                    4096-entry table
 //   k_decode       - one lane per block: table-driven Huffman decode from a
 //                    register bit buffer fed through a per-lane LDS ring,
 //                    outlier overwrite, in-block prefix sums (inverse
@@ -20,8 +21,9 @@ namespace fz {
 // and bits 6..15 read as a signed 10-bit field are symbol - radius, the
 // residual.  The lengths must describe a complete code (Kraft sum exactly
 // 1, every length 1..12, at least two symbols).
-__global__ __launch_bounds__(1024) void k_lut(const uint8_t* __restrict__ lensp, uint16_t* __restrict__ lut,
-                                              Misc* misc) {
+// Executed by one whole workgroup of 1024 threads (thread = symbol).
+__device__ __forceinline__ void build_lut(const uint8_t* __restrict__ lensp, uint16_t* __restrict__ lut,
+                                          Misc* misc) {
     __shared__ CanonShared cs;
     __shared__ uint32_t rk[16], ru[16], rb[16];
     const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -69,6 +71,22 @@ __global__ __launch_bounds__(1024) void k_lut(const uint8_t* __restrict__ lensp,
         }
         lut[v] = e;
     }
+}
+
+// The decompression's first kernel: the per-call reset (Misc by workgroup
+// 0, the arrays by the whole grid) and the decode table, built by
+// workgroup 0 once its reset of Misc is visible to its threads (the table
+// build may flag a corrupt code in Misc).
+__global__ __launch_bounds__(1024) void k_reset_lut(Misc* misc, uint32_t* hist, uint64_t* d1, uint32_t n1,
+                                                    uint64_t* d2, uint32_t n2, uint64_t* d3, uint32_t n3,
+                                                    uint64_t off_chunks, uint64_t off_stream, uint64_t nreg,
+                                                    const uint8_t* __restrict__ lensp, uint16_t* __restrict__ lut) {
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid == 0) reset_misc(misc, off_chunks, off_stream, nreg);
+    clear_scratch(gid, gridDim.x * blockDim.x, hist, d1, n1, d2, n2, d3, n3);
+    if (blockIdx.x != 0) return;
+    __syncthreads();
+    build_lut(lensp, lut, misc);
 }
 
 // ----------------------------------------------------------------- decode
@@ -946,8 +964,16 @@ void launch_copy(hipStream_t st, const uint8_t* src, float* dst, uint64_t n) {
     hipLaunchKernelGGL(k_copy, dim3((uint32_t)grid), dim3(256), 0, st, src, dst, n, vec);
 }
 
-void launch_lut(hipStream_t st, const uint8_t* lens_packed, uint16_t* lut, Misc* misc) {
-    hipLaunchKernelGGL(k_lut, dim3(1), dim3(1024), 0, st, lens_packed, lut, misc);
+void launch_reset_lut(hipStream_t st, Misc* misc, uint32_t* hist, uint64_t* d1, uint32_t n1, uint64_t* d2,
+                      uint32_t n2, uint64_t* d3, uint32_t n3, uint64_t off_chunks, uint64_t off_stream,
+                      uint64_t nreg, const uint8_t* lens_packed, uint16_t* lut) {
+    uint32_t n = n1 > n2 ? n1 : n2;
+    if (n3 > n) n = n3;
+    uint32_t grid = (n + 1023) / 1024;
+    if (grid < 1) grid = 1;
+    if (grid > 256) grid = 256;
+    hipLaunchKernelGGL(k_reset_lut, dim3(grid), dim3(1024), 0, st, misc, hist, d1, n1, d2, n2, d3, n3, off_chunks,
+                       off_stream, nreg, lens_packed, lut);
 }
 
 namespace {

@@ -61,7 +61,10 @@ void launch_gather_headers(hipStream_t st, const uint8_t* in, const uint64_t* of
 
 // fz_decode.hip
 void launch_copy(hipStream_t st, const uint8_t* src, float* dst, uint64_t n);
-void launch_lut(hipStream_t st, const uint8_t* lens_packed, uint16_t* lut, Misc* misc);
+// reset (as launch_reset) and decode table (as launch_lut) in one launch
+void launch_reset_lut(hipStream_t st, Misc* misc, uint32_t* hist, uint64_t* d1, uint32_t n1, uint64_t* d2,
+                      uint32_t n2, uint64_t* d3, uint32_t n3, uint64_t off_chunks, uint64_t off_stream,
+                      uint64_t nreg, const uint8_t* lens_packed, uint16_t* lut);
 void launch_outlier_index(hipStream_t st, const Geom& g, const uint32_t* opos, uint64_t n_out, uint2* oidx,
                           Misc* misc);
 void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,

@@ -14,20 +14,8 @@ namespace fz {
 __global__ void k_reset(Misc* misc, uint32_t* hist, uint64_t* d1, uint32_t n1, uint64_t* d2, uint32_t n2,
                         uint64_t* d3, uint32_t n3, uint64_t off_chunks, uint64_t off_stream, uint64_t nreg) {
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    if (gid == 0) {
-        Misc m = {};
-        m.mm_lo = 0xFFFFFFFFu;
-        m.mm_hi = 0u;
-        m.off_chunks = off_chunks;
-        m.off_stream = off_stream;
-        m.nreg = nreg;
-        *misc = m;
-    }
-    for (uint32_t i = gid; i < (uint32_t)(kHistCopies * kBins); i += stride) hist[i] = 0;
-    for (uint32_t i = gid; i < n1; i += stride) d1[i] = 0;
-    for (uint32_t i = gid; i < n2; i += stride) d2[i] = 0;
-    for (uint32_t i = gid; i < n3; i += stride) d3[i] = 0;
+    if (gid == 0) reset_misc(misc, off_chunks, off_stream, nreg);
+    clear_scratch(gid, gridDim.x * blockDim.x, hist, d1, n1, d2, n2, d3, n3);
 }
 
 // -------------------------------------------------------------- min/max
