@@ -539,7 +539,7 @@ struct FastDec {
 // RES = false: inverse Lorenzo, dequantisation and rows of floats (two
 // float4 stores per row when VEC, rows 16-byte aligned; else eight dword
 // stores); RES = true: residuals (int32, block-major) for the mapped decoder.
-template <int ND, bool RES, bool VEC>
+template <int ND, bool RES, bool VEC, bool XT = false>
 __global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint32_t ib1, uint32_t nint,
                                                      const uint32_t* __restrict__ stream, uint64_t nwords,
                                                      const uint64_t* __restrict__ off,
@@ -551,6 +551,9 @@ __global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint3
     __shared__ uint16_t LUT[kLut];
     __shared__ uint32_t SRING[kDecLanes * kRing];
     __shared__ uint32_t ORING[kDecLanes * kORing];
+    // XT: a wave's 64 blocks are one run along x, so its rows of a step are
+    // 2 KiB of contiguous output: staged here and stored 1 KiB per instruction
+    __shared__ f32x4 XS[XT ? 4 * 128 : 1];
     const uint32_t t = threadIdx.x;
     for (uint32_t i = t; i < (uint32_t)kLut; i += 256) LUT[i] = lut_g[i];
     __syncthreads();
@@ -577,8 +580,24 @@ __global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint3
             f32x4* p = reinterpret_cast<f32x4*>(out + idx);
             const f32x4 a = {deq(q[0]), deq(q[1]), deq(q[2]), deq(q[3])};
             const f32x4 c = {deq(q[4]), deq(q[5]), deq(q[6]), deq(q[7])};
-            __builtin_nontemporal_store(a, p);
-            __builtin_nontemporal_store(c, p + 1);
+            if (XT) {
+                const uint32_t lane = t & 63;
+                f32x4* xs = &XS[(t >> 6) * 128];
+                xs[2 * lane] = a;
+                xs[2 * lane + 1] = c;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const f32x4 u = xs[lane], v = xs[64 + lane];
+                if (active) {
+                    f32x4* w0 = reinterpret_cast<f32x4*>(out + (idx - 8 * (uint64_t)lane));
+                    __builtin_nontemporal_store(u, w0 + lane);
+                    __builtin_nontemporal_store(v, w0 + 64 + lane);
+                }
+            } else {
+                __builtin_nontemporal_store(a, p);
+                __builtin_nontemporal_store(c, p + 1);
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < 8; i++) __builtin_nontemporal_store(deq(q[i]), out + idx + i);
@@ -1019,7 +1038,13 @@ void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64
 #define FZ_FAST(NDV, V)                                                                                               \
     hipLaunchKernelGGL((k_decode_fast<NDV, false, V>), dim3(fg), dim3(256), 0, st, g, I.ib[0], I.ib[1], I.n, stream, \
                        stream_words, off, chunks, lut, oval, oidx, n_out, e2, out, (int32_t*)nullptr, misc)
-        if (vec) {
+        if (vec && g.ndim == 3 && I.ib[0] % 64 == 0) {
+            // whole waves on one run of 64 blocks along x (I.n is then a
+            // multiple of 64: a wave is all active or all inactive)
+            hipLaunchKernelGGL((k_decode_fast<3, false, true, true>), dim3(fg), dim3(256), 0, st, g, I.ib[0], I.ib[1],
+                               I.n, stream, stream_words, off, chunks, lut, oval, oidx, n_out, e2, out,
+                               (int32_t*)nullptr, misc);
+        } else if (vec) {
             if (g.ndim == 3) FZ_FAST(3, true);
             else if (g.ndim == 2) FZ_FAST(2, true);
             else FZ_FAST(1, true);

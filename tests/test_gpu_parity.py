@@ -40,6 +40,12 @@ CASES = [
     ("3d-zeros-one-symbol", "zeros", (16, 16, 16), 1e-3, 0),
     ("3d-denormal", "denormal", (16, 16, 16), 1e-44, 0),
     ("3d-noise-verbatim", "noise", (20, 30, 40), 1e-7, 1),
+    # x extent a multiple of 512: the fast decoder's staged row stores (a
+    # wave = one run of 64 blocks along x), with inactive waves in the last
+    # workgroup, ragged y/z edge blocks beside it, and a tight bound
+    ("3d-x512-partial-waves", "smooth", (20, 12, 512), 1e-3, 1),
+    ("3d-x1024-ragged-yz", "smooth", (9, 17, 1024), 1e-2, 1),
+    ("3d-x512-tight", "smooth", (16, 24, 512), 1e-5, 1),
     ("2d-ragged", "smooth", (1001, 777), 1e-3, 1),
     ("2d-tight", "smooth", (257, 1800), 1e-5, 1),
     ("2d-small", "smooth", (3, 5), 1e-2, 1),
