@@ -80,6 +80,13 @@ __host__ __device__ inline uint64_t pos_hash(uint32_t p) {
     return h ^ (h >> 29);
 }
 
+// Term of one outlier position in the decoder's consistency check (the sum
+// over the codes met against the sum over the stored list): the row of 8
+// the position lies in, mixed, times 2^(position in the row).  The terms of
+// one row sum to pos_hash(row) * (the row's 8-bit outlier mask), so a
+// decoder may add a whole row at once.
+__host__ __device__ inline uint64_t outlier_term(uint32_t p) { return pos_hash(p >> 3) << (p & 7); }
+
 // Unsigned division by a runtime constant d <= 2^23 for numerators <= 2^23:
 // q = (umulhi(n, m) + n) >> l with l = ceil(log2 d), m = 2^32 (2^l - d) / d + 1
 // (Granlund & Montgomery; the sum cannot overflow for these ranges).

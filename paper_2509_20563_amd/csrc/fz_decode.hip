@@ -184,7 +184,7 @@ struct OutQ {
     uint64_t n_out;
     uint32_t oi;    // list index of the next outlier
     int32_t next;   // its value
-    uint64_t hash;  // sum of pos_hash over the outlier codes met
+    uint64_t hash;  // sum of outlier_term over the outlier codes met
     __device__ __forceinline__ void init(const int32_t* v, uint64_t n, uint32_t first) {
         oval = v;
         n_out = n;
@@ -194,7 +194,7 @@ struct OutQ {
     }
     __device__ __forceinline__ int32_t take(uint32_t pos) {
         const int32_t d = next;
-        hash += pos_hash(pos);
+        hash += outlier_term(pos);
         oi++;
         if (n_out) next = oval[(uint64_t)oi < n_out ? oi : (uint32_t)(n_out - 1)];
         return d;
@@ -505,21 +505,27 @@ struct FastDec {
         // wave whose row holds none skips the outlier handling
         const int32_t mn = min(min(min(d[0], d[1]), min(d[2], d[3])), min(min(d[4], d[5]), min(d[6], d[7])));
         if (!__ballot(mn == -kRadius)) return;
-        uint32_t mmask = 0, m0 = 0;
+        // the row's outlier mask; the k-th outlier of the row takes list
+        // entry oi + k, read from the ring when landed (index below oL),
+        // without a branch per value
+        uint32_t m = 0;
+#pragma unroll
+        for (int i = 0; i < 8; i++) m |= (d[i] == -kRadius ? 1u : 0u) << i;
+        const uint32_t cnt = (uint32_t)__popc(m);
+        hash += pos_hash(pos0 >> 3) * (uint64_t)m;  // the row's outlier_term sum (pos0 % 8 == 0)
+        const uint32_t nland = oL > oi ? min(cnt, oL - oi) : 0u;
+        uint32_t mmask = 0;
 #pragma unroll
         for (int i = 0; i < 8; i++) {
-            if (d[i] == -kRadius) {
-                hash += pos_hash(pos0 + i);
-                if (oi < oL) {
-                    d[i] = (int32_t)orr[(oi & (kORing - 1)) * kDecLanes];
-                } else {
-                    m0 = mmask ? m0 : oi;
-                    mmask |= 1u << i;
-                    d[i] = 0;
-                }
-                oi++;
-            }
+            const uint32_t k = (uint32_t)__popc(m & ((1u << i) - 1u));
+            const int32_t v = (int32_t)orr[((oi + k) & (kORing - 1)) * kDecLanes];
+            const bool out = (m >> i) & 1u;
+            const bool land = k < nland;
+            d[i] = out ? (land ? v : 0) : d[i];
+            mmask |= (out && !land) ? (1u << i) : 0u;
         }
+        const uint32_t m0 = oi + nland;
+        oi += cnt;
         if (__ballot(mmask != 0)) {
 #pragma unroll
             for (int i = 0; i < 8; i++)
@@ -885,7 +891,7 @@ __device__ __forceinline__ void outlier_entry(uint64_t i, uint32_t p, bool has_p
                                               bool& bad) {
     const uint32_t b = p >> 9;
     bad |= (has_prev && prev >= p) || b >= nblocks;
-    h += pos_hash(p);
+    h += outlier_term(p);
     if (b < nblocks && (!has_prev || (prev >> 9) != b)) oidx[b].x = (uint32_t)i;
     if (b < nblocks && (!has_next || (next >> 9) != b)) oidx[b].y = (uint32_t)(i + 1);
 }
