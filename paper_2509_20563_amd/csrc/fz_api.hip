@@ -327,17 +327,19 @@ void t_start(fz_ctx* c, hipStream_t st, const char* name) {
 }
 void t_mark(fz_ctx* c, hipStream_t st, const char* name) {
     if (!c->timing || c->nev > kMaxStages) return;
-    if (c->nev >= 1 && t_whole(c)) {
-        // the end event moves to each stage's end: the last one counts
-        hipEventRecord(c->ev[1], st);
-        c->names[0] = "call";
-        c->nev = 2;
-        return;
-    }
+    if (t_whole(c)) return;  // the call's end is recorded by t_finish
     if (c->tstage[0] && (c->nev != 1 || strcmp(name, c->tstage) != 0)) return;
     hipEventRecord(c->ev[c->nev], st);
     c->names[c->nev - 1] = name;
     c->nev++;
+}
+// After the call's last kernel is enqueued (before its result copy): the
+// end event of the whole-call timing.
+void t_finish(fz_ctx* c, hipStream_t st) {
+    if (!c->timing || c->nev != 1 || !t_whole(c)) return;
+    hipEventRecord(c->ev[1], st);
+    c->names[0] = "call";
+    c->nev = 2;
 }
 void t_end(fz_ctx* c) {
     if (!c->timing) return;
@@ -727,6 +729,7 @@ int fz_compress(fz_ctx* c, const fz_params* p, const float* d_in, void* d_out, u
     c->have_hist = false;
     t_begin(c, st);
     compress_enqueue(c, p, g, d_in, (uint8_t*)d_out, st, c->tune_default, true);
+    t_finish(c, st);
     if (hipMemcpyAsync(c->h_misc, c->misc, sizeof(Misc), hipMemcpyDeviceToHost, st) != hipSuccess) return FZ_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
     if (hipGetLastError() != hipSuccess) return FZ_ERR_HIP;
@@ -772,6 +775,7 @@ int fz_decompress(fz_ctx* c, const void* d_in, uint64_t in_bytes, const void* h_
     if (rc) return rc;
     t_begin(c, st);
     decompress_enqueue(c, r, in, d_out, st, true);
+    t_finish(c, st);
     if (hipMemcpyAsync(c->h_misc, c->misc, sizeof(Misc), hipMemcpyDeviceToHost, st) != hipSuccess) return FZ_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
     if (hipGetLastError() != hipSuccess) return FZ_ERR_HIP;
@@ -814,6 +818,7 @@ int analysis_begin(fz_ctx* c, const fz_params* p, const float* d_in, hipStream_t
 }
 
 int analysis_end(fz_ctx* c, hipStream_t st) {
+    t_finish(c, st);
     if (hipMemcpyAsync(c->h_misc, c->misc, sizeof(Misc), hipMemcpyDeviceToHost, st) != hipSuccess) return FZ_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
     if (hipGetLastError() != hipSuccess) return FZ_ERR_HIP;
