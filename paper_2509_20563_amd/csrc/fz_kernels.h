@@ -61,7 +61,8 @@ void launch_gather_headers(hipStream_t st, const uint8_t* in, const uint64_t* of
 
 // fz_decode.hip
 void launch_copy(hipStream_t st, const uint8_t* src, float* dst, uint64_t n);
-// reset (as launch_reset) and decode table (as launch_lut) in one launch
+// the decompression's first launch: the per-call reset (as launch_reset) and
+// the decode table built from the packed code lengths
 void launch_reset_lut(hipStream_t st, Misc* misc, uint32_t* hist, uint64_t* d1, uint32_t n1, uint64_t* d2,
                       uint32_t n2, uint64_t* d3, uint32_t n3, uint64_t off_chunks, uint64_t off_stream,
                       uint64_t nreg, const uint8_t* lens_packed, uint16_t* lut);
