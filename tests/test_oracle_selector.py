@@ -249,3 +249,68 @@ def test_adam_first_step_closed_form():
     w2 = w1.copy()
     oracle.adam_step(w2, m, v, g, 2, lr=1e-3)
     assert np.allclose(w2[o1:] - w1[o1:], -1e-3 * g[o1:] / (np.abs(g[o1:]) + 1e-8), rtol=1e-9, atol=1e-15)
+
+
+def _block3(fn):
+    """One 8^3 block with q[lz, ly, lx] = fn(lx, ly, lz)."""
+    l = np.arange(8)
+    lz, ly, lx = np.meshgrid(l, l, l, indexing="ij")
+    return np.ascontiguousarray(fn(lx, ly, lz).astype(np.int32))
+
+
+def test_ramp_z_3d():
+    """q = lz: the 3D sample is the two lowest z-planes, so the only z pairs
+    are (lz = 1, lz = 0), each with difference 1; nothing varies along x or
+    y.  A y/z stride mix-up in the oracle would read 0 here."""
+    f = oracle.features_q(_block3(lambda x, y, z: z))[0]
+    assert f[4] == _plog2_1p(1.0) == 1.0
+    assert f[2] == 0 and f[3] == 0
+    assert np.all(f[5:11] == 0)
+    assert f[0] == _plog2_1p(0.25)  # lz in {0, 1}, 64 values each: variance 1/4
+    assert f[14] == _plog2_1p(1) and f[15] == _plog2_1p(0.5)
+
+
+def test_second_difference_z_is_outside_the_3d_sample():
+    """Feature 7 (mean |second difference along z|) needs three z-planes;
+    the 3D sample holds two, so it is 0 for every 3D block: a z-quadratic
+    (lz^2), a z-cubic and random blocks.  Their first z difference at
+    lz = 1 is q(1) - q(0): 1 for lz^2, 1 for lz^3."""
+    for fn in (lambda x, y, z: z * z, lambda x, y, z: z ** 3):
+        f = oracle.features_q(_block3(fn))[0]
+        assert f[7] == 0.0 and f[4] == 1.0
+        assert f[2] == 0 and f[3] == 0 and f[5] == 0 and f[6] == 0
+    r = np.random.default_rng(9)
+    q = r.integers(-500, 500, size=(13, 17, 19)).astype(np.int32)
+    assert np.all(oracle.features_q(q)[:, 7] == 0)
+
+
+def test_mixed_difference_yz():
+    """q = ly * lz: the yz mixed difference is 1 wherever ly, lz >= 1; the
+    xy and xz ones vanish.  Along z the difference is ly (mean 3.5 over the
+    64 pairs at lz = 1); along y it is lz (0 on the lz = 0 plane, 1 on
+    lz = 1: mean 1/2 over 112 pairs)."""
+    f = oracle.features_q(_block3(lambda x, y, z: y * z))[0]
+    assert f[9] == 1.0 and f[8] == 0 and f[10] == 0
+    assert f[4] == _plog2_1p(3.5)
+    assert f[3] == _plog2_1p(0.5) == 0.5
+    assert f[2] == 0 and f[5] == 0 and f[6] == 0 and f[7] == 0
+
+
+def test_mixed_difference_xz():
+    """q = lx * lz: the xz mixed difference is 1 wherever lx, lz >= 1; the
+    xy and yz ones vanish; along z the difference is lx (mean 3.5)."""
+    f = oracle.features_q(_block3(lambda x, y, z: x * z))[0]
+    assert f[10] == 1.0 and f[8] == 0 and f[9] == 0
+    assert f[4] == _plog2_1p(3.5)
+    assert f[3] == 0 and f[6] == 0 and f[7] == 0
+
+
+def test_axis_features_follow_the_axis_not_the_stride():
+    """The same 1D profile put along x, then y, then z moves its first
+    difference feature from index 2 to 3 to 4 (ramps of slope 3, so the
+    mean |difference| is 3 and the feature plog2(4) = 2)."""
+    for a, fn in enumerate((lambda x, y, z: 3 * x, lambda x, y, z: 3 * y, lambda x, y, z: 3 * z)):
+        f = oracle.features_q(_block3(fn))[0]
+        want = np.zeros(3, np.float32)
+        want[a] = 2.0
+        assert np.array_equal(f[2:5], want), (a, f[2:5])
