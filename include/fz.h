@@ -293,6 +293,19 @@ int fz_selector_train(fz_ctx *ctx, const float *d_feat, const uint32_t *d_costs,
 int fz_selector_grad(fz_ctx *ctx, const float *d_feat, const float *d_target, uint64_t n, float *h_grad,
                      float *h_loss, void *stream);
 
+/* One Adam step (Kingma and Ba) of the training kernel on host arrays of
+ * FZ_SELECTOR_PARAMS floats each, in place: for every learned parameter
+ * (W1 onwards; mu and rs are left as they are)
+ *   m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
+ *   w -= lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps),
+ * step number t >= 1, fp32.  The same kernel fz_selector_train runs after
+ * each minibatch; exposed for checks against a reference Adam.  Copies the
+ * four arrays through device memory the context allocates for the call;
+ * synchronises `stream`.  FZ_ERR_ARG for a null array, t < 1, lr <= 0,
+ * eps <= 0 or a beta outside [0, 1). */
+int fz_selector_adam_step(fz_ctx *ctx, float *h_w, float *h_m, float *h_v, const float *h_g, int t, float lr,
+                          float beta1, float beta2, float eps, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

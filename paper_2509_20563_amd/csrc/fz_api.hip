@@ -21,18 +21,28 @@ namespace {
 
 constexpr int kMaxStages = 16;
 
-// A buffer a context replaces is retired, not freed: a captured batch graph
-// may still reference it (freeing memory a live graph references and then
-// destroying or replaying that graph is a use after free in the runtime).
-void retire(fz_ctx* c, void* p, bool host);
-
+// Grow a device buffer to `need` elements (contents are not kept).  Batch
+// graphs reference only buffers of their own kind, and a batch call drops
+// its kind's graph before it grows any of them, so the old buffer is freed
+// at once.
 template <class T>
-hipError_t grow(fz_ctx* c, T*& p, uint64_t& cap, uint64_t need) {
+hipError_t grow(T*& p, uint64_t& cap, uint64_t need) {
     if (need <= cap && p) return hipSuccess;
-    retire(c, p, false);
+    hipFree(p);
     p = nullptr;
     cap = 0;
     hipError_t e = hipMalloc((void**)&p, sizeof(T) * (need ? need : 1));
+    if (e == hipSuccess) cap = need;
+    return e;
+}
+
+template <class T>
+hipError_t grow_pinned(T*& p, uint64_t& cap, uint64_t need) {
+    if (need <= cap && p) return hipSuccess;
+    if (p) hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    hipError_t e = hipHostMalloc((void**)&p, sizeof(T) * (need ? need : 1), hipHostMallocDefault);
     if (e == hipSuccess) cap = need;
     return e;
 }
@@ -47,23 +57,13 @@ struct GraphCache {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<uint8_t> key;
-    uint64_t at = 0;  // capture epoch of the owning context
     void drop() {
         if (exec) hipGraphExecDestroy(exec);
         if (graph) hipGraphDestroy(graph);
         exec = nullptr;
         graph = nullptr;
         key.clear();
-        at = 0;
     }
-};
-
-// A retired buffer and the owning context's capture epoch when it was
-// retired: graphs captured at or before that epoch may reference it.
-struct DeadBuf {
-    void* p;
-    bool host;
-    uint64_t r;
 };
 
 struct Tune {
@@ -72,6 +72,29 @@ struct Tune {
 };
 
 }  // namespace
+
+// Everything one kind of batch call (compression or decompression) uses
+// inside its captured graph: the chain contexts (each with its own scratch)
+// and their streams, the per-field records with their pinned host copy, the
+// offsets, a staging buffer (compression: the containers before packing;
+// decompression: the gathered headers) and the graph itself.  The two kinds
+// share none of it, so a call of one kind never reallocates memory that the
+// other kind's graph references; a call drops its own graph before it
+// reallocates or re-prepares anything (drop_and_grow below).
+struct BatchSide {
+    fz_ctx* kids[kMaxChains] = {};
+    hipStream_t kstream[kMaxChains] = {};
+    int nkids = 0;
+    uint64_t* rec = nullptr;  // 5 u64 per field
+    uint64_t* offs = nullptr;  // n + 1
+    uint8_t* buf = nullptr;
+    uint64_t rec_cap = 0, offs_cap = 0, buf_cap = 0;
+    uint64_t* h_rec = nullptr;  // pinned copies
+    uint64_t* h_offs = nullptr;
+    uint8_t* h_buf = nullptr;
+    uint64_t h_rec_cap = 0, h_offs_cap = 0, h_buf_cap = 0;
+    GraphCache g;
+};
 
 struct fz_ctx {
     int device = 0;
@@ -138,78 +161,17 @@ struct fz_ctx {
     // min/max: two workgroups per CU stream the field at close to full
     // bandwidth with few same-address atomics (which serialise at ~12 ns)
     Tune tune_default = {8, 2};
-    // batches: child contexts with their own scratch and stream (one chain
-    // of fields each), staging of the containers, per-field records, the
-    // captured graph of the last batch and the autotuner's choices
-    fz_ctx* kids[kMaxChains] = {};
-    hipStream_t kstream[kMaxChains] = {};
+    // batches: the compression and decompression resources (each with its
+    // own chain contexts, buffers and captured graph), the origin stream of
+    // captures, the fork/join events and the autotuner's choices
+    BatchSide bc, bd;
+    hipStream_t cstream = nullptr;
     hipEvent_t kev[kMaxChains + 1] = {};
-    int nkids = 0;
-    uint8_t* stage = nullptr;
-    uint64_t stage_cap = 0;
-    uint64_t* rec = nullptr;   // 5 u64 per field
-    uint64_t* offs = nullptr;  // n + 1
-    uint64_t rec_cap = 0, offs_cap = 0;
-    uint64_t* h_rec = nullptr;  // pinned copies
-    uint64_t* h_offs = nullptr;
-    uint64_t h_rec_cap = 0, h_offs_cap = 0;
-    uint8_t* hdrs = nullptr;  // gathered headers (device) and pinned copy
-    uint8_t* h_hdrs = nullptr;
-    uint64_t hdrs_cap = 0, h_hdrs_cap = 0;
-    hipStream_t cstream = nullptr;  // origin stream of graph captures
-    GraphCache gc, gd;              // compress / decompress batches
-    std::map<uint32_t, Tune> tune_field;   // per field class
+    std::map<uint32_t, Tune> tune_field;       // per field class
     std::map<uint32_t, uint32_t> tune_chains;  // per batch class
-    // graph bookkeeping: a chain context's root is the context whose graphs
-    // use its scratch; the root counts captures and keeps the buffers it or
-    // its chains replaced while a graph could still reference them
-    fz_ctx* root = nullptr;
-    uint64_t epoch = 0;
-    std::vector<DeadBuf> dead;
 };
 
 namespace {
-
-fz_ctx* root_of(fz_ctx* c) { return c->root ? c->root : c; }
-
-void free_buf(void* p, bool host) {
-    if (host) hipHostFree(p);
-    else hipFree(p);
-}
-
-// Free the retired buffers that no live graph can reference: those retired
-// after the capture of every live graph.
-void sweep(fz_ctx* r) {
-    uint64_t m = ~0ull;
-    if (r->gc.exec) m = std::min(m, r->gc.at);
-    if (r->gd.exec) m = std::min(m, r->gd.at);
-    size_t k = 0;
-    for (const DeadBuf& d : r->dead) {
-        if (d.r < m) free_buf(d.p, d.host);
-        else r->dead[k++] = d;
-    }
-    r->dead.resize(k);
-}
-
-void retire(fz_ctx* c, void* p, bool host) {
-    if (!p) return;
-    fz_ctx* r = root_of(c);
-    if (!r->gc.exec && !r->gd.exec) {
-        free_buf(p, host);
-        return;
-    }
-    r->dead.push_back(DeadBuf{p, host, r->epoch});
-}
-
-void drop_graph(fz_ctx* c, GraphCache& g) {
-    g.drop();
-    sweep(c);
-}
-
-void captured(fz_ctx* c, GraphCache& g) {
-    g.at = ++c->epoch;
-    sweep(c);
-}
 
 struct DeviceGuard {
     int prev = -1;
@@ -278,19 +240,19 @@ int ensure(fz_ctx* c, const Geom& g) {
     const uint64_t sd_tiles = scan_tiles((uint32_t)ntiles);
     const uint64_t sd_blocks = scan_tiles((uint32_t)nb);
     hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = grow(c, c->codes, c->codes_cap, nb * kBlockElems);
-    if (e == hipSuccess) e = grow(c, c->ostage, c->ostage_cap, slots);
-    if (e == hipSuccess) e = grow(c, c->pstage, c->pstage_cap, slots);
-    if (e == hipSuccess) e = grow(c, c->tile_cnt, c->tile_cnt_cap, ntiles);
-    if (e == hipSuccess) e = grow(c, c->tile_off, c->tile_off_cap, ntiles);
-    if (e == hipSuccess) e = grow(c, c->tile_start, c->tile_start_cap, ntiles);
-    if (e == hipSuccess) e = grow(c, c->tfirst, c->tfirst_cap, ntiles);
-    if (e == hipSuccess) e = grow(c, c->tlast, c->tlast_cap, ntiles);
-    if (e == hipSuccess) e = grow(c, c->desc_cnt, c->desc_cnt_cap, sd_tiles);
-    if (e == hipSuccess) e = grow(c, c->desc_bits, c->desc_bits_cap, encode_groups((uint32_t)ntiles));
-    if (e == hipSuccess) e = grow(c, c->desc_chunks, c->desc_chunks_cap, sd_blocks);
-    if (e == hipSuccess) e = grow(c, c->off, c->off_cap, nb);
-    if (e == hipSuccess) e = grow(c, c->oidx, c->oidx_cap, nb);
+    if (e == hipSuccess) e = grow(c->codes, c->codes_cap, nb * kBlockElems);
+    if (e == hipSuccess) e = grow(c->ostage, c->ostage_cap, slots);
+    if (e == hipSuccess) e = grow(c->pstage, c->pstage_cap, slots);
+    if (e == hipSuccess) e = grow(c->tile_cnt, c->tile_cnt_cap, ntiles);
+    if (e == hipSuccess) e = grow(c->tile_off, c->tile_off_cap, ntiles);
+    if (e == hipSuccess) e = grow(c->tile_start, c->tile_start_cap, ntiles);
+    if (e == hipSuccess) e = grow(c->tfirst, c->tfirst_cap, ntiles);
+    if (e == hipSuccess) e = grow(c->tlast, c->tlast_cap, ntiles);
+    if (e == hipSuccess) e = grow(c->desc_cnt, c->desc_cnt_cap, sd_tiles);
+    if (e == hipSuccess) e = grow(c->desc_bits, c->desc_bits_cap, encode_groups((uint32_t)ntiles));
+    if (e == hipSuccess) e = grow(c->desc_chunks, c->desc_chunks_cap, sd_blocks);
+    if (e == hipSuccess) e = grow(c->off, c->off_cap, nb);
+    if (e == hipSuccess) e = grow(c->oidx, c->oidx_cap, nb);
     return e == hipSuccess ? FZ_OK : FZ_ERR_NOMEM;
 }
 
@@ -298,12 +260,12 @@ int ensure(fz_ctx* c, const Geom& g) {
 int ensure_pred(fz_ctx* c, const Geom& g, bool decode) {
     const uint64_t nb = g.nblocks;
     hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = grow(c, c->bpred, c->bpred_cap, nb);
-    if (e == hipSuccess) e = grow(c, c->reg_idx, c->reg_idx_cap, nb);
-    if (e == hipSuccess) e = grow(c, c->coef, c->coef_cap, 4 * nb);
-    if (e == hipSuccess) e = grow(c, c->costs, c->costs_cap, 3 * nb);
-    if (e == hipSuccess) e = grow(c, c->desc_pmap, c->desc_pmap_cap, scan_tiles((uint32_t)nb));
-    if (e == hipSuccess && decode) e = grow(c, c->res, c->res_cap, nb * kBlockElems);
+    if (e == hipSuccess) e = grow(c->bpred, c->bpred_cap, nb);
+    if (e == hipSuccess) e = grow(c->reg_idx, c->reg_idx_cap, nb);
+    if (e == hipSuccess) e = grow(c->coef, c->coef_cap, 4 * nb);
+    if (e == hipSuccess) e = grow(c->costs, c->costs_cap, 3 * nb);
+    if (e == hipSuccess) e = grow(c->desc_pmap, c->desc_pmap_cap, scan_tiles((uint32_t)nb));
+    if (e == hipSuccess && decode) e = grow(c->res, c->res_cap, nb * kBlockElems);
     return e == hipSuccess ? FZ_OK : FZ_ERR_NOMEM;
 }
 
@@ -456,7 +418,7 @@ int compress_prepare(fz_ctx* c, const fz_params* p, const Geom& g) {
     int rc = ensure(c, g);
     if (rc == FZ_OK && p->pred != FZ_PRED_LORENZO1) rc = ensure_pred(c, g, false);
     if (rc == FZ_OK && p->pred == FZ_PRED_AUTO_MLP &&
-        grow(c, c->featb, c->featb_cap, (uint64_t)g.nblocks * kNFeat) != hipSuccess)
+        grow(c->featb, c->featb_cap, (uint64_t)g.nblocks * kNFeat) != hipSuccess)
         rc = FZ_ERR_NOMEM;
     return rc;
 }
@@ -613,6 +575,28 @@ int decode_status(const Misc& m, const Parsed& r) {
     return FZ_OK;
 }
 
+// Release one kind's batch resources: the graph first (it references the
+// rest), then the chain contexts, their streams and the buffers.
+void destroy_side(BatchSide& b) {
+    b.g.drop();
+    for (int k = 0; k < b.nkids; k++) {
+        fz_ctx_destroy(b.kids[k]);
+        if (b.kstream[k]) hipStreamDestroy(b.kstream[k]);
+        b.kids[k] = nullptr;
+        b.kstream[k] = nullptr;
+    }
+    b.nkids = 0;
+    hipFree(b.rec);
+    hipFree(b.offs);
+    hipFree(b.buf);
+    if (b.h_rec) hipHostFree(b.h_rec);
+    if (b.h_offs) hipHostFree(b.h_offs);
+    if (b.h_buf) hipHostFree(b.h_buf);
+    b.rec = b.offs = b.h_rec = b.h_offs = nullptr;
+    b.buf = b.h_buf = nullptr;
+    b.rec_cap = b.offs_cap = b.buf_cap = b.h_rec_cap = b.h_offs_cap = b.h_buf_cap = 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -657,10 +641,8 @@ void fz_ctx_destroy(fz_ctx* c) {
     if (!c) return;
     DeviceGuard dg(c->device);
     // the graphs go first: they reference the buffers freed below
-    c->gc.drop();
-    c->gd.drop();
-    for (const DeadBuf& d : c->dead) free_buf(d.p, d.host);
-    c->dead.clear();
+    destroy_side(c->bc);
+    destroy_side(c->bd);
     hipFree(c->misc);
     hipFree(c->hist);
     hipFree(c->cw);
@@ -686,20 +668,9 @@ void fz_ctx_destroy(fz_ctx* c) {
     hipFree(c->cw_ref);
     hipFree(c->lens_ref);
     hipFree(c->sel);
-    for (int k = 0; k < c->nkids; k++) {
-        fz_ctx_destroy(c->kids[k]);
-        if (c->kstream[k]) hipStreamDestroy(c->kstream[k]);
-    }
     for (int k = 0; k <= kMaxChains; k++)
         if (c->kev[k]) hipEventDestroy(c->kev[k]);
     if (c->cstream) hipStreamDestroy(c->cstream);
-    hipFree(c->stage);
-    hipFree(c->rec);
-    hipFree(c->offs);
-    hipFree(c->hdrs);
-    if (c->h_rec) hipHostFree(c->h_rec);
-    if (c->h_offs) hipHostFree(c->h_offs);
-    if (c->h_hdrs) hipHostFree(c->h_hdrs);
     hipFree(c->desc_pmap);
     hipFree(c->res);
     if (c->h_misc) hipHostFree(c->h_misc);
@@ -858,7 +829,7 @@ int fz_block_select(fz_ctx* c, const fz_params* p, const float* d_in, uint8_t* d
     hipStream_t st = (hipStream_t)stream;
     int rc = analysis_begin(c, p, d_in, st, &g, &vec, &ntiles, &grid);
     if (rc) return rc;
-    if (grow(c, c->featb, c->featb_cap, (uint64_t)g.nblocks * kNFeat) != hipSuccess) return FZ_ERR_NOMEM;
+    if (grow(c->featb, c->featb_cap, (uint64_t)g.nblocks * kNFeat) != hipSuccess) return FZ_ERR_NOMEM;
     t_start(c, st, "select");
     launch_features(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->featb);
     launch_mlp(st, grid, c->featb, g.nblocks, c->sel, d_y, d_choice);
@@ -1050,19 +1021,32 @@ int fz_selector_grad(fz_ctx* c, const float* d_feat, const float* d_target, uint
     return FZ_OK;
 }
 
+int fz_selector_adam_step(fz_ctx* c, float* h_w, float* h_m, float* h_v, const float* h_g, int t, float lr,
+                          float beta1, float beta2, float eps, void* stream) {
+    if (!c || !h_w || !h_m || !h_v || !h_g || t < 1 || !(lr > 0.0f) || !(eps > 0.0f) || !(beta1 >= 0.0f) ||
+        !(beta1 < 1.0f) || !(beta2 >= 0.0f) || !(beta2 < 1.0f))
+        return FZ_ERR_ARG;
+    DeviceGuard dg(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    float* d = nullptr;  // w, m, v, g back to back
+    const size_t nb = sizeof(float) * kSelectorParams;
+    if (hipMalloc((void**)&d, 4 * nb) != hipSuccess) return FZ_ERR_NOMEM;
+    float* src[4] = {h_w, h_m, h_v, const_cast<float*>(h_g)};
+    bool ok = true;
+    for (int k = 0; ok && k < 4; k++)
+        ok = hipMemcpyAsync(d + k * kSelectorParams, src[k], nb, hipMemcpyHostToDevice, st) == hipSuccess;
+    if (ok) launch_adam(st, d, d + kSelectorParams, d + 2 * kSelectorParams, d + 3 * kSelectorParams, t, lr, beta1,
+                        beta2, eps);
+    for (int k = 0; ok && k < 3; k++)
+        ok = hipMemcpyAsync(src[k], d + k * kSelectorParams, nb, hipMemcpyDeviceToHost, st) == hipSuccess;
+    ok = ok && hipStreamSynchronize(st) == hipSuccess && hipGetLastError() == hipSuccess;
+    hipFree(d);
+    return ok ? FZ_OK : FZ_ERR_HIP;
+}
+
 }  // extern "C"
 
 namespace {
-
-hipError_t grow_pinned(fz_ctx* c, void** p, uint64_t& cap, uint64_t need) {
-    if (need <= cap && *p) return hipSuccess;
-    retire(c, *p, true);
-    *p = nullptr;
-    cap = 0;
-    hipError_t e = hipHostMalloc(p, need ? need : 1, hipHostMallocDefault);
-    if (e == hipSuccess) cap = need;
-    return e;
-}
 
 uint32_t ilog2_ceil(uint64_t v) {
     uint32_t l = 0;
@@ -1078,20 +1062,22 @@ uint32_t field_class(const fz_params* p, const Geom& g) {
 
 uint32_t batch_class(uint32_t n, uint64_t total) { return (ilog2_ceil(n) << 8) | ilog2_ceil(total); }
 
-int ensure_kids(fz_ctx* c, int k) {
+// The capture stream and fork/join events of the root context, and at least
+// k chain contexts of one batch kind (created on first use; never while
+// that kind's graph is alive: callers drop it first).
+int ensure_kids(fz_ctx* c, BatchSide& s, int k) {
     if (!c->cstream && hipStreamCreateWithFlags(&c->cstream, hipStreamNonBlocking) != hipSuccess) return FZ_ERR_HIP;
     for (int i = 0; i <= kMaxChains; i++)
         if (!c->kev[i] && hipEventCreateWithFlags(&c->kev[i], hipEventDisableTiming) != hipSuccess) return FZ_ERR_HIP;
-    while (c->nkids < k) {
+    while (s.nkids < k) {
         fz_ctx* kid = nullptr;
         int rc = fz_ctx_create(&kid, c->device, 0);
         if (rc) return rc;
-        if (hipStreamCreateWithFlags(&c->kstream[c->nkids], hipStreamNonBlocking) != hipSuccess) {
+        if (hipStreamCreateWithFlags(&s.kstream[s.nkids], hipStreamNonBlocking) != hipSuccess) {
             fz_ctx_destroy(kid);
             return FZ_ERR_HIP;
         }
-        kid->root = c;
-        c->kids[c->nkids++] = kid;
+        s.kids[s.nkids++] = kid;
     }
     return FZ_OK;
 }
@@ -1101,12 +1087,7 @@ int ensure_kids(fz_ctx* c, int k) {
 std::vector<std::vector<uint32_t>> assign_chains(uint32_t n, const std::vector<Geom>& g, int K) {
     std::vector<uint32_t> order(n);
     for (uint32_t i = 0; i < n; i++) order[i] = i;
-    for (uint32_t i = 1; i < n; i++)  // insertion sort by N descending, stable
-        for (uint32_t j = i; j > 0 && g[order[j]].N > g[order[j - 1]].N; j--) {
-            const uint32_t t = order[j];
-            order[j] = order[j - 1];
-            order[j - 1] = t;
-        }
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return g[a].N > g[b].N; });
     std::vector<std::vector<uint32_t>> chains(K);
     std::vector<uint64_t> load(K, 0);
     for (uint32_t i : order) {
@@ -1123,15 +1104,6 @@ template <class T>
 void key_put(std::vector<uint8_t>& k, const T& v) {
     const uint8_t* b = reinterpret_cast<const uint8_t*>(&v);
     k.insert(k.end(), b, b + sizeof(T));
-}
-
-// Every scratch pointer of a context (a captured graph holds them).
-void key_scratch(std::vector<uint8_t>& k, const fz_ctx* c) {
-    const void* ps[] = {c->misc, c->hist, c->cw, c->lut, c->codes, c->ostage, c->pstage,
-                        c->tile_cnt, c->tile_off, c->tile_start, c->tfirst, c->tlast, c->desc_cnt,
-                        c->desc_bits, c->desc_chunks, c->off, c->oidx, c->bpred, c->reg_idx, c->coef, c->costs,
-                        c->cw_ref, c->lens_ref, c->desc_pmap, c->res, c->sel, c->featb};
-    for (const void* q : ps) key_put(k, q);
 }
 
 Tune tune_of(fz_ctx* c, const fz_params* p, const Geom& g) {
@@ -1171,86 +1143,101 @@ int batch_check(fz_ctx* c, uint32_t n, const fz_params* p, const float* const* d
     return FZ_OK;
 }
 
+// Fork the K chain streams from the capture stream, and join them back.
+void fork_chains(fz_ctx* c, BatchSide& s, int K) {
+    hipEventRecord(c->kev[kMaxChains], c->cstream);
+    for (int k = 0; k < K; k++) hipStreamWaitEvent(s.kstream[k], c->kev[kMaxChains], 0);
+}
+void join_chains(fz_ctx* c, BatchSide& s, int K) {
+    for (int k = 0; k < K; k++) {
+        hipEventRecord(c->kev[k], s.kstream[k]);
+        hipStreamWaitEvent(c->cstream, c->kev[k], 0);
+    }
+}
+
+// End a capture on the root's capture stream and instantiate it as the
+// side's graph.
+int finish_capture(fz_ctx* c, BatchSide& s, std::vector<uint8_t>&& key) {
+    hipGraph_t graph = nullptr;
+    if (hipStreamEndCapture(c->cstream, &graph) != hipSuccess || !graph) {
+        hipGetLastError();
+        return FZ_ERR_HIP;
+    }
+    s.g.graph = graph;
+    if (hipGraphInstantiate(&s.g.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        s.g.drop();
+        return FZ_ERR_HIP;
+    }
+    s.g.key = std::move(key);
+    return FZ_OK;
+}
+
 // Run (capturing first if the batch differs from the cached one) a batch
 // compression with K chains and the given per-field launch knobs.
 int batch_compress_run(fz_ctx* c, const BatchIn& b, uint8_t* d_out, hipStream_t st, int K,
                        const std::vector<Tune>& tunes) {
+    BatchSide& s = c->bc;
     const uint32_t n = b.n;
-    int rc = ensure_kids(c, K);
-    if (rc) return rc;
-    hipError_t e = grow(c, c->stage, c->stage_cap, b.slot[n]);
-    if (e == hipSuccess) e = grow(c, c->rec, c->rec_cap, 5ull * n);
-    if (e == hipSuccess) e = grow(c, c->offs, c->offs_cap, (uint64_t)n + 1);
-    if (e == hipSuccess) e = grow_pinned(c, (void**)&c->h_rec, c->h_rec_cap, 40ull * n);
-    if (e == hipSuccess) e = grow_pinned(c, (void**)&c->h_offs, c->h_offs_cap, 8ull * (n + 1));
-    if (e != hipSuccess) return FZ_ERR_NOMEM;
-    const auto chains = assign_chains(n, b.g, K);
     bool need_sel = false;
     for (uint32_t i = 0; i < n; i++) need_sel |= b.p[i].pred == FZ_PRED_AUTO_MLP;
-    for (int k = 0; k < K; k++) {
-        fz_ctx* kid = c->kids[k];
-        if (need_sel) {
-            if (hipMemcpy(kid->sel, c->sel, sizeof(float) * kSelectorParams, hipMemcpyDeviceToDevice) != hipSuccess)
-                return FZ_ERR_HIP;
-            kid->have_sel = true;
-        }
-        for (uint32_t i : chains[k]) {
-            rc = compress_prepare(kid, &b.p[i], b.g[i]);
-            if (rc) return rc;
-        }
-    }
+    // the batch's description: the graph is replayed only for the same one
+    // (then every buffer it references is still the one it was captured
+    // with: nothing of this kind is reallocated between captures)
     std::vector<uint8_t> key;
     key_put(key, n);
     key_put(key, K);
     key_put(key, d_out);
-    key_put(key, c->stage);
-    key_put(key, c->rec);
-    key_put(key, c->offs);
-    key_put(key, c->h_rec);
-    key_put(key, c->h_offs);
     for (uint32_t i = 0; i < n; i++) {
         key_put(key, b.p[i]);
         key_put(key, b.x[i]);
         key_put(key, tunes[i]);
     }
-    for (int k = 0; k < K; k++) key_scratch(key, c->kids[k]);  // scratch may have moved
-    if (key != c->gc.key || !c->gc.exec) {
-        drop_graph(c, c->gc);
-        hipStream_t cs = c->cstream;
-        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return FZ_ERR_HIP;
-        hipEventRecord(c->kev[kMaxChains], cs);
-        for (int k = 0; k < K; k++) hipStreamWaitEvent(c->kstream[k], c->kev[kMaxChains], 0);
+    if (key != s.g.key || !s.g.exec) {
+        // drop the old graph before anything it references is reallocated
+        s.g.drop();
+        int rc = ensure_kids(c, s, K);
+        if (rc) return rc;
+        hipError_t e = grow(s.buf, s.buf_cap, b.slot[n]);
+        if (e == hipSuccess) e = grow(s.rec, s.rec_cap, 3ull * n);
+        if (e == hipSuccess) e = grow(s.offs, s.offs_cap, (uint64_t)n + 1);
+        if (e == hipSuccess) e = grow_pinned(s.h_rec, s.h_rec_cap, 3ull * n);
+        if (e == hipSuccess) e = grow_pinned(s.h_offs, s.h_offs_cap, (uint64_t)n + 1);
+        if (e != hipSuccess) return FZ_ERR_NOMEM;
+        const auto chains = assign_chains(n, b.g, K);
         for (int k = 0; k < K; k++)
             for (uint32_t i : chains[k]) {
-                compress_enqueue(c->kids[k], &b.p[i], b.g[i], b.x[i], c->stage + b.slot[i], c->kstream[k], tunes[i],
-                                 false);
-                launch_field_record(c->kstream[k], c->kids[k]->misc, b.slot[i], c->rec + 3ull * i, 0);
+                rc = compress_prepare(s.kids[k], &b.p[i], b.g[i]);
+                if (rc) return rc;
             }
-        for (int k = 0; k < K; k++) {
-            hipEventRecord(c->kev[k], c->kstream[k]);
-            hipStreamWaitEvent(cs, c->kev[k], 0);
-        }
-        launch_pack(cs, c->stage, c->rec, c->offs, n, d_out);
-        hipMemcpyAsync(c->h_rec, c->rec, 24ull * n, hipMemcpyDeviceToHost, cs);
-        hipMemcpyAsync(c->h_offs, c->offs, 8ull * (n + 1), hipMemcpyDeviceToHost, cs);
-        hipGraph_t graph = nullptr;
-        if (hipStreamEndCapture(cs, &graph) != hipSuccess || !graph) {
-            hipGetLastError();
-            return FZ_ERR_HIP;
-        }
-        c->gc.graph = graph;
-        if (hipGraphInstantiate(&c->gc.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-            drop_graph(c, c->gc);
-            return FZ_ERR_HIP;
-        }
-        c->gc.key = key;
-        captured(c, c->gc);
+        if (hipStreamBeginCapture(c->cstream, hipStreamCaptureModeThreadLocal) != hipSuccess) return FZ_ERR_HIP;
+        fork_chains(c, s, K);
+        for (int k = 0; k < K; k++)
+            for (uint32_t i : chains[k]) {
+                compress_enqueue(s.kids[k], &b.p[i], b.g[i], b.x[i], s.buf + b.slot[i], s.kstream[k], tunes[i],
+                                 false);
+                launch_field_record(s.kstream[k], s.kids[k]->misc, b.slot[i], s.rec + 3ull * i, 0);
+            }
+        join_chains(c, s, K);
+        launch_pack(c->cstream, s.buf, s.rec, s.offs, n, d_out);
+        hipMemcpyAsync(s.h_rec, s.rec, 24ull * n, hipMemcpyDeviceToHost, c->cstream);
+        hipMemcpyAsync(s.h_offs, s.offs, 8ull * (n + 1), hipMemcpyDeviceToHost, c->cstream);
+        rc = finish_capture(c, s, std::move(key));
+        if (rc) return rc;
     }
-    if (hipGraphLaunch(c->gc.exec, st) != hipSuccess) return FZ_ERR_HIP;
+    // the selector of the AUTO_MLP fields: the root's current parameters
+    // (each chain reads its own copy, at an address fixed for its lifetime)
+    if (need_sel)
+        for (int k = 0; k < K; k++) {
+            if (hipMemcpy(s.kids[k]->sel, c->sel, sizeof(float) * kSelectorParams, hipMemcpyDeviceToDevice) !=
+                hipSuccess)
+                return FZ_ERR_HIP;
+            s.kids[k]->have_sel = true;
+        }
+    if (hipGraphLaunch(s.g.exec, st) != hipSuccess) return FZ_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
     if (hipGetLastError() != hipSuccess) return FZ_ERR_HIP;
     for (uint32_t i = 0; i < n; i++) {
-        rc = flags_status((uint32_t)c->h_rec[3 * i + 2] & ~(uint32_t)F_CORRUPT);
+        int rc = flags_status((uint32_t)s.h_rec[3 * i + 2] & ~(uint32_t)F_CORRUPT);
         if (rc) return rc;
     }
     return FZ_OK;
@@ -1287,16 +1274,17 @@ int fz_compress_batch(fz_ctx* c, uint32_t n, const fz_params* p, const float* co
     }
     rc = batch_compress_run(c, b, (uint8_t*)d_out, (hipStream_t)stream, chains_of(c, n, total), tunes);
     if (rc) return rc;
-    for (uint32_t i = 0; i <= n; i++) h_offsets[i] = c->h_offs[i];
+    for (uint32_t i = 0; i <= n; i++) h_offsets[i] = c->bc.h_offs[i];
     return FZ_OK;
 }
 
 int fz_batch_autotune(fz_ctx* c, uint32_t n, const fz_params* p, const float* const* d_in, void* d_out,
                       uint64_t out_cap, void* stream) {
     if (!c || !n || !p || !d_in || !d_out || ((uintptr_t)d_out & 15)) return FZ_ERR_ARG;
-    // switched off: a run of the autotuner over twelve launch configurations
-    // ended in a host segmentation fault whose cause is not found yet; the
-    // batch calls use the default knobs meanwhile
+    // switched off: a run over the twelve launch configurations ended in a
+    // host crash whose cause is not found (the library's buffer lifetimes
+    // are cleared by a replay on a stub runtime); batches use the default
+    // knobs meanwhile
     if (kAutotuneOff) return FZ_ERR_UNSUPPORTED;
     BatchIn b;
     int rc = batch_check(c, n, p, d_in, &b);
@@ -1325,7 +1313,7 @@ int fz_batch_autotune(fz_ctx* c, uint32_t n, const fz_params* p, const float* co
             if (rc) break;
             hipEventRecord(e0, st);
             for (int r = 0; r < 3 && rc == FZ_OK; r++)
-                if (hipGraphLaunch(c->gc.exec, st) != hipSuccess) rc = FZ_ERR_HIP;
+                if (hipGraphLaunch(c->bc.g.exec, st) != hipSuccess) rc = FZ_ERR_HIP;
             hipEventRecord(e1, st);
             if (rc || hipEventSynchronize(e1) != hipSuccess) {
                 rc = rc ? rc : FZ_ERR_HIP;
@@ -1370,27 +1358,34 @@ int fz_decompress_batch(fz_ctx* c, uint32_t n, const void* d_in, const uint64_t*
         if ((h_offsets[i] & 15) || h_offsets[i + 1] < h_offsets[i] + kHdr) return FZ_ERR_CORRUPT;
     }
     DeviceGuard dg(c->device);
+    BatchSide& s = c->bd;
     hipStream_t st = (hipStream_t)stream;
     const uint8_t* in = (const uint8_t*)d_in;
-    hipError_t e = grow(c, c->offs, c->offs_cap, (uint64_t)n + 1);
-    if (e == hipSuccess) e = grow(c, c->hdrs, c->hdrs_cap, (uint64_t)kHdr * n);
-    if (e == hipSuccess) e = grow(c, c->rec, c->rec_cap, 5ull * n);
-    if (e == hipSuccess) e = grow_pinned(c, (void**)&c->h_hdrs, c->h_hdrs_cap, (uint64_t)kHdr * n);
-    if (e == hipSuccess) e = grow_pinned(c, (void**)&c->h_offs, c->h_offs_cap, 8ull * (n + 1));
-    if (e == hipSuccess) e = grow_pinned(c, (void**)&c->h_rec, c->h_rec_cap, 40ull * n);
+    // the header gather uses the side's offsets and staging; the graph
+    // references only its records, but a batch of more fields than the
+    // last is a new description anyway, so the graph goes first
+    if ((uint64_t)n + 1 > s.offs_cap || (uint64_t)kHdr * n > s.buf_cap || (uint64_t)kHdr * n > s.h_buf_cap ||
+        (uint64_t)n + 1 > s.h_offs_cap || 5ull * n > s.rec_cap || 5ull * n > s.h_rec_cap)
+        s.g.drop();
+    hipError_t e = grow(s.offs, s.offs_cap, (uint64_t)n + 1);
+    if (e == hipSuccess) e = grow(s.buf, s.buf_cap, (uint64_t)kHdr * n);
+    if (e == hipSuccess) e = grow(s.rec, s.rec_cap, 5ull * n);
+    if (e == hipSuccess) e = grow_pinned(s.h_buf, s.h_buf_cap, (uint64_t)kHdr * n);
+    if (e == hipSuccess) e = grow_pinned(s.h_offs, s.h_offs_cap, (uint64_t)n + 1);
+    if (e == hipSuccess) e = grow_pinned(s.h_rec, s.h_rec_cap, 5ull * n);
     if (e != hipSuccess) return FZ_ERR_NOMEM;
     // headers: one gather, one copy, one synchronisation
-    for (uint32_t i = 0; i <= n; i++) c->h_offs[i] = h_offsets[i];
-    if (hipMemcpyAsync(c->offs, c->h_offs, 8ull * (n + 1), hipMemcpyHostToDevice, st) != hipSuccess) return FZ_ERR_HIP;
-    launch_gather_headers(st, in, c->offs, n, c->hdrs);
-    if (hipMemcpyAsync(c->h_hdrs, c->hdrs, (uint64_t)kHdr * n, hipMemcpyDeviceToHost, st) != hipSuccess)
+    for (uint32_t i = 0; i <= n; i++) s.h_offs[i] = h_offsets[i];
+    if (hipMemcpyAsync(s.offs, s.h_offs, 8ull * (n + 1), hipMemcpyHostToDevice, st) != hipSuccess) return FZ_ERR_HIP;
+    launch_gather_headers(st, in, s.offs, n, s.buf);
+    if (hipMemcpyAsync(s.h_buf, s.buf, (uint64_t)kHdr * n, hipMemcpyDeviceToHost, st) != hipSuccess)
         return FZ_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
     std::vector<Parsed> r(n);
     std::vector<Geom> g(n);
     uint64_t total = 0;
     for (uint32_t i = 0; i < n; i++) {
-        int rc = parse_header(c->h_hdrs + (uint64_t)kHdr * i, kHdr, &r[i]);
+        int rc = parse_header(s.h_buf + (uint64_t)kHdr * i, kHdr, &r[i]);
         if (rc) return rc;
         if (r[i].total > h_offsets[i + 1] - h_offsets[i]) return FZ_ERR_CORRUPT;
         if (out_elems[i] < r[i].g.N) return FZ_ERR_CAPACITY;
@@ -1398,68 +1393,50 @@ int fz_decompress_batch(fz_ctx* c, uint32_t n, const void* d_in, const uint64_t*
         total += g[i].N;
     }
     const int K = chains_of(c, n, total);
-    int rc = ensure_kids(c, K);
-    if (rc) return rc;
-    const auto chains = assign_chains(n, g, K);
-    for (int k = 0; k < K; k++)
-        for (uint32_t i : chains[k]) {
-            rc = decompress_prepare(c->kids[k], r[i]);
-            if (rc) return rc;
-        }
     std::vector<uint8_t> key;
     key_put(key, n);
     key_put(key, K);
     key_put(key, d_in);
-    key_put(key, c->rec);
-    key_put(key, c->h_rec);
-    key.insert(key.end(), c->h_hdrs, c->h_hdrs + (uint64_t)kHdr * n);
+    key.insert(key.end(), s.h_buf, s.h_buf + (uint64_t)kHdr * n);
     for (uint32_t i = 0; i < n; i++) {
         key_put(key, h_offsets[i]);
         key_put(key, d_out[i]);
     }
-    for (int k = 0; k < K; k++) key_scratch(key, c->kids[k]);
-    if (key != c->gd.key || !c->gd.exec) {
-        drop_graph(c, c->gd);
-        hipStream_t cs = c->cstream;
-        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return FZ_ERR_HIP;
-        hipEventRecord(c->kev[kMaxChains], cs);
-        for (int k = 0; k < K; k++) hipStreamWaitEvent(c->kstream[k], c->kev[kMaxChains], 0);
+    if (key != s.g.key || !s.g.exec) {
+        s.g.drop();
+        int rc = ensure_kids(c, s, K);
+        if (rc) return rc;
+        const auto chains = assign_chains(n, g, K);
         for (int k = 0; k < K; k++)
             for (uint32_t i : chains[k]) {
-                decompress_enqueue(c->kids[k], r[i], in + h_offsets[i], d_out[i], c->kstream[k], false);
-                if (!r[i].verbatim) launch_field_record(c->kstream[k], c->kids[k]->misc, 0, c->rec + 5ull * i, 1);
+                rc = decompress_prepare(s.kids[k], r[i]);
+                if (rc) return rc;
             }
-        for (int k = 0; k < K; k++) {
-            hipEventRecord(c->kev[k], c->kstream[k]);
-            hipStreamWaitEvent(cs, c->kev[k], 0);
-        }
-        hipMemcpyAsync(c->h_rec, c->rec, 40ull * n, hipMemcpyDeviceToHost, cs);
-        hipGraph_t graph = nullptr;
-        if (hipStreamEndCapture(cs, &graph) != hipSuccess || !graph) {
-            hipGetLastError();
-            return FZ_ERR_HIP;
-        }
-        c->gd.graph = graph;
-        if (hipGraphInstantiate(&c->gd.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-            drop_graph(c, c->gd);
-            return FZ_ERR_HIP;
-        }
-        c->gd.key = key;
-        captured(c, c->gd);
+        if (hipStreamBeginCapture(c->cstream, hipStreamCaptureModeThreadLocal) != hipSuccess) return FZ_ERR_HIP;
+        fork_chains(c, s, K);
+        for (int k = 0; k < K; k++)
+            for (uint32_t i : chains[k]) {
+                decompress_enqueue(s.kids[k], r[i], in + h_offsets[i], d_out[i], s.kstream[k], false);
+                if (!r[i].verbatim) launch_field_record(s.kstream[k], s.kids[k]->misc, 0, s.rec + 5ull * i, 1);
+            }
+        join_chains(c, s, K);
+        hipMemcpyAsync(s.h_rec, s.rec, 40ull * n, hipMemcpyDeviceToHost, c->cstream);
+        rc = finish_capture(c, s, std::move(key));
+        if (rc) return rc;
     }
-    if (hipGraphLaunch(c->gd.exec, st) != hipSuccess) return FZ_ERR_HIP;
+    if (hipGraphLaunch(s.g.exec, st) != hipSuccess) return FZ_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
     if (hipGetLastError() != hipSuccess) return FZ_ERR_HIP;
     for (uint32_t i = 0; i < n; i++) {
         if (r[i].verbatim) continue;
         Misc m = {};
-        const uint64_t* q = c->h_rec + 5ull * i;
+        const uint64_t* q = s.h_rec + 5ull * i;
         m.flags = (uint32_t)q[0];
         m.code0_count = (uint32_t)q[1];
         m.nreg = q[2];
         m.ohash_dec = q[3];
         m.ohash_list = q[4];
-        rc = decode_status(m, r[i]);
+        int rc = decode_status(m, r[i]);
         if (rc) return rc;
     }
     return FZ_OK;

@@ -116,6 +116,9 @@ def lib() -> ctypes.CDLL:
     L.fz_selector_train.restype = i32
     L.fz_selector_grad.argtypes = [vp, vp, vp, u64, vp, vp, vp]
     L.fz_selector_grad.restype = i32
+    L.fz_selector_adam_step.argtypes = [vp, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                        ctypes.c_float, vp]
+    L.fz_selector_adam_step.restype = i32
     _lib = L
     return L
 
@@ -424,6 +427,18 @@ class Context:
                                       feat.shape[0], g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss),
                                       _stream_handle(feat.device)), "fz_selector_grad")
         return g, loss.value
+
+    def selector_adam_step(self, w, m, v, g, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        """One Adam step of the training kernel on copies of host float32
+        arrays (5475,): returns the new (w, m, v)."""
+        import numpy as np
+        arrs = [np.ascontiguousarray(a, dtype=np.float32).copy() for a in (w, m, v, g)]
+        if any(a.shape != (SELECTOR_PARAMS,) for a in arrs):
+            raise ValueError(f"arrays of {SELECTOR_PARAMS} floats")
+        ptr = [a.ctypes.data_as(ctypes.c_void_p) for a in arrs]
+        _check(lib().fz_selector_adam_step(self._h, *ptr, int(t), lr, beta1, beta2, eps,
+                                           _stream_handle(self.device)), "fz_selector_adam_step")
+        return arrs[0], arrs[1], arrs[2]
 
     def selector_save(self, path: str):
         _check(lib().fz_selector_save(self._h, os.fsencode(path)), "fz_selector_save")

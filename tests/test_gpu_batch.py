@@ -80,9 +80,10 @@ def test_batch_decompress(fz, ctx):
 
 
 @pytest.mark.skip(reason="fz_batch_autotune ended twice in a host segmentation fault (twelve launch "
-                         "configurations captured and replayed); retiring replaced buffers while graphs live did "
-                         "not cure it, the cause is not found, so the autotuner is switched off "
-                         "(FZ_ERR_UNSUPPORTED) and this case stays off the GPU until a cause is shown")
+                         "configurations captured and replayed); a CPU replay of this sequence against a stub "
+                         "runtime (test_batch_lifetime.py) finds no captured node touching freed memory, so the "
+                         "library's buffer lifetimes are cleared but no cause is shown; the autotuner stays "
+                         "switched off (FZ_ERR_UNSUPPORTED) and this case off the GPU")
 def test_autotune_keeps_containers(fz, ctx):
     batch = _small_batch()
     xs, p0, o0 = _run(fz, ctx, batch)
@@ -107,8 +108,9 @@ def _pack_singles(ctx, xs, eb):
 
 
 @pytest.mark.skip(reason="ended twice in a host segmentation fault inside fz_compress_batch (80 one-block fields "
-                         "after batches of both kinds); retiring replaced buffers while graphs live did not cure it, "
-                         "the cause is not found, so this case stays off the GPU until one is shown")
+                         "after batches of both kinds); the CPU replay of this sequence (test_batch_lifetime.py) "
+                         "clears the library's buffer lifetimes, old and current bookkeeping alike, but shows no "
+                         "cause, so this case stays off the GPU")
 def test_batch_recapture_after_growth(fz, ctx):
     """Each kind of batch call keeps its last graph.  A batch call of the
     other kind with more fields grows the record and offset arrays and their

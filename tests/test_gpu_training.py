@@ -75,3 +75,30 @@ def test_training_lowers_loss_and_selects_well(fz, ctx):
             n_p0 = ctx.compress(x, eb, 1, pred=0).numel()
             print(f"[gpu training] seed {s} eb {eb}: bytes mlp {n_mlp} trial {n_trial} p0 {n_p0}", flush=True)
             assert n_mlp <= n_trial / 0.98
+
+
+def test_adam_step_matches_oracle(fz, ctx):
+    """The training's Adam kernel against the oracle's Adam (fp64) from the
+    same parameters, moments and gradient: first, second and a later step,
+    rel <= 1e-4 per tensor; mu and rs are left untouched by both."""
+    r = np.random.default_rng(11)
+    n = oracle.NPARAM
+    w = r.normal(0, 0.3, n).astype(np.float32)
+    m = np.zeros(n, np.float32)
+    v = np.zeros(n, np.float32)
+    wd, md, vd = w.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    o1 = oracle.OFF["W1"][0]
+    for t in (1, 2, 3, 50):
+        g = (r.normal(0, 1e-2, n) * r.uniform(0, 2, n)).astype(np.float32)
+        w, m, v = ctx.selector_adam_step(w, m, v, g, t)
+        oracle.adam_step(wd, md, vd, g.astype(np.float64), t)
+        for name, a, b in (("w", w, wd), ("m", m, md), ("v", v, vd)):
+            for tensor in ("W1", "b1", "W2", "b2", "W3", "b3"):
+                o, k = oracle.OFF[tensor]
+                e = _rel(a[o:o + k].astype(np.float64), b[o:o + k])
+                assert e <= 1e-4, (t, name, tensor, e)
+        assert np.array_equal(w[:o1].astype(np.float64), wd[:o1])
+        # keep both sides on the same inputs for the next step
+        wd, md, vd = w.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    with pytest.raises(fz.FZError):
+        ctx.selector_adam_step(w, m, v, g, 0)
