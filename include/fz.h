@@ -86,7 +86,8 @@ enum {
     FZ_ERR_HIP = -6,         /* a HIP runtime call failed                       */
     FZ_ERR_NOMEM = -7,       /* device or host allocation failed                */
     FZ_ERR_UNSUPPORTED = -8, /* valid but unsupported option (radius, predictor) */
-    FZ_ERR_INTERNAL = -9     /* a device-side consistency check failed          */
+    FZ_ERR_INTERNAL = -9,    /* a device-side consistency check failed          */
+    FZ_ERR_SCRATCH = -10     /* fz_decompress_noalloc: more blocks than its scratch holds */
 };
 
 typedef struct {
@@ -305,6 +306,26 @@ int fz_selector_grad(fz_ctx *ctx, const float *d_feat, const float *d_target, ui
  * eps <= 0 or a beta outside [0, 1). */
 int fz_selector_adam_step(fz_ctx *ctx, float *h_w, float *h_m, float *h_v, const float *h_g, int t, float lr,
                           float beta1, float beta2, float eps, void *stream);
+
+/* Allocation-free decompression, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments and results as fz_decompress, without a
+ * context: the scratch is one statically sized device array per GPU
+ * (fz_noalloc_scratch_bytes bytes, held until the process ends), found on
+ * the current device at the first call there.  Accepts first-order Lorenzo
+ * containers (FZ_PRED_LORENZO1) of at most FZ_NOALLOC_MAX_BLOCKS blocks and
+ * verbatim containers of any size; other predictors give
+ * FZ_ERR_UNSUPPORTED, more blocks FZ_ERR_SCRATCH, before any kernel runs.
+ * Every call on one GPU shares that GPU's array (each call clears what it
+ * needs first): calls that overlap on one GPU, on any streams or host
+ * threads, race and must be serialised by the caller.  Calls no hipMalloc or
+ * hipFree.  Synchronises `stream`. */
+#define FZ_NOALLOC_MAX_BLOCKS 131072u /* 2^26 values in full 8x8x8 blocks */
+int fz_decompress_noalloc(const void *d_in, uint64_t in_bytes, const void *h_hdr, float *d_out,
+                          uint64_t out_elems, void *stream);
+
+/* Size in bytes of the per-GPU scratch array of fz_decompress_noalloc. */
+uint64_t fz_noalloc_scratch_bytes(void);
 
 #ifdef __cplusplus
 }

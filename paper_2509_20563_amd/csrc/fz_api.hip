@@ -754,6 +754,49 @@ int fz_decompress(fz_ctx* c, const void* d_in, uint64_t in_bytes, const void* h_
     return r.verbatim ? FZ_OK : decode_status(*c->h_misc, r);
 }
 
+}  // extern "C"
+
+// First-order Lorenzo (or verbatim) decompression on scratch the caller
+// provides: the same kernels as fz_decompress, with the context's buffers
+// replaced by s.  Allocates nothing; the header comes from h_hdr or one
+// 128-byte copy into host stack memory, the status through another.
+int fz::decompress_on_scratch(const DecodeScratch& s, const void* d_in, uint64_t in_bytes, const void* h_hdr,
+                              float* d_out, uint64_t out_elems, hipStream_t st) {
+    if (!d_in || !d_out) return FZ_ERR_ARG;
+    if (((uintptr_t)d_in & 15) || ((uintptr_t)d_out & 3)) return FZ_ERR_ARG;
+    if (in_bytes < (uint64_t)kHdr) return FZ_ERR_CORRUPT;
+    const uint8_t* in = (const uint8_t*)d_in;
+    uint8_t hbuf[kHdr];
+    const uint8_t* hh = (const uint8_t*)h_hdr;
+    if (!hh) {
+        if (hipMemcpyAsync(hbuf, in, kHdr, hipMemcpyDeviceToHost, st) != hipSuccess) return FZ_ERR_HIP;
+        if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
+        hh = hbuf;
+    }
+    Parsed r;
+    int rc = parse_header(hh, kHdr, &r);
+    if (rc) return rc;
+    if (r.total > in_bytes) return FZ_ERR_CORRUPT;
+    if (out_elems < r.g.N) return FZ_ERR_CAPACITY;
+    if (!r.verbatim && r.p.pred != FZ_PRED_LORENZO1) return FZ_ERR_UNSUPPORTED;
+    if (!r.verbatim && r.g.nblocks > s.max_blocks) return FZ_ERR_SCRATCH;
+    fz_ctx c;  // stand-in holding the scratch pointers (owns nothing)
+    c.misc = s.misc;
+    c.hist = s.hist;
+    c.lut = s.lut;
+    c.desc_chunks = s.desc_chunks;
+    c.off = s.off;
+    c.oidx = s.oidx;
+    decompress_enqueue(&c, r, in, d_out, st, false);
+    Misc m;
+    if (hipMemcpyAsync(&m, s.misc, sizeof(Misc), hipMemcpyDeviceToHost, st) != hipSuccess) return FZ_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
+    if (hipGetLastError() != hipSuccess) return FZ_ERR_HIP;
+    return r.verbatim ? FZ_OK : decode_status(m, r);
+}
+
+extern "C" {
+
 uint64_t fz_block_count(const fz_params* p) {
     Geom g;
     if (!p || make_geom(p->ndim, p->dims, &g) != FZ_OK) return 0;
@@ -1496,6 +1539,7 @@ const char* fz_strerror(int s) {
         case FZ_ERR_NOMEM: return "out of memory";
         case FZ_ERR_UNSUPPORTED: return "unsupported option";
         case FZ_ERR_INTERNAL: return "internal consistency check failed";
+        case FZ_ERR_SCRATCH: return "container needs more scratch than the allocation-free decompression holds";
         default: return "unknown status";
     }
 }

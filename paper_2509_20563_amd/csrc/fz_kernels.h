@@ -81,4 +81,20 @@ void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, u
 void launch_patch(hipStream_t st, const Geom& g, const uint32_t* ppos, const uint32_t* pbits, uint64_t n_pat,
                   float* out, Misc* misc);
 
+// fz_api.hip: decompression of a first-order Lorenzo (or verbatim)
+// container on scratch the caller provides, for up to max_blocks blocks
+// (misc: one Misc; hist: kHistCopies * kBins; lut: kLut; desc_chunks:
+// scan_tiles(max_blocks); off and oidx: max_blocks each)
+struct DecodeScratch {
+    Misc* misc;
+    uint32_t* hist;
+    uint16_t* lut;
+    uint64_t* desc_chunks;
+    uint64_t* off;
+    uint2* oidx;
+    uint32_t max_blocks;
+};
+int decompress_on_scratch(const DecodeScratch& s, const void* d_in, uint64_t in_bytes, const void* h_hdr,
+                          float* d_out, uint64_t out_elems, hipStream_t st);
+
 }  // namespace fz

@@ -28,6 +28,7 @@ SELECTOR_PARAMS = 5475
 STATUS = {
     0: "FZ_OK", -1: "FZ_ERR_ARG", -2: "FZ_ERR_EB", -3: "FZ_ERR_NONFINITE", -4: "FZ_ERR_CAPACITY",
     -5: "FZ_ERR_CORRUPT", -6: "FZ_ERR_HIP", -7: "FZ_ERR_NOMEM", -8: "FZ_ERR_UNSUPPORTED", -9: "FZ_ERR_INTERNAL",
+    -10: "FZ_ERR_SCRATCH",
 }
 
 
@@ -119,6 +120,10 @@ def lib() -> ctypes.CDLL:
     L.fz_selector_adam_step.argtypes = [vp, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                         ctypes.c_float, vp]
     L.fz_selector_adam_step.restype = i32
+    L.fz_decompress_noalloc.argtypes = [vp, u64, vp, vp, u64, vp]
+    L.fz_decompress_noalloc.restype = i32
+    L.fz_noalloc_scratch_bytes.argtypes = []
+    L.fz_noalloc_scratch_bytes.restype = u64
     _lib = L
     return L
 
@@ -468,3 +473,25 @@ def compress(x: torch.Tensor, eb: float, mode: int = EB_REL) -> torch.Tensor:
 
 def decompress(buf: torch.Tensor, header: bytes | None = None) -> torch.Tensor:
     return context(buf.device.index or 0).decompress(buf, header)
+
+
+def decompress_noalloc(buf: torch.Tensor, out: torch.Tensor, header: bytes | None = None) -> torch.Tensor:
+    """fz_decompress_noalloc: decompress a first-order Lorenzo (or verbatim)
+    container into the caller's float32 device tensor `out`, with no device
+    allocation (the library's static per-GPU scratch)."""
+    if buf.dtype != torch.uint8 or not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("buf must be a contiguous uint8 device tensor")
+    if out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 device tensor")
+    h = None
+    if header is not None:
+        h = (ctypes.c_uint8 * HDR_BYTES).from_buffer_copy(bytes(header[:HDR_BYTES]))
+    with torch.cuda.device(buf.device):
+        rc = lib().fz_decompress_noalloc(ctypes.c_void_p(buf.data_ptr()), buf.numel(), h,
+                                         ctypes.c_void_p(out.data_ptr()), out.numel(), _stream_handle(buf.device))
+    _check(rc, "fz_decompress_noalloc")
+    return out
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().fz_noalloc_scratch_bytes())
