@@ -77,6 +77,9 @@ def lib():
         L.orc_adam_step.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double]
         L.orc_adam_step.restype = None
+        L.orc_speed_compress.argtypes = [vp, ctypes.c_int, u64p, ctypes.c_int, ctypes.c_double, vp,
+                                         ctypes.c_uint64, u64p]
+        L.orc_speed_stage.argtypes = [vp, ctypes.c_int, u64p, ctypes.c_int, ctypes.c_double, vp, vp]
         _lib = L
     return _lib
 
@@ -354,3 +357,35 @@ def adam_step(w, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     g = np.ascontiguousarray(g, dtype=np.float64)
     lib().orc_adam_step(_ptr(w), _ptr(m), _ptr(v), _ptr(g), int(t), lr, b1, b2, eps)
+
+
+# ----------------------------------------------------- bit-shuffle codec
+FLAG_SHUFFLE = 2
+SYM_OUTLIER = 1023
+
+
+def speed_compress(x, eb, mode=1):
+    """Bit-shuffle (FZMod-Speed) container of a float32 field, as bytes."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    nd, d = dims_of(x.shape)
+    cap = compress_bound(x.shape)
+    out = np.zeros(max(cap, HDR), np.uint8)
+    n = ctypes.c_uint64(0)
+    rc = lib().orc_speed_compress(_ptr(x), nd, d, int(mode), float(eb), _ptr(out), out.size, ctypes.byref(n))
+    if rc:
+        raise OracleError(rc)
+    return out[: n.value].tobytes()
+
+
+def speed_stage(x, eb, mode=1):
+    """(symbols (nblocks, 512) uint16, shuffled words (nblocks, 16, 10)
+    uint32) of a field, as the bit-shuffle codec computes them."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    nd, d = dims_of(x.shape)
+    nb = nblocks_of(x.shape)
+    sym = np.zeros((nb, 512), np.uint16)
+    words = np.zeros((nb, 16, 10), np.uint32)
+    rc = lib().orc_speed_stage(_ptr(x), nd, d, int(mode), float(eb), _ptr(sym), _ptr(words))
+    if rc:
+        raise OracleError(rc)
+    return sym, words

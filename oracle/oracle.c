@@ -60,6 +60,7 @@
 #define ORC_BLOCK_ELEMS 512   /* every block holds at most 512 values        */
 #define ORC_MAGIC 0x314D5A46u /* bytes 'F' 'Z' 'M' '1'                       */
 #define ORC_VERSION 1
+#define ORC_FLAG_SHUFFLE 2    /* header flag: bit-shuffle codec container    */
 
 /* ------------------------------------------------------------ block shapes
  * 1D blocks are 512 long, 2D blocks 32 (x) by 16 (y), 3D blocks 8x8x8.
@@ -838,6 +839,8 @@ int orc_header(const uint8_t *in, uint64_t n, int *ndim, uint64_t dims[3], int *
     return ORC_OK;
 }
 
+static int speed_decompress(const uint8_t *in, const geom_t *g, double eb_abs, float *out);
+
 int orc_decompress(const uint8_t *in, uint64_t n, float *out, uint64_t out_elems) {
     int ndim, mode, verbatim;
     uint64_t dims[3];
@@ -851,11 +854,13 @@ int orc_decompress(const uint8_t *in, uint64_t n, float *out, uint64_t out_elems
     if (out_elems < g.N) return ORC_ERR_CAPACITY;
     uint64_t total = ld64(in + 64);
     if (total > n) return ORC_ERR_CORRUPT;
+    if (ld16(in + 6) & ~(1 | ORC_FLAG_SHUFFLE)) return ORC_ERR_CORRUPT;
     if (verbatim) {
         if (total != ORC_HDR + 4 * g.N) return ORC_ERR_CORRUPT;
         memcpy(out, in + ORC_HDR, 4 * g.N);
         return ORC_OK;
     }
+    if (ld16(in + 6) & ORC_FLAG_SHUFFLE) return speed_decompress(in, &g, eb_abs, out);
     if (!(eb_abs >= 1e-300 && eb_abs <= 1e300)) return ORC_ERR_CORRUPT;
     uint64_t nblocks = ld32(in + 72), nout = ld32(in + 76), npat = ld32(in + 80);
     uint64_t words = ld32(in + 84), bits = ld64(in + 88), nreg = ld32(in + 96);
@@ -963,6 +968,245 @@ int orc_decompress(const uint8_t *in, uint64_t n, float *out, uint64_t out_elems
         }
     }
     free(refs); free(bcount); free(a); free(bp); free(cf);
+    return rc;
+}
+
+/* ------------------------------------------ bit-shuffle codec (FZMod-Speed)
+ * The throughput-oriented pipeline of the paper swaps the Huffman stage
+ * for the bit-shuffle and dictionary (zero-word) encoding of FZ-GPU
+ * (Sec. 3.2 module list, Sec. 3.3 FZMod-Speed); the paper gives no
+ * bit-level detail, so this is the reading the project fixes:
+ *   - steps 1-4 as above with first-order Lorenzo in every block;
+ *   - every value gets a 10-bit symbol: the residual d (|d| < radius) folded
+ *     to an unsigned number, zigzag(d) = 2d for d >= 0 and -2d - 1 for
+ *     d < 0 (0, -1, 1, -2, ... -> 0, 1, 2, 3, ...), and 1023 for an outlier;
+ *   - a block owns 512 symbol slots (slot = position mod 512; slots of a
+ *     truncated block that hold no value are 0), cut into 16 groups of 32;
+ *   - bit-shuffle: group g gives 10 words, word p holding bit p of the
+ *     group's 32 symbols, symbol j of the group in bit j;
+ *   - zero-word elimination: bit 10 g + p of the block's 160-bit mask says
+ *     whether word p of group g is non-zero; only non-zero words are kept,
+ *     in mask-bit order, blocks one after the other.
+ * Container: header (flag bit 1 set, predictor 0, "words" = kept words,
+ * "bits" = 0) | masks u32[5 per block] (mask bit k in word k/32, bit k%32)
+ * | kept words u32[] | outlier pos u32[] | outlier residual i32[] | patch
+ * pos u32[] | patch bits u32[]; sections 16-byte aligned, padding zero.   */
+#define ORC_SYM_OUTLIER 1023u
+#define ORC_GROUPS 16
+#define ORC_PLANES 10
+#define ORC_MASK_WORDS 5
+
+typedef struct {
+    uint64_t masks, words, opos, oval, ppos, pbits, total;
+} slayout_t;
+
+static slayout_t speed_layout(uint64_t nblocks, uint64_t words, uint64_t nout, uint64_t npat) {
+    slayout_t L;
+    L.masks = ORC_HDR;
+    L.words = a16(L.masks + 4 * ORC_MASK_WORDS * nblocks);
+    L.opos = a16(L.words + 4 * words);
+    L.oval = a16(L.opos + 4 * nout);
+    L.ppos = a16(L.oval + 4 * nout);
+    L.pbits = a16(L.ppos + 4 * npat);
+    L.total = a16(L.pbits + 4 * npat);
+    return L;
+}
+
+static uint32_t zigzag(int32_t d) { return d >= 0 ? 2u * (uint32_t)d : 2u * (uint32_t)(-(int64_t)d) - 1u; }
+static int32_t unzigzag(uint32_t s) { return (s & 1u) ? -(int32_t)((s + 1u) / 2u) : (int32_t)(s / 2u); }
+
+/* Symbols of every block, 512 slots each (block order), from the residual
+ * codes: code 0 (outlier) -> 1023, code c -> zigzag(c - radius).          */
+static void speed_symbols(const geom_t *g, const elem_ref *refs, const uint16_t *codes, uint16_t *sym) {
+    memset(sym, 0, sizeof(uint16_t) * g->nblocks * ORC_BLOCK_ELEMS);
+    for (uint64_t k = 0; k < g->N; k++)
+        sym[refs[k].pos] = codes[k] == 0 ? (uint16_t)ORC_SYM_OUTLIER : (uint16_t)zigzag((int32_t)codes[k] - ORC_RADIUS);
+}
+
+/* word p of one group of 32 symbols */
+static uint32_t shuffle_word(const uint16_t *s32, int p) {
+    uint32_t w = 0;
+    for (int j = 0; j < 32; j++) w |= (uint32_t)((s32[j] >> p) & 1u) << j;
+    return w;
+}
+
+/* For tests: the symbols (nblocks * 512) and the shuffled words
+ * (nblocks * 160, group-major) of a field. */
+int orc_speed_stage(const float *x, int ndim, const uint64_t dims[3], int mode, double eb, uint16_t *sym_out,
+                    uint32_t *words_out) {
+    geom_t g;
+    int rc = make_geom(ndim, dims, &g);
+    if (rc) return rc;
+    double eb_abs;
+    rc = orc_eb_abs(x, g.N, mode, eb, &eb_abs);
+    if (rc) return rc;
+    int32_t *q = (int32_t *)malloc(sizeof(int32_t) * g.N);
+    uint8_t *patch = (uint8_t *)malloc(g.N);
+    int32_t *res = (int32_t *)malloc(sizeof(int32_t) * g.N);
+    elem_ref *refs = (elem_ref *)malloc(sizeof(elem_ref) * g.N);
+    uint32_t *bcount = (uint32_t *)malloc(sizeof(uint32_t) * g.nblocks);
+    uint16_t *codes = (uint16_t *)malloc(sizeof(uint16_t) * g.N);
+    uint8_t *bp = (uint8_t *)calloc(g.nblocks, 1);
+    int32_t *cf = (int32_t *)calloc(4 * g.nblocks, sizeof(int32_t));
+    orc_prequant(x, g.N, eb_abs, q, patch);
+    block_major_order(&g, refs, bcount);
+    block_codes(&g, q, refs, bp, cf, codes, res);
+    speed_symbols(&g, refs, codes, sym_out);
+    for (uint64_t b = 0; b < g.nblocks; b++)
+        for (int gi = 0; gi < ORC_GROUPS; gi++)
+            for (int p = 0; p < ORC_PLANES; p++)
+                words_out[(b * ORC_GROUPS + gi) * ORC_PLANES + p] =
+                    shuffle_word(sym_out + b * ORC_BLOCK_ELEMS + 32 * gi, p);
+    free(q); free(patch); free(res); free(refs); free(bcount); free(codes); free(bp); free(cf);
+    return ORC_OK;
+}
+
+int orc_speed_compress(const float *x, int ndim, const uint64_t dims[3], int mode, double eb, uint8_t *out,
+                       uint64_t cap, uint64_t *out_bytes) {
+    geom_t g;
+    int rc = make_geom(ndim, dims, &g);
+    if (rc) return rc;
+    if (cap < ORC_HDR + 4 * g.N) return ORC_ERR_CAPACITY;
+    double eb_abs;
+    rc = orc_eb_abs(x, g.N, mode, eb, &eb_abs);
+    if (rc) return rc;
+    int32_t *q = (int32_t *)malloc(sizeof(int32_t) * g.N);
+    uint8_t *patch = (uint8_t *)malloc(g.N);
+    int32_t *res = (int32_t *)malloc(sizeof(int32_t) * g.N);
+    elem_ref *refs = (elem_ref *)malloc(sizeof(elem_ref) * g.N);
+    uint32_t *bcount = (uint32_t *)malloc(sizeof(uint32_t) * g.nblocks);
+    uint16_t *codes = (uint16_t *)malloc(sizeof(uint16_t) * g.N);
+    uint8_t *bp = (uint8_t *)calloc(g.nblocks, 1);
+    int32_t *cf = (int32_t *)calloc(4 * g.nblocks, sizeof(int32_t));
+    uint16_t *sym = (uint16_t *)malloc(sizeof(uint16_t) * g.nblocks * ORC_BLOCK_ELEMS);
+    uint32_t *mask = (uint32_t *)calloc(ORC_MASK_WORDS * g.nblocks, sizeof(uint32_t));
+    uint32_t *kept = (uint32_t *)malloc(sizeof(uint32_t) * (g.nblocks * ORC_GROUPS * ORC_PLANES + 1));
+    if (!q || !patch || !res || !refs || !bcount || !codes || !bp || !cf || !sym || !mask || !kept) {
+        free(q); free(patch); free(res); free(refs); free(bcount); free(codes); free(bp); free(cf);
+        free(sym); free(mask); free(kept);
+        return ORC_ERR_NOMEM;
+    }
+    orc_prequant(x, g.N, eb_abs, q, patch);
+    block_major_order(&g, refs, bcount);
+    block_codes(&g, q, refs, bp, cf, codes, res);
+    speed_symbols(&g, refs, codes, sym);
+    /* shuffle and keep the non-zero words */
+    uint64_t words = 0;
+    for (uint64_t b = 0; b < g.nblocks; b++)
+        for (int gi = 0; gi < ORC_GROUPS; gi++)
+            for (int p = 0; p < ORC_PLANES; p++) {
+                uint32_t w = shuffle_word(sym + b * ORC_BLOCK_ELEMS + 32 * gi, p);
+                if (w) {
+                    int k = gi * ORC_PLANES + p;
+                    mask[ORC_MASK_WORDS * b + k / 32] |= 1u << (k % 32);
+                    kept[words++] = w;
+                }
+            }
+    uint64_t nout = 0, npat = 0;
+    for (uint64_t k = 0; k < g.N; k++) {
+        if (codes[k] == 0) nout++;
+        if (patch[refs[k].idx]) npat++;
+    }
+    slayout_t L = speed_layout(g.nblocks, words, nout, npat);
+    if (L.total >= ORC_HDR + 4 * g.N) {
+        write_header(out, &g, 1 | ORC_FLAG_SHUFFLE, mode, eb, eb_abs, ORC_HDR + 4 * g.N, 0, 0, 0, 0, 0, 0, 0);
+        for (uint64_t i = 0; i < g.N; i++) memcpy(out + ORC_HDR + 4 * i, &x[i], 4);
+        *out_bytes = ORC_HDR + 4 * g.N;
+    } else {
+        memset(out, 0, L.total);
+        write_header(out, &g, ORC_FLAG_SHUFFLE, mode, eb, eb_abs, L.total, g.nblocks, nout, npat, words, 0, 0, 0);
+        for (uint64_t i = 0; i < ORC_MASK_WORDS * g.nblocks; i++) st32(out + L.masks + 4 * i, mask[i]);
+        for (uint64_t i = 0; i < words; i++) st32(out + L.words + 4 * i, kept[i]);
+        uint64_t io = 0, ip = 0;
+        for (uint64_t k = 0; k < g.N; k++) {
+            if (codes[k] == 0) {
+                st32(out + L.opos + 4 * io, refs[k].pos);
+                st32(out + L.oval + 4 * io, (uint32_t)res[k]);
+                io++;
+            }
+            if (patch[refs[k].idx]) {
+                uint32_t fb;
+                memcpy(&fb, &x[refs[k].idx], 4);
+                st32(out + L.ppos + 4 * ip, refs[k].pos);
+                st32(out + L.pbits + 4 * ip, fb);
+                ip++;
+            }
+        }
+        *out_bytes = L.total;
+    }
+    free(q); free(patch); free(res); free(refs); free(bcount); free(codes); free(bp); free(cf);
+    free(sym); free(mask); free(kept);
+    return ORC_OK;
+}
+
+/* Decoding of a bit-shuffle container (header already checked for magic,
+ * geometry, size and the verbatim flag by orc_decompress). */
+static int speed_decompress(const uint8_t *in, const geom_t *g, double eb_abs, float *out) {
+    uint64_t nblocks = ld32(in + 72), nout = ld32(in + 76), npat = ld32(in + 80);
+    uint64_t words = ld32(in + 84), total = ld64(in + 64);
+    if (nblocks != g->nblocks || ld64(in + 88) != 0 || ld32(in + 12) != ORC_P0 || ld32(in + 96) != 0)
+        return ORC_ERR_CORRUPT;
+    if (!(eb_abs >= 1e-300 && eb_abs <= 1e300)) return ORC_ERR_CORRUPT;
+    slayout_t L = speed_layout(nblocks, words, nout, npat);
+    if (L.total != total) return ORC_ERR_CORRUPT;
+    elem_ref *refs = (elem_ref *)malloc(sizeof(elem_ref) * g->N);
+    uint32_t *bcount = (uint32_t *)malloc(sizeof(uint32_t) * g->nblocks);
+    int32_t *a = (int32_t *)malloc(sizeof(int32_t) * g->N);
+    uint16_t *sym = (uint16_t *)calloc(g->nblocks * ORC_BLOCK_ELEMS, sizeof(uint16_t));
+    if (!refs || !bcount || !a || !sym) {
+        free(refs); free(bcount); free(a); free(sym);
+        return ORC_ERR_NOMEM;
+    }
+    block_major_order(g, refs, bcount);
+    /* unshuffle: the kept words, in mask-bit order, block after block */
+    uint64_t next = 0;
+    int rc = ORC_OK;
+    for (uint64_t b = 0; b < g->nblocks && rc == ORC_OK; b++)
+        for (int k = 0; k < ORC_GROUPS * ORC_PLANES; k++) {
+            uint32_t m = ld32(in + L.masks + 4 * (ORC_MASK_WORDS * b + k / 32));
+            if (!((m >> (k % 32)) & 1u)) continue;
+            if (next >= words) { rc = ORC_ERR_CORRUPT; break; }
+            uint32_t w = ld32(in + L.words + 4 * next);
+            next++;
+            int gi = k / ORC_PLANES, p = k % ORC_PLANES;
+            for (int j = 0; j < 32; j++)
+                sym[b * ORC_BLOCK_ELEMS + 32 * gi + j] |= (uint16_t)(((w >> j) & 1u) << p);
+        }
+    /* every kept word used */
+    if (rc == ORC_OK && next != words) rc = ORC_ERR_CORRUPT;
+    /* residuals; an outlier symbol takes the next listed outlier, whose
+     * position must be this value's */
+    uint64_t io = 0;
+    for (uint64_t k = 0; k < g->N && rc == ORC_OK; k++) {
+        uint32_t s = sym[refs[k].pos];
+        int32_t d;
+        if (s == ORC_SYM_OUTLIER) {
+            if (io >= nout || ld32(in + L.opos + 4 * io) != refs[k].pos) { rc = ORC_ERR_CORRUPT; break; }
+            d = (int32_t)ld32(in + L.oval + 4 * io);
+            io++;
+        } else {
+            d = unzigzag(s);
+        }
+        a[refs[k].idx] = d;
+    }
+    if (rc == ORC_OK && io != nout) rc = ORC_ERR_CORRUPT;
+    if (rc == ORC_OK) {
+        for (uint64_t b = 0; b < g->nblocks; b++) block_inverse(g, a, b, ORC_P0, NULL);
+        double e2 = 2.0 * eb_abs;
+        for (uint64_t i = 0; i < g->N; i++) out[i] = dequant(a[i], e2);
+        uint64_t kk = 0;
+        uint32_t last = 0;
+        for (uint64_t ip = 0; ip < npat; ip++) {
+            uint32_t pos = ld32(in + L.ppos + 4 * ip);
+            uint32_t fb = ld32(in + L.pbits + 4 * ip);
+            if (ip > 0 && pos <= last) { rc = ORC_ERR_CORRUPT; break; }
+            last = pos;
+            while (kk < g->N && refs[kk].pos < pos) kk++;
+            if (kk >= g->N || refs[kk].pos != pos) { rc = ORC_ERR_CORRUPT; break; }
+            memcpy(&out[refs[kk].idx], &fb, 4);
+        }
+    }
+    free(refs); free(bcount); free(a); free(sym);
     return rc;
 }
 
