@@ -119,6 +119,24 @@ uint64_t fz_compress_bound(const fz_params *p);
 int fz_compress(fz_ctx *ctx, const fz_params *p, const float *d_in, void *d_out, uint64_t out_cap,
                 uint64_t *h_out_bytes, void *stream);
 
+/* FZMod-Speed pipeline (Sec. 3.3; Sec. 3.2 names the FZ-GPU bit-shuffle and
+ * dictionary encoder as the fast alternative to Huffman coding): the same
+ * error bound, prequantisation, first-order Lorenzo prediction, outliers and
+ * patches as fz_compress, then, in place of the histogram, Huffman code and
+ * encoder, a bit-shuffle of the codes: each value's residual d folded to a
+ * 10-bit symbol (zigzag: 0, -1, 1, -2 -> 0, 1, 2, 3; 1023 = outlier), each
+ * block's 512 symbol slots cut into 16 groups of 32 whose 10 bit planes are
+ * 32-bit words, and only the non-zero words kept, listed by a 160-bit mask
+ * per block.  No histogram barrier: the encoder runs right after the
+ * quantiser.  Container: header flag bit 1 set, predictor 0, then the masks
+ * (5 u32 per block), the kept words, the outliers and the patches (16-byte
+ * aligned sections); verbatim when not smaller than the raw floats.
+ * fz_decompress and fz_decompress_batch read these containers too.  p->pred
+ * must be FZ_PRED_LORENZO1 (else FZ_ERR_UNSUPPORTED); otherwise as
+ * fz_compress. */
+int fz_compress_speed(fz_ctx *ctx, const fz_params *p, const float *d_in, void *d_out, uint64_t out_cap,
+                      uint64_t *h_out_bytes, void *stream);
+
 /* Parse a container header held in host memory (at least 128 bytes).
  * Fills *p, *n_elems (values in the field) and *total_bytes (container size).
  * Returns FZ_OK or FZ_ERR_CORRUPT. */
@@ -313,8 +331,8 @@ int fz_selector_adam_step(fz_ctx *ctx, float *h_w, float *h_m, float *h_v, const
  * context: the scratch is one statically sized device array per GPU
  * (fz_noalloc_scratch_bytes bytes, held until the process ends), found on
  * the current device at the first call there.  Accepts first-order Lorenzo
- * containers (FZ_PRED_LORENZO1) of at most FZ_NOALLOC_MAX_BLOCKS blocks and
- * verbatim containers of any size; other predictors give
+ * containers (FZ_PRED_LORENZO1, Huffman or bit-shuffle coded) of at most
+ * FZ_NOALLOC_MAX_BLOCKS blocks and verbatim containers of any size; other predictors give
  * FZ_ERR_UNSUPPORTED, more blocks FZ_ERR_SCRATCH, before any kernel runs.
  * Every call on one GPU shares that GPU's array (each call clears what it
  * needs first): calls that overlap on one GPU, on any streams or host

@@ -249,7 +249,10 @@ int ensure(fz_ctx* c, const Geom& g) {
     if (e == hipSuccess) e = grow(c->tfirst, c->tfirst_cap, ntiles);
     if (e == hipSuccess) e = grow(c->tlast, c->tlast_cap, ntiles);
     if (e == hipSuccess) e = grow(c->desc_cnt, c->desc_cnt_cap, sd_tiles);
-    if (e == hipSuccess) e = grow(c->desc_bits, c->desc_bits_cap, encode_groups((uint32_t)ntiles));
+    // look-back descriptors of the Huffman encoder's groups and of the
+    // bit-shuffle encoder's groups (both 32 blocks)
+    const uint64_t ngroups = std::max<uint64_t>(encode_groups((uint32_t)ntiles), shuffle_groups((uint32_t)nb));
+    if (e == hipSuccess) e = grow(c->desc_bits, c->desc_bits_cap, ngroups);
     if (e == hipSuccess) e = grow(c->desc_chunks, c->desc_chunks_cap, sd_blocks);
     if (e == hipSuccess) e = grow(c->off, c->off_cap, nb);
     if (e == hipSuccess) e = grow(c->oidx, c->oidx_cap, nb);
@@ -348,6 +351,7 @@ struct Parsed {
     fz_params p;
     Geom g;
     int verbatim;
+    int shuffle;  // bit-shuffle codec container (header flag bit 1)
     double eb_abs;
     uint64_t total, nblocks, nout, npat, words, bits, nreg;
 };
@@ -356,9 +360,10 @@ int parse_header(const uint8_t* h, uint64_t n, Parsed* r) {
     if (!h || n < (uint64_t)kHdr) return FZ_ERR_CORRUPT;
     if (ld32(h, 0) != kMagic || (h[4] | (h[5] << 8)) != kVersion) return FZ_ERR_CORRUPT;
     const int flags = h[6] | (h[7] << 8);
-    if (flags & ~1) return FZ_ERR_CORRUPT;
+    if (flags & ~(1 | (int)kFlagShuffle)) return FZ_ERR_CORRUPT;
     memset(r, 0, sizeof(*r));
     r->verbatim = flags & 1;
+    r->shuffle = (flags & (int)kFlagShuffle) ? 1 : 0;
     r->p.ndim = ld32(h, 8);
     r->p.pred = ld32(h, 12);
     r->p.dims[0] = ld64(h, 16);
@@ -383,6 +388,14 @@ int parse_header(const uint8_t* h, uint64_t n, Parsed* r) {
         return FZ_OK;
     }
     if (!(r->eb_abs >= 1e-300 && r->eb_abs <= 1e300)) return FZ_ERR_CORRUPT;
+    if (r->shuffle) {
+        // first-order Lorenzo only; at most 160 kept words per block
+        if (r->p.pred != FZ_PRED_LORENZO1 || r->nreg || r->bits || r->nblocks != r->g.nblocks) return FZ_ERR_CORRUPT;
+        if (r->words > (uint64_t)kPlanes * 16 * r->nblocks || r->nout > r->g.N || r->npat > r->g.N)
+            return FZ_ERR_CORRUPT;
+        if (make_speed_layout(r->nblocks, r->words, r->nout, r->npat).total != r->total) return FZ_ERR_CORRUPT;
+        return FZ_OK;
+    }
     // every value costs at least one bit, so the stream is never empty
     if (r->nblocks != r->g.nblocks || r->words != (r->bits + 31) / 32 || r->bits < r->g.N) return FZ_ERR_CORRUPT;
     if (r->nout > r->g.N || r->npat > r->g.N) return FZ_ERR_CORRUPT;
@@ -503,6 +516,47 @@ void compress_enqueue(fz_ctx* c, const fz_params* p, const Geom& g, const float*
     mark("finalize");
 }
 
+// Every kernel of one bit-shuffle compression (first-order Lorenzo) on `st`:
+// the same quantisation as compress_enqueue, then the shuffle encoder in
+// place of the histogram -> code -> encode stages.
+void compress_speed_enqueue(fz_ctx* c, const fz_params* p, const Geom& g, const float* d_in, uint8_t* out,
+                            hipStream_t st, const Tune& tn, bool marks) {
+    auto mark = [&](const char* name) {
+        if (marks) t_mark(c, st, name);
+    };
+    auto start = [&](const char* name) {
+        if (marks) t_start(c, st, name);
+    };
+    const uint32_t ntiles = (g.nblocks + kTileBlocks - 1) / kTileBlocks;
+    const int vec = (((uintptr_t)d_in & 15) == 0) && (g.ndim == 1 || (g.n[0] & 3) == 0);
+    const uint32_t sd_tiles = scan_tiles(ntiles);
+    const uint32_t gmax = (uint32_t)c->n_cu * tn.wg_per_cu;
+    const int grid = (int)(ntiles < gmax ? ntiles : gmax);
+    start("reset");
+    launch_reset(st, c->misc, c->hist, c->desc_cnt, sd_tiles, c->desc_bits, shuffle_groups(g.nblocks), nullptr, 0,
+                 0, 0, 0);
+    mark("reset");
+    if (p->eb_mode == FZ_EB_REL) {
+        start("minmax");
+        launch_minmax(st, d_in, g.N, (((uintptr_t)d_in & 15) == 0), c->misc, minmax_grid(c, g.N, tn.mm_wg_per_cu));
+        mark("minmax");
+    }
+    start("quant");
+    launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt,
+                 c->ostage, c->pstage, FZ_PRED_LORENZO1, nullptr, nullptr);
+    mark("quant");
+    start("scan_counts");
+    launch_scan(st, SCAN_COUNTS, c->tile_cnt, ntiles, c->tile_off, c->desc_cnt, &c->misc->qtile_ctr, c->misc, 0);
+    mark("scan_counts");
+    start("shuffle");
+    launch_shuffle(st, g, c->codes, out, (uint64_t)kHdr + 4 * g.N, c->desc_bits, c->misc);
+    mark("shuffle");
+    start("finalize");
+    launch_finalize(st, g, p->eb_mode, p->eb, FZ_PRED_LORENZO1, c->misc, out, ntiles, c->tile_start, c->tfirst,
+                    c->tlast, c->tile_cnt, c->tile_off, c->ostage, c->pstage, c->bpred, c->reg_idx, c->coef, d_in, 1);
+    mark("finalize");
+}
+
 int decompress_prepare(fz_ctx* c, const Parsed& r) {
     if (r.verbatim) return FZ_OK;
     int rc = ensure(c, r.g);
@@ -527,8 +581,34 @@ void decompress_enqueue(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_
     }
     const uint32_t pred = r.p.pred;
     const bool has_map = pred_has_map(pred);
-    const Layout L = make_layout(r.nblocks, has_map, r.nreg, r.words, r.nout, r.npat);
     const uint32_t stiles = scan_tiles(g.nblocks);
+    if (r.shuffle) {
+        // bit-shuffle container: kept-word offsets from the mask popcounts,
+        // the outlier index, then one wave per block rebuilds the values
+        const Layout L = make_speed_layout(r.nblocks, r.words, r.nout, r.npat);
+        start("lut");
+        launch_reset(st, c->misc, c->hist, c->desc_chunks, stiles, nullptr, 0,
+                     r.nout ? reinterpret_cast<uint64_t*>(c->oidx) : nullptr, r.nout ? (uint32_t)g.nblocks : 0u, 0, 0,
+                     0);
+        mark("lut");
+        start("scan");
+        launch_scan(st, SCAN_MASKS, in + L.chunks, g.nblocks, c->off, c->desc_chunks, &c->misc->stile_ctr, c->misc,
+                    r.words);
+        mark("scan");
+        start("oindex");
+        launch_outlier_index(st, g, (const uint32_t*)(in + L.opos), r.nout, c->oidx, c->misc);
+        mark("oindex");
+        start("decode");
+        launch_unshuffle(st, g, (const uint32_t*)(in + L.chunks), (const uint32_t*)(in + L.stream), r.words, c->off,
+                         (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->oidx, r.nout,
+                         2.0 * r.eb_abs, d_out, c->misc);
+        mark("decode");
+        start("patch");
+        launch_patch(st, g, (const uint32_t*)(in + L.ppos), (const uint32_t*)(in + L.pbits), r.npat, d_out, c->misc);
+        mark("patch");
+        return;
+    }
+    const Layout L = make_layout(r.nblocks, has_map, r.nreg, r.words, r.nout, r.npat);
     const int vec = (((uintptr_t)d_out & 15) == 0) && (g.ndim == 1 || (g.n[0] & 3) == 0);
     // one launch: the reset (which also clears the per-block outlier index)
     // and the decode table
@@ -570,6 +650,8 @@ void decompress_enqueue(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_
 int decode_status(const Misc& m, const Parsed& r) {
     int rc = flags_status(m.flags);
     if (rc) return rc;
+    // the bit-shuffle decoder checks every outlier against the list itself
+    if (r.shuffle) return FZ_OK;
     if (m.code0_count != r.nout || m.ohash_dec != m.ohash_list) return FZ_ERR_CORRUPT;
     if (pred_has_map(r.p.pred) && m.nreg != r.nreg) return FZ_ERR_CORRUPT;
     return FZ_OK;
@@ -709,6 +791,33 @@ int fz_compress(fz_ctx* c, const fz_params* p, const float* d_in, void* d_out, u
     rc = flags_status(m.flags & ~(uint32_t)F_CORRUPT);
     if (rc) return rc;
     c->have_hist = true;
+    *h_out_bytes = m.total_bytes;
+    return FZ_OK;
+}
+
+int fz_compress_speed(fz_ctx* c, const fz_params* p, const float* d_in, void* d_out, uint64_t out_cap,
+                      uint64_t* h_out_bytes, void* stream) {
+    if (h_out_bytes) *h_out_bytes = 0;
+    if (!c || !d_in || !d_out || !h_out_bytes) return FZ_ERR_ARG;
+    Geom g;
+    int rc = compress_check(c, p, d_in, d_out, out_cap, &g);
+    if (rc) return rc;
+    if (p->pred != FZ_PRED_LORENZO1) return FZ_ERR_UNSUPPORTED;
+    DeviceGuard dg(c->device);
+    rc = compress_prepare(c, p, g);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    c->have_hist = false;
+    t_begin(c, st);
+    compress_speed_enqueue(c, p, g, d_in, (uint8_t*)d_out, st, c->tune_default, true);
+    t_finish(c, st);
+    if (hipMemcpyAsync(c->h_misc, c->misc, sizeof(Misc), hipMemcpyDeviceToHost, st) != hipSuccess) return FZ_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
+    if (hipGetLastError() != hipSuccess) return FZ_ERR_HIP;
+    t_end(c);
+    const Misc m = *c->h_misc;
+    rc = flags_status(m.flags & ~(uint32_t)F_CORRUPT);
+    if (rc) return rc;
     *h_out_bytes = m.total_bytes;
     return FZ_OK;
 }

@@ -38,7 +38,7 @@ constexpr int kSelectorParams = 2 * kNFeat + kNHid * kNFeat + kNHid + kNHid * kN
 constexpr uint16_t kVersion = 1;
 
 // prefix-scan kinds (fz_scan.hip)
-enum { SCAN_COUNTS = 0, SCAN_CHUNKS = 2, SCAN_PMAP = 3 };
+enum { SCAN_COUNTS = 0, SCAN_CHUNKS = 2, SCAN_PMAP = 3, SCAN_MASKS = 4 };
 
 // flag bits raised by kernels in Misc::flags
 enum : uint32_t {
@@ -55,12 +55,13 @@ struct Misc {
     uint32_t flags;
     uint32_t mm_lo, mm_hi;     // order-preserving encodings of min and max
     uint32_t qtile_ctr;        // dynamic tile counters (look-back order)
-    uint32_t pad0;
+    uint32_t xtile_ctr;        // bit-shuffle encoder (look-back order)
     uint32_t stile_ctr;
     uint32_t code0_count;      // decode: outlier codes seen
     uint32_t mtile_ctr;        // predictor-map scan
     uint64_t total_bits_cb;    // sum hist[c] * len[c]
-    uint64_t total_bits_enc;   // end of the last encoded tile
+    uint64_t total_bits_enc;   // end of the last encoded tile (bit-shuffle
+                               // codec: kept words)
     uint64_t n_out;            // outliers (inclusive count of the last tile)
     uint64_t n_pat;            // lossless patches
     uint64_t total_bytes;      // container size (non-verbatim)
@@ -186,6 +187,26 @@ __host__ __device__ inline Layout make_layout(uint64_t nblocks, bool has_map, ui
     L.coef = align16(L.map + (has_map ? (nblocks + 3) / 4 : 0));
     L.chunks = align16(L.coef + 16 * nreg);
     L.stream = align16(L.chunks + 2 * nblocks);
+    L.opos = align16(L.stream + 4 * words);
+    L.oval = align16(L.opos + 4 * nout);
+    L.ppos = align16(L.oval + 4 * nout);
+    L.pbits = align16(L.ppos + 4 * npat);
+    L.total = align16(L.pbits + 4 * npat);
+    return L;
+}
+
+// Bit-shuffle codec (header flag bit 1): per block a 160-bit mask of the
+// non-zero plane words (5 u32), then the kept words of all blocks; the
+// outlier and patch sections as above.  lens, map and coef are unused
+// (set to the mask section), chunks = the masks, stream = the kept words.
+constexpr uint32_t kFlagShuffle = 2;
+constexpr int kMaskWords = 5;
+constexpr int kPlanes = 10;
+constexpr uint32_t kSymOutlier = 1023;
+__host__ __device__ inline Layout make_speed_layout(uint64_t nblocks, uint64_t words, uint64_t nout, uint64_t npat) {
+    Layout L;
+    L.lens = L.map = L.coef = L.chunks = kHdr;
+    L.stream = align16(L.chunks + 4 * kMaskWords * nblocks);
     L.opos = align16(L.stream + 4 * words);
     L.oval = align16(L.opos + 4 * nout);
     L.ppos = align16(L.oval + 4 * nout);
@@ -427,6 +448,63 @@ __device__ inline uint32_t canonical_code(uint32_t len, CanonShared& sh) {
     }
     __syncthreads();
     return code;
+}
+
+// ------------------------------------------ wave-cooperative block inverse
+// Inclusive prefix sums of the residuals of one block, lane = segment of
+// 8 slots (3D: row (y, z) = (lane % 8, lane / 8); 2D: x from 8 (lane % 4),
+// y = lane / 4; 1D: x from 8 lane).
+template <int ND>
+__device__ __forceinline__ void block_prefix(int32_t (&v)[8], uint32_t lane) {
+#pragma unroll
+    for (int i = 1; i < 8; i++) v[i] += v[i - 1];
+    if (ND == 1) {
+        // carry from the lanes before along x
+        const uint32_t tot = (uint32_t)v[7];
+        const uint32_t excl = wave_incl_scan(tot) - tot;
+#pragma unroll
+        for (int i = 0; i < 8; i++) v[i] += (int32_t)excl;
+        return;
+    }
+    if (ND == 2) {
+        // x: carry from the (up to 3) lanes before in the same row of 4
+        int32_t tot = v[7], carry = 0;
+#pragma unroll
+        for (int d = 1; d < 4; d <<= 1) {
+            const int32_t o = __shfl_up(tot, d, 4);
+            if ((lane & 3) >= (uint32_t)d) tot += o;
+        }
+        carry = tot - v[7];
+#pragma unroll
+        for (int i = 0; i < 8; i++) v[i] += carry;
+        // y: lanes 4 apart
+#pragma unroll
+        for (int d = 4; d < 64; d <<= 1) {
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                const int32_t o = __shfl_up(v[i], d, 64);
+                if (lane >= (uint32_t)d) v[i] += o;
+            }
+        }
+        return;
+    }
+    // 3D: y within the 8 lanes of one z, then z (lanes 8 apart)
+#pragma unroll
+    for (int d = 1; d < 8; d <<= 1) {
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const int32_t o = __shfl_up(v[i], d, 8);
+            if ((lane & 7) >= (uint32_t)d) v[i] += o;
+        }
+    }
+#pragma unroll
+    for (int d = 8; d < 64; d <<= 1) {
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const int32_t o = __shfl_up(v[i], d, 64);
+            if (lane >= (uint32_t)d) v[i] += o;
+        }
+    }
 }
 
 }  // namespace fz

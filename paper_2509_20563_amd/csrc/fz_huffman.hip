@@ -342,9 +342,9 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ cod
 // -------------------------------------------------------------- verbatim
 // The verbatim container: header (flag bit 0) and the raw floats, written by
 // the whole finalize grid.
-__device__ void write_verbatim(const Geom& g, uint32_t mode, double eb, uint32_t pred, const Misc* misc,
-                               const float* __restrict__ x, uint8_t* __restrict__ out, int vec, uint64_t gid,
-                               uint64_t stride) {
+__device__ void write_verbatim(const Geom& g, uint32_t mode, double eb, uint32_t pred, uint32_t hflags,
+                               const Misc* misc, const float* __restrict__ x, uint8_t* __restrict__ out, int vec,
+                               uint64_t gid, uint64_t stride) {
     if (gid == 0) {
         double eb_abs;
         resolve_eb(mode, eb, misc->mm_lo, misc->mm_hi, &eb_abs);
@@ -355,7 +355,7 @@ __device__ void write_verbatim(const Geom& g, uint32_t mode, double eb, uint32_t
         st32(0, kMagic);
         h[4] = (uint8_t)kVersion;
         h[5] = (uint8_t)(kVersion >> 8);
-        h[6] = 1;
+        h[6] = (uint8_t)hflags;
         st32(8, g.ndim);
         st32(12, pred);
         st64(16, g.n[0]);
@@ -397,24 +397,28 @@ __global__ __launch_bounds__(256) void k_finalize(Geom g, uint32_t mode, double 
                                                   const uint8_t* __restrict__ bpred,
                                                   const uint64_t* __restrict__ reg_idx,
                                                   const int32_t* __restrict__ coef, const float* __restrict__ x,
-                                                  int xvec) {
+                                                  int xvec, uint32_t codec) {
     const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint32_t flags = misc->flags;
-    const uint64_t bits = misc->total_bits_enc;
-    const uint64_t words = (bits + 31) / 32;
+    const bool shuffle = codec != 0;
+    // Huffman: stream bits; bit-shuffle: kept words (no bit count)
+    const uint64_t bits = shuffle ? 0 : misc->total_bits_enc;
+    const uint64_t words = shuffle ? misc->total_bits_enc : (bits + 31) / 32;
     const uint64_t nout = misc->n_out, npat = misc->n_pat, nreg = misc->nreg;
     const bool has_map = pred_has_map(pred);
-    const Layout L = make_layout(g.nblocks, has_map, nreg, words, nout, npat);
+    const Layout L = shuffle ? make_speed_layout(g.nblocks, words, nout, npat)
+                             : make_layout(g.nblocks, has_map, nreg, words, nout, npat);
     const bool verbatim = (flags & F_OVERFLOW) || L.total >= (uint64_t)kHdr + 4 * g.N;
     if (gid == 0) {
-        if (bits != misc->total_bits_cb || L.chunks != misc->off_chunks) atomicOr(&misc->flags, F_INTERNAL);
+        if (!shuffle && (bits != misc->total_bits_cb || L.chunks != misc->off_chunks))
+            atomicOr(&misc->flags, F_INTERNAL);
         misc->verbatim = verbatim ? 1 : 0;
         misc->total_bytes = verbatim ? (uint64_t)kHdr + 4 * g.N : L.total;
     }
     if (flags & (F_NONFINITE | F_EB | F_INTERNAL | F_TIMEOUT)) return;
     if (verbatim) {
-        write_verbatim(g, mode, eb, pred, misc, x, out, xvec, gid, stride);
+        write_verbatim(g, mode, eb, pred, shuffle ? 1u | kFlagShuffle : 1u, misc, x, out, xvec, gid, stride);
         return;
     }
 
@@ -436,7 +440,7 @@ __global__ __launch_bounds__(256) void k_finalize(Geom g, uint32_t mode, double 
             reinterpret_cast<int4*>(out + L.coef)[r] = reinterpret_cast<const int4*>(coef)[b];
         }
     uint32_t* stream = reinterpret_cast<uint32_t*>(out + L.stream);
-    for (uint64_t i = gid + 1; i < ntiles; i += stride) {
+    for (uint64_t i = gid + 1; !shuffle && i < ntiles; i += stride) {
         const uint64_t G = tile_start[i];
         if (G & 31) stream[G >> 5] = tlast[i - 1] | tfirst[i];
     }
@@ -493,10 +497,11 @@ __global__ __launch_bounds__(256) void k_finalize(Geom g, uint32_t mode, double 
     if (gid == 0) {
         // zero padding between and after sections
         const uint64_t ends[8] = {L.map + (has_map ? ((uint64_t)g.nblocks + 3) / 4 : 0), L.coef + 16 * nreg,
-                                  L.chunks + 2 * (uint64_t)g.nblocks, L.stream + 4 * words, L.opos + 4 * nout,
-                                  L.oval + 4 * nout, L.ppos + 4 * npat, L.pbits + 4 * npat};
+                                  L.chunks + (shuffle ? 4 * kMaskWords : 2) * (uint64_t)g.nblocks,
+                                  L.stream + 4 * words, L.opos + 4 * nout, L.oval + 4 * nout, L.ppos + 4 * npat,
+                                  L.pbits + 4 * npat};
         const uint64_t starts[8] = {L.coef, L.chunks, L.stream, L.opos, L.oval, L.ppos, L.pbits, L.total};
-        for (int k = 0; k < 8; k++)
+        for (int k = shuffle ? 2 : 0; k < 8; k++)
             for (uint64_t a = ends[k]; a < starts[k]; a++) out[a] = 0;
         // header
         double eb_abs;
@@ -508,6 +513,7 @@ __global__ __launch_bounds__(256) void k_finalize(Geom g, uint32_t mode, double 
         st32(0, kMagic);
         h[4] = (uint8_t)kVersion;
         h[5] = (uint8_t)(kVersion >> 8);
+        h[6] = shuffle ? (uint8_t)kFlagShuffle : 0;
         st32(8, g.ndim);
         st32(12, pred);
         st64(16, g.n[0]);
@@ -557,14 +563,14 @@ void launch_finalize(hipStream_t st, const Geom& g, uint32_t mode, double eb, ui
                      uint8_t* out, uint32_t ntiles, const uint64_t* tile_start, const uint32_t* tfirst,
                      const uint32_t* tlast, const uint32_t* tile_cnt, const uint64_t* tile_off, const uint2* ostage,
                      const uint2* pstage, const uint8_t* bpred, const uint64_t* reg_idx, const int32_t* coef,
-                     const float* x) {
+                     const float* x, uint32_t codec) {
     // about four tiles per wave for the outlier/patch compaction
     uint32_t grid = (ntiles + 15) / 16;
     if (grid < 1024) grid = 1024;
     if (grid > 8192) grid = 8192;
     hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(256), 0, st, g, mode, eb, pred, misc, out, ntiles, tile_start,
                        tfirst, tlast, tile_cnt, tile_off, ostage, pstage, bpred, reg_idx, coef, x,
-                       (int)(((uintptr_t)x & 15) == 0));
+                       (int)(((uintptr_t)x & 15) == 0), codec);
 }
 
 }  // namespace fz

@@ -40,7 +40,7 @@ void launch_finalize(hipStream_t st, const Geom& g, uint32_t mode, double eb, ui
                      uint8_t* out, uint32_t ntiles, const uint64_t* tile_start, const uint32_t* tfirst,
                      const uint32_t* tlast, const uint32_t* tile_cnt, const uint64_t* tile_off, const uint2* ostage,
                      const uint2* pstage, const uint8_t* bpred, const uint64_t* reg_idx, const int32_t* coef,
-                     const float* x);
+                     const float* x, uint32_t codec = 0);
 
 // fz_train.hip: selector training (device scratch of one minibatch)
 struct TrainScratch {
@@ -53,6 +53,15 @@ void launch_train_batch(hipStream_t st, const float* w, const float* feat, const
 void launch_adam(hipStream_t st, float* w, float* m, float* v, const float* g, int t, float lr, float b1, float b2,
                  float eps);
 
+
+// fz_speed.hip: the bit-shuffle codec (codes -> masks + kept words, with
+// the group offsets by decoupled look-back; masks + kept words -> field)
+uint32_t shuffle_groups(uint32_t nblocks);
+void launch_shuffle(hipStream_t st, const Geom& g, const uint16_t* codes, uint8_t* out, uint64_t limit,
+                    uint64_t* desc, Misc* misc);
+void launch_unshuffle(hipStream_t st, const Geom& g, const uint32_t* masks, const uint32_t* kept, uint64_t nkept,
+                      const uint64_t* off, const uint32_t* opos, const int32_t* oval, const uint2* oidx,
+                      uint64_t n_out, double e2, float* out, Misc* misc);
 
 // fz_batch.hip
 void launch_field_record(hipStream_t st, const Misc* misc, uint64_t slot, uint64_t* rec, int decode);

@@ -6,6 +6,8 @@
 //   SCAN_CHUNKS - u16 bit count per block (container) -> bit offset per block
 //   SCAN_PMAP   - per-block predictor (u8) -> index of each regression block
 //                 among the regression blocks; sets the section offsets
+//   SCAN_MASKS  - per-block plane-word mask (5 u32, bit-shuffle codec) ->
+//                 offset of the block's first kept word
 #include <type_traits>
 
 #include "fz_common.h"
@@ -41,6 +43,9 @@ __global__ __launch_bounds__(256) void k_scan(const void* __restrict__ in, uint3
                 e = (uint64_t)(c & 0xFFFFu) | ((uint64_t)(c >> 16) << 31);
             } else if (KIND == SCAN_PMAP) {
                 e = static_cast<const uint8_t*>(in)[base + k] == 2 ? 1u : 0u;
+            } else if (KIND == SCAN_MASKS) {
+                const uint32_t* m = static_cast<const uint32_t*>(in) + 5 * (base + k);
+                e = __popc(m[0]) + __popc(m[1]) + __popc(m[2]) + __popc(m[3]) + __popc(m[4]);
             } else {
                 e = static_cast<const uint16_t*>(in)[base + k];
             }
@@ -106,6 +111,9 @@ void launch_scan(hipStream_t st, int kind, const void* in, uint32_t n, uint64_t*
                            expect);
     else if (kind == SCAN_PMAP)
         hipLaunchKernelGGL(k_scan<SCAN_PMAP>, dim3(ntiles), dim3(256), 0, st, in, n, out, desc, ctr, ntiles, misc,
+                           expect);
+    else if (kind == SCAN_MASKS)
+        hipLaunchKernelGGL(k_scan<SCAN_MASKS>, dim3(ntiles), dim3(256), 0, st, in, n, out, desc, ctr, ntiles, misc,
                            expect);
     else
         hipLaunchKernelGGL(k_scan<SCAN_CHUNKS>, dim3(ntiles), dim3(256), 0, st, in, n, out, desc, ctr, ntiles, misc,

@@ -120,6 +120,8 @@ def lib() -> ctypes.CDLL:
     L.fz_selector_adam_step.argtypes = [vp, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                         ctypes.c_float, vp]
     L.fz_selector_adam_step.restype = i32
+    L.fz_compress_speed.argtypes = [vp, P, vp, vp, u64, ctypes.POINTER(u64), vp]
+    L.fz_compress_speed.restype = i32
     L.fz_decompress_noalloc.argtypes = [vp, u64, vp, vp, u64, vp]
     L.fz_decompress_noalloc.restype = i32
     L.fz_noalloc_scratch_bytes.argtypes = []
@@ -213,8 +215,10 @@ class Context:
         return int(lib().fz_compress_bound(ctypes.byref(params_for(shape, 1.0))))
 
     def compress(self, x: torch.Tensor, eb: float, mode: int = EB_REL, out: torch.Tensor | None = None,
-                 pred: int = PRED_LORENZO1) -> torch.Tensor:
-        """Compress a float32 device field; returns a uint8 device tensor (view of `out`)."""
+                 pred: int = PRED_LORENZO1, codec: str = "huffman") -> torch.Tensor:
+        """Compress a float32 device field; returns a uint8 device tensor (view
+        of `out`).  codec "huffman" (fz_compress) or "shuffle" (the
+        bit-shuffle codec, fz_compress_speed)."""
         if x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous():
             raise ValueError("x must be a contiguous float32 device tensor")
         key = (tuple(x.shape), float(eb), int(mode), int(pred))
@@ -229,10 +233,15 @@ class Context:
                 raise FZError(-1, "fz_compress_bound")
             out = torch.empty(cap, dtype=torch.uint8, device=x.device)
         n = ctypes.c_uint64(0)
-        rc = lib().fz_compress(self._h, ctypes.byref(p), ctypes.c_void_p(x.data_ptr()),
-                               ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(n),
-                               _stream_handle(x.device))
-        _check(rc, "fz_compress")
+        if codec == "huffman":
+            fn, name = lib().fz_compress, "fz_compress"
+        elif codec == "shuffle":
+            fn, name = lib().fz_compress_speed, "fz_compress_speed"
+        else:
+            raise ValueError("codec is 'huffman' or 'shuffle'")
+        rc = fn(self._h, ctypes.byref(p), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                out.numel(), ctypes.byref(n), _stream_handle(x.device))
+        _check(rc, name)
         return out[: n.value]
 
     # -------------------------------------------------------------- decompress

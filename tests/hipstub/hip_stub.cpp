@@ -303,6 +303,7 @@ namespace fz {
 uint32_t scan_tiles(uint32_t n) { return (n + 1023) / 1024; }
 uint32_t encode_groups(uint32_t ntiles) { return (ntiles + 7) / 8; }
 uint32_t feature_tiles(uint32_t nblocks) { return (nblocks + 15) / 16; }
+uint32_t shuffle_groups(uint32_t nblocks) { return (nblocks + 31) / 32; }
 
 #define K(name, ...) submit(st, Node{name, {__VA_ARGS__}})
 #define R(p) Ref{(const void*)(p), 0}
@@ -357,7 +358,8 @@ void launch_encode(hipStream_t st, int, const uint16_t* codes, const Geom& g, co
 void launch_finalize(hipStream_t st, const Geom& g, uint32_t mode, double eb, uint32_t pred, Misc* misc, uint8_t* out,
                      uint32_t ntiles, const uint64_t* tile_start, const uint32_t* tfirst, const uint32_t* tlast,
                      const uint32_t* tile_cnt, const uint64_t* tile_off, const uint2* ostage, const uint2* pstage,
-                     const uint8_t* bpred, const uint64_t* reg_idx, const int32_t* coef, const float* x) {
+                     const uint8_t* bpred, const uint64_t* reg_idx, const int32_t* coef, const float* x,
+                     uint32_t) {
     Node nd{"finalize", {{misc, sizeof(Misc)}, R(out), {tile_start, 8ull * ntiles}, {tfirst, 4ull * ntiles},
                          {tlast, 4ull * ntiles}, {tile_cnt, 4ull * ntiles}, {tile_off, 8ull * ntiles}, R(ostage),
                          R(pstage), R(bpred), R(reg_idx), R(coef), {x, 4 * g.N}}};
@@ -484,6 +486,17 @@ void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, u
     K("decode_pred", {stream, 4 * words}, {off, 8ull * g.nblocks}, {chunks, 2ull * g.nblocks}, {lut, 2ull * kLut},
       {opos, 4 * n_out}, {oval, 4 * n_out}, {oidx, 8ull * g.nblocks}, {res, 4ull * g.nblocks * kBlockElems},
       R(bpred), R(reg_idx), {coefs, 16 * nreg}, {out, 4 * g.N}, {misc, sizeof(Misc)});
+}
+void launch_shuffle(hipStream_t st, const Geom& g, const uint16_t* codes, uint8_t* out, uint64_t limit,
+                    uint64_t* desc, Misc* misc) {
+    K("shuffle", {codes, 2ull * g.nblocks * kBlockElems}, {out, limit}, {desc, 8ull * shuffle_groups(g.nblocks)},
+      {misc, sizeof(Misc)});
+}
+void launch_unshuffle(hipStream_t st, const Geom& g, const uint32_t* masks, const uint32_t* kept, uint64_t nkept,
+                      const uint64_t* off, const uint32_t* opos, const int32_t* oval, const uint2* oidx,
+                      uint64_t n_out, double, float* out, Misc* misc) {
+    K("unshuffle", {masks, 20ull * g.nblocks}, {kept, 4 * nkept}, {off, 8ull * g.nblocks}, {opos, 4 * n_out},
+      {oval, 4 * n_out}, {oidx, 8ull * g.nblocks}, {out, 4 * g.N}, {misc, sizeof(Misc)});
 }
 void launch_patch(hipStream_t st, const Geom& g, const uint32_t* ppos, const uint32_t* pbits, uint64_t n_pat, float* out,
                   Misc* misc) {
