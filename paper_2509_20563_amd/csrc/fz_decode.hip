@@ -545,7 +545,12 @@ struct FastDec {
 // RES = false: inverse Lorenzo, dequantisation and rows of floats (two
 // float4 stores per row when VEC, rows 16-byte aligned; else eight dword
 // stores); RES = true: residuals (int32, block-major) for the mapped decoder.
-template <int ND, bool RES, bool VEC, bool XT = false>
+// MAP (with RES = false): each lane's block has its own predictor (the map,
+// or fixed_pred >= 0): a first-order block is finished as above, a
+// regression block adds its fixed-point plane to the residuals in place of
+// the prefix sums, and a second-order block writes its residuals (its row
+// stores carry first-order values that k_inverse_wave overwrites).
+template <int ND, bool RES, bool VEC, bool XT = false, bool MAP = false>
 __global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint32_t ib1, uint32_t nint,
                                                      const uint32_t* __restrict__ stream, uint64_t nwords,
                                                      const uint64_t* __restrict__ off,
@@ -553,7 +558,10 @@ __global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint3
                                                      const uint16_t* __restrict__ lut_g,
                                                      const int32_t* __restrict__ oval,
                                                      const uint2* __restrict__ oidx, uint64_t n_out, double e2,
-                                                     float* __restrict__ out, int32_t* __restrict__ res, Misc* misc) {
+                                                     float* __restrict__ out, int32_t* __restrict__ res, Misc* misc,
+                                                     int fixed_pred, const uint8_t* __restrict__ bpred,
+                                                     const uint64_t* __restrict__ reg_idx,
+                                                     const int32_t* __restrict__ coefs, uint64_t nreg) {
     __shared__ uint16_t LUT[kLut];
     __shared__ uint32_t SRING[kDecLanes * kRing];
     __shared__ uint32_t ORING[kDecLanes * kORing];
@@ -596,6 +604,32 @@ __global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint3
     fd.O = reinterpret_cast<const uint4*>(oval);
     fd.init(start, bits, oval, n_out, first, count);
     const uint32_t pos_b = b * kBlockElems;
+    // MAP: this lane's predictor; a regression block's plane as
+    // floor((A + Bx u + By v + Bz w + 128) / 256), u = 2 lx - (bs0 - 1), ...
+    bool lreg = false, lsec = false;
+    int64_t cA = 0, cX = 0, cY = 0, cZ = 0;
+    if (MAP) {
+        const uint32_t p = fixed_pred >= 0 ? (uint32_t)fixed_pred : bpred[b];
+        lsec = p == 1;
+        lreg = p == 2;
+        if (lreg) {
+            const uint64_t r = fixed_pred >= 0 ? b : reg_idx[b];
+            if (r < nreg) {
+                const int4 c = reinterpret_cast<const int4*>(coefs)[r];
+                cA = c.x;
+                cX = c.y;
+                cY = c.z;
+                cZ = c.w;
+            } else if (active) {
+                atomicOr(&misc->flags, F_CORRUPT);
+            }
+        }
+    }
+    // plane at (lx = 0, ly, lz) + 128, the step along x is 2 Bx
+    auto plane_row = [&](int32_t ly, int32_t lz) -> int64_t {
+        return cA + 128 - cX * (int64_t)(g.bs[0] - 1) + cY * (int64_t)(2 * ly - ((int32_t)g.bs[1] - 1)) +
+               cZ * (int64_t)(2 * lz - ((int32_t)g.bs[2] - 1));
+    };
     auto deq = [&](int32_t q) -> float { return (float)((double)q * e2); };
     auto store8 = [&](uint64_t idx, const int32_t* q) {
         if (VEC) {
@@ -656,6 +690,16 @@ __global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint3
                         qp[y * 8 + x] += pr[x];
                         q[x] = qp[y * 8 + x];
                     }
+                    if (MAP) {
+                        if (lsec) store_res(pos0, d);
+                        int64_t sv = plane_row(y, (int32_t)z);
+#pragma unroll
+                        for (int x = 0; x < 8; x++) {
+                            const int32_t rq = (int32_t)((uint32_t)d[x] + (uint32_t)(int32_t)(sv >> 8));
+                            q[x] = lreg ? rq : q[x];
+                            sv += 2 * cX;
+                        }
+                    }
                     const uint64_t yg = (uint64_t)iby * 8 + y, zg = (uint64_t)ibz * 8 + z;
                     store8(x0 + (uint64_t)g.n[0] * (yg + (uint64_t)g.n[1] * zg), q);
                 }
@@ -684,6 +728,16 @@ __global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint3
                         qp[x8 * 8 + i] += rs;
                         q[i] = qp[x8 * 8 + i];
                     }
+                    if (MAP) {
+                        if (lsec) store_res(pos0, d);
+                        int64_t sv = plane_row((int32_t)y, 0) + 2 * cX * (int64_t)(8 * x8);
+#pragma unroll
+                        for (int i = 0; i < 8; i++) {
+                            const int32_t rq = (int32_t)((uint32_t)d[i] + (uint32_t)(int32_t)(sv >> 8));
+                            q[i] = lreg ? rq : q[i];
+                            sv += 2 * cX;
+                        }
+                    }
                     store8(row + x8 * 8, q);
                 }
             }
@@ -706,6 +760,16 @@ __global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint3
                     for (int i = 0; i < 8; i++) {
                         acc += d[i];
                         q[i] = acc;
+                    }
+                    if (MAP) {
+                        if (lsec) store_res(pos_b + i0s, d);
+                        int64_t sv = plane_row(0, 0) + 2 * cX * (int64_t)i0s;
+#pragma unroll
+                        for (int i = 0; i < 8; i++) {
+                            const int32_t rq = (int32_t)((uint32_t)d[i] + (uint32_t)(int32_t)(sv >> 8));
+                            q[i] = lreg ? rq : q[i];
+                            sv += 2 * cX;
+                        }
                     }
                     store8(row + i0s, q);
                 }
@@ -786,110 +850,67 @@ __global__ __launch_bounds__(256) void k_decode_res(Geom g, const uint32_t* __re
     outlier_totals(t, active, oq, oi0, misc, reinterpret_cast<uint32_t*>(LUT));
 }
 
-// One wave (workgroup of 64) per block: residuals -> grid values in LDS by
-// the block's inverse, then dequantised row stores.
+// The blocks the fast decoder leaves as residuals (edge blocks, and
+// second-order blocks, or all blocks of a second-order container): one wave
+// per block, lane = segment of 8 values along x (as the residual layout),
+// the inverse as prefix sums in registers and across lanes (twice for the
+// second order: prefix sums along different axes commute) or the
+// regression plane added, then dequantised row stores.  With interior_done
+// the interior blocks other than second-order ones are already written.
 template <int ND>
-__global__ __launch_bounds__(64) void k_inverse(Geom g, const int32_t* __restrict__ res, int fixed_pred,
-                                                const uint8_t* __restrict__ bpred,
-                                                const uint64_t* __restrict__ reg_idx,
-                                                const int32_t* __restrict__ coefs, uint64_t nreg, double e2,
-                                                float* __restrict__ out, int vec, Misc* misc) {
-    __shared__ int32_t A[kBlockElems];
-    const uint32_t b = blockIdx.x;
-    const uint32_t lane = threadIdx.x;
-    const BlockInfo info = block_info(g, b);
-    const uint32_t p = fixed_pred >= 0 ? (uint32_t)fixed_pred : bpred[b];
-    const int32_t* rb = res + (uint64_t)b * kBlockElems;
-    {
-        const int4* src = reinterpret_cast<const int4*>(rb + 8 * lane);
-        int4* dst = reinterpret_cast<int4*>(&A[8 * lane]);
-        dst[0] = src[0];
-        dst[1] = src[1];
-    }
-    __syncthreads();
-    const uint32_t bs0 = g.bs[0], bs1 = g.bs[1];
-    const uint32_t ext[3] = {info.ex, info.ey, info.ez};
-    if (p <= 1) {
-        // inclusive prefix sums along x, y, z (twice each for the second order)
-        const int passes = p == 1 ? 2 : 1;
-        for (int axis = 0; axis < (int)ND; axis++) {
-            const uint32_t len = ext[axis];
-            const uint32_t stride = axis == 0 ? 1 : (axis == 1 ? bs0 : bs0 * bs1);
-            const uint32_t nlines = kBlockElems / (axis == 0 ? bs0 : (axis == 1 ? bs1 : 8));
-            if (ND == 1) {
-                // one line of 512: lane-local prefix over 8, wave scan of totals
-                for (int rep = 0; rep < passes; rep++) {
-                    int32_t v[8];
-                    int32_t acc = 0;
-#pragma unroll
-                    for (int i = 0; i < 8; i++) {
-                        acc += A[8 * lane + i];
-                        v[i] = acc;
-                    }
-                    const int32_t incl = (int32_t)wave_incl_scan((uint32_t)acc);
-                    const int32_t excl = incl - acc;
-#pragma unroll
-                    for (int i = 0; i < 8; i++) A[8 * lane + i] = v[i] + excl;
-                    __syncthreads();
-                }
-            } else {
-                for (uint32_t line = lane; line < nlines; line += 64) {
-                    // base of this line: the remaining coordinates
-                    uint32_t base;
-                    if (axis == 0) base = line * bs0;
-                    else if (axis == 1) base = (line % bs0) + (line / bs0) * bs0 * bs1;
-                    else base = line;
-                    for (int rep = 0; rep < passes; rep++) {
-                        int32_t acc = 0;
-                        for (uint32_t i = 0; i < len; i++) {
-                            acc += A[base + i * stride];
-                            A[base + i * stride] = acc;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
-    } else {
-        // regression: add the fixed-point plane back
-        // a map that selects more regression blocks than the container
-        // holds coefficients for is corrupt (checked again on the host)
-        const uint64_t r = fixed_pred >= 0 ? b : reg_idx[b];
-        int4 c = make_int4(0, 0, 0, 0);
-        if (r < nreg) c = reinterpret_cast<const int4*>(coefs)[r];
-        else if (lane == 0) atomicOr(&misc->flags, F_CORRUPT);
-        for (uint32_t k = lane; k < kBlockElems; k += 64) {
-            const uint32_t lx = k % bs0, ly = (k / bs0) % bs1, lz = k / (bs0 * bs1);
-            if (lx < info.ex && ly < info.ey && lz < info.ez) {
-                const int64_t sum = (int64_t)c.x + (int64_t)c.y * (2 * (int32_t)lx - ((int32_t)info.ex - 1)) +
-                                    (int64_t)c.z * (2 * (int32_t)ly - ((int32_t)info.ey - 1)) +
-                                    (int64_t)c.w * (2 * (int32_t)lz - ((int32_t)info.ez - 1)) + 128;
-                A[k] += (int32_t)(sum >> 8);
-            }
-        }
-        __syncthreads();
-    }
-    // dequantise and store: lane = segment of 8 values along x
-    uint32_t lx0, ly, lz;
-    seg_coords<ND>(lane, lx0, ly, lz);
-    if (ly < info.ey && lz < info.ez && lx0 < info.ex) {
-        const uint32_t nv = min(8u, info.ex - lx0);
-        const uint64_t idx = ((uint64_t)info.bx * g.bs[0] + lx0) +
-                             (uint64_t)g.n[0] * (((uint64_t)info.by * g.bs[1] + ly) +
-                                                 (uint64_t)g.n[1] * ((uint64_t)info.bz * g.bs[2] + lz));
-        float v[8];
-#pragma unroll
-        for (int i = 0; i < 8; i++) v[i] = (float)((double)A[8 * lane + i] * e2);
-        if (nv == 8 && vec) {
-            f32x4* q4 = reinterpret_cast<f32x4*>(out + idx);
-            const f32x4 a = {v[0], v[1], v[2], v[3]};
-            const f32x4 c = {v[4], v[5], v[6], v[7]};
-            q4[0] = a;
-            q4[1] = c;
+__global__ __launch_bounds__(256) void k_inverse_wave(Geom g, const int32_t* __restrict__ res, int fixed_pred,
+                                                      const uint8_t* __restrict__ bpred,
+                                                      const uint64_t* __restrict__ reg_idx,
+                                                      const int32_t* __restrict__ coefs, uint64_t nreg, double e2,
+                                                      float* __restrict__ out, int vec, Misc* misc, uint32_t ib0,
+                                                      uint32_t ib1, uint32_t ib2, int interior_done) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t nw = gridDim.x * 4;
+    const uint32_t ib[3] = {ib0, ib1, ib2};
+    bool bad = false;
+    for (uint32_t b = blockIdx.x * 4 + (threadIdx.x >> 6); b < g.nblocks; b += nw) {
+        const uint32_t p = fixed_pred >= 0 ? (uint32_t)fixed_pred : bpred[b];
+        const BlockInfo bi = block_info(g, b);
+        if (interior_done && p != 1 && is_interior(bi, ib)) continue;
+        const int4* src = reinterpret_cast<const int4*>(res + (uint64_t)b * kBlockElems + 8 * lane);
+        const int4 r0 = src[0], r1 = src[1];
+        int32_t v[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+        uint32_t lx0, ly, lz;
+        seg_coords<ND>(lane, lx0, ly, lz);
+        if (p <= 1) {
+            block_prefix<ND>(v, lane);
+            if (p == 1) block_prefix<ND>(v, lane);
         } else {
-            for (uint32_t i = 0; i < nv; i++) out[idx + i] = v[i];
+            const uint64_t r = fixed_pred >= 0 ? b : reg_idx[b];
+            int4 c = make_int4(0, 0, 0, 0);
+            if (r < nreg) c = reinterpret_cast<const int4*>(coefs)[r];
+            else bad = true;
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                const int64_t sum = (int64_t)c.x + (int64_t)c.y * (2 * (int32_t)(lx0 + i) - ((int32_t)bi.ex - 1)) +
+                                    (int64_t)c.z * (2 * (int32_t)ly - ((int32_t)bi.ey - 1)) +
+                                    (int64_t)c.w * (2 * (int32_t)lz - ((int32_t)bi.ez - 1)) + 128;
+                v[i] = (int32_t)((uint32_t)v[i] + (uint32_t)(int32_t)(sum >> 8));
+            }
+        }
+        uint32_t nvalid;
+        const uint64_t row = seg_index<ND>(g, bi, lane, nvalid);
+        if (nvalid) {
+            float f[8];
+#pragma unroll
+            for (int i = 0; i < 8; i++) f[i] = (float)((double)v[i] * e2);
+            if (nvalid == 8 && vec && (row & 3) == 0) {
+                f32x4* o4 = reinterpret_cast<f32x4*>(out + row);
+                o4[0] = f32x4{f[0], f[1], f[2], f[3]};
+                o4[1] = f32x4{f[4], f[5], f[6], f[7]};
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; i++)
+                    if ((uint32_t)i < nvalid) out[row + i] = f[i];
+            }
         }
     }
+    if (__ballot(bad) && lane == 0) atomicOr(&misc->flags, F_CORRUPT);
 }
 
 // ------------------------------------------------------ outlier block index
@@ -1059,7 +1080,8 @@ void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64
         const uint32_t fg = (I.n + 255) / 256;
 #define FZ_FAST(NDV, V)                                                                                               \
     hipLaunchKernelGGL((k_decode_fast<NDV, false, V>), dim3(fg), dim3(256), 0, st, g, I.ib[0], I.ib[1], I.n, stream, \
-                       stream_words, off, chunks, lut, oval, oidx, n_out, e2, out, (int32_t*)nullptr, misc)
+                       stream_words, off, chunks, lut, oval, oidx, n_out, e2, out, (int32_t*)nullptr, misc, -1,      \
+                       (const uint8_t*)nullptr, (const uint64_t*)nullptr, (const int32_t*)nullptr, (uint64_t)0)
         if (vec && g.ndim == 3 && I.ib[0] % 64 == 0) {
             // staged row stores where a wave covers one run of 64 blocks
             // along x (measured: 512^3 decodes 37% faster at 1e-2; a 384^3
@@ -1067,7 +1089,8 @@ void launch_decode(hipStream_t st, const Geom& g, const uint32_t* stream, uint64
             // 8% slower staged than with the strided stores)
             hipLaunchKernelGGL((k_decode_fast<3, false, true, true>), dim3(fg), dim3(256), 0, st, g, I.ib[0], I.ib[1],
                                I.n, stream, stream_words, off, chunks, lut, oval, oidx, n_out, e2, out,
-                               (int32_t*)nullptr, misc);
+                               (int32_t*)nullptr, misc, -1, (const uint8_t*)nullptr, (const uint64_t*)nullptr,
+                               (const int32_t*)nullptr, (uint64_t)0);
         } else if (vec) {
             if (g.ndim == 3) FZ_FAST(3, true);
             else if (g.ndim == 2) FZ_FAST(2, true);
@@ -1101,25 +1124,41 @@ void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, u
                         int fixed_pred, const uint8_t* bpred, const uint64_t* reg_idx, const int32_t* coefs,
                         uint64_t nreg, double e2, float* out, int vec, Misc* misc) {
     const Interior I = interior_of(g);
+    // interior blocks: the fast decoder finishes first-order and regression
+    // blocks (a second-order container only gets its residuals there)
+    const bool fused = I.n && fixed_pred != 1;
     if (I.n) {
         const uint32_t fg = (I.n + 255) / 256;
-#define FZ_FAST(NDV)                                                                                               \
-    hipLaunchKernelGGL((k_decode_fast<NDV, true, false>), dim3(fg), dim3(256), 0, st, g, I.ib[0], I.ib[1], I.n,     \
-                       stream,                                                                                      \
-                       stream_words, off, chunks, lut, oval, oidx, n_out, e2, (float*)nullptr, res, misc)
-        if (g.ndim == 3) FZ_FAST(3);
-        else if (g.ndim == 2) FZ_FAST(2);
-        else FZ_FAST(1);
-#undef FZ_FAST
+#define FZ_ARGS                                                                                                     \
+    dim3(fg), dim3(256), 0, st, g, I.ib[0], I.ib[1], I.n, stream, stream_words, off, chunks, lut, oval, oidx, n_out, \
+        e2, out, res, misc, fixed_pred, bpred, reg_idx, coefs, nreg
+        if (!fused) {
+            if (g.ndim == 3) hipLaunchKernelGGL((k_decode_fast<3, true, false>), FZ_ARGS);
+            else if (g.ndim == 2) hipLaunchKernelGGL((k_decode_fast<2, true, false>), FZ_ARGS);
+            else hipLaunchKernelGGL((k_decode_fast<1, true, false>), FZ_ARGS);
+        } else if (vec && g.ndim == 3 && I.ib[0] % 64 == 0) {
+            hipLaunchKernelGGL((k_decode_fast<3, false, true, true, true>), FZ_ARGS);
+        } else if (vec) {
+            if (g.ndim == 3) hipLaunchKernelGGL((k_decode_fast<3, false, true, false, true>), FZ_ARGS);
+            else if (g.ndim == 2) hipLaunchKernelGGL((k_decode_fast<2, false, true, false, true>), FZ_ARGS);
+            else hipLaunchKernelGGL((k_decode_fast<1, false, true, false, true>), FZ_ARGS);
+        } else {
+            if (g.ndim == 3) hipLaunchKernelGGL((k_decode_fast<3, false, false, false, true>), FZ_ARGS);
+            else if (g.ndim == 2) hipLaunchKernelGGL((k_decode_fast<2, false, false, false, true>), FZ_ARGS);
+            else hipLaunchKernelGGL((k_decode_fast<1, false, false, false, true>), FZ_ARGS);
+        }
+#undef FZ_ARGS
     }
     const uint32_t grid = (g.nblocks + 255) / 256;
     const int skip = I.n ? 1 : 0;
+    uint32_t wg = (g.nblocks + 3) / 4;
+    if (wg > 8192) wg = 8192;
 #define FZ_DRES(NDV)                                                                                                \
     if (I.n != g.nblocks)                                                                                           \
         hipLaunchKernelGGL(k_decode_res<NDV>, dim3(grid), dim3(256), 0, st, g, stream, stream_words, off, chunks,   \
                            lut, opos, oval, oidx, n_out, res, misc, skip, I.ib[0], I.ib[1], I.ib[2]);            \
-    hipLaunchKernelGGL(k_inverse<NDV>, dim3(g.nblocks), dim3(64), 0, st, g, res, fixed_pred, bpred, reg_idx, coefs, \
-                       nreg, e2, out, vec, misc)
+    hipLaunchKernelGGL(k_inverse_wave<NDV>, dim3(wg), dim3(256), 0, st, g, res, fixed_pred, bpred, reg_idx, coefs,  \
+                       nreg, e2, out, vec, misc, I.ib[0], I.ib[1], I.ib[2], fused ? 1 : 0)
     if (g.ndim == 3) {
         FZ_DRES(3);
     } else if (g.ndim == 2) {
