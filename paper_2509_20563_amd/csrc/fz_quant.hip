@@ -427,20 +427,24 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
             pk.w = code[6] | (code[7] << 16);
             *reinterpret_cast<uint4*>(&codes[(uint64_t)b * kBlockElems + s * 8]) = pk;
         }
-        // histogram: one candidate code per wave (lane 0's first): its
-        // matches are counted by ballots and added once; every other valid
-        // code is added by its lane
+        // histogram: the zero residual's code (the most frequent one in
+        // smooth and in flat regions) is counted by ballots and added once
+        // per wave; every other valid code is added by its lane.  (A
+        // candidate taken from the block's corner, whose residual is the
+        // grid value itself, left most lanes of flat blocks adding to one
+        // bin in the same instruction: 64-way serialised LDS atomics, 2.8 ms
+        // instead of 1.9 on the 1024^3 fronts/spikes field.)
         if (blk) {
-            const uint32_t cand = (uint32_t)__builtin_amdgcn_readfirstlane((int)code[0]);
-            uint32_t nmatch = 0;
+            const uint32_t ca = (uint32_t)kRadius;
+            uint32_t na = 0;
 #pragma unroll
             for (int i = 0; i < 8; i++) {
                 const bool valid = i < (int)nv;
-                const bool match = valid && code[i] == cand;
-                nmatch += (uint32_t)__popcll(__ballot(match));
-                if (valid && !match) atomicAdd(&H[code[i]], 1u);
+                const bool ma = valid && code[i] == ca;
+                na += (uint32_t)__popcll(__ballot(ma));
+                if (valid && !ma) atomicAdd(&H[code[i]], 1u);
             }
-            if (lane == 0 && nmatch) atomicAdd(&H[cand], nmatch);
+            if (lane == 0 && na) atomicAdd(&H[ca], na);
         }
 
         // ---------------- outliers and patches (block order inside the tile)
