@@ -72,12 +72,21 @@ __global__ __launch_bounds__(256) void k_shuffle(Geom g, const uint16_t* __restr
                 const bool valid = lx < bi.ex && ly < bi.ey && lz < bi.ez;
                 s[r] = valid ? fold_code(cb[slot]) : 0u;
             }
+            // planes above the block's highest symbol bit, and rounds whose
+            // 64 symbols are all zero, hold only zero words (wave-uniform
+            // skips)
+            uint32_t orl = s[0] | s[1] | s[2] | s[3] | s[4] | s[5] | s[6] | s[7];
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1) orl |= (uint32_t)__shfl_xor((int)orl, d, 64);
+            const int P = 32 - __clz((int)orl);
             // round r covers groups 2r (low half of each ballot) and 2r + 1;
             // word k = 10 group + plane goes to lane k mod 64, slot k / 64
 #pragma unroll
-            for (int r = 0; r < 8; r++)
+            for (int r = 0; r < 8; r++) {
+                if (!__ballot(s[r] != 0)) continue;
 #pragma unroll
                 for (int p = 0; p < kPlanes; p++) {
+                    if (p >= P) break;
                     const uint64_t bal = __ballot((s[r] >> p) & 1u);
                     const uint32_t k0 = (2 * r) * kPlanes + p, k1 = k0 + kPlanes;
                     const uint32_t lo = (uint32_t)bal, hi = (uint32_t)(bal >> 32);
@@ -92,6 +101,7 @@ __global__ __launch_bounds__(256) void k_shuffle(Geom g, const uint16_t* __restr
                         else w2 = hi;
                     }
                 }
+            }
         }
         kw[i][0] = w0;
         kw[i][1] = w1;
@@ -179,23 +189,31 @@ __global__ __launch_bounds__(256) void k_unshuffle(Geom g, const uint32_t* __res
         uint32_t before = (uint32_t)__popc(wa & ((1u << sh) - 1u));
         before += (a > 0 ? __popc(mw0) : 0) + (a > 1 ? __popc(mw1) : 0) + (a > 2 ? __popc(mw2) : 0) +
                   (a > 3 ? __popc(mw3) : 0);
-        uint32_t pw[kPlanes];
+        // planes no group of the block keeps are zero for every lane
+        uint32_t orf = field;
 #pragma unroll
-        for (int p = 0; p < kPlanes; p++) {
-            const uint64_t idx = base + before + (uint32_t)__popc(field & ((1u << p) - 1u));
-            const bool has = (field >> p) & 1u;
-            const bool inb = idx < nkept;
-            bad |= has && !inb;
-            pw[p] = (has && inb) ? kept[idx] : 0u;
-        }
+        for (int d = 32; d > 0; d >>= 1) orf |= (uint32_t)__shfl_xor((int)orf, d, 64);
+        const int P = 32 - __clz((int)orf);
         const uint32_t bo = 8 * (lane & 3);
-        uint32_t s[8];
+        uint32_t s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (P) {
+            uint32_t pb[kPlanes];  // this lane's 8 bits of each plane word
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
-            uint32_t v = 0;
+            for (int p = 0; p < kPlanes; p++) {
+                pb[p] = 0;
+                if (p >= P) continue;
+                const uint64_t idx = base + before + (uint32_t)__popc(field & ((1u << p) - 1u));
+                const bool has = (field >> p) & 1u;
+                const bool inb = idx < nkept;
+                bad |= has && !inb;
+                pb[p] = (has && inb) ? (kept[idx] >> bo) & 0xFFu : 0u;
+            }
 #pragma unroll
-            for (int p = 0; p < kPlanes; p++) v |= ((pw[p] >> (bo + i)) & 1u) << p;
-            s[i] = v;
+            for (int p = 0; p < kPlanes; p++) {
+                if (p >= P) break;
+#pragma unroll
+                for (int i = 0; i < 8; i++) s[i] |= ((pb[p] >> i) & 1u) << p;
+            }
         }
         const BlockInfo bi = block_info(g, b);
         uint32_t nvalid;
