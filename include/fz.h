@@ -150,6 +150,28 @@ int fz_header_read(const void *h_hdr, uint64_t n, fz_params *p, uint64_t *n_elem
 int fz_decompress(fz_ctx *ctx, const void *d_in, uint64_t in_bytes, const void *h_hdr, float *d_out,
                   uint64_t out_elems, void *stream);
 
+/* Graph mode (Sec. 3.3.1: the paper runs pipelines as CUDASTF tasks over
+ * logical data; the runtime infers the data dependencies from the tasks'
+ * access modes and runs independent stages concurrently).  With graph mode
+ * on, each fz_compress, fz_compress_speed and fz_decompress call is built
+ * as a list of stage tasks, each declaring the data it reads, writes or
+ * reduces into; dependencies are inferred from those accesses, independent
+ * stages are placed on separate streams (for example the outlier-count scan
+ * beside the Huffman code and encoder, or the outlier index beside the
+ * chunk-offset scan), and the call is captured once into a graph that later
+ * calls with the same parameters, header and buffers replay.  Outputs are
+ * identical to the eager calls.  Per-stage timing is not recorded in graph
+ * mode (the whole-call timing filter "call" is).  Returns FZ_OK or
+ * FZ_ERR_ARG. */
+int fz_set_graph_mode(fz_ctx *ctx, int enable);
+
+/* Shape of the last captured graph of a kind (which: 0 = compression,
+ * 1 = decompression): its tasks, the streams they were laid out on, the
+ * most tasks at one depth of the dependency graph (1 = a chain) and its
+ * dependency edges after transitive reduction.  FZ_ERR_ARG when no graph of
+ * that kind was captured. */
+int fz_graph_info(fz_ctx *ctx, int which, int *h_tasks, int *h_streams, int *h_width, int *h_edges);
+
 /* Human-readable text for a status code (static storage). */
 const char *fz_strerror(int status);
 

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <map>
 #include <new>
 #include <vector>
@@ -14,6 +15,7 @@
 #include "../../include/fz.h"
 #include "fz_common.h"
 #include "fz_kernels.h"
+#include "fz_taskgraph.h"
 
 using namespace fz;
 
@@ -69,6 +71,14 @@ struct GraphCache {
 struct Tune {
     uint32_t wg_per_cu;     // quantiser / encoder / trial workgroups per CU
     uint32_t mm_wg_per_cu;  // min/max workgroups per CU
+};
+
+// A single call captured as a graph of its stage tasks (graph mode).
+constexpr int kGraphStreams = 4;  // the capture stream and three side streams
+constexpr int kGraphTasks = 16;   // tasks of one call, at most
+struct GraphCall {
+    GraphCache g;
+    fz::Schedule sched;
 };
 
 }  // namespace
@@ -165,6 +175,13 @@ struct fz_ctx {
     // own chain contexts, buffers and captured graph), the origin stream of
     // captures, the fork/join events and the autotuner's choices
     BatchSide bc, bd;
+    // graph mode of single calls: the last compression and decompression
+    // graphs, their schedules, and the side streams and events they were
+    // captured with
+    bool graph_mode = false;
+    GraphCall gcall[2];
+    hipStream_t gst[kGraphStreams] = {};
+    hipEvent_t gev[kGraphTasks + kGraphStreams + 1] = {};
     hipStream_t cstream = nullptr;
     hipEvent_t kev[kMaxChains + 1] = {};
     std::map<uint32_t, Tune> tune_field;       // per field class
@@ -436,17 +453,45 @@ int compress_prepare(fz_ctx* c, const fz_params* p, const Geom& g) {
     return rc;
 }
 
-// Every kernel of one compression on `st` (no host synchronisation; the
-// container size ends in c->misc->total_bytes, the verbatim container is
-// written on the device).
-void compress_enqueue(fz_ctx* c, const fz_params* p, const Geom& g, const float* d_in, uint8_t* out, hipStream_t st,
-                      const Tune& tn, bool marks) {
-    auto mark = [&](const char* name) {
-        if (marks) t_mark(c, st, name);
-    };
-    auto start = [&](const char* name) {
-        if (marks) t_start(c, st, name);
-    };
+// ----------------------------------------------------------- call tasks
+// A call is a list of stage tasks, each with the data it reads, writes or
+// reduces into (fz_taskgraph.h).  Eagerly the tasks run in order on the
+// call's stream; in graph mode the list becomes a captured graph whose
+// independent stages run as concurrent branches.
+struct Task {
+    const char* name;
+    std::vector<Acc> acc;
+    std::function<void(hipStream_t)> run;
+};
+using TaskList = std::vector<Task>;
+
+// Data identities of the Misc fields, grouped by the stage that owns them
+// (addresses inside the device struct, used as keys only).
+struct MiscIds {
+    const void *range, *qctr, *cb, *enc, *flags, *total, *mtile, *stile, *xtile, *dec, *ohl;
+    explicit MiscIds(Misc* m)
+        : range(&m->mm_lo), qctr(&m->qtile_ctr), cb(&m->total_bits_cb), enc(&m->total_bits_enc), flags(&m->flags),
+          total(&m->total_bytes), mtile(&m->mtile_ctr), stile(&m->stile_ctr), xtile(&m->xtile_ctr),
+          dec(&m->code0_count), ohl(&m->ohash_list) {}
+    void reset_all(std::vector<Acc>& a) const {
+        for (const void* d : {range, qctr, cb, enc, flags, total, mtile, stile, xtile, dec, ohl}) a.push_back({d, ACC_W});
+    }
+};
+
+void run_eager(fz_ctx* c, const TaskList& T, hipStream_t st, bool marks) {
+    for (const Task& k : T) {
+        if (marks) t_start(c, st, k.name);
+        k.run(st);
+        if (marks) t_mark(c, st, k.name);
+    }
+}
+
+// Every stage of one compression (no host synchronisation; the container
+// size ends in c->misc->total_bytes, the verbatim container is written on
+// the device).
+void compress_tasks(fz_ctx* c, const fz_params* p, const Geom& g, const float* d_in, uint8_t* out, const Tune& tn,
+                    TaskList& T) {
+    const MiscIds M(c->misc);
     const uint32_t pred = p->pred;
     const bool has_map = pred_has_map(pred);
     const uint32_t ntiles = (g.nblocks + kTileBlocks - 1) / kTileBlocks;
@@ -459,102 +504,155 @@ void compress_enqueue(fz_ctx* c, const fz_params* p, const Geom& g, const float*
     const uint64_t nreg_fixed = pred == FZ_PRED_REGRESSION ? g.nblocks : 0;
     const Layout L0 = make_layout(g.nblocks, has_map, nreg_fixed, 0, 0, 0);
     const uint32_t sd_blocks = has_map ? scan_tiles(g.nblocks) : 0;
-    start("reset");
-    launch_reset(st, c->misc, c->hist, c->desc_cnt, sd_tiles, c->desc_bits, encode_groups(ntiles), c->desc_pmap,
-                 sd_blocks,
-                 L0.chunks, L0.stream, nreg_fixed);
-    mark("reset");
-    if (p->eb_mode == FZ_EB_REL) {
-        start("minmax");
-        launch_minmax(st, d_in, g.N, (((uintptr_t)d_in & 15) == 0), c->misc, minmax_grid(c, g.N, tn.mm_wg_per_cu));
-        mark("minmax");
+    const fz_params P = *p;
+    {
+        std::vector<Acc> a = {{c->hist, ACC_W}, {c->desc_cnt, ACC_W}, {c->desc_bits, ACC_W}, {c->desc_pmap, ACC_W}};
+        M.reset_all(a);
+        T.push_back({"reset", a, [=](hipStream_t st) {
+                         launch_reset(st, c->misc, c->hist, c->desc_cnt, sd_tiles, c->desc_bits, encode_groups(ntiles),
+                                      c->desc_pmap, sd_blocks, L0.chunks, L0.stream, nreg_fixed);
+                     }});
     }
-    if (pred == FZ_PRED_AUTO_TRIAL) {
+    if (P.eb_mode == FZ_EB_REL)
+        T.push_back({"minmax", {{d_in, ACC_R}, {M.range, ACC_RED}, {M.flags, ACC_RED}}, [=](hipStream_t st) {
+                         launch_minmax(st, d_in, g.N, (((uintptr_t)d_in & 15) == 0), c->misc,
+                                       minmax_grid(c, g.N, tn.mm_wg_per_cu));
+                     }});
+    if (pred == FZ_PRED_AUTO_TRIAL)
         // reference code: the Huffman code of the first-order Lorenzo
         // histogram; then every block tries the three predictors
-        start("trial");
-        launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt,
-                     c->ostage, c->pstage, 0, nullptr, nullptr);
-        launch_codebook(st, c->hist, c->lens_ref, c->cw_ref, c->misc);
-        launch_trial(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, ntiles, c->cw_ref, c->bpred, c->costs);
-        launch_fill32(st, c->hist, kHistCopies * kBins, 0);
-        mark("trial");
-    }
-    if (pred == FZ_PRED_AUTO_MLP) {
+        T.push_back({"trial",
+                     {{d_in, ACC_R}, {M.range, ACC_R}, {c->codes, ACC_W}, {c->tile_cnt, ACC_W}, {c->ostage, ACC_W},
+                      {c->pstage, ACC_W}, {c->hist, ACC_RW}, {c->lens_ref, ACC_W}, {c->cw_ref, ACC_W}, {M.cb, ACC_W},
+                      {c->bpred, ACC_W}, {c->costs, ACC_W}, {M.flags, ACC_RED}},
+                     [=](hipStream_t st) {
+                         launch_quant(st, grid, d_in, g, P.eb_mode, P.eb, vec, c->misc, c->hist, c->codes, ntiles,
+                                      c->tile_cnt, c->ostage, c->pstage, 0, nullptr, nullptr);
+                         launch_codebook(st, c->hist, c->lens_ref, c->cw_ref, c->misc);
+                         launch_trial(st, grid, d_in, g, P.eb_mode, P.eb, vec, c->misc, ntiles, c->cw_ref, c->bpred,
+                                      c->costs);
+                         launch_fill32(st, c->hist, kHistCopies * kBins, 0);
+                     }});
+    if (pred == FZ_PRED_AUTO_MLP)
         // the network chooses each block's predictor from the features of
         // the block's sample (a pass over a quarter of the field)
-        start("select");
-        launch_features(st, (int)gmax, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->featb);
-        launch_mlp(st, (int)gmax, c->featb, g.nblocks, c->sel, nullptr, c->bpred);
-        mark("select");
-    }
-    start("quant");
+        T.push_back({"select",
+                     {{d_in, ACC_R}, {M.range, ACC_R}, {c->featb, ACC_W}, {c->sel, ACC_R}, {c->bpred, ACC_W},
+                      {M.flags, ACC_RED}},
+                     [=](hipStream_t st) {
+                         launch_features(st, (int)gmax, d_in, g, P.eb_mode, P.eb, vec, c->misc, c->featb);
+                         launch_mlp(st, (int)gmax, c->featb, g.nblocks, c->sel, nullptr, c->bpred);
+                     }});
     {
         const int fixed = has_map ? -1 : (int)pred;
-        launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt,
-                     c->ostage, c->pstage, fixed, c->bpred, c->coef);
+        std::vector<Acc> a = {{d_in, ACC_R},         {M.range, ACC_R},     {c->codes, ACC_W}, {c->tile_cnt, ACC_W},
+                              {c->ostage, ACC_W},    {c->pstage, ACC_W},   {c->hist, ACC_RED}, {M.flags, ACC_RED}};
+        if (pred != FZ_PRED_LORENZO1) {
+            a.push_back({c->bpred, ACC_R});
+            a.push_back({c->coef, ACC_W});
+        }
+        T.push_back({"quant", a, [=](hipStream_t st) {
+                         launch_quant(st, grid, d_in, g, P.eb_mode, P.eb, vec, c->misc, c->hist, c->codes, ntiles,
+                                      c->tile_cnt, c->ostage, c->pstage, fixed, c->bpred, c->coef);
+                     }});
     }
-    mark("quant");
-    if (has_map) {
-        start("scan_map");
-        launch_scan(st, SCAN_PMAP, c->bpred, g.nblocks, c->reg_idx, c->desc_pmap, &c->misc->mtile_ctr, c->misc, 0);
-        mark("scan_map");
-    }
-    start("scan_counts");
-    launch_scan(st, SCAN_COUNTS, c->tile_cnt, ntiles, c->tile_off, c->desc_cnt, &c->misc->qtile_ctr, c->misc, 0);
-    mark("scan_counts");
-    start("codebook");
-    launch_codebook(st, c->hist, out + kHdr, c->cw, c->misc);
-    mark("codebook");
-    start("encode");
-    launch_encode(st, grid, c->codes, g, c->cw, c->misc, ntiles, out, c->desc_bits, c->tile_start, c->tfirst,
-                  c->tlast);
-    mark("encode");
-    start("finalize");
-    launch_finalize(st, g, p->eb_mode, p->eb, pred, c->misc, out, ntiles, c->tile_start, c->tfirst, c->tlast,
-                    c->tile_cnt, c->tile_off, c->ostage, c->pstage, c->bpred, c->reg_idx, c->coef, d_in);
-    mark("finalize");
+    if (has_map)
+        T.push_back({"scan_map",
+                     {{c->bpred, ACC_R}, {c->reg_idx, ACC_W}, {c->desc_pmap, ACC_RW}, {M.mtile, ACC_RW},
+                      {M.flags, ACC_RED}},
+                     [=](hipStream_t st) {
+                         launch_scan(st, SCAN_PMAP, c->bpred, g.nblocks, c->reg_idx, c->desc_pmap,
+                                     &c->misc->mtile_ctr, c->misc, 0);
+                     }});
+    T.push_back({"scan_counts",
+                 {{c->tile_cnt, ACC_R}, {c->tile_off, ACC_W}, {c->desc_cnt, ACC_RW}, {M.qctr, ACC_RW},
+                  {M.flags, ACC_RED}},
+                 [=](hipStream_t st) {
+                     launch_scan(st, SCAN_COUNTS, c->tile_cnt, ntiles, c->tile_off, c->desc_cnt, &c->misc->qtile_ctr,
+                                 c->misc, 0);
+                 }});
+    T.push_back({"codebook", {{c->hist, ACC_RW}, {out, ACC_W}, {c->cw, ACC_W}, {M.cb, ACC_W}, {M.flags, ACC_RED}},
+                 [=](hipStream_t st) { launch_codebook(st, c->hist, out + kHdr, c->cw, c->misc); }});
+    T.push_back({"encode",
+                 {{c->codes, ACC_R}, {c->cw, ACC_R}, {M.mtile, ACC_R}, {out, ACC_W}, {c->desc_bits, ACC_RW},
+                  {c->tile_start, ACC_W}, {c->tfirst, ACC_W}, {c->tlast, ACC_W}, {M.enc, ACC_W}, {M.flags, ACC_RED}},
+                 [=](hipStream_t st) {
+                     launch_encode(st, grid, c->codes, g, c->cw, c->misc, ntiles, out, c->desc_bits, c->tile_start,
+                                   c->tfirst, c->tlast);
+                 }});
+    T.push_back({"finalize",
+                 {{M.range, ACC_R}, {M.qctr, ACC_R}, {M.cb, ACC_R}, {M.enc, ACC_R}, {M.mtile, ACC_R}, {M.flags, ACC_RW},
+                  {M.total, ACC_W}, {out, ACC_W}, {c->tile_start, ACC_R}, {c->tfirst, ACC_R}, {c->tlast, ACC_R},
+                  {c->tile_cnt, ACC_R}, {c->tile_off, ACC_R}, {c->ostage, ACC_R}, {c->pstage, ACC_R},
+                  {c->bpred, ACC_R}, {c->reg_idx, ACC_R}, {c->coef, ACC_R}, {d_in, ACC_R}},
+                 [=](hipStream_t st) {
+                     launch_finalize(st, g, P.eb_mode, P.eb, pred, c->misc, out, ntiles, c->tile_start, c->tfirst,
+                                     c->tlast, c->tile_cnt, c->tile_off, c->ostage, c->pstage, c->bpred, c->reg_idx,
+                                     c->coef, d_in);
+                 }});
 }
 
-// Every kernel of one bit-shuffle compression (first-order Lorenzo) on `st`:
-// the same quantisation as compress_enqueue, then the shuffle encoder in
-// place of the histogram -> code -> encode stages.
-void compress_speed_enqueue(fz_ctx* c, const fz_params* p, const Geom& g, const float* d_in, uint8_t* out,
-                            hipStream_t st, const Tune& tn, bool marks) {
-    auto mark = [&](const char* name) {
-        if (marks) t_mark(c, st, name);
-    };
-    auto start = [&](const char* name) {
-        if (marks) t_start(c, st, name);
-    };
+void compress_enqueue(fz_ctx* c, const fz_params* p, const Geom& g, const float* d_in, uint8_t* out, hipStream_t st,
+                      const Tune& tn, bool marks) {
+    TaskList T;
+    compress_tasks(c, p, g, d_in, out, tn, T);
+    run_eager(c, T, st, marks);
+}
+
+// Every stage of one bit-shuffle compression (first-order Lorenzo): the
+// same quantisation as compress_tasks, then the shuffle encoder in place of
+// the histogram -> code -> encode stages.
+void compress_speed_tasks(fz_ctx* c, const fz_params* p, const Geom& g, const float* d_in, uint8_t* out,
+                          const Tune& tn, TaskList& T) {
+    const MiscIds M(c->misc);
     const uint32_t ntiles = (g.nblocks + kTileBlocks - 1) / kTileBlocks;
     const int vec = (((uintptr_t)d_in & 15) == 0) && (g.ndim == 1 || (g.n[0] & 3) == 0);
     const uint32_t sd_tiles = scan_tiles(ntiles);
     const uint32_t gmax = (uint32_t)c->n_cu * tn.wg_per_cu;
     const int grid = (int)(ntiles < gmax ? ntiles : gmax);
-    start("reset");
-    launch_reset(st, c->misc, c->hist, c->desc_cnt, sd_tiles, c->desc_bits, shuffle_groups(g.nblocks), nullptr, 0,
-                 0, 0, 0);
-    mark("reset");
-    if (p->eb_mode == FZ_EB_REL) {
-        start("minmax");
-        launch_minmax(st, d_in, g.N, (((uintptr_t)d_in & 15) == 0), c->misc, minmax_grid(c, g.N, tn.mm_wg_per_cu));
-        mark("minmax");
+    const fz_params P = *p;
+    {
+        std::vector<Acc> a = {{c->hist, ACC_W}, {c->desc_cnt, ACC_W}, {c->desc_bits, ACC_W}};
+        M.reset_all(a);
+        T.push_back({"reset", a, [=](hipStream_t st) {
+                         launch_reset(st, c->misc, c->hist, c->desc_cnt, sd_tiles, c->desc_bits,
+                                      shuffle_groups(g.nblocks), nullptr, 0, 0, 0, 0);
+                     }});
     }
-    start("quant");
-    launch_quant(st, grid, d_in, g, p->eb_mode, p->eb, vec, c->misc, c->hist, c->codes, ntiles, c->tile_cnt,
-                 c->ostage, c->pstage, FZ_PRED_LORENZO1, nullptr, nullptr);
-    mark("quant");
-    start("scan_counts");
-    launch_scan(st, SCAN_COUNTS, c->tile_cnt, ntiles, c->tile_off, c->desc_cnt, &c->misc->qtile_ctr, c->misc, 0);
-    mark("scan_counts");
-    start("shuffle");
-    launch_shuffle(st, g, c->codes, out, (uint64_t)kHdr + 4 * g.N, c->desc_bits, c->misc);
-    mark("shuffle");
-    start("finalize");
-    launch_finalize(st, g, p->eb_mode, p->eb, FZ_PRED_LORENZO1, c->misc, out, ntiles, c->tile_start, c->tfirst,
-                    c->tlast, c->tile_cnt, c->tile_off, c->ostage, c->pstage, c->bpred, c->reg_idx, c->coef, d_in, 1);
-    mark("finalize");
+    if (P.eb_mode == FZ_EB_REL)
+        T.push_back({"minmax", {{d_in, ACC_R}, {M.range, ACC_RED}, {M.flags, ACC_RED}}, [=](hipStream_t st) {
+                         launch_minmax(st, d_in, g.N, (((uintptr_t)d_in & 15) == 0), c->misc,
+                                       minmax_grid(c, g.N, tn.mm_wg_per_cu));
+                     }});
+    T.push_back({"quant",
+                 {{d_in, ACC_R}, {M.range, ACC_R}, {c->codes, ACC_W}, {c->tile_cnt, ACC_W}, {c->ostage, ACC_W},
+                  {c->pstage, ACC_W}, {c->hist, ACC_RED}, {M.flags, ACC_RED}},
+                 [=](hipStream_t st) {
+                     launch_quant(st, grid, d_in, g, P.eb_mode, P.eb, vec, c->misc, c->hist, c->codes, ntiles,
+                                  c->tile_cnt, c->ostage, c->pstage, FZ_PRED_LORENZO1, nullptr, nullptr);
+                 }});
+    T.push_back({"scan_counts",
+                 {{c->tile_cnt, ACC_R}, {c->tile_off, ACC_W}, {c->desc_cnt, ACC_RW}, {M.qctr, ACC_RW},
+                  {M.flags, ACC_RED}},
+                 [=](hipStream_t st) {
+                     launch_scan(st, SCAN_COUNTS, c->tile_cnt, ntiles, c->tile_off, c->desc_cnt, &c->misc->qtile_ctr,
+                                 c->misc, 0);
+                 }});
+    T.push_back({"shuffle",
+                 {{c->codes, ACC_R}, {out, ACC_W}, {c->desc_bits, ACC_RW}, {M.xtile, ACC_RW}, {M.enc, ACC_W},
+                  {M.flags, ACC_RED}},
+                 [=](hipStream_t st) {
+                     launch_shuffle(st, g, c->codes, out, (uint64_t)kHdr + 4 * g.N, c->desc_bits, c->misc);
+                 }});
+    T.push_back({"finalize",
+                 {{M.range, ACC_R}, {M.qctr, ACC_R}, {M.enc, ACC_R}, {M.mtile, ACC_R}, {M.flags, ACC_RW},
+                  {M.total, ACC_W}, {out, ACC_W}, {c->tile_cnt, ACC_R}, {c->tile_off, ACC_R}, {c->ostage, ACC_R},
+                  {c->pstage, ACC_R}, {d_in, ACC_R}},
+                 [=](hipStream_t st) {
+                     launch_finalize(st, g, P.eb_mode, P.eb, FZ_PRED_LORENZO1, c->misc, out, ntiles, c->tile_start,
+                                     c->tfirst, c->tlast, c->tile_cnt, c->tile_off, c->ostage, c->pstage, c->bpred,
+                                     c->reg_idx, c->coef, d_in, 1);
+                 }});
 }
 
 int decompress_prepare(fz_ctx* c, const Parsed& r) {
@@ -564,86 +662,189 @@ int decompress_prepare(fz_ctx* c, const Parsed& r) {
     return rc;
 }
 
-// Every kernel of one decompression on `st` (no host synchronisation).
-void decompress_enqueue(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_out, hipStream_t st, bool marks) {
-    auto mark = [&](const char* name) {
-        if (marks) t_mark(c, st, name);
-    };
-    auto start = [&](const char* name) {
-        if (marks) t_start(c, st, name);
-    };
-    const Geom& g = r.g;
+// Every stage of one decompression (no host synchronisation).
+void decompress_tasks(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_out, TaskList& T) {
+    const MiscIds M(c->misc);
+    const Geom g = r.g;
     if (r.verbatim) {
-        start("copy");
-        launch_copy(st, in + kHdr, d_out, g.N);
-        mark("copy");
+        T.push_back({"copy", {{in, ACC_R}, {d_out, ACC_W}},
+                     [=](hipStream_t st) { launch_copy(st, in + kHdr, d_out, g.N); }});
         return;
     }
     const uint32_t pred = r.p.pred;
     const bool has_map = pred_has_map(pred);
     const uint32_t stiles = scan_tiles(g.nblocks);
+    const uint64_t nout = r.nout, npat = r.npat, words = r.words, nreg = r.nreg, bits = r.bits;
+    const double e2 = 2.0 * r.eb_abs;
     if (r.shuffle) {
         // bit-shuffle container: kept-word offsets from the mask popcounts,
         // the outlier index, then one wave per block rebuilds the values
-        const Layout L = make_speed_layout(r.nblocks, r.words, r.nout, r.npat);
-        start("lut");
-        launch_reset(st, c->misc, c->hist, c->desc_chunks, stiles, nullptr, 0,
-                     r.nout ? reinterpret_cast<uint64_t*>(c->oidx) : nullptr, r.nout ? (uint32_t)g.nblocks : 0u, 0, 0,
-                     0);
-        mark("lut");
-        start("scan");
-        launch_scan(st, SCAN_MASKS, in + L.chunks, g.nblocks, c->off, c->desc_chunks, &c->misc->stile_ctr, c->misc,
-                    r.words);
-        mark("scan");
-        start("oindex");
-        launch_outlier_index(st, g, (const uint32_t*)(in + L.opos), r.nout, c->oidx, c->misc);
-        mark("oindex");
-        start("decode");
-        launch_unshuffle(st, g, (const uint32_t*)(in + L.chunks), (const uint32_t*)(in + L.stream), r.words, c->off,
-                         (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->oidx, r.nout,
-                         2.0 * r.eb_abs, d_out, c->misc);
-        mark("decode");
-        start("patch");
-        launch_patch(st, g, (const uint32_t*)(in + L.ppos), (const uint32_t*)(in + L.pbits), r.npat, d_out, c->misc);
-        mark("patch");
+        const Layout L = make_speed_layout(r.nblocks, words, nout, npat);
+        {
+            std::vector<Acc> a = {{c->hist, ACC_W}, {c->desc_chunks, ACC_W}, {c->oidx, ACC_W}};
+            M.reset_all(a);
+            T.push_back({"lut", a, [=](hipStream_t st) {
+                             launch_reset(st, c->misc, c->hist, c->desc_chunks, stiles, nullptr, 0,
+                                          nout ? reinterpret_cast<uint64_t*>(c->oidx) : nullptr,
+                                          nout ? (uint32_t)g.nblocks : 0u, 0, 0, 0);
+                         }});
+        }
+        T.push_back({"scan",
+                     {{in, ACC_R}, {c->off, ACC_W}, {c->desc_chunks, ACC_RW}, {M.stile, ACC_RW}, {M.flags, ACC_RED}},
+                     [=](hipStream_t st) {
+                         launch_scan(st, SCAN_MASKS, in + L.chunks, g.nblocks, c->off, c->desc_chunks,
+                                     &c->misc->stile_ctr, c->misc, words);
+                     }});
+        T.push_back({"oindex", {{in, ACC_R}, {c->oidx, ACC_RW}, {M.ohl, ACC_RED}, {M.flags, ACC_RED}},
+                     [=](hipStream_t st) {
+                         launch_outlier_index(st, g, (const uint32_t*)(in + L.opos), nout, c->oidx, c->misc);
+                     }});
+        T.push_back({"decode",
+                     {{in, ACC_R}, {c->off, ACC_R}, {c->oidx, ACC_R}, {d_out, ACC_W}, {M.flags, ACC_RED}},
+                     [=](hipStream_t st) {
+                         launch_unshuffle(st, g, (const uint32_t*)(in + L.chunks), (const uint32_t*)(in + L.stream),
+                                          words, c->off, (const uint32_t*)(in + L.opos),
+                                          (const int32_t*)(in + L.oval), c->oidx, nout, e2, d_out, c->misc);
+                     }});
+        T.push_back({"patch", {{in, ACC_R}, {d_out, ACC_RW}, {M.flags, ACC_RED}}, [=](hipStream_t st) {
+                         launch_patch(st, g, (const uint32_t*)(in + L.ppos), (const uint32_t*)(in + L.pbits), npat,
+                                      d_out, c->misc);
+                     }});
         return;
     }
-    const Layout L = make_layout(r.nblocks, has_map, r.nreg, r.words, r.nout, r.npat);
+    const Layout L = make_layout(r.nblocks, has_map, nreg, words, nout, npat);
     const int vec = (((uintptr_t)d_out & 15) == 0) && (g.ndim == 1 || (g.n[0] & 3) == 0);
     // one launch: the reset (which also clears the per-block outlier index)
     // and the decode table
-    start("lut");
-    launch_reset_lut(st, c->misc, c->hist, c->desc_chunks, stiles, has_map ? c->desc_pmap : nullptr,
-                     has_map ? stiles : 0, r.nout ? reinterpret_cast<uint64_t*>(c->oidx) : nullptr,
-                     r.nout ? (uint32_t)g.nblocks : 0u, L.chunks, L.stream, r.nreg, in + L.lens, c->lut);
-    mark("lut");
-    start("scan");
-    launch_scan(st, SCAN_CHUNKS, in + L.chunks, g.nblocks, c->off, c->desc_chunks, &c->misc->stile_ctr, c->misc,
-                r.bits);
-    mark("scan");
-    start("oindex");
-    launch_outlier_index(st, g, (const uint32_t*)(in + L.opos), r.nout, c->oidx, c->misc);
-    mark("oindex");
-    start("decode");
-    if (pred == FZ_PRED_LORENZO1) {
-        launch_decode(st, g, (const uint32_t*)(in + L.stream), r.words, c->off, (const uint16_t*)(in + L.chunks),
-                      c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->oidx,
-                      r.nout, 2.0 * r.eb_abs, d_out, vec, c->misc);
-    } else {
-        if (has_map) {
-            launch_map_unpack(st, in + L.map, g.nblocks, c->bpred, c->misc);
-            launch_scan(st, SCAN_PMAP, c->bpred, g.nblocks, c->reg_idx, c->desc_pmap, &c->misc->mtile_ctr, c->misc,
-                        0);
-        }
-        launch_decode_pred(st, g, (const uint32_t*)(in + L.stream), r.words, c->off, (const uint16_t*)(in + L.chunks),
-                           c->lut, (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval), c->oidx,
-                           r.nout, c->res, has_map ? -1 : (int)pred, c->bpred, c->reg_idx, (const int32_t*)(in + L.coef),
-                           r.nreg, 2.0 * r.eb_abs, d_out, vec, c->misc);
+    {
+        std::vector<Acc> a = {{c->hist, ACC_W}, {c->desc_chunks, ACC_W}, {c->desc_pmap, ACC_W}, {c->oidx, ACC_W},
+                              {c->lut, ACC_W}, {in, ACC_R}};
+        M.reset_all(a);
+        T.push_back({"lut", a, [=](hipStream_t st) {
+                         launch_reset_lut(st, c->misc, c->hist, c->desc_chunks, stiles,
+                                          has_map ? c->desc_pmap : nullptr, has_map ? stiles : 0,
+                                          nout ? reinterpret_cast<uint64_t*>(c->oidx) : nullptr,
+                                          nout ? (uint32_t)g.nblocks : 0u, L.chunks, L.stream, nreg, in + L.lens,
+                                          c->lut);
+                     }});
     }
-    mark("decode");
-    start("patch");
-    launch_patch(st, g, (const uint32_t*)(in + L.ppos), (const uint32_t*)(in + L.pbits), r.npat, d_out, c->misc);
-    mark("patch");
+    T.push_back({"scan", {{in, ACC_R}, {c->off, ACC_W}, {c->desc_chunks, ACC_RW}, {M.stile, ACC_RW}, {M.flags, ACC_RED}},
+                 [=](hipStream_t st) {
+                     launch_scan(st, SCAN_CHUNKS, in + L.chunks, g.nblocks, c->off, c->desc_chunks,
+                                 &c->misc->stile_ctr, c->misc, bits);
+                 }});
+    T.push_back({"oindex", {{in, ACC_R}, {c->oidx, ACC_RW}, {M.ohl, ACC_RED}, {M.flags, ACC_RED}},
+                 [=](hipStream_t st) {
+                     launch_outlier_index(st, g, (const uint32_t*)(in + L.opos), nout, c->oidx, c->misc);
+                 }});
+    if (pred == FZ_PRED_LORENZO1) {
+        T.push_back({"decode",
+                     {{in, ACC_R}, {c->off, ACC_R}, {c->lut, ACC_R}, {c->oidx, ACC_R}, {d_out, ACC_W}, {M.dec, ACC_RED},
+                      {M.flags, ACC_RED}},
+                     [=](hipStream_t st) {
+                         launch_decode(st, g, (const uint32_t*)(in + L.stream), words, c->off,
+                                       (const uint16_t*)(in + L.chunks), c->lut, (const uint32_t*)(in + L.opos),
+                                       (const int32_t*)(in + L.oval), c->oidx, nout, e2, d_out, vec, c->misc);
+                     }});
+    } else {
+        T.push_back({"decode",
+                     {{in, ACC_R}, {c->off, ACC_R}, {c->lut, ACC_R}, {c->oidx, ACC_R}, {c->bpred, ACC_W},
+                      {c->reg_idx, ACC_W}, {c->desc_pmap, ACC_RW}, {M.mtile, ACC_RW}, {c->res, ACC_W},
+                      {d_out, ACC_W}, {M.dec, ACC_RED}, {M.flags, ACC_RED}},
+                     [=](hipStream_t st) {
+                         if (has_map) {
+                             launch_map_unpack(st, in + L.map, g.nblocks, c->bpred, c->misc);
+                             launch_scan(st, SCAN_PMAP, c->bpred, g.nblocks, c->reg_idx, c->desc_pmap,
+                                         &c->misc->mtile_ctr, c->misc, 0);
+                         }
+                         launch_decode_pred(st, g, (const uint32_t*)(in + L.stream), words, c->off,
+                                            (const uint16_t*)(in + L.chunks), c->lut, (const uint32_t*)(in + L.opos),
+                                            (const int32_t*)(in + L.oval), c->oidx, nout, c->res,
+                                            has_map ? -1 : (int)pred, c->bpred, c->reg_idx,
+                                            (const int32_t*)(in + L.coef), nreg, e2, d_out, vec, c->misc);
+                     }});
+    }
+    T.push_back({"patch", {{in, ACC_R}, {d_out, ACC_RW}, {M.flags, ACC_RED}}, [=](hipStream_t st) {
+                     launch_patch(st, g, (const uint32_t*)(in + L.ppos), (const uint32_t*)(in + L.pbits), npat, d_out,
+                                  c->misc);
+                 }});
+}
+
+void decompress_enqueue(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_out, hipStream_t st, bool marks) {
+    TaskList T;
+    decompress_tasks(c, r, in, d_out, T);
+    run_eager(c, T, st, marks);
+}
+
+// Graph-mode key of a call: the call's own bytes (parameters or header),
+// then every task's name and every datum it touches (the addresses the
+// captured kernels were given: a reallocated buffer makes a new key).
+std::vector<uint8_t> graph_key(const void* head, size_t n, const TaskList& T) {
+    std::vector<uint8_t> k((const uint8_t*)head, (const uint8_t*)head + n);
+    for (const Task& t : T) {
+        k.insert(k.end(), t.name, t.name + strlen(t.name) + 1);
+        for (const Acc& a : t.acc) {
+            const uintptr_t d = (uintptr_t)a.data;
+            const uint8_t* b = reinterpret_cast<const uint8_t*>(&d);
+            k.insert(k.end(), b, b + sizeof(d));
+            k.push_back((uint8_t)a.mode);
+        }
+    }
+    return k;
+}
+
+// Run a call's tasks as a graph on `st`: captured (dependencies inferred
+// from the tasks' accesses, independent tasks on their own streams, joined
+// by events) when the key differs from the cached graph's, else replayed.
+int run_graph(fz_ctx* c, GraphCall& gc, const TaskList& T, std::vector<uint8_t>&& key, hipStream_t st) {
+    if (key != gc.g.key || !gc.g.exec) {
+        gc.g.drop();
+        if (T.empty() || (int)T.size() > kGraphTasks) return FZ_ERR_INTERNAL;
+        std::vector<std::vector<Acc>> acc;
+        for (const Task& t : T) acc.push_back(t.acc);
+        const Schedule S = schedule_tasks(acc, kGraphStreams);
+        if (!c->cstream && hipStreamCreateWithFlags(&c->cstream, hipStreamNonBlocking) != hipSuccess) return FZ_ERR_HIP;
+        for (int k = 1; k < kGraphStreams; k++)
+            if (!c->gst[k] && hipStreamCreateWithFlags(&c->gst[k], hipStreamNonBlocking) != hipSuccess)
+                return FZ_ERR_HIP;
+        for (int k = 0; k < kGraphTasks + kGraphStreams + 1; k++)
+            if (!c->gev[k] && hipEventCreateWithFlags(&c->gev[k], hipEventDisableTiming) != hipSuccess)
+                return FZ_ERR_HIP;
+        hipStream_t sts[kGraphStreams] = {c->cstream, c->gst[1], c->gst[2], c->gst[3]};
+        hipEvent_t* done = c->gev;                          // one per task
+        hipEvent_t* join = c->gev + kGraphTasks;            // one per side stream
+        hipEvent_t fork = c->gev[kGraphTasks + kGraphStreams];
+        if (hipStreamBeginCapture(c->cstream, hipStreamCaptureModeThreadLocal) != hipSuccess) return FZ_ERR_HIP;
+        bool ok = hipEventRecord(fork, c->cstream) == hipSuccess;
+        for (int k = 1; k < S.nstreams; k++) ok = ok && hipStreamWaitEvent(sts[k], fork, 0) == hipSuccess;
+        for (int j = 0; j < S.n && ok; j++) {
+            hipStream_t sj = sts[S.stream[j]];
+            for (int i : S.deps[j])
+                if (S.stream[i] != S.stream[j]) ok = ok && hipStreamWaitEvent(sj, done[i], 0) == hipSuccess;
+            T[j].run(sj);
+            if (S.signal[j]) ok = ok && hipEventRecord(done[j], sj) == hipSuccess;
+        }
+        for (int k = 1; k < S.nstreams; k++) {
+            ok = ok && hipEventRecord(join[k], sts[k]) == hipSuccess;
+            ok = ok && hipStreamWaitEvent(c->cstream, join[k], 0) == hipSuccess;
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->cstream, &graph);
+        if (!ok || e != hipSuccess || !graph) {
+            if (graph) hipGraphDestroy(graph);
+            hipGetLastError();
+            return FZ_ERR_HIP;
+        }
+        gc.g.graph = graph;
+        if (hipGraphInstantiate(&gc.g.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            gc.g.drop();
+            hipGetLastError();
+            return FZ_ERR_HIP;
+        }
+        gc.g.key = std::move(key);
+        gc.sched = S;
+    }
+    return hipGraphLaunch(gc.g.exec, st) == hipSuccess ? FZ_OK : FZ_ERR_HIP;
 }
 
 // Validation results a decode leaves in Misc, against the header.
@@ -725,6 +926,12 @@ void fz_ctx_destroy(fz_ctx* c) {
     // the graphs go first: they reference the buffers freed below
     destroy_side(c->bc);
     destroy_side(c->bd);
+    c->gcall[0].g.drop();
+    c->gcall[1].g.drop();
+    for (int k = 0; k < kGraphStreams; k++)
+        if (c->gst[k]) hipStreamDestroy(c->gst[k]);
+    for (int k = 0; k < kGraphTasks + kGraphStreams + 1; k++)
+        if (c->gev[k]) hipEventDestroy(c->gev[k]);
     hipFree(c->misc);
     hipFree(c->hist);
     hipFree(c->cw);
@@ -781,7 +988,14 @@ int fz_compress(fz_ctx* c, const fz_params* p, const float* d_in, void* d_out, u
     hipStream_t st = (hipStream_t)stream;
     c->have_hist = false;
     t_begin(c, st);
-    compress_enqueue(c, p, g, d_in, (uint8_t*)d_out, st, c->tune_default, true);
+    if (c->graph_mode) {
+        TaskList T;
+        compress_tasks(c, p, g, d_in, (uint8_t*)d_out, c->tune_default, T);
+        rc = run_graph(c, c->gcall[0], T, graph_key(p, sizeof(*p), T), st);
+        if (rc) return rc;
+    } else {
+        compress_enqueue(c, p, g, d_in, (uint8_t*)d_out, st, c->tune_default, true);
+    }
     t_finish(c, st);
     if (hipMemcpyAsync(c->h_misc, c->misc, sizeof(Misc), hipMemcpyDeviceToHost, st) != hipSuccess) return FZ_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
@@ -809,7 +1023,19 @@ int fz_compress_speed(fz_ctx* c, const fz_params* p, const float* d_in, void* d_
     hipStream_t st = (hipStream_t)stream;
     c->have_hist = false;
     t_begin(c, st);
-    compress_speed_enqueue(c, p, g, d_in, (uint8_t*)d_out, st, c->tune_default, true);
+    {
+        TaskList T;
+        compress_speed_tasks(c, p, g, d_in, (uint8_t*)d_out, c->tune_default, T);
+        if (c->graph_mode) {
+            uint8_t head[sizeof(fz_params) + 1];
+            memcpy(head, p, sizeof(*p));
+            head[sizeof(*p)] = 1;  // the bit-shuffle codec
+            rc = run_graph(c, c->gcall[0], T, graph_key(head, sizeof(head), T), st);
+            if (rc) return rc;
+        } else {
+            run_eager(c, T, st, true);
+        }
+    }
     t_finish(c, st);
     if (hipMemcpyAsync(c->h_misc, c->misc, sizeof(Misc), hipMemcpyDeviceToHost, st) != hipSuccess) return FZ_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
@@ -854,7 +1080,14 @@ int fz_decompress(fz_ctx* c, const void* d_in, uint64_t in_bytes, const void* h_
     rc = decompress_prepare(c, r);
     if (rc) return rc;
     t_begin(c, st);
-    decompress_enqueue(c, r, in, d_out, st, true);
+    if (c->graph_mode) {
+        TaskList T;
+        decompress_tasks(c, r, in, d_out, T);
+        rc = run_graph(c, c->gcall[1], T, graph_key(hh, kHdr, T), st);
+        if (rc) return rc;
+    } else {
+        decompress_enqueue(c, r, in, d_out, st, true);
+    }
     t_finish(c, st);
     if (hipMemcpyAsync(c->h_misc, c->misc, sizeof(Misc), hipMemcpyDeviceToHost, st) != hipSuccess) return FZ_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return FZ_ERR_HIP;
@@ -1651,6 +1884,25 @@ const char* fz_strerror(int s) {
         case FZ_ERR_SCRATCH: return "container needs more scratch than the allocation-free decompression holds";
         default: return "unknown status";
     }
+}
+
+int fz_set_graph_mode(fz_ctx* c, int enable) {
+    if (!c) return FZ_ERR_ARG;
+    c->graph_mode = enable != 0;
+    return FZ_OK;
+}
+
+int fz_graph_info(fz_ctx* c, int which, int* h_tasks, int* h_streams, int* h_width, int* h_edges) {
+    if (!c || which < 0 || which > 1) return FZ_ERR_ARG;
+    const GraphCall& gc = c->gcall[which];
+    if (!gc.g.exec) return FZ_ERR_ARG;
+    int edges = 0;
+    for (const auto& d : gc.sched.deps) edges += (int)d.size();
+    if (h_tasks) *h_tasks = gc.sched.n;
+    if (h_streams) *h_streams = gc.sched.nstreams;
+    if (h_width) *h_width = gc.sched.width;
+    if (h_edges) *h_edges = edges;
+    return FZ_OK;
 }
 
 int fz_set_timing(fz_ctx* c, int enable) {

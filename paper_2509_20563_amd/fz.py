@@ -120,6 +120,11 @@ def lib() -> ctypes.CDLL:
     L.fz_selector_adam_step.argtypes = [vp, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                         ctypes.c_float, vp]
     L.fz_selector_adam_step.restype = i32
+    L.fz_set_graph_mode.argtypes = [vp, i32]
+    L.fz_set_graph_mode.restype = i32
+    L.fz_graph_info.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                ctypes.POINTER(i32)]
+    L.fz_graph_info.restype = i32
     L.fz_compress_speed.argtypes = [vp, P, vp, vp, u64, ctypes.POINTER(u64), vp]
     L.fz_compress_speed.restype = i32
     L.fz_decompress_noalloc.argtypes = [vp, u64, vp, vp, u64, vp]
@@ -276,6 +281,17 @@ class Context:
                                  ctypes.c_void_p(out.data_ptr()), out.numel(), _stream_handle(buf.device))
         _check(rc, "fz_decompress")
         return out
+
+    # ------------------------------------------------------------ graph mode
+    def set_graph_mode(self, on: bool = True):
+        _check(lib().fz_set_graph_mode(self._h, 1 if on else 0), "fz_set_graph_mode")
+
+    def graph_info(self, which: int):
+        """(tasks, streams, width, edges) of the last captured graph of a kind
+        (0 = compression, 1 = decompression)."""
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(lib().fz_graph_info(self._h, int(which), *[ctypes.byref(x) for x in v]), "fz_graph_info")
+        return tuple(x.value for x in v)
 
     # ------------------------------------------------------------ diagnostics
     def set_timing(self, on: bool = True):
