@@ -160,10 +160,12 @@ int fz_decompress(fz_ctx *ctx, const void *d_in, uint64_t in_bytes, const void *
  * beside the Huffman code and encoder, or the outlier index beside the
  * chunk-offset scan), and the call is captured once into a graph that later
  * calls with the same parameters, header and buffers replay.  Outputs are
- * identical to the eager calls.  Per-stage timing is not recorded in graph
- * mode (the whole-call timing filter "call" is).  Returns FZ_OK or
- * FZ_ERR_ARG. */
-int fz_set_graph_mode(fz_ctx *ctx, int enable);
+ * identical to the eager calls.  `streams`: 0 = eager calls (the default);
+ * 1 = graph mode with every stage on one stream (a captured chain);
+ * 2..4 = at most that many streams (larger values mean 4).  Per-stage timing
+ * is not recorded in graph mode (the whole-call timing filter "call" is).
+ * Returns FZ_OK, or FZ_ERR_ARG for a negative count. */
+int fz_set_graph_mode(fz_ctx *ctx, int streams);
 
 /* Shape of the last captured graph of a kind (which: 0 = compression,
  * 1 = decompression): its tasks, the streams they were laid out on, the

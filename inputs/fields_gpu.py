@@ -60,9 +60,11 @@ def _grf_periodic(shape, alpha, seed, device) -> torch.Tensor:
 
 
 def fronts_spikes(shape=(1024, 1024, 1024), seed=3, n_fronts=64, spike_frac=0.01, spike_sigma=2.0,
-                  alpha=11.0 / 3.0, device="cuda") -> torch.Tensor:
+                  alpha=11.0 / 3.0, device="cuda", with_base_range=False):
     """k^-11/3 field in [0, 1] + ``n_fronts`` tanh steps (width ~2 cells) +
-    ``spike_frac`` of the cells replaced by exp(sigma Z)."""
+    ``spike_frac`` of the cells replaced by exp(sigma Z).  With
+    ``with_base_range`` also returns max - min of the field before the
+    spikes are set (float)."""
     f = grf(shape, alpha=alpha, seed=seed * 7919 + 1, device=device)
     g = _gen(seed, device)
     nz, ny, nx = shape
@@ -80,12 +82,13 @@ def fronts_spikes(shape=(1024, 1024, 1024), seed=3, n_fronts=64, spike_frac=0.01
         px, py, pz = (float(t) for t in p)
         d = (xc - px) * vx + (yc - py) * vy + (zc - pz) * vz
         f += amp * torch.tanh(d * 0.5)
+    base_range = float(f.max()) - float(f.min()) if with_base_range else None
     m = int(math.floor(spike_frac * f.numel()))
     if m:
         idx = torch.randint(0, f.numel(), (m,), generator=g, device=device)
         vals = torch.exp(spike_sigma * torch.randn(m, generator=g, device=device))
         f.view(-1)[idx] = vals
-    return f.contiguous()
+    return (f.contiguous(), base_range) if with_base_range else f.contiguous()
 
 
 def sorted_positions(n, seed=5, box=256.0, device="cuda") -> torch.Tensor:

@@ -179,6 +179,7 @@ struct fz_ctx {
     // graphs, their schedules, and the side streams and events they were
     // captured with
     bool graph_mode = false;
+    int graph_streams = kGraphStreams;  // streams a captured call may use
     GraphCall gcall[2];
     hipStream_t gst[kGraphStreams] = {};
     hipEvent_t gev[kGraphTasks + kGraphStreams + 1] = {};
@@ -802,7 +803,7 @@ int run_graph(fz_ctx* c, GraphCall& gc, const TaskList& T, std::vector<uint8_t>&
         if (T.empty() || (int)T.size() > kGraphTasks) return FZ_ERR_INTERNAL;
         std::vector<std::vector<Acc>> acc;
         for (const Task& t : T) acc.push_back(t.acc);
-        const Schedule S = schedule_tasks(acc, kGraphStreams);
+        const Schedule S = schedule_tasks(acc, c->graph_streams);
         if (!c->cstream && hipStreamCreateWithFlags(&c->cstream, hipStreamNonBlocking) != hipSuccess) return FZ_ERR_HIP;
         for (int k = 1; k < kGraphStreams; k++)
             if (!c->gst[k] && hipStreamCreateWithFlags(&c->gst[k], hipStreamNonBlocking) != hipSuccess)
@@ -1886,9 +1887,16 @@ const char* fz_strerror(int s) {
     }
 }
 
-int fz_set_graph_mode(fz_ctx* c, int enable) {
-    if (!c) return FZ_ERR_ARG;
-    c->graph_mode = enable != 0;
+int fz_set_graph_mode(fz_ctx* c, int streams) {
+    if (!c || streams < 0) return FZ_ERR_ARG;
+    const int s = streams > kGraphStreams ? kGraphStreams : streams;
+    if (s != (c->graph_mode ? c->graph_streams : 0)) {
+        // another layout: the cached graphs are captured again
+        c->gcall[0].g.drop();
+        c->gcall[1].g.drop();
+    }
+    c->graph_mode = s > 0;
+    if (s > 0) c->graph_streams = s;
     return FZ_OK;
 }
 

@@ -283,8 +283,10 @@ class Context:
         return out
 
     # ------------------------------------------------------------ graph mode
-    def set_graph_mode(self, on: bool = True):
-        _check(lib().fz_set_graph_mode(self._h, 1 if on else 0), "fz_set_graph_mode")
+    def set_graph_mode(self, streams: int | bool = True):
+        """Graph mode with at most `streams` streams (True = 4, False/0 = eager calls)."""
+        n = (4 if streams else 0) if isinstance(streams, bool) else int(streams)
+        _check(lib().fz_set_graph_mode(self._h, n), "fz_set_graph_mode")
 
     def graph_info(self, which: int):
         """(tasks, streams, width, edges) of the last captured graph of a kind
