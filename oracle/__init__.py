@@ -80,6 +80,8 @@ def lib():
         L.orc_speed_compress.argtypes = [vp, ctypes.c_int, u64p, ctypes.c_int, ctypes.c_double, vp,
                                          ctypes.c_uint64, u64p]
         L.orc_speed_stage.argtypes = [vp, ctypes.c_int, u64p, ctypes.c_int, ctypes.c_double, vp, vp]
+        L.orc_interp_classes.argtypes = [ctypes.c_int, u64p, vp, vp]
+        L.orc_interp_classes.restype = None
         _lib = L
     return _lib
 
@@ -158,7 +160,7 @@ def compress_bound(shape):
     return int(lib().orc_compress_bound(nd, d))
 
 
-P0, P1, P2, P_SELECTED, P_TRIAL = 0, 1, 2, 3, 4
+P0, P1, P2, P_SELECTED, P_TRIAL, P_INTERP = 0, 1, 2, 3, 4, 5
 
 
 def nblocks_of(shape):
@@ -389,3 +391,13 @@ def speed_stage(x, eb, mode=1):
     if rc:
         raise OracleError(rc)
     return sym, words
+
+
+def interp_classes(shape):
+    """(axis, stride) per point of the interpolation predictor: axis in
+    numpy order of dims (0 = x) or -1 for an anchor; stride 8 for anchors."""
+    nd, d = dims_of(shape)
+    ax = np.zeros(shape, np.int8)
+    st = np.zeros(shape, np.uint8)
+    lib().orc_interp_classes(nd, d, _ptr(ax), _ptr(st))
+    return ax, st

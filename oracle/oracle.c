@@ -491,9 +491,119 @@ static int32_t regression_pred(const int32_t coef[4], const int ext[3], int lx, 
 }
 
 /* residual of the value at (x, y, z) under predictor p (coef: P2 only) */
+/* ------------------------------------------ interpolation predictor (G-Interp)
+ * The prediction of the quality-oriented pipeline (Sec. 3.2, Sec. 3.3
+ * FZMod-Quality: the G-Interp spline interpolator of cuSZ-i in place of the
+ * Lorenzo predictor).  The paper gives no formula; this is the reading the
+ * project fixes, on the prequantised integers (dual quantisation, as the
+ * Lorenzo path), over the whole field (not block-local):
+ *   - anchors: points whose every coordinate is a multiple of 8, predicted
+ *     by first-order Lorenzo on the grid of anchors (neighbours 8 apart,
+ *     zero outside the field);
+ *   - levels of stride s = 4, 2, 1: a point whose coordinates are all
+ *     multiples of s, not all of 2s, is interpolated along its axis a: x if
+ *     x is an odd multiple of s, else y if y is, else z (for a level the
+ *     z-odd points come first, then the y-odd, then the x-odd, so every
+ *     neighbour used is known before);
+ *   - along a, with neighbours at a -/+ s and a -/+ 3s: cubic when both
+ *     3s neighbours lie in the field, floor((-q[-3s] + 9 q[-s] + 9 q[+s]
+ *     - q[+3s] + 8) / 16); else linear when a + s lies in the field,
+ *     floor((q[-s] + q[+s] + 1) / 2); else q[-s];
+ *   - residual = q - prediction (modulo 2^32).
+ * Codes, outliers, patches and Huffman chunks (8^3 blocks, block-major
+ * positions) are those of the Lorenzo path; decoding rebuilds the anchors by
+ * prefix sums over the anchor grid, then the levels in the order above.   */
+#define ORC_P_INTERP 5
+
+static int64_t floordiv(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+/* axis interpolated at (c[0], c[1], c[2]) and its stride, or -1 for an anchor */
+static int interp_axis(const geom_t *g, const uint64_t c[3], int *stride) {
+    for (int s = 4; s >= 1; s >>= 1) {
+        int all = 1;
+        for (int a = 0; a < g->ndim; a++) if (c[a] % (uint64_t)s) all = 0;
+        if (!all) continue;
+        int coarse = 1;
+        for (int a = 0; a < g->ndim; a++) if (c[a] % (uint64_t)(2 * s)) coarse = 0;
+        if (coarse) {
+            if (s == 4) { *stride = 8; return -1; }
+            continue;
+        }
+        *stride = s;
+        for (int a = 0; a < g->ndim; a++) if (c[a] % (uint64_t)(2 * s)) return a;
+    }
+    *stride = 8;
+    return -1;
+}
+
+static int32_t qat(const geom_t *g, const int32_t *q, const uint64_t c[3]) { return q[rm(g, c[0], c[1], c[2])]; }
+
+static int32_t interp_pred(const geom_t *g, const int32_t *q, uint64_t x, uint64_t y, uint64_t z) {
+    uint64_t c[3] = {x, y, z};
+    int s;
+    int a = interp_axis(g, c, &s);
+    if (a < 0) {
+        /* anchor: first-order Lorenzo on the anchor grid */
+        int64_t pred = 0;
+        for (int m = 1; m < (1 << g->ndim); m++) {
+            uint64_t d[3] = {c[0], c[1], c[2]};
+            int ok = 1, bits = 0;
+            for (int k = 0; k < g->ndim; k++)
+                if (m >> k & 1) {
+                    if (d[k] < 8) ok = 0; else d[k] -= 8;
+                    bits++;
+                }
+            if (ok) pred += (bits & 1) ? qat(g, q, d) : -(int64_t)qat(g, q, d);
+        }
+        return (int32_t)pred;
+    }
+    uint64_t m1[3] = {c[0], c[1], c[2]}, p1[3] = {c[0], c[1], c[2]}, m3[3] = {c[0], c[1], c[2]},
+             p3[3] = {c[0], c[1], c[2]};
+    m1[a] -= (uint64_t)s;
+    p1[a] += (uint64_t)s;
+    int has_m3 = c[a] >= (uint64_t)(3 * s), has_p1 = c[a] + s < g->n[a], has_p3 = c[a] + 3 * s < g->n[a];
+    if (has_m3 && has_p3) {
+        m3[a] -= (uint64_t)(3 * s);
+        p3[a] += (uint64_t)(3 * s);
+        int64_t num = -(int64_t)qat(g, q, m3) + 9 * (int64_t)qat(g, q, m1) + 9 * (int64_t)qat(g, q, p1) -
+                      (int64_t)qat(g, q, p3);
+        return (int32_t)floordiv(num + 8, 16);
+    }
+    if (has_p1) return (int32_t)floordiv((int64_t)qat(g, q, m1) + (int64_t)qat(g, q, p1) + 1, 2);
+    return qat(g, q, m1);
+}
+
+/* Inverse over the whole field, in place: residuals in, grid values out. */
+static void interp_inverse(const geom_t *g, int32_t *a) {
+    /* anchors: inclusive prefix sums along each axis of the anchor grid */
+    for (int ax = 0; ax < g->ndim; ax++)
+        for (uint64_t z = 0; z < g->n[2]; z += (g->ndim >= 3 ? 8 : 1))
+            for (uint64_t y = 0; y < g->n[1]; y += (g->ndim >= 2 ? 8 : 1))
+                for (uint64_t x = 0; x < g->n[0]; x += 8) {
+                    uint64_t c[3] = {x, y, z};
+                    if (c[ax] < 8) continue;
+                    uint64_t d[3] = {x, y, z};
+                    d[ax] -= 8;
+                    a[rm(g, x, y, z)] += a[rm(g, d[0], d[1], d[2])];
+                }
+    /* levels: stride 4, 2, 1; the z-odd, then y-odd, then x-odd points */
+    for (int s = 4; s >= 1; s >>= 1)
+        for (int ax = g->ndim - 1; ax >= 0; ax--)
+            for (uint64_t z = 0; z < g->n[2]; z++)
+                for (uint64_t y = 0; y < g->n[1]; y++)
+                    for (uint64_t x = 0; x < g->n[0]; x++) {
+                        uint64_t c[3] = {x, y, z};
+                        int st;
+                        if (interp_axis(g, c, &st) != ax || st != s) continue;
+                        uint64_t i = rm(g, x, y, z);
+                        a[i] = (int32_t)((uint32_t)a[i] + (uint32_t)interp_pred(g, a, x, y, z));
+                    }
+}
+
 static int32_t residual_at(const geom_t *g, const int32_t *q, uint64_t x, uint64_t y, uint64_t z, int p,
                            const int32_t coef[4]) {
     if (p == ORC_P1) return lorenzo2_at(g, q, x, y, z);
+    if (p == ORC_P_INTERP) return (int32_t)((uint32_t)q[rm(g, x, y, z)] - (uint32_t)interp_pred(g, q, x, y, z));
     if (p == ORC_P2) {
         int ext[3];
         uint64_t bc[3];
@@ -564,7 +674,26 @@ void orc_residual_inverse(const int32_t *delta, int ndim, const uint64_t dims[3]
     geom_t g;
     if (make_geom(ndim, dims, &g) != ORC_OK) return;
     memcpy(q, delta, sizeof(int32_t) * g.N);
+    if (p == ORC_P_INTERP) {
+        interp_inverse(&g, q);
+        return;
+    }
     for (uint64_t b = 0; b < g.nblocks; b++) block_inverse(&g, q, b, p, coef ? coef + 4 * b : NULL);
+}
+
+/* For tests: the interpolation axis of every point (-1 = anchor) and its
+ * stride (8 for anchors). */
+void orc_interp_classes(int ndim, const uint64_t dims[3], int8_t *axis, uint8_t *stride) {
+    geom_t g;
+    if (make_geom(ndim, dims, &g) != ORC_OK) return;
+    for (uint64_t z = 0; z < g.n[2]; z++)
+        for (uint64_t y = 0; y < g.n[1]; y++)
+            for (uint64_t x = 0; x < g.n[0]; x++) {
+                uint64_t c[3] = {x, y, z};
+                int s;
+                axis[rm(&g, x, y, z)] = (int8_t)interp_axis(&g, c, &s);
+                stride[rm(&g, x, y, z)] = (uint8_t)s;
+            }
 }
 
 /* ---------------------------------------------------------- container layout
@@ -696,7 +825,7 @@ int orc_compress_ex(const float *x, int ndim, const uint64_t dims[3], int mode, 
     geom_t g;
     int rc = make_geom(ndim, dims, &g);
     if (rc) return rc;
-    if (pred < 0 || pred > 4 || (pred == 3 && !choice_in)) return ORC_ERR_ARG;
+    if (pred < 0 || pred > 5 || (pred == 3 && !choice_in)) return ORC_ERR_ARG;
     if (cap < ORC_HDR + 4 * g.N) return ORC_ERR_CAPACITY;
     double eb_abs;
     rc = orc_eb_abs(x, g.N, mode, eb, &eb_abs);
@@ -716,12 +845,12 @@ int orc_compress_ex(const float *x, int ndim, const uint64_t dims[3], int mode, 
     }
     orc_prequant(x, g.N, eb_abs, q, patch);
     block_major_order(&g, refs, bcount);
-    if (pred <= 2) memset(bp, pred, g.nblocks);
+    if (pred <= 2 || pred == ORC_P_INTERP) memset(bp, pred, g.nblocks);
     else if (pred == 3) memcpy(bp, choice_in, g.nblocks);
     else trial_choose(&g, q, refs, bcount, bp, NULL);
     uint64_t nreg = 0;
     for (uint64_t b = 0; b < g.nblocks; b++) {
-        if (bp[b] > ORC_P2) bp[b] = ORC_P0;
+        if (bp[b] > ORC_P2 && bp[b] != ORC_P_INTERP) bp[b] = ORC_P0;
         if (bp[b] == ORC_P2) {
             regression_coeffs(&g, q, b, cf + 4 * b);
             nreg++;
@@ -744,7 +873,7 @@ int orc_compress_ex(const float *x, int ndim, const uint64_t dims[3], int mode, 
     uint64_t bits = 0;
     for (int s = 0; s < ORC_NBINS; s++) bits += (uint64_t)hist[s] * len[s];
     uint64_t words = (bits + 31) / 32;
-    int has_map = pred >= 3;
+    int has_map = pred == 3 || pred == 4;
     layout_t L = make_layout(g.nblocks, has_map, nreg, words, nout, npat);
 
     if (L.total >= ORC_HDR + 4 * g.N) {
@@ -850,7 +979,7 @@ int orc_decompress(const uint8_t *in, uint64_t n, float *out, uint64_t out_elems
     geom_t g;
     if (make_geom(ndim, dims, &g) != ORC_OK) return ORC_ERR_CORRUPT;
     int pred = (int)ld32(in + 12);
-    if (pred > 4 || ld32(in + 44) != ORC_RADIUS) return ORC_ERR_UNSUPPORTED;
+    if (pred > 5 || ld32(in + 44) != ORC_RADIUS) return ORC_ERR_UNSUPPORTED;
     if (out_elems < g.N) return ORC_ERR_CAPACITY;
     uint64_t total = ld64(in + 64);
     if (total > n) return ORC_ERR_CORRUPT;
@@ -865,7 +994,7 @@ int orc_decompress(const uint8_t *in, uint64_t n, float *out, uint64_t out_elems
     uint64_t nblocks = ld32(in + 72), nout = ld32(in + 76), npat = ld32(in + 80);
     uint64_t words = ld32(in + 84), bits = ld64(in + 88), nreg = ld32(in + 96);
     if (nblocks != g.nblocks || words != (bits + 31) / 32) return ORC_ERR_CORRUPT;
-    int has_map = pred >= 3;
+    int has_map = pred == 3 || pred == 4;
     if (nreg > g.nblocks) return ORC_ERR_CORRUPT;
     layout_t L = make_layout(nblocks, has_map, nreg, words, nout, npat);
     if (L.total != total) return ORC_ERR_CORRUPT;
@@ -876,7 +1005,7 @@ int orc_decompress(const uint8_t *in, uint64_t n, float *out, uint64_t out_elems
     uint64_t ir = 0;
     for (uint64_t b = 0; b < g.nblocks; b++) {
         bp[b] = has_map ? (uint8_t)((in[L.map + b / 4] >> (2 * (b % 4))) & 3) : (uint8_t)pred;
-        if (bp[b] > ORC_P2) { free(bp); free(cf); return ORC_ERR_CORRUPT; }
+        if (bp[b] > ORC_P2 && bp[b] != ORC_P_INTERP) { free(bp); free(cf); return ORC_ERR_CORRUPT; }
         if (bp[b] == ORC_P2) {
             if (ir >= nreg) { free(bp); free(cf); return ORC_ERR_CORRUPT; }
             for (int k = 0; k < 4; k++) cf[4 * b + k] = (int32_t)ld32(in + L.coef + 16 * ir + 4 * k);
@@ -951,7 +1080,9 @@ int orc_decompress(const uint8_t *in, uint64_t n, float *out, uint64_t out_elems
     }
     if (rc == ORC_OK && (io != nout || bitpos != bits)) rc = ORC_ERR_CORRUPT;
     if (rc == ORC_OK) {
-        for (uint64_t b = 0; b < g.nblocks; b++) block_inverse(&g, a, b, bp[b], cf + 4 * b);
+        if (pred == ORC_P_INTERP) interp_inverse(&g, a);
+        else
+            for (uint64_t b = 0; b < g.nblocks; b++) block_inverse(&g, a, b, bp[b], cf + 4 * b);
         double e2 = 2.0 * eb_abs;
         for (uint64_t i = 0; i < g.N; i++) out[i] = dequant(a[i], e2);
         /* lossless patches: positions ascending, each names a real element */
