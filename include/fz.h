@@ -66,6 +66,17 @@ enum { FZ_EB_ABS = 0, FZ_EB_REL = 1 };
  *                     bits under the Huffman code of the first-order
  *                     histogram (+64 bits per outlier, +128 for the
  *                     coefficients); ties go to the lower number.
+ *  FZ_PRED_INTERP     the interpolation predictor of the quality-oriented
+ *                     pipeline (Sec. 3.3, FZMod-Quality: G-Interp in place
+ *                     of Lorenzo), over the whole field, not block-local:
+ *                     anchors every 8 values per axis by first-order
+ *                     Lorenzo on the anchor grid, then levels of stride 4,
+ *                     2, 1 interpolated along one axis from the neighbours
+ *                     at -/+s and -/+3s (cubic (-1, 9, 9, -1)/16, linear at
+ *                     the upper edge, the lower neighbour past it).  The
+ *                     paper gives no formula: this is the library's reading.
+ *                     Huffman codec only; one residual field of 4 bytes per
+ *                     value of extra device memory in both directions.
  * The AUTO modes store a 2-bit map of the choice in the container, so
  * decompression never repeats the choice. */
 enum {
@@ -73,7 +84,8 @@ enum {
     FZ_PRED_LORENZO2 = 1,
     FZ_PRED_REGRESSION = 2,
     FZ_PRED_AUTO_MLP = 3,
-    FZ_PRED_AUTO_TRIAL = 4
+    FZ_PRED_AUTO_TRIAL = 4,
+    FZ_PRED_INTERP = 5
 };
 
 enum {

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfz.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["fz_quant.hip", "fz_select.hip", "fz_scan.hip", "fz_huffman.hip", "fz_decode.hip", "fz_train.hip", "fz_batch.hip", "fz_speed.hip", "fz_api.hip", "fz_noalloc.hip"]
+SOURCES = ["fz_quant.hip", "fz_select.hip", "fz_scan.hip", "fz_huffman.hip", "fz_decode.hip", "fz_train.hip", "fz_batch.hip", "fz_speed.hip", "fz_interp.hip", "fz_api.hip", "fz_noalloc.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -48,7 +48,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,-z,defs", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -237,7 +237,7 @@ int check_params(const fz_params* p, Geom* g) {
     if (rc) return rc;
     if (p->eb_mode != FZ_EB_ABS && p->eb_mode != FZ_EB_REL) return FZ_ERR_ARG;
     if (!(p->eb > 0.0) || !__builtin_isfinite(p->eb)) return FZ_ERR_EB;
-    if (p->pred > FZ_PRED_AUTO_TRIAL) return FZ_ERR_ARG;
+    if (p->pred > FZ_PRED_INTERP) return FZ_ERR_ARG;
     if (p->radius != 0 && p->radius != (uint32_t)kRadius) return FZ_ERR_UNSUPPORTED;
     return FZ_OK;
 }
@@ -399,7 +399,7 @@ int parse_header(const uint8_t* h, uint64_t n, Parsed* r) {
     r->bits = ld64(h, 88);
     r->nreg = ld32(h, 96);
     if (make_geom(r->p.ndim, r->p.dims, &r->g) != FZ_OK) return FZ_ERR_CORRUPT;
-    if (r->p.pred > FZ_PRED_AUTO_TRIAL || r->p.radius != (uint32_t)kRadius) return FZ_ERR_CORRUPT;
+    if (r->p.pred > FZ_PRED_INTERP || r->p.radius != (uint32_t)kRadius) return FZ_ERR_CORRUPT;
     if (r->p.eb_mode > 1) return FZ_ERR_CORRUPT;
     if (r->verbatim) {
         if (r->total != (uint64_t)kHdr + 4 * r->g.N) return FZ_ERR_CORRUPT;
@@ -417,11 +417,12 @@ int parse_header(const uint8_t* h, uint64_t n, Parsed* r) {
     // every value costs at least one bit, so the stream is never empty
     if (r->nblocks != r->g.nblocks || r->words != (r->bits + 31) / 32 || r->bits < r->g.N) return FZ_ERR_CORRUPT;
     if (r->nout > r->g.N || r->npat > r->g.N) return FZ_ERR_CORRUPT;
-    // regression coefficients: every block (P2), none (P0, P1), or the
-    // blocks the map selects (counted again on the device)
+    // regression coefficients: every block (P2), none (P0, P1, the
+    // interpolation predictor), or the blocks the map selects (counted
+    // again on the device)
     const uint32_t pred = r->p.pred;
-    if ((pred == FZ_PRED_REGRESSION && r->nreg != r->nblocks) || (pred < FZ_PRED_REGRESSION && r->nreg) ||
-        r->nreg > r->nblocks)
+    if ((pred == FZ_PRED_REGRESSION && r->nreg != r->nblocks) ||
+        (pred != FZ_PRED_REGRESSION && !pred_has_map(pred) && r->nreg) || r->nreg > r->nblocks)
         return FZ_ERR_CORRUPT;
     const Layout L = make_layout(r->nblocks, pred_has_map(pred), r->nreg, r->words, r->nout, r->npat);
     if (L.total != r->total) return FZ_ERR_CORRUPT;
@@ -447,7 +448,9 @@ int compress_check(fz_ctx* c, const fz_params* p, const float* d_in, const void*
 
 int compress_prepare(fz_ctx* c, const fz_params* p, const Geom& g) {
     int rc = ensure(c, g);
-    if (rc == FZ_OK && p->pred != FZ_PRED_LORENZO1) rc = ensure_pred(c, g, false);
+    // the interpolation predictor keeps the field's grid values in the
+    // residual buffer
+    if (rc == FZ_OK && p->pred != FZ_PRED_LORENZO1) rc = ensure_pred(c, g, p->pred == FZ_PRED_INTERP);
     if (rc == FZ_OK && p->pred == FZ_PRED_AUTO_MLP &&
         grow(c->featb, c->featb_cap, (uint64_t)g.nblocks * kNFeat) != hipSuccess)
         rc = FZ_ERR_NOMEM;
@@ -544,17 +547,27 @@ void compress_tasks(fz_ctx* c, const fz_params* p, const Geom& g, const float* d
                          launch_features(st, (int)gmax, d_in, g, P.eb_mode, P.eb, vec, c->misc, c->featb);
                          launch_mlp(st, (int)gmax, c->featb, g.nblocks, c->sel, nullptr, c->bpred);
                      }});
+    const bool interp = pred == FZ_PRED_INTERP;
+    if (interp)
+        // the interpolation predictor reads neighbours anywhere in the
+        // field: its grid values first, row-major, in the residual buffer
+        T.push_back({"grid", {{d_in, ACC_R}, {M.range, ACC_R}, {c->res, ACC_W}}, [=](hipStream_t st) {
+                         launch_grid_values(st, d_in, g.N, P.eb_mode, P.eb, c->misc, c->res);
+                     }});
     {
         const int fixed = has_map ? -1 : (int)pred;
         std::vector<Acc> a = {{d_in, ACC_R},         {M.range, ACC_R},     {c->codes, ACC_W}, {c->tile_cnt, ACC_W},
                               {c->ostage, ACC_W},    {c->pstage, ACC_W},   {c->hist, ACC_RED}, {M.flags, ACC_RED}};
-        if (pred != FZ_PRED_LORENZO1) {
+        if (interp) {
+            a.push_back({c->res, ACC_R});
+        } else if (pred != FZ_PRED_LORENZO1) {
             a.push_back({c->bpred, ACC_R});
             a.push_back({c->coef, ACC_W});
         }
         T.push_back({"quant", a, [=](hipStream_t st) {
                          launch_quant(st, grid, d_in, g, P.eb_mode, P.eb, vec, c->misc, c->hist, c->codes, ntiles,
-                                      c->tile_cnt, c->ostage, c->pstage, fixed, c->bpred, c->coef);
+                                      c->tile_cnt, c->ostage, c->pstage, fixed, c->bpred, c->coef,
+                                      interp ? c->res : nullptr);
                      }});
     }
     if (has_map)
@@ -747,6 +760,20 @@ void decompress_tasks(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_ou
                                        (const uint16_t*)(in + L.chunks), c->lut, (const uint32_t*)(in + L.opos),
                                        (const int32_t*)(in + L.oval), c->oidx, nout, e2, d_out, vec, c->misc);
                      }});
+    } else if (pred == FZ_PRED_INTERP) {
+        // residuals of every block, then the anchors and levels of the
+        // interpolation in place, then dequantised row stores
+        T.push_back({"decode",
+                     {{in, ACC_R}, {c->off, ACC_R}, {c->lut, ACC_R}, {c->oidx, ACC_R}, {c->res, ACC_W},
+                      {M.dec, ACC_RED}, {M.flags, ACC_RED}},
+                     [=](hipStream_t st) {
+                         launch_decode_residuals(st, g, (const uint32_t*)(in + L.stream), words, c->off,
+                                                 (const uint16_t*)(in + L.chunks), c->lut,
+                                                 (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval),
+                                                 c->oidx, nout, c->res, c->misc);
+                     }});
+        T.push_back({"interp", {{c->res, ACC_RW}, {d_out, ACC_W}},
+                     [=](hipStream_t st) { launch_interp_inverse(st, g, c->res, e2, d_out); }});
     } else {
         T.push_back({"decode",
                      {{in, ACC_R}, {c->off, ACC_R}, {c->lut, ACC_R}, {c->oidx, ACC_R}, {c->bpred, ACC_W},

@@ -218,7 +218,74 @@ __host__ __device__ inline Layout make_speed_layout(uint64_t nblocks, uint64_t w
 // Predictor modes (header field): 0, 1, 2 = that predictor in every block;
 // 3 = chosen per block by the learned selector, 4 = by exhaustive trial.
 constexpr uint32_t kPredSelected = 3, kPredTrial = 4;
-__host__ __device__ inline bool pred_has_map(uint32_t pred) { return pred >= kPredSelected; }
+__host__ __device__ inline bool pred_has_map(uint32_t pred) { return pred == kPredSelected || pred == kPredTrial; }
+
+// Interpolation predictor (header predictor 5): over the whole field, not
+// block-local.  Anchors (every coordinate a multiple of 8) are predicted by
+// first-order Lorenzo on the anchor grid; a point whose coordinates are all
+// multiples of s in {4, 2, 1} (not all of 2s) is interpolated along the
+// first axis, in x, y, z order, on which it is an odd multiple of s, from
+// the neighbours at -/+ s and -/+ 3s: cubic floor((-q[-3s] + 9 q[-s] +
+// 9 q[+s] - q[+3s] + 8) / 16) when both 3s neighbours are inside, else
+// floor((q[-s] + q[+s] + 1) / 2) when +s is, else q[-s].  Decoding rebuilds
+// the anchors, then for s = 4, 2, 1 the points interpolated along z, then
+// y, then x, each from points rebuilt before.
+constexpr uint32_t kPredInterp = 5;
+
+// Axis a point is interpolated along (-1 for an anchor) and its stride.
+__host__ __device__ inline int interp_class(const uint32_t c[3], int nd, uint32_t& s) {
+    uint32_t orc = 0;
+    for (int a = 0; a < nd; a++) orc |= c[a];
+    if ((orc & 7u) == 0) {
+        s = 8;
+        return -1;
+    }
+    s = (orc & 3u) == 0 ? 4u : ((orc & 1u) == 0 ? 2u : 1u);
+    for (int a = 0; a < nd; a++)
+        if (c[a] & s) return a;
+    return -1;
+}
+
+// Prediction at c from the grid values q_at(x, y, z) (n: field extents).
+template <class QAt>
+__host__ __device__ inline int32_t interp_predict(const uint32_t c[3], const uint32_t n[3], int nd, QAt q_at) {
+    uint32_t s;
+    const int a = interp_class(c, nd, s);
+    if (a < 0) {
+        // Lorenzo on the anchor grid: +/- the neighbours 8 below in every
+        // non-empty subset of the axes (odd subsets added), zero outside
+        int64_t p = 0;
+        for (int m = 1; m < (1 << nd); m++) {
+            uint32_t d[3] = {c[0], c[1], c[2]};
+            bool in = true;
+            for (int k = 0; k < nd; k++)
+                if (m >> k & 1) {
+                    if (d[k] < 8) in = false;
+                    else d[k] -= 8;
+                }
+            if (!in) continue;
+            const int64_t v = q_at(d[0], d[1], d[2]);
+            p += (__builtin_popcount((unsigned)m) & 1) ? v : -v;
+        }
+        return (int32_t)p;
+    }
+    uint32_t lo1[3] = {c[0], c[1], c[2]}, hi1[3] = {c[0], c[1], c[2]};
+    lo1[a] -= s;
+    hi1[a] += s;
+    const uint32_t ca = c[a];
+    const bool m3 = ca >= 3 * s, p1 = ca + s < n[a], p3 = ca + 3 * s < n[a];
+    if (m3 && p3) {
+        uint32_t lo3[3] = {c[0], c[1], c[2]}, hi3[3] = {c[0], c[1], c[2]};
+        lo3[a] -= 3 * s;
+        hi3[a] += 3 * s;
+        const int64_t num = -(int64_t)q_at(lo3[0], lo3[1], lo3[2]) + 9 * (int64_t)q_at(lo1[0], lo1[1], lo1[2]) +
+                            9 * (int64_t)q_at(hi1[0], hi1[1], hi1[2]) - (int64_t)q_at(hi3[0], hi3[1], hi3[2]);
+        return (int32_t)((num + 8) >> 4);
+    }
+    if (p1)
+        return (int32_t)(((int64_t)q_at(lo1[0], lo1[1], lo1[2]) + (int64_t)q_at(hi1[0], hi1[1], hi1[2]) + 1) >> 1);
+    return q_at(lo1[0], lo1[1], lo1[2]);
+}
 
 // ------------------------------------------------------- device helpers
 // Order-preserving map float -> u32 (unsigned compare = float compare).

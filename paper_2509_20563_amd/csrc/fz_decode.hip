@@ -1169,6 +1169,33 @@ void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, u
 #undef FZ_DRES
 }
 
+void launch_decode_residuals(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,
+                             const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
+                             const int32_t* oval, const uint2* oidx, uint64_t n_out, int32_t* res, Misc* misc) {
+    const Interior I = interior_of(g);
+    if (I.n) {
+        const uint32_t fg = (I.n + 255) / 256;
+#define FZ_ARGS                                                                                                     \
+    dim3(fg), dim3(256), 0, st, g, I.ib[0], I.ib[1], I.n, stream, stream_words, off, chunks, lut, oval, oidx, n_out, \
+        0.0, (float*)nullptr, res, misc, 0, (const uint8_t*)nullptr, (const uint64_t*)nullptr,                     \
+        (const int32_t*)nullptr, (uint64_t)0
+        if (g.ndim == 3) hipLaunchKernelGGL((k_decode_fast<3, true, false>), FZ_ARGS);
+        else if (g.ndim == 2) hipLaunchKernelGGL((k_decode_fast<2, true, false>), FZ_ARGS);
+        else hipLaunchKernelGGL((k_decode_fast<1, true, false>), FZ_ARGS);
+#undef FZ_ARGS
+    }
+    if (I.n == g.nblocks) return;
+    const uint32_t grid = (g.nblocks + 255) / 256;
+    const int skip = I.n ? 1 : 0;
+#define FZ_DRES(NDV)                                                                                              \
+    hipLaunchKernelGGL(k_decode_res<NDV>, dim3(grid), dim3(256), 0, st, g, stream, stream_words, off, chunks, lut, \
+                       opos, oval, oidx, n_out, res, misc, skip, I.ib[0], I.ib[1], I.ib[2])
+    if (g.ndim == 3) FZ_DRES(3);
+    else if (g.ndim == 2) FZ_DRES(2);
+    else FZ_DRES(1);
+#undef FZ_DRES
+}
+
 void launch_patch(hipStream_t st, const Geom& g, const uint32_t* ppos, const uint32_t* pbits, uint64_t n_pat,
                   float* out, Misc* misc) {
     if (n_pat == 0) return;

@@ -13,7 +13,11 @@ void launch_minmax(hipStream_t st, const float* x, uint64_t N, int vec, Misc* mi
 void launch_quant(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
                   Misc* misc, uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt, uint2* ostage,
                   uint2* pstage, int fixed_pred, const uint8_t* bpred,
-                  int32_t* coef);
+                  int32_t* coef, const int32_t* qf = nullptr);
+// grid values q of every value (row-major int32), for the interpolation
+// predictor
+void launch_grid_values(hipStream_t st, const float* x, uint64_t N, uint32_t mode, double eb, const Misc* misc,
+                        int32_t* q);
 void launch_trial(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
                   Misc* misc, uint32_t ntiles, const uint32_t* cw_ref, uint8_t* choice, uint32_t* costs);
 
@@ -87,6 +91,13 @@ void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, u
                         const int32_t* oval, const uint2* oidx, uint64_t n_out, int32_t* res,
                         int fixed_pred, const uint8_t* bpred, const uint64_t* reg_idx, const int32_t* coefs,
                         uint64_t nreg, double e2, float* out, int vec, Misc* misc);
+// residuals only (block-major int32), for the interpolation predictor
+void launch_decode_residuals(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,
+                             const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
+                             const int32_t* oval, const uint2* oidx, uint64_t n_out, int32_t* res, Misc* misc);
+// fz_interp.hip: residuals (block-major, in place) to grid values, then
+// dequantised row-major floats
+void launch_interp_inverse(hipStream_t st, const Geom& g, int32_t* q, double e2, float* out);
 void launch_patch(hipStream_t st, const Geom& g, const uint32_t* ppos, const uint32_t* pbits, uint64_t n_pat,
                   float* out, Misc* misc);
 

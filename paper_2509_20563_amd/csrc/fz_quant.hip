@@ -118,7 +118,11 @@ __device__ __forceinline__ void read_row(const int32_t* Q, uint32_t off, int32_t
 // per block: fixed_pred >= 0 for every block, else bpred[b]), kQuantTrial
 // (no codes: per-block cost of each predictor under a reference code,
 // cheapest predictor -> choice[b], the three costs -> costs[3 b + p]).
-constexpr int kQuantP0 = 0, kQuantPred = 1, kQuantTrial = 2;
+// kQuantInterp: the interpolation predictor over the whole field, its
+// neighbours read from the field's grid values qf (row-major), and a top-3
+// histogram (the codes of residuals -1, 0, 1 counted by ballots: the
+// interpolation residuals pile up there).
+constexpr int kQuantP0 = 0, kQuantPred = 1, kQuantTrial = 2, kQuantInterp = 3;
 
 template <int ND, int MODE>
 __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom g, uint32_t mode, double eb,
@@ -128,7 +132,7 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
                                                uint2* __restrict__ pstage, int fixed_pred,
                                                const uint8_t* __restrict__ bpred, int32_t* __restrict__ coef,
                                                const uint32_t* __restrict__ cw_ref, uint8_t* __restrict__ choice,
-                                               uint32_t* __restrict__ costs) {
+                                               uint32_t* __restrict__ costs, const int32_t* __restrict__ qf) {
     constexpr bool PRED = MODE != kQuantP0;
     // q per block, regions padded by 8 words so the load-mapped writes of
     // four blocks do not fall into the same banks; one extra zero row
@@ -255,7 +259,23 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
             seg_coords<ND>(s, lx0, ly, lz);
             nv = (blk && ly < info.ey && lz < info.ez && lx0 < info.ex) ? min(8u, info.ex - lx0) : 0u;
             auto residual = [&](const uint32_t pr) {
-            if (pr == 0) {
+            if (MODE == kQuantInterp) {
+                // the field's own grid values from LDS, the prediction from
+                // neighbours anywhere in the field (qf)
+                int32_t r0[8];
+                read_row<ND>(Q, Qb + s * 8, r0);
+                const uint32_t n3[3] = {g.n[0], g.n[1], g.n[2]};
+                auto q_at = [&](uint32_t xx, uint32_t yy, uint32_t zz) -> int32_t {
+                    return qf[(uint64_t)xx + (uint64_t)g.n[0] * ((uint64_t)yy + (uint64_t)g.n[1] * zz)];
+                };
+#pragma unroll
+                for (int i = 0; i < 8; i++) {
+                    const uint32_t c[3] = {info.bx * g.bs[0] + lx0 + i, info.by * g.bs[1] + ly,
+                                           info.bz * g.bs[2] + lz};
+                    const int32_t pq = i < (int)nv ? interp_predict(c, n3, ND, q_at) : 0;
+                    d[i] = (int32_t)((uint32_t)r0[i] - (uint32_t)pq);
+                }
+            } else if (pr == 0) {
                 // first-order Lorenzo: A = residual along y/z of the rows,
                 // then the backward difference along x
                 int32_t r0[8], A[8];
@@ -434,7 +454,7 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
         // grid value itself, left most lanes of flat blocks adding to one
         // bin in the same instruction: 64-way serialised LDS atomics, 2.8 ms
         // instead of 1.9 on the 1024^3 fronts/spikes field.)
-        if (blk) {
+        if (blk && MODE != kQuantInterp) {
             const uint32_t ca = (uint32_t)kRadius;
             uint32_t na = 0;
 #pragma unroll
@@ -445,6 +465,18 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
                 if (valid && !ma) atomicAdd(&H[code[i]], 1u);
             }
             if (lane == 0 && na) atomicAdd(&H[ca], na);
+        } else if (blk) {
+            // top-3: residuals -1, 0, 1 by ballots, one add each per wave
+            uint32_t nk[3] = {0, 0, 0};
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                const bool valid = i < (int)nv;
+                const uint32_t k = code[i] - (uint32_t)(kRadius - 1);  // 0, 1, 2 for codes 511..513
+#pragma unroll
+                for (uint32_t j = 0; j < 3; j++) nk[j] += (uint32_t)__popcll(__ballot(valid && k == j));
+                if (valid && k > 2u) atomicAdd(&H[code[i]], 1u);
+            }
+            if (lane < 3 && nk[lane]) atomicAdd(&H[kRadius - 1 + lane], nk[lane]);
         }
 
         // ---------------- outliers and patches (block order inside the tile)
@@ -499,7 +531,29 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
         if (H[i]) atomicAdd(&hist_g[(blockIdx.x % kHistCopies) * kBins + i], H[i]);
 }
 
+// Grid values of the whole field, row-major (the interpolation predictor
+// reads neighbours anywhere in the field): q = rint(x / 2eb), 0 where |t|
+// reaches 2^24 (those values are lossless patches).
+__global__ __launch_bounds__(256) void k_grid_values(const float* __restrict__ x, uint64_t N, uint32_t mode, double eb,
+                                                      const Misc* misc, int32_t* __restrict__ q) {
+    double eb_abs;
+    if (!resolve_eb(mode, eb, misc->mm_lo, misc->mm_hi, &eb_abs)) return;
+    const double e2 = 2.0 * eb_abs, inv = 1.0 / e2;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+        bool p;
+        q[i] = prequant1(x[i], e2, inv, eb_abs, p);
+    }
+}
+
 // ------------------------------------------------------------ launchers
+void launch_grid_values(hipStream_t st, const float* x, uint64_t N, uint32_t mode, double eb, const Misc* misc,
+                        int32_t* q) {
+    uint64_t grid = (N + 255) / 256;
+    if (grid > 8192) grid = 8192;
+    hipLaunchKernelGGL(k_grid_values, dim3((uint32_t)grid), dim3(256), 0, st, x, N, mode, eb, misc, q);
+}
+
 void launch_reset(hipStream_t st, Misc* misc, uint32_t* hist, uint64_t* d1, uint32_t n1, uint64_t* d2,
                   uint32_t n2, uint64_t* d3, uint32_t n3, uint64_t off_chunks, uint64_t off_stream, uint64_t nreg) {
     uint32_t n = n1 > n2 ? n1 : n2;
@@ -517,14 +571,20 @@ void launch_minmax(hipStream_t st, const float* x, uint64_t N, int vec, Misc* mi
 
 #define FZ_QUANT(NDV, MV)                                                                                        \
     hipLaunchKernelGGL((k_quant<NDV, MV>), dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, hist, codes, \
-                       ntiles, tile_cnt, ostage, pstage, fixed_pred, bpred, coef, cw_ref, choice, costs)
+                       ntiles, tile_cnt, ostage, pstage, fixed_pred, bpred, coef, cw_ref, choice, costs, qf)
 
 void launch_quant(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
                   Misc* misc, uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt, uint2* ostage,
-                  uint2* pstage, int fixed_pred, const uint8_t* bpred, int32_t* coef) {
+                  uint2* pstage, int fixed_pred, const uint8_t* bpred, int32_t* coef, const int32_t* qf) {
     const uint32_t* cw_ref = nullptr;
     uint8_t* choice = nullptr;
     uint32_t* costs = nullptr;
+    if (fixed_pred == (int)kPredInterp) {
+        if (g.ndim == 3) FZ_QUANT(3, kQuantInterp);
+        else if (g.ndim == 2) FZ_QUANT(2, kQuantInterp);
+        else FZ_QUANT(1, kQuantInterp);
+        return;
+    }
     const bool pred = fixed_pred != 0;
     if (g.ndim == 3) {
         if (pred) FZ_QUANT(3, kQuantPred); else FZ_QUANT(3, kQuantP0);
@@ -543,6 +603,7 @@ void launch_trial(hipStream_t st, int grid, const float* x, const Geom& g, uint3
     uint2 *ostage = nullptr, *pstage = nullptr;
     int32_t* coef = nullptr;
     const uint8_t* bpred = nullptr;
+    const int32_t* qf = nullptr;
     const int fixed_pred = -1;
     if (g.ndim == 3) FZ_QUANT(3, kQuantTrial);
     else if (g.ndim == 2) FZ_QUANT(2, kQuantTrial);
