@@ -151,7 +151,8 @@ struct fz_ctx {
     uint8_t* lens_ref = nullptr;  // kBins / 2 bytes
     uint64_t* desc_pmap = nullptr;
     int32_t* res = nullptr;
-    uint64_t bpred_cap = 0, reg_idx_cap = 0, coef_cap = 0, costs_cap = 0, desc_pmap_cap = 0, res_cap = 0;
+    int32_t* ival = nullptr;  // interpolation decode: grid values of the coarse levels
+    uint64_t bpred_cap = 0, reg_idx_cap = 0, coef_cap = 0, costs_cap = 0, desc_pmap_cap = 0, res_cap = 0, ival_cap = 0;
     // block features of the learned selector ([nblocks][16] float)
     float* featb = nullptr;
     uint64_t featb_cap = 0;
@@ -448,9 +449,7 @@ int compress_check(fz_ctx* c, const fz_params* p, const float* d_in, const void*
 
 int compress_prepare(fz_ctx* c, const fz_params* p, const Geom& g) {
     int rc = ensure(c, g);
-    // the interpolation predictor keeps the field's grid values in the
-    // residual buffer
-    if (rc == FZ_OK && p->pred != FZ_PRED_LORENZO1) rc = ensure_pred(c, g, p->pred == FZ_PRED_INTERP);
+    if (rc == FZ_OK && p->pred != FZ_PRED_LORENZO1) rc = ensure_pred(c, g, false);
     if (rc == FZ_OK && p->pred == FZ_PRED_AUTO_MLP &&
         grow(c->featb, c->featb_cap, (uint64_t)g.nblocks * kNFeat) != hipSuccess)
         rc = FZ_ERR_NOMEM;
@@ -548,26 +547,17 @@ void compress_tasks(fz_ctx* c, const fz_params* p, const Geom& g, const float* d
                          launch_mlp(st, (int)gmax, c->featb, g.nblocks, c->sel, nullptr, c->bpred);
                      }});
     const bool interp = pred == FZ_PRED_INTERP;
-    if (interp)
-        // the interpolation predictor reads neighbours anywhere in the
-        // field: its grid values first, row-major, in the residual buffer
-        T.push_back({"grid", {{d_in, ACC_R}, {M.range, ACC_R}, {c->res, ACC_W}}, [=](hipStream_t st) {
-                         launch_grid_values(st, d_in, g.N, P.eb_mode, P.eb, c->misc, c->res);
-                     }});
     {
         const int fixed = has_map ? -1 : (int)pred;
         std::vector<Acc> a = {{d_in, ACC_R},         {M.range, ACC_R},     {c->codes, ACC_W}, {c->tile_cnt, ACC_W},
                               {c->ostage, ACC_W},    {c->pstage, ACC_W},   {c->hist, ACC_RED}, {M.flags, ACC_RED}};
-        if (interp) {
-            a.push_back({c->res, ACC_R});
-        } else if (pred != FZ_PRED_LORENZO1) {
+        if (pred != FZ_PRED_LORENZO1 && !interp) {
             a.push_back({c->bpred, ACC_R});
             a.push_back({c->coef, ACC_W});
         }
         T.push_back({"quant", a, [=](hipStream_t st) {
                          launch_quant(st, grid, d_in, g, P.eb_mode, P.eb, vec, c->misc, c->hist, c->codes, ntiles,
-                                      c->tile_cnt, c->ostage, c->pstage, fixed, c->bpred, c->coef,
-                                      interp ? c->res : nullptr);
+                                      c->tile_cnt, c->ostage, c->pstage, fixed, c->bpred, c->coef);
                      }});
     }
     if (has_map)
@@ -673,6 +663,9 @@ int decompress_prepare(fz_ctx* c, const Parsed& r) {
     if (r.verbatim) return FZ_OK;
     int rc = ensure(c, r.g);
     if (rc == FZ_OK && r.p.pred != FZ_PRED_LORENZO1) rc = ensure_pred(c, r.g, true);
+    if (rc == FZ_OK && r.p.pred == FZ_PRED_INTERP && r.g.ndim == 3 &&
+        grow(c->ival, c->ival_cap, (uint64_t)r.g.nblocks * kBlockElems) != hipSuccess)
+        rc = FZ_ERR_NOMEM;
     return rc;
 }
 
@@ -772,8 +765,10 @@ void decompress_tasks(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_ou
                                                  (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval),
                                                  c->oidx, nout, c->res, c->misc);
                      }});
-        T.push_back({"interp", {{c->res, ACC_RW}, {d_out, ACC_W}},
-                     [=](hipStream_t st) { launch_interp_inverse(st, g, c->res, e2, d_out); }});
+        const uint32_t max_grid = (uint32_t)c->n_cu * 8;
+        T.push_back({"interp", {{c->res, ACC_RW}, {c->ival, ACC_W}, {d_out, ACC_W}}, [=](hipStream_t st) {
+                         launch_interp_inverse(st, g, c->res, c->ival, e2, d_out, vec, max_grid);
+                     }});
     } else {
         T.push_back({"decode",
                      {{in, ACC_R}, {c->off, ACC_R}, {c->lut, ACC_R}, {c->oidx, ACC_R}, {c->bpred, ACC_W},
@@ -990,6 +985,7 @@ void fz_ctx_destroy(fz_ctx* c) {
     if (c->cstream) hipStreamDestroy(c->cstream);
     hipFree(c->desc_pmap);
     hipFree(c->res);
+    hipFree(c->ival);
     if (c->h_misc) hipHostFree(c->h_misc);
     if (c->h_hdr) hipHostFree(c->h_hdr);
     for (int i = 0; i <= kMaxStages; i++)

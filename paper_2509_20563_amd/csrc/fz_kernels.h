@@ -95,9 +95,11 @@ void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, u
 void launch_decode_residuals(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,
                              const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
                              const int32_t* oval, const uint2* oidx, uint64_t n_out, int32_t* res, Misc* misc);
-// fz_interp.hip: residuals (block-major, in place) to grid values, then
-// dequantised row-major floats
-void launch_interp_inverse(hipStream_t st, const Geom& g, int32_t* q, double e2, float* out);
+// fz_interp.hip: residuals q (block-major) to grid values, then dequantised
+// row-major floats; 3D uses v (block-major) for the coarse levels and leaves
+// q unchanged, 1D/2D work in place on q
+void launch_interp_inverse(hipStream_t st, const Geom& g, int32_t* q, int32_t* v, double e2, float* out, int vec,
+                           uint32_t max_grid);
 void launch_patch(hipStream_t st, const Geom& g, const uint32_t* ppos, const uint32_t* pbits, uint64_t n_pat,
                   float* out, Misc* misc);
 

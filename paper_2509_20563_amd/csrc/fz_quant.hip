@@ -260,13 +260,32 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
             nv = (blk && ly < info.ey && lz < info.ez && lx0 < info.ex) ? min(8u, info.ex - lx0) : 0u;
             auto residual = [&](const uint32_t pr) {
             if (MODE == kQuantInterp) {
-                // the field's own grid values from LDS, the prediction from
-                // neighbours anywhere in the field (qf)
+                // the prediction reads neighbours anywhere in the field:
+                // from LDS where they fall in this tile's blocks, else the
+                // value itself, prequantised here (the same arithmetic as
+                // phase A, so the same grid value)
                 int32_t r0[8];
                 read_row<ND>(Q, Qb + s * 8, r0);
                 const uint32_t n3[3] = {g.n[0], g.n[1], g.n[2]};
+                const uint32_t b0 = tile * kTileBlocks;
                 auto q_at = [&](uint32_t xx, uint32_t yy, uint32_t zz) -> int32_t {
-                    return qf[(uint64_t)xx + (uint64_t)g.n[0] * ((uint64_t)yy + (uint64_t)g.n[1] * zz)];
+                    uint32_t bb, loc;
+                    if (ND == 3) {
+                        bb = (xx >> 3) + g.nb[0] * ((yy >> 3) + g.nb[1] * (zz >> 3));
+                        loc = (xx & 7u) + 8u * ((yy & 7u) + 8u * (zz & 7u));
+                    } else if (ND == 2) {
+                        bb = (xx >> 5) + g.nb[0] * (yy >> 4);
+                        loc = (xx & 31u) + 32u * (yy & 15u);
+                    } else {
+                        bb = xx >> 9;
+                        loc = xx & 511u;
+                    }
+                    const uint32_t rel = bb - b0;
+                    if (rel < (uint32_t)kTileBlocks) return Q[rel * kQStride + loc];
+                    if (qf) return qf[(uint64_t)xx + (uint64_t)g.n[0] * ((uint64_t)yy + (uint64_t)g.n[1] * zz)];
+                    bool pq;
+                    return prequant1(x[(uint64_t)xx + (uint64_t)g.n[0] * ((uint64_t)yy + (uint64_t)g.n[1] * zz)], e2,
+                                     inv, eb_abs, pq);
                 };
 #pragma unroll
                 for (int i = 0; i < 8; i++) {

@@ -497,8 +497,9 @@ void launch_decode_residuals(hipStream_t st, const Geom& g, const uint32_t* stre
       {lut, 2ull * kLut}, {opos, 4 * n_out}, {oval, 4 * n_out}, {oidx, 8ull * g.nblocks},
       {res, 4ull * g.nblocks * kBlockElems}, {misc, sizeof(Misc)});
 }
-void launch_interp_inverse(hipStream_t st, const Geom& g, int32_t* q, double, float* out) {
-    K("interp_inverse", {q, 4ull * g.nblocks * kBlockElems}, {out, 4 * g.N});
+void launch_interp_inverse(hipStream_t st, const Geom& g, int32_t* q, int32_t* v, double, float* out, int, uint32_t) {
+    K("interp_inverse", {q, 4ull * g.nblocks * kBlockElems}, {v, g.ndim == 3 ? 4ull * g.nblocks * kBlockElems : 0ull},
+      {out, 4 * g.N});
 }
 void launch_shuffle(hipStream_t st, const Geom& g, const uint16_t* codes, uint8_t* out, uint64_t limit,
                     uint64_t* desc, Misc* misc) {

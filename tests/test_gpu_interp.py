@@ -101,10 +101,9 @@ def test_interp_in_graph_mode(fz, ctx):
         assert ctx.compress(d, 1e-4, 1, pred=PI).cpu().numpy().tobytes() == ref
         y = g.decompress(c).cpu().numpy()
         assert np.array_equal(y.view(np.uint32), yo.view(np.uint32)), f"graph reconstruction (replay {rep})"
-    # the grid-value stage feeds the quantiser; the residual decode feeds the
-    # interpolation passes
+    # the residual decode feeds the interpolation passes
     tasks, _, _, _ = g.graph_info(0)
-    assert tasks == 8
+    assert tasks == 7
     tasks, _, _, _ = g.graph_info(1)
     assert tasks == 6
 
