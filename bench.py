@@ -58,7 +58,7 @@ STAGE_KERNEL = {
     "compress:encode": ("fz::k_encode<3>", "fz_huffman.hip"),
     "compress:finalize": ("fz::k_finalize", "fz_huffman.hip"),
     "decompress:oindex": ("fz::k_outlier_index", "fz_decode.hip"),
-    "decompress:decode": ("fz::k_decode_fast<3, false, true, true>", "fz_decode.hip"),
+    "decompress:decode": ("fz::k_decode_fast<3, false, true, true, false>", "fz_decode.hip"),
 }
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_1024cubed_fronts_spikes.md")
 
@@ -310,6 +310,10 @@ def bench_c3(args):
         "call_roofline": {"compress": _roof(call_bytes("compress", "shuffle", n, ssize), tc),
                           "decompress": _roof(call_bytes("decompress", "shuffle", n, ssize), td)}}
 
+    # the interpolation predictor (FZMod-Quality front end) on the same field
+    print("[bench] interpolation predictor", file=sys.stderr, flush=True)
+    interp_mode = quality_mode(ctx, fz, metrics, x, C3_EB, sbuf, rec)
+
     # dominant first-order Lorenzo kernel and its roofline (HIP events
     # around it inside the timed region)
     by_stage = per_stage(stages)
@@ -371,6 +375,7 @@ def bench_c3(args):
                    "n_values": n, "eb_rel": C3_EB, "modes": [m for m, _ in MODES]},
         "modes": modes,
         "shuffle_codec": shuffle_mode,
+        "interp_predictor": interp_mode,
         "selector": selector_vs,
         "training": training,
         "stages": stage_summary,
@@ -410,6 +415,35 @@ def selector_summary(ctx, fz, x, modes):
     return selector_vs
 
 
+def quality_mode(ctx, fz, metrics, x, eb, buf, rec):
+    """One field through the interpolation predictor (Huffman codec):
+    ratio, error, PSNR, whole-call rates and rooflines.  The algorithmic
+    bytes are first-order Lorenzo's (the method reads the field once for the
+    prediction; the halo reads of neighbouring tiles are implementation
+    traffic)."""
+    n = x.numel()
+    c = ctx.compress(x, eb, fz.EB_REL, out=buf, pred=fz.PRED_INTERP)
+    size = c.numel()
+    hdr = c[:128].cpu().numpy().tobytes()
+    ctx.decompress(c, header=hdr, out=rec)
+    tc = _call_ms(ctx, lambda: ctx.compress(x, eb, fz.EB_REL, out=buf, pred=fz.PRED_INTERP))
+    td = _call_ms(ctx, lambda: ctx.decompress(buf[:size], header=hdr, out=rec))
+    h = fz.header_fields(hdr)
+    diff = rec.double() - x.double()
+    err = diff.abs().max().item()
+    mse = (diff * diff).mean().item()
+    del diff
+    rng = float(x.max()) - float(x.min())
+    return {"bytes": size, "cr": round(metrics.compression_ratio(n, size), 4),
+            "max_err_over_eb": err / h["eb_abs"],
+            "psnr_db": round(20 * math.log10(rng / math.sqrt(mse)), 3) if mse > 0 else None,
+            "n_outliers": h["n_outliers"],
+            "compress_gbps": round(4.0 * n / (tc * 1e-3) / 1e9, 2),
+            "decompress_gbps": round(4.0 * n / (td * 1e-3) / 1e9, 2),
+            "call_roofline": {"compress": _roof(call_bytes("compress", "lorenzo1", n, size), tc),
+                              "decompress": _roof(call_bytes("decompress", "lorenzo1", n, size), td)}}
+
+
 def c2_extra(ctx, fz, metrics, dev):
     """The 512^3 k^-3 field at rel 1e-2/1e-3/1e-4, first-order Lorenzo:
     whole-call rates and rooflines per bound."""
@@ -445,6 +479,7 @@ def c2_extra(ctx, fz, metrics, dev):
                    "decompress_gbps": round(4.0 * n / (std * 1e-3) / 1e9, 2),
                    "call_roofline": {"compress": _roof(call_bytes("compress", "shuffle", n, ssize), stc),
                                      "decompress": _roof(call_bytes("decompress", "shuffle", n, ssize), std)}}
+        interp = quality_mode(ctx, fz, metrics, x, eb, out2, rec)
         ctx.decompress(out[:size], header=hdr, out=rec)
         rows.append({"eb_rel": eb, "bytes": size, "cr": round(metrics.compression_ratio(n, size), 4),
                      "max_err_over_eb": (rec.double() - x.double()).abs().max().item() / h["eb_abs"],
@@ -453,7 +488,7 @@ def c2_extra(ctx, fz, metrics, dev):
                      "decompress_gbps": round(4.0 * n / (td * 1e-3) / 1e9, 2),
                      "call_roofline": {"compress": _roof(call_bytes("compress", "lorenzo1", n, size), tc),
                                        "decompress": _roof(call_bytes("decompress", "lorenzo1", n, size), td)},
-                     "shuffle_codec": shuffle})
+                     "shuffle_codec": shuffle, "interp_predictor": interp})
     del x, out, out2, rec
     torch.cuda.empty_cache()
     return {"workload": "512x512x512 k^-3 Gaussian random field, first-order Lorenzo", "per_eb": rows}

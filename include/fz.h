@@ -149,13 +149,16 @@ int fz_compress(fz_ctx *ctx, const fz_params *p, const float *d_in, void *d_out,
 int fz_compress_speed(fz_ctx *ctx, const fz_params *p, const float *d_in, void *d_out, uint64_t out_cap,
                       uint64_t *h_out_bytes, void *stream);
 
-/* Parse a container header held in host memory (at least 128 bytes).
- * Fills *p, *n_elems (values in the field) and *total_bytes (container size).
- * Returns FZ_OK or FZ_ERR_CORRUPT. */
+/* Parse a container header held in host memory (at least 128 bytes): the
+ * container the compressor writes, whose size defines the compression ratio
+ * (Sec. 4.2).  Fills *p, *n_elems (values in the field) and *total_bytes
+ * (container size).  Returns FZ_OK or FZ_ERR_CORRUPT. */
 int fz_header_read(const void *h_hdr, uint64_t n, fz_params *p, uint64_t *n_elems, uint64_t *total_bytes);
 
 /* Decompress the container d_in (device, in_bytes) into d_out (device,
- * out_elems >= N floats).  h_hdr is an optional host copy of the first 128
+ * out_elems >= N floats): the reverse path (Sec. 1, Sec. 3.3.1: Huffman or
+ * bit-shuffle decoding, outlier scatter, inverse prediction, dequantisation,
+ * then the lossless patches).  h_hdr is an optional host copy of the first 128
  * bytes of the container (NULL: the library copies it from the device).
  * Synchronises `stream` at the end to report validation errors.
  * Returns FZ_OK, FZ_ERR_CORRUPT, FZ_ERR_CAPACITY, ... */

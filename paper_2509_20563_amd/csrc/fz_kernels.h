@@ -13,11 +13,7 @@ void launch_minmax(hipStream_t st, const float* x, uint64_t N, int vec, Misc* mi
 void launch_quant(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
                   Misc* misc, uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt, uint2* ostage,
                   uint2* pstage, int fixed_pred, const uint8_t* bpred,
-                  int32_t* coef, const int32_t* qf = nullptr);
-// grid values q of every value (row-major int32), for the interpolation
-// predictor
-void launch_grid_values(hipStream_t st, const float* x, uint64_t N, uint32_t mode, double eb, const Misc* misc,
-                        int32_t* q);
+                  int32_t* coef);
 void launch_trial(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
                   Misc* misc, uint32_t ntiles, const uint32_t* cw_ref, uint8_t* choice, uint32_t* costs);
 

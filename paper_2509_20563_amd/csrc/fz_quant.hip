@@ -119,7 +119,7 @@ __device__ __forceinline__ void read_row(const int32_t* Q, uint32_t off, int32_t
 // (no codes: per-block cost of each predictor under a reference code,
 // cheapest predictor -> choice[b], the three costs -> costs[3 b + p]).
 // kQuantInterp: the interpolation predictor over the whole field, its
-// neighbours read from the field's grid values qf (row-major), and a top-3
+// neighbours read from LDS or prequantised from the field, and a top-3
 // histogram (the codes of residuals -1, 0, 1 counted by ballots: the
 // interpolation residuals pile up there).
 constexpr int kQuantP0 = 0, kQuantPred = 1, kQuantTrial = 2, kQuantInterp = 3;
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
                                                uint2* __restrict__ pstage, int fixed_pred,
                                                const uint8_t* __restrict__ bpred, int32_t* __restrict__ coef,
                                                const uint32_t* __restrict__ cw_ref, uint8_t* __restrict__ choice,
-                                               uint32_t* __restrict__ costs, const int32_t* __restrict__ qf) {
+                                               uint32_t* __restrict__ costs) {
     constexpr bool PRED = MODE != kQuantP0;
     // q per block, regions padded by 8 words so the load-mapped writes of
     // four blocks do not fall into the same banks; one extra zero row
@@ -282,7 +282,6 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
                     }
                     const uint32_t rel = bb - b0;
                     if (rel < (uint32_t)kTileBlocks) return Q[rel * kQStride + loc];
-                    if (qf) return qf[(uint64_t)xx + (uint64_t)g.n[0] * ((uint64_t)yy + (uint64_t)g.n[1] * zz)];
                     bool pq;
                     return prequant1(x[(uint64_t)xx + (uint64_t)g.n[0] * ((uint64_t)yy + (uint64_t)g.n[1] * zz)], e2,
                                      inv, eb_abs, pq);
@@ -550,29 +549,7 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
         if (H[i]) atomicAdd(&hist_g[(blockIdx.x % kHistCopies) * kBins + i], H[i]);
 }
 
-// Grid values of the whole field, row-major (the interpolation predictor
-// reads neighbours anywhere in the field): q = rint(x / 2eb), 0 where |t|
-// reaches 2^24 (those values are lossless patches).
-__global__ __launch_bounds__(256) void k_grid_values(const float* __restrict__ x, uint64_t N, uint32_t mode, double eb,
-                                                      const Misc* misc, int32_t* __restrict__ q) {
-    double eb_abs;
-    if (!resolve_eb(mode, eb, misc->mm_lo, misc->mm_hi, &eb_abs)) return;
-    const double e2 = 2.0 * eb_abs, inv = 1.0 / e2;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
-        bool p;
-        q[i] = prequant1(x[i], e2, inv, eb_abs, p);
-    }
-}
-
 // ------------------------------------------------------------ launchers
-void launch_grid_values(hipStream_t st, const float* x, uint64_t N, uint32_t mode, double eb, const Misc* misc,
-                        int32_t* q) {
-    uint64_t grid = (N + 255) / 256;
-    if (grid > 8192) grid = 8192;
-    hipLaunchKernelGGL(k_grid_values, dim3((uint32_t)grid), dim3(256), 0, st, x, N, mode, eb, misc, q);
-}
-
 void launch_reset(hipStream_t st, Misc* misc, uint32_t* hist, uint64_t* d1, uint32_t n1, uint64_t* d2,
                   uint32_t n2, uint64_t* d3, uint32_t n3, uint64_t off_chunks, uint64_t off_stream, uint64_t nreg) {
     uint32_t n = n1 > n2 ? n1 : n2;
@@ -590,11 +567,11 @@ void launch_minmax(hipStream_t st, const float* x, uint64_t N, int vec, Misc* mi
 
 #define FZ_QUANT(NDV, MV)                                                                                        \
     hipLaunchKernelGGL((k_quant<NDV, MV>), dim3(grid), dim3(256), 0, st, x, g, mode, eb, vec, misc, hist, codes, \
-                       ntiles, tile_cnt, ostage, pstage, fixed_pred, bpred, coef, cw_ref, choice, costs, qf)
+                       ntiles, tile_cnt, ostage, pstage, fixed_pred, bpred, coef, cw_ref, choice, costs)
 
 void launch_quant(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
                   Misc* misc, uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt, uint2* ostage,
-                  uint2* pstage, int fixed_pred, const uint8_t* bpred, int32_t* coef, const int32_t* qf) {
+                  uint2* pstage, int fixed_pred, const uint8_t* bpred, int32_t* coef) {
     const uint32_t* cw_ref = nullptr;
     uint8_t* choice = nullptr;
     uint32_t* costs = nullptr;
@@ -622,7 +599,6 @@ void launch_trial(hipStream_t st, int grid, const float* x, const Geom& g, uint3
     uint2 *ostage = nullptr, *pstage = nullptr;
     int32_t* coef = nullptr;
     const uint8_t* bpred = nullptr;
-    const int32_t* qf = nullptr;
     const int fixed_pred = -1;
     if (g.ndim == 3) FZ_QUANT(3, kQuantTrial);
     else if (g.ndim == 2) FZ_QUANT(2, kQuantTrial);
