@@ -160,7 +160,7 @@ def compress_bound(shape):
     return int(lib().orc_compress_bound(nd, d))
 
 
-P0, P1, P2, P_SELECTED, P_TRIAL, P_INTERP = 0, 1, 2, 3, 4, 5
+P0, P1, P2, P_SELECTED, P_TRIAL, P_INTERP, P_GLOBAL = 0, 1, 2, 3, 4, 5, 6
 
 
 def nblocks_of(shape):

@@ -600,10 +600,54 @@ static void interp_inverse(const geom_t *g, int32_t *a) {
                     }
 }
 
+/* ------------------------------------------ global (non-blocked) Lorenzo
+ * The first-order Lorenzo predictor of Sec. 3.1 over the whole field: the
+ * same formula as P0 with neighbours taken anywhere in the field (zero only
+ * outside it), so block faces cost nothing.  Residuals modulo 2^32.  The
+ * inverse is the inclusive prefix sum along x of every row of the field,
+ * then along y, then along z (the Lorenzo residual is the backward
+ * difference along each axis, and prefix sums undo them one axis at a
+ * time).  Codes, outliers, patches, chunks and container as for P0; header
+ * predictor 6, no map.                                                    */
+#define ORC_P_GLOBAL 6
+
+static int32_t gnb(const geom_t *g, const int32_t *q, uint64_t x, uint64_t y, uint64_t z, int dx, int dy, int dz) {
+    /* q at (x-dx, y-dy, z-dz) if that point lies in the field, else 0 */
+    if ((uint64_t)dx > x || (uint64_t)dy > y || (uint64_t)dz > z) return 0;
+    return q[rm(g, x - dx, y - dy, z - dz)];
+}
+
+static int32_t global_lorenzo_at(const geom_t *g, const int32_t *q, uint64_t x, uint64_t y, uint64_t z) {
+    /* sum over the corners (dx, dy, dz) of the unit cell below the point,
+     * sign (-1)^(dx + dy + dz), axes beyond ndim fixed at 0 */
+    int64_t d = 0;
+    for (int dz = 0; dz <= (g->ndim >= 3); dz++)
+        for (int dy = 0; dy <= (g->ndim >= 2); dy++)
+            for (int dx = 0; dx <= 1; dx++) {
+                int64_t v = gnb(g, q, x, y, z, dx, dy, dz);
+                d += ((dx + dy + dz) & 1) ? -v : v;
+            }
+    return (int32_t)(uint32_t)(uint64_t)d;
+}
+
+static void global_inverse(const geom_t *g, int32_t *a) {
+    for (int axis = 0; axis < g->ndim; axis++)
+        for (uint64_t z = 0; z < g->n[2]; z++)
+            for (uint64_t y = 0; y < g->n[1]; y++)
+                for (uint64_t x = 0; x < g->n[0]; x++) {
+                    uint64_t c[3] = {x, y, z};
+                    if (c[axis] == 0) continue;
+                    c[axis] -= 1;
+                    uint64_t i = rm(g, x, y, z);
+                    a[i] = (int32_t)((uint32_t)a[i] + (uint32_t)a[rm(g, c[0], c[1], c[2])]);
+                }
+}
+
 static int32_t residual_at(const geom_t *g, const int32_t *q, uint64_t x, uint64_t y, uint64_t z, int p,
                            const int32_t coef[4]) {
     if (p == ORC_P1) return lorenzo2_at(g, q, x, y, z);
     if (p == ORC_P_INTERP) return (int32_t)((uint32_t)q[rm(g, x, y, z)] - (uint32_t)interp_pred(g, q, x, y, z));
+    if (p == ORC_P_GLOBAL) return global_lorenzo_at(g, q, x, y, z);
     if (p == ORC_P2) {
         int ext[3];
         uint64_t bc[3];
@@ -676,6 +720,10 @@ void orc_residual_inverse(const int32_t *delta, int ndim, const uint64_t dims[3]
     memcpy(q, delta, sizeof(int32_t) * g.N);
     if (p == ORC_P_INTERP) {
         interp_inverse(&g, q);
+        return;
+    }
+    if (p == ORC_P_GLOBAL) {
+        global_inverse(&g, q);
         return;
     }
     for (uint64_t b = 0; b < g.nblocks; b++) block_inverse(&g, q, b, p, coef ? coef + 4 * b : NULL);
@@ -825,7 +873,7 @@ int orc_compress_ex(const float *x, int ndim, const uint64_t dims[3], int mode, 
     geom_t g;
     int rc = make_geom(ndim, dims, &g);
     if (rc) return rc;
-    if (pred < 0 || pred > 5 || (pred == 3 && !choice_in)) return ORC_ERR_ARG;
+    if (pred < 0 || pred > 6 || (pred == 3 && !choice_in)) return ORC_ERR_ARG;
     if (cap < ORC_HDR + 4 * g.N) return ORC_ERR_CAPACITY;
     double eb_abs;
     rc = orc_eb_abs(x, g.N, mode, eb, &eb_abs);
@@ -845,12 +893,12 @@ int orc_compress_ex(const float *x, int ndim, const uint64_t dims[3], int mode, 
     }
     orc_prequant(x, g.N, eb_abs, q, patch);
     block_major_order(&g, refs, bcount);
-    if (pred <= 2 || pred == ORC_P_INTERP) memset(bp, pred, g.nblocks);
+    if (pred <= 2 || pred == ORC_P_INTERP || pred == ORC_P_GLOBAL) memset(bp, pred, g.nblocks);
     else if (pred == 3) memcpy(bp, choice_in, g.nblocks);
     else trial_choose(&g, q, refs, bcount, bp, NULL);
     uint64_t nreg = 0;
     for (uint64_t b = 0; b < g.nblocks; b++) {
-        if (bp[b] > ORC_P2 && bp[b] != ORC_P_INTERP) bp[b] = ORC_P0;
+        if (bp[b] > ORC_P2 && bp[b] != ORC_P_INTERP && bp[b] != ORC_P_GLOBAL) bp[b] = ORC_P0;
         if (bp[b] == ORC_P2) {
             regression_coeffs(&g, q, b, cf + 4 * b);
             nreg++;
@@ -979,7 +1027,7 @@ int orc_decompress(const uint8_t *in, uint64_t n, float *out, uint64_t out_elems
     geom_t g;
     if (make_geom(ndim, dims, &g) != ORC_OK) return ORC_ERR_CORRUPT;
     int pred = (int)ld32(in + 12);
-    if (pred > 5 || ld32(in + 44) != ORC_RADIUS) return ORC_ERR_UNSUPPORTED;
+    if (pred > 6 || ld32(in + 44) != ORC_RADIUS) return ORC_ERR_UNSUPPORTED;
     if (out_elems < g.N) return ORC_ERR_CAPACITY;
     uint64_t total = ld64(in + 64);
     if (total > n) return ORC_ERR_CORRUPT;
@@ -1005,7 +1053,7 @@ int orc_decompress(const uint8_t *in, uint64_t n, float *out, uint64_t out_elems
     uint64_t ir = 0;
     for (uint64_t b = 0; b < g.nblocks; b++) {
         bp[b] = has_map ? (uint8_t)((in[L.map + b / 4] >> (2 * (b % 4))) & 3) : (uint8_t)pred;
-        if (bp[b] > ORC_P2 && bp[b] != ORC_P_INTERP) { free(bp); free(cf); return ORC_ERR_CORRUPT; }
+        if (bp[b] > ORC_P2 && bp[b] != ORC_P_INTERP && bp[b] != ORC_P_GLOBAL) { free(bp); free(cf); return ORC_ERR_CORRUPT; }
         if (bp[b] == ORC_P2) {
             if (ir >= nreg) { free(bp); free(cf); return ORC_ERR_CORRUPT; }
             for (int k = 0; k < 4; k++) cf[4 * b + k] = (int32_t)ld32(in + L.coef + 16 * ir + 4 * k);
@@ -1081,6 +1129,7 @@ int orc_decompress(const uint8_t *in, uint64_t n, float *out, uint64_t out_elems
     if (rc == ORC_OK && (io != nout || bitpos != bits)) rc = ORC_ERR_CORRUPT;
     if (rc == ORC_OK) {
         if (pred == ORC_P_INTERP) interp_inverse(&g, a);
+        else if (pred == ORC_P_GLOBAL) global_inverse(&g, a);
         else
             for (uint64_t b = 0; b < g.nblocks; b++) block_inverse(&g, a, b, bp[b], cf + 4 * b);
         double e2 = 2.0 * eb_abs;
