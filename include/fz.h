@@ -77,6 +77,13 @@ enum { FZ_EB_ABS = 0, FZ_EB_REL = 1 };
  *                     paper gives no formula: this is the library's reading.
  *                     Huffman codec only; one residual field of 4 bytes per
  *                     value of extra device memory in both directions.
+ *  FZ_PRED_GLOBAL     first-order Lorenzo over the whole field (Sec. 3.1's
+ *                     predictor with neighbours in other blocks; zero only
+ *                     outside the field): no residuals at block faces, so
+ *                     smooth fields lose the per-block corner outliers.
+ *                     Decoding adds prefix-sum passes over the whole field
+ *                     and 4 bytes per value of residual scratch.  Huffman
+ *                     codec only.
  * The AUTO modes store a 2-bit map of the choice in the container, so
  * decompression never repeats the choice. */
 enum {
@@ -85,7 +92,8 @@ enum {
     FZ_PRED_REGRESSION = 2,
     FZ_PRED_AUTO_MLP = 3,
     FZ_PRED_AUTO_TRIAL = 4,
-    FZ_PRED_INTERP = 5
+    FZ_PRED_INTERP = 5,
+    FZ_PRED_GLOBAL = 6
 };
 
 enum {

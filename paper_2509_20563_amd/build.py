@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfz.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["fz_quant.hip", "fz_select.hip", "fz_scan.hip", "fz_huffman.hip", "fz_decode.hip", "fz_train.hip", "fz_batch.hip", "fz_speed.hip", "fz_interp.hip", "fz_api.hip", "fz_noalloc.hip"]
+SOURCES = ["fz_quant.hip", "fz_select.hip", "fz_scan.hip", "fz_huffman.hip", "fz_decode.hip", "fz_train.hip", "fz_batch.hip", "fz_speed.hip", "fz_interp.hip", "fz_global.hip", "fz_api.hip", "fz_noalloc.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

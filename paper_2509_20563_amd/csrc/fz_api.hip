@@ -152,6 +152,8 @@ struct fz_ctx {
     uint64_t* desc_pmap = nullptr;
     int32_t* res = nullptr;
     int32_t* ival = nullptr;  // interpolation decode: grid values of the coarse levels
+    uint64_t* gdesc = nullptr;  // global Lorenzo decode (1D): look-back descriptors
+    uint64_t gdesc_cap = 0;
     uint64_t bpred_cap = 0, reg_idx_cap = 0, coef_cap = 0, costs_cap = 0, desc_pmap_cap = 0, res_cap = 0, ival_cap = 0;
     // block features of the learned selector ([nblocks][16] float)
     float* featb = nullptr;
@@ -238,7 +240,7 @@ int check_params(const fz_params* p, Geom* g) {
     if (rc) return rc;
     if (p->eb_mode != FZ_EB_ABS && p->eb_mode != FZ_EB_REL) return FZ_ERR_ARG;
     if (!(p->eb > 0.0) || !__builtin_isfinite(p->eb)) return FZ_ERR_EB;
-    if (p->pred > FZ_PRED_INTERP) return FZ_ERR_ARG;
+    if (p->pred > FZ_PRED_GLOBAL) return FZ_ERR_ARG;
     if (p->radius != 0 && p->radius != (uint32_t)kRadius) return FZ_ERR_UNSUPPORTED;
     return FZ_OK;
 }
@@ -400,7 +402,7 @@ int parse_header(const uint8_t* h, uint64_t n, Parsed* r) {
     r->bits = ld64(h, 88);
     r->nreg = ld32(h, 96);
     if (make_geom(r->p.ndim, r->p.dims, &r->g) != FZ_OK) return FZ_ERR_CORRUPT;
-    if (r->p.pred > FZ_PRED_INTERP || r->p.radius != (uint32_t)kRadius) return FZ_ERR_CORRUPT;
+    if (r->p.pred > FZ_PRED_GLOBAL || r->p.radius != (uint32_t)kRadius) return FZ_ERR_CORRUPT;
     if (r->p.eb_mode > 1) return FZ_ERR_CORRUPT;
     if (r->verbatim) {
         if (r->total != (uint64_t)kHdr + 4 * r->g.N) return FZ_ERR_CORRUPT;
@@ -551,7 +553,7 @@ void compress_tasks(fz_ctx* c, const fz_params* p, const Geom& g, const float* d
         const int fixed = has_map ? -1 : (int)pred;
         std::vector<Acc> a = {{d_in, ACC_R},         {M.range, ACC_R},     {c->codes, ACC_W}, {c->tile_cnt, ACC_W},
                               {c->ostage, ACC_W},    {c->pstage, ACC_W},   {c->hist, ACC_RED}, {M.flags, ACC_RED}};
-        if (pred != FZ_PRED_LORENZO1 && !interp) {
+        if (pred != FZ_PRED_LORENZO1 && !interp && pred != FZ_PRED_GLOBAL) {
             a.push_back({c->bpred, ACC_R});
             a.push_back({c->coef, ACC_W});
         }
@@ -666,6 +668,9 @@ int decompress_prepare(fz_ctx* c, const Parsed& r) {
     if (rc == FZ_OK && r.p.pred == FZ_PRED_INTERP && r.g.ndim == 3 &&
         grow(c->ival, c->ival_cap, (uint64_t)r.g.nblocks * kBlockElems) != hipSuccess)
         rc = FZ_ERR_NOMEM;
+    if (rc == FZ_OK && r.p.pred == FZ_PRED_GLOBAL && r.g.ndim == 1 &&
+        grow(c->gdesc, c->gdesc_cap, global_scan_tiles(r.g.N)) != hipSuccess)
+        rc = FZ_ERR_NOMEM;
     return rc;
 }
 
@@ -753,7 +758,7 @@ void decompress_tasks(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_ou
                                        (const uint16_t*)(in + L.chunks), c->lut, (const uint32_t*)(in + L.opos),
                                        (const int32_t*)(in + L.oval), c->oidx, nout, e2, d_out, vec, c->misc);
                      }});
-    } else if (pred == FZ_PRED_INTERP) {
+    } else if (pred == FZ_PRED_INTERP || pred == FZ_PRED_GLOBAL) {
         // residuals of every block, then the anchors and levels of the
         // interpolation in place, then dequantised row stores
         T.push_back({"decode",
@@ -766,9 +771,15 @@ void decompress_tasks(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_ou
                                                  c->oidx, nout, c->res, c->misc);
                      }});
         const uint32_t max_grid = (uint32_t)c->n_cu * 8;
-        T.push_back({"interp", {{c->res, ACC_RW}, {c->ival, ACC_W}, {d_out, ACC_W}}, [=](hipStream_t st) {
-                         launch_interp_inverse(st, g, c->res, c->ival, e2, d_out, vec, max_grid);
-                     }});
+        if (pred == FZ_PRED_INTERP)
+            T.push_back({"interp", {{c->res, ACC_RW}, {c->ival, ACC_W}, {d_out, ACC_W}}, [=](hipStream_t st) {
+                             launch_interp_inverse(st, g, c->res, c->ival, e2, d_out, vec, max_grid);
+                         }});
+        else
+            // prefix sums along every axis of the whole field
+            T.push_back({"inverse",
+                         {{c->res, ACC_RW}, {c->gdesc, ACC_W}, {M.mtile, ACC_RW}, {M.flags, ACC_RED}, {d_out, ACC_W}},
+                         [=](hipStream_t st) { launch_global_inverse(st, g, c->res, c->gdesc, c->misc, e2, d_out); }});
     } else {
         T.push_back({"decode",
                      {{in, ACC_R}, {c->off, ACC_R}, {c->lut, ACC_R}, {c->oidx, ACC_R}, {c->bpred, ACC_W},
@@ -986,6 +997,7 @@ void fz_ctx_destroy(fz_ctx* c) {
     hipFree(c->desc_pmap);
     hipFree(c->res);
     hipFree(c->ival);
+    hipFree(c->gdesc);
     if (c->h_misc) hipHostFree(c->h_misc);
     if (c->h_hdr) hipHostFree(c->h_hdr);
     for (int i = 0; i <= kMaxStages; i++)

@@ -232,6 +232,11 @@ __host__ __device__ inline bool pred_has_map(uint32_t pred) { return pred == kPr
 // y, then x, each from points rebuilt before.
 constexpr uint32_t kPredInterp = 5;
 
+// Global first-order Lorenzo (header predictor 6): the Lorenzo formula with
+// neighbours anywhere in the field (zero outside it); the inverse is the
+// prefix sum along x of every row of the field, then along y, then along z.
+constexpr uint32_t kPredGlobal = 6;
+
 // Axis a point is interpolated along (-1 for an anchor) and its stride.
 __host__ __device__ inline int interp_class(const uint32_t c[3], int nd, uint32_t& s) {
     uint32_t orc = 0;

@@ -96,6 +96,12 @@ void launch_decode_residuals(hipStream_t st, const Geom& g, const uint32_t* stre
 // q unchanged, 1D/2D work in place on q
 void launch_interp_inverse(hipStream_t st, const Geom& g, int32_t* q, int32_t* v, double e2, float* out, int vec,
                            uint32_t max_grid);
+// fz_global.hip: residuals q (block-major, in place) of the global Lorenzo
+// predictor to dequantised row-major floats; 1D uses desc (look-back
+// descriptors, global_scan_tiles(N) of them) and misc->mtile_ctr
+uint32_t global_scan_tiles(uint64_t N);
+void launch_global_inverse(hipStream_t st, const Geom& g, int32_t* q, uint64_t* desc, Misc* misc, double e2,
+                           float* out);
 void launch_patch(hipStream_t st, const Geom& g, const uint32_t* ppos, const uint32_t* pbits, uint64_t n_pat,
                   float* out, Misc* misc);
 

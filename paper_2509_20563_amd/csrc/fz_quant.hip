@@ -122,7 +122,9 @@ __device__ __forceinline__ void read_row(const int32_t* Q, uint32_t off, int32_t
 // neighbours read from LDS or prequantised from the field, and a top-3
 // histogram (the codes of residuals -1, 0, 1 counted by ballots: the
 // interpolation residuals pile up there).
-constexpr int kQuantP0 = 0, kQuantPred = 1, kQuantTrial = 2, kQuantInterp = 3;
+// kQuantGlobal: first-order Lorenzo over the whole field (neighbours in
+// other blocks read as in kQuantInterp).
+constexpr int kQuantP0 = 0, kQuantPred = 1, kQuantTrial = 2, kQuantInterp = 3, kQuantGlobal = 4;
 
 template <int ND, int MODE>
 __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom g, uint32_t mode, double eb,
@@ -258,34 +260,34 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
             uint32_t lx0, ly, lz;
             seg_coords<ND>(s, lx0, ly, lz);
             nv = (blk && ly < info.ey && lz < info.ez && lx0 < info.ex) ? min(8u, info.ex - lx0) : 0u;
+            // whole-field predictors (interpolation, global Lorenzo): the
+            // grid value anywhere in the field, from LDS where it falls in
+            // this tile's blocks, else the value prequantised here (the same
+            // arithmetic as phase A, so the same grid value)
+            const uint32_t b0 = tile * kTileBlocks;
+            auto q_at = [&](uint32_t xx, uint32_t yy, uint32_t zz) -> int32_t {
+                uint32_t bb, loc;
+                if (ND == 3) {
+                    bb = (xx >> 3) + g.nb[0] * ((yy >> 3) + g.nb[1] * (zz >> 3));
+                    loc = (xx & 7u) + 8u * ((yy & 7u) + 8u * (zz & 7u));
+                } else if (ND == 2) {
+                    bb = (xx >> 5) + g.nb[0] * (yy >> 4);
+                    loc = (xx & 31u) + 32u * (yy & 15u);
+                } else {
+                    bb = xx >> 9;
+                    loc = xx & 511u;
+                }
+                const uint32_t rel = bb - b0;
+                if (rel < (uint32_t)kTileBlocks) return Q[rel * kQStride + loc];
+                bool pq;
+                return prequant1(x[(uint64_t)xx + (uint64_t)g.n[0] * ((uint64_t)yy + (uint64_t)g.n[1] * zz)], e2,
+                                 inv, eb_abs, pq);
+            };
             auto residual = [&](const uint32_t pr) {
             if (MODE == kQuantInterp) {
-                // the prediction reads neighbours anywhere in the field:
-                // from LDS where they fall in this tile's blocks, else the
-                // value itself, prequantised here (the same arithmetic as
-                // phase A, so the same grid value)
                 int32_t r0[8];
                 read_row<ND>(Q, Qb + s * 8, r0);
                 const uint32_t n3[3] = {g.n[0], g.n[1], g.n[2]};
-                const uint32_t b0 = tile * kTileBlocks;
-                auto q_at = [&](uint32_t xx, uint32_t yy, uint32_t zz) -> int32_t {
-                    uint32_t bb, loc;
-                    if (ND == 3) {
-                        bb = (xx >> 3) + g.nb[0] * ((yy >> 3) + g.nb[1] * (zz >> 3));
-                        loc = (xx & 7u) + 8u * ((yy & 7u) + 8u * (zz & 7u));
-                    } else if (ND == 2) {
-                        bb = (xx >> 5) + g.nb[0] * (yy >> 4);
-                        loc = (xx & 31u) + 32u * (yy & 15u);
-                    } else {
-                        bb = xx >> 9;
-                        loc = xx & 511u;
-                    }
-                    const uint32_t rel = bb - b0;
-                    if (rel < (uint32_t)kTileBlocks) return Q[rel * kQStride + loc];
-                    bool pq;
-                    return prequant1(x[(uint64_t)xx + (uint64_t)g.n[0] * ((uint64_t)yy + (uint64_t)g.n[1] * zz)], e2,
-                                     inv, eb_abs, pq);
-                };
 #pragma unroll
                 for (int i = 0; i < 8; i++) {
                     const uint32_t c[3] = {info.bx * g.bs[0] + lx0 + i, info.by * g.bs[1] + ly,
@@ -293,6 +295,43 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
                     const int32_t pq = i < (int)nv ? interp_predict(c, n3, ND, q_at) : 0;
                     d[i] = (int32_t)((uint32_t)r0[i] - (uint32_t)pq);
                 }
+            } else if (MODE == kQuantGlobal) {
+                // first-order Lorenzo over the whole field: the rows below
+                // the segment (y - 1, z - 1, both) and the value left of each
+                // row, from this block's LDS rows where they lie in the
+                // block, else through q_at; zero outside the field
+                const uint32_t X0 = info.bx * g.bs[0] + lx0, Y = info.by * g.bs[1] + ly, Z = info.bz * g.bs[2] + lz;
+                constexpr uint32_t kRowSeg = ND == 2 ? 4u : 1u;  // segment step of y - 1
+                auto row9 = [&](uint32_t dy, uint32_t dz, int32_t r[9]) {
+#pragma unroll
+                    for (int i = 0; i < 9; i++) r[i] = 0;
+                    if (dy > Y || dz > Z || nv == 0) return;
+                    const uint32_t yy = Y - dy, zz = Z - dz;
+                    if (dy <= ly && dz <= lz) {
+                        read_row<ND>(Q, Qb + (s - dy * kRowSeg - dz * 8u) * 8, &r[1]);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 8; i++) r[1 + i] = (i < (int)nv) ? q_at(X0 + i, yy, zz) : 0;
+                    }
+                    if (X0 > 0) r[0] = q_at(X0 - 1, yy, zz);
+                };
+                int32_t A[9];
+                row9(0, 0, A);
+                if (ND >= 2) {
+                    int32_t ry[9];
+                    row9(1, 0, ry);
+#pragma unroll
+                    for (int i = 0; i < 9; i++) A[i] -= ry[i];
+                }
+                if (ND == 3) {
+                    int32_t rz[9], ryz[9];
+                    row9(0, 1, rz);
+                    row9(1, 1, ryz);
+#pragma unroll
+                    for (int i = 0; i < 9; i++) A[i] = A[i] - rz[i] + ryz[i];
+                }
+#pragma unroll
+                for (int i = 0; i < 8; i++) d[i] = A[i + 1] - A[i];
             } else if (pr == 0) {
                 // first-order Lorenzo: A = residual along y/z of the rows,
                 // then the backward difference along x
@@ -579,6 +618,12 @@ void launch_quant(hipStream_t st, int grid, const float* x, const Geom& g, uint3
         if (g.ndim == 3) FZ_QUANT(3, kQuantInterp);
         else if (g.ndim == 2) FZ_QUANT(2, kQuantInterp);
         else FZ_QUANT(1, kQuantInterp);
+        return;
+    }
+    if (fixed_pred == (int)kPredGlobal) {
+        if (g.ndim == 3) FZ_QUANT(3, kQuantGlobal);
+        else if (g.ndim == 2) FZ_QUANT(2, kQuantGlobal);
+        else FZ_QUANT(1, kQuantGlobal);
         return;
     }
     const bool pred = fixed_pred != 0;

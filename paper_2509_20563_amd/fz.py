@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(HERE, "libfz.so")
 HEADER_PATH = os.path.join(os.path.dirname(HERE), "include", "fz.h")
 
 EB_ABS, EB_REL = 0, 1
-PRED_LORENZO1, PRED_LORENZO2, PRED_REGRESSION, PRED_AUTO_MLP, PRED_AUTO_TRIAL, PRED_INTERP = 0, 1, 2, 3, 4, 5
+PRED_LORENZO1, PRED_LORENZO2, PRED_REGRESSION, PRED_AUTO_MLP, PRED_AUTO_TRIAL, PRED_INTERP, PRED_GLOBAL = \
+    0, 1, 2, 3, 4, 5, 6
 HDR_BYTES = 128
 NFEAT = 16
 SELECTOR_PARAMS = 5475

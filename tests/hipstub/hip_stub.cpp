@@ -319,17 +319,14 @@ void launch_minmax(hipStream_t st, const float* x, uint64_t N, int, Misc* misc, 
 }
 void launch_quant(hipStream_t st, int, const float* x, const Geom& g, uint32_t, double, int, Misc* misc,
                   uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt, uint2* ostage, uint2* pstage,
-                  int fixed, const uint8_t* bpred, int32_t* coef, const int32_t* qf) {
+                  int fixed, const uint8_t* bpred, int32_t* coef) {
     // the first-order instance (fixed 0) touches neither the map nor the
     // coefficients; a map is read when fixed < 0, coefficients written
     // for regression blocks
     K("quant", {x, 4 * g.N}, {misc, sizeof(Misc)}, {hist, 4ull * kBins}, {codes, 2ull * g.nblocks * kBlockElems},
       {tile_cnt, 4ull * ntiles}, {ostage, 8ull * ntiles * kTileBlocks * kBlockElems},
       {pstage, 8ull * ntiles * kTileBlocks * kBlockElems}, {bpred, fixed < 0 ? g.nblocks : 0ull},
-      {coef, fixed < 0 || fixed == 2 ? 16ull * g.nblocks : 0ull}, {qf, qf ? 4 * g.N : 0ull});
-}
-void launch_grid_values(hipStream_t st, const float* x, uint64_t N, uint32_t, double, const Misc* misc, int32_t* q) {
-    K("grid_values", {x, 4 * N}, {misc, sizeof(Misc)}, {q, 4 * N});
+      {coef, fixed < 0 || fixed == 2 ? 16ull * g.nblocks : 0ull});
 }
 void launch_trial(hipStream_t st, int, const float* x, const Geom& g, uint32_t, double, int, Misc* misc, uint32_t,
                   const uint32_t* cw_ref, uint8_t* choice, uint32_t* costs) {
@@ -496,6 +493,11 @@ void launch_decode_residuals(hipStream_t st, const Geom& g, const uint32_t* stre
     K("decode_residuals", {stream, 4 * words}, {off, 8ull * g.nblocks}, {chunks, 2ull * g.nblocks},
       {lut, 2ull * kLut}, {opos, 4 * n_out}, {oval, 4 * n_out}, {oidx, 8ull * g.nblocks},
       {res, 4ull * g.nblocks * kBlockElems}, {misc, sizeof(Misc)});
+}
+uint32_t global_scan_tiles(uint64_t N) { return (uint32_t)((N + 2047) / 2048); }
+void launch_global_inverse(hipStream_t st, const Geom& g, int32_t* q, uint64_t* desc, Misc* misc, double, float* out) {
+    K("global_inverse", {q, 4ull * g.nblocks * kBlockElems}, {desc, g.ndim == 1 ? 8ull * global_scan_tiles(g.N) : 0ull},
+      {misc, sizeof(Misc)}, {out, 4 * g.N});
 }
 void launch_interp_inverse(hipStream_t st, const Geom& g, int32_t* q, int32_t* v, double, float* out, int, uint32_t) {
     K("interp_inverse", {q, 4ull * g.nblocks * kBlockElems}, {v, g.ndim == 3 ? 4ull * g.nblocks * kBlockElems : 0ull},
