@@ -313,6 +313,8 @@ def bench_c3(args):
     # the interpolation predictor (FZMod-Quality front end) on the same field
     print("[bench] interpolation predictor", file=sys.stderr, flush=True)
     interp_mode = quality_mode(ctx, fz, metrics, x, C3_EB, sbuf, rec)
+    print("[bench] global Lorenzo", file=sys.stderr, flush=True)
+    global_mode = quality_mode(ctx, fz, metrics, x, C3_EB, sbuf, rec, pred=fz.PRED_GLOBAL)
 
     # dominant first-order Lorenzo kernel and its roofline (HIP events
     # around it inside the timed region)
@@ -376,6 +378,7 @@ def bench_c3(args):
         "modes": modes,
         "shuffle_codec": shuffle_mode,
         "interp_predictor": interp_mode,
+        "global_lorenzo": global_mode,
         "selector": selector_vs,
         "training": training,
         "stages": stage_summary,
@@ -415,18 +418,20 @@ def selector_summary(ctx, fz, x, modes):
     return selector_vs
 
 
-def quality_mode(ctx, fz, metrics, x, eb, buf, rec):
-    """One field through the interpolation predictor (Huffman codec):
-    ratio, error, PSNR, whole-call rates and rooflines.  The algorithmic
-    bytes are first-order Lorenzo's (the method reads the field once for the
-    prediction; the halo reads of neighbouring tiles are implementation
-    traffic)."""
+def quality_mode(ctx, fz, metrics, x, eb, buf, rec, pred=None):
+    """One field through a whole-field predictor (the interpolation
+    predictor by default, or global Lorenzo; Huffman codec): ratio, error,
+    PSNR, whole-call rates and rooflines.  The algorithmic bytes are
+    first-order Lorenzo's (the method reads the field once for the
+    prediction and writes it once on decompression; halo reads and the
+    decoder's residual and prefix-sum passes are implementation traffic)."""
+    pred = fz.PRED_INTERP if pred is None else pred
     n = x.numel()
-    c = ctx.compress(x, eb, fz.EB_REL, out=buf, pred=fz.PRED_INTERP)
+    c = ctx.compress(x, eb, fz.EB_REL, out=buf, pred=pred)
     size = c.numel()
     hdr = c[:128].cpu().numpy().tobytes()
     ctx.decompress(c, header=hdr, out=rec)
-    tc = _call_ms(ctx, lambda: ctx.compress(x, eb, fz.EB_REL, out=buf, pred=fz.PRED_INTERP))
+    tc = _call_ms(ctx, lambda: ctx.compress(x, eb, fz.EB_REL, out=buf, pred=pred))
     td = _call_ms(ctx, lambda: ctx.decompress(buf[:size], header=hdr, out=rec))
     h = fz.header_fields(hdr)
     diff = rec.double() - x.double()
@@ -480,6 +485,7 @@ def c2_extra(ctx, fz, metrics, dev):
                    "call_roofline": {"compress": _roof(call_bytes("compress", "shuffle", n, ssize), stc),
                                      "decompress": _roof(call_bytes("decompress", "shuffle", n, ssize), std)}}
         interp = quality_mode(ctx, fz, metrics, x, eb, out2, rec)
+        glob = quality_mode(ctx, fz, metrics, x, eb, out2, rec, pred=fz.PRED_GLOBAL)
         ctx.decompress(out[:size], header=hdr, out=rec)
         rows.append({"eb_rel": eb, "bytes": size, "cr": round(metrics.compression_ratio(n, size), 4),
                      "max_err_over_eb": (rec.double() - x.double()).abs().max().item() / h["eb_abs"],
@@ -488,7 +494,7 @@ def c2_extra(ctx, fz, metrics, dev):
                      "decompress_gbps": round(4.0 * n / (td * 1e-3) / 1e9, 2),
                      "call_roofline": {"compress": _roof(call_bytes("compress", "lorenzo1", n, size), tc),
                                        "decompress": _roof(call_bytes("decompress", "lorenzo1", n, size), td)},
-                     "shuffle_codec": shuffle, "interp_predictor": interp})
+                     "shuffle_codec": shuffle, "interp_predictor": interp, "global_lorenzo": glob})
     del x, out, out2, rec
     torch.cuda.empty_cache()
     return {"workload": "512x512x512 k^-3 Gaussian random field, first-order Lorenzo", "per_eb": rows}

@@ -779,7 +779,7 @@ void decompress_tasks(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_ou
             // prefix sums along every axis of the whole field
             T.push_back({"inverse",
                          {{c->res, ACC_RW}, {c->gdesc, ACC_W}, {M.mtile, ACC_RW}, {M.flags, ACC_RED}, {d_out, ACC_W}},
-                         [=](hipStream_t st) { launch_global_inverse(st, g, c->res, c->gdesc, c->misc, e2, d_out); }});
+                         [=](hipStream_t st) { launch_global_inverse(st, g, c->res, c->gdesc, c->misc, e2, d_out, vec); }});
     } else {
         T.push_back({"decode",
                      {{in, ACC_R}, {c->off, ACC_R}, {c->lut, ACC_R}, {c->oidx, ACC_R}, {c->bpred, ACC_W},

@@ -4,10 +4,11 @@
 // the inverse is a prefix sum along each axis over the whole field, done
 // here one axis per launch on that field, in place, each thread carrying
 // the running sum of one line across the blocks:
-//   3D  k_gl_x3 - line along x: lane = (ly, lz) of a block row, 8 values
-//                 per block (two 16-byte loads), blocks bx = 0, 1, ...
-//       k_gl_y3 - line along y: lane = (lx, lz), 8 values per block
-//       k_gl_z3 - line along z: lane = (lx, ly), dequantised row stores
+//   3D  k_gl_y3 - line along y: lane = (lx, lz), 8 values per block
+//       k_gl_z3 - line along z: lane = (lx, ly), 8 values per block
+//       k_gl_x3_store - line along x: lane = (ly, lz) of a block row, two
+//                 16-byte loads per block, dequantised values staged in
+//                 LDS and stored as whole 256-byte pieces of the lines
 //   2D  k_gl_x2 - line along x: lane = ly, 32 values per block
 //       k_gl_y2 - line along y: lane = lx, dequantised stores
 //   1D  k_gl_scan1 - one prefix sum over the field: tiles of 2048 values
@@ -28,32 +29,6 @@ __device__ __forceinline__ uint4 scan4(uint4 a, uint32_t& carry) {
     a.w += a.z;
     carry = a.w;
     return a;
-}
-
-__global__ __launch_bounds__(256) void k_gl_x3(Geom g, uint32_t* __restrict__ R) {
-    const uint32_t gid = blockIdx.x * 256 + threadIdx.x;
-    if (gid >= 64u * g.nb[1] * g.nb[2]) return;
-    const uint32_t seg = gid & 63u, br = gid >> 6;
-    const uint64_t row0 = (uint64_t)g.nb[0] * br;  // first block of this block row
-    uint32_t carry = 0;
-    uint4* p = reinterpret_cast<uint4*>(R + row0 * kBlockElems + seg * 8);
-    uint4 a = p[0], c = p[1];
-    for (uint32_t bx = 0; bx < g.nb[0]; bx++) {
-        // the next block's row is loaded before this one is stored
-        uint4 na = a, nc = c;
-        uint4* q = p + kBlockElems / 4;
-        if (bx + 1 < g.nb[0]) {
-            na = q[0];
-            nc = q[1];
-        }
-        a = scan4(a, carry);
-        c = scan4(c, carry);
-        p[0] = a;
-        p[1] = c;
-        p = q;
-        a = na;
-        c = nc;
-    }
 }
 
 __global__ __launch_bounds__(256) void k_gl_y3(Geom g, uint32_t* __restrict__ R) {
@@ -77,30 +52,78 @@ __global__ __launch_bounds__(256) void k_gl_y3(Geom g, uint32_t* __restrict__ R)
     }
 }
 
-__global__ __launch_bounds__(256) void k_gl_z3(Geom g, const uint32_t* __restrict__ R, double e2,
-                                               float* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_gl_z3(Geom g, uint32_t* __restrict__ R) {
     const uint32_t gid = blockIdx.x * 256 + threadIdx.x;
     if (gid >= 64u * g.nb[0] * g.nb[1]) return;
-    const uint32_t seg = gid & 63u, bc = gid >> 6;
-    const uint32_t lx = seg & 7u, ly = seg >> 3;
-    const uint32_t bx = bc % g.nb[0], by = bc / g.nb[0];
-    const uint32_t x = bx * 8 + lx, y = by * 8 + ly;
-    const bool in = x < g.n[0] && y < g.n[1];
+    const uint32_t seg = gid & 63u, bc = gid >> 6;  // seg = lx + 8 ly
     uint32_t carry = 0;
-    for (uint32_t bz = 0; bz < g.nb[2]; bz++) {
-        const uint64_t b = bx + (uint64_t)g.nb[0] * (by + (uint64_t)g.nb[1] * bz);
-        const uint32_t* p = R + b * kBlockElems + seg;
+    const uint64_t plane = (uint64_t)g.nb[0] * g.nb[1];
+    uint32_t* p = R + (uint64_t)bc * kBlockElems + seg;
+    for (uint32_t bz = 0; bz < g.nb[2]; bz++, p += plane * kBlockElems) {
         uint32_t v[8];
 #pragma unroll
         for (int k = 0; k < 8; k++) v[k] = p[64 * k];
 #pragma unroll
         for (int k = 0; k < 8; k++) {
             carry += v[k];
-            const uint32_t z = bz * 8 + (uint32_t)k;
-            if (in && z < g.n[2])
-                __builtin_nontemporal_store((float)((double)(int32_t)carry * e2),
-                                            out + x + (uint64_t)g.n[0] * (y + (uint64_t)g.n[1] * z));
+            p[64 * k] = carry;
         }
+    }
+}
+
+// 3D, last pass: lines along x with dequantisation.  Wave = one block row
+// (lane = (ly, lz)); every 8 blocks along x a lane has 64 values of its
+// line, staged in LDS (64 lines x 64 values per wave) and stored as whole
+// 256-byte line pieces: each store instruction writes four lines' pieces.
+__global__ __launch_bounds__(256) void k_gl_x3_store(Geom g, const uint32_t* __restrict__ R, double e2,
+                                                     float* __restrict__ out, int vec) {
+    __shared__ float S[4][64 * 65];  // per wave, line l at l * 65 (padding against bank conflicts)
+    const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const uint32_t br = blockIdx.x * 4 + wave;  // block row: by + nb1 * bz
+    const bool act = br < g.nb[1] * g.nb[2];
+    const uint32_t by = act ? br % g.nb[1] : 0, bz = act ? br / g.nb[1] : 0;
+    float* Sw = S[wave];
+    uint32_t carry = 0;
+    const uint4* p = reinterpret_cast<const uint4*>(R + (uint64_t)g.nb[0] * br * kBlockElems + lane * 8);
+    for (uint32_t bx0 = 0; bx0 < g.nb[0]; bx0 += 8) {
+        const uint32_t nbk = min(8u, g.nb[0] - bx0);
+        if (act) {
+            for (uint32_t j = 0; j < nbk; j++) {
+                const uint4 a = p[0], c = p[1];
+                p += kBlockElems / 4;
+                const uint32_t q[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
+#pragma unroll
+                for (int i = 0; i < 8; i++) {
+                    carry += q[i];
+                    Sw[lane * 65 + 8 * j + i] = (float)((double)(int32_t)carry * e2);
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // store: 16 rounds, four lines per round (lane = line 4 r + lane / 16,
+        // float4 index lane % 16 of the 64 values)
+        if (act) {
+            const uint32_t x0 = bx0 * 8;
+            for (uint32_t r = 0; r < 16; r++) {
+                const uint32_t l = 4 * r + lane / 16, f = lane % 16;  // line (ly + 8 lz), float4 in it
+                const uint32_t y = by * 8 + (l & 7), z = bz * 8 + (l >> 3);
+                const uint32_t x = x0 + 4 * f;
+                if (y >= g.n[1] || z >= g.n[2] || x >= g.n[0]) continue;
+                const float* src = &Sw[l * 65 + 4 * f];
+                const uint64_t o = x + (uint64_t)g.n[0] * (y + (uint64_t)g.n[1] * z);
+                if (vec && x + 4 <= g.n[0]) {
+                    const f32x4 w = {src[0], src[1], src[2], src[3]};
+                    __builtin_nontemporal_store(w, reinterpret_cast<f32x4*>(out + o));
+                } else {
+                    for (uint32_t m = 0; m < 4 && x + m < g.n[0]; m++) out[o + m] = src[m];
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -184,13 +207,15 @@ __global__ __launch_bounds__(256) void k_gl_scan1(uint64_t N, const uint32_t* __
 uint32_t global_scan_tiles(uint64_t N) { return (uint32_t)((N + kScan1 - 1) / kScan1); }
 
 void launch_global_inverse(hipStream_t st, const Geom& g, int32_t* res, uint64_t* desc, Misc* misc, double e2,
-                           float* out) {
+                           float* out, int vec) {
     uint32_t* R = reinterpret_cast<uint32_t*>(res);
     auto grid = [](uint64_t threads) { return dim3((uint32_t)((threads + 255) / 256)); };
     if (g.ndim == 3) {
-        hipLaunchKernelGGL(k_gl_x3, grid(64ull * g.nb[1] * g.nb[2]), dim3(256), 0, st, g, R);
+        // y and z in place, then x (the output's contiguous axis) with the
+        // dequantised, staged row stores
         hipLaunchKernelGGL(k_gl_y3, grid(64ull * g.nb[0] * g.nb[2]), dim3(256), 0, st, g, R);
-        hipLaunchKernelGGL(k_gl_z3, grid(64ull * g.nb[0] * g.nb[1]), dim3(256), 0, st, g, R, e2, out);
+        hipLaunchKernelGGL(k_gl_z3, grid(64ull * g.nb[0] * g.nb[1]), dim3(256), 0, st, g, R);
+        hipLaunchKernelGGL(k_gl_x3_store, dim3((g.nb[1] * g.nb[2] + 3) / 4), dim3(256), 0, st, g, R, e2, out, vec);
     } else if (g.ndim == 2) {
         hipLaunchKernelGGL(k_gl_x2, grid(16ull * g.nb[1]), dim3(256), 0, st, g, R);
         hipLaunchKernelGGL(k_gl_y2, grid(32ull * g.nb[0]), dim3(256), 0, st, g, R, e2, out);

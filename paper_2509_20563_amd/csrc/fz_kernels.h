@@ -101,7 +101,7 @@ void launch_interp_inverse(hipStream_t st, const Geom& g, int32_t* q, int32_t* v
 // descriptors, global_scan_tiles(N) of them) and misc->mtile_ctr
 uint32_t global_scan_tiles(uint64_t N);
 void launch_global_inverse(hipStream_t st, const Geom& g, int32_t* q, uint64_t* desc, Misc* misc, double e2,
-                           float* out);
+                           float* out, int vec);
 void launch_patch(hipStream_t st, const Geom& g, const uint32_t* ppos, const uint32_t* pbits, uint64_t n_pat,
                   float* out, Misc* misc);
 

@@ -495,7 +495,8 @@ void launch_decode_residuals(hipStream_t st, const Geom& g, const uint32_t* stre
       {res, 4ull * g.nblocks * kBlockElems}, {misc, sizeof(Misc)});
 }
 uint32_t global_scan_tiles(uint64_t N) { return (uint32_t)((N + 2047) / 2048); }
-void launch_global_inverse(hipStream_t st, const Geom& g, int32_t* q, uint64_t* desc, Misc* misc, double, float* out) {
+void launch_global_inverse(hipStream_t st, const Geom& g, int32_t* q, uint64_t* desc, Misc* misc, double, float* out,
+                           int) {
     K("global_inverse", {q, 4ull * g.nblocks * kBlockElems}, {desc, g.ndim == 1 ? 8ull * global_scan_tiles(g.N) : 0ull},
       {misc, sizeof(Misc)}, {out, 4 * g.N});
 }
