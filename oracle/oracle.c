@@ -904,6 +904,14 @@ int orc_compress_ex(const float *x, int ndim, const uint64_t dims[3], int mode, 
             nreg++;
         }
     }
+    /* a per-block choice of first-order Lorenzo everywhere is written as a
+     * first-order container: the map would only add a quarter byte per
+     * block */
+    if (pred == 3 || pred == 4) {
+        int any = 0;
+        for (uint64_t b = 0; b < g.nblocks; b++) any |= bp[b] != ORC_P0;
+        if (!any) pred = ORC_P0;
+    }
     block_codes(&g, q, refs, bp, cf, codes, res);
 
     uint64_t nout = 0, npat = 0;
@@ -1603,6 +1611,8 @@ int orc_features_q(const int32_t *q, int ndim, const uint64_t dims[3], float *fe
 #define OFF_B3 (OFF_W3 + ORC_NOUT * ORC_H)
 #define ORC_NPARAM (OFF_B3 + ORC_NOUT)
 
+#define ORC_MARGIN 0.0078125f
+
 int orc_mlp_nparam(void) { return ORC_NPARAM; }
 
 void orc_mlp_infer(const float *w, const float *feat, uint64_t n, float *y, uint8_t *choice) {
@@ -1628,9 +1638,17 @@ void orc_mlp_infer(const float *w, const float *feat, uint64_t n, float *y, uint
             for (int i = 0; i < ORC_H; i++) acc = fmaf(w[OFF_W3 + ORC_H * k + i], h2[i], acc);
             o[k] = acc;
         }
+        /* the choice: the lowest score, ties to the lower index; a
+         * predictor other than first-order Lorenzo scores its output plus
+         * ORC_MARGIN = 1/128 (a predicted saving below 2^(1/128) - 1 = 0.54%
+         * is not worth the risk of a wrong switch and its share of the
+         * map) */
         int best = 0;
-        for (int k = 1; k < ORC_NOUT; k++)
-            if (o[k] < o[best]) best = k;
+        float bs = o[0];
+        for (int k = 1; k < ORC_NOUT; k++) {
+            float sk = o[k] + ORC_MARGIN;
+            if (sk < bs) { best = k; bs = sk; }
+        }
         if (y)
             for (int k = 0; k < ORC_NOUT; k++) y[ORC_NOUT * s + k] = o[k];
         if (choice) choice[s] = (uint8_t)best;

@@ -59,6 +59,8 @@ struct Misc {
     uint32_t stile_ctr;
     uint32_t code0_count;      // decode: outlier codes seen
     uint32_t mtile_ctr;        // predictor-map scan
+    uint32_t map_off;          // per-block choice is first-order everywhere:
+                               // written as a first-order container
     uint64_t total_bits_cb;    // sum hist[c] * len[c]
     uint64_t total_bits_enc;   // end of the last encoded tile (bit-shuffle
                                // codec: kept words)

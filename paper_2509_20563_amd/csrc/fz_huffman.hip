@@ -406,6 +406,9 @@ __global__ __launch_bounds__(256) void k_finalize(Geom g, uint32_t mode, double 
     const uint64_t bits = shuffle ? 0 : misc->total_bits_enc;
     const uint64_t words = shuffle ? misc->total_bits_enc : (bits + 31) / 32;
     const uint64_t nout = misc->n_out, npat = misc->n_pat, nreg = misc->nreg;
+    // a per-block choice of first-order Lorenzo everywhere is written as a
+    // first-order container (no map)
+    if (pred_has_map(pred) && misc->map_off) pred = 0;
     const bool has_map = pred_has_map(pred);
     const Layout L = shuffle ? make_speed_layout(g.nblocks, words, nout, npat)
                              : make_layout(g.nblocks, has_map, nreg, words, nout, npat);

@@ -21,7 +21,10 @@ template <int KIND>
 __global__ __launch_bounds__(256) void k_scan(const void* __restrict__ in, uint32_t n, uint64_t* __restrict__ out,
                                               uint64_t* desc, uint32_t* ctr, uint32_t ntiles, Misc* misc,
                                               uint64_t expect) {
-    using Op = typename std::conditional<KIND == SCAN_COUNTS, OpPair31, OpAdd>::type;
+    // packed pairs: (outliers, patches); for the map (regression blocks,
+    // blocks off first-order Lorenzo)
+    constexpr bool PAIR = KIND == SCAN_COUNTS || KIND == SCAN_PMAP;
+    using Op = typename std::conditional<PAIR, OpPair31, OpAdd>::type;
     const Op op;
     __shared__ uint64_t wsum[4];
     __shared__ uint32_t s_tile;
@@ -42,7 +45,8 @@ __global__ __launch_bounds__(256) void k_scan(const void* __restrict__ in, uint3
                 const uint32_t c = static_cast<const uint32_t*>(in)[base + k];
                 e = (uint64_t)(c & 0xFFFFu) | ((uint64_t)(c >> 16) << 31);
             } else if (KIND == SCAN_PMAP) {
-                e = static_cast<const uint8_t*>(in)[base + k] == 2 ? 1u : 0u;
+                const uint8_t pr = static_cast<const uint8_t*>(in)[base + k];
+                e = (pr == 2 ? 1ull : 0ull) | ((pr != 0 ? 1ull : 0ull) << 31);
             } else if (KIND == SCAN_MASKS) {
                 const uint32_t* m = static_cast<const uint32_t*>(in) + 5 * (base + k);
                 e = __popc(m[0]) + __popc(m[1]) + __popc(m[2]) + __popc(m[3]) + __popc(m[4]);
@@ -73,9 +77,14 @@ __global__ __launch_bounds__(256) void k_scan(const void* __restrict__ in, uint3
                     misc->n_pat = total >> 31;
                     if ((total & m) == m || (total >> 31) == m) atomicOr(&misc->flags, F_OVERFLOW);
                 } else if (KIND == SCAN_PMAP) {
-                    // regression blocks decide where the chunk table starts
-                    const Layout L = make_layout(n, true, total, 0, 0, 0);
-                    misc->nreg = total;
+                    // regression blocks decide where the chunk table starts;
+                    // with no block off first-order Lorenzo there is no map
+                    const uint64_t m = (1ull << 31) - 1;
+                    const uint64_t nreg = total & m;
+                    const bool map = (total >> 31) != 0;
+                    const Layout L = make_layout(n, map, nreg, 0, 0, 0);
+                    misc->nreg = nreg;
+                    misc->map_off = map ? 0u : 1u;
                     misc->off_chunks = L.chunks;
                     misc->off_stream = L.stream;
                 } else if (total != expect) {
@@ -88,7 +97,7 @@ __global__ __launch_bounds__(256) void k_scan(const void* __restrict__ in, uint3
     // exclusive prefix of this thread's first entry: the wave-exclusive part
     // (exact: no field saturates inside one tile), earlier waves, the tile
     uint64_t excl_wave;
-    if (KIND == SCAN_COUNTS) {
+    if (PAIR) {
         const uint64_t m = (1ull << 31) - 1;
         excl_wave = ((incl & m) - (sum & m)) | (((incl >> 31) - (sum >> 31)) << 31);
     } else {
@@ -97,7 +106,8 @@ __global__ __launch_bounds__(256) void k_scan(const void* __restrict__ in, uint3
     uint64_t p = op(op(s_excl, wpre), excl_wave);
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-        if (base + k < n) out[base + k] = p;
+        // the map's output is the regression-block index alone
+        if (base + k < n) out[base + k] = KIND == SCAN_PMAP ? (p & ((1ull << 31) - 1)) : p;
         p = op(p, v[k]);
     }
 }

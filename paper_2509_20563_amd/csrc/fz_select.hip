@@ -363,6 +363,9 @@ __global__ __launch_bounds__(256) void k_features(const float* __restrict__ x, G
 constexpr int kPMu = 0, kPRs = kNFeat, kPW1 = 2 * kNFeat, kPB1 = kPW1 + kNHid * kNFeat, kPW2 = kPB1 + kNHid,
               kPB2 = kPW2 + kNHid * kNHid, kPW3 = kPB2 + kNHid, kPB3 = kPW3 + kNOut * kNHid,
               kPParams = kPB3 + kNOut;
+// the selector keeps first-order Lorenzo unless another predictor's output
+// (log2 of 1 + its predicted bits) is lower by more than this
+constexpr float kChoiceMargin = 0.0078125f;
 static_assert(kPParams == kSelectorParams, "selector layout");
 
 __global__ __launch_bounds__(256) void k_mlp(const float* __restrict__ feat, uint32_t n, const float* __restrict__ sel,
@@ -405,10 +408,14 @@ __global__ __launch_bounds__(256) void k_mlp(const float* __restrict__ feat, uin
             y1 = __builtin_fmaf(P[kPW3 + kNHid + j], h, y1);
             y2 = __builtin_fmaf(P[kPW3 + 2 * kNHid + j], h, y2);
         }
+        // lowest score, ties to the lower index; second-order Lorenzo and
+        // regression score their output plus a margin of 1/128 (a predicted
+        // saving under 0.54% keeps first-order Lorenzo)
         uint32_t best = 0;
         float bv = y0;
-        if (y1 < bv) { best = 1; bv = y1; }
-        if (y2 < bv) best = 2;
+        const float s1 = y1 + kChoiceMargin, s2 = y2 + kChoiceMargin;
+        if (s1 < bv) { best = 1; bv = s1; }
+        if (s2 < bv) best = 2;
         if (choice) choice[b] = (uint8_t)best;
         if (yout) {
             yout[3 * (uint64_t)b] = y0;

@@ -139,7 +139,14 @@ def test_round_trip_with_predictors(pred, shape, eb):
     y = oracle.decompress(c)
     assert np.abs(x.astype(np.float64) - y).max() <= h["eb_abs"]
     if not h["flags"] & 1:
-        assert h["pred"] == pred
+        # a per-block choice of first-order Lorenzo everywhere is written as
+        # a first-order container
+        want = pred
+        if pred == 3 and not choice.any():
+            want = 0
+        if pred == 4 and not oracle.trial(x, eb, 1)[0].any():
+            want = 0
+        assert h["pred"] == want
         if pred == 2:
             assert h["n_reg"] == oracle.nblocks_of(shape)
         if pred == 3:
@@ -152,3 +159,21 @@ def test_trial_never_worse_than_fixed_by_reference_cost():
         choice, costs = oracle.trial(x, eb, 1)
         best = costs[np.arange(costs.shape[0]), choice].sum()
         assert best <= costs[:, 0].sum() and best <= costs[:, 1].sum() and best <= costs[:, 2].sum()
+
+
+def test_all_first_order_choice_is_a_first_order_container():
+    # no map when every block keeps first-order Lorenzo: the same bytes as
+    # the first-order container, for the selector's and trial's choices
+    x = fields.grf((130, 70), seed=200)
+    nb = oracle.nblocks_of(x.shape)
+    for eb in (1e-2, 1e-4):
+        ref = oracle.compress(x, eb, 1, pred=0)
+        assert oracle.compress(x, eb, 1, pred=3, choice=np.zeros(nb, np.uint8)) == ref
+        ch, _ = oracle.trial(x, eb, 1)
+        if not ch.any():
+            assert oracle.compress(x, eb, 1, pred=4) == ref
+    # one block off first-order keeps the map
+    ch = np.zeros(nb, np.uint8)
+    ch[3] = 1
+    h = oracle.header(oracle.compress(x, 1e-2, 1, pred=3, choice=ch))
+    assert h["pred"] == 3

@@ -133,12 +133,17 @@ def test_mlp_permutation_network():
     y, ch = oracle.mlp_infer(_net_permutation(), feat)
     want = feat[:, [11, 14, 15]]
     assert np.array_equal(y, want)
-    assert np.array_equal(ch, np.argmin(want, axis=1))
+    # scores: first-order Lorenzo its output, the others output + 1/128
+    score = want.astype(np.float32) + np.array([0, 0.0078125, 0.0078125], np.float32)
+    assert np.array_equal(ch, np.argmin(score, axis=1))
 
 
 def test_mlp_bias_only_ties_lowest():
     feat = np.ones((3, 16), np.float32)
-    for b3, c in [((1, 1, 0), 2), ((0, 0, 1), 0), ((2, 1, 1), 1), ((5, 5, 5), 0)]:
+    # ties to the lower index; other predictors need to beat first-order
+    # Lorenzo by more than the margin of 1/128 (exact in float32)
+    for b3, c in [((1, 1, 0), 2), ((0, 0, 1), 0), ((2, 1, 1), 1), ((5, 5, 5), 0), ((1, 0.995, 2), 0),
+                  ((1, 0.9921875, 2), 0), ((1, 0.99, 2), 1), ((1, 2, 0.5), 2), ((1, 0.99, 0.985), 2)]:
         y, ch = oracle.mlp_infer(oracle.pack_params(b3=b3), feat)
         assert np.all(ch == c) and np.all(y == np.float32(b3))
 
