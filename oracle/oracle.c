@@ -904,13 +904,18 @@ int orc_compress_ex(const float *x, int ndim, const uint64_t dims[3], int mode, 
             nreg++;
         }
     }
-    /* a per-block choice of first-order Lorenzo everywhere is written as a
-     * first-order container: the map would only add a quarter byte per
-     * block */
+    /* the map costs a quarter byte per block: it is kept only when at
+     * least one block in 64 leaves first-order Lorenzo (a switched block
+     * then pays for at most 128 bits of map); otherwise every block is
+     * coded with first-order Lorenzo in a first-order container */
     if (pred == 3 || pred == 4) {
-        int any = 0;
-        for (uint64_t b = 0; b < g.nblocks; b++) any |= bp[b] != ORC_P0;
-        if (!any) pred = ORC_P0;
+        uint64_t off = 0;
+        for (uint64_t b = 0; b < g.nblocks; b++) off += bp[b] != ORC_P0;
+        if (64 * off < g.nblocks) {
+            pred = ORC_P0;
+            memset(bp, ORC_P0, g.nblocks);
+            nreg = 0;
+        }
     }
     block_codes(&g, q, refs, bp, cf, codes, res);
 

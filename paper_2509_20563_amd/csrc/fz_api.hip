@@ -548,6 +548,16 @@ void compress_tasks(fz_ctx* c, const fz_params* p, const Geom& g, const float* d
                          launch_features(st, (int)gmax, d_in, g, P.eb_mode, P.eb, vec, c->misc, c->featb);
                          launch_mlp(st, (int)gmax, c->featb, g.nblocks, c->sel, nullptr, c->bpred);
                      }});
+    // the map scan first: it decides whether the map is kept (at least one
+    // block in 64 off first-order Lorenzo), which the quantiser follows
+    if (has_map)
+        T.push_back({"scan_map",
+                     {{c->bpred, ACC_R}, {c->reg_idx, ACC_W}, {c->desc_pmap, ACC_RW}, {M.mtile, ACC_RW},
+                      {M.flags, ACC_RED}},
+                     [=](hipStream_t st) {
+                         launch_scan(st, SCAN_PMAP, c->bpred, g.nblocks, c->reg_idx, c->desc_pmap,
+                                     &c->misc->mtile_ctr, c->misc, 0);
+                     }});
     const bool interp = pred == FZ_PRED_INTERP;
     {
         const int fixed = has_map ? -1 : (int)pred;
@@ -557,19 +567,12 @@ void compress_tasks(fz_ctx* c, const fz_params* p, const Geom& g, const float* d
             a.push_back({c->bpred, ACC_R});
             a.push_back({c->coef, ACC_W});
         }
+        if (has_map) a.push_back({M.mtile, ACC_R});
         T.push_back({"quant", a, [=](hipStream_t st) {
                          launch_quant(st, grid, d_in, g, P.eb_mode, P.eb, vec, c->misc, c->hist, c->codes, ntiles,
                                       c->tile_cnt, c->ostage, c->pstage, fixed, c->bpred, c->coef);
                      }});
     }
-    if (has_map)
-        T.push_back({"scan_map",
-                     {{c->bpred, ACC_R}, {c->reg_idx, ACC_W}, {c->desc_pmap, ACC_RW}, {M.mtile, ACC_RW},
-                      {M.flags, ACC_RED}},
-                     [=](hipStream_t st) {
-                         launch_scan(st, SCAN_PMAP, c->bpred, g.nblocks, c->reg_idx, c->desc_pmap,
-                                     &c->misc->mtile_ctr, c->misc, 0);
-                     }});
     T.push_back({"scan_counts",
                  {{c->tile_cnt, ACC_R}, {c->tile_off, ACC_W}, {c->desc_cnt, ACC_RW}, {M.qctr, ACC_RW},
                   {M.flags, ACC_RED}},

@@ -160,6 +160,9 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
     // under the value-range bound the min/max pass has already flagged
     // non-finite input; the absolute bound has no such pass
     const bool check_finite = mode != 1;
+    // per-block choice whose map the map scan dropped (too few blocks off
+    // first-order Lorenzo): every block first-order
+    const bool map_off = MODE == kQuantPred && fixed_pred < 0 && misc->map_off != 0;
     for (uint32_t i = t; i < (uint32_t)kBins; i += 256) H[i] = 0;
     if (MODE == kQuantTrial) {
         // reference code lengths; an unused code counts as kLmax + 1 bits
@@ -480,7 +483,11 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
                     }
                 }
             } else {
-                residual(PRED ? (fixed_pred >= 0 ? (uint32_t)fixed_pred : (blk ? (uint32_t)bpred[b] : 0u)) : 0u);
+                // a map dropped by the map scan (too few blocks off
+                // first-order Lorenzo) codes every block first-order
+                residual(PRED ? (fixed_pred >= 0 ? (uint32_t)fixed_pred
+                                                 : ((blk && !map_off) ? (uint32_t)bpred[b] : 0u))
+                              : 0u);
             }
         }
         if (MODE == kQuantTrial) {

@@ -78,10 +78,12 @@ __global__ __launch_bounds__(256) void k_scan(const void* __restrict__ in, uint3
                     if ((total & m) == m || (total >> 31) == m) atomicOr(&misc->flags, F_OVERFLOW);
                 } else if (KIND == SCAN_PMAP) {
                     // regression blocks decide where the chunk table starts;
-                    // with no block off first-order Lorenzo there is no map
+                    // the map (a quarter byte per block) is kept only when at
+                    // least one block in 64 leaves first-order Lorenzo, else
+                    // every block is coded first-order and there is no map
                     const uint64_t m = (1ull << 31) - 1;
-                    const uint64_t nreg = total & m;
-                    const bool map = (total >> 31) != 0;
+                    const bool map = 64 * (total >> 31) >= (uint64_t)n;
+                    const uint64_t nreg = map ? (total & m) : 0;
                     const Layout L = make_layout(n, map, nreg, 0, 0, 0);
                     misc->nreg = nreg;
                     misc->map_off = map ? 0u : 1u;

@@ -139,12 +139,13 @@ def test_round_trip_with_predictors(pred, shape, eb):
     y = oracle.decompress(c)
     assert np.abs(x.astype(np.float64) - y).max() <= h["eb_abs"]
     if not h["flags"] & 1:
-        # a per-block choice of first-order Lorenzo everywhere is written as
-        # a first-order container
+        # the map is kept only when at least one block in 64 leaves
+        # first-order Lorenzo; otherwise a first-order container
         want = pred
-        if pred == 3 and not choice.any():
+        nb = oracle.nblocks_of(shape)
+        if pred == 3 and 64 * int((choice != 0).sum()) < nb:
             want = 0
-        if pred == 4 and not oracle.trial(x, eb, 1)[0].any():
+        if pred == 4 and 64 * int((oracle.trial(x, eb, 1)[0] != 0).sum()) < nb:
             want = 0
         assert h["pred"] == want
         if pred == 2:
@@ -163,7 +164,9 @@ def test_trial_never_worse_than_fixed_by_reference_cost():
 
 def test_all_first_order_choice_is_a_first_order_container():
     # no map when every block keeps first-order Lorenzo: the same bytes as
-    # the first-order container, for the selector's and trial's choices
+    # the first-order container, for the selector's and trial's choices;
+    # likewise when fewer than one block in 64 leaves it (those blocks are
+    # coded first-order too)
     x = fields.grf((130, 70), seed=200)
     nb = oracle.nblocks_of(x.shape)
     for eb in (1e-2, 1e-4):
@@ -172,8 +175,16 @@ def test_all_first_order_choice_is_a_first_order_container():
         ch, _ = oracle.trial(x, eb, 1)
         if not ch.any():
             assert oracle.compress(x, eb, 1, pred=4) == ref
-    # one block off first-order keeps the map
+    # one block off first-order among the 27 keeps the map
     ch = np.zeros(nb, np.uint8)
     ch[3] = 1
     h = oracle.header(oracle.compress(x, 1e-2, 1, pred=3, choice=ch))
-    assert h["pred"] == 3
+    assert h["pred"] == 3 and nb == 27
+    # 3D, 512 blocks: 7 switched blocks (64 * 7 < 512) drop the map, 8 keep it
+    y = fields.grf((64, 64, 64), seed=201)
+    ch = np.zeros(512, np.uint8)
+    ch[:7] = 2
+    assert oracle.compress(y, 1e-3, 1, pred=3, choice=ch) == oracle.compress(y, 1e-3, 1, pred=0)
+    ch[7] = 1
+    h = oracle.header(oracle.compress(y, 1e-3, 1, pred=3, choice=ch))
+    assert h["pred"] == 3 and h["n_reg"] == 7
