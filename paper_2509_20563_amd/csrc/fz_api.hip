@@ -762,8 +762,9 @@ void decompress_tasks(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_ou
                                        (const int32_t*)(in + L.oval), c->oidx, nout, e2, d_out, vec, c->misc);
                      }});
     } else if (pred == FZ_PRED_INTERP || pred == FZ_PRED_GLOBAL) {
-        // residuals of every block, then the anchors and levels of the
-        // interpolation in place, then dequantised row stores
+        // residuals of every value (row-major), then the predictor's inverse
+        // over the whole field with dequantised row stores
+        const int rvec = (g.ndim == 1 || (g.n[0] & 3) == 0);  // the residual buffer is 256-byte aligned
         T.push_back({"decode",
                      {{in, ACC_R}, {c->off, ACC_R}, {c->lut, ACC_R}, {c->oidx, ACC_R}, {c->res, ACC_W},
                       {M.dec, ACC_RED}, {M.flags, ACC_RED}},
@@ -771,7 +772,7 @@ void decompress_tasks(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_ou
                          launch_decode_residuals(st, g, (const uint32_t*)(in + L.stream), words, c->off,
                                                  (const uint16_t*)(in + L.chunks), c->lut,
                                                  (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval),
-                                                 c->oidx, nout, c->res, c->misc);
+                                                 c->oidx, nout, c->res, rvec, c->misc);
                      }});
         const uint32_t max_grid = (uint32_t)c->n_cu * 8;
         if (pred == FZ_PRED_INTERP)

@@ -550,7 +550,7 @@ struct FastDec {
 // regression block adds its fixed-point plane to the residuals in place of
 // the prefix sums, and a second-order block writes its residuals (its row
 // stores carry first-order values that k_inverse_wave overwrites).
-template <int ND, bool RES, bool VEC, bool XT = false, bool MAP = false>
+template <int ND, bool RES, bool VEC, bool XT = false, bool MAP = false, bool ROW = false>
 __global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint32_t ib1, uint32_t nint,
                                                      const uint32_t* __restrict__ stream, uint64_t nwords,
                                                      const uint64_t* __restrict__ off,
@@ -630,7 +630,9 @@ __global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint3
         return cA + 128 - cX * (int64_t)(g.bs[0] - 1) + cY * (int64_t)(2 * ly - ((int32_t)g.bs[1] - 1)) +
                cZ * (int64_t)(2 * lz - ((int32_t)g.bs[2] - 1));
     };
-    auto deq = [&](int32_t q) -> float { return (float)((double)q * e2); };
+    // ROW (with RES): residuals as raw int32 bits, row-major, through the
+    // field's store path (out is the residual field)
+    auto deq = [&](int32_t q) -> float { return ROW ? __int_as_float(q) : (float)((double)q * e2); };
     auto store8 = [&](uint64_t idx, const int32_t* q) {
         if (VEC) {
             f32x4* p = reinterpret_cast<f32x4*>(out + idx);
@@ -679,7 +681,10 @@ __global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint3
                 int32_t d[8];
                 const uint32_t pos0 = pos_b + 8 * y + 64 * z;
                 fd.row8(LUT, pos0, d);
-                if (RES) {
+                if (RES && ROW) {
+                    const uint64_t yg = (uint64_t)iby * 8 + y, zg = (uint64_t)ibz * 8 + z;
+                    store8(x0 + (uint64_t)g.n[0] * (yg + (uint64_t)g.n[1] * zg), d);
+                } else if (RES) {
                     store_res(pos0, d);
                 } else {
                     int32_t rs = 0, q[8];
@@ -718,7 +723,9 @@ __global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint3
                 int32_t d[8];
                 const uint32_t pos0 = pos_b + 32 * y + 8 * x8;
                 fd.row8(LUT, pos0, d);
-                if (RES) {
+                if (RES && ROW) {
+                    store8(row + x8 * 8, d);
+                } else if (RES) {
                     store_res(pos0, d);
                 } else {
                     int32_t q[8];
@@ -752,7 +759,9 @@ __global__ __launch_bounds__(256) void k_decode_fast(Geom g, uint32_t ib0, uint3
                 int32_t d[8];
                 const uint32_t i0s = 16 * s2 + 8 * h;
                 fd.row8(LUT, pos_b + i0s, d);
-                if (RES) {
+                if (RES && ROW) {
+                    store8(row + i0s, d);
+                } else if (RES) {
                     store_res(pos_b + i0s, d);
                 } else {
                     int32_t q[8];
@@ -809,7 +818,7 @@ __global__ __launch_bounds__(256) void k_decode_res(Geom g, const uint32_t* __re
                                                     const uint32_t* __restrict__ opos, const int32_t* __restrict__ oval,
                                                     const uint2* __restrict__ oidx, uint64_t n_out,
                                                     int32_t* __restrict__ res, Misc* misc, int skip, uint32_t ib0,
-                                                    uint32_t ib1, uint32_t ib2) {
+                                                    uint32_t ib1, uint32_t ib2, int rowmajor) {
     __shared__ uint16_t LUT[kLut];
     __shared__ uint32_t RING[kDecLanes * kRing];
     const uint32_t t = threadIdx.x;
@@ -832,7 +841,8 @@ __global__ __launch_bounds__(256) void k_decode_res(Geom g, const uint32_t* __re
     bool bad = false;
     const uint32_t pos_b = b * kBlockElems;
     if (active) {
-        // rows of 8 along x in block order; residuals stored block-major
+        // rows of 8 along x in block order; residuals stored block-major, or
+        // row-major (the real values only)
         for (uint32_t lz = 0; lz < info.ez; lz++)
             for (uint32_t ly = 0; ly < info.ey; ly++)
                 for (uint32_t lx0 = 0; lx0 < info.ex; lx0 += 8) {
@@ -840,9 +850,16 @@ __global__ __launch_bounds__(256) void k_decode_res(Geom g, const uint32_t* __re
                     const uint32_t nv = min(8u, info.ex - lx0);
                     const uint32_t pos0 = pos_b + lx0 + g.bs[0] * (ly + g.bs[1] * lz);
                     dec_row8(ld, LUT, nv, pos0, oq, d);
-                    int4* dst = reinterpret_cast<int4*>(res + pos0);
-                    dst[0] = make_int4(d[0], d[1], d[2], d[3]);
-                    dst[1] = make_int4(d[4], d[5], d[6], d[7]);
+                    if (rowmajor) {
+                        const uint64_t o = (uint64_t)info.bx * g.bs[0] + lx0 +
+                                           (uint64_t)g.n[0] * ((uint64_t)info.by * g.bs[1] + ly +
+                                                               (uint64_t)g.n[1] * ((uint64_t)info.bz * g.bs[2] + lz));
+                        for (uint32_t i = 0; i < nv; i++) res[o + i] = d[i];
+                    } else {
+                        int4* dst = reinterpret_cast<int4*>(res + pos0);
+                        dst[0] = make_int4(d[0], d[1], d[2], d[3]);
+                        dst[1] = make_int4(d[4], d[5], d[6], d[7]);
+                    }
                 }
     }
     if (active && ld.consumed(start) != chunks[b]) bad = true;
@@ -1156,7 +1173,7 @@ void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, u
 #define FZ_DRES(NDV)                                                                                                \
     if (I.n != g.nblocks)                                                                                           \
         hipLaunchKernelGGL(k_decode_res<NDV>, dim3(grid), dim3(256), 0, st, g, stream, stream_words, off, chunks,   \
-                           lut, opos, oval, oidx, n_out, res, misc, skip, I.ib[0], I.ib[1], I.ib[2]);            \
+                           lut, opos, oval, oidx, n_out, res, misc, skip, I.ib[0], I.ib[1], I.ib[2], 0);         \
     hipLaunchKernelGGL(k_inverse_wave<NDV>, dim3(wg), dim3(256), 0, st, g, res, fixed_pred, bpred, reg_idx, coefs,  \
                        nreg, e2, out, vec, misc, I.ib[0], I.ib[1], I.ib[2], fused ? 1 : 0)
     if (g.ndim == 3) {
@@ -1171,17 +1188,29 @@ void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, u
 
 void launch_decode_residuals(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,
                              const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
-                             const int32_t* oval, const uint2* oidx, uint64_t n_out, int32_t* res, Misc* misc) {
+                             const int32_t* oval, const uint2* oidx, uint64_t n_out, int32_t* res, int vec,
+                             Misc* misc) {
+    // row-major int32 residuals through the field's store path (staged row
+    // stores where a wave covers one run of 64 blocks along x)
     const Interior I = interior_of(g);
+    float* rf = reinterpret_cast<float*>(res);
     if (I.n) {
         const uint32_t fg = (I.n + 255) / 256;
 #define FZ_ARGS                                                                                                     \
     dim3(fg), dim3(256), 0, st, g, I.ib[0], I.ib[1], I.n, stream, stream_words, off, chunks, lut, oval, oidx, n_out, \
-        0.0, (float*)nullptr, res, misc, 0, (const uint8_t*)nullptr, (const uint64_t*)nullptr,                     \
+        0.0, rf, (int32_t*)nullptr, misc, 0, (const uint8_t*)nullptr, (const uint64_t*)nullptr,                    \
         (const int32_t*)nullptr, (uint64_t)0
-        if (g.ndim == 3) hipLaunchKernelGGL((k_decode_fast<3, true, false>), FZ_ARGS);
-        else if (g.ndim == 2) hipLaunchKernelGGL((k_decode_fast<2, true, false>), FZ_ARGS);
-        else hipLaunchKernelGGL((k_decode_fast<1, true, false>), FZ_ARGS);
+        if (vec && g.ndim == 3 && I.ib[0] % 64 == 0)
+            hipLaunchKernelGGL((k_decode_fast<3, true, true, true, false, true>), FZ_ARGS);
+        else if (vec) {
+            if (g.ndim == 3) hipLaunchKernelGGL((k_decode_fast<3, true, true, false, false, true>), FZ_ARGS);
+            else if (g.ndim == 2) hipLaunchKernelGGL((k_decode_fast<2, true, true, false, false, true>), FZ_ARGS);
+            else hipLaunchKernelGGL((k_decode_fast<1, true, true, false, false, true>), FZ_ARGS);
+        } else {
+            if (g.ndim == 3) hipLaunchKernelGGL((k_decode_fast<3, true, false, false, false, true>), FZ_ARGS);
+            else if (g.ndim == 2) hipLaunchKernelGGL((k_decode_fast<2, true, false, false, false, true>), FZ_ARGS);
+            else hipLaunchKernelGGL((k_decode_fast<1, true, false, false, false, true>), FZ_ARGS);
+        }
 #undef FZ_ARGS
     }
     if (I.n == g.nblocks) return;
@@ -1189,7 +1218,7 @@ void launch_decode_residuals(hipStream_t st, const Geom& g, const uint32_t* stre
     const int skip = I.n ? 1 : 0;
 #define FZ_DRES(NDV)                                                                                              \
     hipLaunchKernelGGL(k_decode_res<NDV>, dim3(grid), dim3(256), 0, st, g, stream, stream_words, off, chunks, lut, \
-                       opos, oval, oidx, n_out, res, misc, skip, I.ib[0], I.ib[1], I.ib[2])
+                       opos, oval, oidx, n_out, res, misc, skip, I.ib[0], I.ib[1], I.ib[2], 1)
     if (g.ndim == 3) FZ_DRES(3);
     else if (g.ndim == 2) FZ_DRES(2);
     else FZ_DRES(1);

@@ -1,6 +1,6 @@
 // Decoding of the interpolation predictor (FZMod-Quality pipeline, Sec. 3.3:
 // the G-Interp interpolator in place of Lorenzo).  The Huffman decoders
-// leave the residuals of every value in the block-major residual field;
+// leave the residuals of every value in the row-major residual field;
 // these kernels turn them into grid values in place, in the order the
 // prediction needs (fz_common.h, interp_predict):
 //   k_interp_anchor - prefix sums along one axis of the anchor grid (every
@@ -10,25 +10,16 @@
 //                     the z- and y-pass points of a halo of 2 lattice steps
 //   k_interp_level  - 1D/2D: the points of one stride and axis, one thread
 //                     per point, in place
-//   k_interp_store  - 1D/2D: dequantisation, block-major grid values to the
-//                     row-major field
+//   k_interp_store  - 1D/2D: dequantisation
 #include "fz_common.h"
 #include "fz_kernels.h"
 
 namespace fz {
 
-// Position of (x, y, z) in the block-major residual field.
+// Position of (x, y, z) in the row-major residual and grid-value fields.
 template <int ND>
-__device__ __forceinline__ uint64_t bm_index(const Geom& g, uint32_t x, uint32_t y, uint32_t z) {
-    if (ND == 3) {
-        const uint32_t b = (x >> 3) + g.nb[0] * ((y >> 3) + g.nb[1] * (z >> 3));
-        return (uint64_t)b * kBlockElems + ((x & 7u) + 8u * ((y & 7u) + 8u * (z & 7u)));
-    }
-    if (ND == 2) {
-        const uint32_t b = (x >> 5) + g.nb[0] * (y >> 4);
-        return (uint64_t)b * kBlockElems + ((x & 31u) + 32u * (y & 15u));
-    }
-    return (uint64_t)(x >> 9) * kBlockElems + (x & 511u);
+__device__ __forceinline__ uint64_t rm_index(const Geom& g, uint32_t x, uint32_t y, uint32_t z) {
+    return (uint64_t)x + (uint64_t)g.n[0] * ((uint64_t)y + (uint64_t)g.n[1] * z);
 }
 
 // Number of coordinates c < n with c = first + step k.
@@ -51,7 +42,7 @@ __global__ __launch_bounds__(256) void k_interp_anchor(Geom g, const int32_t* sr
         int32_t acc = 0;
         for (uint32_t k = 0; k < cnt[axis]; k++) {
             c[axis] = 8 * k;
-            const uint64_t i = bm_index<ND>(g, c[0], c[1], c[2]);
+            const uint64_t i = rm_index<ND>(g, c[0], c[1], c[2]);
             acc = (int32_t)((uint32_t)acc + (uint32_t)src[i]);
             dst[i] = acc;
         }
@@ -71,14 +62,14 @@ __global__ __launch_bounds__(256) void k_interp_level(Geom g, int32_t* __restric
     }
     const uint64_t npts = (uint64_t)cnt[0] * cnt[1] * cnt[2];
     const uint32_t n3[3] = {g.n[0], g.n[1], g.n[2]};
-    auto q_at = [&](uint32_t x, uint32_t y, uint32_t z) -> int32_t { return q[bm_index<ND>(g, x, y, z)]; };
+    auto q_at = [&](uint32_t x, uint32_t y, uint32_t z) -> int32_t { return q[rm_index<ND>(g, x, y, z)]; };
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npts; p += stride) {
         const uint32_t c[3] = {first[0] + step[0] * (uint32_t)(p % cnt[0]),
                                first[1] + step[1] * (uint32_t)((p / cnt[0]) % cnt[1]),
                                first[2] + step[2] * (uint32_t)(p / ((uint64_t)cnt[0] * cnt[1]))};
         const int32_t pred = interp_predict(c, n3, ND, q_at);
-        const uint64_t i = bm_index<ND>(g, c[0], c[1], c[2]);
+        const uint64_t i = rm_index<ND>(g, c[0], c[1], c[2]);
         q[i] = (int32_t)((uint32_t)q[i] + (uint32_t)pred);
     }
 }
@@ -121,7 +112,7 @@ __global__ __launch_bounds__(256) void k_interp_tile3(Geom g, const int32_t* __r
         for (uint32_t e = t; e < 343; e += 256) {
             const int32_t i = 2 * (int32_t)(e % 7) - 2, j = 2 * (int32_t)((e / 7) % 7) - 2, k = 2 * (int32_t)(e / 49) - 2;
             const int32_t x = X0 + (int32_t)S * i, y = Y0 + (int32_t)S * j, z = Z0 + (int32_t)S * k;
-            C[e] = inside(x, y, z) ? V[bm_index<3>(g, x, y, z)] : 0;
+            C[e] = inside(x, y, z) ? V[rm_index<3>(g, x, y, z)] : 0;
         }
         __syncthreads();
         // z pass
@@ -135,7 +126,7 @@ __global__ __launch_bounds__(256) void k_interp_tile3(Geom g, const int32_t* __r
                 const uint32_t cc = e % 49, ko = e / 49;
                 const int32_t m3 = C[ko * 49 + cc], m1 = C[(ko + 1) * 49 + cc], p1 = C[(ko + 2) * 49 + cc],
                               p3 = C[(ko + 3) * 49 + cc];
-                v = (int32_t)((uint32_t)R[bm_index<3>(g, x, y, z)] +
+                v = (int32_t)((uint32_t)R[rm_index<3>(g, x, y, z)] +
                               (uint32_t)pick_pred((uint32_t)z, g.n[2], S, m3, m1, p1, p3));
             }
             Z[e] = v;
@@ -158,7 +149,7 @@ __global__ __launch_bounds__(256) void k_interp_tile3(Geom g, const int32_t* __r
                     const uint32_t jj = (uint32_t)jo + (uint32_t)q;
                     nb[q] = (k & 1) ? Z[((uint32_t)(k - 1) / 2) * 49 + jj * 7 + ii] : C[((uint32_t)(k + 2) / 2) * 49 + jj * 7 + ii];
                 }
-                v = (int32_t)((uint32_t)R[bm_index<3>(g, x, y, z)] +
+                v = (int32_t)((uint32_t)R[rm_index<3>(g, x, y, z)] +
                               (uint32_t)pick_pred((uint32_t)y, g.n[1], S, nb[0], nb[1], nb[2], nb[3]));
             }
             Y[e] = v;
@@ -178,10 +169,10 @@ __global__ __launch_bounds__(256) void k_interp_tile3(Geom g, const int32_t* __r
                     else if (k & 1) nb[q] = Z[((k - 1) / 2) * 49 + ((j + 2) / 2) * 7 + ii];
                     else nb[q] = C[((k + 2) / 2) * 49 + ((j + 2) / 2) * 7 + ii];
                 }
-                const int32_t v = (int32_t)((uint32_t)R[bm_index<3>(g, x, y, z)] +
+                const int32_t v = (int32_t)((uint32_t)R[rm_index<3>(g, x, y, z)] +
                                             (uint32_t)pick_pred((uint32_t)x, g.n[0], S, nb[0], nb[1], nb[2], nb[3]));
                 if (S == 1) T[i + 8 * (j + 8 * k)] = v;
-                else V[bm_index<3>(g, x, y, z)] = v;
+                else V[rm_index<3>(g, x, y, z)] = v;
             }
         }
         if (S == 1) {
@@ -221,12 +212,12 @@ __global__ __launch_bounds__(256) void k_interp_tile3(Geom g, const int32_t* __r
             if (t < 64) {
                 const uint32_t i = 2 * (t % 4), j = 2 * ((t / 4) % 4), k = 2 * (t / 16) + 1;
                 const int32_t x = X0 + (int32_t)(S * i), y = Y0 + (int32_t)(S * j), z = Z0 + (int32_t)(S * k);
-                if (inside(x, y, z)) V[bm_index<3>(g, x, y, z)] = Z[((k - 1) / 2) * 49 + ((j + 2) / 2) * 7 + (i + 2) / 2];
+                if (inside(x, y, z)) V[rm_index<3>(g, x, y, z)] = Z[((k - 1) / 2) * 49 + ((j + 2) / 2) * 7 + (i + 2) / 2];
             } else if (t < 192) {
                 const uint32_t e = t - 64;
                 const uint32_t i = 2 * (e % 4), j = 2 * ((e / 4) % 4) + 1, k = e / 16;
                 const int32_t x = X0 + (int32_t)(S * i), y = Y0 + (int32_t)(S * j), z = Z0 + (int32_t)(S * k);
-                if (inside(x, y, z)) V[bm_index<3>(g, x, y, z)] = Y[k * 28 + ((j - 1) / 2) * 7 + (i + 2) / 2];
+                if (inside(x, y, z)) V[rm_index<3>(g, x, y, z)] = Y[k * 28 + ((j - 1) / 2) * 7 + (i + 2) / 2];
             }
         }
         __syncthreads();
@@ -238,10 +229,7 @@ __global__ __launch_bounds__(256) void k_interp_store(Geom g, const int32_t* __r
                                                       float* __restrict__ out) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.N; i += stride) {
-        const uint32_t x = (uint32_t)(i % g.n[0]);
-        const uint64_t r = i / g.n[0];
-        const uint32_t y = (uint32_t)(r % g.n[1]), z = (uint32_t)(r / g.n[1]);
-        out[i] = (float)((double)q[bm_index<ND>(g, x, y, z)] * e2);
+        out[i] = (float)((double)q[i] * e2);
     }
 }
 

@@ -87,16 +87,19 @@ void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, u
                         const int32_t* oval, const uint2* oidx, uint64_t n_out, int32_t* res,
                         int fixed_pred, const uint8_t* bpred, const uint64_t* reg_idx, const int32_t* coefs,
                         uint64_t nreg, double e2, float* out, int vec, Misc* misc);
-// residuals only (block-major int32), for the interpolation predictor
+// residuals only (row-major int32, N values), for the whole-field
+// predictors (interpolation, global Lorenzo); vec: res 16-byte aligned and
+// rows a multiple of 4 values
 void launch_decode_residuals(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t stream_words,
                              const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
-                             const int32_t* oval, const uint2* oidx, uint64_t n_out, int32_t* res, Misc* misc);
-// fz_interp.hip: residuals q (block-major) to grid values, then dequantised
-// row-major floats; 3D uses v (block-major) for the coarse levels and leaves
+                             const int32_t* oval, const uint2* oidx, uint64_t n_out, int32_t* res, int vec,
+                             Misc* misc);
+// fz_interp.hip: residuals q (row-major) to grid values, then dequantised
+// row-major floats; 3D uses v (row-major) for the coarse levels and leaves
 // q unchanged, 1D/2D work in place on q
 void launch_interp_inverse(hipStream_t st, const Geom& g, int32_t* q, int32_t* v, double e2, float* out, int vec,
                            uint32_t max_grid);
-// fz_global.hip: residuals q (block-major, in place) of the global Lorenzo
+// fz_global.hip: residuals q (row-major, in place) of the global Lorenzo
 // predictor to dequantised row-major floats; 1D uses desc (look-back
 // descriptors, global_scan_tiles(N) of them) and misc->mtile_ctr
 uint32_t global_scan_tiles(uint64_t N);

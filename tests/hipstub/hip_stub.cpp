@@ -489,7 +489,7 @@ void launch_decode_pred(hipStream_t st, const Geom& g, const uint32_t* stream, u
 }
 void launch_decode_residuals(hipStream_t st, const Geom& g, const uint32_t* stream, uint64_t words,
                              const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
-                             const int32_t* oval, const uint2* oidx, uint64_t n_out, int32_t* res, Misc* misc) {
+                             const int32_t* oval, const uint2* oidx, uint64_t n_out, int32_t* res, int, Misc* misc) {
     K("decode_residuals", {stream, 4 * words}, {off, 8ull * g.nblocks}, {chunks, 2ull * g.nblocks},
       {lut, 2ull * kLut}, {opos, 4 * n_out}, {oval, 4 * n_out}, {oidx, 8ull * g.nblocks},
       {res, 4ull * g.nblocks * kBlockElems}, {misc, sizeof(Misc)});
