@@ -151,10 +151,9 @@ struct fz_ctx {
     uint8_t* lens_ref = nullptr;  // kBins / 2 bytes
     uint64_t* desc_pmap = nullptr;
     int32_t* res = nullptr;
-    int32_t* ival = nullptr;  // interpolation decode: grid values of the coarse levels
     uint64_t* gdesc = nullptr;  // global Lorenzo decode (1D): look-back descriptors
     uint64_t gdesc_cap = 0;
-    uint64_t bpred_cap = 0, reg_idx_cap = 0, coef_cap = 0, costs_cap = 0, desc_pmap_cap = 0, res_cap = 0, ival_cap = 0;
+    uint64_t bpred_cap = 0, reg_idx_cap = 0, coef_cap = 0, costs_cap = 0, desc_pmap_cap = 0, res_cap = 0;
     // block features of the learned selector ([nblocks][16] float)
     float* featb = nullptr;
     uint64_t featb_cap = 0;
@@ -668,9 +667,6 @@ int decompress_prepare(fz_ctx* c, const Parsed& r) {
     if (r.verbatim) return FZ_OK;
     int rc = ensure(c, r.g);
     if (rc == FZ_OK && r.p.pred != FZ_PRED_LORENZO1) rc = ensure_pred(c, r.g, true);
-    if (rc == FZ_OK && r.p.pred == FZ_PRED_INTERP && r.g.ndim == 3 &&
-        grow(c->ival, c->ival_cap, (uint64_t)r.g.nblocks * kBlockElems) != hipSuccess)
-        rc = FZ_ERR_NOMEM;
     if (rc == FZ_OK && r.p.pred == FZ_PRED_GLOBAL && r.g.ndim == 1 &&
         grow(c->gdesc, c->gdesc_cap, global_scan_tiles(r.g.N)) != hipSuccess)
         rc = FZ_ERR_NOMEM;
@@ -774,11 +770,9 @@ void decompress_tasks(fz_ctx* c, const Parsed& r, const uint8_t* in, float* d_ou
                                                  (const uint32_t*)(in + L.opos), (const int32_t*)(in + L.oval),
                                                  c->oidx, nout, c->res, rvec, c->misc);
                      }});
-        const uint32_t max_grid = (uint32_t)c->n_cu * 8;
         if (pred == FZ_PRED_INTERP)
-            T.push_back({"interp", {{c->res, ACC_RW}, {c->ival, ACC_W}, {d_out, ACC_W}}, [=](hipStream_t st) {
-                             launch_interp_inverse(st, g, c->res, c->ival, e2, d_out, vec, max_grid);
-                         }});
+            T.push_back({"interp", {{c->res, ACC_RW}, {d_out, ACC_W}},
+                         [=](hipStream_t st) { launch_interp_inverse(st, g, c->res, e2, d_out); }});
         else
             // prefix sums along every axis of the whole field
             T.push_back({"inverse",
@@ -1000,7 +994,6 @@ void fz_ctx_destroy(fz_ctx* c) {
     if (c->cstream) hipStreamDestroy(c->cstream);
     hipFree(c->desc_pmap);
     hipFree(c->res);
-    hipFree(c->ival);
     hipFree(c->gdesc);
     if (c->h_misc) hipHostFree(c->h_misc);
     if (c->h_hdr) hipHostFree(c->h_hdr);

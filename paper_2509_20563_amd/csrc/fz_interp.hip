@@ -2,15 +2,17 @@
 // the G-Interp interpolator in place of Lorenzo).  The Huffman decoders
 // leave the residuals of every value in the row-major residual field;
 // these kernels turn them into grid values in place, in the order the
-// prediction needs (fz_common.h, interp_predict):
-//   k_interp_anchor - prefix sums along one axis of the anchor grid (every
-//                     coordinate a multiple of 8), one thread per line
-//   k_interp_tile3  - 3D: one level (stride 4, 2 or 1) per launch, tiles of
-//                     8^3 lattice points in LDS with the coarser values and
-//                     the z- and y-pass points of a halo of 2 lattice steps
-//   k_interp_level  - 1D/2D: the points of one stride and axis, one thread
-//                     per point, in place
-//   k_interp_store  - 1D/2D: dequantisation
+// prediction needs (fz_common.h, interp_predict), one launch per stride and
+// axis:
+//   k_interp_anchor  - prefix sums along one axis of the anchor grid (every
+//                      coordinate a multiple of 8), one thread per line
+//   k_interp_level   - strides 4 and 2: the points of one stride and axis,
+//                      one thread per point
+//   k_interp_pairs   - stride 1, z and y passes: a thread per pair of
+//                      points (2m, 2m + 1) of a row (the even one is the
+//                      level's point), so that stores cover whole lines
+//   k_interp_final_x - stride 1, x pass: the odd point of each pair, and
+//                      both values of the pair dequantised to the output
 #include "fz_common.h"
 #include "fz_kernels.h"
 
@@ -49,43 +51,9 @@ __global__ __launch_bounds__(256) void k_interp_anchor(Geom g, const int32_t* sr
     }
 }
 
-template <int ND>
-__global__ __launch_bounds__(256) void k_interp_level(Geom g, int32_t* __restrict__ q, uint32_t s, int axis) {
-    // points interpolated along `axis` at stride s: an odd multiple of s on
-    // that axis, even multiples (of 2s) on the axes before it in x, y, z
-    // order, any multiple of s on the axes after it
-    uint32_t first[3] = {0, 0, 0}, step[3] = {1, 1, 1}, cnt[3] = {1, 1, 1};
-    for (int a = 0; a < ND; a++) {
-        first[a] = a == axis ? s : 0u;
-        step[a] = a <= axis ? 2 * s : s;
-        cnt[a] = n_coords(g.n[a], first[a], step[a]);
-    }
-    const uint64_t npts = (uint64_t)cnt[0] * cnt[1] * cnt[2];
-    const uint32_t n3[3] = {g.n[0], g.n[1], g.n[2]};
-    auto q_at = [&](uint32_t x, uint32_t y, uint32_t z) -> int32_t { return q[rm_index<ND>(g, x, y, z)]; };
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npts; p += stride) {
-        const uint32_t c[3] = {first[0] + step[0] * (uint32_t)(p % cnt[0]),
-                               first[1] + step[1] * (uint32_t)((p / cnt[0]) % cnt[1]),
-                               first[2] + step[2] * (uint32_t)(p / ((uint64_t)cnt[0] * cnt[1]))};
-        const int32_t pred = interp_predict(c, n3, ND, q_at);
-        const uint64_t i = rm_index<ND>(g, c[0], c[1], c[2]);
-        q[i] = (int32_t)((uint32_t)q[i] + (uint32_t)pred);
-    }
-}
-
-// 3D: one level of stride S on tiles of 8x8x8 lattice points (spacing S,
-// the box [X0, X0 + 8S) per axis), one workgroup per tile.  The level's
-// points are those with an odd lattice coordinate; lattice points with all
-// coordinates even are the coarser levels (final in V).  In LDS:
-//   C  coarse values at even lattice coordinates -2..10 on every axis
-//   Z  the z-pass points (i, j even in -2..10, k odd in 1..7), rebuilt here
-//      also where they lie outside the tile (the y and x passes read them)
-//   Y  the y-pass points (i even in -2..10, j odd in 1..7, k in 0..7)
-// then the x-pass points of the tile.  Residuals come from R (read-only
-// here, so rebuilding a neighbour tile's points races with nothing); the
-// tile's own points go to V (S > 1) or, at S = 1, every value of the tile
-// (one 8^3 block) is dequantised into row-major floats.
+// Prediction of a point at coordinate c along its axis (field extent n,
+// stride s) from the neighbours at -3s, -s, +s, +3s (those outside the
+// field are not used).
 __device__ __forceinline__ int32_t pick_pred(uint32_t c, uint32_t n, uint32_t s, int32_t m3, int32_t m1, int32_t p1,
                                              int32_t p3) {
     if (c >= 3 * s && c + 3 * s < n) return (int32_t)((-(int64_t)m3 + 9 * (int64_t)m1 + 9 * (int64_t)p1 - (int64_t)p3 + 8) >> 4);
@@ -93,143 +61,104 @@ __device__ __forceinline__ int32_t pick_pred(uint32_t c, uint32_t n, uint32_t s,
     return m1;
 }
 
-template <uint32_t S>
-__global__ __launch_bounds__(256) void k_interp_tile3(Geom g, const int32_t* __restrict__ R, int32_t* __restrict__ V,
-                                                      double e2, float* __restrict__ out, uint32_t ntx, uint32_t nty,
-                                                      uint32_t ntiles, int vec) {
-    __shared__ int32_t C[343];
-    __shared__ int32_t Z[196];
-    __shared__ int32_t Y[224];
-    __shared__ int32_t T[S == 1 ? 512 : 1];
-    const uint32_t t = threadIdx.x;
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t tx = tile % ntx, r1 = tile / ntx, ty = r1 % nty, tz = r1 / nty;
-        const int32_t X0 = (int32_t)(tx * 8 * S), Y0 = (int32_t)(ty * 8 * S), Z0 = (int32_t)(tz * 8 * S);
-        auto inside = [&](int32_t x, int32_t y, int32_t z) {
-            return x >= 0 && y >= 0 && z >= 0 && (uint32_t)x < g.n[0] && (uint32_t)y < g.n[1] && (uint32_t)z < g.n[2];
-        };
-        // coarse values
-        for (uint32_t e = t; e < 343; e += 256) {
-            const int32_t i = 2 * (int32_t)(e % 7) - 2, j = 2 * (int32_t)((e / 7) % 7) - 2, k = 2 * (int32_t)(e / 49) - 2;
-            const int32_t x = X0 + (int32_t)S * i, y = Y0 + (int32_t)S * j, z = Z0 + (int32_t)S * k;
-            C[e] = inside(x, y, z) ? V[rm_index<3>(g, x, y, z)] : 0;
-        }
-        __syncthreads();
-        // z pass
-        if (t < 196) {
-            const uint32_t e = t;
-            const int32_t i = 2 * (int32_t)(e % 7) - 2, j = 2 * (int32_t)((e / 7) % 7) - 2, k = 2 * (int32_t)(e / 49) + 1;
-            const int32_t x = X0 + (int32_t)S * i, y = Y0 + (int32_t)S * j, z = Z0 + (int32_t)S * k;
-            int32_t v = 0;
-            if (inside(x, y, z)) {
-                // planes k - 3, k - 1, k + 1, k + 3 are C planes ko .. ko + 3
-                const uint32_t cc = e % 49, ko = e / 49;
-                const int32_t m3 = C[ko * 49 + cc], m1 = C[(ko + 1) * 49 + cc], p1 = C[(ko + 2) * 49 + cc],
-                              p3 = C[(ko + 3) * 49 + cc];
-                v = (int32_t)((uint32_t)R[rm_index<3>(g, x, y, z)] +
-                              (uint32_t)pick_pred((uint32_t)z, g.n[2], S, m3, m1, p1, p3));
-            }
-            Z[e] = v;
-        }
-        __syncthreads();
-        // y pass
-        if (t < 224) {
-            const uint32_t e = t;
-            const int32_t i = 2 * (int32_t)(e % 7) - 2, jo = (int32_t)((e / 7) % 4), k = (int32_t)(e / 28);
-            const int32_t j = 2 * jo + 1;
-            const int32_t x = X0 + (int32_t)S * i, y = Y0 + (int32_t)S * j, z = Z0 + (int32_t)S * k;
-            int32_t v = 0;
-            if (inside(x, y, z)) {
-                const uint32_t ii = e % 7;
-                // rows j - 3, j - 1, j + 1, j + 3 are even rows jo .. jo + 3
-                // (numbered from -2)
-                int32_t nb[4];
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const uint32_t jj = (uint32_t)jo + (uint32_t)q;
-                    nb[q] = (k & 1) ? Z[((uint32_t)(k - 1) / 2) * 49 + jj * 7 + ii] : C[((uint32_t)(k + 2) / 2) * 49 + jj * 7 + ii];
-                }
-                v = (int32_t)((uint32_t)R[rm_index<3>(g, x, y, z)] +
-                              (uint32_t)pick_pred((uint32_t)y, g.n[1], S, nb[0], nb[1], nb[2], nb[3]));
-            }
-            Y[e] = v;
-        }
-        __syncthreads();
-        // x pass: the tile's own points (i odd)
-        {
-            const uint32_t io = t % 4, j = (t / 4) % 8, k = t / 32;
-            const int32_t i = 2 * (int32_t)io + 1;
-            const int32_t x = X0 + (int32_t)S * i, y = Y0 + (int32_t)S * (int32_t)j, z = Z0 + (int32_t)S * (int32_t)k;
-            if (inside(x, y, z)) {
-                int32_t nb[4];
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const uint32_t ii = io + (uint32_t)q;  // i - 3 + 2 q in the -2..10 numbering
-                    if (j & 1) nb[q] = Y[k * 28 + ((j - 1) / 2) * 7 + ii];
-                    else if (k & 1) nb[q] = Z[((k - 1) / 2) * 49 + ((j + 2) / 2) * 7 + ii];
-                    else nb[q] = C[((k + 2) / 2) * 49 + ((j + 2) / 2) * 7 + ii];
-                }
-                const int32_t v = (int32_t)((uint32_t)R[rm_index<3>(g, x, y, z)] +
-                                            (uint32_t)pick_pred((uint32_t)x, g.n[0], S, nb[0], nb[1], nb[2], nb[3]));
-                if (S == 1) T[i + 8 * (j + 8 * k)] = v;
-                else V[rm_index<3>(g, x, y, z)] = v;
-            }
-        }
-        if (S == 1) {
-            // the tile's coarse, z- and y-pass values into T
-            if (t < 64) {
-                const uint32_t i = 2 * (t % 4), j = 2 * ((t / 4) % 4), k = 2 * (t / 16);
-                T[i + 8 * (j + 8 * k)] = C[((k + 2) / 2) * 49 + ((j + 2) / 2) * 7 + (i + 2) / 2];
-            } else if (t < 128) {
-                const uint32_t e = t - 64;
-                const uint32_t i = 2 * (e % 4), j = 2 * ((e / 4) % 4), k = 2 * (e / 16) + 1;
-                T[i + 8 * (j + 8 * k)] = Z[((k - 1) / 2) * 49 + ((j + 2) / 2) * 7 + (i + 2) / 2];
-            } else {
-                const uint32_t e = t - 128;  // 128 y-pass points of the tile
-                const uint32_t i = 2 * (e % 4), j = 2 * ((e / 4) % 4) + 1, k = e / 16;
-                T[i + 8 * (j + 8 * k)] = Y[k * 28 + ((j - 1) / 2) * 7 + (i + 2) / 2];
-            }
-            __syncthreads();
-            // rows of 8 floats: thread = half row
-            if (t < 128) {
-                const uint32_t row = t / 2, h = t % 2;
-                const uint32_t y = (uint32_t)Y0 + row % 8, z = (uint32_t)Z0 + row / 8;
-                const uint32_t x = (uint32_t)X0 + 4 * h;
-                if (y < g.n[1] && z < g.n[2] && x < g.n[0]) {
-                    const int32_t* src = &T[4 * h + 8 * row];
-                    const uint64_t o = (uint64_t)x + (uint64_t)g.n[0] * ((uint64_t)y + (uint64_t)g.n[1] * z);
-                    auto dq = [&](int32_t q) { return (float)((double)q * e2); };
-                    if (vec && x + 4 <= g.n[0]) {
-                        const f32x4 w = {dq(src[0]), dq(src[1]), dq(src[2]), dq(src[3])};
-                        __builtin_nontemporal_store(w, reinterpret_cast<f32x4*>(out + o));
-                    } else {
-                        for (uint32_t m = 0; m < 4 && x + m < g.n[0]; m++) out[o + m] = dq(src[m]);
-                    }
-                }
-            }
-        } else {
-            // the tile's own z- and y-pass points to V
-            if (t < 64) {
-                const uint32_t i = 2 * (t % 4), j = 2 * ((t / 4) % 4), k = 2 * (t / 16) + 1;
-                const int32_t x = X0 + (int32_t)(S * i), y = Y0 + (int32_t)(S * j), z = Z0 + (int32_t)(S * k);
-                if (inside(x, y, z)) V[rm_index<3>(g, x, y, z)] = Z[((k - 1) / 2) * 49 + ((j + 2) / 2) * 7 + (i + 2) / 2];
-            } else if (t < 192) {
-                const uint32_t e = t - 64;
-                const uint32_t i = 2 * (e % 4), j = 2 * ((e / 4) % 4) + 1, k = e / 16;
-                const int32_t x = X0 + (int32_t)(S * i), y = Y0 + (int32_t)(S * j), z = Z0 + (int32_t)(S * k);
-                if (inside(x, y, z)) V[rm_index<3>(g, x, y, z)] = Y[k * 28 + ((j - 1) / 2) * 7 + (i + 2) / 2];
-            }
-        }
-        __syncthreads();
+// The points of one stride s and axis AXIS (an odd multiple of s on that
+// axis, even multiples (of 2s) on the axes before it in x, y, z order, any
+// multiple of s on the axes after it), in place on the row-major grid
+// values: thread = one point, blockIdx.x along x, rows of (y, z) over
+// blockIdx.y; every neighbour along AXIS is a point rebuilt before.
+template <int AXIS>
+__global__ __launch_bounds__(256) void k_interp_level(Geom g, int32_t* __restrict__ q, uint32_t s, uint32_t f0,
+                                                      uint32_t s0, uint32_t c0, uint32_t f1, uint32_t s1, uint32_t c1,
+                                                      uint32_t f2, uint32_t s2, uint32_t nrows) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= c0) return;
+    const uint32_t x = f0 + s0 * i;
+    const uint64_t sa = AXIS == 0 ? 1ull : (AXIS == 1 ? (uint64_t)g.n[0] : (uint64_t)g.n[0] * g.n[1]);
+    for (uint32_t r = blockIdx.y; r < nrows; r += gridDim.y) {
+        const uint32_t j = r % c1, k = r / c1;
+        const uint32_t y = f1 + s1 * j, z = f2 + s2 * k;
+        const uint64_t idx = (uint64_t)x + (uint64_t)g.n[0] * ((uint64_t)y + (uint64_t)g.n[1] * z);
+        const uint32_t ca = AXIS == 0 ? x : (AXIS == 1 ? y : z), na = g.n[AXIS];
+        const uint64_t d1 = (uint64_t)s * sa, d3 = 3 * d1;
+        const int32_t m1 = q[idx - d1];
+        const int32_t p1 = ca + s < na ? q[idx + d1] : 0;
+        const int32_t m3 = ca >= 3 * s ? q[idx - d3] : 0;
+        const int32_t p3 = ca + 3 * s < na ? q[idx + d3] : 0;
+        q[idx] = (int32_t)((uint32_t)q[idx] + (uint32_t)pick_pred(ca, na, s, m3, m1, p1, p3));
     }
 }
 
-template <int ND>
-__global__ __launch_bounds__(256) void k_interp_store(Geom g, const int32_t* __restrict__ q, double e2,
-                                                      float* __restrict__ out) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.N; i += stride) {
-        out[i] = (float)((double)q[i] * e2);
+// Stride 1, the last level.  A thread takes the pair of points (2m, 2m + 1)
+// of a row, so that every store covers whole lines.  z and y passes (the
+// even point of the pair is the level's point, the odd one is rewritten
+// unchanged), in place:
+template <int AXIS>
+__global__ __launch_bounds__(256) void k_interp_pairs(Geom g, int32_t* __restrict__ q, uint32_t f1, uint32_t s1,
+                                                      uint32_t c1, uint32_t f2, uint32_t s2, uint32_t nrows) {
+    const uint32_t m = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t x = 2 * m;
+    if (x >= g.n[0]) return;
+    const bool two = x + 1 < g.n[0];
+    const bool v2 = two && (g.n[0] & 1) == 0;  // 8-byte aligned pairs
+    const uint64_t sa = AXIS == 1 ? (uint64_t)g.n[0] : (uint64_t)g.n[0] * g.n[1];
+    for (uint32_t r = blockIdx.y; r < nrows; r += gridDim.y) {
+        const uint32_t j = r % c1, k = r / c1;
+        const uint32_t y = f1 + s1 * j, z = f2 + s2 * k;
+        const uint64_t idx = (uint64_t)x + (uint64_t)g.n[0] * ((uint64_t)y + (uint64_t)g.n[1] * z);
+        const uint32_t ca = AXIS == 1 ? y : z, na = g.n[AXIS];
+        const int32_t m1 = q[idx - sa];
+        const int32_t p1 = ca + 1 < na ? q[idx + sa] : 0;
+        const int32_t m3 = ca >= 3 ? q[idx - 3 * sa] : 0;
+        const int32_t p3 = ca + 3 < na ? q[idx + 3 * sa] : 0;
+        const int32_t pr = pick_pred(ca, na, 1, m3, m1, p1, p3);
+        if (v2) {
+            int2 v = *reinterpret_cast<const int2*>(q + idx);
+            v.x = (int32_t)((uint32_t)v.x + (uint32_t)pr);
+            *reinterpret_cast<int2*>(q + idx) = v;
+        } else {
+            q[idx] = (int32_t)((uint32_t)q[idx] + (uint32_t)pr);
+        }
+    }
+}
+
+// the x pass (the odd point of each pair) with dequantisation: the pair
+// (even point final before this pass, odd point rebuilt here) goes to the
+// output as two floats, so this pass writes the whole field
+__global__ __launch_bounds__(256) void k_interp_final_x(Geom g, const int32_t* __restrict__ q, double e2,
+                                                        float* __restrict__ out, uint32_t nrows) {
+    const uint32_t m = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t x = 2 * m;
+    if (x >= g.n[0]) return;
+    const uint32_t n0 = g.n[0];
+    const bool two = x + 1 < n0;
+    const bool v2 = two && (n0 & 1) == 0;
+    auto dq = [&](int32_t v) { return (float)((double)v * e2); };
+    for (uint32_t r = blockIdx.y; r < nrows; r += gridDim.y) {
+        const uint64_t idx = (uint64_t)x + (uint64_t)n0 * r;
+        int32_t e0, o = 0;
+        if (v2) {
+            const int2 v = *reinterpret_cast<const int2*>(q + idx);
+            e0 = v.x;
+            o = v.y;
+        } else {
+            e0 = q[idx];
+            if (two) o = q[idx + 1];
+        }
+        if (two) {
+            const uint32_t ca = x + 1;
+            const int32_t p1 = ca + 1 < n0 ? q[idx + 2] : 0;
+            const int32_t m3 = ca >= 3 ? q[idx - 2] : 0;
+            const int32_t p3 = ca + 3 < n0 ? q[idx + 4] : 0;
+            o = (int32_t)((uint32_t)o + (uint32_t)pick_pred(ca, n0, 1, m3, e0, p1, p3));
+        }
+        if (v2) {
+            const float2 w = make_float2(dq(e0), dq(o));
+            __builtin_nontemporal_store(w.x, out + idx);
+            __builtin_nontemporal_store(w.y, out + idx + 1);
+        } else {
+            out[idx] = dq(e0);
+            if (two) out[idx + 1] = dq(o);
+        }
     }
 }
 
@@ -254,39 +183,51 @@ static void interp_anchors(hipStream_t st, const Geom& g, const int32_t* src, in
 template <int ND>
 static void interp_inverse_passes(hipStream_t st, const Geom& g, int32_t* q, double e2, float* out) {
     interp_anchors<ND>(st, g, q, q);
-    for (uint32_t s = 4; s >= 1; s >>= 1)
+    for (uint32_t s = 4; s >= 2; s >>= 1)
         for (int a = ND - 1; a >= 0; a--) {
-            // at most N / s points per pass
-            hipLaunchKernelGGL(k_interp_level<ND>, dim3(grid_for(g.N / s + 1)), dim3(256), 0, st, g, q, s, a);
+            uint32_t first[3] = {0, 0, 0}, step[3] = {1, 1, 1}, cnt[3] = {1, 1, 1};
+            for (int d = 0; d < ND; d++) {
+                first[d] = d == a ? s : 0u;
+                step[d] = d <= a ? 2 * s : s;
+                cnt[d] = g.n[d] > first[d] ? (g.n[d] - first[d] + step[d] - 1) / step[d] : 0u;
+            }
+            const uint64_t rows = (uint64_t)cnt[1] * cnt[2];
+            if (!cnt[0] || !rows) continue;
+            const dim3 grid((cnt[0] + 255) / 256, (uint32_t)(rows < 65535 ? rows : 65535));
+#define FZ_LEVEL(AX)                                                                                             \
+    hipLaunchKernelGGL(k_interp_level<AX>, grid, dim3(256), 0, st, g, q, s, first[0], step[0], cnt[0], first[1], \
+                       step[1], cnt[1], first[2], step[2], (uint32_t)rows)
+            if (a == 0) FZ_LEVEL(0);
+            else if (a == 1) FZ_LEVEL(1);
+            else FZ_LEVEL(2);
+#undef FZ_LEVEL
         }
-    hipLaunchKernelGGL(k_interp_store<ND>, dim3(grid_for(g.N)), dim3(256), 0, st, g, q, e2, out);
-}
-
-template <uint32_t S>
-static void launch_tile3(hipStream_t st, const Geom& g, const int32_t* R, int32_t* V, double e2, float* out, int vec,
-                         uint32_t max_grid) {
-    const uint32_t span = 8 * S;
-    const uint32_t ntx = (g.n[0] + span - 1) / span, nty = (g.n[1] + span - 1) / span,
-                   ntz = (g.n[2] + span - 1) / span;
-    const uint32_t ntiles = ntx * nty * ntz;
-    const uint32_t grid = ntiles < max_grid ? ntiles : max_grid;
-    hipLaunchKernelGGL(k_interp_tile3<S>, dim3(grid), dim3(256), 0, st, g, R, V, e2, out, ntx, nty, ntiles, vec);
-}
-
-void launch_interp_inverse(hipStream_t st, const Geom& g, int32_t* q, int32_t* v, double e2, float* out, int vec,
-                           uint32_t max_grid) {
-    if (g.ndim == 3) {
-        // anchors into V, then the levels of stride 4, 2 (into V) and 1
-        // (into the output)
-        interp_anchors<3>(st, g, q, v);
-        launch_tile3<4>(st, g, q, v, e2, out, vec, max_grid);
-        launch_tile3<2>(st, g, q, v, e2, out, vec, max_grid);
-        launch_tile3<1>(st, g, q, v, e2, out, vec, max_grid);
-    } else if (g.ndim == 2) {
-        interp_inverse_passes<2>(st, g, q, e2, out);
-    } else {
-        interp_inverse_passes<1>(st, g, q, e2, out);
+    // stride 1: pairs of points per thread; z (x, y even, z odd), y (x even,
+    // y odd), then x with the output
+    const uint32_t npairs = (g.n[0] + 1) / 2;
+    auto cap = [](uint64_t r) { return (uint32_t)(r < 65535 ? r : 65535); };
+    if (ND == 3 && g.n[2] > 1) {
+        const uint32_t c1 = (g.n[1] + 1) / 2, c2 = g.n[2] / 2;  // y even, z odd
+        const uint64_t rows = (uint64_t)c1 * c2;
+        if (rows)
+            hipLaunchKernelGGL(k_interp_pairs<2>, dim3((npairs + 255) / 256, cap(rows)), dim3(256), 0, st, g, q, 0u, 2u,
+                               c1, 1u, 2u, (uint32_t)rows);
     }
+    if (ND >= 2 && g.n[1] > 1) {
+        const uint32_t c1 = g.n[1] / 2, c2 = g.n[2];  // y odd, any z
+        const uint64_t rows = (uint64_t)c1 * c2;
+        hipLaunchKernelGGL(k_interp_pairs<1>, dim3((npairs + 255) / 256, cap(rows)), dim3(256), 0, st, g, q, 1u, 2u, c1,
+                           0u, 1u, (uint32_t)rows);
+    }
+    const uint64_t rows = (uint64_t)g.n[1] * g.n[2];
+    hipLaunchKernelGGL(k_interp_final_x, dim3((npairs + 255) / 256, cap(rows)), dim3(256), 0, st, g, q, e2, out,
+                       (uint32_t)rows);
+}
+
+void launch_interp_inverse(hipStream_t st, const Geom& g, int32_t* q, double e2, float* out) {
+    if (g.ndim == 3) interp_inverse_passes<3>(st, g, q, e2, out);
+    else if (g.ndim == 2) interp_inverse_passes<2>(st, g, q, e2, out);
+    else interp_inverse_passes<1>(st, g, q, e2, out);
 }
 
 }  // namespace fz

@@ -94,11 +94,9 @@ void launch_decode_residuals(hipStream_t st, const Geom& g, const uint32_t* stre
                              const uint64_t* off, const uint16_t* chunks, const uint16_t* lut, const uint32_t* opos,
                              const int32_t* oval, const uint2* oidx, uint64_t n_out, int32_t* res, int vec,
                              Misc* misc);
-// fz_interp.hip: residuals q (row-major) to grid values, then dequantised
-// row-major floats; 3D uses v (row-major) for the coarse levels and leaves
-// q unchanged, 1D/2D work in place on q
-void launch_interp_inverse(hipStream_t st, const Geom& g, int32_t* q, int32_t* v, double e2, float* out, int vec,
-                           uint32_t max_grid);
+// fz_interp.hip: residuals q (row-major) to grid values in place, then
+// dequantised row-major floats
+void launch_interp_inverse(hipStream_t st, const Geom& g, int32_t* q, double e2, float* out);
 // fz_global.hip: residuals q (row-major, in place) of the global Lorenzo
 // predictor to dequantised row-major floats; 1D uses desc (look-back
 // descriptors, global_scan_tiles(N) of them) and misc->mtile_ctr

@@ -500,9 +500,8 @@ void launch_global_inverse(hipStream_t st, const Geom& g, int32_t* q, uint64_t* 
     K("global_inverse", {q, 4ull * g.nblocks * kBlockElems}, {desc, g.ndim == 1 ? 8ull * global_scan_tiles(g.N) : 0ull},
       {misc, sizeof(Misc)}, {out, 4 * g.N});
 }
-void launch_interp_inverse(hipStream_t st, const Geom& g, int32_t* q, int32_t* v, double, float* out, int, uint32_t) {
-    K("interp_inverse", {q, 4ull * g.nblocks * kBlockElems}, {v, g.ndim == 3 ? 4ull * g.nblocks * kBlockElems : 0ull},
-      {out, 4 * g.N});
+void launch_interp_inverse(hipStream_t st, const Geom& g, int32_t* q, double, float* out) {
+    K("interp_inverse", {q, 4ull * g.N}, {out, 4 * g.N});
 }
 void launch_shuffle(hipStream_t st, const Geom& g, const uint16_t* codes, uint8_t* out, uint64_t limit,
                     uint64_t* desc, Misc* misc) {
