@@ -145,6 +145,14 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
     __shared__ uint32_t H[kBins];
     __shared__ uint32_t wsum[4];
     __shared__ uint8_t LREF[kBins];
+    // global Lorenzo: grid values just outside each block's lower faces (3D:
+    // the plane below in z, the row below in y for every z, their shared
+    // row; 2D: the row below), then the column left of the tile's first
+    // block (3D: its 9 x 9 (y, z) from -1; 2D: 17 y from -1; 1D: one value);
+    // zero outside the field
+    constexpr int kHB = ND == 3 ? 136 : (ND == 2 ? 32 : 0);
+    constexpr int kHL = ND == 3 ? 81 : (ND == 2 ? 17 : 1);
+    __shared__ int32_t HG[MODE == kQuantGlobal ? kTileBlocks * kHB + kHL : 1];
     // selector network, hidden-layer weights transposed (lane = unit)
 
     const uint32_t t = threadIdx.x;
@@ -242,6 +250,54 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
             dst[1] = make_int4(q[4], q[5], q[6], q[7]);
             PM[la_bi * kSegs + la_s] = (uint8_t)pm;
         }
+        if (MODE == kQuantGlobal) {
+            for (uint32_t e = t; e < (uint32_t)(kTileBlocks * kHB + kHL); e += 256) {
+                const bool left = e >= (uint32_t)(kTileBlocks * kHB);
+                const uint32_t bi = left ? 0u : e / (uint32_t)(kHB ? kHB : 1);
+                const uint32_t k = left ? e - kTileBlocks * kHB : e % (uint32_t)(kHB ? kHB : 1);
+                const uint32_t bk = tile * kTileBlocks + bi;
+                int32_t v = 0;
+                if (bk < g.nblocks) {
+                    const BlockInfo ik = block_info(g, bk);
+                    const int32_t X0 = (int32_t)(ik.bx * g.bs[0]), Y0 = (int32_t)(ik.by * g.bs[1]),
+                                  Z0 = (int32_t)(ik.bz * g.bs[2]);
+                    int32_t xx = X0, yy = Y0, zz = Z0;
+                    if (left) {
+                        xx = X0 - 1;
+                        if (ND == 3) {
+                            yy = Y0 + (int32_t)(k % 9) - 1;
+                            zz = Z0 + (int32_t)(k / 9) - 1;
+                        } else if (ND == 2) {
+                            yy = Y0 + (int32_t)k - 1;
+                        }
+                    } else if (ND == 3) {
+                        if (k < 64) {
+                            xx = X0 + (int32_t)(k & 7);
+                            yy = Y0 + (int32_t)(k >> 3);
+                            zz = Z0 - 1;
+                        } else if (k < 128) {
+                            xx = X0 + (int32_t)(k & 7);
+                            yy = Y0 - 1;
+                            zz = Z0 + (int32_t)((k - 64) >> 3);
+                        } else {
+                            xx = X0 + (int32_t)(k - 128);
+                            yy = Y0 - 1;
+                            zz = Z0 - 1;
+                        }
+                    } else {
+                        xx = X0 + (int32_t)k;
+                        yy = Y0 - 1;
+                    }
+                    if (xx >= 0 && yy >= 0 && zz >= 0 && (uint32_t)xx < g.n[0] && (uint32_t)yy < g.n[1] &&
+                        (uint32_t)zz < g.n[2]) {
+                        bool pq;
+                        v = prequant1(x[(uint64_t)xx + (uint64_t)g.n[0] * ((uint64_t)yy + (uint64_t)g.n[1] * zz)], e2,
+                                      inv, eb_abs, pq);
+                    }
+                }
+                HG[e] = v;
+            }
+        }
         __syncthreads();
         {
             const uint32_t nt = tile + gridDim.x;
@@ -299,24 +355,55 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
                     d[i] = (int32_t)((uint32_t)r0[i] - (uint32_t)pq);
                 }
             } else if (MODE == kQuantGlobal) {
-                // first-order Lorenzo over the whole field: the rows below
-                // the segment (y - 1, z - 1, both) and the value left of each
-                // row, from this block's LDS rows where they lie in the
-                // block, else through q_at; zero outside the field
-                const uint32_t X0 = info.bx * g.bs[0] + lx0, Y = info.by * g.bs[1] + ly, Z = info.bz * g.bs[2] + lz;
-                constexpr uint32_t kRowSeg = ND == 2 ? 4u : 1u;  // segment step of y - 1
+                // first-order Lorenzo over the whole field, every neighbour
+                // from LDS: this block's rows, the halo rows below its lower
+                // faces, and left of the segment the previous segment, the
+                // previous block of the tile or the tile's left column
+                const uint32_t bi = wave;
+                const int32_t* Hb = &HG[bi * kHB];
+                // row (y - dy, z - dz) of the lane's segment into r[1..8], the
+                // value left of it into r[0]
                 auto row9 = [&](uint32_t dy, uint32_t dz, int32_t r[9]) {
+                    const bool iny = dy <= ly, inz = dz <= lz;
+                    if (ND == 3) {
+                        const int32_t* src = (iny && inz) ? &Q[Qb + (s - dy - 8 * dz) * 8]
+                                             : (inz ? &Hb[64 + 8 * (lz - dz)]
+                                                    : (iny ? &Hb[8 * (ly - dy)] : &Hb[128]));
 #pragma unroll
-                    for (int i = 0; i < 9; i++) r[i] = 0;
-                    if (dy > Y || dz > Z || nv == 0) return;
-                    const uint32_t yy = Y - dy, zz = Z - dz;
-                    if (dy <= ly && dz <= lz) {
-                        read_row<ND>(Q, Qb + (s - dy * kRowSeg - dz * 8u) * 8, &r[1]);
+                        for (int i = 0; i < 8; i++) r[1 + i] = src[i];
+                        if (info.bx == 0) {
+                            r[0] = 0;
+                        } else if (bi > 0) {
+                            const uint32_t Qp = (bi - 1) * kQStride;
+                            const int32_t* Hp = &HG[(bi - 1) * kHB];
+                            r[0] = (iny && inz) ? Q[Qp + (s - dy - 8 * dz) * 8 + 7]
+                                                : (inz ? Hp[64 + 8 * (lz - dz) + 7]
+                                                       : (iny ? Hp[8 * (ly - dy) + 7] : Hp[135]));
+                        } else {
+                            r[0] = HG[kTileBlocks * kHB + (ly + 1 - dy) + 9 * (lz + 1 - dz)];
+                        }
+                    } else if (ND == 2) {
+                        const uint32_t sx = s & 3;
+                        const int32_t* src = iny ? &Q[Qb + (s - 4 * dy) * 8] : &Hb[8 * sx];
+#pragma unroll
+                        for (int i = 0; i < 8; i++) r[1 + i] = src[i];
+                        if (sx > 0) {
+                            r[0] = iny ? Q[Qb + (s - 4 * dy - 1) * 8 + 7] : Hb[8 * sx - 1];
+                        } else if (info.bx == 0) {
+                            r[0] = 0;
+                        } else if (bi > 0) {
+                            r[0] = iny ? Q[(bi - 1) * kQStride + (3 + 4 * (ly - dy)) * 8 + 7] : HG[(bi - 1) * kHB + 31];
+                        } else {
+                            r[0] = HG[kTileBlocks * kHB + (ly + 1 - dy)];
+                        }
                     } else {
 #pragma unroll
-                        for (int i = 0; i < 8; i++) r[1 + i] = (i < (int)nv) ? q_at(X0 + i, yy, zz) : 0;
+                        for (int i = 0; i < 8; i++) r[1 + i] = Q[Qb + s * 8 + i];
+                        if (s > 0) r[0] = Q[Qb + (s - 1) * 8 + 7];
+                        else if (info.bx == 0) r[0] = 0;
+                        else if (bi > 0) r[0] = Q[(bi - 1) * kQStride + 63 * 8 + 7];
+                        else r[0] = HG[0];
                     }
-                    if (X0 > 0) r[0] = q_at(X0 - 1, yy, zz);
                 };
                 int32_t A[9];
                 row9(0, 0, A);
