@@ -58,7 +58,7 @@ STAGE_KERNEL = {
     "compress:encode": ("fz::k_encode<3>", "fz_huffman.hip"),
     "compress:finalize": ("fz::k_finalize", "fz_huffman.hip"),
     "decompress:oindex": ("fz::k_outlier_index", "fz_decode.hip"),
-    "decompress:decode": ("fz::k_decode_fast<3, false, true, true, false>", "fz_decode.hip"),
+    "decompress:decode": ("fz::k_decode_fast<3, false, true, true, false, false>", "fz_decode.hip"),
 }
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_1024cubed_fronts_spikes.md")
 

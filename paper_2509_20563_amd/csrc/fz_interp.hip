@@ -152,9 +152,9 @@ __global__ __launch_bounds__(256) void k_interp_final_x(Geom g, const int32_t* _
             o = (int32_t)((uint32_t)o + (uint32_t)pick_pred(ca, n0, 1, m3, e0, p1, p3));
         }
         if (v2) {
-            const float2 w = make_float2(dq(e0), dq(o));
-            __builtin_nontemporal_store(w.x, out + idx);
-            __builtin_nontemporal_store(w.y, out + idx + 1);
+            typedef float f32x2 __attribute__((ext_vector_type(2)));
+            const f32x2 w = {dq(e0), dq(o)};
+            __builtin_nontemporal_store(w, reinterpret_cast<f32x2*>(out + idx));
         } else {
             out[idx] = dq(e0);
             if (two) out[idx + 1] = dq(o);
