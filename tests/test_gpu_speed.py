@@ -120,7 +120,7 @@ def test_speed_decode_noalloc_and_batch(fz, ctx):
 
 def test_speed_rejects_other_predictors(fz, ctx):
     x = torch.from_numpy(fields.grf((32, 32, 32), seed=4)).cuda()
-    for pred in (1, 2, 4):
+    for pred in (1, 2, 4, 5, 6):
         with pytest.raises(fz.FZError) as e:
             ctx.compress(x, 1e-3, 1, pred=pred, codec="shuffle")
         assert e.value.code == -8

@@ -77,7 +77,7 @@ def test_noalloc_verbatim(fz, ctx):
 def test_noalloc_rejects(fz, ctx):
     x = fields.random_small((32, 32, 32), 6, "smooth")
     d = torch.from_numpy(x).to("cuda:0")
-    for pred in (1, 2, 4):
+    for pred in (1, 2, 4, 5, 6):
         c = ctx.compress(d, 1e-3, 1, pred=pred)
         with pytest.raises(fz.FZError) as e:
             _noalloc(fz, c, x.size)
