@@ -8,11 +8,15 @@
 //                      coordinate a multiple of 8), one thread per line
 //   k_interp_level   - strides 4 and 2: the points of one stride and axis,
 //                      one thread per point
-//   k_interp_pairs   - stride 1, z and y passes: a thread per pair of
-//                      points (2m, 2m + 1) of a row (the even one is the
-//                      level's point), so that stores cover whole lines
-//   k_interp_final_x - stride 1, x pass: the odd point of each pair, and
-//                      both values of the pair dequantised to the output
+//   k_interp_pairs   - stride 1, z pass: a thread per pair of points
+//                      (2m, 2m + 1) of a row (the even one is the level's
+//                      point), so that stores cover whole lines
+//   k_interp_final_yx - stride 1, y and x passes of a row together (2D/3D):
+//                      the even points' y prediction, exchanged in LDS for
+//                      the odd points' x prediction, the pair dequantised
+//                      to the output
+//   k_interp_final_x - stride 1, x pass alone (1D, and fields one row
+//                      high)
 #include "fz_common.h"
 #include "fz_kernels.h"
 
@@ -89,8 +93,8 @@ __global__ __launch_bounds__(256) void k_interp_level(Geom g, int32_t* __restric
 }
 
 // Stride 1, the last level.  A thread takes the pair of points (2m, 2m + 1)
-// of a row, so that every store covers whole lines.  z and y passes (the
-// even point of the pair is the level's point, the odd one is rewritten
+// of a row, so that every store covers whole lines.  The z pass (the even
+// point of the pair is the level's point, the odd one is rewritten
 // unchanged), in place:
 template <int AXIS>
 __global__ __launch_bounds__(256) void k_interp_pairs(Geom g, int32_t* __restrict__ q, uint32_t f1, uint32_t s1,
@@ -121,7 +125,7 @@ __global__ __launch_bounds__(256) void k_interp_pairs(Geom g, int32_t* __restric
     }
 }
 
-// the x pass (the odd point of each pair) with dequantisation: the pair
+// the x pass alone (the odd point of each pair) with dequantisation: the pair
 // (even point final before this pass, odd point rebuilt here) goes to the
 // output as two floats, so this pass writes the whole field
 __global__ __launch_bounds__(256) void k_interp_final_x(Geom g, const int32_t* __restrict__ q, double e2,
@@ -159,6 +163,80 @@ __global__ __launch_bounds__(256) void k_interp_final_x(Geom g, const int32_t* _
             out[idx] = dq(e0);
             if (two) out[idx + 1] = dq(o);
         }
+    }
+}
+
+// Stride 1, the y and x passes of a row together (2D/3D, after the z
+// pass): workgroup = 256 pairs (512 values) of one row, rows over
+// blockIdx.y.  The even point of each pair is final in the grid values
+// for an even y and gets its y prediction (the rows y -/+ 1, 3, whose even
+// points are final) for an odd y; the even points go through LDS (with the
+// pairs just left and the two just right of the workgroup's range, rebuilt
+// by three lanes) to the x prediction of the odd points, and the pair is
+// written dequantised.  The grid values are only read.
+__global__ __launch_bounds__(256) void k_interp_final_yx(Geom g, const int32_t* __restrict__ q, double e2,
+                                                         float* __restrict__ out, uint32_t nrows) {
+    __shared__ int32_t E[256 + 3];  // even points of the pairs m0 - 1 .. m0 + 257
+    const uint32_t t = threadIdx.x;
+    const uint32_t n0 = g.n[0], n1 = g.n[1];
+    const uint32_t m0 = blockIdx.x * 256;
+    const uint32_t x = 2 * (m0 + t);
+    const bool in = x < n0;
+    const bool two = x + 1 < n0;
+    const bool v2 = two && (n0 & 1) == 0;
+    const uint64_t sy = n0;
+    auto dq = [&](int32_t v) { return (float)((double)v * e2); };
+    // halo lanes: 0 the pair left of the range, 1 and 2 the two right of it
+    const bool halo = t < 3;
+    const uint32_t hx = t == 0 ? 2 * m0 - 2 : 2 * (m0 + 255 + t);
+    const bool hin = halo && (t == 0 ? m0 > 0 : hx < n0);
+    for (uint32_t r = blockIdx.y; r < nrows; r += gridDim.y) {
+        const uint32_t y = r % n1;
+        const bool ypass = (y & 1) != 0;
+        const uint64_t rb = (uint64_t)n0 * r;
+        auto even_at = [&](uint32_t xx) -> int32_t {
+            const uint64_t i = rb + xx;
+            uint32_t v = (uint32_t)q[i];
+            if (ypass) {
+                const int32_t m1 = q[i - sy];
+                const int32_t p1 = y + 1 < n1 ? q[i + sy] : 0;
+                const int32_t m3 = y >= 3 ? q[i - 3 * sy] : 0;
+                const int32_t p3 = y + 3 < n1 ? q[i + 3 * sy] : 0;
+                v += (uint32_t)pick_pred(y, n1, 1, m3, m1, p1, p3);
+            }
+            return (int32_t)v;
+        };
+        int32_t e0 = 0, o = 0;
+        if (in) {
+            if (v2) {
+                const int2 v = *reinterpret_cast<const int2*>(q + rb + x);
+                e0 = v.x;
+                o = v.y;
+            } else {
+                e0 = q[rb + x];
+                if (two) o = q[rb + x + 1];
+            }
+            if (ypass) e0 = even_at(x);
+        }
+        E[1 + t] = e0;
+        if (halo) E[t == 0 ? 0 : 256 + t] = hin ? even_at(hx) : 0;
+        __syncthreads();
+        if (two) {
+            const uint32_t ca = x + 1;
+            const int32_t p1 = ca + 1 < n0 ? E[t + 2] : 0;
+            const int32_t m3 = ca >= 3 ? E[t] : 0;
+            const int32_t p3 = ca + 3 < n0 ? E[t + 3] : 0;
+            o = (int32_t)((uint32_t)o + (uint32_t)pick_pred(ca, n0, 1, m3, e0, p1, p3));
+        }
+        if (v2) {
+            typedef float f32x2 __attribute__((ext_vector_type(2)));
+            const f32x2 w = {dq(e0), dq(o)};
+            __builtin_nontemporal_store(w, reinterpret_cast<f32x2*>(out + rb + x));
+        } else if (in) {
+            out[rb + x] = dq(e0);
+            if (two) out[rb + x + 1] = dq(o);
+        }
+        __syncthreads();
     }
 }
 
@@ -202,8 +280,8 @@ static void interp_inverse_passes(hipStream_t st, const Geom& g, int32_t* q, dou
             else FZ_LEVEL(2);
 #undef FZ_LEVEL
         }
-    // stride 1: pairs of points per thread; z (x, y even, z odd), y (x even,
-    // y odd), then x with the output
+    // stride 1: pairs of points per thread; z (x, y even, z odd), then y
+    // (x even, y odd) and x together with the output
     const uint32_t npairs = (g.n[0] + 1) / 2;
     auto cap = [](uint64_t r) { return (uint32_t)(r < 65535 ? r : 65535); };
     if (ND == 3 && g.n[2] > 1) {
@@ -213,15 +291,15 @@ static void interp_inverse_passes(hipStream_t st, const Geom& g, int32_t* q, dou
             hipLaunchKernelGGL(k_interp_pairs<2>, dim3((npairs + 255) / 256, cap(rows)), dim3(256), 0, st, g, q, 0u, 2u,
                                c1, 1u, 2u, (uint32_t)rows);
     }
-    if (ND >= 2 && g.n[1] > 1) {
-        const uint32_t c1 = g.n[1] / 2, c2 = g.n[2];  // y odd, any z
-        const uint64_t rows = (uint64_t)c1 * c2;
-        hipLaunchKernelGGL(k_interp_pairs<1>, dim3((npairs + 255) / 256, cap(rows)), dim3(256), 0, st, g, q, 1u, 2u, c1,
-                           0u, 1u, (uint32_t)rows);
-    }
     const uint64_t rows = (uint64_t)g.n[1] * g.n[2];
-    hipLaunchKernelGGL(k_interp_final_x, dim3((npairs + 255) / 256, cap(rows)), dim3(256), 0, st, g, q, e2, out,
-                       (uint32_t)rows);
+    if (ND >= 2 && g.n[1] > 1) {
+        // y and x together, the output written
+        hipLaunchKernelGGL(k_interp_final_yx, dim3((npairs + 255) / 256, cap(rows)), dim3(256), 0, st, g, q, e2, out,
+                           (uint32_t)rows);
+    } else {
+        hipLaunchKernelGGL(k_interp_final_x, dim3((npairs + 255) / 256, cap(rows)), dim3(256), 0, st, g, q, e2, out,
+                           (uint32_t)rows);
+    }
 }
 
 void launch_interp_inverse(hipStream_t st, const Geom& g, int32_t* q, double e2, float* out) {

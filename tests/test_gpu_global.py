@@ -2,7 +2,7 @@
 (predictor 6) with the oracle: byte-identical containers, bit-identical
 reconstructions within the bound, on 3D, 2D and 1D fields with ragged
 edges, thin and tiny extents, outliers, lossless patches and the verbatim
-fallback; graph mode and the batch call; a 512^3 field at three bounds
+fallback; large 3D fields through the fused x/y inverse; graph mode and the batch call; a 512^3 field at three bounds
 (containers byte for byte, reconstructions against the prequantised values,
 which dual quantisation reproduces exactly at any size), and a 1D field of
 2^24 values (the look-back scan over many tiles)."""
@@ -31,6 +31,13 @@ CASES = [
     ("3d-thin", "smooth", (3, 64, 40), 1e-3, 1),
     ("3d-tiny", "smooth", (2, 3, 5), 1e-3, 1),
     ("3d-const", "const", (17, 9, 33), 1e-3, 1),
+    # large 3D fields decode by the fused x/y pass (one workgroup per plane,
+    # at least 2048 waves): 1, 2 and 4 chunks of 256 per wave and row, 2-4
+    # waves per row, ragged rows and rows not a multiple of 4
+    ("3d-fused-xy", "smooth", (4096, 3, 260), 1e-3, 1),
+    ("3d-fused-xy-c2-ragged", "smooth", (700, 3, 1501), 1e-4, 1),
+    ("3d-fused-xy-c4", "smooth", (1100, 2, 3000), 1e-3, 1),
+    ("3d-fused-xy-w4", "grf", (600, 5, 1024), 1e-4, 1),
     ("2d-ragged", "smooth", (1001, 777), 1e-3, 1),
     ("2d-small", "smooth", (3, 5), 1e-2, 1),
     ("1d-positions", "positions", (300007,), 1e-4, 1),

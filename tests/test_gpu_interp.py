@@ -31,6 +31,10 @@ CASES = [
     ("3d-thin", "smooth", (3, 64, 40), 1e-3, 1),
     ("3d-tiny", "smooth", (2, 3, 5), 1e-3, 1),
     ("3d-const", "const", (17, 9, 33), 1e-3, 1),
+    # rows longer than one workgroup's 512 values: the even points of the
+    # neighbouring workgroups' pairs rebuilt at the range edges
+    ("3d-long-rows", "smooth", (20, 21, 1100), 1e-3, 1),
+    ("3d-long-rows-odd", "smooth", (18, 17, 1025), 1e-4, 1),
     ("2d-ragged", "smooth", (1001, 777), 1e-3, 1),
     ("2d-small", "smooth", (3, 5), 1e-2, 1),
     ("1d-positions", "positions", (300007,), 1e-4, 1),
