@@ -114,14 +114,108 @@ __device__ __forceinline__ void read_row(const int32_t* Q, uint32_t off, int32_t
     r[4] = c.x; r[5] = c.y; r[6] = c.z; r[7] = c.w;
 }
 
+// Halo of the 3D interpolation quantiser: the grid values outside a tile
+// that its predictions read, at the positions the stride-s classes need
+// (for a block with origin (X0, Y0, Z0), i, ly, lz its local coordinates;
+// sh = log2 s):
+//   per block (kIHB values), for s = 1, 2, 4 the three y rows and z planes
+//   outside the block that stride-s points reach, Y0 - 2s, Y0 + 8,
+//   Y0 + 8 + 2s (row k = 0, 1, 2), at the points of that stride:
+//     y rows: i a multiple of 2s, lz of s (32, 8, 2 values per row)
+//     z planes: i and ly multiples of 2s (16, 4, 1 values per plane)
+//     then the anchor's (X0 - 8, Y0 - 8, Z0), (X0 - 8, Y0, Z0 - 8),
+//     (X0 - 8, Y0 - 8, Z0 - 8), (X0, Y0 - 8, Z0 - 8)
+//   per tile (kIHX values), x columns of every (ly, lz) row taking them
+//     left of the first block: X0 - 2 (all 64 rows), X0 - 4 (even ly and
+//     lz), X0 - 8 (ly, lz in {0, 4})
+//     right of the last block: X0 + 8, X0 + 10 (all rows), X0 + 12 (even
+//     ly and lz), X0 + 16 (ly, lz in {0, 4})
+// The indices are arithmetic in (r, i, ly, lz, sh) so that the lookups
+// compile without branches.
+constexpr int kIHY = 126, kIHZ = 63, kIHB = kIHY + kIHZ + 4, kIHX = 232, kIHAnchor = kIHY + kIHZ;
+// y row at local ly = r (outside 0..7, reached by stride 1 << sh) of x = i, plane lz
+__device__ __forceinline__ int interp_halo_y(int r, int i, int lz, int sh) {
+    const int k = (r > 0 ? 1 : 0) + (r > 8 ? 1 : 0);
+    return (sh > 0 ? 96 : 0) + (sh > 1 ? 24 : 0) + k * (32 >> (2 * sh)) + (i >> (sh + 1)) + (lz >> sh) * (4 >> sh);
+}
+// z plane at local lz = r (outside 0..7, reached by stride 1 << sh) of x = i, row ly
+__device__ __forceinline__ int interp_halo_z(int r, int i, int ly, int sh) {
+    const int k = (r > 0 ? 1 : 0) + (r > 8 ? 1 : 0);
+    return kIHY + (sh > 0 ? 48 : 0) + (sh > 1 ? 12 : 0) + k * (16 >> (2 * sh)) + (i >> (sh + 1)) +
+           (ly >> (sh + 1)) * (4 >> sh);
+}
+// x column j = -2, -4, -8 left of the tile's first block, row (ly, lz)
+__device__ __forceinline__ int interp_halo_left(int j, int ly, int lz) {
+    if (j == -2) return ly + 8 * lz;
+    if (j == -4) return 64 + (ly >> 1) + 4 * (lz >> 1);
+    return 80 + (ly >> 2) + 2 * (lz >> 2);
+}
+// x column j = 8, 10, 12, 16 from the origin of the tile's last block
+__device__ __forceinline__ int interp_halo_right(int j, int ly, int lz) {
+    const int a = (j == 8 ? 84 : 148) + ly + 8 * lz;
+    const int b = j == 12 ? 212 + (ly >> 1) + 4 * (lz >> 1) : 228 + (ly >> 2) + 2 * (lz >> 2);
+    return j <= 10 ? a : b;
+}
+// Entry e of the halo: the block of the tile it is relative to and its
+// offset from that block's origin.
+__device__ __forceinline__ void interp_halo_at(uint32_t e, uint32_t& bi, int& dx, int& dy, int& dz) {
+    if (e >= (uint32_t)(kTileBlocks * kIHB)) {
+        int k = (int)(e - kTileBlocks * kIHB);
+        if (k < 84) {
+            bi = 0;
+            if (k < 64) { dx = -2; dy = k & 7; dz = k >> 3; }
+            else if (k < 80) { k -= 64; dx = -4; dy = 2 * (k & 3); dz = 2 * (k >> 2); }
+            else { k -= 80; dx = -8; dy = 4 * (k & 1); dz = 4 * (k >> 1); }
+        } else {
+            bi = kTileBlocks - 1;
+            k -= 84;
+            if (k < 64) { dx = 8; dy = k & 7; dz = k >> 3; }
+            else if (k < 128) { k -= 64; dx = 10; dy = k & 7; dz = k >> 3; }
+            else if (k < 144) { k -= 128; dx = 12; dy = 2 * (k & 3); dz = 2 * (k >> 2); }
+            else { k -= 144; dx = 16; dy = 4 * (k & 1); dz = 4 * (k >> 1); }
+        }
+        return;
+    }
+    bi = e / kIHB;
+    int k = (int)(e - bi * kIHB);
+    if (k < kIHY) {
+        // y rows: s = 1 (0..95), 2 (96..119), 4 (120..125); 32 >> 2 sh
+        // points per row, 4 >> sh of them along x
+        const int sh = k < 96 ? 0 : (k < 120 ? 1 : 2);
+        const int m0 = k - (sh == 0 ? 0 : (sh == 1 ? 96 : 120));
+        const int r = m0 >> (5 - 2 * sh), m = m0 & ((32 >> (2 * sh)) - 1);
+        const int sv = 1 << sh;
+        dy = r == 0 ? -2 * sv : (r == 1 ? 8 : 8 + 2 * sv);
+        dx = (m & ((4 >> sh) - 1)) * 2 * sv;
+        dz = (m >> (2 - sh)) * sv;
+    } else if (k < kIHY + kIHZ) {
+        // z planes: s = 1 (0..47), 2 (48..59), 4 (60..62); 16 >> 2 sh
+        // points per plane, 4 >> sh of them along x
+        const int kk = k - kIHY;
+        const int sh = kk < 48 ? 0 : (kk < 60 ? 1 : 2);
+        const int m0 = kk - (sh == 0 ? 0 : (sh == 1 ? 48 : 60));
+        const int r = m0 >> (4 - 2 * sh), m = m0 & ((16 >> (2 * sh)) - 1);
+        const int sv = 1 << sh;
+        dz = r == 0 ? -2 * sv : (r == 1 ? 8 : 8 + 2 * sv);
+        dx = (m & ((4 >> sh) - 1)) * 2 * sv;
+        dy = (m >> (2 - sh)) * 2 * sv;
+    } else {
+        const int a = k - kIHAnchor;  // (x-8, y-8), (x-8, z-8), (x-8, y-8, z-8), (y-8, z-8)
+        dx = a == 3 ? 0 : -8;
+        dy = (a == 0 || a >= 2) ? -8 : 0;
+        dz = a >= 1 ? -8 : 0;
+    }
+}
+
 // MODE: kQuantP0 (first-order Lorenzo everywhere), kQuantPred (predictor
 // per block: fixed_pred >= 0 for every block, else bpred[b]), kQuantTrial
 // (no codes: per-block cost of each predictor under a reference code,
 // cheapest predictor -> choice[b], the three costs -> costs[3 b + p]).
-// kQuantInterp: the interpolation predictor over the whole field, its
-// neighbours read from LDS or prequantised from the field, and a top-3
-// histogram (the codes of residuals -1, 0, 1 counted by ballots: the
-// interpolation residuals pile up there).
+// kQuantInterp: the interpolation predictor over the whole field, and a
+// top-3 histogram (the codes of residuals -1, 0, 1 counted by ballots: the
+// interpolation residuals pile up there).  3D: every neighbour from LDS
+// (the tile's blocks and a halo staged in phase A); 1D/2D: from LDS, or
+// prequantised from the field outside the tile.
 // kQuantGlobal: first-order Lorenzo over the whole field (neighbours in
 // other blocks read as in kQuantInterp).
 constexpr int kQuantP0 = 0, kQuantPred = 1, kQuantTrial = 2, kQuantInterp = 3, kQuantGlobal = 4;
@@ -140,7 +234,11 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
     // four blocks do not fall into the same banks; one extra zero row
     constexpr int kQStride = kBlockElems + 8;
     constexpr uint32_t kZero = kTileBlocks * kQStride;
-    __shared__ int32_t Q[kTileBlocks * kQStride + 8];
+    // (the 3D interpolation predictor keeps its halo after the zero row,
+    // HI, so that one LDS index reaches the tile's values or the halo)
+    constexpr int kHI = MODE == kQuantInterp && ND == 3 ? kTileBlocks * kIHB + kIHX : 0;
+    __shared__ int32_t Q[kTileBlocks * kQStride + 8 + kHI];
+    int32_t* const HI = &Q[kTileBlocks * kQStride + 8];
     __shared__ uint8_t PM[kTileBlocks * kSegs];
     __shared__ uint32_t H[kBins];
     __shared__ uint32_t wsum[4];
@@ -188,6 +286,20 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
     load_map<ND>(t, la_bi, la_s);
     seg_coords<ND>(la_s, la_lx0, la_ly, la_lz);
     const uint32_t la_rowoff = la_lx0 + g.n[0] * (la_ly + g.n[1] * la_lz);
+    // 3D interpolation: this thread's halo entries t + 256 k, decoded once
+    // (block of the tile in bits 0-1, dx + 8, dy + 8, dz + 8 in 5 bits each)
+    constexpr int kIHPerThread = MODE == kQuantInterp && ND == 3 ? (kTileBlocks * kIHB + kIHX + 255) / 256 : 1;
+    uint32_t ih_code[kIHPerThread];
+    if (MODE == kQuantInterp && ND == 3) {
+#pragma unroll
+        for (int k = 0; k < kIHPerThread; k++) {
+            uint32_t bi = 0;
+            int dx = 0, dy = 0, dz = 0;
+            const uint32_t e = t + 256u * k;
+            if (e < (uint32_t)(kTileBlocks * kIHB + kIHX)) interp_halo_at(e, bi, dx, dy, dz);
+            ih_code[k] = bi | (uint32_t)(dx + 8) << 2 | (uint32_t)(dy + 8) << 7 | (uint32_t)(dz + 8) << 12;
+        }
+    }
     // phase-B lane (segment = lane) offset, for reloading patched values
     uint32_t lb_lx0, lb_ly, lb_lz;
     seg_coords<ND>(lane, lb_lx0, lb_ly, lb_lz);
@@ -249,6 +361,34 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
             dst[0] = make_int4(q[0], q[1], q[2], q[3]);
             dst[1] = make_int4(q[4], q[5], q[6], q[7]);
             PM[la_bi * kSegs + la_s] = (uint8_t)pm;
+        }
+        if (MODE == kQuantInterp && ND == 3) {
+            // interpolation (3D): the grid values outside the blocks that
+            // the stride-s predictions of the tile read (interp_halo_at,
+            // decoded once per thread)
+#pragma unroll
+            for (int k = 0; k < kIHPerThread; k++) {
+                const uint32_t e = t + 256u * k;
+                if (e >= (uint32_t)(kTileBlocks * kIHB + kIHX)) break;
+                const uint32_t hv = ih_code[k];
+                const uint32_t bi = hv & 3u;
+                const int dx = (int)((hv >> 2) & 31u) - 8, dy = (int)((hv >> 7) & 31u) - 8,
+                          dz = (int)((hv >> 12) & 31u) - 8;
+                const uint32_t bk = tile * kTileBlocks + bi;
+                int32_t v = 0;
+                if (bk < g.nblocks) {
+                    const BlockInfo ik = block_info(g, bk);
+                    const int64_t xx = (int64_t)ik.bx * 8 + dx, yy = (int64_t)ik.by * 8 + dy,
+                                  zz = (int64_t)ik.bz * 8 + dz;
+                    if (xx >= 0 && yy >= 0 && zz >= 0 && xx < (int64_t)g.n[0] && yy < (int64_t)g.n[1] &&
+                        zz < (int64_t)g.n[2]) {
+                        bool pq;
+                        v = prequant1(x[(uint64_t)xx + (uint64_t)g.n[0] * ((uint64_t)yy + (uint64_t)g.n[1] * (uint64_t)zz)],
+                                      e2, inv, eb_abs, pq);
+                    }
+                }
+                HI[e] = v;
+            }
         }
         if (MODE == kQuantGlobal) {
             for (uint32_t e = t; e < (uint32_t)(kTileBlocks * kHB + kHL); e += 256) {
@@ -343,7 +483,103 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
                                  inv, eb_abs, pq);
             };
             auto residual = [&](const uint32_t pr) {
-            if (MODE == kQuantInterp) {
+            if (MODE == kQuantInterp && ND == 3) {
+                // 3D: lane = row (ly, lz) of the block, values at x = X0 + i.
+                // An odd i is a stride-1 point along x; an even i's stride
+                // and axis follow from i | y | z (the row's y | z known per
+                // lane), an x axis only for i = 2, 6 (stride 2) and 4
+                // (stride 4).  Every neighbour is in this row's registers or
+                // in LDS (the tile's blocks or its halo), read without
+                // branches: the x and the y/z candidates of an even i are
+                // both formed and one is selected per lane.  Grid values
+                // are at most 2^24 in magnitude, so the cubic and linear
+                // rules are exact in 32-bit integers.
+                int32_t r0[8];
+                read_row<ND>(Q, Qb + s * 8, r0);
+                const uint32_t n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+                const uint32_t X0 = info.bx * 8, Y = info.by * 8 + ly, Z = info.bz * 8 + lz;
+                const uint32_t yz = Y | Z;
+                // indices into Q: this block's halo, the tile's x halo
+                const int hb = kTileBlocks * kQStride + 8 + (int)wave * kIHB;
+                const int hx = kTileBlocks * kQStride + 8 + kTileBlocks * kIHB;
+                const int32_t* Hb = &Q[hb];
+                const int rowQ = (int)Qb + (int)s * 8;  // this row in Q
+                // one of two indices by a mask (no branch)
+                auto sel = [](bool c, int a, int b) { return b + ((a - b) & -(int)c); };
+                // x = X0 + j of this row (j compile-time after unrolling):
+                // this row, a block of the tile, or the tile's x halo (left
+                // of its first block, right of its last one)
+                auto qx = [&](int j) -> int32_t {
+                    if (j >= 0 && j < 8) return r0[j];
+                    const int ob = (j + 16) / 8 - 2;  // block offset along x (j >= -16)
+                    const int wb = (int)wave + ob;
+                    const int ih = hx + (j < 0 ? interp_halo_left(j, (int)ly, (int)lz)
+                                               : interp_halo_right((int)wave * 8 - 8 * (kTileBlocks - 1) + j,
+                                                                   (int)ly, (int)lz));
+                    return Q[sel(wb >= 0 && wb < kTileBlocks, rowQ + ob * kQStride + (j - 8 * ob), ih)];
+                };
+                // offset d along y (ay) or z at x = X0 + i: this block, or
+                // its y or z halo
+                auto qyz = [&](int i, bool ay, int d, int sh) -> int32_t {
+                    const int l = (ay ? (int)ly : (int)lz) + d;
+                    const int iq = rowQ + i + d * (ay ? 8 : 64);
+                    const int ih = hb + sel(ay, interp_halo_y(l, i, (int)lz, sh), interp_halo_z(l, i, (int)ly, sh));
+                    return Q[sel((uint32_t)l < 8u, iq, ih)];
+                };
+                auto pick = [](bool m3, bool p1, bool p3, int32_t vm3, int32_t vm1, int32_t vp1, int32_t vp3) {
+                    const int32_t cub = (-vm3 + 9 * vm1 + 9 * vp1 - vp3 + 8) >> 4;
+                    const int32_t lin = (vm1 + vp1 + 1) >> 1;
+                    return (m3 && p3) ? cub : (p1 ? lin : vm1);
+                };
+#pragma unroll
+                for (int i = 0; i < 8; i++) {
+                    const uint32_t xx = X0 + i;
+                    int32_t pq;
+                    if (i & 1) {
+                        pq = pick(xx >= 3, xx + 1 < n0, xx + 3 < n0, qx(i - 3), qx(i - 1), qx(i + 1), qx(i + 3));
+                    } else {
+                        const uint32_t orc = (uint32_t)i | yz;
+                        const int sh = (orc & 1u) ? 0 : ((orc & 2u) ? 1 : 2);
+                        const uint32_t sv = 1u << sh;
+                        const int si = (int)sv;
+                        const bool ay = (Y & sv) != 0;
+                        const uint32_t ca = ay ? Y : Z, na = ay ? n1 : n2;
+                        bool m3 = ca >= 3 * sv, p1 = ca + sv < na, p3 = ca + 3 * sv < na;
+                        int32_t vm3 = qyz(i, ay, -3 * si, sh), vm1 = qyz(i, ay, -si, sh), vp1 = qyz(i, ay, si, sh),
+                                vp3 = qyz(i, ay, 3 * si, sh);
+                        if (i != 0) {
+                            // stride 2 (i = 2, 6) or 4 (i = 4) along x
+                            const int sx = i == 4 ? 4 : 2;
+                            const bool isx = ((uint32_t)i & sv) != 0;
+                            const int32_t xm3 = qx(i - 3 * sx), xm1 = qx(i - sx), xp1 = qx(i + sx),
+                                          xp3 = qx(i + 3 * sx);
+                            m3 = isx ? xx >= 3u * sx : m3;
+                            p1 = isx ? xx + sx < n0 : p1;
+                            p3 = isx ? xx + 3u * sx < n0 : p3;
+                            vm3 = isx ? xm3 : vm3;
+                            vm1 = isx ? xm1 : vm1;
+                            vp1 = isx ? xp1 : vp1;
+                            vp3 = isx ? xp3 : vp3;
+                        }
+                        pq = pick(m3, p1, p3, vm3, vm1, vp1, vp3);
+                        if (i == 0) {
+                            // the block's anchor (ly = lz = 0): Lorenzo on the
+                            // anchor grid, the neighbours 8 below in x, y, z
+                            const bool ix = X0 >= 8, iy = Y >= 8, iz = Z >= 8;
+                            int32_t pa = 0;
+                            pa += ix ? qx(-8) : 0;
+                            pa += iy ? Hb[interp_halo_y(-8, 0, 0, 2)] : 0;
+                            pa += iz ? Hb[interp_halo_z(-8, 0, 0, 2)] : 0;
+                            pa -= (ix && iy) ? Hb[kIHAnchor + 0] : 0;
+                            pa -= (ix && iz) ? Hb[kIHAnchor + 1] : 0;
+                            pa -= (iy && iz) ? Hb[kIHAnchor + 3] : 0;
+                            pa += (ix && iy && iz) ? Hb[kIHAnchor + 2] : 0;
+                            pq = (yz & 7u) == 0 ? pa : pq;
+                        }
+                    }
+                    d[i] = i < (int)nv ? (int32_t)((uint32_t)r0[i] - (uint32_t)pq) : 0;
+                }
+            } else if (MODE == kQuantInterp) {
                 int32_t r0[8];
                 read_row<ND>(Q, Qb + s * 8, r0);
                 const uint32_t n3[3] = {g.n[0], g.n[1], g.n[2]};
