@@ -562,22 +562,35 @@ __device__ __forceinline__ void block_prefix(int32_t (&v)[8], uint32_t lane) {
         }
         return;
     }
-    // 3D: y within the 8 lanes of one z, then z (lanes 8 apart)
+    // 3D (the whole wave active): y within the 8 lanes of one z by DPP row
+    // shifts (lanes whose source lies in the other z of the 16-lane row
+    // masked), then z over lane bits 3-5 by butterflies: the partner's
+    // running total of its 2^k z-levels, lane ^ 8 by a DPP row rotation,
+    // lane ^ 16 and lane ^ 32 by the permlane swaps, added to the prefix of
+    // the lanes in the upper half
+    const uint32_t ly = lane & 7;
 #pragma unroll
-    for (int d = 1; d < 8; d <<= 1) {
-#pragma unroll
-        for (int i = 0; i < 8; i++) {
-            const int32_t o = __shfl_up(v[i], d, 8);
-            if ((lane & 7) >= (uint32_t)d) v[i] += o;
-        }
-    }
-#pragma unroll
-    for (int d = 8; d < 64; d <<= 1) {
-#pragma unroll
-        for (int i = 0; i < 8; i++) {
-            const int32_t o = __shfl_up(v[i], d, 64);
-            if (lane >= (uint32_t)d) v[i] += o;
-        }
+    for (int i = 0; i < 8; i++) {
+        // every cross-lane read by all lanes, outside the selects
+        uint32_t a = (uint32_t)v[i];
+        const uint32_t y1 = dpp32<0x111, 0xf>(a);
+        a += ly >= 1 ? y1 : 0u;
+        const uint32_t y2 = dpp32<0x112, 0xf>(a);
+        a += ly >= 2 ? y2 : 0u;
+        const uint32_t y4 = dpp32<0x114, 0xf>(a);
+        a += ly >= 4 ? y4 : 0u;
+        uint32_t tot = a;
+        uint32_t o = dpp32<0x128, 0xf>(tot);  // lane ^ 8
+        a += (lane & 8) ? o : 0u;
+        tot += o;
+        const auto s16 = __builtin_amdgcn_permlane16_swap(tot, tot, false, false);
+        o = (lane & 16) ? s16[0] : s16[1];  // lane ^ 16
+        a += (lane & 16) ? o : 0u;
+        tot += o;
+        const auto s32 = __builtin_amdgcn_permlane32_swap(tot, tot, false, false);
+        o = (lane & 32) ? s32[0] : s32[1];  // lane ^ 32
+        a += (lane & 32) ? o : 0u;
+        v[i] = (int32_t)a;
     }
 }
 

@@ -6,13 +6,16 @@
 // a block's 512 symbol slots form 16 groups of 32, each group 10 plane words
 // (word p: bit p of the group's symbols, symbol j in bit j), and only the
 // non-zero words are kept, flagged in a 160-bit mask per block.
-//   k_shuffle   - one wave per block: symbols by lane (slot 64 r + lane in
-//                 round r), one ballot per plane and round gives two plane
-//                 words; per-block masks and word counts; a workgroup of 32
+//   k_shuffle   - one wave per block: lane = 8 consecutive slots (one
+//                 16-byte code load), their symbols' bits transposed (8 x 8
+//                 delta swaps) to one byte per plane, the quad's bytes
+//                 transposed across lanes to the group's plane words;
+//                 per-block masks and word counts; a workgroup of 32
 //                 blocks finds its first kept word by decoupled look-back
 //                 and writes its masks and kept words
 //   k_unshuffle - one wave per block: lane = 8 consecutive slots (a row),
 //                 the lane's group's kept words gathered by mask popcounts,
+//                 its byte of each plane transposed back to 8 symbols,
 //                 symbols -> residuals (outliers from the list), the
 //                 inverse Lorenzo as in-lane and cross-lane prefix sums,
 //                 dequantisation, row stores
@@ -22,6 +25,7 @@
 namespace fz {
 
 constexpr int kShufBlocks = 32;  // blocks per workgroup (8 per wave)
+constexpr int kGroups = kBlockElems / 32;  // 32-symbol groups per block
 
 uint32_t shuffle_groups(uint32_t nblocks) { return (nblocks + kShufBlocks - 1) / kShufBlocks; }
 
@@ -31,6 +35,17 @@ __device__ __forceinline__ void slot_coords(uint32_t s, uint32_t& lx, uint32_t& 
     if (ND == 3) { lx = s & 7; ly = (s >> 3) & 7; lz = s >> 6; }
     else if (ND == 2) { lx = s & 31; ly = s >> 5; lz = 0; }
     else { lx = s; ly = 0; lz = 0; }
+}
+
+// 8 x 8 bit-matrix transpose (three delta swaps, Hacker's Delight 7-3):
+// bit c of byte r moves to bit r of byte c.
+__device__ __forceinline__ uint64_t transpose8(uint64_t x) {
+    uint64_t t = (x ^ (x >> 7)) & 0x00AA00AA00AA00AAull;
+    x = x ^ t ^ (t << 7);
+    t = (x ^ (x >> 14)) & 0x0000CCCC0000CCCCull;
+    x = x ^ t ^ (t << 14);
+    t = (x ^ (x >> 28)) & 0x00000000F0F0F0F0ull;
+    return x ^ t ^ (t << 28);
 }
 
 // Symbol of a quantisation code.
@@ -54,54 +69,58 @@ __global__ __launch_bounds__(256) void k_shuffle(Geom g, const uint16_t* __restr
     __syncthreads();
     const uint32_t grp = s_group;
     if (grp >= ngroups) return;
+    // the plane words of this wave's blocks through LDS (one block at a
+    // time), read back with lane = word index mod 64
+    __shared__ uint32_t s_words[4][kGroups * kPlanes];
+    uint32_t* W = s_words[wave];
+    // quad byte transpose selectors (v_perm): step 1 pairs lanes k, k ^ 1
+    // (bytes), step 2 pairs k, k ^ 2 (16-bit halves)
+    const uint32_t k4 = lane & 3;
+    const uint32_t sel1 = (k4 & 1) ? 0x03070105u : 0x06020400u;
+    const uint32_t sel2 = (k4 & 2) ? 0x03020706u : 0x05040100u;
+    auto quad_t = [&](uint32_t v) {
+        const uint32_t p1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // lane ^ 1
+        const uint32_t t1 = __builtin_amdgcn_perm(p1, v, sel1);
+        const uint32_t p2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)t1, 0x4E, 0xF, 0xF, false);  // lane ^ 2
+        return __builtin_amdgcn_perm(p2, t1, sel2);
+    };
     // the kept words of this wave's blocks, lane = word index mod 64
     uint32_t kw[8][3];
 #pragma unroll
     for (int i = 0; i < 8; i++) {
         const uint32_t b = grp * kShufBlocks + wave * 8 + i;
         uint32_t w0 = 0, w1 = 0, w2 = 0;
-        if (b < g.nblocks) {
+        if (b < g.nblocks) {  // uniform over the wave
             const BlockInfo bi = block_info(g, b);
-            const uint16_t* cb = codes + (uint64_t)b * kBlockElems;
-            uint32_t s[8];
+            // lane = 8 consecutive slots 8 lane + j of group lane / 4,
+            // symbol 8 (lane & 3) + j of its plane words
+            const uint4 cv = *reinterpret_cast<const uint4*>(codes + (uint64_t)b * kBlockElems + 8 * lane);
+            const uint32_t c8[8] = {cv.x & 0xFFFFu, cv.x >> 16, cv.y & 0xFFFFu, cv.y >> 16,
+                                    cv.z & 0xFFFFu, cv.z >> 16, cv.w & 0xFFFFu, cv.w >> 16};
+            uint64_t lo = 0, hi = 0;
 #pragma unroll
-            for (int r = 0; r < 8; r++) {
-                const uint32_t slot = 64 * r + lane;
+            for (int j = 0; j < 8; j++) {
                 uint32_t lx, ly, lz;
-                slot_coords<ND>(slot, lx, ly, lz);
+                slot_coords<ND>(8 * lane + j, lx, ly, lz);
                 const bool valid = lx < bi.ex && ly < bi.ey && lz < bi.ez;
-                s[r] = valid ? fold_code(cb[slot]) : 0u;
+                const uint32_t sv = valid ? fold_code(c8[j]) : 0u;
+                lo |= (uint64_t)(sv & 0xFFu) << (8 * j);
+                hi |= (uint64_t)(sv >> 8) << (8 * j);
             }
-            // planes above the block's highest symbol bit, and rounds whose
-            // 64 symbols are all zero, hold only zero words (wave-uniform
-            // skips)
-            uint32_t orl = s[0] | s[1] | s[2] | s[3] | s[4] | s[5] | s[6] | s[7];
-#pragma unroll
-            for (int d = 32; d > 0; d >>= 1) orl |= (uint32_t)__shfl_xor((int)orl, d, 64);
-            const int P = 32 - __clz((int)orl);
-            // round r covers groups 2r (low half of each ballot) and 2r + 1;
-            // word k = 10 group + plane goes to lane k mod 64, slot k / 64
-#pragma unroll
-            for (int r = 0; r < 8; r++) {
-                if (!__ballot(s[r] != 0)) continue;
-#pragma unroll
-                for (int p = 0; p < kPlanes; p++) {
-                    if (p >= P) break;
-                    const uint64_t bal = __ballot((s[r] >> p) & 1u);
-                    const uint32_t k0 = (2 * r) * kPlanes + p, k1 = k0 + kPlanes;
-                    const uint32_t lo = (uint32_t)bal, hi = (uint32_t)(bal >> 32);
-                    if (lane == (k0 & 63)) {
-                        if ((k0 >> 6) == 0) w0 = lo;
-                        else if ((k0 >> 6) == 1) w1 = lo;
-                        else w2 = lo;
-                    }
-                    if (lane == (k1 & 63)) {
-                        if ((k1 >> 6) == 0) w0 = hi;
-                        else if ((k1 >> 6) == 1) w1 = hi;
-                        else w2 = hi;
-                    }
-                }
-            }
+            // transposed: byte p = plane p's 8 bits of this lane's slots
+            const uint64_t tl = transpose8(lo), th = transpose8(hi);
+            // across the quad: lane 4 g + k gets the words of planes k,
+            // 4 + k (and 8 + k for k < 2) of group g
+            const uint32_t wa = quad_t((uint32_t)tl), wb = quad_t((uint32_t)(tl >> 32)), wc = quad_t((uint32_t)th);
+            const uint32_t g0 = (lane >> 2) * kPlanes;
+            W[g0 + k4] = wa;
+            W[g0 + 4 + k4] = wb;
+            if (k4 < 2) W[g0 + 8 + k4] = wc;
+            __builtin_amdgcn_wave_barrier();
+            w0 = W[lane];
+            w1 = W[64 + lane];
+            w2 = lane < kGroups * kPlanes - 128 ? W[128 + lane] : 0u;
+            __builtin_amdgcn_wave_barrier();
         }
         kw[i][0] = w0;
         kw[i][1] = w1;
@@ -174,7 +193,8 @@ __global__ __launch_bounds__(256) void k_unshuffle(Geom g, const uint32_t* __res
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t nw = gridDim.x * 4;
     bool bad = false;
-    for (uint32_t b = blockIdx.x * 4 + (threadIdx.x >> 6); b < g.nblocks; b += nw) {
+    const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    for (uint32_t b = b0; b < g.nblocks; b += nw) {  // wave-uniform: masks and offset by scalar loads
         const uint32_t* mb = masks + (uint64_t)kMaskWords * b;
         const uint32_t mw0 = mb[0], mw1 = mb[1], mw2 = mb[2], mw3 = mb[3], mw4 = mb[4];
         const uint64_t base = off[b];
@@ -189,30 +209,34 @@ __global__ __launch_bounds__(256) void k_unshuffle(Geom g, const uint32_t* __res
         uint32_t before = (uint32_t)__popc(wa & ((1u << sh) - 1u));
         before += (a > 0 ? __popc(mw0) : 0) + (a > 1 ? __popc(mw1) : 0) + (a > 2 ? __popc(mw2) : 0) +
                   (a > 3 ? __popc(mw3) : 0);
-        // planes no group of the block keeps are zero for every lane
-        uint32_t orf = field;
-#pragma unroll
-        for (int d = 32; d > 0; d >>= 1) orf |= (uint32_t)__shfl_xor((int)orf, d, 64);
-        const int P = 32 - __clz((int)orf);
         const uint32_t bo = 8 * (lane & 3);
         uint32_t s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (P) {
+        // a block whose groups keep no word has only zero symbols; else the
+        // ten plane loads are issued together (a plane the group does not
+        // keep reads word 0 and is masked), so their latencies overlap
+        if (__ballot(field != 0) && nkept) {
             uint32_t pb[kPlanes];  // this lane's 8 bits of each plane word
+            uint64_t idx = base + before;
 #pragma unroll
             for (int p = 0; p < kPlanes; p++) {
-                pb[p] = 0;
-                if (p >= P) continue;
-                const uint64_t idx = base + before + (uint32_t)__popc(field & ((1u << p) - 1u));
-                const bool has = (field >> p) & 1u;
-                const bool inb = idx < nkept;
-                bad |= has && !inb;
-                pb[p] = (has && inb) ? (kept[idx] >> bo) & 0xFFu : 0u;
+                const uint32_t has = (field >> p) & 1u;
+                const bool use = has && idx < nkept;
+                bad |= has && !use;
+                const uint32_t v = kept[use ? idx : 0];
+                pb[p] = use ? (v >> bo) & 0xFFu : 0u;
+                idx += has;
             }
+            // planes 0-7 as the rows of an 8 x 8 bit matrix: transposed,
+            // byte i holds bits 0-7 of symbol i; planes 8-9 likewise
+            const uint64_t lo8 = (uint64_t)(pb[0] | pb[1] << 8 | pb[2] << 16 | pb[3] << 24) |
+                                 (uint64_t)(pb[4] | pb[5] << 8 | pb[6] << 16 | pb[7] << 24) << 32;
+            const uint64_t tl = transpose8(lo8);
 #pragma unroll
-            for (int p = 0; p < kPlanes; p++) {
-                if (p >= P) break;
+            for (int i = 0; i < 8; i++) s[i] = (uint32_t)(tl >> (8 * i)) & 0xFFu;
+            if (__ballot((field >> 8) != 0)) {
+                const uint64_t th = transpose8((uint64_t)(pb[8] | pb[9] << 8));
 #pragma unroll
-                for (int i = 0; i < 8; i++) s[i] |= ((pb[p] >> i) & 1u) << p;
+                for (int i = 0; i < 8; i++) s[i] |= ((uint32_t)(th >> (8 * i)) & 3u) << 8;
             }
         }
         const BlockInfo bi = block_info(g, b);
