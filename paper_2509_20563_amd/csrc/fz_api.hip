@@ -269,10 +269,8 @@ int ensure(fz_ctx* c, const Geom& g) {
     if (e == hipSuccess) e = grow(c->tfirst, c->tfirst_cap, ntiles);
     if (e == hipSuccess) e = grow(c->tlast, c->tlast_cap, ntiles);
     if (e == hipSuccess) e = grow(c->desc_cnt, c->desc_cnt_cap, sd_tiles);
-    // look-back descriptors of the Huffman encoder's groups and of the
-    // bit-shuffle encoder's groups (both 32 blocks)
-    const uint64_t ngroups = std::max<uint64_t>(encode_groups((uint32_t)ntiles), shuffle_groups((uint32_t)nb));
-    if (e == hipSuccess) e = grow(c->desc_bits, c->desc_bits_cap, ngroups);
+    // look-back descriptors of the Huffman encoder's groups
+    if (e == hipSuccess) e = grow(c->desc_bits, c->desc_bits_cap, encode_groups((uint32_t)ntiles));
     if (e == hipSuccess) e = grow(c->desc_chunks, c->desc_chunks_cap, sd_blocks);
     if (e == hipSuccess) e = grow(c->off, c->off_cap, nb);
     if (e == hipSuccess) e = grow(c->oidx, c->oidx_cap, nb);
@@ -472,13 +470,13 @@ using TaskList = std::vector<Task>;
 // Data identities of the Misc fields, grouped by the stage that owns them
 // (addresses inside the device struct, used as keys only).
 struct MiscIds {
-    const void *range, *qctr, *cb, *enc, *flags, *total, *mtile, *stile, *xtile, *dec, *ohl;
+    const void *range, *qctr, *cb, *enc, *flags, *total, *mtile, *stile, *dec, *ohl;
     explicit MiscIds(Misc* m)
         : range(&m->mm_lo), qctr(&m->qtile_ctr), cb(&m->total_bits_cb), enc(&m->total_bits_enc), flags(&m->flags),
-          total(&m->total_bytes), mtile(&m->mtile_ctr), stile(&m->stile_ctr), xtile(&m->xtile_ctr),
+          total(&m->total_bytes), mtile(&m->mtile_ctr), stile(&m->stile_ctr),
           dec(&m->code0_count), ohl(&m->ohash_list) {}
     void reset_all(std::vector<Acc>& a) const {
-        for (const void* d : {range, qctr, cb, enc, flags, total, mtile, stile, xtile, dec, ohl}) a.push_back({d, ACC_W});
+        for (const void* d : {range, qctr, cb, enc, flags, total, mtile, stile, dec, ohl}) a.push_back({d, ACC_W});
     }
 };
 
@@ -608,23 +606,27 @@ void compress_enqueue(fz_ctx* c, const fz_params* p, const Geom& g, const float*
 }
 
 // Every stage of one bit-shuffle compression (first-order Lorenzo): the
-// same quantisation as compress_tasks, then the shuffle encoder in place of
-// the histogram -> code -> encode stages.
+// quantiser builds each block's plane words, masks and kept words in a
+// staging slot (the codes buffer) in place of codes and histogram; the
+// slots' mask popcounts are scanned to word offsets, and the copy writes
+// masks and kept words into the container.
 void compress_speed_tasks(fz_ctx* c, const fz_params* p, const Geom& g, const float* d_in, uint8_t* out,
                           const Tune& tn, TaskList& T) {
     const MiscIds M(c->misc);
     const uint32_t ntiles = (g.nblocks + kTileBlocks - 1) / kTileBlocks;
     const int vec = (((uintptr_t)d_in & 15) == 0) && (g.ndim == 1 || (g.n[0] & 3) == 0);
     const uint32_t sd_tiles = scan_tiles(ntiles);
+    const uint32_t sb_tiles = scan_tiles(g.nblocks);
     const uint32_t gmax = (uint32_t)c->n_cu * tn.wg_per_cu;
     const int grid = (int)(ntiles < gmax ? ntiles : gmax);
     const fz_params P = *p;
+    uint32_t* slots = reinterpret_cast<uint32_t*>(c->codes);
     {
-        std::vector<Acc> a = {{c->hist, ACC_W}, {c->desc_cnt, ACC_W}, {c->desc_bits, ACC_W}};
+        std::vector<Acc> a = {{c->hist, ACC_W}, {c->desc_cnt, ACC_W}, {c->desc_chunks, ACC_W}};
         M.reset_all(a);
         T.push_back({"reset", a, [=](hipStream_t st) {
-                         launch_reset(st, c->misc, c->hist, c->desc_cnt, sd_tiles, c->desc_bits,
-                                      shuffle_groups(g.nblocks), nullptr, 0, 0, 0, 0);
+                         launch_reset(st, c->misc, c->hist, c->desc_cnt, sd_tiles, c->desc_chunks, sb_tiles, nullptr,
+                                      0, 0, 0, 0);
                      }});
     }
     if (P.eb_mode == FZ_EB_REL)
@@ -634,10 +636,10 @@ void compress_speed_tasks(fz_ctx* c, const fz_params* p, const Geom& g, const fl
                      }});
     T.push_back({"quant",
                  {{d_in, ACC_R}, {M.range, ACC_R}, {c->codes, ACC_W}, {c->tile_cnt, ACC_W}, {c->ostage, ACC_W},
-                  {c->pstage, ACC_W}, {c->hist, ACC_RED}, {M.flags, ACC_RED}},
+                  {c->pstage, ACC_W}, {M.flags, ACC_RED}},
                  [=](hipStream_t st) {
-                     launch_quant(st, grid, d_in, g, P.eb_mode, P.eb, vec, c->misc, c->hist, c->codes, ntiles,
-                                  c->tile_cnt, c->ostage, c->pstage, FZ_PRED_LORENZO1, nullptr, nullptr);
+                     launch_quant_shuffle(st, grid, d_in, g, P.eb_mode, P.eb, vec, c->misc, c->hist, slots, ntiles,
+                                          c->tile_cnt, c->ostage, c->pstage);
                  }});
     T.push_back({"scan_counts",
                  {{c->tile_cnt, ACC_R}, {c->tile_off, ACC_W}, {c->desc_cnt, ACC_RW}, {M.qctr, ACC_RW},
@@ -646,11 +648,15 @@ void compress_speed_tasks(fz_ctx* c, const fz_params* p, const Geom& g, const fl
                      launch_scan(st, SCAN_COUNTS, c->tile_cnt, ntiles, c->tile_off, c->desc_cnt, &c->misc->qtile_ctr,
                                  c->misc, 0);
                  }});
-    T.push_back({"shuffle",
-                 {{c->codes, ACC_R}, {out, ACC_W}, {c->desc_bits, ACC_RW}, {M.xtile, ACC_RW}, {M.enc, ACC_W},
+    T.push_back({"scan_words",
+                 {{c->codes, ACC_R}, {c->off, ACC_W}, {c->desc_chunks, ACC_RW}, {M.stile, ACC_RW}, {M.enc, ACC_W},
                   {M.flags, ACC_RED}},
                  [=](hipStream_t st) {
-                     launch_shuffle(st, g, c->codes, out, (uint64_t)kHdr + 4 * g.N, c->desc_bits, c->misc);
+                     launch_scan(st, SCAN_SLOTS, slots, g.nblocks, c->off, c->desc_chunks, &c->misc->stile_ctr,
+                                 c->misc, 0);
+                 }});
+    T.push_back({"shuffle", {{c->codes, ACC_R}, {c->off, ACC_R}, {out, ACC_W}}, [=](hipStream_t st) {
+                     launch_shuffle_copy(st, g, slots, c->off, out, (uint64_t)kHdr + 4 * g.N);
                  }});
     T.push_back({"finalize",
                  {{M.range, ACC_R}, {M.qctr, ACC_R}, {M.enc, ACC_R}, {M.mtile, ACC_R}, {M.flags, ACC_RW},

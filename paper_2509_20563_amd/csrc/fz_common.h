@@ -38,7 +38,7 @@ constexpr int kSelectorParams = 2 * kNFeat + kNHid * kNFeat + kNHid + kNHid * kN
 constexpr uint16_t kVersion = 1;
 
 // prefix-scan kinds (fz_scan.hip)
-enum { SCAN_COUNTS = 0, SCAN_CHUNKS = 2, SCAN_PMAP = 3, SCAN_MASKS = 4 };
+enum { SCAN_COUNTS = 0, SCAN_CHUNKS = 2, SCAN_PMAP = 3, SCAN_MASKS = 4, SCAN_SLOTS = 5 };
 
 // flag bits raised by kernels in Misc::flags
 enum : uint32_t {
@@ -55,7 +55,6 @@ struct Misc {
     uint32_t flags;
     uint32_t mm_lo, mm_hi;     // order-preserving encodings of min and max
     uint32_t qtile_ctr;        // dynamic tile counters (look-back order)
-    uint32_t xtile_ctr;        // bit-shuffle encoder (look-back order)
     uint32_t stile_ctr;
     uint32_t code0_count;      // decode: outlier codes seen
     uint32_t mtile_ctr;        // predictor-map scan
@@ -592,6 +591,71 @@ __device__ __forceinline__ void block_prefix(int32_t (&v)[8], uint32_t lane) {
         a += (lane & 32) ? o : 0u;
         v[i] = (int32_t)a;
     }
+}
+
+
+// ------------------------------------------------ bit-shuffle plane words
+// Symbols of the bit-shuffle codec: a block's 512 slots form 16 groups of
+// 32 symbols, each group 10 plane words (word p: bit p of the group's
+// symbols, symbol j in bit j), word k = 10 group + plane.
+constexpr int kShufGroups = kBlockElems / 32;
+constexpr int kShufWords = kShufGroups * kPlanes;  // 160
+// Slot of a block in the fused encoder's staging: 5 mask words, then the
+// kept words in order (at most 160), 256 words per block.
+constexpr int kShufSlot = 256;
+
+// Symbol of a quantisation code: 0 (outlier) -> 1023, c -> zigzag(c - 512).
+__device__ __forceinline__ uint32_t fold_code(uint32_t code) {
+    const int32_t d = (int32_t)code - kRadius;
+    const uint32_t z = ((uint32_t)d << 1) ^ (uint32_t)(d >> 31);
+    return code ? z : kSymOutlier;
+}
+
+// 8 x 8 bit-matrix transpose (three delta swaps, Hacker's Delight 7-3):
+// bit c of byte r moves to bit r of byte c.
+__device__ __forceinline__ uint64_t transpose8(uint64_t x) {
+    uint64_t t = (x ^ (x >> 7)) & 0x00AA00AA00AA00AAull;
+    x = x ^ t ^ (t << 7);
+    t = (x ^ (x >> 14)) & 0x0000CCCC0000CCCCull;
+    x = x ^ t ^ (t << 14);
+    t = (x ^ (x >> 28)) & 0x00000000F0F0F0F0ull;
+    return x ^ t ^ (t << 28);
+}
+
+// The plane words of one block, the whole wave active, lane = the 8
+// consecutive slots 8 lane + j (symbols sym[j]; 4 lanes per group): each
+// lane transposes its symbols' bits to one byte per plane, the quad's
+// bytes are transposed across lanes (DPP swaps with lane ^ 1 and lane ^ 2,
+// byte permutes) into the group's words, and a per-wave LDS buffer W of
+// kShufWords returns them as word k = lane + 64 j in w[j].
+__device__ __forceinline__ void shuffle_words(const uint32_t sym[8], uint32_t lane, uint32_t* W, uint32_t w[3]) {
+    uint64_t lo = 0, hi = 0;
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        lo |= (uint64_t)(sym[j] & 0xFFu) << (8 * j);
+        hi |= (uint64_t)(sym[j] >> 8) << (8 * j);
+    }
+    const uint64_t tl = transpose8(lo), th = transpose8(hi);
+    const uint32_t k4 = lane & 3;
+    const uint32_t sel1 = (k4 & 1) ? 0x03070105u : 0x06020400u;
+    const uint32_t sel2 = (k4 & 2) ? 0x03020706u : 0x05040100u;
+    auto quad_t = [&](uint32_t v) {
+        const uint32_t p1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // lane ^ 1
+        const uint32_t t1 = __builtin_amdgcn_perm(p1, v, sel1);
+        const uint32_t p2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)t1, 0x4E, 0xF, 0xF, false);  // lane ^ 2
+        return __builtin_amdgcn_perm(p2, t1, sel2);
+    };
+    // lane 4 g + k: the words of planes k, 4 + k (and 8 + k for k < 2)
+    const uint32_t wa = quad_t((uint32_t)tl), wb = quad_t((uint32_t)(tl >> 32)), wc = quad_t((uint32_t)th);
+    const uint32_t g0 = (lane >> 2) * kPlanes;
+    W[g0 + k4] = wa;
+    W[g0 + 4 + k4] = wb;
+    if (k4 < 2) W[g0 + 8 + k4] = wc;
+    __builtin_amdgcn_wave_barrier();
+    w[0] = W[lane];
+    w[1] = W[64 + lane];
+    w[2] = lane < kShufWords - 128 ? W[128 + lane] : 0u;
+    __builtin_amdgcn_wave_barrier();
 }
 
 }  // namespace fz

@@ -14,6 +14,9 @@ void launch_quant(hipStream_t st, int grid, const float* x, const Geom& g, uint3
                   Misc* misc, uint32_t* hist, uint16_t* codes, uint32_t ntiles, uint32_t* tile_cnt, uint2* ostage,
                   uint2* pstage, int fixed_pred, const uint8_t* bpred,
                   int32_t* coef);
+void launch_quant_shuffle(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
+                          Misc* misc, uint32_t* hist, uint32_t* slots, uint32_t ntiles, uint32_t* tile_cnt,
+                          uint2* ostage, uint2* pstage);
 void launch_trial(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
                   Misc* misc, uint32_t ntiles, const uint32_t* cw_ref, uint8_t* choice, uint32_t* costs);
 
@@ -54,11 +57,11 @@ void launch_adam(hipStream_t st, float* w, float* m, float* v, const float* g, i
                  float eps);
 
 
-// fz_speed.hip: the bit-shuffle codec (codes -> masks + kept words, with
-// the group offsets by decoupled look-back; masks + kept words -> field)
-uint32_t shuffle_groups(uint32_t nblocks);
-void launch_shuffle(hipStream_t st, const Geom& g, const uint16_t* codes, uint8_t* out, uint64_t limit,
-                    uint64_t* desc, Misc* misc);
+// fz_speed.hip: the bit-shuffle codec (staging slots of the quantiser +
+// offsets -> masks + kept words in the container; masks + kept words ->
+// field)
+void launch_shuffle_copy(hipStream_t st, const Geom& g, const uint32_t* slots, const uint64_t* off, uint8_t* out,
+                         uint64_t limit);
 void launch_unshuffle(hipStream_t st, const Geom& g, const uint32_t* masks, const uint32_t* kept, uint64_t nkept,
                       const uint64_t* off, const uint32_t* opos, const int32_t* oval, const uint2* oidx,
                       uint64_t n_out, double e2, float* out, Misc* misc);

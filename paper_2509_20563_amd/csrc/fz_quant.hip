@@ -218,7 +218,11 @@ __device__ __forceinline__ void interp_halo_at(uint32_t e, uint32_t& bi, int& dx
 // prequantised from the field outside the tile.
 // kQuantGlobal: first-order Lorenzo over the whole field (neighbours in
 // other blocks read as in kQuantInterp).
-constexpr int kQuantP0 = 0, kQuantPred = 1, kQuantTrial = 2, kQuantInterp = 3, kQuantGlobal = 4;
+// kQuantShuffle: first-order Lorenzo for the bit-shuffle codec: no codes
+// and no histogram; each block's plane words (shuffle_words) go to its
+// staging slot in `codes` (kShufSlot words: the 5 mask words, then the
+// kept words in order).
+constexpr int kQuantP0 = 0, kQuantPred = 1, kQuantTrial = 2, kQuantInterp = 3, kQuantGlobal = 4, kQuantShuffle = 5;
 
 template <int ND, int MODE>
 __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom g, uint32_t mode, double eb,
@@ -229,7 +233,9 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
                                                const uint8_t* __restrict__ bpred, int32_t* __restrict__ coef,
                                                const uint32_t* __restrict__ cw_ref, uint8_t* __restrict__ choice,
                                                uint32_t* __restrict__ costs) {
-    constexpr bool PRED = MODE != kQuantP0;
+    constexpr bool PRED = MODE != kQuantP0 && MODE != kQuantShuffle;
+    // bit-shuffle: one block's plane words per wave
+    __shared__ uint32_t SW[MODE == kQuantShuffle ? 4 * kShufWords : 1];
     // q per block, regions padded by 8 words so the load-mapped writes of
     // four blocks do not fall into the same banks; one extra zero row
     constexpr int kQStride = kBlockElems + 8;
@@ -826,7 +832,28 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
             code[i] = u < (uint32_t)(2 * kRadius - 1) ? u + 1 : 0u;
             if (i < (int)nv) cmin = min(cmin, code[i]);
         }
-        if (blk) {
+        if (MODE == kQuantShuffle && blk) {
+            // lane = slots 8 s .. 8 s + 7 of the block (the segment): the
+            // block's plane words, its masks and kept words to its slot
+            uint32_t sym[8];
+#pragma unroll
+            for (int i = 0; i < 8; i++) sym[i] = i < (int)nv ? fold_code(code[i]) : 0u;
+            uint32_t w[3];
+            shuffle_words(sym, lane, &SW[wave * kShufWords], w);
+            const uint64_t m0 = __ballot(w[0] != 0), m1 = __ballot(w[1] != 0), m2 = __ballot(w[2] != 0);
+            uint32_t* S = reinterpret_cast<uint32_t*>(codes) + (uint64_t)kShufSlot * b;
+            if (lane < kMaskWords)
+                S[lane] = lane == 0 ? (uint32_t)m0
+                        : lane == 1 ? (uint32_t)(m0 >> 32)
+                        : lane == 2 ? (uint32_t)m1
+                        : lane == 3 ? (uint32_t)(m1 >> 32)
+                                    : (uint32_t)m2;
+            const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+            const uint32_t c0 = (uint32_t)__popcll(m0), c1 = (uint32_t)__popcll(m1);
+            if (w[0]) S[kMaskWords + __popcll(m0 & below)] = w[0];
+            if (w[1]) S[kMaskWords + c0 + __popcll(m1 & below)] = w[1];
+            if (w[2]) S[kMaskWords + c0 + c1 + __popcll(m2 & below)] = w[2];
+        } else if (blk) {
             uint4 pk;
             pk.x = code[0] | (code[1] << 16);
             pk.y = code[2] | (code[3] << 16);
@@ -841,7 +868,9 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
         // grid value itself, left most lanes of flat blocks adding to one
         // bin in the same instruction: 64-way serialised LDS atomics, 2.8 ms
         // instead of 1.9 on the 1024^3 fronts/spikes field.)
-        if (blk && MODE != kQuantInterp) {
+        if (MODE == kQuantShuffle) {
+            // no histogram: the bit-shuffle codec needs none
+        } else if (blk && MODE != kQuantInterp) {
             const uint32_t ca = (uint32_t)kRadius;
             uint32_t na = 0;
 #pragma unroll
@@ -964,6 +993,21 @@ void launch_quant(hipStream_t st, int grid, const float* x, const Geom& g, uint3
     } else {
         if (pred) FZ_QUANT(1, kQuantPred); else FZ_QUANT(1, kQuantP0);
     }
+}
+
+void launch_quant_shuffle(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,
+                          Misc* misc, uint32_t* hist, uint32_t* slots, uint32_t ntiles, uint32_t* tile_cnt,
+                          uint2* ostage, uint2* pstage) {
+    uint16_t* codes = reinterpret_cast<uint16_t*>(slots);
+    const int fixed_pred = 0;
+    const uint8_t* bpred = nullptr;
+    int32_t* coef = nullptr;
+    const uint32_t* cw_ref = nullptr;
+    uint8_t* choice = nullptr;
+    uint32_t* costs = nullptr;
+    if (g.ndim == 3) FZ_QUANT(3, kQuantShuffle);
+    else if (g.ndim == 2) FZ_QUANT(2, kQuantShuffle);
+    else FZ_QUANT(1, kQuantShuffle);
 }
 
 void launch_trial(hipStream_t st, int grid, const float* x, const Geom& g, uint32_t mode, double eb, int vec,

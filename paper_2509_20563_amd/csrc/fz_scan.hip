@@ -8,6 +8,9 @@
 //                 among the regression blocks; sets the section offsets
 //   SCAN_MASKS  - per-block plane-word mask (5 u32, bit-shuffle codec) ->
 //                 offset of the block's first kept word
+//   SCAN_SLOTS  - the same from the encoder's staging slots (the mask at the
+//                 start of each kShufSlot-word slot); the total kept words
+//                 go to misc->total_bits_enc
 #include <type_traits>
 
 #include "fz_common.h"
@@ -47,8 +50,9 @@ __global__ __launch_bounds__(256) void k_scan(const void* __restrict__ in, uint3
             } else if (KIND == SCAN_PMAP) {
                 const uint8_t pr = static_cast<const uint8_t*>(in)[base + k];
                 e = (pr == 2 ? 1ull : 0ull) | ((pr != 0 ? 1ull : 0ull) << 31);
-            } else if (KIND == SCAN_MASKS) {
-                const uint32_t* m = static_cast<const uint32_t*>(in) + 5 * (base + k);
+            } else if (KIND == SCAN_MASKS || KIND == SCAN_SLOTS) {
+                const uint32_t* m =
+                    static_cast<const uint32_t*>(in) + (KIND == SCAN_SLOTS ? kShufSlot : kMaskWords) * (base + k);
                 e = __popc(m[0]) + __popc(m[1]) + __popc(m[2]) + __popc(m[3]) + __popc(m[4]);
             } else {
                 e = static_cast<const uint16_t*>(in)[base + k];
@@ -89,6 +93,8 @@ __global__ __launch_bounds__(256) void k_scan(const void* __restrict__ in, uint3
                     misc->map_off = map ? 0u : 1u;
                     misc->off_chunks = L.chunks;
                     misc->off_stream = L.stream;
+                } else if (KIND == SCAN_SLOTS) {
+                    misc->total_bits_enc = total;
                 } else if (total != expect) {
                     atomicOr(&misc->flags, F_CORRUPT);
                 }
@@ -126,6 +132,9 @@ void launch_scan(hipStream_t st, int kind, const void* in, uint32_t n, uint64_t*
                            expect);
     else if (kind == SCAN_MASKS)
         hipLaunchKernelGGL(k_scan<SCAN_MASKS>, dim3(ntiles), dim3(256), 0, st, in, n, out, desc, ctr, ntiles, misc,
+                           expect);
+    else if (kind == SCAN_SLOTS)
+        hipLaunchKernelGGL(k_scan<SCAN_SLOTS>, dim3(ntiles), dim3(256), 0, st, in, n, out, desc, ctr, ntiles, misc,
                            expect);
     else
         hipLaunchKernelGGL(k_scan<SCAN_CHUNKS>, dim3(ntiles), dim3(256), 0, st, in, n, out, desc, ctr, ntiles, misc,

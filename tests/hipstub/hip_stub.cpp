@@ -303,7 +303,6 @@ namespace fz {
 uint32_t scan_tiles(uint32_t n) { return (n + 1023) / 1024; }
 uint32_t encode_groups(uint32_t ntiles) { return (ntiles + 7) / 8; }
 uint32_t feature_tiles(uint32_t nblocks) { return (nblocks + 15) / 16; }
-uint32_t shuffle_groups(uint32_t nblocks) { return (nblocks + 31) / 32; }
 
 #define K(name, ...) submit(st, Node{name, {__VA_ARGS__}})
 #define R(p) Ref{(const void*)(p), 0}
@@ -327,6 +326,14 @@ void launch_quant(hipStream_t st, int, const float* x, const Geom& g, uint32_t, 
       {tile_cnt, 4ull * ntiles}, {ostage, 8ull * ntiles * kTileBlocks * kBlockElems},
       {pstage, 8ull * ntiles * kTileBlocks * kBlockElems}, {bpred, fixed < 0 ? g.nblocks : 0ull},
       {coef, fixed < 0 || fixed == 2 ? 16ull * g.nblocks : 0ull});
+}
+void launch_quant_shuffle(hipStream_t st, int, const float* x, const Geom& g, uint32_t, double, int, Misc* misc,
+                          uint32_t*, uint32_t* slots, uint32_t ntiles, uint32_t* tile_cnt, uint2* ostage,
+                          uint2* pstage) {
+    // no histogram; the staging slots are the codes buffer
+    K("quant_shuffle", {x, 4 * g.N}, {misc, sizeof(Misc)}, {slots, 2ull * g.nblocks * kBlockElems},
+      {tile_cnt, 4ull * ntiles}, {ostage, 8ull * ntiles * kTileBlocks * kBlockElems},
+      {pstage, 8ull * ntiles * kTileBlocks * kBlockElems});
 }
 void launch_trial(hipStream_t st, int, const float* x, const Geom& g, uint32_t, double, int, Misc* misc, uint32_t,
                   const uint32_t* cw_ref, uint8_t* choice, uint32_t* costs) {
@@ -503,10 +510,9 @@ void launch_global_inverse(hipStream_t st, const Geom& g, int32_t* q, uint64_t* 
 void launch_interp_inverse(hipStream_t st, const Geom& g, int32_t* q, double, float* out) {
     K("interp_inverse", {q, 4ull * g.N}, {out, 4 * g.N});
 }
-void launch_shuffle(hipStream_t st, const Geom& g, const uint16_t* codes, uint8_t* out, uint64_t limit,
-                    uint64_t* desc, Misc* misc) {
-    K("shuffle", {codes, 2ull * g.nblocks * kBlockElems}, {out, limit}, {desc, 8ull * shuffle_groups(g.nblocks)},
-      {misc, sizeof(Misc)});
+void launch_shuffle_copy(hipStream_t st, const Geom& g, const uint32_t* slots, const uint64_t* off, uint8_t* out,
+                         uint64_t limit) {
+    K("shuffle_copy", {slots, 2ull * g.nblocks * kBlockElems}, {off, 8ull * g.nblocks}, {out, limit});
 }
 void launch_unshuffle(hipStream_t st, const Geom& g, const uint32_t* masks, const uint32_t* kept, uint64_t nkept,
                       const uint64_t* off, const uint32_t* opos, const int32_t* oval, const uint2* oidx,
