@@ -36,30 +36,83 @@ __device__ __forceinline__ void slot_coords(uint32_t s, uint32_t& lx, uint32_t& 
 // ------------------------------------------------------------- encoder
 // The plane words, masks and kept words of each block come from the
 // quantiser (k_quant<ND, kQuantShuffle>) in the block's staging slot, and
-// the slot scan (SCAN_SLOTS) gives the offset of its first kept word.  One
-// wave per block writes the 5 mask words after the header and the kept
-// words to the stream; nothing beyond limit (the verbatim size: such a
-// container is written verbatim by k_finalize).
+// the slot scan (SCAN_SLOTS) gives the offset of its first kept word.  A
+// wave takes 64 consecutive blocks (lane = block): their mask words go
+// after the header, and their kept words, one contiguous run of the
+// stream, are written in order: with fewer than 32 kept words per block on
+// average lane = output word, its block found by a binary search over the
+// wave's word prefix in LDS, else block by block.  Nothing beyond limit
+// (the verbatim size: such a container is written verbatim by k_finalize).
 __global__ __launch_bounds__(256) void k_shuffle_copy(Geom g, const uint32_t* __restrict__ slots,
                                                       const uint64_t* __restrict__ off, uint8_t* __restrict__ out,
                                                       uint64_t limit) {
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t nw = gridDim.x * 4;
+    __shared__ uint32_t s_pre[4][64];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t nw = (uint64_t)gridDim.x * 4;
     const uint64_t words_at = align16((uint64_t)kHdr + 4ull * kMaskWords * g.nblocks);
     uint32_t* outw = reinterpret_cast<uint32_t*>(out);
-    const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
-    for (uint32_t b = b0; b < g.nblocks; b += nw) {  // wave-uniform
-        const uint32_t* S = slots + (uint64_t)kShufSlot * b;
-        const uint32_t cnt = (uint32_t)(__popc(S[0]) + __popc(S[1]) + __popc(S[2]) + __popc(S[3]) + __popc(S[4]));
-        if (lane < kMaskWords) {
-            const uint64_t at = (uint64_t)kHdr + 4ull * (kMaskWords * (uint64_t)b + lane);
-            if (at + 4 <= limit) outw[at >> 2] = S[lane];
+    uint32_t* P = s_pre[wave];
+    for (uint64_t c0 = ((uint64_t)blockIdx.x * 4 + wave) * 64; c0 < g.nblocks; c0 += nw * 64) {
+        const uint64_t b = c0 + lane;
+        const bool in = b < g.nblocks;
+        const uint32_t* S = slots + (uint64_t)kShufSlot * (in ? b : c0);
+        uint32_t m[kMaskWords];
+#pragma unroll
+        for (int k = 0; k < kMaskWords; k++) m[k] = in ? S[k] : 0u;
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int k = 0; k < kMaskWords; k++) {
+            cnt += (uint32_t)__popc(m[k]);
+            const uint64_t at = (uint64_t)kHdr + 4ull * (kMaskWords * b + k);
+            if (in && at + 4 <= limit) outw[at >> 2] = m[k];
         }
-        const uint64_t base = off[b];
-        for (uint32_t j = lane; j < cnt; j += 64) {
-            const uint64_t at = words_at + 4 * (base + j);
-            if (at + 4 <= limit) outw[at >> 2] = S[kMaskWords + j];
+        const uint32_t incl = wave_incl_scan(cnt);
+        P[lane] = incl - cnt;
+        const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        const uint64_t base = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)off[c0]) |
+                               ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(off[c0] >> 32))
+                                << 32));
+        __builtin_amdgcn_wave_barrier();
+        if (total >= 64u * 32u) {
+            // dense (32 or more kept words per block on average): block by
+            // block, lane = word of the block
+            // four blocks at a time, every load issued before the stores
+            for (uint32_t k0 = 0; k0 < 64; k0 += 4) {
+                uint32_t v[4][3];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const uint32_t ck = (uint32_t)__builtin_amdgcn_readlane((int)cnt, (int)(k0 + u));
+                    const uint32_t* src = slots + (uint64_t)kShufSlot * (c0 + k0 + u) + kMaskWords;
+#pragma unroll
+                    for (int r = 0; r < 3; r++) {
+                        const uint32_t j = lane + 64 * r;
+                        v[u][r] = j < ck ? src[j] : 0u;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const uint32_t ck = (uint32_t)__builtin_amdgcn_readlane((int)cnt, (int)(k0 + u));
+                    const uint32_t pk = P[k0 + u];
+#pragma unroll
+                    for (int r = 0; r < 3; r++) {
+                        const uint32_t j = lane + 64 * r;
+                        const uint64_t at = words_at + 4 * (base + pk + j);
+                        if (j < ck && at + 4 <= limit) outw[at >> 2] = v[u][r];
+                    }
+                }
+            }
+        } else {
+            for (uint32_t q = lane; q < total; q += 64) {
+                // the last block whose first word is at or before q
+                uint32_t k = 0;
+#pragma unroll
+                for (uint32_t st = 32; st > 0; st >>= 1)
+                    if (P[k + st] <= q) k += st;
+                const uint64_t at = words_at + 4 * (base + q);
+                if (at + 4 <= limit) outw[at >> 2] = slots[(uint64_t)kShufSlot * (c0 + k) + kMaskWords + (q - P[k])];
+            }
         }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -176,7 +229,8 @@ __global__ __launch_bounds__(256) void k_unshuffle(Geom g, const uint32_t* __res
 // ------------------------------------------------------------ launchers
 void launch_shuffle_copy(hipStream_t st, const Geom& g, const uint32_t* slots, const uint64_t* off, uint8_t* out,
                          uint64_t limit) {
-    uint32_t grid = (g.nblocks + 3) / 4;
+    // 64 blocks per wave, 4 waves per workgroup
+    uint32_t grid = (uint32_t)((g.nblocks + 255) / 256);
     if (grid > 8192) grid = 8192;
     if (!grid) return;
     hipLaunchKernelGGL(k_shuffle_copy, dim3(grid), dim3(256), 0, st, g, slots, off, out, limit);
