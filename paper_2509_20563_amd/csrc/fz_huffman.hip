@@ -201,7 +201,8 @@ __device__ __forceinline__ uint32_t code_entries(const uint4& pk, uint32_t nv, c
 }
 
 // Single pass over the codes.  A workgroup takes kEncTiles consecutive
-// 4-block tiles: it reads their codes once (kept in registers), writes the
+// 4-block tiles: it reads their codes once (all loads issued together, kept
+// packed in registers), writes the
 // chunk table, publishes the group's bit count and obtains the group's
 // stream offset by a decoupled look-back over groups, then writes the bits
 // tile by tile.  A group publishes its count before it waits, and waits
@@ -229,26 +230,21 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ cod
     __syncthreads();
     const uint32_t grp = blockIdx.x;
     const uint32_t tile0 = grp * kEncTiles;
-    // pass over the group's codes: codeword entries, chunk table, tile
-    // totals; each tile's codes are loaded while the previous one is
-    // processed
-    uint32_t e8[kEncTiles][8];
-    uint32_t nv_next;
-    uint4 pk_next = load_codes<ND>(codes, g, tile0 < ntiles ? tile0 * kTileBlocks + wave : g.nblocks, lane, nv_next);
+    // pass over the group's codes: every tile's codes loaded at once
+    // (packed, 4 registers per tile, so the loads' latencies overlap), then
+    // the tiles' bit counts and totals; the codeword entries are looked up
+    // again when the bits are written
+    uint4 pk[kEncTiles];
+    uint32_t nvk[kEncTiles];
 #pragma unroll
     for (uint32_t k = 0; k < kEncTiles; k++) {
         const uint32_t b = (tile0 + k) * kTileBlocks + wave;
-        const uint4 pk = pk_next;
-        const uint32_t nv = nv_next;
-        if (k + 1 < kEncTiles)
-            pk_next = load_codes<ND>(codes, g, tile0 + k + 1 < ntiles ? b + kTileBlocks : g.nblocks, lane, nv_next);
-        uint32_t nb = 0;
-        if (tile0 + k < ntiles) {
-            nb = code_entries(pk, nv, CW, e8[k]);
-        } else {
+        pk[k] = load_codes<ND>(codes, g, tile0 + k < ntiles ? b : g.nblocks, lane, nvk[k]);
+    }
 #pragma unroll
-            for (int i = 0; i < 8; i++) e8[k][i] = 0;
-        }
+    for (uint32_t k = 0; k < kEncTiles; k++) {
+        uint32_t e8[8];
+        const uint32_t nb = tile0 + k < ntiles ? code_entries(pk[k], nvk[k], CW, e8) : 0u;
         const uint32_t incl = wave_incl_scan(nb);
         if (lane == 63) wsum[k][wave] = incl;
     }
@@ -287,17 +283,19 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ cod
         }
         // the lane's bit string as two shift-or chains of 4 codewords
         // (at most 48 bits each)
+        uint32_t e8[8];
+        code_entries(pk[k], nvk[k], CW, e8);
         uint64_t a0 = 0, a1 = 0;
         uint32_t n0 = 0, n1 = 0;
 #pragma unroll
         for (int i = 0; i < 4; i++) {
-            const uint32_t e = e8[k][i], l = e >> 16;
+            const uint32_t e = e8[i], l = e >> 16;
             a0 = (a0 << l) | (e & 0xFFFFu);
             n0 += l;
         }
 #pragma unroll
         for (int i = 4; i < 8; i++) {
-            const uint32_t e = e8[k][i], l = e >> 16;
+            const uint32_t e = e8[i], l = e >> 16;
             a1 = (a1 << l) | (e & 0xFFFFu);
             n1 += l;
         }
