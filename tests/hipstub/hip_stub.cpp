@@ -301,7 +301,7 @@ hipError_t hipGraphDestroy(hipGraph_t g) {
 namespace fz {
 
 uint32_t scan_tiles(uint32_t n) { return (n + 1023) / 1024; }
-uint32_t encode_groups(uint32_t ntiles) { return (ntiles + 7) / 8; }
+uint32_t encode_groups(uint32_t ntiles) { return (ntiles + 11) / 12; }
 uint32_t feature_tiles(uint32_t nblocks) { return (nblocks + 15) / 16; }
 
 #define K(name, ...) submit(st, Node{name, {__VA_ARGS__}})
