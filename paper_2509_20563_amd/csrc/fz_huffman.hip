@@ -168,7 +168,8 @@ __device__ __forceinline__ void or_shl128(uint64_t& hi, uint64_t& lo, uint64_t v
     lo |= upper ? 0ull : (v << s);
 }
 
-constexpr int kEncWords = kTileBlocks * kBlockElems * kLmax / 32 + 8;
+// words of one tile at most (every value at kLmax bits)
+constexpr int kEncTileWords = kTileBlocks * kBlockElems * kLmax / 32;
 
 // A lane's 8 codes of block b, segment s (from the start of the codes when
 // the block or segment holds no values, so the load is unconditional and
@@ -210,8 +211,10 @@ __device__ __forceinline__ uint32_t code_entries(const uint4& pk, uint32_t nv, c
 // chain never waits on a workgroup that is not running; the wait is bounded
 // anyway (F_TIMEOUT).
 // tiles per group: 12 measured fastest at 1024^3 (0.88 ms; 4: 1.21, 8:
-// 0.93, 16: 0.92)
+// 0.93, 16: 0.92); the bits are written in passes of kEncPass tiles
 constexpr uint32_t kEncTiles = 12;
+constexpr uint32_t kEncPass = 6;
+constexpr int kEncWords = (int)kEncPass * kEncTileWords + 8;  // one pass (+ bit offset and window overrun)
 
 template <int ND>
 __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ codes, Geom g,
@@ -220,7 +223,8 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ cod
                                                 uint64_t* __restrict__ tile_start, uint32_t* __restrict__ tfirst,
                                                 uint32_t* __restrict__ tlast) {
     __shared__ uint32_t CW[kBins];
-    __shared__ uint32_t W[2][kEncWords];  // alternate tiles: one barrier per tile
+    __shared__ uint32_t W[kEncWords];  // one pass of tiles
+    __shared__ uint32_t s_carry[2];    // a pass's partial last word, for the next pass (by pass parity)
     __shared__ uint32_t wsum[kEncTiles][4];
     __shared__ uint64_t s_excl;
     uint16_t* chunks = reinterpret_cast<uint16_t*>(out + misc->off_chunks);
@@ -228,7 +232,7 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ cod
     const uint32_t t = threadIdx.x, lane = t & 63;
     const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 6));
     for (uint32_t i = t; i < (uint32_t)kBins; i += 256) CW[i] = cw_g[i];
-    for (uint32_t i = t; i < (uint32_t)(2 * kEncWords); i += 256) (&W[0][0])[i] = 0;
+    for (uint32_t i = t; i < (uint32_t)kEncWords; i += 256) W[i] = 0;
     __syncthreads();
     const uint32_t grp = blockIdx.x;
     const uint32_t tile0 = grp * kEncTiles;
@@ -268,74 +272,97 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ cod
         }
     }
     __syncthreads();
-    uint64_t G = s_excl;
+    // the bits, in passes of kEncPass tiles: each pass's tiles are OR-ed
+    // into one LDS buffer (one barrier), then its words are stored as one
+    // contiguous run.  The group's partial first and last words are shared
+    // with the neighbouring groups and merged by k_finalize (tile_start of
+    // the group's first tile; its other tiles start at 0, nothing to
+    // merge); a pass's partial last word is carried into the next pass.
+    const uint64_t G0 = s_excl;
+    const uint32_t tend = min(tile0 + kEncTiles, ntiles);  // past the group's last tile
+    if (t < kEncTiles && tile0 + t < ntiles) tile_start[tile0 + t] = t == 0 ? G0 : 0ull;
+    uint64_t G = G0;
 #pragma unroll
-    for (uint32_t k = 0; k < kEncTiles; k++) {
-        const uint32_t tile = tile0 + k;
-        if (tile >= ntiles) break;  // uniform
-        uint32_t* Wk = W[k & 1];
-        uint32_t wpre = 0, T = 0;
-        for (uint32_t w = 0; w < 4; w++) {
-            if (w < wave) wpre += wsum[k][w];
-            T += wsum[k][w];
-        }
-        if (t == 0) {
-            tile_start[tile] = G;  // k_finalize merges the shared boundary words
-            if (tile != ntiles - 1 && T < 32) atomicOr(&misc->flags, F_INTERNAL);
-        }
-        // the lane's bit string as two shift-or chains of 4 codewords
-        // (at most 48 bits each)
-        uint32_t e8[8];
-        code_entries(pk[k], nvk[k], CW, e8);
-        uint64_t a0 = 0, a1 = 0;
-        uint32_t n0 = 0, n1 = 0;
+    for (uint32_t h = 0; h < kEncTiles / kEncPass; h++) {
+        const uint32_t k0 = h * kEncPass;
+        if (tile0 + k0 >= ntiles) break;  // uniform
+        const uint32_t shp = (uint32_t)(G & 31);
+        uint32_t rel = 0;  // bits of the pass's earlier tiles
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-            const uint32_t e = e8[i], l = e >> 16;
-            a0 = (a0 << l) | (e & 0xFFFFu);
-            n0 += l;
-        }
+        for (uint32_t kk = 0; kk < kEncPass; kk++) {
+            const uint32_t k = k0 + kk;
+            const uint32_t tile = tile0 + k;
+            if (tile >= ntiles) break;  // uniform
+            uint32_t wpre = 0, T = 0;
+            for (uint32_t w = 0; w < 4; w++) {
+                if (w < wave) wpre += wsum[k][w];
+                T += wsum[k][w];
+            }
+            if (t == 0 && tile != ntiles - 1 && T < 32) atomicOr(&misc->flags, F_INTERNAL);
+            // the lane's bit string as two shift-or chains of 4 codewords
+            // (at most 48 bits each)
+            uint32_t e8[8];
+            code_entries(pk[k], nvk[k], CW, e8);
+            uint64_t a0 = 0, a1 = 0;
+            uint32_t n0 = 0, n1 = 0;
 #pragma unroll
-        for (int i = 4; i < 8; i++) {
-            const uint32_t e = e8[i], l = e >> 16;
-            a1 = (a1 << l) | (e & 0xFFFFu);
-            n1 += l;
-        }
-        const uint32_t nb = n0 + n1;
-        const uint32_t sh = (uint32_t)(G & 31);
-        // the scan runs with every lane active (lanes with no bits add 0)
-        const uint32_t incl = wave_incl_scan(nb);
-        if (nb) {
-            // place the string at bit o of word w0, most significant first:
-            // 128-bit window (hi, lo) = words w0 .. w0 + 3 (o + nb <= 127)
-            const uint32_t p = sh + wpre + incl - nb;
-            const uint32_t o = p & 31, w0 = p >> 5;
-            uint64_t hi = 0, lo = 0;
-            or_shl128(hi, lo, a0, (128 - o - n0) & 127);  // a0 = 0 when n0 = 0
-            or_shl128(hi, lo, a1, 128 - o - nb);
-            const uint32_t o0 = (uint32_t)(hi >> 32), o1 = (uint32_t)hi, o2 = (uint32_t)(lo >> 32),
-                           o3 = (uint32_t)lo;
-            if (o0) atomicOr(&Wk[w0], o0);
-            if (o1) atomicOr(&Wk[w0 + 1], o1);
-            if (o2) atomicOr(&Wk[w0 + 2], o2);
-            if (o3) atomicOr(&Wk[w0 + 3], o3);
+            for (int i = 0; i < 4; i++) {
+                const uint32_t e = e8[i], l = e >> 16;
+                a0 = (a0 << l) | (e & 0xFFFFu);
+                n0 += l;
+            }
+#pragma unroll
+            for (int i = 4; i < 8; i++) {
+                const uint32_t e = e8[i], l = e >> 16;
+                a1 = (a1 << l) | (e & 0xFFFFu);
+                n1 += l;
+            }
+            const uint32_t nb = n0 + n1;
+            // the scan runs with every lane active (lanes with no bits add 0)
+            const uint32_t incl = wave_incl_scan(nb);
+            if (nb) {
+                // place the string at bit o of word w0 (from the pass's
+                // first word), most significant first: 128-bit window
+                // (hi, lo) = words w0 .. w0 + 3 (o + nb <= 127)
+                const uint32_t p = shp + rel + wpre + incl - nb;
+                const uint32_t o = p & 31, w0 = p >> 5;
+                uint64_t hi = 0, lo = 0;
+                or_shl128(hi, lo, a0, (128 - o - n0) & 127);  // a0 = 0 when n0 = 0
+                or_shl128(hi, lo, a1, 128 - o - nb);
+                const uint32_t o0 = (uint32_t)(hi >> 32), o1 = (uint32_t)hi, o2 = (uint32_t)(lo >> 32),
+                               o3 = (uint32_t)lo;
+                if (o0) atomicOr(&W[w0], o0);
+                if (o1) atomicOr(&W[w0 + 1], o1);
+                if (o2) atomicOr(&W[w0 + 2], o2);
+                if (o3) atomicOr(&W[w0 + 3], o3);
+            }
+            rel += T;
         }
         __syncthreads();
-        // interior words go to the stream; the partial first and last words
-        // are shared with the neighbouring tiles and merged by k_finalize;
-        // the buffer is cleared for the tile after next (the barrier of the
-        // next tile separates the two)
-        const uint32_t nwords = (sh + T + 31) >> 5;
-        const bool last_partial = ((sh + T) & 31) != 0 && tile != ntiles - 1;
+        // the pass's words: the first one shares bits with the previous
+        // pass (carried) or group (parked in tfirst), the last one with the
+        // next pass (carried) or group (parked in tlast of the group's last
+        // tile); the field's very last word is stored
+        const bool last_pass = tile0 + k0 + kEncPass >= tend;
+        const uint32_t nwords = (shp + rel + 31) >> 5;
+        const bool end_part = ((shp + rel) & 31) != 0;
         const uint64_t wbase = G >> 5;
+        // pass h reads the slot pass h - 1 wrote and writes the other one:
+        // the writer of this pass's carry may run before every thread has
+        // read the previous one
+        const uint32_t carry_in = s_carry[(h + 1) & 1];
         for (uint32_t w = t; w < nwords; w += 256) {
-            const uint32_t v = Wk[w];
-            Wk[w] = 0;
-            if (w == 0 && sh != 0) tfirst[tile] = v;
-            else if (w == nwords - 1 && last_partial) tlast[tile] = v;
+            uint32_t v = W[w];
+            W[w] = 0;
+            const bool first = w == 0 && shp != 0, last = w == nwords - 1 && end_part;
+            if (first && h > 0) v |= carry_in;
+            if (first && h == 0) tfirst[tile0] = v;
+            else if (last && !last_pass) s_carry[h & 1] = v;
+            else if (last && tend != ntiles) tlast[tend - 1] = v;
             else stream[wbase + w] = v;
         }
-        G += T;
+        G += rel;
+        __syncthreads();
     }
 }
 
