@@ -166,17 +166,20 @@ __global__ __launch_bounds__(256) void k_interp_final_x(Geom g, const int32_t* _
     }
 }
 
-// Stride 1, the y and x passes of a row together (2D/3D, after the z
-// pass): workgroup = 256 pairs (512 values) of one row, rows over
-// blockIdx.y.  The even point of each pair is final in the grid values
-// for an even y and gets its y prediction (the rows y -/+ 1, 3, whose even
-// points are final) for an odd y; the even points go through LDS (with the
-// pairs just left and the two just right of the workgroup's range, rebuilt
-// by three lanes) to the x prediction of the odd points, and the pair is
-// written dequantised.  The grid values are only read.
+// Stride 1, the y and x passes together (2D/3D, after the z pass):
+// workgroup = 256 pairs (512 values) of kYXRows consecutive rows of one
+// plane (y0 = kYXRows j), rows groups over blockIdx.y.  Each thread loads
+// its pair of every row of the group once, and the even points of the rows
+// y0 - 2, y0 + 8 and y0 + 10 (final, as every even row's even points are),
+// so an odd row's y prediction (rows y -/+ 1, 3) reads registers.  The
+// rows' even points go through LDS (with the pairs just left and the two
+// just right of the range, rebuilt by three lanes) to the x prediction of
+// the odd points; each pair is written dequantised.  The grid values are
+// only read.
+constexpr int kYXRows = 8;
 __global__ __launch_bounds__(256) void k_interp_final_yx(Geom g, const int32_t* __restrict__ q, double e2,
-                                                         float* __restrict__ out, uint32_t nrows) {
-    __shared__ int32_t E[256 + 3];  // even points of the pairs m0 - 1 .. m0 + 257
+                                                         float* __restrict__ out, uint32_t ngroups, uint32_t gpp) {
+    __shared__ int32_t E[kYXRows][256 + 3];  // even points of the pairs m0 - 1 .. m0 + 257, per row
     const uint32_t t = threadIdx.x;
     const uint32_t n0 = g.n[0], n1 = g.n[1];
     const uint32_t m0 = blockIdx.x * 256;
@@ -190,51 +193,86 @@ __global__ __launch_bounds__(256) void k_interp_final_yx(Geom g, const int32_t* 
     const bool halo = t < 3;
     const uint32_t hx = t == 0 ? 2 * m0 - 2 : 2 * (m0 + 255 + t);
     const bool hin = halo && (t == 0 ? m0 > 0 : hx < n0);
-    for (uint32_t r = blockIdx.y; r < nrows; r += gridDim.y) {
-        const uint32_t y = r % n1;
-        const bool ypass = (y & 1) != 0;
-        const uint64_t rb = (uint64_t)n0 * r;
-        auto even_at = [&](uint32_t xx) -> int32_t {
-            const uint64_t i = rb + xx;
+    for (uint32_t u = blockIdx.y; u < ngroups; u += gridDim.y) {
+        const uint32_t z = u / gpp, y0 = (u - z * gpp) * kYXRows;
+        const uint64_t pb = (uint64_t)n0 * n1 * z;  // the plane
+        // even point of row yy at column xx, final (yy even) or rebuilt
+        // from the rows yy -/+ 1, 3 (yy odd): the halo lanes' path
+        auto even_at = [&](uint32_t xx, uint32_t yy) -> int32_t {
+            const uint64_t i = pb + (uint64_t)n0 * yy + xx;
             uint32_t v = (uint32_t)q[i];
-            if (ypass) {
+            if (yy & 1) {
                 const int32_t m1 = q[i - sy];
-                const int32_t p1 = y + 1 < n1 ? q[i + sy] : 0;
-                const int32_t m3 = y >= 3 ? q[i - 3 * sy] : 0;
-                const int32_t p3 = y + 3 < n1 ? q[i + 3 * sy] : 0;
-                v += (uint32_t)pick_pred(y, n1, 1, m3, m1, p1, p3);
+                const int32_t p1 = yy + 1 < n1 ? q[i + sy] : 0;
+                const int32_t m3 = yy >= 3 ? q[i - 3 * sy] : 0;
+                const int32_t p3 = yy + 3 < n1 ? q[i + 3 * sy] : 0;
+                v += (uint32_t)pick_pred(yy, n1, 1, m3, m1, p1, p3);
             }
             return (int32_t)v;
         };
-        int32_t e0 = 0, o = 0;
-        if (in) {
-            if (v2) {
-                const int2 v = *reinterpret_cast<const int2*>(q + rb + x);
-                e0 = v.x;
-                o = v.y;
-            } else {
-                e0 = q[rb + x];
-                if (two) o = q[rb + x + 1];
+        // this thread's pairs of the group's rows, and the even points of
+        // rows y0 - 2, y0 + 8, y0 + 10
+        int32_t ev[kYXRows + 6];  // even points of rows y0 - 3 .. y0 + 10 (odd rows outside unused)
+        int32_t od[kYXRows];
+#pragma unroll
+        for (int k = 0; k < kYXRows + 6; k++) ev[k] = 0;
+#pragma unroll
+        for (int k = 0; k < kYXRows; k++) {
+            od[k] = 0;
+            const uint32_t yy = y0 + k;
+            if (in && yy < n1) {
+                const uint64_t i = pb + (uint64_t)n0 * yy + x;
+                if (v2) {
+                    const int2 v = *reinterpret_cast<const int2*>(q + i);
+                    ev[k + 3] = v.x;
+                    od[k] = v.y;
+                } else {
+                    ev[k + 3] = q[i];
+                    if (two) od[k] = q[i + 1];
+                }
             }
-            if (ypass) e0 = even_at(x);
         }
-        E[1 + t] = e0;
-        if (halo) E[t == 0 ? 0 : 256 + t] = hin ? even_at(hx) : 0;
+        if (in) {
+            if (y0 >= 2) ev[1] = q[pb + (uint64_t)n0 * (y0 - 2) + x];
+            if (y0 + 8 < n1) ev[kYXRows + 3] = q[pb + (uint64_t)n0 * (y0 + 8) + x];
+            if (y0 + 10 < n1) ev[kYXRows + 5] = q[pb + (uint64_t)n0 * (y0 + 10) + x];
+        }
+        // odd rows: the y prediction from the even rows around them
+        int32_t e[kYXRows];
+#pragma unroll
+        for (int k = 0; k < kYXRows; k++) {
+            const uint32_t yy = y0 + k;
+            e[k] = ev[k + 3];
+            if (k & 1) {
+                const int32_t pr = pick_pred(yy, n1, 1, yy >= 3 ? ev[k] : 0, ev[k + 2],
+                                             yy + 1 < n1 ? ev[k + 4] : 0, yy + 3 < n1 ? ev[k + 6] : 0);
+                e[k] = (int32_t)((uint32_t)e[k] + (uint32_t)pr);
+            }
+            E[k][1 + t] = in ? e[k] : 0;
+            if (halo) E[k][t == 0 ? 0 : 256 + t] = (hin && yy < n1) ? even_at(hx, yy) : 0;
+        }
         __syncthreads();
-        if (two) {
-            const uint32_t ca = x + 1;
-            const int32_t p1 = ca + 1 < n0 ? E[t + 2] : 0;
-            const int32_t m3 = ca >= 3 ? E[t] : 0;
-            const int32_t p3 = ca + 3 < n0 ? E[t + 3] : 0;
-            o = (int32_t)((uint32_t)o + (uint32_t)pick_pred(ca, n0, 1, m3, e0, p1, p3));
-        }
-        if (v2) {
-            typedef float f32x2 __attribute__((ext_vector_type(2)));
-            const f32x2 w = {dq(e0), dq(o)};
-            __builtin_nontemporal_store(w, reinterpret_cast<f32x2*>(out + rb + x));
-        } else if (in) {
-            out[rb + x] = dq(e0);
-            if (two) out[rb + x + 1] = dq(o);
+#pragma unroll
+        for (int k = 0; k < kYXRows; k++) {
+            const uint32_t yy = y0 + k;
+            if (yy >= n1) break;  // uniform
+            int32_t o = od[k];
+            if (two) {
+                const uint32_t ca = x + 1;
+                const int32_t p1 = ca + 1 < n0 ? E[k][t + 2] : 0;
+                const int32_t m3 = ca >= 3 ? E[k][t] : 0;
+                const int32_t p3 = ca + 3 < n0 ? E[k][t + 3] : 0;
+                o = (int32_t)((uint32_t)o + (uint32_t)pick_pred(ca, n0, 1, m3, e[k], p1, p3));
+            }
+            const uint64_t i = pb + (uint64_t)n0 * yy + x;
+            if (v2) {
+                typedef float f32x2 __attribute__((ext_vector_type(2)));
+                const f32x2 w = {dq(e[k]), dq(o)};
+                __builtin_nontemporal_store(w, reinterpret_cast<f32x2*>(out + i));
+            } else if (in) {
+                out[i] = dq(e[k]);
+                if (two) out[i + 1] = dq(o);
+            }
         }
         __syncthreads();
     }
@@ -293,9 +331,11 @@ static void interp_inverse_passes(hipStream_t st, const Geom& g, int32_t* q, dou
     }
     const uint64_t rows = (uint64_t)g.n[1] * g.n[2];
     if (ND >= 2 && g.n[1] > 1) {
-        // y and x together, the output written
-        hipLaunchKernelGGL(k_interp_final_yx, dim3((npairs + 255) / 256, cap(rows)), dim3(256), 0, st, g, q, e2, out,
-                           (uint32_t)rows);
+        // y and x together, the output written: groups of kYXRows rows
+        const uint32_t gpp = (g.n[1] + kYXRows - 1) / kYXRows;
+        const uint64_t ngroups = (uint64_t)gpp * g.n[2];
+        hipLaunchKernelGGL(k_interp_final_yx, dim3((npairs + 255) / 256, cap(ngroups)), dim3(256), 0, st, g, q, e2,
+                           out, (uint32_t)ngroups, gpp);
     } else {
         hipLaunchKernelGGL(k_interp_final_x, dim3((npairs + 255) / 256, cap(rows)), dim3(256), 0, st, g, q, e2, out,
                            (uint32_t)rows);
