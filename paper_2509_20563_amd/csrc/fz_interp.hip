@@ -8,9 +8,10 @@
 //                      coordinate a multiple of 8), one thread per line
 //   k_interp_level   - strides 4 and 2: the points of one stride and axis,
 //                      one thread per point
-//   k_interp_pairs   - stride 1, z pass: a thread per pair of points
-//                      (2m, 2m + 1) of a row (the even one is the level's
-//                      point), so that stores cover whole lines
+//   k_interp_z       - stride 1, z pass: a thread per pair of points
+//                      (2m, 2m + 1) of an even row through a group of 8
+//                      planes (the even one is the level's point), so that
+//                      stores cover whole lines
 //   k_interp_final_yx - stride 1, y and x passes of a row together (2D/3D):
 //                      the even points' y prediction, exchanged in LDS for
 //                      the odd points' x prediction, the pair dequantised
@@ -92,35 +93,47 @@ __global__ __launch_bounds__(256) void k_interp_level(Geom g, int32_t* __restric
     }
 }
 
-// Stride 1, the last level.  A thread takes the pair of points (2m, 2m + 1)
-// of a row, so that every store covers whole lines.  The z pass (the even
-// point of the pair is the level's point, the odd one is rewritten
-// unchanged), in place:
-template <int AXIS>
-__global__ __launch_bounds__(256) void k_interp_pairs(Geom g, int32_t* __restrict__ q, uint32_t f1, uint32_t s1,
-                                                      uint32_t c1, uint32_t f2, uint32_t s2, uint32_t nrows) {
-    const uint32_t m = blockIdx.x * 256 + threadIdx.x;
-    const uint32_t x = 2 * m;
-    if (x >= g.n[0]) return;
-    const bool two = x + 1 < g.n[0];
-    const bool v2 = two && (g.n[0] & 1) == 0;  // 8-byte aligned pairs
-    const uint64_t sa = AXIS == 1 ? (uint64_t)g.n[0] : (uint64_t)g.n[0] * g.n[1];
-    for (uint32_t r = blockIdx.y; r < nrows; r += gridDim.y) {
-        const uint32_t j = r % c1, k = r / c1;
-        const uint32_t y = f1 + s1 * j, z = f2 + s2 * k;
-        const uint64_t idx = (uint64_t)x + (uint64_t)g.n[0] * ((uint64_t)y + (uint64_t)g.n[1] * z);
-        const uint32_t ca = AXIS == 1 ? y : z, na = g.n[AXIS];
-        const int32_t m1 = q[idx - sa];
-        const int32_t p1 = ca + 1 < na ? q[idx + sa] : 0;
-        const int32_t m3 = ca >= 3 ? q[idx - 3 * sa] : 0;
-        const int32_t p3 = ca + 3 < na ? q[idx + 3 * sa] : 0;
-        const int32_t pr = pick_pred(ca, na, 1, m3, m1, p1, p3);
-        if (v2) {
-            int2 v = *reinterpret_cast<const int2*>(q + idx);
-            v.x = (int32_t)((uint32_t)v.x + (uint32_t)pr);
-            *reinterpret_cast<int2*>(q + idx) = v;
-        } else {
-            q[idx] = (int32_t)((uint32_t)q[idx] + (uint32_t)pr);
+// rows (planes) per workgroup group of the stride-1 passes
+constexpr int kYXRows = 8;
+
+// Stride 1, the z pass (3D): the points (x even, y even, z odd).  A
+// thread takes the pair (2m, 2m + 1) of one even row y through a group of
+// kYXRows planes (z0 = kYXRows j): it loads the even planes z0 - 2 ..
+// z0 + 10 once (final grid values) and rewrites the pairs of the group's
+// odd planes, the even point predicted along z, the odd one unchanged (so
+// the stores cover whole lines), in place.
+__global__ __launch_bounds__(256) void k_interp_z(Geom g, int32_t* __restrict__ q, uint32_t ngroups, uint32_t gpr) {
+    const uint32_t n0 = g.n[0], n2 = g.n[2];
+    const uint32_t x = 2 * (blockIdx.x * 256 + threadIdx.x);
+    if (x >= n0) return;
+    const bool two = x + 1 < n0;
+    const bool v2 = two && (n0 & 1) == 0;
+    const uint64_t sz = (uint64_t)n0 * g.n[1];
+    for (uint32_t u = blockIdx.y; u < ngroups; u += gridDim.y) {
+        const uint32_t zg = u / gpr, y = 2 * (u - zg * gpr), z0 = zg * kYXRows;
+        const uint64_t rb = (uint64_t)n0 * y + x;  // (x, y) in plane 0
+        // even points of planes z0 - 3 .. z0 + 10 (the even ones)
+        int32_t ev[kYXRows + 6];
+#pragma unroll
+        for (int j = 0; j < kYXRows + 6; j += 2) {
+            const int zz = (int)z0 - 3 + j + 1;  // even plane z0 - 2 + j
+            ev[j] = 0;
+            ev[j + 1] = (zz >= 0 && (uint32_t)zz < n2) ? q[rb + sz * (uint32_t)zz] : 0;
+        }
+#pragma unroll
+        for (int k = 1; k < kYXRows; k += 2) {
+            const uint32_t z = z0 + k;
+            if (z >= n2) break;  // uniform
+            const uint64_t i = rb + sz * z;
+            const int32_t pr = pick_pred(z, n2, 1, z >= 3 ? ev[k] : 0, ev[k + 2], z + 1 < n2 ? ev[k + 4] : 0,
+                                         z + 3 < n2 ? ev[k + 6] : 0);
+            if (v2) {
+                int2 v = *reinterpret_cast<const int2*>(q + i);
+                v.x = (int32_t)((uint32_t)v.x + (uint32_t)pr);
+                *reinterpret_cast<int2*>(q + i) = v;
+            } else {
+                q[i] = (int32_t)((uint32_t)q[i] + (uint32_t)pr);
+            }
         }
     }
 }
@@ -176,7 +189,6 @@ __global__ __launch_bounds__(256) void k_interp_final_x(Geom g, const int32_t* _
 // just right of the range, rebuilt by three lanes) to the x prediction of
 // the odd points; each pair is written dequantised.  The grid values are
 // only read.
-constexpr int kYXRows = 8;
 __global__ __launch_bounds__(256) void k_interp_final_yx(Geom g, const int32_t* __restrict__ q, double e2,
                                                          float* __restrict__ out, uint32_t ngroups, uint32_t gpp) {
     __shared__ int32_t E[kYXRows][256 + 3];  // even points of the pairs m0 - 1 .. m0 + 257, per row
@@ -323,11 +335,11 @@ static void interp_inverse_passes(hipStream_t st, const Geom& g, int32_t* q, dou
     const uint32_t npairs = (g.n[0] + 1) / 2;
     auto cap = [](uint64_t r) { return (uint32_t)(r < 65535 ? r : 65535); };
     if (ND == 3 && g.n[2] > 1) {
-        const uint32_t c1 = (g.n[1] + 1) / 2, c2 = g.n[2] / 2;  // y even, z odd
-        const uint64_t rows = (uint64_t)c1 * c2;
-        if (rows)
-            hipLaunchKernelGGL(k_interp_pairs<2>, dim3((npairs + 255) / 256, cap(rows)), dim3(256), 0, st, g, q, 0u, 2u,
-                               c1, 1u, 2u, (uint32_t)rows);
+        // even rows y through groups of kYXRows planes
+        const uint32_t gpr = (g.n[1] + 1) / 2;
+        const uint64_t ngroups = (uint64_t)gpr * ((g.n[2] + kYXRows - 1) / kYXRows);
+        hipLaunchKernelGGL(k_interp_z, dim3((npairs + 255) / 256, cap(ngroups)), dim3(256), 0, st, g, q,
+                           (uint32_t)ngroups, gpr);
     }
     const uint64_t rows = (uint64_t)g.n[1] * g.n[2];
     if (ND >= 2 && g.n[1] > 1) {
