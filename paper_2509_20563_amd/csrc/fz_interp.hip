@@ -6,8 +6,10 @@
 // axis:
 //   k_interp_anchor  - prefix sums along one axis of the anchor grid (every
 //                      coordinate a multiple of 8), one thread per line
-//   k_interp_level   - strides 4 and 2: the points of one stride and axis,
-//                      one thread per point
+//   k_interp_level_z, k_interp_level_yx - strides 4 and 2 (2D/3D): the
+//                      stride-1 passes below on the lattice of that stride,
+//                      in place
+//   k_interp_level   - strides 4 and 2 of a 1D field, one thread per point
 //   k_interp_z       - stride 1, z pass: a thread per pair of points
 //                      (2m, 2m + 1) of an even row through a group of 8
 //                      planes (the even one is the level's point), so that
@@ -34,8 +36,12 @@ __device__ __forceinline__ uint32_t n_coords(uint32_t n, uint32_t first, uint32_
     return n > first ? (n - first + step - 1) / step : 0u;
 }
 
+// Loads of one anchor line issued together (the line is read and written
+// in place, so a load cannot move above an earlier store by itself)
+constexpr int kAnchorBatch = 16;
+
 template <int ND>
-__global__ __launch_bounds__(256) void k_interp_anchor(Geom g, const int32_t* src, int32_t* dst, int axis) {
+__global__ __launch_bounds__(64) void k_interp_anchor(Geom g, const int32_t* src, int32_t* dst, int axis) {
     // lines: the anchor coordinates of the other axes
     uint32_t cnt[3] = {1, 1, 1};
     for (int a = 0; a < ND; a++) cnt[a] = n_coords(g.n[a], 0, 8);
@@ -43,15 +49,23 @@ __global__ __launch_bounds__(256) void k_interp_anchor(Geom g, const int32_t* sr
     lc[axis] = 1;
     const uint64_t nlines = (uint64_t)lc[0] * lc[1] * lc[2];
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t sa = 8 * (axis == 0 ? 1ull : (axis == 1 ? (uint64_t)g.n[0] : (uint64_t)g.n[0] * g.n[1]));
+    const uint32_t len = cnt[axis];
     for (uint64_t l = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; l < nlines; l += stride) {
         uint32_t c[3] = {(uint32_t)(l % lc[0]) * 8, (uint32_t)((l / lc[0]) % lc[1]) * 8,
                          (uint32_t)(l / ((uint64_t)lc[0] * lc[1])) * 8};
+        c[axis] = 0;
+        const uint64_t i0 = rm_index<ND>(g, c[0], c[1], c[2]);
         int32_t acc = 0;
-        for (uint32_t k = 0; k < cnt[axis]; k++) {
-            c[axis] = 8 * k;
-            const uint64_t i = rm_index<ND>(g, c[0], c[1], c[2]);
-            acc = (int32_t)((uint32_t)acc + (uint32_t)src[i]);
-            dst[i] = acc;
+        for (uint32_t k0 = 0; k0 < len; k0 += kAnchorBatch) {
+            int32_t v[kAnchorBatch];
+#pragma unroll
+            for (int j = 0; j < kAnchorBatch; j++) v[j] = k0 + j < len ? src[i0 + sa * (k0 + j)] : 0;
+#pragma unroll
+            for (int j = 0; j < kAnchorBatch; j++) {
+                acc = (int32_t)((uint32_t)acc + (uint32_t)v[j]);
+                if (k0 + j < len) dst[i0 + sa * (k0 + j)] = acc;
+            }
         }
     }
 }
@@ -134,6 +148,149 @@ __global__ __launch_bounds__(256) void k_interp_z(Geom g, int32_t* __restrict__ 
             } else {
                 q[i] = (int32_t)((uint32_t)q[i] + (uint32_t)pr);
             }
+        }
+    }
+}
+
+// Strides 4 and 2 on the lattice of stride s (coordinates s X, s Y, s Z,
+// extents N = ceil(n / s)): there a level's z, y and x passes are the
+// stride-1 passes (the edge rules of stride s at s X are those of stride 1
+// at X), in place on the row-major grid values.
+//
+// The z pass (3D): the points (X even, Y even, Z odd).  A thread takes one
+// even X of an even row Y through a group of kYXRows planes Z (Z0 =
+// kYXRows j), loads the even planes Z0 - 2 .. Z0 + 10 once and updates the
+// group's odd planes.
+__global__ __launch_bounds__(256) void k_interp_level_z(Geom g, int32_t* __restrict__ q, uint32_t s, uint32_t N0,
+                                                        uint32_t N2, uint32_t ngroups, uint32_t gpr) {
+    const uint32_t X = 2 * (blockIdx.x * 256 + threadIdx.x);
+    if (X >= N0) return;
+    const uint64_t sz = (uint64_t)g.n[0] * g.n[1] * s;  // one lattice plane
+    for (uint32_t u = blockIdx.y; u < ngroups; u += gridDim.y) {
+        const uint32_t zg = u / gpr, Y = 2 * (u - zg * gpr), Z0 = zg * kYXRows;
+        const uint64_t rb = (uint64_t)g.n[0] * s * Y + (uint64_t)s * X;  // (X, Y) in plane 0
+        // planes Z0 - 3 .. Z0 + 10 (the even ones loaded)
+        int32_t ev[kYXRows + 6];
+#pragma unroll
+        for (int j = 0; j < kYXRows + 6; j += 2) {
+            const int zz = (int)Z0 - 2 + j;
+            ev[j] = 0;
+            ev[j + 1] = (zz >= 0 && (uint32_t)zz < N2) ? q[rb + sz * (uint32_t)zz] : 0;
+        }
+#pragma unroll
+        for (int k = 1; k < kYXRows; k += 2) {
+            const uint32_t Z = Z0 + k;
+            if (Z >= N2) break;  // uniform
+            const uint64_t i = rb + sz * Z;
+            const int32_t pr = pick_pred(Z, N2, 1, Z >= 3 ? ev[k] : 0, ev[k + 2], Z + 1 < N2 ? ev[k + 4] : 0,
+                                         Z + 3 < N2 ? ev[k + 6] : 0);
+            q[i] = (int32_t)((uint32_t)q[i] + (uint32_t)pr);
+        }
+    }
+}
+
+// The y and x passes together (2D/3D, after the z pass): the points (X
+// even, Y odd) predicted along y, then (X odd, any Y) along x.  Workgroup =
+// kYXRows consecutive lattice rows of one lattice plane (Y0 = kYXRows j),
+// the whole row length in chunks of 256 pairs (X = 2m, 2m + 1), so that no
+// other workgroup writes the points this one reads: the even points of odd
+// rows to the right of a chunk, rebuilt by lanes 1 and 2 from their
+// residuals, are only overwritten by the same workgroup's next chunk, and
+// those left of it are carried from the previous chunk by lane 255.  Per
+// chunk a thread loads its pair of every row once and the even points of
+// rows Y0 - 2, Y0 + 8, Y0 + 10 (never written here), so an odd row's y
+// prediction reads registers; the even points then go through LDS to the
+// odd points' x prediction.  Stores cover the points this pass rebuilds.
+__global__ __launch_bounds__(256) void k_interp_level_yx(Geom g, int32_t* __restrict__ q, uint32_t s, uint32_t N0,
+                                                         uint32_t N1, uint32_t ngroups, uint32_t gpp) {
+    __shared__ int32_t E[kYXRows][256 + 3];  // even points of the pairs m0 - 1 .. m0 + 257, per row
+    const uint32_t t = threadIdx.x;
+    const uint64_t sy = (uint64_t)g.n[0] * s;         // one lattice row
+    const uint64_t sp = (uint64_t)g.n[0] * g.n[1] * s;  // one lattice plane
+    const uint32_t nch = (N0 + 511) / 512;
+    for (uint32_t u = blockIdx.x; u < ngroups; u += gridDim.x) {
+        const uint32_t Z = u / gpp, Y0 = (u - Z * gpp) * kYXRows;
+        const uint64_t pb = sp * Z;
+        // even point of lattice row YY at X: final (YY even) or rebuilt from
+        // the rows YY -/+ 1, 3 (YY odd)
+        auto even_at = [&](uint32_t XX, uint32_t YY) -> int32_t {
+            const uint64_t i = pb + sy * YY + (uint64_t)s * XX;
+            uint32_t v = (uint32_t)q[i];
+            if (YY & 1) {
+                const int32_t m1 = q[i - sy];
+                const int32_t p1 = YY + 1 < N1 ? q[i + sy] : 0;
+                const int32_t m3 = YY >= 3 ? q[i - 3 * sy] : 0;
+                const int32_t p3 = YY + 3 < N1 ? q[i + 3 * sy] : 0;
+                v += (uint32_t)pick_pred(YY, N1, 1, m3, m1, p1, p3);
+            }
+            return (int32_t)v;
+        };
+        int32_t prev[kYXRows];  // lane 255: the even points of the previous chunk
+#pragma unroll
+        for (int k = 0; k < kYXRows; k++) prev[k] = 0;
+        for (uint32_t c = 0; c < nch; c++) {
+            const uint32_t m0 = 256 * c;
+            const uint32_t X = 2 * (m0 + t);
+            const bool in = X < N0;
+            const bool two = X + 1 < N0;
+            const uint64_t xb = (uint64_t)s * X;
+            const bool halo = t == 1 || t == 2;
+            const uint32_t hX = 2 * (m0 + 255 + t);
+            const bool hin = halo && hX < N0;
+            int32_t ev[kYXRows + 6];  // even points of rows Y0 - 3 .. Y0 + 10 (odd rows outside unused)
+            int32_t od[kYXRows];
+#pragma unroll
+            for (int k = 0; k < kYXRows + 6; k++) ev[k] = 0;
+#pragma unroll
+            for (int k = 0; k < kYXRows; k++) {
+                od[k] = 0;
+                const uint32_t YY = Y0 + k;
+                if (in && YY < N1) {
+                    const uint64_t i = pb + sy * YY + xb;
+                    ev[k + 3] = q[i];
+                    if (two) od[k] = q[i + s];
+                }
+            }
+            if (in) {
+                if (Y0 >= 2) ev[1] = q[pb + sy * (Y0 - 2) + xb];
+                if (Y0 + 8 < N1) ev[kYXRows + 3] = q[pb + sy * (Y0 + 8) + xb];
+                if (Y0 + 10 < N1) ev[kYXRows + 5] = q[pb + sy * (Y0 + 10) + xb];
+            }
+            int32_t e[kYXRows];
+#pragma unroll
+            for (int k = 0; k < kYXRows; k++) {
+                const uint32_t YY = Y0 + k;
+                e[k] = ev[k + 3];
+                if (k & 1) {
+                    const int32_t pr = pick_pred(YY, N1, 1, YY >= 3 ? ev[k] : 0, ev[k + 2],
+                                                 YY + 1 < N1 ? ev[k + 4] : 0, YY + 3 < N1 ? ev[k + 6] : 0);
+                    e[k] = (int32_t)((uint32_t)e[k] + (uint32_t)pr);
+                }
+                E[k][1 + t] = in ? e[k] : 0;
+                if (t == 255) E[k][0] = prev[k];
+                if (halo) E[k][256 + t] = (hin && YY < N1) ? even_at(hX, YY) : 0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kYXRows; k++) {
+                const uint32_t YY = Y0 + k;
+                prev[k] = e[k];
+                if (YY >= N1) break;  // uniform
+                int32_t o = od[k];
+                if (two) {
+                    const uint32_t ca = X + 1;
+                    const int32_t p1 = ca + 1 < N0 ? E[k][t + 2] : 0;
+                    const int32_t m3 = ca >= 3 ? E[k][t] : 0;
+                    const int32_t p3 = ca + 3 < N0 ? E[k][t + 3] : 0;
+                    o = (int32_t)((uint32_t)o + (uint32_t)pick_pred(ca, N0, 1, m3, e[k], p1, p3));
+                }
+                if (in) {
+                    const uint64_t i = pb + sy * YY + xb;
+                    if (k & 1) q[i] = e[k];
+                    if (two) q[i + s] = o;
+                }
+            }
+            __syncthreads();
         }
     }
 }
@@ -290,20 +447,15 @@ __global__ __launch_bounds__(256) void k_interp_final_yx(Geom g, const int32_t* 
     }
 }
 
-static uint32_t grid_for(uint64_t n) {
-    uint64_t gr = (n + 255) / 256;
-    if (gr < 1) gr = 1;
-    if (gr > 8192) gr = 8192;
-    return (uint32_t)gr;
-}
-
 template <int ND>
 static void interp_anchors(hipStream_t st, const Geom& g, const int32_t* src, int32_t* dst) {
     uint32_t acnt[3] = {1, 1, 1};
     for (int a = 0; a < ND; a++) acnt[a] = (g.n[a] + 7) / 8;
     for (int a = 0; a < ND; a++) {
         uint64_t lines = (uint64_t)acnt[0] * acnt[1] * acnt[2] / acnt[a];
-        hipLaunchKernelGGL(k_interp_anchor<ND>, dim3(grid_for(lines)), dim3(256), 0, st, g, a ? dst : src, dst, a);
+        uint64_t gr = (lines + 63) / 64;
+        if (gr > 32768) gr = 32768;
+        hipLaunchKernelGGL(k_interp_anchor<ND>, dim3((uint32_t)gr), dim3(64), 0, st, g, a ? dst : src, dst, a);
     }
 }
 
@@ -311,29 +463,35 @@ static void interp_anchors(hipStream_t st, const Geom& g, const int32_t* src, in
 template <int ND>
 static void interp_inverse_passes(hipStream_t st, const Geom& g, int32_t* q, double e2, float* out) {
     interp_anchors<ND>(st, g, q, q);
-    for (uint32_t s = 4; s >= 2; s >>= 1)
-        for (int a = ND - 1; a >= 0; a--) {
-            uint32_t first[3] = {0, 0, 0}, step[3] = {1, 1, 1}, cnt[3] = {1, 1, 1};
-            for (int d = 0; d < ND; d++) {
-                first[d] = d == a ? s : 0u;
-                step[d] = d <= a ? 2 * s : s;
-                cnt[d] = g.n[d] > first[d] ? (g.n[d] - first[d] + step[d] - 1) / step[d] : 0u;
+    auto cap = [](uint64_t r) { return (uint32_t)(r < 65535 ? r : 65535); };
+    for (uint32_t s = 4; s >= 2; s >>= 1) {
+        if (ND >= 2) {
+            // the stride-1 passes on the lattice of stride s
+            const uint32_t N0 = (g.n[0] + s - 1) / s, N1 = (g.n[1] + s - 1) / s;
+            const uint32_t N2 = ND == 3 ? (g.n[2] + s - 1) / s : 1u;
+            if (ND == 3 && N2 > 1) {
+                const uint32_t gpr = (N1 + 1) / 2;
+                const uint64_t ngroups = (uint64_t)gpr * ((N2 + kYXRows - 1) / kYXRows);
+                const uint32_t nev = (N0 + 1) / 2;
+                hipLaunchKernelGGL(k_interp_level_z, dim3((nev + 255) / 256, cap(ngroups)), dim3(256), 0, st, g, q, s,
+                                   N0, N2, (uint32_t)ngroups, gpr);
             }
-            const uint64_t rows = (uint64_t)cnt[1] * cnt[2];
-            if (!cnt[0] || !rows) continue;
-            const dim3 grid((cnt[0] + 255) / 256, (uint32_t)(rows < 65535 ? rows : 65535));
-#define FZ_LEVEL(AX)                                                                                             \
-    hipLaunchKernelGGL(k_interp_level<AX>, grid, dim3(256), 0, st, g, q, s, first[0], step[0], cnt[0], first[1], \
-                       step[1], cnt[1], first[2], step[2], (uint32_t)rows)
-            if (a == 0) FZ_LEVEL(0);
-            else if (a == 1) FZ_LEVEL(1);
-            else FZ_LEVEL(2);
-#undef FZ_LEVEL
+            const uint32_t gpp = (N1 + kYXRows - 1) / kYXRows;
+            const uint64_t ngroups = (uint64_t)gpp * N2;
+            const uint32_t grid = (uint32_t)(ngroups < (1u << 20) ? ngroups : (1u << 20));
+            hipLaunchKernelGGL(k_interp_level_yx, dim3(grid), dim3(256), 0, st, g, q, s, N0, N1, (uint32_t)ngroups,
+                               gpp);
+            continue;
         }
+        // 1D: the points of stride s along x, one thread per point
+        const uint32_t c0 = g.n[0] > s ? (g.n[0] - s + 2 * s - 1) / (2 * s) : 0u;
+        if (!c0) continue;
+        hipLaunchKernelGGL(k_interp_level<0>, dim3((c0 + 255) / 256, 1), dim3(256), 0, st, g, q, s, s, 2 * s, c0, 0u,
+                           1u, 1u, 0u, 1u, 1u);
+    }
     // stride 1: pairs of points per thread; z (x, y even, z odd), then y
     // (x even, y odd) and x together with the output
     const uint32_t npairs = (g.n[0] + 1) / 2;
-    auto cap = [](uint64_t r) { return (uint32_t)(r < 65535 ? r : 65535); };
     if (ND == 3 && g.n[2] > 1) {
         // even rows y through groups of kYXRows planes
         const uint32_t gpr = (g.n[1] + 1) / 2;
