@@ -306,6 +306,71 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
             ih_code[k] = bi | (uint32_t)(dx + 8) << 2 | (uint32_t)(dy + 8) << 7 | (uint32_t)(dz + 8) << 12;
         }
     }
+    // 3D interpolation, phase B: the LDS byte offsets of the neighbours
+    // this lane's predictions read (lane = row (ly, lz) of block `wave`).
+    // The axis and stride of the point at x = X0 + i of the row follow from
+    // i | ly | lz alone (block origins are multiples of 8), so the offsets
+    // are the same for every tile: per even i the four neighbours at -3s,
+    // -s, +s, +3s along its axis (slots 2 k, 2 k + 1 for i = 2 k; the
+    // anchor's slots unused), per odd i the columns x = -2, 8, 10 (the
+    // others are in the row's registers); two 16-bit offsets per word.
+    // icls: per even i (4 bits from bit 4 k) the axis (0 x, 1 y, 2 z) and
+    // log2 of the stride.
+    constexpr int kIOff = MODE == kQuantInterp && ND == 3 ? 10 : 1;
+    uint32_t ioff[kIOff];
+    uint32_t icls = 0;
+    if (MODE == kQuantInterp && ND == 3) {
+        const int ly = (int)(lane & 7u), lz = (int)(lane >> 3);
+        const int w = (int)wave;
+        const int rowQ = w * kQStride + (int)lane * 8;
+        const int hb = kTileBlocks * kQStride + 8 + w * kIHB;
+        const int hx = kTileBlocks * kQStride + 8 + kTileBlocks * kIHB;
+        // index of x = X0 + j on this row: the row, a block of the tile,
+        // or the tile's x halo (left of its first block, right of its last)
+        auto ix = [&](int j) -> int {
+            if (j >= 0 && j < 8) return rowQ + j;
+            const int ob = (j + 16) / 8 - 2;  // block offset along x (j >= -16)
+            const int wb = w + ob;
+            if (wb >= 0 && wb < kTileBlocks) return rowQ + ob * kQStride + (j - 8 * ob);
+            return hx + (j < 0 ? interp_halo_left(j, ly, lz)
+                               : interp_halo_right(w * 8 - 8 * (kTileBlocks - 1) + j, ly, lz));
+        };
+        uint32_t o[20];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int i = 2 * k;
+            const int orc = i | ly | lz;
+            const int sh = (orc & 1) ? 0 : ((orc & 2) ? 1 : 2);
+            const int sv = 1 << sh;
+            const int ax = orc == 0 ? 0 : ((i & sv) ? 0 : ((ly & sv) ? 1 : 2));
+            icls |= (uint32_t)(ax | sh << 2) << (4 * k);
+#pragma unroll
+            for (int m = 0; m < 4; m++) {
+                const int dd = (m == 0 ? -3 : (m == 1 ? -1 : (m == 2 ? 1 : 3))) * sv;
+                int idx;
+                if (orc == 0) {
+                    idx = rowQ;  // the anchor: predicted on the anchor grid
+                } else if (ax == 0) {
+                    idx = ix(i + dd);
+                } else if (ax == 1) {
+                    const int l = ly + dd;
+                    idx = (l >= 0 && l < 8) ? rowQ + i + 8 * dd : hb + interp_halo_y(l, i, lz, sh);
+                } else {
+                    const int l = lz + dd;
+                    idx = (l >= 0 && l < 8) ? rowQ + i + 64 * dd : hb + interp_halo_z(l, i, ly, sh);
+                }
+                o[4 * k + m] = 4u * (uint32_t)idx;
+            }
+        }
+        o[16] = 4u * (uint32_t)ix(-2);
+        o[17] = 4u * (uint32_t)ix(8);
+        o[18] = 4u * (uint32_t)ix(10);
+        o[19] = 0;
+#pragma unroll
+        for (int k = 0; k < kIOff; k++) ioff[k] = o[2 * k] | o[2 * k + 1] << 16;
+    } else {
+        ioff[0] = 0;
+    }
     // phase-B lane (segment = lane) offset, for reloading patched values
     uint32_t lb_lx0, lb_ly, lb_lz;
     seg_coords<ND>(lane, lb_lx0, lb_ly, lb_lz);
@@ -337,10 +402,49 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
     // current values would also cover them)
     uint32_t pf_nv = 0;
     float pf[8];
+    // 3D interpolation: this thread's halo entries of the next tile, loaded
+    // with its values (raw; bit k of hpm: entry k inside the field); the
+    // origins of the tile's blocks are wave-uniform
+    float hpf[kIHPerThread];
+    uint32_t hpm = 0;
+    auto halo_load = [&](uint32_t tl) {
+        if (MODE != kQuantInterp || ND != 3) return;
+        uint32_t ox[kTileBlocks], oy[kTileBlocks], oz[kTileBlocks], valid = 0;
+#pragma unroll
+        for (int k = 0; k < kTileBlocks; k++) {
+            const uint32_t bk = tl * kTileBlocks + k;
+            const BlockInfo ik = block_info(g, bk < g.nblocks ? bk : 0);
+            ox[k] = ik.bx * 8;
+            oy[k] = ik.by * 8;
+            oz[k] = ik.bz * 8;
+            valid |= (tl < ntiles && bk < g.nblocks ? 1u : 0u) << k;
+        }
+        hpm = 0;
+#pragma unroll
+        for (int k = 0; k < kIHPerThread; k++) {
+            hpf[k] = 0.0f;
+            const uint32_t e = t + 256u * k;
+            if (e >= (uint32_t)(kTileBlocks * kIHB + kIHX)) break;
+            const uint32_t hv = ih_code[k];
+            const uint32_t bi = hv & 3u;
+            const uint32_t X0 = bi == 0 ? ox[0] : (bi == 1 ? ox[1] : (bi == 2 ? ox[2] : ox[3]));
+            const uint32_t Y0 = bi == 0 ? oy[0] : (bi == 1 ? oy[1] : (bi == 2 ? oy[2] : oy[3]));
+            const uint32_t Z0 = bi == 0 ? oz[0] : (bi == 1 ? oz[1] : (bi == 2 ? oz[2] : oz[3]));
+            const int64_t xx = (int64_t)X0 + ((int)((hv >> 2) & 31u) - 8),
+                          yy = (int64_t)Y0 + ((int)((hv >> 7) & 31u) - 8),
+                          zz = (int64_t)Z0 + ((int)((hv >> 12) & 31u) - 8);
+            if (((valid >> bi) & 1u) && xx >= 0 && yy >= 0 && zz >= 0 && xx < (int64_t)g.n[0] &&
+                yy < (int64_t)g.n[1] && zz < (int64_t)g.n[2]) {
+                hpf[k] = x[(uint64_t)xx + (uint64_t)g.n[0] * ((uint64_t)yy + (uint64_t)g.n[1] * (uint64_t)zz)];
+                hpm |= 1u << k;
+            }
+        }
+    };
     {
         uint32_t base = 0;
         if (blockIdx.x < ntiles) tile_src(blockIdx.x, base, pf_nv);
         tile_load(base, blockIdx.x < ntiles ? pf_nv : 0u, pf);
+        halo_load(blockIdx.x);
     }
 
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -370,30 +474,14 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
         }
         if (MODE == kQuantInterp && ND == 3) {
             // interpolation (3D): the grid values outside the blocks that
-            // the stride-s predictions of the tile read (interp_halo_at,
-            // decoded once per thread)
+            // the stride-s predictions of the tile read (loaded a tile ago)
 #pragma unroll
             for (int k = 0; k < kIHPerThread; k++) {
                 const uint32_t e = t + 256u * k;
                 if (e >= (uint32_t)(kTileBlocks * kIHB + kIHX)) break;
-                const uint32_t hv = ih_code[k];
-                const uint32_t bi = hv & 3u;
-                const int dx = (int)((hv >> 2) & 31u) - 8, dy = (int)((hv >> 7) & 31u) - 8,
-                          dz = (int)((hv >> 12) & 31u) - 8;
-                const uint32_t bk = tile * kTileBlocks + bi;
-                int32_t v = 0;
-                if (bk < g.nblocks) {
-                    const BlockInfo ik = block_info(g, bk);
-                    const int64_t xx = (int64_t)ik.bx * 8 + dx, yy = (int64_t)ik.by * 8 + dy,
-                                  zz = (int64_t)ik.bz * 8 + dz;
-                    if (xx >= 0 && yy >= 0 && zz >= 0 && xx < (int64_t)g.n[0] && yy < (int64_t)g.n[1] &&
-                        zz < (int64_t)g.n[2]) {
-                        bool pq;
-                        v = prequant1(x[(uint64_t)xx + (uint64_t)g.n[0] * ((uint64_t)yy + (uint64_t)g.n[1] * (uint64_t)zz)],
-                                      e2, inv, eb_abs, pq);
-                    }
-                }
-                HI[e] = v;
+                bool pq;
+                const int32_t v = prequant1(hpf[k], e2, inv, eb_abs, pq);
+                HI[e] = ((hpm >> k) & 1u) ? v : 0;
             }
         }
         if (MODE == kQuantGlobal) {
@@ -451,6 +539,7 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
             if (nt < ntiles) tile_src(nt, base, pf_nv);
             else pf_nv = 0;
             tile_load(base, pf_nv, pf);
+            halo_load(nt);
         }
 
         // ---------------- phase B: wave = block, lane = segment
@@ -490,97 +579,59 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
             };
             auto residual = [&](const uint32_t pr) {
             if (MODE == kQuantInterp && ND == 3) {
-                // 3D: lane = row (ly, lz) of the block, values at x = X0 + i.
-                // An odd i is a stride-1 point along x; an even i's stride
-                // and axis follow from i | y | z (the row's y | z known per
-                // lane), an x axis only for i = 2, 6 (stride 2) and 4
-                // (stride 4).  Every neighbour is in this row's registers or
-                // in LDS (the tile's blocks or its halo), read without
-                // branches: the x and the y/z candidates of an even i are
-                // both formed and one is selected per lane.  Grid values
+                // 3D: lane = row (ly, lz) of the block, values at x = X0 + i;
+                // every neighbour in this row's registers or at an LDS
+                // offset taken once per kernel (ioff, icls).  Grid values
                 // are at most 2^24 in magnitude, so the cubic and linear
                 // rules are exact in 32-bit integers.
                 int32_t r0[8];
                 read_row<ND>(Q, Qb + s * 8, r0);
                 const uint32_t n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
                 const uint32_t X0 = info.bx * 8, Y = info.by * 8 + ly, Z = info.bz * 8 + lz;
-                const uint32_t yz = Y | Z;
-                // indices into Q: this block's halo, the tile's x halo
-                const int hb = kTileBlocks * kQStride + 8 + (int)wave * kIHB;
-                const int hx = kTileBlocks * kQStride + 8 + kTileBlocks * kIHB;
-                const int32_t* Hb = &Q[hb];
-                const int rowQ = (int)Qb + (int)s * 8;  // this row in Q
-                // one of two indices by a mask (no branch)
-                auto sel = [](bool c, int a, int b) { return b + ((a - b) & -(int)c); };
-                // x = X0 + j of this row (j compile-time after unrolling):
-                // this row, a block of the tile, or the tile's x halo (left
-                // of its first block, right of its last one)
-                auto qx = [&](int j) -> int32_t {
-                    if (j >= 0 && j < 8) return r0[j];
-                    const int ob = (j + 16) / 8 - 2;  // block offset along x (j >= -16)
-                    const int wb = (int)wave + ob;
-                    const int ih = hx + (j < 0 ? interp_halo_left(j, (int)ly, (int)lz)
-                                               : interp_halo_right((int)wave * 8 - 8 * (kTileBlocks - 1) + j,
-                                                                   (int)ly, (int)lz));
-                    return Q[sel(wb >= 0 && wb < kTileBlocks, rowQ + ob * kQStride + (j - 8 * ob), ih)];
-                };
-                // offset d along y (ay) or z at x = X0 + i: this block, or
-                // its y or z halo
-                auto qyz = [&](int i, bool ay, int d, int sh) -> int32_t {
-                    const int l = (ay ? (int)ly : (int)lz) + d;
-                    const int iq = rowQ + i + d * (ay ? 8 : 64);
-                    const int ih = hb + sel(ay, interp_halo_y(l, i, (int)lz, sh), interp_halo_z(l, i, (int)ly, sh));
-                    return Q[sel((uint32_t)l < 8u, iq, ih)];
+                const int32_t* Hb = &Q[kTileBlocks * kQStride + 8 + (int)wave * kIHB];
+                // the value at the LDS byte offset in half h of word w
+                auto at = [&](uint32_t w, int h) -> int32_t {
+                    const uint32_t off = h ? (w >> 16) : (w & 0xffffu);
+                    return *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(Q) + off);
                 };
                 auto pick = [](bool m3, bool p1, bool p3, int32_t vm3, int32_t vm1, int32_t vp1, int32_t vp3) {
                     const int32_t cub = (-vm3 + 9 * vm1 + 9 * vp1 - vp3 + 8) >> 4;
                     const int32_t lin = (vm1 + vp1 + 1) >> 1;
                     return (m3 && p3) ? cub : (p1 ? lin : vm1);
                 };
+                // x = X0 + j of this row for the odd points (j = -2 .. 10)
+                auto vx = [&](int j) -> int32_t {
+                    if (j >= 0 && j < 8) return r0[j];
+                    return j == -2 ? at(ioff[8], 0) : (j == 8 ? at(ioff[8], 1) : at(ioff[9], 0));
+                };
 #pragma unroll
                 for (int i = 0; i < 8; i++) {
                     const uint32_t xx = X0 + i;
                     int32_t pq;
                     if (i & 1) {
-                        pq = pick(xx >= 3, xx + 1 < n0, xx + 3 < n0, qx(i - 3), qx(i - 1), qx(i + 1), qx(i + 3));
+                        pq = pick(xx >= 3, xx + 1 < n0, xx + 3 < n0, vx(i - 3), vx(i - 1), vx(i + 1), vx(i + 3));
                     } else {
-                        const uint32_t orc = (uint32_t)i | yz;
-                        const int sh = (orc & 1u) ? 0 : ((orc & 2u) ? 1 : 2);
-                        const uint32_t sv = 1u << sh;
-                        const int si = (int)sv;
-                        const bool ay = (Y & sv) != 0;
-                        const uint32_t ca = ay ? Y : Z, na = ay ? n1 : n2;
-                        bool m3 = ca >= 3 * sv, p1 = ca + sv < na, p3 = ca + 3 * sv < na;
-                        int32_t vm3 = qyz(i, ay, -3 * si, sh), vm1 = qyz(i, ay, -si, sh), vp1 = qyz(i, ay, si, sh),
-                                vp3 = qyz(i, ay, 3 * si, sh);
-                        if (i != 0) {
-                            // stride 2 (i = 2, 6) or 4 (i = 4) along x
-                            const int sx = i == 4 ? 4 : 2;
-                            const bool isx = ((uint32_t)i & sv) != 0;
-                            const int32_t xm3 = qx(i - 3 * sx), xm1 = qx(i - sx), xp1 = qx(i + sx),
-                                          xp3 = qx(i + 3 * sx);
-                            m3 = isx ? xx >= 3u * sx : m3;
-                            p1 = isx ? xx + sx < n0 : p1;
-                            p3 = isx ? xx + 3u * sx < n0 : p3;
-                            vm3 = isx ? xm3 : vm3;
-                            vm1 = isx ? xm1 : vm1;
-                            vp1 = isx ? xp1 : vp1;
-                            vp3 = isx ? xp3 : vp3;
-                        }
-                        pq = pick(m3, p1, p3, vm3, vm1, vp1, vp3);
+                        const int k = i / 2;
+                        const uint32_t c = icls >> (4 * k);
+                        const uint32_t ax = c & 3u, sv = 1u << ((c >> 2) & 3u);
+                        const uint32_t ca = ax == 0 ? xx : (ax == 1 ? Y : Z);
+                        const uint32_t na = ax == 0 ? n0 : (ax == 1 ? n1 : n2);
+                        pq = pick(ca >= 3 * sv, ca + sv < na, ca + 3 * sv < na, at(ioff[2 * k], 0),
+                                  at(ioff[2 * k], 1), at(ioff[2 * k + 1], 0), at(ioff[2 * k + 1], 1));
                         if (i == 0) {
                             // the block's anchor (ly = lz = 0): Lorenzo on the
                             // anchor grid, the neighbours 8 below in x, y, z
+                            // (x - 8 is that row's stride-4 neighbour of i = 4)
                             const bool ix = X0 >= 8, iy = Y >= 8, iz = Z >= 8;
                             int32_t pa = 0;
-                            pa += ix ? qx(-8) : 0;
+                            pa += ix ? at(ioff[4], 0) : 0;
                             pa += iy ? Hb[interp_halo_y(-8, 0, 0, 2)] : 0;
                             pa += iz ? Hb[interp_halo_z(-8, 0, 0, 2)] : 0;
                             pa -= (ix && iy) ? Hb[kIHAnchor + 0] : 0;
                             pa -= (ix && iz) ? Hb[kIHAnchor + 1] : 0;
                             pa -= (iy && iz) ? Hb[kIHAnchor + 3] : 0;
                             pa += (ix && iy && iz) ? Hb[kIHAnchor + 2] : 0;
-                            pq = (yz & 7u) == 0 ? pa : pq;
+                            pq = ((Y | Z) & 7u) == 0 ? pa : pq;
                         }
                     }
                     d[i] = i < (int)nv ? (int32_t)((uint32_t)r0[i] - (uint32_t)pq) : 0;

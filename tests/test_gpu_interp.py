@@ -35,6 +35,9 @@ CASES = [
     # neighbouring workgroups' pairs rebuilt at the range edges
     ("3d-long-rows", "smooth", (20, 21, 1100), 1e-3, 1),
     ("3d-long-rows-odd", "smooth", (18, 17, 1025), 1e-4, 1),
+    # rows of several 512-point chunks on the stride-4 and stride-2 lattices
+    ("3d-rows-3-chunks", "smooth", (6, 13, 2301), 1e-4, 1),
+    ("2d-rows-3-chunks", "smooth", (9, 2500), 1e-3, 1),
     ("2d-ragged", "smooth", (1001, 777), 1e-3, 1),
     ("2d-small", "smooth", (3, 5), 1e-2, 1),
     ("1d-positions", "positions", (300007,), 1e-4, 1),
