@@ -440,14 +440,21 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
             }
         }
     };
+    // first tile: workgroup w, or for the 3D interpolation predictor (whose
+    // halo reads the neighbouring tiles) the tiles of one round spread so
+    // that the workgroups of one XCD (w mod 8, dispatch order) take one
+    // contiguous eighth of them
+    uint32_t tile0 = blockIdx.x;
+    if (MODE == kQuantInterp && ND == 3 && (gridDim.x & 7u) == 0)
+        tile0 = (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
     {
         uint32_t base = 0;
-        if (blockIdx.x < ntiles) tile_src(blockIdx.x, base, pf_nv);
-        tile_load(base, blockIdx.x < ntiles ? pf_nv : 0u, pf);
-        halo_load(blockIdx.x);
+        if (tile0 < ntiles) tile_src(tile0, base, pf_nv);
+        tile_load(base, tile0 < ntiles ? pf_nv : 0u, pf);
+        halo_load(tile0);
     }
 
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (uint32_t tile = tile0; tile < ntiles; tile += gridDim.x) {
         // ---------------- phase A: prequantise (values loaded a tile ago)
         {
             const uint32_t nv = pf_nv;
