@@ -38,6 +38,11 @@ CASES = [
     # rows of several 512-point chunks on the stride-4 and stride-2 lattices
     ("3d-rows-3-chunks", "smooth", (6, 13, 2301), 1e-4, 1),
     ("2d-rows-3-chunks", "smooth", (9, 2500), 1e-3, 1),
+    # degenerate lattices: one row per plane, rows of one to three values
+    ("3d-one-row", "smooth", (19, 1, 37), 1e-3, 1),
+    ("3d-narrow-x", "smooth", (21, 18, 3), 1e-3, 1),
+    ("3d-one-x", "smooth", (13, 11, 1), 1e-3, 1),
+    ("2d-one-column", "smooth", (37, 1), 1e-3, 1),
     ("2d-ragged", "smooth", (1001, 777), 1e-3, 1),
     ("2d-small", "smooth", (3, 5), 1e-2, 1),
     ("1d-positions", "positions", (300007,), 1e-4, 1),
