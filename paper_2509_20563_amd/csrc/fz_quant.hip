@@ -207,6 +207,33 @@ __device__ __forceinline__ void interp_halo_at(uint32_t e, uint32_t& bi, int& dx
     }
 }
 
+// Halo of the 3D global Lorenzo quantiser: entry e of a tile, the block of
+// the tile it is relative to and its offset from that block's origin.  Per
+// block (136 entries) the plane below (x, y in 0..7, z = -1), the row below
+// for every z (x, z in 0..7, y = -1) and their shared row (x in 0..7, y = z =
+// -1); then the column left of the tile's first block (x = -1, y and z in
+// -1..7, 81 entries).
+__device__ __forceinline__ void global_halo_at(uint32_t e, uint32_t& bi, int& dx, int& dy, int& dz) {
+    constexpr uint32_t kPerBlock = 136;
+    if (e >= (uint32_t)kTileBlocks * kPerBlock) {
+        const int k = (int)(e - (uint32_t)kTileBlocks * kPerBlock);
+        bi = 0;
+        dx = -1;
+        dy = k % 9 - 1;
+        dz = k / 9 - 1;
+        return;
+    }
+    bi = e / kPerBlock;
+    const int k = (int)(e - bi * kPerBlock);
+    if (k < 64) {
+        dx = k & 7; dy = k >> 3; dz = -1;
+    } else if (k < 128) {
+        dx = k & 7; dy = -1; dz = (k - 64) >> 3;
+    } else {
+        dx = k - 128; dy = -1; dz = -1;
+    }
+}
+
 // MODE: kQuantP0 (first-order Lorenzo everywhere), kQuantPred (predictor
 // per block: fixed_pred >= 0 for every block, else bpred[b]), kQuantTrial
 // (no codes: per-block cost of each predictor under a reference code,
@@ -292,17 +319,23 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
     load_map<ND>(t, la_bi, la_s);
     seg_coords<ND>(la_s, la_lx0, la_ly, la_lz);
     const uint32_t la_rowoff = la_lx0 + g.n[0] * (la_ly + g.n[1] * la_lz);
-    // 3D interpolation: this thread's halo entries t + 256 k, decoded once
-    // (block of the tile in bits 0-1, dx + 8, dy + 8, dz + 8 in 5 bits each)
-    constexpr int kIHPerThread = MODE == kQuantInterp && ND == 3 ? (kTileBlocks * kIHB + kIHX + 255) / 256 : 1;
+    // 3D interpolation and 3D global Lorenzo: this thread's halo entries
+    // t + 256 k, decoded once (block of the tile in bits 0-1, dx + 8, dy + 8,
+    // dz + 8 in 5 bits each)
+    constexpr bool kHalo3 = (MODE == kQuantInterp || MODE == kQuantGlobal) && ND == 3;
+    constexpr int kHaloN = MODE == kQuantInterp ? kTileBlocks * kIHB + kIHX : kTileBlocks * kHB + kHL;
+    constexpr int kIHPerThread = kHalo3 ? (kHaloN + 255) / 256 : 1;
     uint32_t ih_code[kIHPerThread];
-    if (MODE == kQuantInterp && ND == 3) {
+    if (kHalo3) {
 #pragma unroll
         for (int k = 0; k < kIHPerThread; k++) {
             uint32_t bi = 0;
             int dx = 0, dy = 0, dz = 0;
             const uint32_t e = t + 256u * k;
-            if (e < (uint32_t)(kTileBlocks * kIHB + kIHX)) interp_halo_at(e, bi, dx, dy, dz);
+            if (e < (uint32_t)kHaloN) {
+                if (MODE == kQuantInterp) interp_halo_at(e, bi, dx, dy, dz);
+                else global_halo_at(e, bi, dx, dy, dz);
+            }
             ih_code[k] = bi | (uint32_t)(dx + 8) << 2 | (uint32_t)(dy + 8) << 7 | (uint32_t)(dz + 8) << 12;
         }
     }
@@ -402,13 +435,13 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
     // current values would also cover them)
     uint32_t pf_nv = 0;
     float pf[8];
-    // 3D interpolation: this thread's halo entries of the next tile, loaded
-    // with its values (raw; bit k of hpm: entry k inside the field); the
-    // origins of the tile's blocks are wave-uniform
+    // 3D interpolation and global Lorenzo: this thread's halo entries of the
+    // next tile, loaded with its values (raw; bit k of hpm: entry k inside
+    // the field); the origins of the tile's blocks are wave-uniform
     float hpf[kIHPerThread];
     uint32_t hpm = 0;
     auto halo_load = [&](uint32_t tl) {
-        if (MODE != kQuantInterp || ND != 3) return;
+        if (!kHalo3) return;
         uint32_t ox[kTileBlocks], oy[kTileBlocks], oz[kTileBlocks], valid = 0;
 #pragma unroll
         for (int k = 0; k < kTileBlocks; k++) {
@@ -424,7 +457,7 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
         for (int k = 0; k < kIHPerThread; k++) {
             hpf[k] = 0.0f;
             const uint32_t e = t + 256u * k;
-            if (e >= (uint32_t)(kTileBlocks * kIHB + kIHX)) break;
+            if (e >= (uint32_t)kHaloN) break;
             const uint32_t hv = ih_code[k];
             const uint32_t bi = hv & 3u;
             const uint32_t X0 = bi == 0 ? ox[0] : (bi == 1 ? ox[1] : (bi == 2 ? ox[2] : ox[3]));
@@ -491,7 +524,18 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ x, Geom
                 HI[e] = ((hpm >> k) & 1u) ? v : 0;
             }
         }
-        if (MODE == kQuantGlobal) {
+        if (MODE == kQuantGlobal && ND == 3) {
+            // global Lorenzo (3D): the grid values just outside the tile's
+            // blocks (global_halo_at), loaded a tile ago
+#pragma unroll
+            for (int k = 0; k < kIHPerThread; k++) {
+                const uint32_t e = t + 256u * k;
+                if (e >= (uint32_t)kHaloN) break;
+                bool pq;
+                const int32_t v = prequant1(hpf[k], e2, inv, eb_abs, pq);
+                HG[e] = ((hpm >> k) & 1u) ? v : 0;
+            }
+        } else if (MODE == kQuantGlobal) {
             for (uint32_t e = t; e < (uint32_t)(kTileBlocks * kHB + kHL); e += 256) {
                 const bool left = e >= (uint32_t)(kTileBlocks * kHB);
                 const uint32_t bi = left ? 0u : e / (uint32_t)(kHB ? kHB : 1);
