@@ -10,14 +10,14 @@
 //                      stride-1 passes below on the lattice of that stride,
 //                      in place
 //   k_interp_level   - strides 4 and 2 of a 1D field, one thread per point
-//   k_interp_z       - stride 1, z pass: a thread per pair of points
-//                      (2m, 2m + 1) of an even row through a group of 8
-//                      planes (the even one is the level's point), so that
-//                      stores cover whole lines
-//   k_interp_final_yx - stride 1, y and x passes of a row together (2D/3D):
-//                      the even points' y prediction, exchanged in LDS for
-//                      the odd points' x prediction, the pair dequantised
-//                      to the output
+//   k_interp_final_yx - stride 1 (2D/3D): the z pass of the odd planes
+//                      (3D), the y pass and the x pass of a group of rows
+//                      together, the even points exchanged in LDS for the
+//                      odd points' x prediction, the pair dequantised to
+//                      the output
+//   k_interp_z       - stride 1, z pass of fields one row high: a thread per
+//                      pair of points (2m, 2m + 1) of an even row through a
+//                      group of 8 planes, so that stores cover whole lines
 //   k_interp_final_x - stride 1, x pass alone (1D, and fields one row
 //                      high)
 #include "fz_common.h"
@@ -336,114 +336,138 @@ __global__ __launch_bounds__(256) void k_interp_final_x(Geom g, const int32_t* _
     }
 }
 
-// Stride 1, the y and x passes together (2D/3D, after the z pass):
-// workgroup = 256 pairs (512 values) of kYXRows consecutive rows of one
-// plane (y0 = kYXRows j), rows groups over blockIdx.y.  Each thread loads
-// its pair of every row of the group once, and the even points of the rows
-// y0 - 2, y0 + 8 and y0 + 10 (final, as every even row's even points are),
-// so an odd row's y prediction (rows y -/+ 1, 3) reads registers.  The
-// rows' even points go through LDS (with the pairs just left and the two
-// just right of the range, rebuilt by three lanes) to the x prediction of
-// the odd points; each pair is written dequantised.  The grid values are
-// only read.
+// Stride 1, the y and x passes together (2D/3D) and, with ZF (3D), the
+// z pass of the odd planes folded in: workgroup = kYXRows consecutive rows
+// of one plane (y0 = kYXRows j) over their whole length, in chunks of 256
+// pairs (x = 2m, 2m + 1).  Per chunk a thread loads its pair of every row
+// once and the even points of the rows y0 - 2, y0 + 8 and y0 + 10; in an
+// odd plane an even row's even point first takes its z prediction from the
+// planes z -/+ 1, 3 (even planes, whose even rows' even points are final:
+// this pass writes only the output), then an odd row's y prediction reads
+// registers.  The even points go through an LDS ring of three chunks
+// (slot = pair mod 768): chunk c + 1 is built before chunk c's odd points
+// take their x prediction, so the pairs right of a chunk are there and
+// those left of it still are.  Each pair is written dequantised.
+template <bool ZF>
 __global__ __launch_bounds__(256) void k_interp_final_yx(Geom g, const int32_t* __restrict__ q, double e2,
                                                          float* __restrict__ out, uint32_t ngroups, uint32_t gpp) {
-    __shared__ int32_t E[kYXRows][256 + 3];  // even points of the pairs m0 - 1 .. m0 + 257, per row
+    constexpr uint32_t kRing = 768;
+    __shared__ int32_t S[kYXRows][kRing];
     const uint32_t t = threadIdx.x;
-    const uint32_t n0 = g.n[0], n1 = g.n[1];
-    const uint32_t m0 = blockIdx.x * 256;
-    const uint32_t x = 2 * (m0 + t);
-    const bool in = x < n0;
-    const bool two = x + 1 < n0;
-    const bool v2 = two && (n0 & 1) == 0;
-    const uint64_t sy = n0;
+    const uint32_t n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+    const uint32_t nch = ((n0 + 1) / 2 + 255) / 256;
+    const bool even_n0 = (n0 & 1) == 0;
+    const uint64_t sy = n0, sz = (uint64_t)n0 * n1;
     auto dq = [&](int32_t v) { return (float)((double)v * e2); };
-    // halo lanes: 0 the pair left of the range, 1 and 2 the two right of it
-    const bool halo = t < 3;
-    const uint32_t hx = t == 0 ? 2 * m0 - 2 : 2 * (m0 + 255 + t);
-    const bool hin = halo && (t == 0 ? m0 > 0 : hx < n0);
-    for (uint32_t u = blockIdx.y; u < ngroups; u += gridDim.y) {
+    for (uint32_t u = blockIdx.x; u < ngroups; u += gridDim.x) {
         const uint32_t z = u / gpp, y0 = (u - z * gpp) * kYXRows;
-        const uint64_t pb = (uint64_t)n0 * n1 * z;  // the plane
-        // even point of row yy at column xx, final (yy even) or rebuilt
-        // from the rows yy -/+ 1, 3 (yy odd): the halo lanes' path
-        auto even_at = [&](uint32_t xx, uint32_t yy) -> int32_t {
-            const uint64_t i = pb + (uint64_t)n0 * yy + xx;
-            uint32_t v = (uint32_t)q[i];
-            if (yy & 1) {
-                const int32_t m1 = q[i - sy];
-                const int32_t p1 = yy + 1 < n1 ? q[i + sy] : 0;
-                const int32_t m3 = yy >= 3 ? q[i - 3 * sy] : 0;
-                const int32_t p3 = yy + 3 < n1 ? q[i + 3 * sy] : 0;
-                v += (uint32_t)pick_pred(yy, n1, 1, m3, m1, p1, p3);
-            }
-            return (int32_t)v;
+        const uint64_t pb = sz * z;  // the plane
+        const bool zodd = ZF && (z & 1u);
+        // z prediction at index i of this (odd) plane from the planes
+        // z -/+ 1, 3
+        auto zpred = [&](uint64_t i) -> uint32_t {
+            const int32_t m1 = q[i - sz];
+            const int32_t p1 = z + 1 < n2 ? q[i + sz] : 0;
+            const int32_t m3 = z >= 3 ? q[i - 3 * sz] : 0;
+            const int32_t p3 = z + 3 < n2 ? q[i + 3 * sz] : 0;
+            return (uint32_t)pick_pred(z, n2, 1, m3, m1, p1, p3);
         };
-        // this thread's pairs of the group's rows, and the even points of
-        // rows y0 - 2, y0 + 8, y0 + 10
-        int32_t ev[kYXRows + 6];  // even points of rows y0 - 3 .. y0 + 10 (odd rows outside unused)
-        int32_t od[kYXRows];
+        // chunk c of the group: this thread's even points after the z and
+        // y passes (e, also into the ring) and odd residuals (od)
+        auto build = [&](uint32_t c, int32_t* e, int32_t* od) {
+            const uint32_t x = 2 * (256 * c + t);
+            const bool in = x < n0;
+            const bool two = x + 1 < n0;
+            const bool v2 = two && even_n0;
+            int32_t ev[kYXRows + 6];  // even points of rows y0 - 3 .. y0 + 10 (odd rows outside unused)
 #pragma unroll
-        for (int k = 0; k < kYXRows + 6; k++) ev[k] = 0;
+            for (int k = 0; k < kYXRows + 6; k++) ev[k] = 0;
 #pragma unroll
-        for (int k = 0; k < kYXRows; k++) {
-            od[k] = 0;
-            const uint32_t yy = y0 + k;
-            if (in && yy < n1) {
-                const uint64_t i = pb + (uint64_t)n0 * yy + x;
-                if (v2) {
-                    const int2 v = *reinterpret_cast<const int2*>(q + i);
-                    ev[k + 3] = v.x;
-                    od[k] = v.y;
-                } else {
-                    ev[k + 3] = q[i];
-                    if (two) od[k] = q[i + 1];
+            for (int k = 0; k < kYXRows; k++) {
+                od[k] = 0;
+                const uint32_t yy = y0 + k;
+                if (in && yy < n1) {
+                    const uint64_t i = pb + sy * yy + x;
+                    if (v2) {
+                        const int2 v = *reinterpret_cast<const int2*>(q + i);
+                        ev[k + 3] = v.x;
+                        od[k] = v.y;
+                    } else {
+                        ev[k + 3] = q[i];
+                        if (two) od[k] = q[i + 1];
+                    }
+                    if (zodd && !(k & 1)) ev[k + 3] = (int32_t)((uint32_t)ev[k + 3] + zpred(i));
                 }
             }
-        }
-        if (in) {
-            if (y0 >= 2) ev[1] = q[pb + (uint64_t)n0 * (y0 - 2) + x];
-            if (y0 + 8 < n1) ev[kYXRows + 3] = q[pb + (uint64_t)n0 * (y0 + 8) + x];
-            if (y0 + 10 < n1) ev[kYXRows + 5] = q[pb + (uint64_t)n0 * (y0 + 10) + x];
-        }
-        // odd rows: the y prediction from the even rows around them
-        int32_t e[kYXRows];
+            if (in) {
+                auto halo_row = [&](uint32_t yy) -> int32_t {
+                    const uint64_t i = pb + sy * yy + x;
+                    uint32_t v = (uint32_t)q[i];
+                    if (zodd) v += zpred(i);
+                    return (int32_t)v;
+                };
+                if (y0 >= 2) ev[1] = halo_row(y0 - 2);
+                if (y0 + 8 < n1) ev[kYXRows + 3] = halo_row(y0 + 8);
+                if (y0 + 10 < n1) ev[kYXRows + 5] = halo_row(y0 + 10);
+            }
+            const uint32_t sl = (256 * c + t) % kRing;
 #pragma unroll
-        for (int k = 0; k < kYXRows; k++) {
-            const uint32_t yy = y0 + k;
-            e[k] = ev[k + 3];
-            if (k & 1) {
-                const int32_t pr = pick_pred(yy, n1, 1, yy >= 3 ? ev[k] : 0, ev[k + 2],
-                                             yy + 1 < n1 ? ev[k + 4] : 0, yy + 3 < n1 ? ev[k + 6] : 0);
-                e[k] = (int32_t)((uint32_t)e[k] + (uint32_t)pr);
+            for (int k = 0; k < kYXRows; k++) {
+                const uint32_t yy = y0 + k;
+                e[k] = ev[k + 3];
+                if (k & 1) {
+                    const int32_t pr = pick_pred(yy, n1, 1, yy >= 3 ? ev[k] : 0, ev[k + 2],
+                                                 yy + 1 < n1 ? ev[k + 4] : 0, yy + 3 < n1 ? ev[k + 6] : 0);
+                    e[k] = (int32_t)((uint32_t)e[k] + (uint32_t)pr);
+                }
+                S[k][sl] = in ? e[k] : 0;
             }
-            E[k][1 + t] = in ? e[k] : 0;
-            if (halo) E[k][t == 0 ? 0 : 256 + t] = (hin && yy < n1) ? even_at(hx, yy) : 0;
-        }
-        __syncthreads();
+        };
+        int32_t e0[kYXRows], o0[kYXRows], e1[kYXRows], o1[kYXRows];
+        build(0, e0, o0);
+        for (uint32_t c = 0; c < nch; c++) {
+            if (c + 1 < nch) build(c + 1, e1, o1);  // uniform
+            __syncthreads();
+            // the x pass of chunk c: odd point of pair P from the even
+            // points of pairs P - 1, P (registers), P + 1, P + 2
+            const uint32_t P = 256 * c + t;
+            const uint32_t x = 2 * P;
+            const bool in = x < n0;
+            const bool two = x + 1 < n0;
+            const bool v2 = two && even_n0;
+            const uint32_t sl = P % kRing;
+            const uint32_t sm1 = sl == 0 ? kRing - 1 : sl - 1;
+            const uint32_t sp1 = sl + 1 == kRing ? 0 : sl + 1;
+            const uint32_t sp2 = sp1 + 1 == kRing ? 0 : sp1 + 1;
 #pragma unroll
-        for (int k = 0; k < kYXRows; k++) {
-            const uint32_t yy = y0 + k;
-            if (yy >= n1) break;  // uniform
-            int32_t o = od[k];
-            if (two) {
-                const uint32_t ca = x + 1;
-                const int32_t p1 = ca + 1 < n0 ? E[k][t + 2] : 0;
-                const int32_t m3 = ca >= 3 ? E[k][t] : 0;
-                const int32_t p3 = ca + 3 < n0 ? E[k][t + 3] : 0;
-                o = (int32_t)((uint32_t)o + (uint32_t)pick_pred(ca, n0, 1, m3, e[k], p1, p3));
+            for (int k = 0; k < kYXRows; k++) {
+                const uint32_t yy = y0 + k;
+                if (yy >= n1) break;  // uniform
+                int32_t o = o0[k];
+                if (two) {
+                    const uint32_t ca = x + 1;
+                    const int32_t p1 = ca + 1 < n0 ? S[k][sp1] : 0;
+                    const int32_t m3 = ca >= 3 ? S[k][sm1] : 0;
+                    const int32_t p3 = ca + 3 < n0 ? S[k][sp2] : 0;
+                    o = (int32_t)((uint32_t)o + (uint32_t)pick_pred(ca, n0, 1, m3, e0[k], p1, p3));
+                }
+                const uint64_t i = pb + sy * yy + x;
+                if (v2) {
+                    typedef float f32x2 __attribute__((ext_vector_type(2)));
+                    const f32x2 w = {dq(e0[k]), dq(o)};
+                    __builtin_nontemporal_store(w, reinterpret_cast<f32x2*>(out + i));
+                } else if (in) {
+                    out[i] = dq(e0[k]);
+                    if (two) out[i + 1] = dq(o);
+                }
             }
-            const uint64_t i = pb + (uint64_t)n0 * yy + x;
-            if (v2) {
-                typedef float f32x2 __attribute__((ext_vector_type(2)));
-                const f32x2 w = {dq(e[k]), dq(o)};
-                __builtin_nontemporal_store(w, reinterpret_cast<f32x2*>(out + i));
-            } else if (in) {
-                out[i] = dq(e[k]);
-                if (two) out[i + 1] = dq(o);
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kYXRows; k++) {
+                e0[k] = e1[k];
+                o0[k] = o1[k];
             }
         }
-        __syncthreads();
     }
 }
 
@@ -489,9 +513,22 @@ static void interp_inverse_passes(hipStream_t st, const Geom& g, int32_t* q, dou
         hipLaunchKernelGGL(k_interp_level<0>, dim3((c0 + 255) / 256, 1), dim3(256), 0, st, g, q, s, s, 2 * s, c0, 0u,
                            1u, 1u, 0u, 1u, 1u);
     }
-    // stride 1: pairs of points per thread; z (x, y even, z odd), then y
-    // (x even, y odd) and x together with the output
+    // stride 1: the y and x passes together, with the z pass of the odd
+    // planes folded in (3D), writing the output; fields one row high: the z
+    // pass (pairs of points through groups of planes), then the x pass
     const uint32_t npairs = (g.n[0] + 1) / 2;
+    if (ND >= 2 && g.n[1] > 1) {
+        const uint32_t gpp = (g.n[1] + kYXRows - 1) / kYXRows;
+        const uint64_t ngroups = (uint64_t)gpp * g.n[2];
+        const uint32_t grid = (uint32_t)(ngroups < (1u << 20) ? ngroups : (1u << 20));
+        if (ND == 3 && g.n[2] > 1)
+            hipLaunchKernelGGL(k_interp_final_yx<true>, dim3(grid), dim3(256), 0, st, g, q, e2, out,
+                               (uint32_t)ngroups, gpp);
+        else
+            hipLaunchKernelGGL(k_interp_final_yx<false>, dim3(grid), dim3(256), 0, st, g, q, e2, out,
+                               (uint32_t)ngroups, gpp);
+        return;
+    }
     if (ND == 3 && g.n[2] > 1) {
         // even rows y through groups of kYXRows planes
         const uint32_t gpr = (g.n[1] + 1) / 2;
@@ -500,16 +537,8 @@ static void interp_inverse_passes(hipStream_t st, const Geom& g, int32_t* q, dou
                            (uint32_t)ngroups, gpr);
     }
     const uint64_t rows = (uint64_t)g.n[1] * g.n[2];
-    if (ND >= 2 && g.n[1] > 1) {
-        // y and x together, the output written: groups of kYXRows rows
-        const uint32_t gpp = (g.n[1] + kYXRows - 1) / kYXRows;
-        const uint64_t ngroups = (uint64_t)gpp * g.n[2];
-        hipLaunchKernelGGL(k_interp_final_yx, dim3((npairs + 255) / 256, cap(ngroups)), dim3(256), 0, st, g, q, e2,
-                           out, (uint32_t)ngroups, gpp);
-    } else {
-        hipLaunchKernelGGL(k_interp_final_x, dim3((npairs + 255) / 256, cap(rows)), dim3(256), 0, st, g, q, e2, out,
-                           (uint32_t)rows);
-    }
+    hipLaunchKernelGGL(k_interp_final_x, dim3((npairs + 255) / 256, cap(rows)), dim3(256), 0, st, g, q, e2, out,
+                       (uint32_t)rows);
 }
 
 void launch_interp_inverse(hipStream_t st, const Geom& g, int32_t* q, double e2, float* out) {
