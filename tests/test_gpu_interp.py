@@ -43,6 +43,8 @@ CASES = [
     ("3d-narrow-x", "smooth", (21, 18, 3), 1e-3, 1),
     ("3d-one-x", "smooth", (13, 11, 1), 1e-3, 1),
     ("2d-one-column", "smooth", (37, 1), 1e-3, 1),
+    ("3d-one-plane", "smooth", (1, 20, 30), 1e-3, 1),
+    ("3d-two-planes-long-rows", "smooth", (2, 9, 1500), 1e-4, 1),
     ("2d-ragged", "smooth", (1001, 777), 1e-3, 1),
     ("2d-small", "smooth", (3, 5), 1e-2, 1),
     ("1d-positions", "positions", (300007,), 1e-4, 1),
